@@ -1,0 +1,104 @@
+"""Pins of O1 (oracle.galerkin): the dense Galerkin CFIE against what the
+mathematics fixes independently of the implementation.
+
+* Mie series far field of the sphere, soft and hard (closed form; Sec. 2's
+  far-field pattern), within the 1e-3 accuracy of the discretisation;
+* Gauss's identity at kappa = 0: K 1 = -1/2 on a closed surface, so the
+  Galerkin rows satisfy K 1 = -1/2 M 1 and the columns 1^T K* = -1/2 1^T M;
+* complex symmetry V = V^T, W = W^T and K* = K^T (bilinear duality, Sec. 4.1);
+* the sphere eigenvalues of V, K and W on the degree-0 and degree-1 modes;
+* the optical theorem on the seeded star (any lossless scatterer);
+* eta-independence of the exact solution (CFIE coupling bookkeeping).
+"""
+import functools
+
+import numpy as np
+import pytest
+
+from oracle import galerkin as G
+from oracle import mie
+from paper_2306_11324_amd import inputs
+
+ALL_OPS = ("V", "Kstar", "K", "W")
+
+
+@functools.lru_cache(maxsize=None)
+def sphere_s2(m, p, kappa):
+    bem = G.DenseBEM(inputs.sphere_patches(), p=p, m=m, kappa=kappa, bc="soft")
+    return bem, bem.operator_rows_s2(np.arange(bem.disc.n2), ops=ALL_OPS)
+
+
+def test_gauss_identity_kappa0():
+    bem = G.DenseBEM(inputs.star_patches(1, 1), p=1, m=1, kappa=0.0, bc="soft", eta=1.0)
+    ops = bem.operator_rows_s2(np.arange(bem.disc.n2), ops=("K", "Kstar"))
+    one = np.ones(bem.disc.n2)
+    m1 = ops["M"] @ one
+    assert np.abs(ops["K"] @ one + 0.5 * m1).max() < 1e-9 * np.abs(m1).max()
+    assert np.abs(one @ ops["Kstar"] + 0.5 * (one @ ops["M"])).max() < 1e-9 * np.abs(m1).max()
+
+
+def test_complex_symmetry():
+    _, ops = sphere_s2(2, 2, 1.5)
+    for op in ("V", "W", "M"):
+        A = ops[op]
+        assert np.abs(A - A.T).max() < 1e-10 * np.abs(A).max(), op
+    assert np.abs(ops["Kstar"] - ops["K"].T).max() < 1e-10 * np.abs(ops["K"]).max()
+
+
+def _project(bem, ops, f):
+    """S^2 coefficients of the L^2 projection of f(x) onto the continuous S^0
+    (the regularised W is the hypersingular operator only on continuous
+    functions)."""
+    from oracle import quadrature as qd
+    disc = bem.disc
+    pts, w = qd.tensor2(8)
+    E = disc.nelem
+    d = disc.eval_on_elements(np.arange(E), np.broadcast_to(pts, (E,) + pts.shape))
+    loc = np.einsum("eq,q,eqa->ea", f(d["X"]) * d["a"], w, d["phi"]) * disc.h ** 2
+    b = np.zeros(disc.n2)
+    np.add.at(b, disc.el_dofs.ravel(), loc.ravel())
+    P = disc.glue_matrix()
+    return P @ np.linalg.solve(P.T @ ops["M"].real @ P, P.T @ b)
+
+
+@pytest.mark.parametrize("n", [0, 1])
+def test_sphere_eigenvalues(n):
+    kappa = 1.5
+    bem, ops = sphere_s2(2, 2, kappa)
+    if n == 0:
+        c = np.ones(bem.disc.n2)
+    else:
+        c = _project(bem, ops, lambda X: X[..., 2])
+    mass = c @ ops["M"] @ c
+    for op, lam in (("V", mie.eig_V), ("K", mie.eig_K), ("Kstar", mie.eig_K), ("W", mie.eig_W)):
+        val = (c @ ops[op] @ c) / mass
+        ref = lam(n, kappa)
+        assert abs(val - ref) < 2e-3 * max(abs(ref), 0.05), (op, n, val, ref)
+
+
+@pytest.mark.parametrize("bc,p,m", [("soft", 1, 2), ("hard", 3, 1)])
+def test_mie_sphere(bc, p, m):
+    """Sphere, kappa = 1, d = (0,0,1), 64 Fibonacci observation directions: far
+    field within 1e-3 of the Mie series (soft: the m = 2, p = 1 workload)."""
+    bem = G.DenseBEM(inputs.sphere_patches(), p=p, m=m, kappa=1.0, bc=bc)
+    d = np.array([0.0, 0.0, 1.0])
+    obs = inputs.fibonacci_directions(64)
+    u = bem.farfield(bem.solve(d), obs)
+    ref = mie.farfield(1.0, obs @ d, bc)
+    assert np.abs(u - ref).max() / np.abs(ref).max() < 1e-3
+
+
+def test_optical_theorem_and_eta_independence_star():
+    bem = G.DenseBEM(inputs.star_patches(0, 2), p=1, m=2, kappa=1.0, bc="soft")
+    d = inputs.random_directions(5, 1)[0]
+    A = bem.matrix()
+    t = np.linalg.solve(A, bem.rhs(d))
+    obs = inputs.fibonacci_directions(400)
+    u = bem.farfield(t, obs)
+    lhs = np.mean(np.abs(u) ** 2) * 4 * np.pi
+    rhs = 4 * np.pi / bem.kappa * bem.farfield(t, d[None])[0].imag
+    assert abs(lhs - rhs) < 2e-3 * abs(rhs)
+    bem2 = G.DenseBEM(inputs.star_patches(0, 2), p=1, m=2, kappa=1.0, bc="soft", eta=3.0)
+    t2 = bem2.solve(d)
+    u2 = bem2.farfield(t2, obs)
+    assert np.abs(u2 - u).max() < 1e-3 * np.abs(u).max()

@@ -1,0 +1,107 @@
+"""Pins of O2 (oracle.h2), the step-by-step reference-domain H^2 matrix.
+
+* the upward / coupling / downward recursion (transfers) equals the far
+  field assembled from directly integrated cluster moments;
+* a polynomial test kernel of degree <= q in each reference coordinate is
+  reproduced exactly (interpolation is exact on polynomials), degree q+1 is not;
+* eta -> infinity leaves no admissible block: the H^2 matrix is O1's matrix;
+* the far blocks approach O1's exact blocks geometrically in q.
+"""
+import functools
+
+import numpy as np
+
+from oracle import galerkin as G
+from oracle import h2
+from paper_2306_11324_amd import inputs
+
+
+@functools.lru_cache(maxsize=None)
+def bem_m3():
+    return G.DenseBEM(inputs.sphere_patches(), p=1, m=3, kappa=2.0, bc="soft")
+
+
+def test_recursion_matches_direct_moments():
+    H = h2.H2Oracle(bem_m3(), q=3, eta=1.6, leaf_depth=1)
+    assert len(H.far) > 0
+    x = inputs.random_complex(12345, bem_m3().n)
+    y = H.far_apply(x)
+    ref = H.far_matrix() @ x
+    assert np.abs(y - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def _direct_separable(H, f, g):
+    """int_t int_s f(x^) g(y^) psi_i psi_j summed over the far blocks, by Gauss
+    quadrature of the (polynomial) integrand on every element."""
+    from oracle import quadrature as qd
+    disc = H.disc
+    pts, w = qd.tensor2(8)
+    E = disc.nelem
+    d = disc.eval_on_elements(np.arange(E), np.broadcast_to(pts, (E,) + pts.shape))
+    uv = np.stack([(disc.el_ex[:, None] + pts[None, :, 0]) * disc.h,
+                   (disc.el_ey[:, None] + pts[None, :, 1]) * disc.h], -1)
+    mf = np.einsum("eq,q,eqa->ea", f(uv), w, d["phi"]) * disc.h ** 2
+    mg = np.einsum("eq,q,eqa->ea", g(uv), w, d["phi"]) * disc.h ** 2
+    A = np.zeros((disc.n2, disc.n2))
+    for t, s in H.far:
+        vf = np.zeros(disc.n2)
+        vg = np.zeros(disc.n2)
+        et, es = H.cluster_elements(t), H.cluster_elements(s)
+        np.add.at(vf, disc.el_dofs[et].ravel(), mf[et].ravel())
+        np.add.at(vg, disc.el_dofs[es].ravel(), mg[es].ravel())
+        A += np.outer(vf, vg)
+    return A
+
+
+def test_polynomial_kernel_reproduced():
+    bem = bem_m3()
+    q = 3
+    f = lambda uv: (uv[..., 0] - 0.3) ** q * (0.2 + uv[..., 1]) ** q
+    g = lambda uv: (uv[..., 0] + 0.1) ** (q - 1) * (uv[..., 1] - 0.7) ** q + 1.0
+    kern = lambda X, Y: f(X) * g(Y)
+    H = h2.H2Oracle(bem, q=q, eta=1.6, leaf_depth=1, coupling_kernel=kern)
+    A = H.far_matrix()
+    ref = _direct_separable(H, f, g)
+    assert np.abs(A - ref).max() < 1e-12 * np.abs(ref).max()
+    f2 = lambda uv: (uv[..., 0] - 0.3) ** (q + 1)
+    H2 = h2.H2Oracle(bem, q=q, eta=1.6, leaf_depth=1, coupling_kernel=lambda X, Y: f2(X) * g(Y))
+    A2 = H2.far_matrix()
+    ref2 = _direct_separable(H2, f2, g)
+    assert np.abs(A2 - ref2).max() > 1e-8 * np.abs(ref2).max()
+
+
+def test_no_admissible_blocks_gives_dense():
+    bem = G.DenseBEM(inputs.sphere_patches(), p=1, m=1, kappa=1.0, bc="soft")
+    H = h2.H2Oracle(bem, q=2, eta=1e12, leaf_depth=1)
+    assert len(H.far) == 0
+    A = bem.matrix()
+    assert np.abs(H.matrix() - A).max() < 1e-14 * np.abs(A).max()
+
+
+def test_block_error_decays_geometrically_in_q():
+    bem = bem_m3()
+    disc = bem.disc
+    H0 = h2.H2Oracle(bem, q=2, eta=1.6, leaf_depth=1)
+    far = H0.far[:: max(1, len(H0.far) // 6)][:6]
+    exact = []
+    for t, s in far:
+        A = np.zeros((disc.n2, disc.n2), dtype=np.complex128)
+        es = H0.cluster_elements(s)
+        for e in H0.cluster_elements(t):
+            blk = bem.element_row_blocks(int(e), sources=es)
+            comb = blk["Kstar"] - 1j * bem.eta * blk["V"]
+            for f in es:
+                A[np.ix_(disc.el_dofs[e], disc.el_dofs[f])] += comb[f]
+        exact.append(A)
+    errs = []
+    for q in (2, 4, 6, 8):
+        H = h2.H2Oracle(bem, q=q, eta=1.6, leaf_depth=1)
+        e = 0.0
+        for (t, s), A in zip(far, exact):
+            K = H.coupling(t, s)["pp"]
+            Ah = H.cluster_moment(t).T @ K @ H.cluster_moment(s)
+            e = max(e, np.linalg.norm(Ah - A) / np.linalg.norm(A))
+        errs.append(e)
+    assert errs[-1] < 1e-6
+    for a, b in zip(errs[:-1], errs[1:]):
+        assert b < a / 8, errs
