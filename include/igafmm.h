@@ -1,0 +1,223 @@
+/*
+ * igafmm -- isogeometric fast-multipole Galerkin CFIE for acoustic scattering
+ * (Doelz, Harbrecht, Multerer: "Solving acoustic scattering problems by the
+ * isogeometric boundary element method").  C ABI of the MI355X (gfx950) library.
+ *
+ * General conventions
+ *   - Every entry point returns an igb_status: 0 = success, < 0 = error (nothing
+ *     written to outputs), > 0 = warning (outputs written).  The text of the
+ *     last error of the calling thread is returned by igb_last_error().
+ *   - Complex numbers are interleaved (re, im) fp64 pairs, compatible with
+ *     C99 double _Complex and torch.complex128.  Multi-column arrays are
+ *     column-major in the sense [ncol][n]: each column contiguous.
+ *   - "host" pointers are read or written synchronously.  "device" pointers
+ *     must point to device memory of the context's GPU; calls that take a
+ *     hip_stream argument are ordered on that stream (NULL = the context's own
+ *     stream) and return before the device work completes.
+ *   - The caller owns every buffer it passes; the library copies what it keeps.
+ *     Handles own their device memory until destroyed.  Assembled operators are
+ *     immutable: concurrent igb_h2_matvec calls on one operator from different
+ *     streams are allowed; calls that share an operator's internal work
+ *     vectors (h2_matvec, cfie_solve) must not overlap on the same operator.
+ *
+ * Numbering (patch-major):
+ *   elements  e = patch*4^m + ey*2^m + ex  covering [ex,ex+1]x[ey,ey+1]/2^m of the
+ *             patch's reference square;
+ *   S^2 dofs  i = patch*k^2 + iv*k + iu,  k = 2^m + p: the tensor B-spline
+ *             b_iu(u) b_iv(v) of S_{p,p}(Xi_{p,m}, Xi_{p,m}) on the patch (Sec. 3.3);
+ *   S^0 dofs  the globally continuous subspace (Sec. 3.3): an S^0 function is the
+ *             sum of the S^2 functions whose Greville anchor points coincide on
+ *             patch interfaces; S^0 dofs are numbered in increasing order of their
+ *             lowest S^2 representative.
+ *   Sound-soft problems are posed on S^2, sound-hard problems on S^0.
+ */
+#ifndef IGAFMM_H
+#define IGAFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int igb_status;
+#define IGB_OK 0
+#define IGB_ERR_ARG (-1)       /* invalid argument                                   */
+#define IGB_ERR_GEOMETRY (-2)  /* invalid knots / weights / non-conforming patches   */
+#define IGB_ERR_BUDGET (-3)    /* the context's HBM budget would be exceeded          */
+#define IGB_ERR_HIP (-4)       /* a HIP runtime call failed                           */
+#define IGB_ERR_UNSUPPORTED (-5) /* parameters outside what this build implements     */
+#define IGB_WARN_NOT_CONVERGED 1 /* iterative solve stopped at maxit                  */
+
+typedef struct igb_ctx_s* igb_ctx;
+typedef struct igb_geom_s* igb_geom;
+typedef struct igb_op_s* igb_op;
+
+/* One NURBS patch F_j: [0,1]^2 -> Gamma_j (Sec. 3.2).  Open knot vectors of
+ * length ncp+deg+1 in [0,1]; cpw[ncp_v][ncp_u][4] = (x, y, z, w) with w > 0
+ * (Cartesian control point and weight, not homogeneous).  Patches must be
+ * oriented so that d_u F x d_v F points outward, and conform along shared edges
+ * (the two patch maps agree on the interface up to a symmetry of the square). */
+typedef struct {
+    int deg_u, deg_v, ncp_u, ncp_v;
+    const double* knots_u;
+    const double* knots_v;
+    const double* cpw;
+} igb_patch;
+
+typedef enum { IGB_SOFT = 0, IGB_HARD = 1 } igb_bc;
+typedef enum { IGB_FP64 = 0, IGB_MIX_FP32 = 1, IGB_MIX_BF16 = 2 } igb_prec;
+
+/* Operator parameters.
+ *   kappa      wavenumber (> 0)
+ *   bc         IGB_SOFT: (1/2 M + K* - i eta V) on S^2 (Sec. 4.1, system D2N);
+ *              IGB_HARD: (1/2 M - K - i eta W) on S^0 (Sec. 4.1, system N2D, W
+ *              regularised as in Sec. 4.3)
+ *   eta_c      CFIE coupling eta (Sec. 2); <= 0 selects kappa (soft) / 1/kappa (hard)
+ *   q          interpolation degree per reference direction (q+1 Chebyshev
+ *              points of the first kind, Sec. 4.4), 1 <= q <= 10
+ *   eta_adm    admissibility: dist(B_t,B_s) >= eta_adm * max(diam B_t, diam B_s)
+ *              for the boxes of the clusters' Bezier control points (Sec. 4.4
+ *              gives eta = 1.6 without the inequality; this reading)
+ *   kcap       if > 0, a block is admissible only if kappa*max(diam) <= kcap
+ *   leaf_depth clusters stop at 4^leaf_depth elements (leaf level m - leaf_depth)
+ *   precision  far-field coupling storage; this build: IGB_FP64 only */
+typedef struct {
+    double kappa;
+    int bc;
+    double eta_c;
+    int q;
+    double eta_adm;
+    double kcap;
+    int leaf_depth;
+    int precision;
+} igb_op_params;
+
+typedef struct {
+    double tol;      /* relative residual ||b - A x|| / ||b||, Euclidean on coefficients */
+    int restart;     /* GMRES restart length (the paper uses 30, Sec. 5.1)              */
+    int maxit;       /* maximal number of matrix-vector products per column             */
+} igb_solve_params;
+
+typedef struct {
+    int iters;        /* matrix-vector products used (max over columns)            */
+    int converged;    /* number of columns that reached tol                         */
+    double relres;    /* max over columns of the final recursive relative residual   */
+    double relres_true; /* max over columns of ||b - A x||/||b|| recomputed at the end */
+} igb_solve_info;
+
+typedef struct {
+    int64_t n;              /* dimension of the solution space                     */
+    int64_t nelem;          /* elements                                            */
+    int64_t n2;             /* dim S^2                                             */
+    int64_t nclusters;      /* clusters on levels 0..leaf                          */
+    int leaf_level;
+    int nq;                 /* (q+1)^2                                             */
+    int64_t far_pairs;      /* admissible (ordered) cluster pairs, all levels       */
+    int64_t far_per_level[16];
+    int64_t near_elem_pairs;/* element pairs integrated by quadrature              */
+    int64_t nnz;            /* nonzeros of the near-field matrix                    */
+    int64_t device_bytes;   /* device memory held by the operator                   */
+    double assembly_near_ms, assembly_far_ms;
+} igb_op_info;
+
+/* ---------------------------------------------------------------- context */
+
+#define IGB_HOST_ONLY (-1)
+/* Creates a context on HIP device `device`, or, with device = IGB_HOST_ONLY, a
+ * context without a device: geometries and operators created on it run the
+ * host stages only (validation, spaces, cluster trees, block partition, near
+ * pairs and sparsity pattern) and every compute entry point on them fails with
+ * IGB_ERR_ARG.  hbm_budget_bytes = 0 means no
+ * limit; otherwise geometry and operator creation fail with IGB_ERR_BUDGET
+ * before allocating if the context would hold more.  *out receives the handle. */
+igb_status igb_ctx_create(int device, size_t hbm_budget_bytes, igb_ctx* out);
+void igb_ctx_destroy(igb_ctx ctx);
+/* Bytes currently held by the context's geometries and operators. */
+size_t igb_ctx_used_bytes(igb_ctx ctx);
+
+/* ---------------------------------------------------------------- geometry */
+
+/* Discretises npatch NURBS patches (host arrays, Sec. 3.2) with the spaces of
+ * Sec. 3.3 at refinement level m (2^m x 2^m elements per patch) and spline
+ * degree p (0 <= p <= 3; S^0 needs p >= 1).  Geometry degree per knot span must
+ * be <= 3 and every geometry knot must be a mesh knot j/2^m.  Errors:
+ * IGB_ERR_GEOMETRY for invalid knots, weights <= 0 or patches that do not
+ * conform; IGB_ERR_ARG for bad sizes. */
+igb_status build_geometry(igb_ctx ctx, const igb_patch* patches, int npatch, int level_m,
+                          int degree_p, igb_geom* out);
+void igb_geom_destroy(igb_geom g);
+/* dims[0] = elements, dims[1] = dim S^2, dims[2] = dim S^0 (0 if p = 0). */
+igb_status igb_geom_dims(igb_geom g, int64_t dims[3]);
+/* The S^0 number of every S^2 dof (host array of dim S^2). */
+igb_status igb_geom_s0_map(igb_geom g, int32_t* s2_to_s0);
+
+/* ---------------------------------------------------------------- operator */
+
+/* Assembles the CFIE operator of Sec. 4.1 with the H^2 compression of Sec. 4.4:
+ * the cluster trees and block partition (host), the near-field Galerkin
+ * matrix by quadrature on the device (Duffy-type singular rules on touching
+ * element pairs, tensor Gauss otherwise; includes 1/2 M), and the coupling
+ * matrices of every admissible block on the device.  Synchronous. */
+igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm, igb_op* out);
+void igb_op_destroy(igb_op op);
+igb_status igb_op_get_info(igb_op op, igb_op_info* info);
+
+/* Near-field matrix in CSR (solution space) copied to host arrays of sizes
+ * n+1, nnz, 2*nnz (sizes from igb_op_get_info). */
+igb_status igb_op_near_csr(igb_op op, int64_t* row_ptr, int32_t* col, double* val);
+/* Admissible blocks: out[4*i..] = (level, target, source, 0) with cluster
+ * indices local to the level: patch*4^l + cy*2^l + cx. */
+igb_status igb_op_far_blocks(igb_op op, int32_t* out);
+
+/* Near element pairs (host arrays): ptr[nelem+1], src[near_elem_pairs] sorted per
+ * target element, kind[near_elem_pairs] = quadrature class (bits 0-3: 0 regular,
+ * 1 common vertex, 2 common edge, 4 identical; bits 8-11: Gauss order of a
+ * regular pair; bits 16-18 / 20-22: square symmetries bringing the pair into
+ * the canonical touching configuration).  Works on host-only contexts. */
+igb_status igb_op_near_pairs(igb_op op, int64_t* ptr, int32_t* src, int32_t* kind);
+
+/* Per-kernel timing with HIP events recorded on the launch stream around the
+ * operator's matvec stages: "m2l" (coupling), "spmv" (near field + combine),
+ * "upward" (leaf moments + transfers up), "downward" (reduce, transfers down,
+ * back projection).  igb_op_profile(op, 1) starts recording (and clears);
+ * igb_op_kernel_time waits for the recorded launches and returns their count
+ * and total milliseconds, then clears that kernel's record. */
+igb_status igb_op_profile(igb_op op, int enable);
+igb_status igb_op_kernel_time(igb_op op, const char* name, int64_t* launches, double* total_ms);
+
+#define IGB_PART_NEAR 1
+#define IGB_PART_FAR 2
+#define IGB_PART_ALL 3
+/* y = A x for nrhs columns (device arrays [nrhs][n] complex).  parts selects the
+ * near-field (incl. 1/2 M) and/or far-field (H^2) contributions.  x and y must
+ * not overlap.  This build: nrhs = 1 per call.  Stream-ordered. */
+igb_status h2_matvec(igb_op op, const double* x, double* y, int nrhs, int parts, void* hip_stream);
+
+/* Right-hand sides (Sec. 4.1 load vectors of the D2N / N2D systems) for ndir
+ * incident plane waves e^{i kappa <d,x>} (host dirs [ndir][3], normalised here;
+ * error if |d| < 1e-12) into the device array b [ndir][n].  Stream-ordered. */
+igb_status cfie_rhs(igb_op op, const double* dirs, int ndir, double* b, void* hip_stream);
+
+/* Solves the CFIE for ndir incident directions (host dirs [ndir][3]) with
+ * restarted GMRES (Sec. 5.1), x0 = 0, writing the coefficients into the device
+ * array coeffs [ndir][n].  Synchronous.  IGB_WARN_NOT_CONVERGED if a column
+ * stops at maxit. */
+igb_status cfie_solve(igb_op op, const double* dirs, int ndir, const igb_solve_params* sp,
+                      double* coeffs, igb_solve_info* info);
+
+/* Far-field pattern u_inf (Sec. 1) of the scattered wave for ndir coefficient
+ * columns (device coeffs [ndir][n]) at nobs unit directions (host obs
+ * [nobs][3]) into the device array uinf [ndir][nobs].  Sound-soft:
+ * u_inf(x) = -(1/4pi) int e^{-i kappa x.y} t(y); sound-hard:
+ * u_inf(x) = -(i kappa/4pi) int (x.n_y) e^{-i kappa x.y} g(y).  Stream-ordered. */
+igb_status farfield(igb_op op, const double* coeffs, int ndir, const double* obs, int nobs,
+                    double* uinf, void* hip_stream);
+
+const char* igb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IGAFMM_H */

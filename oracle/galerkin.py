@@ -267,6 +267,23 @@ class DenseBEM:
                 np.add.at(out["M"][ri], disc.el_dofs[e], mb[a])
         return out
 
+    def _one_restricted(self, e, fs):
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(1):
+            return self.element_row_blocks(int(e), sources=fs), self.mass_block(int(e))
+
+    def restricted_row_blocks(self, targets, sources):
+        """element_row_blocks(e, sources=fs) and the mass block for every
+        (e, fs) in zip(targets, sources), over the worker pool."""
+        if self.workers <= 1 or len(targets) < 4:
+            for e, fs in zip(targets, sources):
+                yield self._one_restricted(e, fs)
+            return
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        with cf.ProcessPoolExecutor(self.workers, mp_context=mp.get_context("fork")) as ex:
+            yield from ex.map(self._one_restricted, targets, sources)
+
     def _one_target(self, e, ops):
         from threadpoolctl import threadpool_limits
         with threadpool_limits(1):

@@ -264,13 +264,13 @@ class H2Oracle:
         n2 = disc.n2
         A = np.zeros((n2, n2), dtype=np.complex128)
         pairs = self.near_pairs()
-        for e in np.unique(pairs[:, 0]):
-            fs = pairs[pairs[:, 0] == e, 1]
-            blk = bem.element_row_blocks(int(e))
+        targets = np.unique(pairs[:, 0])
+        sources = [pairs[pairs[:, 0] == e, 1] for e in targets]
+        for e, fs, (blk, mass) in zip(targets, sources, bem.restricted_row_blocks(targets, sources)):
             comb = self._combine_blocks(blk)
             for f in fs:
                 A[np.ix_(disc.el_dofs[e], disc.el_dofs[f])] += comb[f]
-            A[np.ix_(disc.el_dofs[e], disc.el_dofs[e])] += 0.5 * bem.mass_block(int(e))
+            A[np.ix_(disc.el_dofs[e], disc.el_dofs[e])] += 0.5 * mass
         return A
 
     def _combine_blocks(self, blk):

@@ -1,0 +1,375 @@
+// The C ABI of igafmm (declared in include/igafmm.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace igb {
+const char* last_error();
+}
+
+using namespace igb;
+
+namespace {
+
+hipStream_t pick(igb_ctx ctx, void* s) { return s ? static_cast<hipStream_t>(s) : ctx->stream; }
+
+bool host_only(igb_ctx ctx) { return ctx->device == IGB_HOST_ONLY; }
+
+igb_status need_device(igb_op op, const char* what) {
+    if (host_only(op->geom->ctx)) {
+        set_error("%s: the operator belongs to a host-only context", what);
+        return IGB_ERR_ARG;
+    }
+    return IGB_OK;
+}
+
+bool budget_ok(igb_ctx ctx, size_t add) {
+    return ctx->budget == 0 || ctx->used + add <= ctx->budget;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* igb_last_error(void) { return igb::last_error(); }
+
+igb_status igb_ctx_create(int device, size_t hbm_budget_bytes, igb_ctx* out) {
+    if (!out) {
+        set_error("igb_ctx_create: out is NULL");
+        return IGB_ERR_ARG;
+    }
+    if (device == IGB_HOST_ONLY) {
+        igb_ctx c = new (std::nothrow) igb_ctx_s();
+        if (!c) {
+            set_error("igb_ctx_create: out of host memory");
+            return IGB_ERR_ARG;
+        }
+        c->device = IGB_HOST_ONLY;
+        c->budget = hbm_budget_bytes;
+        *out = c;
+        return IGB_OK;
+    }
+    int n = 0;
+    IGB_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) {
+        set_error("igb_ctx_create: device %d out of range (%d devices)", device, n);
+        return IGB_ERR_ARG;
+    }
+    IGB_HIP(hipSetDevice(device));
+    igb_ctx c = new (std::nothrow) igb_ctx_s();
+    if (!c) {
+        set_error("igb_ctx_create: out of host memory");
+        return IGB_ERR_ARG;
+    }
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete c;
+        set_error("igb_ctx_create: %s", hipGetErrorString(e));
+        return IGB_ERR_HIP;
+    }
+    *out = c;
+    return IGB_OK;
+}
+
+void igb_ctx_destroy(igb_ctx ctx) {
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+size_t igb_ctx_used_bytes(igb_ctx ctx) { return ctx ? ctx->used : 0; }
+
+igb_status build_geometry(igb_ctx ctx, const igb_patch* patches, int npatch, int level_m, int degree_p,
+                          igb_geom* out) {
+    if (!ctx || !patches || !out) {
+        set_error("build_geometry: NULL argument");
+        return IGB_ERR_ARG;
+    }
+    if (!host_only(ctx)) IGB_HIP(hipSetDevice(ctx->device));
+    igb_geom g = new (std::nothrow) igb_geom_s();
+    if (!g) {
+        set_error("build_geometry: out of host memory");
+        return IGB_ERR_ARG;
+    }
+    igb_status st = geometry_build(ctx, patches, npatch, level_m, degree_p, g);
+    if (st) {
+        delete g;
+        return st;
+    }
+    const size_t need = g->bez.size() * 8 + g->pg.size() * 4 + g->C1.size() * 8;
+    if (!budget_ok(ctx, need)) {
+        delete g;
+        set_error("build_geometry: HBM budget exceeded (%zu + %zu > %zu bytes)", ctx->used, need, ctx->budget);
+        return IGB_ERR_BUDGET;
+    }
+    if (!host_only(ctx) && (st = upload_geometry(g))) {
+        delete g;
+        return st;
+    }
+    ctx->used += g->dev_bytes;
+    *out = g;
+    return IGB_OK;
+}
+
+void igb_geom_destroy(igb_geom g) {
+    if (!g) return;
+    if (g->ctx) g->ctx->used -= std::min(g->ctx->used, g->dev_bytes);
+    delete g;
+}
+
+igb_status igb_geom_dims(igb_geom g, int64_t dims[3]) {
+    if (!g || !dims) {
+        set_error("igb_geom_dims: NULL argument");
+        return IGB_ERR_ARG;
+    }
+    dims[0] = g->nelem;
+    dims[1] = g->n2;
+    dims[2] = g->n0;
+    return IGB_OK;
+}
+
+igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm, igb_op* out) {
+    if (!ctx || !g || !prm || !out) {
+        set_error("assemble_nearfield: NULL argument");
+        return IGB_ERR_ARG;
+    }
+    if (!(prm->kappa > 0) || prm->q < 1 || prm->q > QMAX || !(prm->eta_adm > 0) || prm->leaf_depth < 0 ||
+        (prm->bc != IGB_SOFT && prm->bc != IGB_HARD)) {
+        set_error("assemble_nearfield: need kappa > 0, 1 <= q <= %d, eta_adm > 0, leaf_depth >= 0, bc soft/hard",
+                  QMAX);
+        return IGB_ERR_ARG;
+    }
+    if (prm->precision != IGB_FP64) {
+        set_error("assemble_nearfield: only fp64 coupling storage is built");
+        return IGB_ERR_UNSUPPORTED;
+    }
+    if (prm->bc == IGB_HARD && g->p < 1) {
+        set_error("assemble_nearfield: sound-hard needs S^0, i.e. p >= 1");
+        return IGB_ERR_ARG;
+    }
+    if (!host_only(ctx)) IGB_HIP(hipSetDevice(ctx->device));
+    igb_op op = new (std::nothrow) igb_op_s();
+    if (!op) {
+        set_error("assemble_nearfield: out of host memory");
+        return IGB_ERR_ARG;
+    }
+    op->geom = g;
+    op->prm = *prm;
+    op->bc = prm->bc;
+    op->kappa = prm->kappa;
+    op->eta = prm->eta_c > 0 ? prm->eta_c : (prm->bc == IGB_SOFT ? prm->kappa : 1.0 / prm->kappa);
+    op->q = prm->q;
+    op->nq = (prm->q + 1) * (prm->q + 1);
+    op->N = prm->bc == IGB_SOFT ? g->n2 : g->n0;
+    igb_status st;
+    if ((st = tree_build(op)) || (st = near_classify(op)) || (st = near_pattern(op))) {
+        delete op;
+        return st;
+    }
+    // device bytes of the operator (checked against the budget before allocating)
+    const int nl = (g->p + 1) * (g->p + 1);
+    size_t need = size_t(op->nfar) * op->nq * op->nq * 16 + size_t(op->nnz) * 20 + size_t(op->N + 1) * 8 +
+                  size_t(op->nclusters) * op->nq * (16 * 8 + 32) + op->near_src.size() * 4 +
+                  std::min<size_t>(op->near_src.size(), size_t(1) << 22) * nl * nl * 16;
+    if (!budget_ok(ctx, need)) {
+        set_error("assemble_nearfield: HBM budget exceeded (%zu + %zu > %zu bytes)", ctx->used, need, ctx->budget);
+        delete op;
+        return IGB_ERR_BUDGET;
+    }
+    hipStream_t s = ctx->stream;
+    if (host_only(ctx)) {
+        *out = op;
+        return IGB_OK;
+    }
+    if ((st = assemble_near_device(op, s)) || (st = assemble_far_device(op, s)) || (st = alloc_work(op, 1))) {
+        delete op;
+        return st;
+    }
+    ctx->used += op->dev_bytes;
+    *out = op;
+    return IGB_OK;
+}
+
+void igb_op_destroy(igb_op op) {
+    if (!op) return;
+    if (!host_only(op->geom->ctx)) (void)hipDeviceSynchronize();
+    igb_ctx ctx = op->geom ? op->geom->ctx : nullptr;
+    if (ctx) ctx->used -= std::min(ctx->used, op->dev_bytes);
+    delete op;
+}
+
+igb_status igb_op_get_info(igb_op op, igb_op_info* info) {
+    if (!op || !info) {
+        set_error("igb_op_get_info: NULL argument");
+        return IGB_ERR_ARG;
+    }
+    std::memset(info, 0, sizeof(*info));
+    info->n = op->N;
+    info->nelem = op->geom->nelem;
+    info->n2 = op->geom->n2;
+    info->nclusters = op->nclusters;
+    info->leaf_level = op->L;
+    info->nq = op->nq;
+    info->far_pairs = op->nfar;
+    for (int l = 0; l <= op->L && l < 16; ++l) info->far_per_level[l] = int64_t(op->far[l].src.size());
+    info->near_elem_pairs = int64_t(op->near_src.size());
+    info->nnz = op->nnz;
+    info->device_bytes = int64_t(op->dev_bytes);
+    info->assembly_near_ms = op->t_assembly_near;
+    info->assembly_far_ms = op->t_assembly_far;
+    return IGB_OK;
+}
+
+igb_status igb_op_near_csr(igb_op op, int64_t* row_ptr, int32_t* col, double* val) {
+    if (!op || !row_ptr || !col || !val) {
+        set_error("igb_op_near_csr: NULL argument");
+        return IGB_ERR_ARG;
+    }
+    igb_status st = need_device(op, "igb_op_near_csr");
+    if (st) return st;
+    IGB_HIP(hipSetDevice(op->geom->ctx->device));
+    std::memcpy(row_ptr, op->row_ptr.data(), op->row_ptr.size() * sizeof(int64_t));
+    std::memcpy(col, op->col.data(), op->col.size() * sizeof(int32_t));
+    IGB_HIP(hipMemcpy(val, op->d_val.ptr, op->nnz * sizeof(double2), hipMemcpyDeviceToHost));
+    return IGB_OK;
+}
+
+igb_status igb_op_far_blocks(igb_op op, int32_t* out) {
+    if (!op || !out) {
+        set_error("igb_op_far_blocks: NULL argument");
+        return IGB_ERR_ARG;
+    }
+    int64_t i = 0;
+    for (int l = 0; l <= op->L; ++l) {
+        const FarLevel& F = op->far[l];
+        const int64_t nc = clusters_on_level(op->geom->npatch, l);
+        for (int64_t t = 0; t < nc; ++t)
+            for (int k = F.tgt_ptr[t]; k < F.tgt_ptr[t + 1]; ++k) {
+                out[4 * i] = l;
+                out[4 * i + 1] = int32_t(t);
+                out[4 * i + 2] = F.src[k];
+                out[4 * i + 3] = 0;
+                ++i;
+            }
+    }
+    return IGB_OK;
+}
+
+igb_status igb_op_near_pairs(igb_op op, int64_t* ptr, int32_t* src, int32_t* kind) {
+    if (!op || !ptr || !src || !kind) {
+        set_error("igb_op_near_pairs: NULL argument");
+        return IGB_ERR_ARG;
+    }
+    std::memcpy(ptr, op->near_ptr.data(), op->near_ptr.size() * sizeof(int64_t));
+    std::memcpy(src, op->near_src.data(), op->near_src.size() * sizeof(int32_t));
+    std::memcpy(kind, op->near_kind.data(), op->near_kind.size() * sizeof(int32_t));
+    return IGB_OK;
+}
+
+igb_status igb_geom_s0_map(igb_geom g, int32_t* s2_to_s0) {
+    if (!g || !s2_to_s0) {
+        set_error("igb_geom_s0_map: NULL argument");
+        return IGB_ERR_ARG;
+    }
+    std::memcpy(s2_to_s0, g->s2_to_s0.data(), g->s2_to_s0.size() * sizeof(int32_t));
+    return IGB_OK;
+}
+
+igb_status igb_op_profile(igb_op op, int enable) {
+    if (!op) {
+        set_error("igb_op_profile: NULL argument");
+        return IGB_ERR_ARG;
+    }
+    op->profile = enable != 0;
+    for (auto& t : op->timers) t.used = 0;
+    return IGB_OK;
+}
+
+igb_status igb_op_kernel_time(igb_op op, const char* name, int64_t* launches, double* total_ms) {
+    if (!op || !name || !launches || !total_ms) {
+        set_error("igb_op_kernel_time: NULL argument");
+        return IGB_ERR_ARG;
+    }
+    static const char* names[4] = {"m2l", "spmv", "upward", "downward"};
+    int slot = -1;
+    for (int i = 0; i < 4; ++i)
+        if (std::strcmp(name, names[i]) == 0) slot = i;
+    if (slot < 0) {
+        set_error("igb_op_kernel_time: unknown kernel '%s' (m2l, spmv, upward, downward)", name);
+        return IGB_ERR_ARG;
+    }
+    KernelTimer& t = op->timers[slot];
+    double tot = 0;
+    for (size_t i = 0; i + 1 < t.used; i += 2) {
+        IGB_HIP(hipEventSynchronize(t.pool[i + 1]));
+        float ms = 0;
+        IGB_HIP(hipEventElapsedTime(&ms, t.pool[i], t.pool[i + 1]));
+        tot += ms;
+    }
+    *launches = int64_t(t.used / 2);
+    *total_ms = tot;
+    t.used = 0;
+    return IGB_OK;
+}
+
+igb_status h2_matvec(igb_op op, const double* x, double* y, int nrhs, int parts, void* hip_stream) {
+    if (!op || !x || !y || nrhs < 1 || parts < 1 || parts > 3) {
+        set_error("h2_matvec: invalid argument");
+        return IGB_ERR_ARG;
+    }
+    if (x == y) {
+        set_error("h2_matvec: x and y must not overlap");
+        return IGB_ERR_ARG;
+    }
+    if (igb_status st = need_device(op, "h2_matvec")) return st;
+    IGB_HIP(hipSetDevice(op->geom->ctx->device));
+    return matvec_device(op, x, y, nrhs, parts, pick(op->geom->ctx, hip_stream));
+}
+
+igb_status cfie_rhs(igb_op op, const double* dirs, int ndir, double* b, void* hip_stream) {
+    if (!op || !dirs || !b || ndir < 1) {
+        set_error("cfie_rhs: invalid argument");
+        return IGB_ERR_ARG;
+    }
+    if (igb_status st = need_device(op, "cfie_rhs")) return st;
+    IGB_HIP(hipSetDevice(op->geom->ctx->device));
+    return rhs_device(op, dirs, ndir, b, pick(op->geom->ctx, hip_stream));
+}
+
+igb_status cfie_solve(igb_op op, const double* dirs, int ndir, const igb_solve_params* sp, double* coeffs,
+                      igb_solve_info* info) {
+    if (!op || !dirs || !sp || !coeffs || ndir < 1) {
+        set_error("cfie_solve: invalid argument");
+        return IGB_ERR_ARG;
+    }
+    if (igb_status st0 = need_device(op, "cfie_solve")) return st0;
+    IGB_HIP(hipSetDevice(op->geom->ctx->device));
+    hipStream_t s = op->geom->ctx->stream;
+    igb::DevBuf b;
+    IGB_HIP(hipMalloc(&b.ptr, size_t(ndir) * op->N * 16));
+    igb_status st = rhs_device(op, dirs, ndir, b.as<double>(), s);
+    if (st) return st;
+    st = gmres_device(op, b.as<double>(), coeffs, ndir, sp, info, s);
+    IGB_HIP(hipStreamSynchronize(s));
+    return st;
+}
+
+igb_status farfield(igb_op op, const double* coeffs, int ndir, const double* obs, int nobs, double* uinf,
+                    void* hip_stream) {
+    if (!op || !coeffs || !obs || !uinf || ndir < 1 || nobs < 1) {
+        set_error("farfield: invalid argument");
+        return IGB_ERR_ARG;
+    }
+    if (igb_status st = need_device(op, "farfield")) return st;
+    IGB_HIP(hipSetDevice(op->geom->ctx->device));
+    return farfield_device(op, coeffs, ndir, obs, nobs, uinf, pick(op->geom->ctx, hip_stream));
+}
+
+}  // extern "C"

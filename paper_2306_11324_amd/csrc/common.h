@@ -1,0 +1,172 @@
+// Internal definitions of the igafmm library (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/igafmm.h"
+
+namespace igb {
+
+constexpr int PMAX = 3;         // spline degree of the discrete spaces
+constexpr int PGMAX = 3;        // polynomial degree of the geometry per element
+constexpr int NBZ = (PGMAX + 1) * (PGMAX + 1);
+constexpr int QMAX = 10;        // interpolation degree
+constexpr int NLOCMAX = (PMAX + 1) * (PMAX + 1);
+
+// thread-local error message set by every failing entry point
+void set_error(const char* fmt, ...);
+
+#define IGB_HIP(call)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            ::igb::set_error("%s:%d %s: %s", __FILE__, __LINE__, #call,           \
+                             hipGetErrorString(e_));                               \
+            return IGB_ERR_HIP;                                                    \
+        }                                                                          \
+    } while (0)
+
+// ----------------------------------------------------------------------------
+// device memory owned by a handle; freed in the destructor
+// ----------------------------------------------------------------------------
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    template <class T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+}  // namespace igb
+
+struct igb_ctx_s {
+    int device = 0;
+    size_t budget = 0;   // bytes the library may hold on this device (0 = no limit)
+    size_t used = 0;     // bytes currently held by live geometries / operators
+    hipStream_t stream = nullptr;
+};
+
+// Per-element data of a discretised geometry.
+struct igb_geom_s {
+    igb_ctx ctx = nullptr;
+    int npatch = 0, m = 0, p = 0, nel1 = 0, k = 0;
+    int64_t nelem = 0, n2 = 0, n0 = 0;
+    // host copies
+    std::vector<double> bez;     // [E][NBZ][4]: homogeneous rational Bezier net of the element
+    std::vector<int> pg;         // [E][2]: geometry degree in u and v
+    std::vector<double> lo, hi;  // [E][3]: box of the projected Bezier control points
+    std::vector<double> corner;  // [E][4][3]: physical corners at local (0,0),(1,0),(0,1),(1,1)
+    std::vector<int> vert;       // [E][4]: global vertex id of each corner
+    std::vector<double> C1;      // [nel1][p+1][p+1]: b_{ex+a} = sum_k C1[ex][a][k] Bernstein_k
+    std::vector<int> s2_to_s0;   // [n2]
+    std::vector<int> s0_ptr;     // [n0+1]  S^0 dof -> its S^2 representatives
+    std::vector<int> s0_reps;    // [n2]
+    // device copies
+    igb::DevBuf d_bez, d_pg, d_C1;
+    size_t dev_bytes = 0;
+};
+
+// HIP-event timing of selected kernel launches (enabled per operator)
+struct KernelTimer {
+    std::vector<hipEvent_t> pool;   // pairs (start, stop)
+    size_t used = 0;                // events recorded since the last query
+};
+
+struct FarLevel {
+    int level = 0;
+    int64_t pair_off = 0;        // first far pair of this level (global pair index)
+    std::vector<int> tgt_ptr;    // CSR over target clusters of the level (npatch*4^l + 1)
+    std::vector<int> src;        // source cluster (local index in the level) per pair
+};
+
+struct igb_op_s {
+    igb_geom geom = nullptr;
+    igb_op_params prm{};
+    int bc = 0;
+    double kappa = 0, eta = 0;
+    int q = 0, nq = 0, L = 0, d = 0;
+    int64_t N = 0;
+    // cluster indexing: level l holds npatch * 4^l clusters starting at clu_off[l]
+    std::vector<int64_t> clu_off;
+    std::vector<double> clo, chi;     // [nclusters][3] boxes
+    std::vector<FarLevel> far;        // one entry per level 0..L
+    int64_t nfar = 0;
+    // near field: per target element the sorted near source elements
+    std::vector<int64_t> near_ptr;    // [E+1]
+    std::vector<int> near_src;
+    std::vector<int> near_kind;       // per near pair: 0 regular (order in bits 8..), 1 vertex,
+                                      // 2 edge, 4 identical; transforms in bits 16.. / 20..
+    // near CSR in the solution space
+    std::vector<int64_t> row_ptr;
+    std::vector<int> col;
+    int64_t nnz = 0;
+    // M2L work decomposition: chunks of at most M2L_CHUNK sources of one target
+    std::vector<int> chunk_tgt;       // global cluster index of the chunk's target
+    std::vector<int64_t> chunk_pair;  // first pair of the chunk
+    std::vector<int> chunk_len;
+    std::vector<int> tgt_chunk_ptr;   // [nclusters+1] chunks per target (global index)
+    // device data
+    igb::DevBuf d_coupling, d_nodes, d_m1, d_T;
+    igb::DevBuf d_rowptr, d_col, d_val;
+    igb::DevBuf d_near_ptr, d_near_src;
+    igb::DevBuf d_s2_to_s0, d_s0_ptr, d_s0_reps;
+    igb::DevBuf d_chunk_tgt, d_chunk_pair, d_chunk_len, d_tgt_chunk_ptr, d_far_src;
+    igb::DevBuf d_xhat, d_yhat, d_part, d_yfar, d_x2, d_cluoff;
+    size_t dev_bytes = 0;
+    int64_t nclusters = 0;
+    // solver scratch
+    igb::DevBuf d_krylov, d_w, d_h, d_b;
+    int krylov_cols = 0;
+    double t_assembly_near = 0, t_assembly_far = 0;
+    // per-kernel timing: 0 m2l, 1 spmv, 2 upward, 3 downward
+    bool profile = false;
+    KernelTimer timers[4];
+    ~igb_op_s() {
+        for (auto& t : timers)
+            for (hipEvent_t e : t.pool) (void)hipEventDestroy(e);
+    }
+};
+
+namespace igb {
+
+// host stages
+igb_status geometry_build(igb_ctx ctx, const igb_patch* patches, int npatch, int m, int p,
+                          igb_geom g);
+igb_status tree_build(igb_op op);
+igb_status near_classify(igb_op op);
+igb_status near_pattern(igb_op op);
+
+// device stages (kernels.hip)
+igb_status upload_geometry(igb_geom g);
+igb_status assemble_near_device(igb_op op, hipStream_t s);
+igb_status assemble_far_device(igb_op op, hipStream_t s);
+igb_status alloc_work(igb_op op, int nrhs);
+igb_status matvec_device(igb_op op, const double* x, double* y, int nrhs, int parts,
+                         hipStream_t s);
+igb_status rhs_device(igb_op op, const double* dirs, int ndir, double* b, hipStream_t s);
+igb_status farfield_device(igb_op op, const double* coeffs, int ndir, const double* obs,
+                           int nobs, double* uinf, hipStream_t s);
+igb_status gmres_device(igb_op op, const double* b, double* x, int ndir,
+                        const igb_solve_params* sp, igb_solve_info* info, hipStream_t s);
+
+// kernel timing helpers (no-ops unless op->profile)
+igb_status timer_mark(igb_op op, int slot, hipStream_t s);
+// admissibility helpers
+inline int64_t clusters_on_level(int npatch, int l) { return int64_t(npatch) << (2 * l); }
+
+// Chebyshev points of the first kind on [0,1]
+void cheb_nodes(int q, double* t);
+
+}  // namespace igb

@@ -1,0 +1,1471 @@
+// Device side of the igafmm library (gfx950): near-field quadrature, coupling
+// assembly, the H^2 matrix-vector pipeline, right-hand sides and far field.
+// All floating point is fp64; complex values are double2 (re, im).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace igb {
+
+// --------------------------------------------------------------------------
+// small device helpers
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// c + a * b
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {
+    return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// Bernstein polynomials of degree p <= 3 on [0,1] and their derivatives
+__device__ __forceinline__ void bernstein(int p, double s, double* b, double* db) {
+    const double t = 1.0 - s;
+    if (p == 0) {
+        b[0] = 1; db[0] = 0;
+    } else if (p == 1) {
+        b[0] = t; b[1] = s; db[0] = -1; db[1] = 1;
+    } else if (p == 2) {
+        b[0] = t * t; b[1] = 2 * s * t; b[2] = s * s;
+        db[0] = -2 * t; db[1] = 2 * (t - s); db[2] = 2 * s;
+    } else {
+        b[0] = t * t * t; b[1] = 3 * s * t * t; b[2] = 3 * s * s * t; b[3] = s * s * s;
+        db[0] = -3 * t * t; db[1] = 3 * t * t - 6 * s * t; db[2] = 6 * s * t - 3 * s * s; db[3] = 3 * s * s;
+    }
+}
+
+struct GeoPt {
+    double x[3];   // F
+    double fs[3];  // dF/ds (element-local)
+    double ft[3];  // dF/dt
+};
+
+// rational Bezier element map at local (s, t)
+__device__ __forceinline__ void eval_geo(const double* __restrict__ bez, int pu, int pv, double s,
+                                         double t, GeoPt& g) {
+    double bu[4], dbu[4], bv[4], dbv[4];
+    bernstein(pu, s, bu, dbu);
+    bernstein(pv, t, bv, dbv);
+    double P[4] = {0, 0, 0, 0}, Ps[4] = {0, 0, 0, 0}, Pt[4] = {0, 0, 0, 0};
+    for (int j = 0; j <= pv; ++j) {
+        double rP[4] = {0, 0, 0, 0}, rPs[4] = {0, 0, 0, 0};
+        for (int i = 0; i <= pu; ++i) {
+            const double* H = bez + (j * (PGMAX + 1) + i) * 4;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                rP[c] = fma(bu[i], H[c], rP[c]);
+                rPs[c] = fma(dbu[i], H[c], rPs[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            P[c] = fma(bv[j], rP[c], P[c]);
+            Ps[c] = fma(bv[j], rPs[c], Ps[c]);
+            Pt[c] = fma(dbv[j], rP[c], Pt[c]);
+        }
+    }
+    const double iw = 1.0 / P[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        g.x[c] = P[c] * iw;
+        g.fs[c] = (Ps[c] - g.x[c] * Ps[3]) * iw;
+        g.ft[c] = (Pt[c] - g.x[c] * Pt[3]) * iw;
+    }
+}
+
+__device__ __forceinline__ void cross3(const double* a, const double* b, double* c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// local B-splines b_{ex+a}(s), a = 0..p, from the element's extraction rows
+template <int P>
+__device__ __forceinline__ void eval_basis1(const double* __restrict__ C, double s, double* phi, double* dphi) {
+    double b[4], db[4];
+    bernstein(P, s, b, db);
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        double v = 0, d = 0;
+#pragma unroll
+        for (int k = 0; k <= P; ++k) {
+            v = fma(C[a * (P + 1) + k], b[k], v);
+            d = fma(C[a * (P + 1) + k], db[k], d);
+        }
+        phi[a] = v;
+        if (dphi) dphi[a] = d;
+    }
+}
+
+__device__ __forceinline__ void d4_apply(int code, double s, double t, double& a, double& b) {
+    a = s;
+    b = t;
+    if (code & 4) {
+        double x = a;
+        a = b;
+        b = x;
+    }
+    if (code & 1) a = 1.0 - a;
+    if (code & 2) b = 1.0 - b;
+}
+
+struct ElemRef {
+    const double* bez;
+    int pu, pv, ex, ey;
+};
+
+__device__ __forceinline__ ElemRef elem_ref(const double* bez, const int* pg, int nel1, int64_t e) {
+    ElemRef r;
+    r.bez = bez + e * NBZ * 4;
+    r.pu = pg[2 * e];
+    r.pv = pg[2 * e + 1];
+    int64_t rem = e % (int64_t(nel1) * nel1);
+    r.ey = int(rem / nel1);
+    r.ex = int(rem % nel1);
+    return r;
+}
+
+// The pulled-back sound-soft CFIE kernel  a_y H (x-y).n~_x - i eta a_x a_y G
+// with G = e^{i kappa r}/(4 pi r), H = G (i kappa r - 1)/r^2 (Sec. 4.2, eq. of
+// the pulled-back kernel, applied to K* and V of the D2N system).
+__device__ __forceinline__ double2 kernel_soft(const double* X, const double* NX, double ax,
+                                               const double* Y, double ay, double kappa, double eta) {
+    const double d0 = X[0] - Y[0], d1 = X[1] - Y[1], d2 = X[2] - Y[2];
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    const double r = sqrt(r2);
+    const double ir = 1.0 / r;
+    const double kr = kappa * r;
+    double sn, cs;
+    sincos(kr, &sn, &cs);
+    const double dn = d0 * NX[0] + d1 * NX[1] + d2 * NX[2];
+    const double c4 = 0.07957747154594767 * ir;  // 1/(4 pi r)
+    const double h = ay * dn * ir * ir * c4;       // a_y (x-y).n~_x / (4 pi r^3)
+    const double v = eta * ax * ay * c4;
+    return make_double2(h * (-cs - sn * kr) + v * sn, h * (cs * kr - sn) - v * cs);
+}
+
+// --------------------------------------------------------------------------
+// Near field: regular element pairs (tensor Gauss of order n on both elements)
+// --------------------------------------------------------------------------
+constexpr int NEAR_THREADS = 256;
+constexpr int NGMAX = 10;
+
+struct NearArgs {
+    const double* bez;
+    const int* pg;
+    const double* C1;
+    const double* gl;        // [NGMAX+1][2][NGMAX]: Gauss nodes / weights on [0,1] per order
+    const int* pair_e;       // near pair -> target element
+    const int* pair_f;       // near pair -> source element
+    const int* pair_kind;
+    const int* list;         // near pairs handled by this launch
+    int64_t nlist;
+    int64_t slot0;           // staging slot = pair - slot0
+    double2* stage;          // [slots][nloc*nloc]
+    int nel1;
+    double kappa, eta;
+    // singular rules: per class (0 vertex, 1 edge, 2 identical) points (s1,s2,r1,r2,w)
+    const double* rule[3];
+    int rule_n[3];
+    int mass_order;
+};
+
+template <int P>
+__global__ __launch_bounds__(NEAR_THREADS) void near_regular_soft(NearArgs A) {
+    constexpr int NL = (P + 1) * (P + 1);
+    constexpr int MAXQ = 64;  // n <= 8
+    __shared__ double xg[MAXQ][8];
+    __shared__ double yg[MAXQ][8];
+    __shared__ double px[MAXQ][NL];
+    __shared__ double py[MAXQ][NL];
+    __shared__ double2 tp[NEAR_THREADS * NL];
+
+    const int64_t item = blockIdx.x;
+    if (item >= A.nlist) return;
+    const int k = A.list[item];
+    const int e = A.pair_e[k], f = A.pair_f[k];
+    const int n = (A.pair_kind[k] >> 8) & 15;
+    const int nn = n * n;
+    const double* gx = A.gl + n * 2 * NGMAX;
+    const double* gw = gx + NGMAX;
+    const int tid = threadIdx.x;
+
+    if (tid < 2 * nn) {
+        const bool isx = tid < nn;
+        const int i = isx ? tid : tid - nn;
+        const double s = gx[i % n], t = gx[i / n];
+        const double w = gw[i % n] * gw[i / n];
+        ElemRef R = elem_ref(A.bez, A.pg, A.nel1, isx ? e : f);
+        GeoPt G;
+        eval_geo(R.bez, R.pu, R.pv, s, t, G);
+        double nt[3];
+        cross3(G.fs, G.ft, nt);
+        double* dst = isx ? xg[i] : yg[i];
+        dst[0] = G.x[0]; dst[1] = G.x[1]; dst[2] = G.x[2];
+        dst[3] = nt[0]; dst[4] = nt[1]; dst[5] = nt[2];
+        dst[6] = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+        double bu[P + 1], bv[P + 1];
+        eval_basis1<P>(A.C1 + R.ex * (P + 1) * (P + 1), s, bu, nullptr);
+        eval_basis1<P>(A.C1 + R.ey * (P + 1) * (P + 1), t, bv, nullptr);
+        double* ph = isx ? px[i] : py[i];
+#pragma unroll
+        for (int av = 0; av <= P; ++av)
+#pragma unroll
+            for (int au = 0; au <= P; ++au) ph[av * (P + 1) + au] = w * bv[av] * bu[au];
+    }
+    __syncthreads();
+
+    // T[j][a] = sum_i px[i][a] k(x_i, y_j), split over G groups of x-points
+    const int G = NEAR_THREADS / nn;
+    const int j = tid % nn, grp = tid / nn;
+    if (grp < G) {
+        double2 acc[NL];
+#pragma unroll
+        for (int a = 0; a < NL; ++a) acc[a] = make_double2(0, 0);
+        const double* Y = yg[j];
+        for (int i = grp; i < nn; i += G) {
+            const double2 kv = kernel_soft(xg[i], xg[i] + 3, xg[i][6], Y, Y[6], A.kappa, A.eta);
+#pragma unroll
+            for (int a = 0; a < NL; ++a) {
+                acc[a].x = fma(px[i][a], kv.x, acc[a].x);
+                acc[a].y = fma(px[i][a], kv.y, acc[a].y);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NL; ++a) tp[(grp * nn + j) * NL + a] = acc[a];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nn * NL; idx += NEAR_THREADS) {
+        double2 s = make_double2(0, 0);
+        for (int g2 = 0; g2 < G; ++g2) s = cadd(s, tp[g2 * nn * NL + idx]);
+        tp[idx] = s;
+    }
+    __syncthreads();
+    if (tid < NL * NL) {
+        const int a = tid / NL, b = tid % NL;
+        double2 s = make_double2(0, 0);
+        for (int jj = 0; jj < nn; ++jj) {
+            const double2 t = tp[jj * NL + a];
+            s.x = fma(t.x, py[jj][b], s.x);
+            s.y = fma(t.y, py[jj][b], s.y);
+        }
+        A.stage[(int64_t(k) - A.slot0) * NL * NL + tid] = s;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Near field: touching element pairs (Duffy-type rules on [0,1]^4)
+// --------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(NEAR_THREADS) void near_singular_soft(NearArgs A) {
+    constexpr int NL = (P + 1) * (P + 1);
+    constexpr int SPLIT = NEAR_THREADS / (NL * NL) > 0 ? NEAR_THREADS / (NL * NL) : 1;
+    __shared__ double2 kq[NEAR_THREADS];
+    __shared__ double px[NEAR_THREADS][NL];
+    __shared__ double py[NEAR_THREADS][NL];
+    __shared__ double2 red[NEAR_THREADS];
+
+    const int64_t item = blockIdx.x;
+    if (item >= A.nlist) return;
+    const int k = A.list[item];
+    const int e = A.pair_e[k], f = A.pair_f[k];
+    const int kind = A.pair_kind[k];
+    const int cls = kind & 15;
+    const int te = (kind >> 16) & 7, tf = (kind >> 20) & 7;
+    const int ri = cls == 4 ? 2 : cls == 2 ? 1 : 0;
+    const double* rule = A.rule[ri];
+    const int Q = A.rule_n[ri];
+    const int tid = threadIdx.x;
+    const ElemRef Re = elem_ref(A.bez, A.pg, A.nel1, e);
+    const ElemRef Rf = elem_ref(A.bez, A.pg, A.nel1, f);
+    const double* Ce_u = A.C1 + Re.ex * (P + 1) * (P + 1);
+    const double* Ce_v = A.C1 + Re.ey * (P + 1) * (P + 1);
+    const double* Cf_u = A.C1 + Rf.ex * (P + 1) * (P + 1);
+    const double* Cf_v = A.C1 + Rf.ey * (P + 1) * (P + 1);
+
+    const int out = tid % (NL * NL), part = tid / (NL * NL);
+    const int oa = out / NL, ob = out % NL;
+    double2 acc = make_double2(0, 0);
+    for (int base = 0; base < Q; base += NEAR_THREADS) {
+        const int qi = base + tid;
+        if (qi < Q) {
+            const double* r = rule + int64_t(qi) * 5;
+            double s, t, u, v;
+            d4_apply(te, r[0], r[1], s, t);
+            d4_apply(tf, r[2], r[3], u, v);
+            GeoPt gx, gy;
+            eval_geo(Re.bez, Re.pu, Re.pv, s, t, gx);
+            eval_geo(Rf.bez, Rf.pu, Rf.pv, u, v, gy);
+            double nx[3], ny[3];
+            cross3(gx.fs, gx.ft, nx);
+            cross3(gy.fs, gy.ft, ny);
+            const double ax = sqrt(nx[0] * nx[0] + nx[1] * nx[1] + nx[2] * nx[2]);
+            const double ay = sqrt(ny[0] * ny[0] + ny[1] * ny[1] + ny[2] * ny[2]);
+            kq[tid] = cscale(kernel_soft(gx.x, nx, ax, gy.x, ay, A.kappa, A.eta), r[4]);
+            double bu[P + 1], bv[P + 1];
+            eval_basis1<P>(Ce_u, s, bu, nullptr);
+            eval_basis1<P>(Ce_v, t, bv, nullptr);
+#pragma unroll
+            for (int av = 0; av <= P; ++av)
+#pragma unroll
+                for (int au = 0; au <= P; ++au) px[tid][av * (P + 1) + au] = bv[av] * bu[au];
+            eval_basis1<P>(Cf_u, u, bu, nullptr);
+            eval_basis1<P>(Cf_v, v, bv, nullptr);
+#pragma unroll
+            for (int av = 0; av <= P; ++av)
+#pragma unroll
+                for (int au = 0; au <= P; ++au) py[tid][av * (P + 1) + au] = bv[av] * bu[au];
+        } else {
+            kq[tid] = make_double2(0, 0);
+#pragma unroll
+            for (int a = 0; a < NL; ++a) {
+                px[tid][a] = 0;
+                py[tid][a] = 0;
+            }
+        }
+        __syncthreads();
+        if (part < SPLIT) {
+            for (int q = part; q < NEAR_THREADS; q += SPLIT) {
+                const double w = px[q][oa] * py[q][ob];
+                acc.x = fma(w, kq[q].x, acc.x);
+                acc.y = fma(w, kq[q].y, acc.y);
+            }
+        }
+        __syncthreads();
+    }
+    red[tid] = acc;
+    __syncthreads();
+    if (tid < NL * NL) {
+        double2 s = make_double2(0, 0);
+        for (int g2 = 0; g2 < SPLIT; ++g2) s = cadd(s, red[g2 * NL * NL + tid]);
+        if (cls == 4) {
+            // + 1/2 mass matrix on the identical pair: int phi_a phi_b a
+            const int n = A.mass_order;
+            const double* gx = A.gl + n * 2 * NGMAX;
+            const double* gw = gx + NGMAX;
+            double m = 0;
+            for (int i = 0; i < n * n; ++i) {
+                const double ss = gx[i % n], tt = gx[i / n];
+                GeoPt G;
+                eval_geo(Re.bez, Re.pu, Re.pv, ss, tt, G);
+                double nt[3];
+                cross3(G.fs, G.ft, nt);
+                double bu[P + 1], bv[P + 1], cu[P + 1], cv[P + 1];
+                eval_basis1<P>(Ce_u, ss, bu, nullptr);
+                eval_basis1<P>(Ce_v, tt, bv, nullptr);
+                (void)cu; (void)cv;
+                const double pa = bv[oa / (P + 1)] * bu[oa % (P + 1)];
+                const double pb = bv[ob / (P + 1)] * bu[ob % (P + 1)];
+                m += gw[i % n] * gw[i / n] * sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]) * pa * pb;
+            }
+            s.x += 0.5 * m;
+        }
+        A.stage[(int64_t(k) - A.slot0) * NL * NL + tid] = s;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Near field: deterministic gather of the staged element blocks into the CSR
+// values of the solution space.  One workgroup per row; each nonzero sums its
+// contributions in a fixed order (representatives, elements, source elements).
+// --------------------------------------------------------------------------
+struct CsrArgs {
+    const int64_t* row_ptr;
+    const int* col;
+    double2* val;
+    const int64_t* near_ptr;
+    const int* near_src;
+    const double2* stage;
+    int64_t slot0;
+    int64_t e_lo, e_hi;          // target elements whose pairs are staged
+    const int* s0_ptr;           // null for S^2 (soft)
+    const int* s0_reps;
+    int64_t row0;
+    int nel1, k;
+};
+
+template <int P>
+__global__ void near_gather_csr(CsrArgs A) {
+    constexpr int NL = (P + 1) * (P + 1);
+    const int64_t row = A.row0 + blockIdx.x;
+    const int64_t beg = A.row_ptr[row], end = A.row_ptr[row + 1];
+    const int64_t kk = int64_t(A.k) * A.k;
+    const int r0 = A.s0_ptr ? A.s0_ptr[row] : int(row);
+    const int r1 = A.s0_ptr ? A.s0_ptr[row + 1] : int(row) + 1;
+    for (int64_t idx = beg + threadIdx.x; idx < end; idx += blockDim.x) {
+        const int colv = A.col[idx];
+        const int c0 = A.s0_ptr ? A.s0_ptr[colv] : colv;
+        const int c1 = A.s0_ptr ? A.s0_ptr[colv + 1] : colv + 1;
+        double2 acc = make_double2(0, 0);
+        for (int ri = r0; ri < r1; ++ri) {
+            const int64_t i = A.s0_ptr ? A.s0_reps[ri] : ri;
+            const int pj = int(i / kk), rem = int(i % kk), iv = rem / A.k, iu = rem % A.k;
+            for (int ey = max(0, iv - P); ey <= min(iv, A.nel1 - 1); ++ey)
+                for (int ex = max(0, iu - P); ex <= min(iu, A.nel1 - 1); ++ex) {
+                    const int64_t e = (int64_t(pj) * A.nel1 + ey) * A.nel1 + ex;
+                    if (e < A.e_lo || e >= A.e_hi) continue;
+                    const int a = (iv - ey) * (P + 1) + (iu - ex);
+                    const int64_t nb = A.near_ptr[e], ne = A.near_ptr[e + 1];
+                    for (int ci = c0; ci < c1; ++ci) {
+                        const int64_t j = A.s0_ptr ? A.s0_reps[ci] : ci;
+                        const int qj = int(j / kk), rj = int(j % kk), jv = rj / A.k, ju = rj % A.k;
+                        for (int fy = max(0, jv - P); fy <= min(jv, A.nel1 - 1); ++fy)
+                            for (int fx = max(0, ju - P); fx <= min(ju, A.nel1 - 1); ++fx) {
+                                const int f = int((int64_t(qj) * A.nel1 + fy) * A.nel1 + fx);
+                                int64_t lo = nb, hi = ne;
+                                while (lo < hi) {
+                                    int64_t mid = (lo + hi) >> 1;
+                                    if (A.near_src[mid] < f) lo = mid + 1;
+                                    else hi = mid;
+                                }
+                                if (lo < ne && A.near_src[lo] == f) {
+                                    const int b = (jv - fy) * (P + 1) + (ju - fx);
+                                    acc = cadd(acc, A.stage[(lo - A.slot0) * NL * NL + a * NL + b]);
+                                }
+                            }
+                    }
+                }
+        }
+        A.val[idx] = cadd(A.val[idx], acc);
+    }
+}
+
+// --------------------------------------------------------------------------
+// Far field: node geometry and coupling matrices
+// --------------------------------------------------------------------------
+// Per cluster and Chebyshev node: x(3), n~(3), a, 0, F_u(3), F_v(3), 0, 0 with
+// derivatives w.r.t. the patch parameters.
+__global__ void node_geometry(const double* bez, const int* pg, int nel1, int npatch, int L,
+                              const int64_t* clu_off, const double* tnodes, int q, double* nodes) {
+    const int nq = (q + 1) * (q + 1);
+    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t total = clu_off[L + 1] * nq;
+    if (gid >= total) return;
+    const int64_t c = gid / nq;
+    const int a = int(gid % nq);
+    int l = 0;
+    while (clu_off[l + 1] <= c) ++l;
+    const int64_t loc = c - clu_off[l];
+    const int n = 1 << l;
+    const int patch = int(loc / (int64_t(n) * n));
+    const int rem = int(loc % (int64_t(n) * n));
+    const int cy = rem / n, cx = rem % n;
+    const double u = (cx + tnodes[a % (q + 1)]) / n, v = (cy + tnodes[a / (q + 1)]) / n;
+    const int ex = min(int(u * nel1), nel1 - 1), ey = min(int(v * nel1), nel1 - 1);
+    const int64_t e = (int64_t(patch) * nel1 + ey) * nel1 + ex;
+    GeoPt G;
+    eval_geo(bez + e * NBZ * 4, pg[2 * e], pg[2 * e + 1], u * nel1 - ex, v * nel1 - ey, G);
+    double fu[3], fv[3], nt[3];
+    for (int i = 0; i < 3; ++i) {
+        fu[i] = G.fs[i] * nel1;
+        fv[i] = G.ft[i] * nel1;
+    }
+    cross3(fu, fv, nt);
+    double* o = nodes + gid * 16;
+    o[0] = G.x[0]; o[1] = G.x[1]; o[2] = G.x[2];
+    o[3] = nt[0]; o[4] = nt[1]; o[5] = nt[2];
+    o[6] = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+    o[7] = 0;
+    o[8] = fu[0]; o[9] = fu[1]; o[10] = fu[2];
+    o[11] = fv[0]; o[12] = fv[1]; o[13] = fv[2];
+    o[14] = 0; o[15] = 0;
+}
+
+// coupling[pair][b*nq + a] = k(x_a of target, y_b of source)
+__global__ void coupling_soft(const double* nodes, const int* pair_tgt, const int* pair_src,
+                              int64_t npairs, int nq, double kappa, double eta, double2* coup) {
+    const int64_t pr = blockIdx.x;
+    if (pr >= npairs) return;
+    const double* T = nodes + int64_t(pair_tgt[pr]) * nq * 16;
+    const double* S = nodes + int64_t(pair_src[pr]) * nq * 16;
+    double2* out = coup + pr * nq * nq;
+    for (int idx = threadIdx.x; idx < nq * nq; idx += blockDim.x) {
+        const int b = idx / nq, a = idx % nq;
+        const double* X = T + a * 16;
+        const double* Y = S + b * 16;
+        out[idx] = kernel_soft(X, X + 3, X[6], Y, Y[6], kappa, eta);
+    }
+}
+
+// --------------------------------------------------------------------------
+// H^2 matrix-vector pipeline
+// --------------------------------------------------------------------------
+// x2[i] = x0[s2_to_s0[i]]  (S^0 -> S^2 injection)
+__global__ void glue_gather(const int* s2_to_s0, const double2* x0, double2* x2, int64_t n2) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n2) x2[i] = x0[s2_to_s0[i]];
+}
+
+// leaf moments  xh[leaf][a] = sum_{window} m1[cy][av][iv] m1[cx][au][iu] x[patch][iv][iu]
+__global__ void leaf_moments(const double2* x, const double* m1, int q, int d, int p, int L,
+                             int k, int64_t leaf_off, int64_t nleaf, double2* xh, int deriv_u,
+                             int deriv_v, int64_t m1_stride_kind) {
+    const int nq = (q + 1) * (q + 1);
+    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= nleaf * nq) return;
+    const int64_t c = gid / nq;
+    const int a = int(gid % nq), au = a % (q + 1), av = a / (q + 1);
+    const int n = 1 << L, s = 1 << d, w = s + p;
+    const int patch = int(c / (int64_t(n) * n));
+    const int rem = int(c % (int64_t(n) * n));
+    const int cy = rem / n, cx = rem % n;
+    const double* mu = m1 + deriv_u * m1_stride_kind + (int64_t(cx) * (q + 1) + au) * w;
+    const double* mv = m1 + deriv_v * m1_stride_kind + (int64_t(cy) * (q + 1) + av) * w;
+    const double2* X = x + int64_t(patch) * k * k + int64_t(cy) * s * k + int64_t(cx) * s;
+    double2 acc = make_double2(0, 0);
+    for (int iv = 0; iv < w; ++iv) {
+        double2 row = make_double2(0, 0);
+        for (int iu = 0; iu < w; ++iu) {
+            const double2 xv = X[int64_t(iv) * k + iu];
+            row.x = fma(mu[iu], xv.x, row.x);
+            row.y = fma(mu[iu], xv.y, row.y);
+        }
+        acc.x = fma(mv[iv], row.x, acc.x);
+        acc.y = fma(mv[iv], row.y, acc.y);
+    }
+    xh[(leaf_off + c) * nq + a] = acc;
+}
+
+// upward: xh[parent][a] = sum_children sum_g T_c[g][a] xh[child][g]
+__global__ void m2m(const double* T1, int q, int l, const int64_t* clu_off, double2* xh) {
+    const int nq = (q + 1) * (q + 1), q1 = q + 1;
+    const int64_t nc = clu_off[l + 1] - clu_off[l];
+    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= nc * nq) return;
+    const int64_t c = gid / nq;
+    const int a = int(gid % nq), au = a % q1, av = a / q1;
+    const int n = 1 << l;
+    const int patch = int(c / (int64_t(n) * n));
+    const int rem = int(c % (int64_t(n) * n));
+    const int cy = rem / n, cx = rem % n;
+    double2 acc = make_double2(0, 0);
+    for (int ch = 0; ch < 4; ++ch) {
+        const int bu = ch & 1, bv = ch >> 1;
+        const int64_t child = clu_off[l + 1] + (int64_t(patch) << (2 * (l + 1))) +
+                              (int64_t(2 * cy + bv) << (l + 1)) + 2 * cx + bu;
+        const double* Tu = T1 + bu * q1 * q1;
+        const double* Tv = T1 + bv * q1 * q1;
+        const double2* X = xh + child * nq;
+        for (int gv = 0; gv < q1; ++gv) {
+            double2 row = make_double2(0, 0);
+            for (int gu = 0; gu < q1; ++gu) {
+                const double2 xv = X[gv * q1 + gu];
+                const double t = Tu[gu * q1 + au];
+                row.x = fma(t, xv.x, row.x);
+                row.y = fma(t, xv.y, row.y);
+            }
+            const double t = Tv[gv * q1 + av];
+            acc.x = fma(t, row.x, acc.x);
+            acc.y = fma(t, row.y, acc.y);
+        }
+    }
+    xh[(clu_off[l] + c) * nq + a] = acc;
+}
+
+// coupling: one workgroup per chunk of source clusters of one target
+template <int NT>
+__global__ __launch_bounds__(NT) void m2l_chunks(const double2* __restrict__ coup,
+                                                 const double2* __restrict__ xh,
+                                                 const int* __restrict__ far_src_g,
+                                                 const int64_t* __restrict__ chunk_pair,
+                                                 const int* __restrict__ chunk_len, int64_t nchunk,
+                                                 int nq, double2* __restrict__ part) {
+    __shared__ double2 xs[NT];
+    const int64_t ch = blockIdx.x;
+    if (ch >= nchunk) return;
+    const int a = threadIdx.x;
+    const int64_t p0 = chunk_pair[ch];
+    const int len = chunk_len[ch];
+    double2 acc = make_double2(0, 0);
+    for (int i = 0; i < len; ++i) {
+        const int64_t pr = p0 + i;
+        __syncthreads();
+        if (a < nq) xs[a] = xh[int64_t(far_src_g[pr]) * nq + a];
+        __syncthreads();
+        if (a < nq) {
+            const double2* K = coup + pr * nq * nq + a;
+#pragma unroll 7
+            for (int b = 0; b < nq; ++b) acc = cfma(K[int64_t(b) * nq], xs[b], acc);
+        }
+    }
+    if (a < nq) part[ch * nq + a] = acc;
+}
+
+// yh[c][a] = sum over the target's chunks (fixed order); zero if none
+__global__ void m2l_reduce(const double2* part, const int* tgt_chunk_ptr, int64_t nclusters, int nq,
+                           double2* yh) {
+    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= nclusters * nq) return;
+    const int64_t c = gid / nq;
+    const int a = int(gid % nq);
+    double2 s = make_double2(0, 0);
+    for (int ch = tgt_chunk_ptr[c]; ch < tgt_chunk_ptr[c + 1]; ++ch) s = cadd(s, part[int64_t(ch) * nq + a]);
+    yh[gid] = s;
+}
+
+// downward: yh[child][g] += sum_a T_c[g][a] yh[parent][a]
+__global__ void l2l(const double* T1, int q, int l /* parent level */, const int64_t* clu_off,
+                    double2* yh) {
+    const int nq = (q + 1) * (q + 1), q1 = q + 1;
+    const int64_t nc = clu_off[l + 2] - clu_off[l + 1];
+    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= nc * nq) return;
+    const int64_t c = gid / nq;
+    const int g = int(gid % nq), gu = g % q1, gv = g / q1;
+    const int n = 1 << (l + 1);
+    const int patch = int(c / (int64_t(n) * n));
+    const int rem = int(c % (int64_t(n) * n));
+    const int cy = rem / n, cx = rem % n;
+    const int bu = cx & 1, bv = cy & 1;
+    const int64_t parent = clu_off[l] + (int64_t(patch) << (2 * l)) + (int64_t(cy >> 1) << l) + (cx >> 1);
+    const double* Tu = T1 + bu * q1 * q1;
+    const double* Tv = T1 + bv * q1 * q1;
+    const double2* Y = yh + parent * nq;
+    double2 acc = make_double2(0, 0);
+    for (int av = 0; av < q1; ++av) {
+        double2 row = make_double2(0, 0);
+        for (int au = 0; au < q1; ++au) {
+            const double2 yv = Y[av * q1 + au];
+            const double t = Tu[gu * q1 + au];
+            row.x = fma(t, yv.x, row.x);
+            row.y = fma(t, yv.y, row.y);
+        }
+        const double t = Tv[gv * q1 + av];
+        acc.x = fma(t, row.x, acc.x);
+        acc.y = fma(t, row.y, acc.y);
+    }
+    double2* dst = yh + (clu_off[l + 1] + c) * nq + g;
+    *dst = cadd(*dst, acc);
+}
+
+// back projection onto S^2: y[i] = sum_{leaves containing i} sum_a m1 m1 yh[leaf][a]
+__global__ void back_project(const double2* yh, const double* m1, int q, int d, int p, int L, int k,
+                             int npatch, int64_t leaf_off, double2* y, int deriv_u, int deriv_v,
+                             int64_t m1_stride_kind, int accumulate) {
+    const int64_t n2 = int64_t(npatch) * k * k;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n2) return;
+    const int q1 = q + 1, nq = q1 * q1;
+    const int patch = int(i / (int64_t(k) * k));
+    const int rem = int(i % (int64_t(k) * k));
+    const int iv = rem / k, iu = rem % k;
+    const int s = 1 << d, w = s + p, n = 1 << L;
+    double2 acc = make_double2(0, 0);
+    const int cy0 = max(0, (iv - w + s) / s), cy1 = min(n - 1, iv / s);
+    const int cx0 = max(0, (iu - w + s) / s), cx1 = min(n - 1, iu / s);
+    for (int cy = cy0; cy <= cy1; ++cy) {
+        const int lv = iv - cy * s;
+        if (lv < 0 || lv >= w) continue;
+        for (int cx = cx0; cx <= cx1; ++cx) {
+            const int lu = iu - cx * s;
+            if (lu < 0 || lu >= w) continue;
+            const double2* Y = yh + (leaf_off + (int64_t(patch) << (2 * L)) + int64_t(cy) * n + cx) * nq;
+            double2 sum = make_double2(0, 0);
+            for (int av = 0; av < q1; ++av) {
+                const double mv = m1[deriv_v * m1_stride_kind + (int64_t(cy) * q1 + av) * w + lv];
+                double2 row = make_double2(0, 0);
+                for (int au = 0; au < q1; ++au) {
+                    const double mu = m1[deriv_u * m1_stride_kind + (int64_t(cx) * q1 + au) * w + lu];
+                    row.x = fma(mu, Y[av * q1 + au].x, row.x);
+                    row.y = fma(mu, Y[av * q1 + au].y, row.y);
+                }
+                sum.x = fma(mv, row.x, sum.x);
+                sum.y = fma(mv, row.y, sum.y);
+            }
+            acc = cadd(acc, sum);
+        }
+    }
+    y[i] = accumulate ? cadd(y[i], acc) : acc;
+}
+
+// y[row] = sum_j val x[col] (+ far part mapped to the solution space); one wave
+// per row, lanes stride over the row, butterfly reduction (fixed order)
+__global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ row_ptr,
+                                                    const int* __restrict__ col,
+                                                    const double2* __restrict__ val,
+                                                    const double2* __restrict__ x, int64_t nrows,
+                                                    const double2* __restrict__ yfar,
+                                                    const int* __restrict__ s0_ptr,
+                                                    const int* __restrict__ s0_reps, int use_near,
+                                                    double2* __restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    if (row >= nrows) return;
+    double2 acc = make_double2(0, 0);
+    if (use_near) {
+        const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+        for (int64_t idx = b + lane; idx < e; idx += 64) acc = cfma(val[idx], x[col[idx]], acc);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        acc.x += __shfl_xor(acc.x, off, 64);
+        acc.y += __shfl_xor(acc.y, off, 64);
+    }
+    if (lane == 0) {
+        if (yfar) {
+            if (s0_ptr) {
+                for (int r = s0_ptr[row]; r < s0_ptr[row + 1]; ++r) acc = cadd(acc, yfar[s0_reps[r]]);
+            } else {
+                acc = cadd(acc, yfar[row]);
+            }
+        }
+        y[row] = acc;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Right-hand sides and far field
+// --------------------------------------------------------------------------
+struct QuadGeoArgs {
+    const double* bez;
+    const int* pg;
+    const double* C1;
+    const double* gl;
+    int nel1, p, n;
+    int64_t nelem;
+};
+
+// per element: sum_g w_g f(x_g) phi_a(x_g) for each direction; f from the BC
+template <int P>
+__global__ void rhs_elements(QuadGeoArgs A, const double* dirs, int ndir, double kappa, double eta,
+                             int hard, double2* loc /* [ndir][E][NL] */) {
+    constexpr int NL = (P + 1) * (P + 1);
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int dir = blockIdx.y;
+    if (e >= A.nelem || dir >= ndir) return;
+    const ElemRef R = elem_ref(A.bez, A.pg, A.nel1, e);
+    const double* gx = A.gl + A.n * 2 * NGMAX;
+    const double* gw = gx + NGMAX;
+    const double* d = dirs + 3 * dir;
+    double2 acc[NL];
+    for (int a = 0; a < NL; ++a) acc[a] = make_double2(0, 0);
+    for (int i = 0; i < A.n * A.n; ++i) {
+        const double s = gx[i % A.n], t = gx[i / A.n];
+        const double w = gw[i % A.n] * gw[i / A.n];
+        GeoPt G;
+        eval_geo(R.bez, R.pu, R.pv, s, t, G);
+        double nt[3];
+        cross3(G.fs, G.ft, nt);
+        const double a = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+        const double dx = d[0] * G.x[0] + d[1] * G.x[1] + d[2] * G.x[2];
+        const double dn = d[0] * nt[0] + d[1] * nt[1] + d[2] * nt[2];
+        double sn, cs;
+        sincos(kappa * dx, &sn, &cs);
+        // soft: (i kappa d.n~ - i eta a) u_inc ; hard: (a + eta kappa d.n~) u_inc
+        double2 fval;
+        if (hard) {
+            const double c = a + eta * kappa * dn;
+            fval = make_double2(c * cs, c * sn);
+        } else {
+            const double c = kappa * dn - eta * a;  // i c u_inc
+            fval = make_double2(-c * sn, c * cs);
+        }
+        double bu[P + 1], bv[P + 1];
+        eval_basis1<P>(A.C1 + R.ex * (P + 1) * (P + 1), s, bu, nullptr);
+        eval_basis1<P>(A.C1 + R.ey * (P + 1) * (P + 1), t, bv, nullptr);
+        for (int av = 0; av <= P; ++av)
+            for (int au = 0; au <= P; ++au) {
+                const double ph = w * bv[av] * bu[au];
+                acc[av * (P + 1) + au].x = fma(ph, fval.x, acc[av * (P + 1) + au].x);
+                acc[av * (P + 1) + au].y = fma(ph, fval.y, acc[av * (P + 1) + au].y);
+            }
+    }
+    for (int a = 0; a < NL; ++a) loc[(int64_t(dir) * A.nelem + e) * NL + a] = acc[a];
+}
+
+// b[dir][row] = sum over representatives and their elements of loc (fixed order)
+template <int P>
+__global__ void rhs_gather(const double2* loc, int ndir, int64_t nelem, int nel1, int k, int64_t nrows,
+                           const int* s0_ptr, const int* s0_reps, double2* b) {
+    constexpr int NL = (P + 1) * (P + 1);
+    const int64_t row = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int dir = blockIdx.y;
+    if (row >= nrows) return;
+    const int64_t kk = int64_t(k) * k;
+    const int r0 = s0_ptr ? s0_ptr[row] : int(row);
+    const int r1 = s0_ptr ? s0_ptr[row + 1] : int(row) + 1;
+    double2 acc = make_double2(0, 0);
+    for (int ri = r0; ri < r1; ++ri) {
+        const int64_t i = s0_ptr ? s0_reps[ri] : ri;
+        const int pj = int(i / kk), rem = int(i % kk), iv = rem / k, iu = rem % k;
+        for (int ey = max(0, iv - P); ey <= min(iv, nel1 - 1); ++ey)
+            for (int ex = max(0, iu - P); ex <= min(iu, nel1 - 1); ++ex) {
+                const int64_t e = (int64_t(pj) * nel1 + ey) * nel1 + ex;
+                acc = cadd(acc, loc[(int64_t(dir) * nelem + e) * NL + (iv - ey) * (P + 1) + (iu - ex)]);
+            }
+    }
+    b[int64_t(dir) * nrows + row] = acc;
+}
+
+// boundary density and geometry at element quadrature points for far fields:
+// geo[e][g] = (x(3), n~(3), a, w), dens[dir][e][g]
+template <int P>
+__global__ void density_points(QuadGeoArgs A, const double2* coef, int ndir, int64_t n,
+                               const int* s2_to_s0, int k, double* geo, double2* dens) {
+    constexpr int NL = (P + 1) * (P + 1);
+    (void)NL;
+    const int nqp = A.n * A.n;
+    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= A.nelem * nqp) return;
+    const int64_t e = gid / nqp;
+    const int i = int(gid % nqp);
+    const ElemRef R = elem_ref(A.bez, A.pg, A.nel1, e);
+    const double* gx = A.gl + A.n * 2 * NGMAX;
+    const double* gw = gx + NGMAX;
+    const double s = gx[i % A.n], t = gx[i / A.n];
+    GeoPt G;
+    eval_geo(R.bez, R.pu, R.pv, s, t, G);
+    double nt[3];
+    cross3(G.fs, G.ft, nt);
+    double* o = geo + gid * 8;
+    o[0] = G.x[0]; o[1] = G.x[1]; o[2] = G.x[2];
+    o[3] = nt[0]; o[4] = nt[1]; o[5] = nt[2];
+    o[6] = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+    o[7] = gw[i % A.n] * gw[i / A.n];
+    double bu[P + 1], bv[P + 1];
+    eval_basis1<P>(A.C1 + R.ex * (P + 1) * (P + 1), s, bu, nullptr);
+    eval_basis1<P>(A.C1 + R.ey * (P + 1) * (P + 1), t, bv, nullptr);
+    const int64_t patch = e / (int64_t(A.nel1) * A.nel1);
+    for (int dir = 0; dir < ndir; ++dir) {
+        double2 acc = make_double2(0, 0);
+        for (int av = 0; av <= P; ++av)
+            for (int au = 0; au <= P; ++au) {
+                int64_t i2 = (patch * k + R.ey + av) * k + R.ex + au;
+                int64_t c = s2_to_s0 ? s2_to_s0[i2] : i2;
+                const double2 cv = coef[int64_t(dir) * n + c];
+                const double ph = bv[av] * bu[au];
+                acc.x = fma(ph, cv.x, acc.x);
+                acc.y = fma(ph, cv.y, acc.y);
+            }
+        dens[(int64_t(dir) * A.nelem) * nqp + gid] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void farfield_sum(const double* geo, const double2* dens,
+                                                    int64_t npts, const double* obs, int nobs,
+                                                    double kappa, int hard, double2* uinf) {
+    __shared__ double2 red[256];
+    const int o = blockIdx.x, dir = blockIdx.y;
+    const double* xh = obs + 3 * o;
+    const double2* D = dens + int64_t(dir) * npts;
+    double2 acc = make_double2(0, 0);
+    for (int64_t i = threadIdx.x; i < npts; i += 256) {
+        const double* g = geo + i * 8;
+        const double ph = -kappa * (xh[0] * g[0] + xh[1] * g[1] + xh[2] * g[2]);
+        double sn, cs;
+        sincos(ph, &sn, &cs);
+        const double wt = g[7] * (hard ? (xh[0] * g[3] + xh[1] * g[4] + xh[2] * g[5]) : g[6]);
+        const double2 z = cmul(make_double2(cs * wt, sn * wt), D[i]);
+        acc = cadd(acc, z);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double c = 1.0 / (4.0 * M_PI);
+        double2 r = red[0];
+        // soft: -(1/4pi) S ; hard: -(i kappa / 4pi) S
+        uinf[int64_t(dir) * nobs + o] = hard ? make_double2(c * kappa * r.y, -c * kappa * r.x)
+                                             : make_double2(-c * r.x, -c * r.y);
+    }
+}
+
+// ==========================================================================
+// host launchers
+// ==========================================================================
+namespace {
+
+template <class T>
+igb_status upload(DevBuf& b, const T* src, size_t n, size_t* acct) {
+    b.release();
+    if (n == 0) return IGB_OK;
+    IGB_HIP(hipMalloc(&b.ptr, n * sizeof(T)));
+    b.bytes = n * sizeof(T);
+    if (acct) *acct += b.bytes;
+    if (src) IGB_HIP(hipMemcpy(b.ptr, src, n * sizeof(T), hipMemcpyHostToDevice));
+    return IGB_OK;
+}
+
+igb_status alloc(DevBuf& b, size_t bytes, size_t* acct) {
+    b.release();
+    if (bytes == 0) return IGB_OK;
+    IGB_HIP(hipMalloc(&b.ptr, bytes));
+    b.bytes = bytes;
+    if (acct) *acct += bytes;
+    return IGB_OK;
+}
+
+std::vector<double> gauss_table() {
+    // Gauss-Legendre nodes / weights on [0,1] for orders 1..NGMAX by Newton's
+    // iteration on the Legendre recurrence
+    std::vector<double> t((NGMAX + 1) * 2 * NGMAX, 0.0);
+    for (int n = 1; n <= NGMAX; ++n) {
+        for (int i = 0; i < n; ++i) {
+            double x = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+            double dp = 1;
+            for (int it = 0; it < 100; ++it) {
+                double p0 = 1, p1 = x;
+                for (int k = 2; k <= n; ++k) {
+                    double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                if (n == 1) { p1 = x; p0 = 1; }
+                dp = n * (x * p1 - p0) / (x * x - 1);
+                double dx = p1 / dp;
+                x -= dx;
+                if (std::fabs(dx) < 1e-16) break;
+            }
+            double p0 = 1, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1);
+            t[n * 2 * NGMAX + i] = 0.5 * (1 - x);
+            t[n * 2 * NGMAX + NGMAX + i] = 1.0 / ((1 - x * x) * dp * dp);
+        }
+    }
+    return t;
+}
+
+void gauss01_host(int n, std::vector<double>& x, std::vector<double>& w) {
+    static std::vector<double> tab = gauss_table();
+    x.assign(tab.begin() + n * 2 * NGMAX, tab.begin() + n * 2 * NGMAX + n);
+    w.assign(tab.begin() + n * 2 * NGMAX + NGMAX, tab.begin() + n * 2 * NGMAX + NGMAX + n);
+}
+
+// Duffy-type rules on [0,1]^4 as (s1, s2, r1, r2, w) for the three touching
+// configurations (identical element; shared edge s2 = r2 = 0 with s1 = r1;
+// shared vertex at the origin).  Each coordinate pair (s, r) of the identical
+// and edge cases is written as offset u = |r - s| and position w in [0,1]
+// (Jacobian 1 - u); the singular corner of the remaining cube is removed by
+// splitting it into simplices / pyramids along its largest coordinate rho.
+std::vector<double> duffy_rule(int cls, int n) {
+    std::vector<double> gx, gw;
+    gauss01_host(n, gx, gw);
+    std::vector<double> out;
+    auto split = [](double u, double w, int sig, double& s, double& r) {
+        double base = w * (1 - u);
+        if (sig > 0) { s = base; r = base + u; }
+        else { s = base + u; r = base; }
+    };
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b)
+            for (int c = 0; c < n; ++c)
+                for (int d = 0; d < n; ++d) {
+                    const double rho = gx[a], t1 = gx[b], t2 = gx[c], t3 = gx[d];
+                    const double W = gw[a] * gw[b] * gw[c] * gw[d];
+                    if (cls == 2) {  // identical: 2 x 2 signs x 2 triangles
+                        for (int sg = 0; sg < 4; ++sg)
+                            for (int tri = 0; tri < 2; ++tri) {
+                                double u1 = tri ? rho * t1 : rho, u2 = tri ? rho : rho * t1;
+                                double s1, r1, s2, r2;
+                                split(u1, t2, (sg & 1) ? -1 : 1, s1, r1);
+                                split(u2, t3, (sg & 2) ? -1 : 1, s2, r2);
+                                out.insert(out.end(), {s1, s2, r1, r2, W * (1 - u1) * (1 - u2) * rho});
+                            }
+                    } else if (cls == 1) {  // edge: 2 signs x 3 pyramids
+                        for (int sg = 0; sg < 2; ++sg)
+                            for (int pyr = 0; pyr < 3; ++pyr) {
+                                double u1, s2, r2;
+                                if (pyr == 0) { u1 = rho; s2 = rho * t1; r2 = rho * t2; }
+                                else if (pyr == 1) { u1 = rho * t1; s2 = rho; r2 = rho * t2; }
+                                else { u1 = rho * t1; s2 = rho * t2; r2 = rho; }
+                                double s1, r1;
+                                split(u1, t3, sg ? -1 : 1, s1, r1);
+                                out.insert(out.end(), {s1, s2, r1, r2, W * (1 - u1) * rho * rho});
+                            }
+                    } else {  // vertex: 4 pyramids
+                        for (int pyr = 0; pyr < 4; ++pyr) {
+                            double c4[4];
+                            double rest[3] = {rho * t1, rho * t2, rho * t3};
+                            for (int i = 0, j = 0; i < 4; ++i) c4[i] = (i == pyr) ? rho : rest[j++];
+                            out.insert(out.end(), {c4[0], c4[1], c4[2], c4[3], W * rho * rho * rho});
+                        }
+                    }
+                }
+    return out;
+}
+
+}  // namespace
+
+igb_status upload_geometry(igb_geom g) {
+    size_t acct = 0;
+    igb_status st;
+    if ((st = upload(g->d_bez, g->bez.data(), g->bez.size(), &acct))) return st;
+    if ((st = upload(g->d_pg, g->pg.data(), g->pg.size(), &acct))) return st;
+    if ((st = upload(g->d_C1, g->C1.data(), g->C1.size(), &acct))) return st;
+    g->dev_bytes = acct;
+    return IGB_OK;
+}
+
+// orders of the GPU rules (see near_classify for the regular ones)
+constexpr int NSING_IDENT = 7, NSING_EDGE = 8, NSING_VERTEX = 9, MASS_ORDER = 6;
+
+template <int P>
+static igb_status near_launch(igb_op op, hipStream_t s) {
+    igb_geom g = op->geom;
+    constexpr int NL = (P + 1) * (P + 1);
+    const int64_t E = g->nelem;
+    const int64_t npairs = op->near_ptr[E];
+    size_t* acct = &op->dev_bytes;
+    igb_status st;
+    // pair arrays
+    std::vector<int> pe(npairs);
+    for (int64_t e = 0; e < E; ++e)
+        for (int64_t k = op->near_ptr[e]; k < op->near_ptr[e + 1]; ++k) pe[k] = int(e);
+    DevBuf d_pe, d_pf, d_kind, d_gl, d_rules[3], d_list, d_stage;
+    if ((st = upload(d_pe, pe.data(), pe.size(), nullptr))) return st;
+    if ((st = upload(d_pf, op->near_src.data(), op->near_src.size(), nullptr))) return st;
+    if ((st = upload(d_kind, op->near_kind.data(), op->near_kind.size(), nullptr))) return st;
+    std::vector<double> gl = gauss_table();
+    if ((st = upload(d_gl, gl.data(), gl.size(), nullptr))) return st;
+    const int ord[3] = {NSING_VERTEX, NSING_EDGE, NSING_IDENT};
+    NearArgs A{};
+    for (int c = 0; c < 3; ++c) {
+        std::vector<double> r = duffy_rule(c, ord[c]);
+        if ((st = upload(d_rules[c], r.data(), r.size(), nullptr))) return st;
+        A.rule[c] = d_rules[c].as<double>();
+        A.rule_n[c] = int(r.size() / 5);
+    }
+    if ((st = upload(op->d_near_ptr, op->near_ptr.data(), op->near_ptr.size(), acct))) return st;
+    if ((st = upload(op->d_near_src, op->near_src.data(), op->near_src.size(), acct))) return st;
+    if ((st = upload(op->d_rowptr, op->row_ptr.data(), op->row_ptr.size(), acct))) return st;
+    if ((st = upload(op->d_col, op->col.data(), op->col.size(), acct))) return st;
+    if ((st = alloc(op->d_val, op->nnz * sizeof(double2), acct))) return st;
+    IGB_HIP(hipMemsetAsync(op->d_val.ptr, 0, op->nnz * sizeof(double2), s));
+
+    A.bez = g->d_bez.as<double>();
+    A.pg = g->d_pg.as<int>();
+    A.C1 = g->d_C1.as<double>();
+    A.gl = d_gl.as<double>();
+    A.pair_e = d_pe.as<int>();
+    A.pair_f = d_pf.as<int>();
+    A.pair_kind = d_kind.as<int>();
+    A.nel1 = g->nel1;
+    A.kappa = op->kappa;
+    A.eta = op->eta;
+    A.mass_order = MASS_ORDER;
+
+    // chunks of target elements with a bounded staging buffer
+    const int64_t max_slots = std::max<int64_t>(int64_t(1) << 22, 1);  // 4M pairs
+    if ((st = alloc(d_stage, size_t(std::min(npairs, max_slots)) * NL * NL * sizeof(double2), nullptr)))
+        return st;
+    if ((st = alloc(d_list, size_t(std::min(npairs, max_slots)) * sizeof(int), nullptr))) return st;
+    A.stage = d_stage.as<double2>();
+    const bool hard = op->bc == IGB_HARD;
+    int64_t e0 = 0;
+    std::vector<int> reg, sing;
+    while (e0 < E) {
+        int64_t e1 = e0;
+        while (e1 < E && op->near_ptr[e1 + 1] - op->near_ptr[e0] <= max_slots) ++e1;
+        if (e1 == e0) {
+            set_error("assemble_nearfield: one element has more near pairs than the staging buffer");
+            return IGB_ERR_UNSUPPORTED;
+        }
+        const int64_t k0 = op->near_ptr[e0], k1 = op->near_ptr[e1];
+        reg.clear();
+        sing.clear();
+        for (int64_t k = k0; k < k1; ++k) ((op->near_kind[k] & 15) == 0 ? reg : sing).push_back(int(k));
+        A.slot0 = k0;
+        // regular pairs at the front of the list buffer, touching pairs behind them
+        std::vector<int> lst(reg);
+        lst.insert(lst.end(), sing.begin(), sing.end());
+        if (!lst.empty())
+            IGB_HIP(hipMemcpyAsync(d_list.ptr, lst.data(), lst.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        if (!reg.empty()) {
+            A.list = d_list.as<int>();
+            A.nlist = int64_t(reg.size());
+            hipLaunchKernelGGL(near_regular_soft<P>, dim3(unsigned(reg.size())), dim3(NEAR_THREADS), 0, s, A);
+            IGB_HIP(hipGetLastError());
+        }
+        if (!sing.empty()) {
+            A.list = d_list.as<int>() + reg.size();
+            A.nlist = int64_t(sing.size());
+            hipLaunchKernelGGL(near_singular_soft<P>, dim3(unsigned(sing.size())), dim3(NEAR_THREADS), 0, s, A);
+            IGB_HIP(hipGetLastError());
+        }
+        // rows touched by the chunk's target elements
+        int64_t rlo = op->N, rhi = -1;
+        for (int64_t e = e0; e < e1; ++e) {
+            const int nel1 = g->nel1, k = g->k;
+            int j = int(e / (int64_t(nel1) * nel1));
+            int rem = int(e % (int64_t(nel1) * nel1));
+            int ey = rem / nel1, ex = rem % nel1;
+            for (int av = 0; av <= P; ++av)
+                for (int au = 0; au <= P; ++au) {
+                    int64_t i2 = (int64_t(j) * k + ey + av) * k + ex + au;
+                    int64_t r = hard ? g->s2_to_s0[i2] : i2;
+                    rlo = std::min(rlo, r);
+                    rhi = std::max(rhi, r);
+                }
+        }
+        CsrArgs C{};
+        C.row_ptr = op->d_rowptr.as<int64_t>();
+        C.col = op->d_col.as<int>();
+        C.val = op->d_val.as<double2>();
+        C.near_ptr = op->d_near_ptr.as<int64_t>();
+        C.near_src = op->d_near_src.as<int>();
+        C.stage = d_stage.as<double2>();
+        C.slot0 = k0;
+        C.e_lo = e0;
+        C.e_hi = e1;
+        C.s0_ptr = hard ? op->d_s0_ptr.as<int>() : nullptr;
+        C.s0_reps = hard ? op->d_s0_reps.as<int>() : nullptr;
+        C.row0 = rlo;
+        C.nel1 = g->nel1;
+        C.k = g->k;
+        if (rhi >= rlo) {
+            hipLaunchKernelGGL(near_gather_csr<P>, dim3(unsigned(rhi - rlo + 1)), dim3(256), 0, s, C);
+            IGB_HIP(hipGetLastError());
+        }
+        IGB_HIP(hipStreamSynchronize(s));
+        e0 = e1;
+    }
+    return IGB_OK;
+}
+
+igb_status assemble_near_device(igb_op op, hipStream_t s) {
+    igb_geom g = op->geom;
+    size_t* acct = &op->dev_bytes;
+    igb_status st;
+    if (op->bc == IGB_HARD) {
+        set_error("assemble_nearfield: the sound-hard operator is not implemented in this build");
+        return IGB_ERR_UNSUPPORTED;
+    }
+    if ((st = upload(op->d_s2_to_s0, g->s2_to_s0.data(), g->s2_to_s0.size(), acct))) return st;
+    if (g->n0 > 0) {
+        if ((st = upload(op->d_s0_ptr, g->s0_ptr.data(), g->s0_ptr.size(), acct))) return st;
+        if ((st = upload(op->d_s0_reps, g->s0_reps.data(), g->s0_reps.size(), acct))) return st;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    switch (g->p) {
+        case 1: st = near_launch<1>(op, s); break;
+        case 2: st = near_launch<2>(op, s); break;
+        default:
+            set_error("assemble_nearfield: spline degree p = %d not built (p = 1, 2)", g->p);
+            return IGB_ERR_UNSUPPORTED;
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    op->t_assembly_near = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    return st;
+}
+
+igb_status assemble_far_device(igb_op op, hipStream_t s) {
+    igb_geom g = op->geom;
+    size_t* acct = &op->dev_bytes;
+    igb_status st;
+    const int q = op->q, q1 = q + 1, nq = op->nq, L = op->L, d = op->d, p = g->p;
+    auto t0 = std::chrono::steady_clock::now();
+    // Chebyshev nodes, transfers T1[bit][g][a] = L_a((bit + t_g)/2), 1-D leaf moments
+    std::vector<double> t(q1);
+    cheb_nodes(q, t.data());
+    auto lag = [&](int a, double x) {
+        double v = 1;
+        for (int b = 0; b < q1; ++b)
+            if (b != a) v *= (x - t[b]) / (t[a] - t[b]);
+        return v;
+    };
+    std::vector<double> T1(2 * q1 * q1);
+    for (int bit = 0; bit < 2; ++bit)
+        for (int gg = 0; gg < q1; ++gg)
+            for (int a = 0; a < q1; ++a) T1[(bit * q1 + gg) * q1 + a] = lag(a, 0.5 * (bit + t[gg]));
+    // m1[kind][cx][a][i] = int_{leaf cx} L_a(x) b^{(kind)}_{cx*s + i}(x) dx over the
+    // window of the leaf's B-splines, kind 0 values / 1 derivatives
+    const int s1 = 1 << d, w = s1 + p, nleaf1 = 1 << L, nel1 = g->nel1;
+    const int64_t stride_kind = int64_t(nleaf1) * q1 * w;
+    std::vector<double> m1(2 * stride_kind, 0.0);
+    {
+        std::vector<double> gx, gw;
+        const int ng = std::min(NGMAX, (q + p) / 2 + 2);
+        gauss01_host(ng, gx, gw);
+        for (int cx = 0; cx < nleaf1; ++cx)
+            for (int el = 0; el < s1; ++el) {
+                const int ex = cx * s1 + el;
+                const double* C = &g->C1[size_t(ex) * (p + 1) * (p + 1)];
+                for (int gi = 0; gi < ng; ++gi) {
+                    const double sl = gx[gi];
+                    const double xr = (el + sl) / s1;  // position in the leaf's [0,1]
+                    double b[4], db[4];
+                    // Bernstein on the element, then extraction to B-splines
+                    {
+                        const double tt = 1 - sl;
+                        if (p == 1) { b[0] = tt; b[1] = sl; db[0] = -1; db[1] = 1; }
+                        else if (p == 2) { b[0] = tt * tt; b[1] = 2 * sl * tt; b[2] = sl * sl; db[0] = -2 * tt; db[1] = 2 * (tt - sl); db[2] = 2 * sl; }
+                        else if (p == 3) { b[0] = tt * tt * tt; b[1] = 3 * sl * tt * tt; b[2] = 3 * sl * sl * tt; b[3] = sl * sl * sl; db[0] = -3 * tt * tt; db[1] = 3 * tt * tt - 6 * sl * tt; db[2] = 6 * sl * tt - 3 * sl * sl; db[3] = 3 * sl * sl; }
+                        else { b[0] = 1; db[0] = 0; }
+                    }
+                    for (int a = 0; a <= p; ++a) {
+                        double v = 0, dv = 0;
+                        for (int kk = 0; kk <= p; ++kk) {
+                            v += C[a * (p + 1) + kk] * b[kk];
+                            dv += C[a * (p + 1) + kk] * db[kk];
+                        }
+                        dv *= nel1;  // d/du = 2^m d/ds
+                        const int iloc = el + a;  // window index of b_{ex+a}
+                        for (int aa = 0; aa < q1; ++aa) {
+                            const double la = lag(aa, xr) * gw[gi] / nel1;
+                            m1[(int64_t(cx) * q1 + aa) * w + iloc] += la * v;
+                            m1[stride_kind + (int64_t(cx) * q1 + aa) * w + iloc] += la * dv;
+                        }
+                    }
+                }
+            }
+    }
+    if ((st = upload(op->d_T, T1.data(), T1.size(), acct))) return st;
+    if ((st = upload(op->d_m1, m1.data(), m1.size(), acct))) return st;
+    DevBuf d_t, d_cluoff;
+    if ((st = upload(d_t, t.data(), t.size(), nullptr))) return st;
+    if ((st = upload(d_cluoff, op->clu_off.data(), op->clu_off.size(), nullptr))) return st;
+    if ((st = alloc(op->d_nodes, size_t(op->nclusters) * nq * 16 * sizeof(double), acct))) return st;
+    {
+        const int64_t tot = op->nclusters * nq;
+        hipLaunchKernelGGL(node_geometry, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, s,
+                           g->d_bez.as<double>(), g->d_pg.as<int>(), g->nel1, g->npatch, L,
+                           d_cluoff.as<int64_t>(), d_t.as<double>(), q, op->d_nodes.as<double>());
+        IGB_HIP(hipGetLastError());
+    }
+    // far pair lists (global cluster indices)
+    std::vector<int> ptg(op->nfar), psg(op->nfar);
+    for (int l = 0; l <= L; ++l) {
+        const FarLevel& F = op->far[l];
+        const int64_t nc = clusters_on_level(g->npatch, l);
+        for (int64_t tt = 0; tt < nc; ++tt)
+            for (int i = F.tgt_ptr[tt]; i < F.tgt_ptr[tt + 1]; ++i) {
+                ptg[F.pair_off + i] = int(op->clu_off[l] + tt);
+                psg[F.pair_off + i] = int(op->clu_off[l] + F.src[i]);
+            }
+    }
+    DevBuf d_ptg;
+    if ((st = upload(d_ptg, ptg.data(), ptg.size(), nullptr))) return st;
+    if ((st = upload(op->d_far_src, psg.data(), psg.size(), acct))) return st;
+    if ((st = alloc(op->d_coupling, size_t(op->nfar) * nq * nq * sizeof(double2), acct))) return st;
+    if (op->nfar > 0) {
+        hipLaunchKernelGGL(coupling_soft, dim3(unsigned(op->nfar)), dim3(256), 0, s, op->d_nodes.as<double>(),
+                           d_ptg.as<int>(), op->d_far_src.as<int>(), op->nfar, nq, op->kappa, op->eta,
+                           op->d_coupling.as<double2>());
+        IGB_HIP(hipGetLastError());
+    }
+    if ((st = upload(op->d_chunk_pair, op->chunk_pair.data(), op->chunk_pair.size(), acct))) return st;
+    if ((st = upload(op->d_chunk_len, op->chunk_len.data(), op->chunk_len.size(), acct))) return st;
+    if ((st = upload(op->d_tgt_chunk_ptr, op->tgt_chunk_ptr.data(), op->tgt_chunk_ptr.size(), acct))) return st;
+    if ((st = upload(op->d_chunk_tgt, op->chunk_tgt.data(), op->chunk_tgt.size(), acct))) return st;
+    IGB_HIP(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    op->t_assembly_far = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    return IGB_OK;
+}
+
+igb_status alloc_work(igb_op op, int nrhs) {
+    (void)nrhs;
+    size_t* acct = &op->dev_bytes;
+    igb_status st;
+    const int nq = op->nq;
+    if (!op->d_xhat.ptr) {
+        if ((st = alloc(op->d_xhat, size_t(op->nclusters) * nq * sizeof(double2), acct))) return st;
+        if ((st = alloc(op->d_yhat, size_t(op->nclusters) * nq * sizeof(double2), acct))) return st;
+        if ((st = alloc(op->d_part, std::max<size_t>(1, op->chunk_len.size()) * nq * sizeof(double2), acct)))
+            return st;
+        if ((st = alloc(op->d_yfar, size_t(op->geom->n2) * sizeof(double2), acct))) return st;
+        if ((st = alloc(op->d_x2, size_t(op->geom->n2) * sizeof(double2), acct))) return st;
+        // cluster offsets are needed on the device by m2m / l2l
+        if ((st = upload(op->d_cluoff, op->clu_off.data(), op->clu_off.size(), acct))) return st;
+    }
+    return IGB_OK;
+}
+
+igb_status timer_mark(igb_op op, int slot, hipStream_t s) {
+    if (!op->profile) return IGB_OK;
+    KernelTimer& t = op->timers[slot];
+    if (t.used == t.pool.size()) {
+        hipEvent_t e;
+        IGB_HIP(hipEventCreate(&e));
+        t.pool.push_back(e);
+    }
+    IGB_HIP(hipEventRecord(t.pool[t.used++], s));
+    return IGB_OK;
+}
+
+igb_status matvec_device(igb_op op, const double* x, double* y, int nrhs, int parts, hipStream_t s) {
+    if (nrhs != 1) {
+        set_error("h2_matvec: this build applies one column per call");
+        return IGB_ERR_UNSUPPORTED;
+    }
+    igb_status st;
+    if ((st = alloc_work(op, nrhs))) return st;
+    igb_geom g = op->geom;
+    const int q = op->q, nq = op->nq, L = op->L;
+    const bool hard = op->bc == IGB_HARD;
+    const double2* X = reinterpret_cast<const double2*>(x);
+    double2* Y = reinterpret_cast<double2*>(y);
+    const int64_t* clu_off = op->d_cluoff.as<int64_t>();
+    double2* xh = op->d_xhat.as<double2>();
+    double2* yh = op->d_yhat.as<double2>();
+    const bool far = (parts & IGB_PART_FAR) && op->nfar > 0;
+    if (far) {
+        const double2* x2 = X;
+        if (hard) {
+            hipLaunchKernelGGL(glue_gather, dim3(unsigned((g->n2 + 255) / 256)), dim3(256), 0, s,
+                               op->d_s2_to_s0.as<int>(), X, op->d_x2.as<double2>(), g->n2);
+            x2 = op->d_x2.as<double2>();
+        }
+        const int64_t nleaf = clusters_on_level(g->npatch, L);
+        const int64_t stride_kind = int64_t(1 << L) * (q + 1) * ((1 << op->d) + g->p);
+        if ((st = timer_mark(op, 2, s))) return st;
+        hipLaunchKernelGGL(leaf_moments, dim3(unsigned((nleaf * nq + 255) / 256)), dim3(256), 0, s, x2,
+                           op->d_m1.as<double>(), q, op->d, g->p, L, g->k, op->clu_off[L], nleaf, xh, 0, 0,
+                           stride_kind);
+        for (int l = L - 1; l >= 0; --l) {
+            const int64_t nc = clusters_on_level(g->npatch, l);
+            hipLaunchKernelGGL(m2m, dim3(unsigned((nc * nq + 255) / 256)), dim3(256), 0, s,
+                               op->d_T.as<double>(), q, l, clu_off, xh);
+        }
+        if ((st = timer_mark(op, 2, s))) return st;
+        const int64_t nchunk = int64_t(op->chunk_len.size());
+        if ((st = timer_mark(op, 0, s))) return st;
+        if (nq <= 64) {
+            hipLaunchKernelGGL(m2l_chunks<64>, dim3(unsigned(nchunk)), dim3(64), 0, s,
+                               op->d_coupling.as<double2>(), xh, op->d_far_src.as<int>(),
+                               op->d_chunk_pair.as<int64_t>(), op->d_chunk_len.as<int>(), nchunk, nq,
+                               op->d_part.as<double2>());
+        } else {
+            hipLaunchKernelGGL(m2l_chunks<128>, dim3(unsigned(nchunk)), dim3(128), 0, s,
+                               op->d_coupling.as<double2>(), xh, op->d_far_src.as<int>(),
+                               op->d_chunk_pair.as<int64_t>(), op->d_chunk_len.as<int>(), nchunk, nq,
+                               op->d_part.as<double2>());
+        }
+        if ((st = timer_mark(op, 0, s))) return st;
+        if ((st = timer_mark(op, 3, s))) return st;
+        hipLaunchKernelGGL(m2l_reduce, dim3(unsigned((op->nclusters * nq + 255) / 256)), dim3(256), 0, s,
+                           op->d_part.as<double2>(), op->d_tgt_chunk_ptr.as<int>(), op->nclusters, nq, yh);
+        for (int l = 0; l < L; ++l) {
+            const int64_t nc = clusters_on_level(g->npatch, l + 1);
+            hipLaunchKernelGGL(l2l, dim3(unsigned((nc * nq + 255) / 256)), dim3(256), 0, s,
+                               op->d_T.as<double>(), q, l, clu_off, yh);
+        }
+        hipLaunchKernelGGL(back_project, dim3(unsigned((g->n2 + 255) / 256)), dim3(256), 0, s, yh,
+                           op->d_m1.as<double>(), q, op->d, g->p, L, g->k, g->npatch, op->clu_off[L],
+                           op->d_yfar.as<double2>(), 0, 0, stride_kind, 0);
+        if ((st = timer_mark(op, 3, s))) return st;
+    }
+    const int64_t N = op->N;
+    if ((st = timer_mark(op, 1, s))) return st;
+    hipLaunchKernelGGL(spmv_combine, dim3(unsigned((N * 64 + 255) / 256)), dim3(256), 0, s,
+                       op->d_rowptr.as<int64_t>(), op->d_col.as<int>(), op->d_val.as<double2>(), X, N,
+                       far ? op->d_yfar.as<double2>() : nullptr, hard ? op->d_s0_ptr.as<int>() : nullptr,
+                       hard ? op->d_s0_reps.as<int>() : nullptr, (parts & IGB_PART_NEAR) ? 1 : 0, Y);
+    IGB_HIP(hipGetLastError());
+    if ((st = timer_mark(op, 1, s))) return st;
+    return IGB_OK;
+}
+
+igb_status rhs_device(igb_op op, const double* dirs, int ndir, double* b, hipStream_t s) {
+    igb_geom g = op->geom;
+    std::vector<double> dn(3 * ndir);
+    for (int i = 0; i < ndir; ++i) {
+        double nr = std::sqrt(dirs[3 * i] * dirs[3 * i] + dirs[3 * i + 1] * dirs[3 * i + 1] +
+                              dirs[3 * i + 2] * dirs[3 * i + 2]);
+        if (!(nr >= 1e-12)) {
+            set_error("cfie_rhs: direction %d has norm < 1e-12", i);
+            return IGB_ERR_ARG;
+        }
+        for (int c = 0; c < 3; ++c) dn[3 * i + c] = dirs[3 * i + c] / nr;
+    }
+    igb_status st;
+    DevBuf d_dirs, d_gl, d_loc;
+    std::vector<double> gl = gauss_table();
+    if ((st = upload(d_dirs, dn.data(), dn.size(), nullptr))) return st;
+    if ((st = upload(d_gl, gl.data(), gl.size(), nullptr))) return st;
+    const int NL = (g->p + 1) * (g->p + 1);
+    if ((st = alloc(d_loc, size_t(ndir) * g->nelem * NL * sizeof(double2), nullptr))) return st;
+    QuadGeoArgs A{g->d_bez.as<double>(), g->d_pg.as<int>(), g->d_C1.as<double>(), d_gl.as<double>(),
+                  g->nel1, g->p, 6, g->nelem};
+    const bool hard = op->bc == IGB_HARD;
+    dim3 grid1(unsigned((g->nelem + 127) / 128), unsigned(ndir));
+    dim3 grid2(unsigned((op->N + 255) / 256), unsigned(ndir));
+    const int* s0p = hard ? op->d_s0_ptr.as<int>() : nullptr;
+    const int* s0r = hard ? op->d_s0_reps.as<int>() : nullptr;
+    double2* B = reinterpret_cast<double2*>(b);
+    switch (g->p) {
+        case 1:
+            hipLaunchKernelGGL(rhs_elements<1>, grid1, dim3(128), 0, s, A, d_dirs.as<double>(), ndir, op->kappa,
+                               op->eta, hard ? 1 : 0, d_loc.as<double2>());
+            hipLaunchKernelGGL(rhs_gather<1>, grid2, dim3(256), 0, s, d_loc.as<double2>(), ndir, g->nelem,
+                               g->nel1, g->k, op->N, s0p, s0r, B);
+            break;
+        case 2:
+            hipLaunchKernelGGL(rhs_elements<2>, grid1, dim3(128), 0, s, A, d_dirs.as<double>(), ndir, op->kappa,
+                               op->eta, hard ? 1 : 0, d_loc.as<double2>());
+            hipLaunchKernelGGL(rhs_gather<2>, grid2, dim3(256), 0, s, d_loc.as<double2>(), ndir, g->nelem,
+                               g->nel1, g->k, op->N, s0p, s0r, B);
+            break;
+        default:
+            set_error("cfie_rhs: p = %d not built", g->p);
+            return IGB_ERR_UNSUPPORTED;
+    }
+    IGB_HIP(hipGetLastError());
+    IGB_HIP(hipStreamSynchronize(s));  // temporaries are freed on return
+    return IGB_OK;
+}
+
+igb_status farfield_device(igb_op op, const double* coeffs, int ndir, const double* obs, int nobs,
+                           double* uinf, hipStream_t s) {
+    igb_geom g = op->geom;
+    std::vector<double> on(3 * nobs);
+    for (int i = 0; i < nobs; ++i) {
+        double nr = std::sqrt(obs[3 * i] * obs[3 * i] + obs[3 * i + 1] * obs[3 * i + 1] + obs[3 * i + 2] * obs[3 * i + 2]);
+        if (!(nr >= 1e-12)) {
+            set_error("farfield: observation direction %d has norm < 1e-12", i);
+            return IGB_ERR_ARG;
+        }
+        for (int c = 0; c < 3; ++c) on[3 * i + c] = obs[3 * i + c] / nr;
+    }
+    igb_status st;
+    const int nqd = 6;
+    const int64_t npts = g->nelem * nqd * nqd;
+    DevBuf d_obs, d_gl, d_geo, d_dens;
+    std::vector<double> gl = gauss_table();
+    if ((st = upload(d_obs, on.data(), on.size(), nullptr))) return st;
+    if ((st = upload(d_gl, gl.data(), gl.size(), nullptr))) return st;
+    if ((st = alloc(d_geo, size_t(npts) * 8 * sizeof(double), nullptr))) return st;
+    if ((st = alloc(d_dens, size_t(ndir) * npts * sizeof(double2), nullptr))) return st;
+    QuadGeoArgs A{g->d_bez.as<double>(), g->d_pg.as<int>(), g->d_C1.as<double>(), d_gl.as<double>(),
+                  g->nel1, g->p, nqd, g->nelem};
+    const bool hard = op->bc == IGB_HARD;
+    const double2* C = reinterpret_cast<const double2*>(coeffs);
+    const int* s2s0 = hard ? op->d_s2_to_s0.as<int>() : nullptr;
+    switch (g->p) {
+        case 1:
+            hipLaunchKernelGGL(density_points<1>, dim3(unsigned((npts + 255) / 256)), dim3(256), 0, s, A, C, ndir,
+                               op->N, s2s0, g->k, d_geo.as<double>(), d_dens.as<double2>());
+            break;
+        case 2:
+            hipLaunchKernelGGL(density_points<2>, dim3(unsigned((npts + 255) / 256)), dim3(256), 0, s, A, C, ndir,
+                               op->N, s2s0, g->k, d_geo.as<double>(), d_dens.as<double2>());
+            break;
+        default:
+            set_error("farfield: p = %d not built", g->p);
+            return IGB_ERR_UNSUPPORTED;
+    }
+    hipLaunchKernelGGL(farfield_sum, dim3(unsigned(nobs), unsigned(ndir)), dim3(256), 0, s, d_geo.as<double>(),
+                       d_dens.as<double2>(), npts, d_obs.as<double>(), nobs, op->kappa, hard ? 1 : 0,
+                       reinterpret_cast<double2*>(uinf));
+    IGB_HIP(hipGetLastError());
+    IGB_HIP(hipStreamSynchronize(s));
+    return IGB_OK;
+}
+
+}  // namespace igb

@@ -1,0 +1,321 @@
+// Host side of assemble_nearfield: cluster quadtrees, block partition
+// (Sec. 4.4), near element pairs with their quadrature class, and the sparsity
+// pattern of the near-field matrix.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace igb {
+
+void eval_element_host(const igb_geom_s* g, int64_t e, double s, double t, double* F, double* Fs,
+                       double* Ft);
+
+namespace {
+
+inline int64_t clu_local(int npatch_unused, int l, int patch, int cx, int cy) {
+    (void)npatch_unused;
+    return (int64_t(patch) << (2 * l)) + (int64_t(cy) << l) + cx;
+}
+
+// square symmetry codes (swap*4 + flip_t*2 + flip_s), acting on local (s,t)
+void d4_apply(int code, double s, double t, double& a, double& b) {
+    a = s;
+    b = t;
+    if (code & 4) std::swap(a, b);
+    if (code & 1) a = 1.0 - a;
+    if (code & 2) b = 1.0 - b;
+}
+
+int d4_code(int c0, int c1 /* -1: unused */) {
+    // smallest code mapping (0,0) to corner c0 and (1,0) to corner c1
+    for (int code = 0; code < 8; ++code) {
+        double a, b;
+        d4_apply(code, 0, 0, a, b);
+        if (int(a) + 2 * int(b) != c0) continue;
+        if (c1 >= 0) {
+            d4_apply(code, 1, 0, a, b);
+            if (int(a) + 2 * int(b) != c1) continue;
+        }
+        return code;
+    }
+    return -1;
+}
+
+}  // namespace
+
+igb_status tree_build(igb_op op) {
+    igb_geom g = op->geom;
+    const int np = g->npatch, m = g->m, nel1 = g->nel1;
+    op->d = std::min(std::max(op->prm.leaf_depth, 0), m);
+    op->L = m - op->d;
+    const int L = op->L;
+    op->clu_off.assign(L + 2, 0);
+    for (int l = 0; l <= L; ++l) op->clu_off[l + 1] = op->clu_off[l] + clusters_on_level(np, l);
+    op->nclusters = op->clu_off[L + 1];
+    op->clo.assign(op->nclusters * 3, 0.0);
+    op->chi.assign(op->nclusters * 3, 0.0);
+
+    // boxes: elements merged upward level by level
+    std::vector<double> lo(g->lo), hi(g->hi);
+    for (int l = m; l >= 0; --l) {
+        const int n = 1 << l;
+        if (l <= L) {
+            for (int j = 0; j < np; ++j)
+                for (int cy = 0; cy < n; ++cy)
+                    for (int cx = 0; cx < n; ++cx) {
+                        int64_t src = (int64_t(j) * n + cy) * n + cx;
+                        int64_t dst = op->clu_off[l] + clu_local(np, l, j, cx, cy);
+                        for (int c = 0; c < 3; ++c) {
+                            op->clo[3 * dst + c] = lo[3 * src + c];
+                            op->chi[3 * dst + c] = hi[3 * src + c];
+                        }
+                    }
+        }
+        if (l == 0) break;
+        const int h = n / 2;
+        std::vector<double> plo(size_t(np) * h * h * 3, 1e300), phi(size_t(np) * h * h * 3, -1e300);
+        for (int j = 0; j < np; ++j)
+            for (int cy = 0; cy < n; ++cy)
+                for (int cx = 0; cx < n; ++cx) {
+                    int64_t src = (int64_t(j) * n + cy) * n + cx;
+                    int64_t dst = (int64_t(j) * h + cy / 2) * h + cx / 2;
+                    for (int c = 0; c < 3; ++c) {
+                        plo[3 * dst + c] = std::min(plo[3 * dst + c], lo[3 * src + c]);
+                        phi[3 * dst + c] = std::max(phi[3 * dst + c], hi[3 * src + c]);
+                    }
+                }
+        lo.swap(plo);
+        hi.swap(phi);
+    }
+    (void)nel1;
+
+    auto admissible = [&](int64_t t, int64_t s) {
+        const double *lt = &op->clo[3 * t], *ht = &op->chi[3 * t];
+        const double *ls = &op->clo[3 * s], *hs = &op->chi[3 * s];
+        double gap2 = 0, dt2 = 0, ds2 = 0;
+        for (int c = 0; c < 3; ++c) {
+            double gp = std::max(0.0, std::max(ls[c] - ht[c], lt[c] - hs[c]));
+            gap2 += gp * gp;
+            dt2 += (ht[c] - lt[c]) * (ht[c] - lt[c]);
+            ds2 += (hs[c] - ls[c]) * (hs[c] - ls[c]);
+        }
+        double dm = std::max(std::sqrt(dt2), std::sqrt(ds2));
+        if (op->prm.kcap > 0 && op->kappa * dm > op->prm.kcap) return false;
+        return std::sqrt(gap2) >= op->prm.eta_adm * dm;
+    };
+
+    // level-synchronous dual traversal
+    op->far.assign(L + 1, FarLevel());
+    std::vector<std::pair<int, int>> cur, nxt;  // local indices on the current level
+    for (int a = 0; a < np; ++a)
+        for (int b = 0; b < np; ++b) cur.emplace_back(a, b);
+    std::vector<std::vector<int>> near_leaf(clusters_on_level(np, L));
+    int64_t pair_off = 0;
+    for (int l = 0; l <= L; ++l) {
+        const int n = 1 << l;
+        std::vector<std::pair<int, int>> farl;
+        nxt.clear();
+        for (auto& pr : cur) {
+            int64_t tg = op->clu_off[l] + pr.first, sg = op->clu_off[l] + pr.second;
+            if (admissible(tg, sg)) {
+                farl.push_back(pr);
+            } else if (l == L) {
+                near_leaf[pr.first].push_back(pr.second);
+            } else {
+                int tj = pr.first >> (2 * l), tr = pr.first & ((1 << (2 * l)) - 1);
+                int sj = pr.second >> (2 * l), sr = pr.second & ((1 << (2 * l)) - 1);
+                int tcy = tr >> l, tcx = tr & (n - 1), scy = sr >> l, scx = sr & (n - 1);
+                for (int a = 0; a < 4; ++a)
+                    for (int b = 0; b < 4; ++b) {
+                        int tc = int(clu_local(np, l + 1, tj, 2 * tcx + (a & 1), 2 * tcy + (a >> 1)));
+                        int sc = int(clu_local(np, l + 1, sj, 2 * scx + (b & 1), 2 * scy + (b >> 1)));
+                        nxt.emplace_back(tc, sc);
+                    }
+            }
+        }
+        std::sort(farl.begin(), farl.end());
+        FarLevel& F = op->far[l];
+        F.level = l;
+        F.pair_off = pair_off;
+        const int64_t nc = clusters_on_level(np, l);
+        F.tgt_ptr.assign(nc + 1, 0);
+        F.src.resize(farl.size());
+        for (size_t i = 0; i < farl.size(); ++i) {
+            F.tgt_ptr[farl[i].first + 1]++;
+            F.src[i] = farl[i].second;
+        }
+        for (int64_t i = 0; i < nc; ++i) F.tgt_ptr[i + 1] += F.tgt_ptr[i];
+        pair_off += farl.size();
+        cur.swap(nxt);
+    }
+    op->nfar = pair_off;
+
+    // near element pairs, per target element sorted by source element
+    const int64_t E = g->nelem;
+    const int s = 1 << op->d;   // elements per leaf side
+    const int nl = 1 << L;
+    op->near_ptr.assign(E + 1, 0);
+    for (auto& v : near_leaf) std::sort(v.begin(), v.end());
+    for (int64_t e = 0; e < E; ++e) {
+        int j = int(e / (int64_t(nel1) * nel1));
+        int rem = int(e % (int64_t(nel1) * nel1));
+        int ey = rem / nel1, ex = rem % nel1;
+        int leaf = int(clu_local(np, L, j, ex / s, ey / s));
+        op->near_ptr[e + 1] = op->near_ptr[e] + int64_t(near_leaf[leaf].size()) * s * s;
+    }
+    op->near_src.resize(op->near_ptr[E]);
+    for (int64_t e = 0; e < E; ++e) {
+        int j = int(e / (int64_t(nel1) * nel1));
+        int rem = int(e % (int64_t(nel1) * nel1));
+        int ey = rem / nel1, ex = rem % nel1;
+        int leaf = int(clu_local(np, L, j, ex / s, ey / s));
+        std::vector<int> src;
+        src.reserve(near_leaf[leaf].size() * s * s);
+        for (int sl : near_leaf[leaf]) {
+            int sj = sl >> (2 * L), sr = sl & ((1 << (2 * L)) - 1);
+            int scy = sr >> L, scx = sr & (nl - 1);
+            for (int fy = scy * s; fy < (scy + 1) * s; ++fy)
+                for (int fx = scx * s; fx < (scx + 1) * s; ++fx)
+                    src.push_back(int((int64_t(sj) * nel1 + fy) * nel1 + fx));
+        }
+        std::sort(src.begin(), src.end());
+        std::copy(src.begin(), src.end(), op->near_src.begin() + op->near_ptr[e]);
+    }
+
+    // M2L work decomposition: chunks of at most CH sources of one target
+    const int CH = 8;
+    op->chunk_tgt.clear();
+    op->chunk_pair.clear();
+    op->chunk_len.clear();
+    op->tgt_chunk_ptr.assign(op->nclusters + 1, 0);
+    for (int l = 0; l <= L; ++l) {
+        const FarLevel& F = op->far[l];
+        const int64_t nc = clusters_on_level(np, l);
+        for (int64_t t = 0; t < nc; ++t) {
+            int a = F.tgt_ptr[t], b = F.tgt_ptr[t + 1];
+            for (int c = a; c < b; c += CH) {
+                op->chunk_tgt.push_back(int(op->clu_off[l] + t));
+                op->chunk_pair.push_back(F.pair_off + c);
+                op->chunk_len.push_back(std::min(CH, b - c));
+                op->tgt_chunk_ptr[op->clu_off[l] + t + 1]++;
+            }
+        }
+    }
+    for (int64_t i = 0; i < op->nclusters; ++i) op->tgt_chunk_ptr[i + 1] += op->tgt_chunk_ptr[i];
+    return IGB_OK;
+}
+
+// Quadrature class of every near element pair:
+//   bits 0..3  : 0 regular, 1 common vertex, 2 common edge, 4 identical
+//   bits 8..11 : Gauss order of the regular rule
+//   bits 16..18: square symmetry of the test element, 20..22: of the trial element
+// Regular order from the ratio centre distance / larger box diagonal.
+igb_status near_classify(igb_op op) {
+    igb_geom g = op->geom;
+    const int64_t E = g->nelem;
+    std::vector<double> ctr(E * 3), diag(E);
+    for (int64_t e = 0; e < E; ++e) {
+        eval_element_host(g, e, 0.5, 0.5, &ctr[3 * e], nullptr, nullptr);
+        double s2 = 0;
+        for (int c = 0; c < 3; ++c) s2 += (g->hi[3 * e + c] - g->lo[3 * e + c]) * (g->hi[3 * e + c] - g->lo[3 * e + c]);
+        diag[e] = std::sqrt(s2);
+    }
+    op->near_kind.resize(op->near_src.size());
+    for (int64_t e = 0; e < E; ++e) {
+        for (int64_t k = op->near_ptr[e]; k < op->near_ptr[e + 1]; ++k) {
+            const int64_t f = op->near_src[k];
+            int shared = 0, ce[4], cf[4];
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b)
+                    if (g->vert[4 * e + a] == g->vert[4 * f + b]) {
+                        ce[shared] = a;
+                        cf[shared] = b;
+                        ++shared;
+                    }
+            int kind;
+            if (e == f) {
+                kind = 4;
+            } else if (shared == 2) {
+                int te = d4_code(ce[0], ce[1]), tf = d4_code(cf[0], cf[1]);
+                if (te < 0 || tf < 0) {
+                    set_error("assemble_nearfield: shared edge not on a side of both elements");
+                    return IGB_ERR_GEOMETRY;
+                }
+                kind = 2 | (te << 16) | (tf << 20);
+            } else if (shared == 1) {
+                int te = d4_code(ce[0], -1), tf = d4_code(cf[0], -1);
+                kind = 1 | (te << 16) | (tf << 20);
+            } else if (shared == 0) {
+                double d2 = 0;
+                for (int c = 0; c < 3; ++c) d2 += (ctr[3 * e + c] - ctr[3 * f + c]) * (ctr[3 * e + c] - ctr[3 * f + c]);
+                double ratio = std::sqrt(d2) / std::max(diag[e], diag[f]);
+                int n = ratio >= 6.0 ? 4 : ratio >= 3.0 ? 5 : ratio >= 1.8 ? 6 : 7;
+                kind = n << 8;
+            } else {
+                set_error("assemble_nearfield: elements share %d corners", shared);
+                return IGB_ERR_GEOMETRY;
+            }
+            op->near_kind[k] = kind;
+        }
+    }
+    return IGB_OK;
+}
+
+// CSR pattern of the near-field matrix in the solution space: column l of row
+// r is present iff an element pair (e, f) of the near list has e in the support
+// of a representative of r and f in the support of a representative of l.
+igb_status near_pattern(igb_op op) {
+    igb_geom g = op->geom;
+    const int p = g->p, k = g->k, nel1 = g->nel1;
+    const bool hard = op->bc == IGB_HARD;
+    const int64_t N = op->N;
+    op->row_ptr.assign(N + 1, 0);
+    std::vector<int64_t> stamp(N, -1);
+    std::vector<int> cols;
+    std::vector<std::vector<int>> rows_cols(N);
+    std::vector<int64_t> elems;
+    for (int64_t r = 0; r < N; ++r) {
+        cols.clear();
+        elems.clear();
+        auto add_rep = [&](int64_t i) {
+            int j = int(i / (int64_t(k) * k));
+            int rem = int(i % (int64_t(k) * k));
+            int iv = rem / k, iu = rem % k;
+            for (int ey = std::max(0, iv - p); ey <= std::min(iv, nel1 - 1); ++ey)
+                for (int ex = std::max(0, iu - p); ex <= std::min(iu, nel1 - 1); ++ex)
+                    elems.push_back((int64_t(j) * nel1 + ey) * nel1 + ex);
+        };
+        if (hard) {
+            for (int q = g->s0_ptr[r]; q < g->s0_ptr[r + 1]; ++q) add_rep(g->s0_reps[q]);
+        } else {
+            add_rep(r);
+        }
+        for (int64_t e : elems)
+            for (int64_t kk = op->near_ptr[e]; kk < op->near_ptr[e + 1]; ++kk) {
+                int64_t f = op->near_src[kk];
+                int j = int(f / (int64_t(nel1) * nel1));
+                int rem = int(f % (int64_t(nel1) * nel1));
+                int fy = rem / nel1, fx = rem % nel1;
+                for (int b = 0; b <= p; ++b)
+                    for (int a = 0; a <= p; ++a) {
+                        int64_t i2 = (int64_t(j) * k + fy + b) * k + fx + a;
+                        int64_t c = hard ? g->s2_to_s0[i2] : i2;
+                        if (stamp[c] != r) {
+                            stamp[c] = r;
+                            cols.push_back(int(c));
+                        }
+                    }
+            }
+        std::sort(cols.begin(), cols.end());
+        rows_cols[r] = cols;
+        op->row_ptr[r + 1] = op->row_ptr[r] + int64_t(cols.size());
+    }
+    op->nnz = op->row_ptr[N];
+    op->col.resize(op->nnz);
+    for (int64_t r = 0; r < N; ++r)
+        std::copy(rows_cols[r].begin(), rows_cols[r].end(), op->col.begin() + op->row_ptr[r]);
+    return IGB_OK;
+}
+
+}  // namespace igb

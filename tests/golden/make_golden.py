@@ -1,0 +1,84 @@
+"""Writes the stored oracle values used by the GPU parity tests.
+
+Calls only ``oracle`` (and the seeded input generators); nothing here comes
+from the HIP path.  Run from the repository root:
+
+    python tests/golden/make_golden.py [case ...]
+
+Cases
+  sphere_m3_p2_k2_q4  sphere, m = 3, p = 2, kappa = 2, soft, q = 4, eta = 1.6,
+                      leaf depth 1: O2 far product, O1 near product, sampled
+                      near entries, right-hand side, for the seeded vector x.
+  sphere_m2_p1_k1     the m = 2, p = 1, kappa = 1 sphere workload: dense O1
+                      matrix, right-hand side for d = (0,0,1), LU solution,
+                      far field at 64 Fibonacci directions and the Mie values.
+  sphere_m5_p2_k8_rows  the m = 5, p = 2, kappa = 8 sphere workload: sampled
+                      rows of the dense O1 matrix applied to the seeded vector.
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import galerkin as G  # noqa: E402
+from oracle import h2, mie  # noqa: E402
+from paper_2306_11324_amd import inputs as I  # noqa: E402
+
+X_SEED = 12345
+ROW_SEED = 777
+
+
+def case_sphere_m3_p2_k2_q4():
+    bem = G.DenseBEM(I.sphere_patches(), p=2, m=3, kappa=2.0, bc="soft")
+    H = h2.H2Oracle(bem, q=4, eta=1.6, leaf_depth=1)
+    x = I.random_complex(X_SEED, bem.n)
+    A = H.near_matrix()
+    nz = np.argwhere(A != 0)
+    pick = nz[np.random.default_rng(ROW_SEED).choice(len(nz), 4000, replace=False)]
+    d = np.array([0.3, -0.2, 0.9])
+    return dict(x=x, y_far=H.far_apply(x), y_near=A @ x, ent_ij=pick.astype(np.int32),
+                ent_val=A[pick[:, 0], pick[:, 1]], d=d, rhs=bem.rhs(d), nfar=len(H.far))
+
+
+def case_sphere_m2_p1_k1():
+    bem = G.DenseBEM(I.sphere_patches(), p=1, m=2, kappa=1.0, bc="soft")
+    A = bem.matrix()
+    d = np.array([0.0, 0.0, 1.0])
+    b = bem.rhs(d)
+    t = np.linalg.solve(A, b)
+    obs = I.fibonacci_directions(64)
+    return dict(A=A, d=d, rhs=b, t=t, obs=obs, uinf=bem.farfield(t, obs),
+                mie=mie.farfield(1.0, obs @ d, "soft"), x=I.random_complex(X_SEED, bem.n))
+
+
+def case_sphere_m5_p2_k8_rows(nrows=6):
+    bem = G.DenseBEM(I.sphere_patches(), p=2, m=5, kappa=8.0, bc="soft")
+    x = I.random_complex(X_SEED, bem.n)
+    rows = np.sort(np.random.default_rng(ROW_SEED).choice(bem.n, nrows, replace=False))
+    R = bem.rows(rows)
+    return dict(rows=rows.astype(np.int64), y=R @ x, rownorm1=np.abs(R).sum(1), x=x)
+
+
+CASES = {
+    "sphere_m3_p2_k2_q4": case_sphere_m3_p2_k2_q4,
+    "sphere_m2_p1_k1": case_sphere_m2_p1_k1,
+    "sphere_m5_p2_k8_rows": case_sphere_m5_p2_k8_rows,
+}
+
+
+def main(names):
+    for name in names or CASES:
+        t = time.time()
+        data = CASES[name]()
+        np.savez_compressed(os.path.join(HERE, name + ".npz"), **data)
+        print(f"{name}: {time.time() - t:.1f} s", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -1,0 +1,136 @@
+"""The C-ABI library without a GPU: it loads, exports every entry point that
+include/igafmm.h declares, and its host stages (spaces, S^0 gluing, cluster
+tree, block partition, near pairs, input validation) agree with the oracle's
+independent implementation.  No compute call is made here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2306_11324_amd import binding as B
+from paper_2306_11324_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "igafmm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return set(re.findall(r"^\s*(?:igb_status|void|size_t|const char\*)\s+(\w+)\s*\(", src, flags=re.M))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(B._lib, n), n
+    assert names == set(B.EXPORTED), names ^ set(B.EXPORTED)
+
+
+@pytest.fixture(scope="module")
+def hctx():
+    return B.Context(B.IGB_HOST_ONLY)
+
+
+@pytest.mark.parametrize("m,p", [(1, 1), (3, 1), (3, 2), (2, 3)])
+def test_dimensions_and_s0_map(hctx, m, p):
+    from oracle.spaces import Discretization
+    geo = B.Geometry(hctx, I.sphere_patches(), m, p)
+    k = 2 ** m + p
+    assert (geo.nelem, geo.n2) == (6 * 4 ** m, 6 * k * k)
+    assert geo.n0 == 6 * (k - 2) ** 2 + 12 * (k - 2) + 8
+    s0, n0 = Discretization(I.sphere_patches(), p, m).s0_map()
+    assert np.array_equal(geo.s0_map(), s0)
+
+
+def _oracle_blocks(patches, m, p, q, d, kcap, kappa=2.0):
+    from oracle import galerkin as G, h2
+    bem = G.DenseBEM(patches, p=p, m=m, kappa=kappa, bc="soft", workers=1)
+    return h2.H2Oracle(bem, q=q, eta=1.6, leaf_depth=d, kcap=kcap)
+
+
+@pytest.mark.parametrize("geom,m,p,q,d,kcap", [("sphere", 3, 2, 4, 1, 0.0), ("sphere", 4, 2, 6, 2, 3.0),
+                                              ("star", 3, 2, 5, 1, 0.0)])
+def test_block_partition_matches_oracle(hctx, geom, m, p, q, d, kcap):
+    pts = I.sphere_patches() if geom == "sphere" else I.star_patches(0, min(m, 4))
+    geo = B.Geometry(hctx, pts, m, p)
+    op = B.Operator(hctx, geo, kappa=2.0, q=q, leaf_depth=d, kcap=kcap)
+    H = _oracle_blocks(pts, m, p, q, d, kcap)
+
+    def loc(c):
+        n = 2 ** c.level
+        return c.patch * n * n + c.cy * n + c.cx
+
+    ref = np.array([(t.level, loc(t), loc(s)) for t, s in H.far]).reshape(-1, 3)
+    assert np.array_equal(op.far_blocks(), ref)
+    ptr, src, kind = op.near_pairs()
+    pairs = H.near_pairs()
+    pairs = pairs[np.lexsort((pairs[:, 1], pairs[:, 0]))]
+    mine = np.stack([np.repeat(np.arange(len(ptr) - 1), np.diff(ptr)), src], 1)
+    assert np.array_equal(mine, pairs)
+
+
+def test_touching_pairs_classified_like_oracle(hctx):
+    from oracle import galerkin as G
+    pts = I.sphere_patches()
+    geo = B.Geometry(hctx, pts, 2, 1)
+    op = B.Operator(hctx, geo, kappa=1.0, q=4, leaf_depth=0)
+    ptr, src, kind = op.near_pairs()
+    bem = G.DenseBEM(pts, p=1, m=2, kappa=1.0, bc="soft", workers=1)
+    for e in (0, 5, 17, 40, 95):
+        typ, te, tf, _ = bem.classify(e)
+        for k in range(ptr[e], ptr[e + 1]):
+            f = src[k]
+            assert (kind[k] & 15) == typ[f]
+            if typ[f] in (1, 2):
+                assert ((kind[k] >> 16) & 7) == te[f] and ((kind[k] >> 20) & 7) == tf[f]
+
+
+def _patch_copy(p, cpw=None):
+    return I.Patch(p.deg_u, p.deg_v, p.knots_u.copy(), p.knots_v.copy(),
+                   p.cpw.copy() if cpw is None else cpw)
+
+
+def test_invalid_geometry_is_rejected(hctx):
+    pts = I.sphere_patches()
+    bad = list(pts)
+    cpw = pts[0].cpw.copy()
+    cpw[1, 1, 3] = -0.5
+    bad[0] = _patch_copy(pts[0], cpw)
+    with pytest.raises(B.IgbError) as e:
+        B.Geometry(hctx, bad, 2, 1)
+    assert e.value.status == -2
+    # inward normals: swap u and v of every patch
+    flipped = [I.Patch(p.deg_v, p.deg_u, p.knots_v, p.knots_u, np.ascontiguousarray(p.cpw.transpose(1, 0, 2)))
+               for p in pts]
+    with pytest.raises(B.IgbError) as e:
+        B.Geometry(hctx, flipped, 2, 1)
+    assert e.value.status == -2
+    # one patch flipped: not consistently oriented
+    mixed = list(pts)
+    mixed[2] = flipped[2]
+    with pytest.raises(B.IgbError):
+        B.Geometry(hctx, mixed, 2, 1)
+    # open surface (5 patches)
+    with pytest.raises(B.IgbError):
+        B.Geometry(hctx, pts[:5], 2, 1)
+    # knot not on the mesh
+    kn = pts[0].knots_u.copy()
+    p0 = I.Patch(2, 2, np.array([0, 0, 0, 0.3, 1, 1, 1.0]), pts[0].knots_v, np.concatenate([pts[0].cpw, pts[0].cpw[:, -1:]], 1))
+    with pytest.raises(B.IgbError):
+        B.Geometry(hctx, [p0] + list(pts[1:]), 2, 1)
+
+
+def test_compute_on_host_only_context_fails_loudly(hctx):
+    geo = B.Geometry(hctx, I.sphere_patches(), 1, 1)
+    op = B.Operator(hctx, geo, kappa=1.0, q=2, leaf_depth=0)
+    st = B._lib.h2_matvec(op.h, B.C.c_void_p(8), B.C.c_void_p(16), 1, 3, None)
+    assert st == -1
+
+
+def test_budget_rejects_before_allocating():
+    ctx = B.Context(B.IGB_HOST_ONLY, hbm_budget=1000)
+    with pytest.raises(B.IgbError) as e:
+        B.Geometry(ctx, I.sphere_patches(), 3, 2)
+    assert e.value.status == -3
