@@ -1,0 +1,220 @@
+"""Benchmark: H^2 CFIE matvecs/s on one MI355X.
+
+Workload (default): the unit sphere as six rational-quadratic patches, level
+m = 5 (6144 elements), degree-2 B-splines (N = 6936), kappa = 8, sound-soft
+CFIE, interpolation degree q = 6, admissibility eta = 1.6, leaf depth 2, fp64,
+one incident plane wave d = (0,0,1), GMRES(30) to 1e-8.
+
+One timed step = one CFIE solve on the assembled operator (right-hand side,
+restarted GMRES with one H^2 matvec plus CGS2 Arnoldi per iteration, final
+residual check) followed by the far field at 64 directions.  `value` counts
+every operator application inside the timed steps.  Operator assembly (near
+field quadrature + coupling matrices) is timed separately and reported.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "H2 matvecs/s and CFIE solves/s vs plain FP64 at 1e-6 rel err; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "sphere_m5_p2_k8": dict(geometry="sphere", m=5, p=2, kappa=8.0, q=6, eta_adm=1.6, leaf_depth=2,
+                            kcap=0.0, tol=1e-8, golden="sphere_m5_p2_k8_rows"),
+}
+
+
+def cpu_baseline(w, seconds_target=20.0):
+    """The oracle (dense O1 Galerkin rows, fp64 NumPy) timed on the host: rows
+    of the dense CFIE matrix applied to the same vector; one oracle matvec is
+    extrapolated from the sampled rows (x N / rows)."""
+    from oracle import galerkin as G  # test infrastructure: baseline leg only
+    from paper_2306_11324_amd import inputs as I
+    pts = I.sphere_patches() if w["geometry"] == "sphere" else I.star_patches(0, min(w["m"], 4))
+    bem = G.DenseBEM(pts, p=w["p"], m=w["m"], kappa=w["kappa"], bc="soft")
+    x = I.random_complex(12345, bem.n)
+    rng = np.random.default_rng(4321)
+    rows_done, t_used = 0, 0.0
+    while t_used < seconds_target and rows_done < 64:
+        r = rng.integers(0, bem.n, 1)
+        t0 = time.perf_counter()
+        _ = bem.rows(r) @ x
+        t_used += time.perf_counter() - t0
+        rows_done += 1
+    per_matvec = t_used / rows_done * bem.n
+    return {"value": 1.0 / per_matvec, "unit": "matvecs/s", "cores": bem.workers, "kind": "oracle",
+            "sample": f"{rows_done} rows of the dense fp64 Galerkin CFIE matrix (N={bem.n}) assembled "
+                      f"and applied in {t_used:.1f} s, extrapolated x N/{rows_done}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sphere_m5_p2_k8", choices=sorted(WORKLOADS))
+    ap.add_argument("--matvecs", type=int, default=50, help="matvec-only timing loop length")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration for profiles)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "described in DESIGN.md but not built)"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2306_11324_amd import binding as B
+    from paper_2306_11324_amd import inputs as I
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.init()
+    ctx = B.Context(0)
+    pts = I.sphere_patches() if w["geometry"] == "sphere" else I.star_patches(0, min(w["m"], 4))
+    t0 = time.perf_counter()
+    geo = B.Geometry(ctx, pts, w["m"], w["p"])
+    op = B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"], kcap=w["kcap"],
+                    leaf_depth=w["leaf_depth"])
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    info = op.info
+    n = op.n
+    print(f"# workload {args.workload}: N={n} far_pairs={info.far_pairs} near_pairs={info.near_elem_pairs} "
+          f"nnz={info.nnz} device={info.device_bytes / 1e9:.2f} GB setup={t_setup:.2f}s "
+          f"(near {info.assembly_near_ms:.0f} ms, far {info.assembly_far_ms:.0f} ms)", file=sys.stderr, flush=True)
+
+    d = np.array([[0.0, 0.0, 1.0]])
+    obs = I.fibonacci_directions(64)
+    coeff = torch.zeros(n, dtype=torch.complex128, device=dev)
+    uinf = torch.zeros(64, dtype=torch.complex128, device=dev)
+
+    def step():
+        sinfo, st = op.cfie_solve(d, coeff, tol=w["tol"], restart=30, maxit=2000)
+        op.farfield(coeff, obs, uinf)
+        return sinfo
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    mv_total, iters = 0, []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        si = step()
+        mv_total += si.matvecs
+        iters.append(si.iters)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    value = mv_total / T
+    relres_true = si.relres_true
+
+    # matvec-only loop with HIP-event kernel timing on the launch stream
+    x = torch.from_numpy(I.random_complex(12345, n)).to(dev)
+    y = torch.zeros_like(x)
+    op.h2_matvec(x, y)
+    torch.cuda.synchronize()
+    op.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.matvecs):
+        op.h2_matvec(x, y)
+    torch.cuda.synchronize()
+    t_mv = (time.perf_counter() - t0) / args.matvecs
+    m2l_n, m2l_ms = op.kernel_time("m2l")
+    spmv_n, spmv_ms = op.kernel_time("spmv")
+    up_n, up_ms = op.kernel_time("upward")
+    dn_n, dn_ms = op.kernel_time("downward")
+    op.profile(False)
+    op.h2_matvec(x, y)
+    torch.cuda.synchronize()
+    yv = y.cpu().numpy()
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    nq = info.nq
+    m2l_bytes = info.far_pairs * nq * nq * 16 + info.far_pairs * nq * 16
+    m2l_avg = m2l_ms / max(m2l_n, 1) / 1e3
+    achieved = m2l_bytes / m2l_avg / 1e9 if m2l_n else None
+
+    # error against the stored fp64 oracle rows / Mie
+    err_oracle = None
+    gp = os.path.join(ROOT, "tests", "golden", w["golden"] + ".npz")
+    if os.path.exists(gp):
+        g = np.load(gp)
+        xg = torch.from_numpy(g["x"]).to(dev)
+        yg = torch.zeros_like(xg)
+        op.h2_matvec(xg, yg)
+        torch.cuda.synchronize()
+        yr = yg.cpu().numpy()[g["rows"]]
+        err_oracle = float(np.max(np.abs(yr - g["y"]) / (g["rownorm1"] * np.abs(g["x"]).max())))
+    err_mie = None
+    if w["geometry"] == "sphere":
+        from scipy.special import eval_legendre, spherical_jn, spherical_yn
+        ka = w["kappa"]
+        ct = obs @ d[0]
+        ref = np.zeros(len(ct), dtype=np.complex128)
+        for nn in range(int(ka) + 30):
+            h = spherical_jn(nn, ka) + 1j * spherical_yn(nn, ka)
+            ref += (2 * nn + 1) * spherical_jn(nn, ka) / h * eval_legendre(nn, ct)
+        ref *= 1j / ka
+        u = uinf.cpu().numpy()
+        err_mie = float(np.abs(u - ref).max() / np.abs(ref).max())
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "geometry": "unit sphere, 6 rational-quadratic patches",
+                   "level_m": w["m"], "degree_p": w["p"], "N": n, "kappa": w["kappa"], "bc": "soft",
+                   "q": w["q"], "eta_adm": w["eta_adm"], "kcap": w["kcap"], "leaf_depth": w["leaf_depth"],
+                   "rhs": 1, "gmres": f"restart 30, tol {w['tol']}", "far_pairs": info.far_pairs,
+                   "nnz_near": info.nnz},
+        "solves_per_s": args.steps / T,
+        "gmres_iters": iters[-1],
+        "relres_true": relres_true,
+        "matvec_only_per_s": 1.0 / t_mv,
+        "assembly_ms": info.assembly_near_ms + info.assembly_far_ms,
+        "assembly_near_ms": info.assembly_near_ms,
+        "assembly_far_ms": info.assembly_far_ms,
+        "kernel_ms": {"m2l": m2l_ms / max(m2l_n, 1), "spmv": spmv_ms / max(spmv_n, 1),
+                      "upward": up_ms / max(up_n, 1), "downward": dn_ms / max(dn_n, 1)},
+        "err_matvec_vs_oracle_rows": err_oracle,
+        "err_farfield_vs_mie": err_mie,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "kernel": "m2l_chunks", "bytes_per_launch": m2l_bytes,
+                     "avg_launch_ms": m2l_avg * 1e3},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -105,6 +105,7 @@ typedef struct {
     int converged;    /* number of columns that reached tol                         */
     double relres;    /* max over columns of the final recursive relative residual   */
     double relres_true; /* max over columns of ||b - A x||/||b|| recomputed at the end */
+    int64_t matvecs;  /* operator applications in total (Arnoldi + residual checks) */
 } igb_solve_info;
 
 typedef struct {

@@ -45,7 +45,7 @@ class IgbSolveParams(C.Structure):
 
 class IgbSolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("relres", C.c_double),
-                ("relres_true", C.c_double)]
+                ("relres_true", C.c_double), ("matvecs", C.c_int64)]
 
 
 class IgbOpInfo(C.Structure):

@@ -143,6 +143,7 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
         IGB_HIP(hipStreamSynchronize(s));
         const double bnorm = std::sqrt(nrm_h);
         int iters = 0;
+        int64_t applications = 0;
         bool conv = bnorm == 0.0;
         double relres = conv ? 0.0 : 1.0;
         IGB_HIP(hipMemcpyAsync(r, B, n * sizeof(double2), hipMemcpyDeviceToDevice, s));
@@ -158,6 +159,7 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
                                               reinterpret_cast<double*>(w), 1, IGB_PART_ALL, s);
                 if (st) return st;
                 ++iters;
+                ++applications;
                 // CGS2
                 hipLaunchKernelGGL(cdots, dim3(j + 1), dim3(RT), 0, s, V, n, w, h, 0);
                 hipLaunchKernelGGL(cmaxpy, dim3(gb), dim3(256), 0, s, V, j + 1, n, h, w);
@@ -219,6 +221,7 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
             igb_status st = matvec_device(op, reinterpret_cast<const double*>(X), reinterpret_cast<double*>(r), 1,
                                           IGB_PART_ALL, s);
             if (st) return st;
+            ++applications;
             hipLaunchKernelGGL(csub_from, dim3(gb), dim3(256), 0, s, B, n, r);
             hipLaunchKernelGGL(cnorm2, dim3(1), dim3(1024), 0, s, r, n, nrm);
             IGB_HIP(hipMemcpyAsync(&nrm_h, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -229,6 +232,7 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
         }
         const double true_rel = bnorm > 0 ? rnorm / bnorm : 0.0;
         out.iters = std::max(out.iters, iters);
+        out.matvecs += applications;
         out.converged += conv ? 1 : 0;
         out.relres = std::max(out.relres, relres);
         out.relres_true = std::max(out.relres_true, true_rel);
