@@ -81,7 +81,8 @@ typedef enum { IGB_FP64 = 0, IGB_MIX_FP32 = 1, IGB_MIX_BF16 = 2 } igb_prec;
  *              for the boxes of the clusters' Bezier control points (Sec. 4.4
  *              gives eta = 1.6 without the inequality; this reading)
  *   kcap       if > 0, a block is admissible only if kappa*max(diam) <= kcap
- *   leaf_depth clusters stop at 4^leaf_depth elements (leaf level m - leaf_depth)
+ *   leaf_depth clusters stop at 4^leaf_depth elements (leaf level m - leaf_depth),
+ *              0 <= leaf_depth <= 6
  *   precision  far-field coupling storage; this build: IGB_FP64 only */
 typedef struct {
     double kappa;

@@ -141,8 +141,9 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
         return IGB_ERR_ARG;
     }
     if (!(prm->kappa > 0) || prm->q < 1 || prm->q > QMAX || !(prm->eta_adm > 0) || prm->leaf_depth < 0 ||
+        prm->leaf_depth > 6 ||
         (prm->bc != IGB_SOFT && prm->bc != IGB_HARD)) {
-        set_error("assemble_nearfield: need kappa > 0, 1 <= q <= %d, eta_adm > 0, leaf_depth >= 0, bc soft/hard",
+        set_error("assemble_nearfield: need kappa > 0, 1 <= q <= %d, eta_adm > 0, 0 <= leaf_depth <= 6, bc soft/hard",
                   QMAX);
         return IGB_ERR_ARG;
     }

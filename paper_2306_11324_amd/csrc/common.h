@@ -123,7 +123,7 @@ struct igb_op_s {
     igb::DevBuf d_near_ptr, d_near_src;
     igb::DevBuf d_s2_to_s0, d_s0_ptr, d_s0_reps;
     igb::DevBuf d_chunk_tgt, d_chunk_pair, d_chunk_len, d_tgt_chunk_ptr, d_far_src;
-    igb::DevBuf d_xhat, d_yhat, d_part, d_yfar, d_x2, d_cluoff;
+    igb::DevBuf d_xhat, d_yhat, d_part, d_yfar, d_x2, d_cluoff, d_leafbuf;
     size_t dev_bytes = 0;
     int64_t nclusters = 0;
     // solver scratch

@@ -534,40 +534,174 @@ __global__ void leaf_moments(const double2* x, const double* m1, int q, int d, i
     xh[(leaf_off + c) * nq + a] = acc;
 }
 
-// upward: xh[parent][a] = sum_children sum_g T_c[g][a] xh[child][g]
-__global__ void m2m(const double* T1, int q, int l, const int64_t* clu_off, double2* xh) {
-    const int nq = (q + 1) * (q + 1), q1 = q + 1;
-    const int64_t nc = clu_off[l + 1] - clu_off[l];
-    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (gid >= nc * nq) return;
-    const int64_t c = gid / nq;
-    const int a = int(gid % nq), au = a % q1, av = a / q1;
+// ---- workgroup-per-cluster tree kernels (LDS staged, sum-factorised) ----
+constexpr int TREE_THREADS = 128;
+constexpr int TQ1 = QMAX + 1;
+constexpr int TNQ = TQ1 * TQ1;
+
+// upward, one workgroup per parent at level l:
+//   x^_P[av][au] = sum_c sum_gv Tv_c[gv][av] sum_gu Tu_c[gu][au] x^_c[gv][gu]
+__global__ __launch_bounds__(TREE_THREADS) void m2m_wg(const double* __restrict__ T1, int q, int l,
+                                                       int64_t off_l, int64_t off_l1, double2* xh) {
+    __shared__ double T[2 * TQ1 * TQ1];
+    __shared__ double2 X[4 * TNQ];
+    __shared__ double2 tmp[4 * TNQ];
+    const int q1 = q + 1, nq = q1 * q1, tid = threadIdx.x;
+    const int64_t c = blockIdx.x;
     const int n = 1 << l;
     const int patch = int(c / (int64_t(n) * n));
     const int rem = int(c % (int64_t(n) * n));
     const int cy = rem / n, cx = rem % n;
-    double2 acc = make_double2(0, 0);
-    for (int ch = 0; ch < 4; ++ch) {
-        const int bu = ch & 1, bv = ch >> 1;
-        const int64_t child = clu_off[l + 1] + (int64_t(patch) << (2 * (l + 1))) +
-                              (int64_t(2 * cy + bv) << (l + 1)) + 2 * cx + bu;
-        const double* Tu = T1 + bu * q1 * q1;
-        const double* Tv = T1 + bv * q1 * q1;
-        const double2* X = xh + child * nq;
-        for (int gv = 0; gv < q1; ++gv) {
-            double2 row = make_double2(0, 0);
-            for (int gu = 0; gu < q1; ++gu) {
-                const double2 xv = X[gv * q1 + gu];
-                const double t = Tu[gu * q1 + au];
-                row.x = fma(t, xv.x, row.x);
-                row.y = fma(t, xv.y, row.y);
+    for (int i = tid; i < 2 * q1 * q1; i += TREE_THREADS) T[i] = T1[i];
+    for (int i = tid; i < 4 * nq; i += TREE_THREADS) {
+        const int ch = i / nq, a = i % nq, bu = ch & 1, bv = ch >> 1;
+        const int64_t child = off_l1 + (int64_t(patch) << (2 * (l + 1))) + (int64_t(2 * cy + bv) << (l + 1)) +
+                              2 * cx + bu;
+        X[i] = xh[child * nq + a];
+    }
+    __syncthreads();
+    for (int i = tid; i < 4 * nq; i += TREE_THREADS) {
+        const int ch = i / nq, r = i % nq, gv = r / q1, au = r % q1, bu = ch & 1;
+        const double* Tu = T + bu * q1 * q1;
+        double2 acc = make_double2(0, 0);
+        for (int gu = 0; gu < q1; ++gu) {
+            const double t = Tu[gu * q1 + au];
+            const double2 xv = X[ch * nq + gv * q1 + gu];
+            acc.x = fma(t, xv.x, acc.x);
+            acc.y = fma(t, xv.y, acc.y);
+        }
+        tmp[i] = acc;
+    }
+    __syncthreads();
+    for (int a = tid; a < nq; a += TREE_THREADS) {
+        const int av = a / q1, au = a % q1;
+        double2 acc = make_double2(0, 0);
+        for (int ch = 0; ch < 4; ++ch) {
+            const double* Tv = T + (ch >> 1) * q1 * q1;
+            for (int gv = 0; gv < q1; ++gv) {
+                const double t = Tv[gv * q1 + av];
+                const double2 v = tmp[ch * nq + gv * q1 + au];
+                acc.x = fma(t, v.x, acc.x);
+                acc.y = fma(t, v.y, acc.y);
             }
+        }
+        xh[(off_l + c) * nq + a] = acc;
+    }
+}
+
+// downward, one workgroup per parent at level l:
+//   y^_c[gv][gu] += sum_av Tv_c[gv][av] sum_au Tu_c[gu][au] y^_P[av][au]
+__global__ __launch_bounds__(TREE_THREADS) void l2l_wg(const double* __restrict__ T1, int q, int l,
+                                                       int64_t off_l, int64_t off_l1, double2* yh) {
+    __shared__ double T[2 * TQ1 * TQ1];
+    __shared__ double2 Y[TNQ];
+    __shared__ double2 tmp[2 * TNQ];
+    const int q1 = q + 1, nq = q1 * q1, tid = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    const int n = 1 << l;
+    const int patch = int(c / (int64_t(n) * n));
+    const int rem = int(c % (int64_t(n) * n));
+    const int cy = rem / n, cx = rem % n;
+    for (int i = tid; i < 2 * q1 * q1; i += TREE_THREADS) T[i] = T1[i];
+    for (int i = tid; i < nq; i += TREE_THREADS) Y[i] = yh[(off_l + c) * nq + i];
+    __syncthreads();
+    // tmp[bv][gv][au] = sum_av Tv[bv][gv][av] Y[av][au]
+    for (int i = tid; i < 2 * nq; i += TREE_THREADS) {
+        const int bv = i / nq, r = i % nq, gv = r / q1, au = r % q1;
+        const double* Tv = T + bv * q1 * q1;
+        double2 acc = make_double2(0, 0);
+        for (int av = 0; av < q1; ++av) {
             const double t = Tv[gv * q1 + av];
-            acc.x = fma(t, row.x, acc.x);
-            acc.y = fma(t, row.y, acc.y);
+            const double2 v = Y[av * q1 + au];
+            acc.x = fma(t, v.x, acc.x);
+            acc.y = fma(t, v.y, acc.y);
+        }
+        tmp[i] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < 4 * nq; i += TREE_THREADS) {
+        const int ch = i / nq, g = i % nq, gv = g / q1, gu = g % q1, bu = ch & 1, bv = ch >> 1;
+        const double* Tu = T + bu * q1 * q1;
+        double2 acc = make_double2(0, 0);
+        for (int au = 0; au < q1; ++au) {
+            const double t = Tu[gu * q1 + au];
+            const double2 v = tmp[bv * nq + gv * q1 + au];
+            acc.x = fma(t, v.x, acc.x);
+            acc.y = fma(t, v.y, acc.y);
+        }
+        const int64_t child = off_l1 + (int64_t(patch) << (2 * (l + 1))) + (int64_t(2 * cy + bv) << (l + 1)) +
+                              2 * cx + bu;
+        double2* dst = yh + child * nq + g;
+        *dst = cadd(*dst, acc);
+    }
+}
+
+// back projection, one workgroup per leaf: out[lv][lu] = sum_av m_v[av][lv] sum_au m_u[au][lu] y^[av][au]
+// over the leaf's (s+p)^2 window, written to a per-leaf buffer
+constexpr int WMAX = 64 + PMAX;
+__global__ __launch_bounds__(TREE_THREADS) void back_project_leaf(const double2* __restrict__ yh,
+                                                                  const double* __restrict__ m1, int q, int w,
+                                                                  int L, int64_t leaf_off, int deriv_u,
+                                                                  int deriv_v, int64_t m1_stride_kind,
+                                                                  double2* __restrict__ leafbuf) {
+    __shared__ double2 Y[TNQ];
+    __shared__ double2 tmp[TQ1 * WMAX];
+    const int q1 = q + 1, nq = q1 * q1, tid = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    const int n = 1 << L;
+    const int rem = int(c % (int64_t(n) * n));
+    const int cy = rem / n, cx = rem % n;
+    const double* mu = m1 + deriv_u * m1_stride_kind + int64_t(cx) * q1 * w;
+    const double* mv = m1 + deriv_v * m1_stride_kind + int64_t(cy) * q1 * w;
+    for (int i = tid; i < nq; i += TREE_THREADS) Y[i] = yh[(leaf_off + c) * nq + i];
+    __syncthreads();
+    for (int i = tid; i < q1 * w; i += TREE_THREADS) {
+        const int av = i / w, lu = i % w;
+        double2 acc = make_double2(0, 0);
+        for (int au = 0; au < q1; ++au) {
+            const double t = mu[au * w + lu];
+            acc.x = fma(t, Y[av * q1 + au].x, acc.x);
+            acc.y = fma(t, Y[av * q1 + au].y, acc.y);
+        }
+        tmp[i] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < w * w; i += TREE_THREADS) {
+        const int lv = i / w, lu = i % w;
+        double2 acc = make_double2(0, 0);
+        for (int av = 0; av < q1; ++av) {
+            const double t = mv[av * w + lv];
+            acc.x = fma(t, tmp[av * w + lu].x, acc.x);
+            acc.y = fma(t, tmp[av * w + lu].y, acc.y);
+        }
+        leafbuf[c * w * w + i] = acc;
+    }
+}
+
+// y[i] (+)= sum over the leaves whose window contains i (fixed order)
+__global__ void leaf_gather(const double2* __restrict__ leafbuf, int d, int p, int L, int k, int npatch,
+                            double2* __restrict__ y, int accumulate) {
+    const int64_t n2 = int64_t(npatch) * k * k;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n2) return;
+    const int patch = int(i / (int64_t(k) * k));
+    const int rem = int(i % (int64_t(k) * k));
+    const int iv = rem / k, iu = rem % k;
+    const int s = 1 << d, w = s + p, n = 1 << L;
+    double2 acc = make_double2(0, 0);
+    const int cy0 = max(0, (iv - w + s) / s), cy1 = min(n - 1, iv / s);
+    const int cx0 = max(0, (iu - w + s) / s), cx1 = min(n - 1, iu / s);
+    for (int cy = cy0; cy <= cy1; ++cy) {
+        const int lv = iv - cy * s;
+        if (lv < 0 || lv >= w) continue;
+        for (int cx = cx0; cx <= cx1; ++cx) {
+            const int lu = iu - cx * s;
+            if (lu < 0 || lu >= w) continue;
+            const int64_t leaf = (int64_t(patch) << (2 * L)) + int64_t(cy) * n + cx;
+            acc = cadd(acc, leafbuf[leaf * w * w + lv * w + lu]);
         }
     }
-    xh[(clu_off[l] + c) * nq + a] = acc;
+    y[i] = accumulate ? cadd(y[i], acc) : acc;
 }
 
 // coupling: one workgroup per chunk of source clusters of one target
@@ -609,81 +743,6 @@ __global__ void m2l_reduce(const double2* part, const int* tgt_chunk_ptr, int64_
     double2 s = make_double2(0, 0);
     for (int ch = tgt_chunk_ptr[c]; ch < tgt_chunk_ptr[c + 1]; ++ch) s = cadd(s, part[int64_t(ch) * nq + a]);
     yh[gid] = s;
-}
-
-// downward: yh[child][g] += sum_a T_c[g][a] yh[parent][a]
-__global__ void l2l(const double* T1, int q, int l /* parent level */, const int64_t* clu_off,
-                    double2* yh) {
-    const int nq = (q + 1) * (q + 1), q1 = q + 1;
-    const int64_t nc = clu_off[l + 2] - clu_off[l + 1];
-    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (gid >= nc * nq) return;
-    const int64_t c = gid / nq;
-    const int g = int(gid % nq), gu = g % q1, gv = g / q1;
-    const int n = 1 << (l + 1);
-    const int patch = int(c / (int64_t(n) * n));
-    const int rem = int(c % (int64_t(n) * n));
-    const int cy = rem / n, cx = rem % n;
-    const int bu = cx & 1, bv = cy & 1;
-    const int64_t parent = clu_off[l] + (int64_t(patch) << (2 * l)) + (int64_t(cy >> 1) << l) + (cx >> 1);
-    const double* Tu = T1 + bu * q1 * q1;
-    const double* Tv = T1 + bv * q1 * q1;
-    const double2* Y = yh + parent * nq;
-    double2 acc = make_double2(0, 0);
-    for (int av = 0; av < q1; ++av) {
-        double2 row = make_double2(0, 0);
-        for (int au = 0; au < q1; ++au) {
-            const double2 yv = Y[av * q1 + au];
-            const double t = Tu[gu * q1 + au];
-            row.x = fma(t, yv.x, row.x);
-            row.y = fma(t, yv.y, row.y);
-        }
-        const double t = Tv[gv * q1 + av];
-        acc.x = fma(t, row.x, acc.x);
-        acc.y = fma(t, row.y, acc.y);
-    }
-    double2* dst = yh + (clu_off[l + 1] + c) * nq + g;
-    *dst = cadd(*dst, acc);
-}
-
-// back projection onto S^2: y[i] = sum_{leaves containing i} sum_a m1 m1 yh[leaf][a]
-__global__ void back_project(const double2* yh, const double* m1, int q, int d, int p, int L, int k,
-                             int npatch, int64_t leaf_off, double2* y, int deriv_u, int deriv_v,
-                             int64_t m1_stride_kind, int accumulate) {
-    const int64_t n2 = int64_t(npatch) * k * k;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n2) return;
-    const int q1 = q + 1, nq = q1 * q1;
-    const int patch = int(i / (int64_t(k) * k));
-    const int rem = int(i % (int64_t(k) * k));
-    const int iv = rem / k, iu = rem % k;
-    const int s = 1 << d, w = s + p, n = 1 << L;
-    double2 acc = make_double2(0, 0);
-    const int cy0 = max(0, (iv - w + s) / s), cy1 = min(n - 1, iv / s);
-    const int cx0 = max(0, (iu - w + s) / s), cx1 = min(n - 1, iu / s);
-    for (int cy = cy0; cy <= cy1; ++cy) {
-        const int lv = iv - cy * s;
-        if (lv < 0 || lv >= w) continue;
-        for (int cx = cx0; cx <= cx1; ++cx) {
-            const int lu = iu - cx * s;
-            if (lu < 0 || lu >= w) continue;
-            const double2* Y = yh + (leaf_off + (int64_t(patch) << (2 * L)) + int64_t(cy) * n + cx) * nq;
-            double2 sum = make_double2(0, 0);
-            for (int av = 0; av < q1; ++av) {
-                const double mv = m1[deriv_v * m1_stride_kind + (int64_t(cy) * q1 + av) * w + lv];
-                double2 row = make_double2(0, 0);
-                for (int au = 0; au < q1; ++au) {
-                    const double mu = m1[deriv_u * m1_stride_kind + (int64_t(cx) * q1 + au) * w + lu];
-                    row.x = fma(mu, Y[av * q1 + au].x, row.x);
-                    row.y = fma(mu, Y[av * q1 + au].y, row.y);
-                }
-                sum.x = fma(mv, row.x, sum.x);
-                sum.y = fma(mv, row.y, sum.y);
-            }
-            acc = cadd(acc, sum);
-        }
-    }
-    y[i] = accumulate ? cadd(y[i], acc) : acc;
 }
 
 // y[row] = sum_j val x[col] (+ far part mapped to the solution space); one wave
@@ -1281,6 +1340,10 @@ igb_status alloc_work(igb_op op, int nrhs) {
             return st;
         if ((st = alloc(op->d_yfar, size_t(op->geom->n2) * sizeof(double2), acct))) return st;
         if ((st = alloc(op->d_x2, size_t(op->geom->n2) * sizeof(double2), acct))) return st;
+        const int64_t w = (int64_t(1) << op->d) + op->geom->p;
+        if ((st = alloc(op->d_leafbuf, size_t(clusters_on_level(op->geom->npatch, op->L)) * w * w * sizeof(double2),
+                        acct)))
+            return st;
         // cluster offsets are needed on the device by m2m / l2l
         if ((st = upload(op->d_cluoff, op->clu_off.data(), op->clu_off.size(), acct))) return st;
     }
@@ -1330,8 +1393,8 @@ igb_status matvec_device(igb_op op, const double* x, double* y, int nrhs, int pa
                            stride_kind);
         for (int l = L - 1; l >= 0; --l) {
             const int64_t nc = clusters_on_level(g->npatch, l);
-            hipLaunchKernelGGL(m2m, dim3(unsigned((nc * nq + 255) / 256)), dim3(256), 0, s,
-                               op->d_T.as<double>(), q, l, clu_off, xh);
+            hipLaunchKernelGGL(m2m_wg, dim3(unsigned(nc)), dim3(TREE_THREADS), 0, s, op->d_T.as<double>(), q, l,
+                               op->clu_off[l], op->clu_off[l + 1], xh);
         }
         if ((st = timer_mark(op, 2, s))) return st;
         const int64_t nchunk = int64_t(op->chunk_len.size());
@@ -1352,13 +1415,17 @@ igb_status matvec_device(igb_op op, const double* x, double* y, int nrhs, int pa
         hipLaunchKernelGGL(m2l_reduce, dim3(unsigned((op->nclusters * nq + 255) / 256)), dim3(256), 0, s,
                            op->d_part.as<double2>(), op->d_tgt_chunk_ptr.as<int>(), op->nclusters, nq, yh);
         for (int l = 0; l < L; ++l) {
-            const int64_t nc = clusters_on_level(g->npatch, l + 1);
-            hipLaunchKernelGGL(l2l, dim3(unsigned((nc * nq + 255) / 256)), dim3(256), 0, s,
-                               op->d_T.as<double>(), q, l, clu_off, yh);
+            const int64_t nc = clusters_on_level(g->npatch, l);
+            hipLaunchKernelGGL(l2l_wg, dim3(unsigned(nc)), dim3(TREE_THREADS), 0, s, op->d_T.as<double>(), q, l,
+                               op->clu_off[l], op->clu_off[l + 1], yh);
         }
-        hipLaunchKernelGGL(back_project, dim3(unsigned((g->n2 + 255) / 256)), dim3(256), 0, s, yh,
-                           op->d_m1.as<double>(), q, op->d, g->p, L, g->k, g->npatch, op->clu_off[L],
-                           op->d_yfar.as<double2>(), 0, 0, stride_kind, 0);
+        const int w = (1 << op->d) + g->p;
+        hipLaunchKernelGGL(back_project_leaf, dim3(unsigned(nleaf)), dim3(TREE_THREADS), 0, s, yh,
+                           op->d_m1.as<double>(), q, w, L, op->clu_off[L], 0, 0, stride_kind,
+                           op->d_leafbuf.as<double2>());
+        hipLaunchKernelGGL(leaf_gather, dim3(unsigned((g->n2 + 255) / 256)), dim3(256), 0, s,
+                           op->d_leafbuf.as<double2>(), op->d, g->p, L, g->k, g->npatch,
+                           op->d_yfar.as<double2>(), 0);
         if ((st = timer_mark(op, 3, s))) return st;
     }
     const int64_t N = op->N;
