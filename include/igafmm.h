@@ -15,7 +15,9 @@
  *     hip_stream argument are ordered on that stream (NULL = the context's own
  *     stream) and return before the device work completes.
  *   - The caller owns every buffer it passes; the library copies what it keeps.
- *     Handles own their device memory until destroyed.  Assembled operators are
+ *     Handles own their device memory until destroyed; they may be destroyed in
+ *     any order (an operator keeps its geometry, a geometry its context alive
+ *     until the last dependent handle is destroyed).  Assembled operators are
  *     immutable: concurrent igb_h2_matvec calls on one operator from different
  *     streams are allowed; calls that share an operator's internal work
  *     vectors (h2_matvec, cfie_solve) must not overlap on the same operator.
@@ -83,7 +85,11 @@ typedef enum { IGB_FP64 = 0, IGB_MIX_FP32 = 1, IGB_MIX_BF16 = 2 } igb_prec;
  *   kcap       if > 0, a block is admissible only if kappa*max(diam) <= kcap
  *   leaf_depth clusters stop at 4^leaf_depth elements (leaf level m - leaf_depth),
  *              0 <= leaf_depth <= 6
- *   precision  far-field coupling storage; this build: IGB_FP64 only */
+ *   precision  far-field coupling storage: IGB_FP64; IGB_MIX_FP32 / IGB_MIX_BF16 keep
+ *              the fp64 couplings and add a copy rounded (RNE) to fp32 / bf16 that
+ *              cfie_solve uses inside iterative refinement (inner GMRES on the
+ *              rounded far field, outer residual in fp64) and h2_matvec uses with
+ *              IGB_MV_LOWPREC; near field, Arnoldi and residuals stay fp64 */
 typedef struct {
     double kappa;
     int bc;
@@ -98,7 +104,10 @@ typedef struct {
 typedef struct {
     double tol;      /* relative residual ||b - A x|| / ||b||, Euclidean on coefficients */
     int restart;     /* GMRES restart length (the paper uses 30, Sec. 5.1)              */
-    int maxit;       /* maximal number of matrix-vector products per column             */
+    int maxit;       /* maximal number of Arnoldi steps per column                      */
+    double inner_tol;/* mixed precision: lower bound of the inner relative tolerance;
+                        <= 0 selects 0 (fp32) / 1e-3 (bf16)                             */
+    int refine_max;  /* mixed precision: maximal refinement steps (<= 0: 10)           */
 } igb_solve_params;
 
 typedef struct {
@@ -107,6 +116,7 @@ typedef struct {
     double relres;    /* max over columns of the final recursive relative residual   */
     double relres_true; /* max over columns of ||b - A x||/||b|| recomputed at the end */
     int64_t matvecs;  /* operator applications in total (Arnoldi + residual checks) */
+    int refinements;  /* mixed precision: outer refinement steps taken (all columns)  */
 } igb_solve_info;
 
 typedef struct {
@@ -192,6 +202,7 @@ igb_status igb_op_kernel_time(igb_op op, const char* name, int64_t* launches, do
 #define IGB_PART_NEAR 1
 #define IGB_PART_FAR 2
 #define IGB_PART_ALL 3
+#define IGB_MV_LOWPREC 4   /* with IGB_MIX_* operators: far field from the rounded copy */
 /* y = A x for nrhs columns (device arrays [nrhs][n] complex).  parts selects the
  * near-field (incl. 1/2 M) and/or far-field (H^2) contributions.  x and y must
  * not overlap.  This build: nrhs = 1 per call.  Stream-ordered. */
@@ -204,7 +215,9 @@ igb_status cfie_rhs(igb_op op, const double* dirs, int ndir, double* b, void* hi
 
 /* Solves the CFIE for ndir incident directions (host dirs [ndir][3]) with
  * restarted GMRES (Sec. 5.1), x0 = 0, writing the coefficients into the device
- * array coeffs [ndir][n].  Synchronous.  IGB_WARN_NOT_CONVERGED if a column
+ * array coeffs [ndir][n].  Operators with IGB_MIX_* precision solve by
+ * iterative refinement: x += GMRES(A_rounded, b - A_fp64 x) until the fp64
+ * residual reaches tol.  Synchronous.  IGB_WARN_NOT_CONVERGED if a column
  * stops at maxit. */
 igb_status cfie_solve(igb_op op, const double* dirs, int ndir, const igb_solve_params* sp,
                       double* coeffs, igb_solve_info* info);

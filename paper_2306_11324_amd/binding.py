@@ -25,6 +25,7 @@ IGB_HOST_ONLY = -1
 SOFT, HARD = 0, 1
 FP64, MIX_FP32, MIX_BF16 = 0, 1, 2
 PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
+MV_LOWPREC = 4
 
 
 class IgbPatch(C.Structure):
@@ -40,12 +41,13 @@ class IgbOpParams(C.Structure):
 
 
 class IgbSolveParams(C.Structure):
-    _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int)]
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("inner_tol", C.c_double),
+                ("refine_max", C.c_int)]
 
 
 class IgbSolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("relres", C.c_double),
-                ("relres_true", C.c_double), ("matvecs", C.c_int64)]
+                ("relres_true", C.c_double), ("matvecs", C.c_int64), ("refinements", C.c_int)]
 
 
 class IgbOpInfo(C.Structure):
@@ -233,9 +235,9 @@ class Operator:
         _check("cfie_rhs", _lib.cfie_rhs(self.h, pd, d.shape[0], _dptr(b, d.shape[0] * self.n), _stream(stream)))
         return b
 
-    def cfie_solve(self, dirs, coeffs, tol=1e-8, restart=30, maxit=1000):
+    def cfie_solve(self, dirs, coeffs, tol=1e-8, restart=30, maxit=1000, inner_tol=0.0, refine_max=0):
         d, pd = _dbl(np.atleast_2d(dirs))
-        sp = IgbSolveParams(tol, restart, maxit)
+        sp = IgbSolveParams(tol, restart, maxit, inner_tol, refine_max)
         info = IgbSolveInfo()
         st = _check("cfie_solve", _lib.cfie_solve(self.h, pd, d.shape[0], C.byref(sp),
                                                   _dptr(coeffs, d.shape[0] * self.n), C.byref(info)),

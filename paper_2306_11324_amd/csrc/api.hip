@@ -78,11 +78,23 @@ igb_status igb_ctx_create(int device, size_t hbm_budget_bytes, igb_ctx* out) {
     return IGB_OK;
 }
 
-void igb_ctx_destroy(igb_ctx ctx) {
-    if (!ctx) return;
+// Handles are reference counted so that the caller may destroy them in any
+// order: a geometry keeps its context alive, an operator its geometry.
+void ctx_release(igb_ctx ctx) {
+    if (!ctx || --ctx->refs > 0) return;
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
+
+void geom_release(igb_geom g) {
+    if (!g || --g->refs > 0) return;
+    igb_ctx ctx = g->ctx;
+    if (ctx) ctx->used -= std::min(ctx->used, g->dev_bytes);
+    delete g;
+    ctx_release(ctx);
+}
+
+void igb_ctx_destroy(igb_ctx ctx) { ctx_release(ctx); }
 
 size_t igb_ctx_used_bytes(igb_ctx ctx) { return ctx ? ctx->used : 0; }
 
@@ -114,15 +126,12 @@ igb_status build_geometry(igb_ctx ctx, const igb_patch* patches, int npatch, int
         return st;
     }
     ctx->used += g->dev_bytes;
+    ++ctx->refs;
     *out = g;
     return IGB_OK;
 }
 
-void igb_geom_destroy(igb_geom g) {
-    if (!g) return;
-    if (g->ctx) g->ctx->used -= std::min(g->ctx->used, g->dev_bytes);
-    delete g;
-}
+void igb_geom_destroy(igb_geom g) { geom_release(g); }
 
 igb_status igb_geom_dims(igb_geom g, int64_t dims[3]) {
     if (!g || !dims) {
@@ -147,9 +156,9 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
                   QMAX);
         return IGB_ERR_ARG;
     }
-    if (prm->precision != IGB_FP64) {
-        set_error("assemble_nearfield: only fp64 coupling storage is built");
-        return IGB_ERR_UNSUPPORTED;
+    if (prm->precision != IGB_FP64 && prm->precision != IGB_MIX_FP32 && prm->precision != IGB_MIX_BF16) {
+        set_error("assemble_nearfield: precision must be IGB_FP64, IGB_MIX_FP32 or IGB_MIX_BF16");
+        return IGB_ERR_ARG;
     }
     if (prm->bc == IGB_HARD && g->p < 1) {
         set_error("assemble_nearfield: sound-hard needs S^0, i.e. p >= 1");
@@ -176,7 +185,8 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
     }
     // device bytes of the operator (checked against the budget before allocating)
     const int nl = (g->p + 1) * (g->p + 1);
-    size_t need = size_t(op->nfar) * op->nq * op->nq * 16 + size_t(op->nnz) * 20 + size_t(op->N + 1) * 8 +
+    const size_t coup_elem = 16 + (prm->precision == IGB_MIX_FP32 ? 8 : prm->precision == IGB_MIX_BF16 ? 4 : 0);
+    size_t need = size_t(op->nfar) * op->nq * op->nq * coup_elem * (prm->bc == IGB_HARD ? 2 : 1) + size_t(op->nnz) * 20 + size_t(op->N + 1) * 8 +
                   size_t(op->nclusters) * op->nq * (16 * 8 + 32) + op->near_src.size() * 4 +
                   std::min<size_t>(op->near_src.size(), size_t(1) << 22) * nl * nl * 16;
     if (!budget_ok(ctx, need)) {
@@ -186,6 +196,7 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
     }
     hipStream_t s = ctx->stream;
     if (host_only(ctx)) {
+        ++g->refs;
         *out = op;
         return IGB_OK;
     }
@@ -194,16 +205,22 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
         return st;
     }
     ctx->used += op->dev_bytes;
+    ++g->refs;
     *out = op;
     return IGB_OK;
 }
 
 void igb_op_destroy(igb_op op) {
     if (!op) return;
-    if (!host_only(op->geom->ctx)) (void)hipDeviceSynchronize();
-    igb_ctx ctx = op->geom ? op->geom->ctx : nullptr;
-    if (ctx) ctx->used -= std::min(ctx->used, op->dev_bytes);
+    igb_geom g = op->geom;
+    igb_ctx ctx = g->ctx;
+    if (!host_only(ctx)) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+    }
+    ctx->used -= std::min(ctx->used, op->dev_bytes);
     delete op;
+    geom_release(g);
 }
 
 igb_status igb_op_get_info(igb_op op, igb_op_info* info) {
@@ -321,7 +338,7 @@ igb_status igb_op_kernel_time(igb_op op, const char* name, int64_t* launches, do
 }
 
 igb_status h2_matvec(igb_op op, const double* x, double* y, int nrhs, int parts, void* hip_stream) {
-    if (!op || !x || !y || nrhs < 1 || parts < 1 || parts > 3) {
+    if (!op || !x || !y || nrhs < 1 || (parts & 3) == 0 || parts > 7) {
         set_error("h2_matvec: invalid argument");
         return IGB_ERR_ARG;
     }

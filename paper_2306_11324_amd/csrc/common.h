@@ -52,6 +52,7 @@ struct DevBuf {
 }  // namespace igb
 
 struct igb_ctx_s {
+    int refs = 1;        // the caller's handle + one per live geometry
     int device = 0;
     size_t budget = 0;   // bytes the library may hold on this device (0 = no limit)
     size_t used = 0;     // bytes currently held by live geometries / operators
@@ -60,6 +61,7 @@ struct igb_ctx_s {
 
 // Per-element data of a discretised geometry.
 struct igb_geom_s {
+    int refs = 1;                // the caller's handle + one per live operator
     igb_ctx ctx = nullptr;
     int npatch = 0, m = 0, p = 0, nel1 = 0, k = 0;
     int64_t nelem = 0, n2 = 0, n0 = 0;
@@ -118,12 +120,12 @@ struct igb_op_s {
     std::vector<int> chunk_len;
     std::vector<int> tgt_chunk_ptr;   // [nclusters+1] chunks per target (global index)
     // device data
-    igb::DevBuf d_coupling, d_nodes, d_m1, d_T;
+    igb::DevBuf d_coupling, d_coupling_lo, d_nodes, d_m1, d_T;
     igb::DevBuf d_rowptr, d_col, d_val;
     igb::DevBuf d_near_ptr, d_near_src;
     igb::DevBuf d_s2_to_s0, d_s0_ptr, d_s0_reps;
     igb::DevBuf d_chunk_tgt, d_chunk_pair, d_chunk_len, d_tgt_chunk_ptr, d_far_src;
-    igb::DevBuf d_xhat, d_yhat, d_part, d_yfar, d_x2, d_cluoff, d_leafbuf;
+    igb::DevBuf d_xhat, d_yhat, d_yraw, d_part, d_yfar, d_x2, d_cluoff, d_leafbuf;
     size_t dev_bytes = 0;
     int64_t nclusters = 0;
     // solver scratch

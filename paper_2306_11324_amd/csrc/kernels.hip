@@ -178,15 +178,90 @@ struct NearArgs {
     int mass_order;
 };
 
-template <int P>
-__global__ __launch_bounds__(NEAR_THREADS) void near_regular_soft(NearArgs A) {
+// Kernel values at one point pair (element-local coordinates, n~ unnormalised):
+//   soft: s = a_y H (x-y).n~_x - i eta a_x a_y G                      (K* - i eta V)
+//   hard: s = a_x H (x-y).n~_y + i eta kappa^2 G n~_x.n~_y            (-K, kappa^2 part of -i eta W)
+//         g = -i eta G, multiplying the curl product c_i(x).c_j(y)    (curl part of -i eta W)
+struct KVal {
+    double2 s, g;
+};
+
+template <bool HARD>
+__device__ __forceinline__ KVal kernel_pair(const double* X, const double* NX, double ax, const double* Y,
+                                            const double* NY, double ay, double kappa, double eta) {
+    KVal k;
+    if (!HARD) {
+        k.s = kernel_soft(X, NX, ax, Y, ay, kappa, eta);
+        k.g = make_double2(0, 0);
+        return k;
+    }
+    const double d0 = X[0] - Y[0], d1 = X[1] - Y[1], d2 = X[2] - Y[2];
+    const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double ir = 1.0 / r;
+    const double kr = kappa * r;
+    double sn, cs;
+    sincos(kr, &sn, &cs);
+    const double c4 = 0.07957747154594767 * ir;
+    const double dny = d0 * NY[0] + d1 * NY[1] + d2 * NY[2];
+    const double nn = NX[0] * NY[0] + NX[1] * NY[1] + NX[2] * NY[2];
+    const double h = ax * dny * ir * ir * c4;
+    const double v = eta * kappa * kappa * nn * c4;
+    k.s = make_double2(h * (-cs - sn * kr) - v * sn, h * (cs * kr - sn) + v * cs);
+    k.g = make_double2(eta * c4 * sn, -eta * c4 * cs);
+    return k;
+}
+
+// Point data of one element at local (s,t): position, n~, a and, per local basis
+// function, w*phi (component 0) and for the hypersingular part w*c with
+// c = d_s phi F_t - d_t phi F_s (components 1..3).
+template <int P, bool HARD>
+__device__ __forceinline__ void point_data(const ElemRef& R, const double* Cu, const double* Cv, double s,
+                                           double t, double w, double* g7, double* ph /*[NL][NV]*/) {
+    constexpr int NV = HARD ? 4 : 1;
+    GeoPt G;
+    eval_geo(R.bez, R.pu, R.pv, s, t, G);
+    double nt[3];
+    cross3(G.fs, G.ft, nt);
+    g7[0] = G.x[0]; g7[1] = G.x[1]; g7[2] = G.x[2];
+    g7[3] = nt[0]; g7[4] = nt[1]; g7[5] = nt[2];
+    g7[6] = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+    double bu[P + 1], bv[P + 1], dbu[P + 1], dbv[P + 1];
+    eval_basis1<P>(Cu, s, bu, dbu);
+    eval_basis1<P>(Cv, t, bv, dbv);
+#pragma unroll
+    for (int av = 0; av <= P; ++av)
+#pragma unroll
+        for (int au = 0; au <= P; ++au) {
+            double* o = ph + (av * (P + 1) + au) * NV;
+            o[0] = w * bv[av] * bu[au];
+            if (HARD) {
+                const double ds = bv[av] * dbu[au], dt = dbv[av] * bu[au];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) o[1 + c] = w * (ds * G.ft[c] - dt * G.fs[c]);
+            }
+        }
+}
+
+// --------------------------------------------------------------------------
+// Near field: regular element pairs, tensor Gauss of order n (<= 7) on both
+// elements.  Kernel values are produced in chunks of CI test points in LDS;
+// thread items (j, a) accumulate T[j][a] = sum_i w phi_a(x_i) k(x_i, y_j);
+// finally B[a][b] = sum_j T[j][a] . w phi_b(y_j).
+// --------------------------------------------------------------------------
+template <int P, bool HARD>
+__global__ __launch_bounds__(NEAR_THREADS) void near_regular(NearArgs A) {
     constexpr int NL = (P + 1) * (P + 1);
-    constexpr int MAXQ = 64;  // n <= 8
-    __shared__ double xg[MAXQ][8];
-    __shared__ double yg[MAXQ][8];
-    __shared__ double px[MAXQ][NL];
-    __shared__ double py[MAXQ][NL];
-    __shared__ double2 tp[NEAR_THREADS * NL];
+    constexpr int NV = HARD ? 4 : 1;
+    constexpr int NK = HARD ? 2 : 1;
+    constexpr int MAXQ = 49;
+    constexpr int CI = 8;
+    constexpr int BUF = (CI * MAXQ * NK > MAXQ * NL * NV) ? CI * MAXQ * NK : MAXQ * NL * NV;
+    constexpr int ITEMS = (MAXQ * NL + NEAR_THREADS - 1) / NEAR_THREADS;
+    __shared__ double xg[MAXQ][7];
+    __shared__ double yg[MAXQ][7];
+    __shared__ double px[MAXQ][NL * NV];
+    __shared__ double py[MAXQ][NL * NV];
+    __shared__ double2 buf[BUF];
 
     const int64_t item = blockIdx.x;
     if (item >= A.nlist) return;
@@ -201,76 +276,86 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_regular_soft(NearArgs A) {
     if (tid < 2 * nn) {
         const bool isx = tid < nn;
         const int i = isx ? tid : tid - nn;
-        const double s = gx[i % n], t = gx[i / n];
-        const double w = gw[i % n] * gw[i / n];
-        ElemRef R = elem_ref(A.bez, A.pg, A.nel1, isx ? e : f);
-        GeoPt G;
-        eval_geo(R.bez, R.pu, R.pv, s, t, G);
-        double nt[3];
-        cross3(G.fs, G.ft, nt);
-        double* dst = isx ? xg[i] : yg[i];
-        dst[0] = G.x[0]; dst[1] = G.x[1]; dst[2] = G.x[2];
-        dst[3] = nt[0]; dst[4] = nt[1]; dst[5] = nt[2];
-        dst[6] = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
-        double bu[P + 1], bv[P + 1];
-        eval_basis1<P>(A.C1 + R.ex * (P + 1) * (P + 1), s, bu, nullptr);
-        eval_basis1<P>(A.C1 + R.ey * (P + 1) * (P + 1), t, bv, nullptr);
-        double* ph = isx ? px[i] : py[i];
-#pragma unroll
-        for (int av = 0; av <= P; ++av)
-#pragma unroll
-            for (int au = 0; au <= P; ++au) ph[av * (P + 1) + au] = w * bv[av] * bu[au];
+        const ElemRef R = elem_ref(A.bez, A.pg, A.nel1, isx ? e : f);
+        point_data<P, HARD>(R, A.C1 + R.ex * (P + 1) * (P + 1), A.C1 + R.ey * (P + 1) * (P + 1), gx[i % n],
+                            gx[i / n], gw[i % n] * gw[i / n], isx ? xg[i] : yg[i], isx ? px[i] : py[i]);
     }
     __syncthreads();
 
-    // T[j][a] = sum_i px[i][a] k(x_i, y_j), split over G groups of x-points
-    const int G = NEAR_THREADS / nn;
-    const int j = tid % nn, grp = tid / nn;
-    if (grp < G) {
-        double2 acc[NL];
+    double2 acc[ITEMS][NV];
 #pragma unroll
-        for (int a = 0; a < NL; ++a) acc[a] = make_double2(0, 0);
-        const double* Y = yg[j];
-        for (int i = grp; i < nn; i += G) {
-            const double2 kv = kernel_soft(xg[i], xg[i] + 3, xg[i][6], Y, Y[6], A.kappa, A.eta);
+    for (int it = 0; it < ITEMS; ++it)
 #pragma unroll
-            for (int a = 0; a < NL; ++a) {
-                acc[a].x = fma(px[i][a], kv.x, acc[a].x);
-                acc[a].y = fma(px[i][a], kv.y, acc[a].y);
+        for (int v = 0; v < NV; ++v) acc[it][v] = make_double2(0, 0);
+    for (int i0 = 0; i0 < nn; i0 += CI) {
+        const int ci = min(CI, nn - i0);
+        for (int idx = tid; idx < ci * nn; idx += NEAR_THREADS) {
+            const int i = i0 + idx / nn, j = idx % nn;
+            const KVal kv = kernel_pair<HARD>(xg[i], xg[i] + 3, xg[i][6], yg[j], yg[j] + 3, yg[j][6], A.kappa, A.eta);
+            buf[idx * NK] = kv.s;
+            if (HARD) buf[idx * NK + 1] = kv.g;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int w = tid + it * NEAR_THREADS;
+            if (w < nn * NL) {
+                const int j = w / NL, a = w % NL;
+                for (int ii = 0; ii < ci; ++ii) {
+                    const double* pxv = &px[i0 + ii][a * NV];
+                    const double2 ks = buf[(ii * nn + j) * NK];
+                    acc[it][0].x = fma(pxv[0], ks.x, acc[it][0].x);
+                    acc[it][0].y = fma(pxv[0], ks.y, acc[it][0].y);
+                    if (HARD) {
+                        const double2 kg = buf[(ii * nn + j) * NK + 1];
+#pragma unroll
+                        for (int v = 1; v < NV; ++v) {
+                            acc[it][v].x = fma(pxv[v], kg.x, acc[it][v].x);
+                            acc[it][v].y = fma(pxv[v], kg.y, acc[it][v].y);
+                        }
+                    }
+                }
             }
         }
-#pragma unroll
-        for (int a = 0; a < NL; ++a) tp[(grp * nn + j) * NL + a] = acc[a];
+        __syncthreads();
     }
-    __syncthreads();
-    for (int idx = tid; idx < nn * NL; idx += NEAR_THREADS) {
-        double2 s = make_double2(0, 0);
-        for (int g2 = 0; g2 < G; ++g2) s = cadd(s, tp[g2 * nn * NL + idx]);
-        tp[idx] = s;
+    // T[j][a][v] into LDS
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int w = tid + it * NEAR_THREADS;
+        if (w < nn * NL)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) buf[w * NV + v] = acc[it][v];
     }
     __syncthreads();
     if (tid < NL * NL) {
         const int a = tid / NL, b = tid % NL;
-        double2 s = make_double2(0, 0);
-        for (int jj = 0; jj < nn; ++jj) {
-            const double2 t = tp[jj * NL + a];
-            s.x = fma(t.x, py[jj][b], s.x);
-            s.y = fma(t.y, py[jj][b], s.y);
-        }
-        A.stage[(int64_t(k) - A.slot0) * NL * NL + tid] = s;
+        double2 sum = make_double2(0, 0);
+        for (int j = 0; j < nn; ++j)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double2 t = buf[(j * NL + a) * NV + v];
+                const double y = py[j][b * NV + v];
+                sum.x = fma(t.x, y, sum.x);
+                sum.y = fma(t.y, y, sum.y);
+            }
+        A.stage[(int64_t(k) - A.slot0) * NL * NL + tid] = sum;
     }
 }
 
 // --------------------------------------------------------------------------
-// Near field: touching element pairs (Duffy-type rules on [0,1]^4)
+// Near field: touching element pairs (Duffy-type rules on [0,1]^4), points in
+// batches staged through LDS; output (a,b) accumulated by SPLIT threads each.
 // --------------------------------------------------------------------------
-template <int P>
-__global__ __launch_bounds__(NEAR_THREADS) void near_singular_soft(NearArgs A) {
+template <int P, bool HARD>
+__global__ __launch_bounds__(NEAR_THREADS) void near_singular(NearArgs A) {
     constexpr int NL = (P + 1) * (P + 1);
+    constexpr int NV = HARD ? 4 : 1;
+    constexpr int BATCH = HARD ? 64 : NEAR_THREADS;
     constexpr int SPLIT = NEAR_THREADS / (NL * NL) > 0 ? NEAR_THREADS / (NL * NL) : 1;
-    __shared__ double2 kq[NEAR_THREADS];
-    __shared__ double px[NEAR_THREADS][NL];
-    __shared__ double py[NEAR_THREADS][NL];
+    __shared__ KVal kq[BATCH];
+    __shared__ double px[BATCH][NL * NV];
+    __shared__ double py[BATCH][NL * NV];
     __shared__ double2 red[NEAR_THREADS];
 
     const int64_t item = blockIdx.x;
@@ -294,49 +379,44 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_singular_soft(NearArgs A) {
     const int out = tid % (NL * NL), part = tid / (NL * NL);
     const int oa = out / NL, ob = out % NL;
     double2 acc = make_double2(0, 0);
-    for (int base = 0; base < Q; base += NEAR_THREADS) {
-        const int qi = base + tid;
-        if (qi < Q) {
-            const double* r = rule + int64_t(qi) * 5;
-            double s, t, u, v;
-            d4_apply(te, r[0], r[1], s, t);
-            d4_apply(tf, r[2], r[3], u, v);
-            GeoPt gx, gy;
-            eval_geo(Re.bez, Re.pu, Re.pv, s, t, gx);
-            eval_geo(Rf.bez, Rf.pu, Rf.pv, u, v, gy);
-            double nx[3], ny[3];
-            cross3(gx.fs, gx.ft, nx);
-            cross3(gy.fs, gy.ft, ny);
-            const double ax = sqrt(nx[0] * nx[0] + nx[1] * nx[1] + nx[2] * nx[2]);
-            const double ay = sqrt(ny[0] * ny[0] + ny[1] * ny[1] + ny[2] * ny[2]);
-            kq[tid] = cscale(kernel_soft(gx.x, nx, ax, gy.x, ay, A.kappa, A.eta), r[4]);
-            double bu[P + 1], bv[P + 1];
-            eval_basis1<P>(Ce_u, s, bu, nullptr);
-            eval_basis1<P>(Ce_v, t, bv, nullptr);
+    for (int base = 0; base < Q; base += BATCH) {
+        if (tid < BATCH) {
+            const int qi = base + tid;
+            if (qi < Q) {
+                const double* r = rule + int64_t(qi) * 5;
+                double s, t, u, v;
+                d4_apply(te, r[0], r[1], s, t);
+                d4_apply(tf, r[2], r[3], u, v);
+                double gxv[7], gyv[7];
+                point_data<P, HARD>(Re, Ce_u, Ce_v, s, t, 1.0, gxv, px[tid]);
+                point_data<P, HARD>(Rf, Cf_u, Cf_v, u, v, 1.0, gyv, py[tid]);
+                KVal kv = kernel_pair<HARD>(gxv, gxv + 3, gxv[6], gyv, gyv + 3, gyv[6], A.kappa, A.eta);
+                kv.s = cscale(kv.s, r[4]);
+                kv.g = cscale(kv.g, r[4]);
+                kq[tid] = kv;
+            } else {
+                kq[tid].s = make_double2(0, 0);
+                kq[tid].g = make_double2(0, 0);
 #pragma unroll
-            for (int av = 0; av <= P; ++av)
-#pragma unroll
-                for (int au = 0; au <= P; ++au) px[tid][av * (P + 1) + au] = bv[av] * bu[au];
-            eval_basis1<P>(Cf_u, u, bu, nullptr);
-            eval_basis1<P>(Cf_v, v, bv, nullptr);
-#pragma unroll
-            for (int av = 0; av <= P; ++av)
-#pragma unroll
-                for (int au = 0; au <= P; ++au) py[tid][av * (P + 1) + au] = bv[av] * bu[au];
-        } else {
-            kq[tid] = make_double2(0, 0);
-#pragma unroll
-            for (int a = 0; a < NL; ++a) {
-                px[tid][a] = 0;
-                py[tid][a] = 0;
+                for (int a = 0; a < NL * NV; ++a) {
+                    px[tid][a] = 0;
+                    py[tid][a] = 0;
+                }
             }
         }
         __syncthreads();
         if (part < SPLIT) {
-            for (int q = part; q < NEAR_THREADS; q += SPLIT) {
-                const double w = px[q][oa] * py[q][ob];
-                acc.x = fma(w, kq[q].x, acc.x);
-                acc.y = fma(w, kq[q].y, acc.y);
+            for (int q = part; q < BATCH; q += SPLIT) {
+                const double w = px[q][oa * NV] * py[q][ob * NV];
+                acc.x = fma(w, kq[q].s.x, acc.x);
+                acc.y = fma(w, kq[q].s.y, acc.y);
+                if (HARD) {
+                    double c = 0;
+#pragma unroll
+                    for (int v = 1; v < NV; ++v) c = fma(px[q][oa * NV + v], py[q][ob * NV + v], c);
+                    acc.x = fma(c, kq[q].g.x, acc.x);
+                    acc.y = fma(c, kq[q].g.y, acc.y);
+                }
             }
         }
         __syncthreads();
@@ -344,8 +424,8 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_singular_soft(NearArgs A) {
     red[tid] = acc;
     __syncthreads();
     if (tid < NL * NL) {
-        double2 s = make_double2(0, 0);
-        for (int g2 = 0; g2 < SPLIT; ++g2) s = cadd(s, red[g2 * NL * NL + tid]);
+        double2 sum = make_double2(0, 0);
+        for (int g2 = 0; g2 < SPLIT; ++g2) sum = cadd(sum, red[g2 * NL * NL + tid]);
         if (cls == 4) {
             // + 1/2 mass matrix on the identical pair: int phi_a phi_b a
             const int n = A.mass_order;
@@ -358,17 +438,16 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_singular_soft(NearArgs A) {
                 eval_geo(Re.bez, Re.pu, Re.pv, ss, tt, G);
                 double nt[3];
                 cross3(G.fs, G.ft, nt);
-                double bu[P + 1], bv[P + 1], cu[P + 1], cv[P + 1];
+                double bu[P + 1], bv[P + 1];
                 eval_basis1<P>(Ce_u, ss, bu, nullptr);
                 eval_basis1<P>(Ce_v, tt, bv, nullptr);
-                (void)cu; (void)cv;
                 const double pa = bv[oa / (P + 1)] * bu[oa % (P + 1)];
                 const double pb = bv[ob / (P + 1)] * bu[ob % (P + 1)];
                 m += gw[i % n] * gw[i / n] * sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]) * pa * pb;
             }
-            s.x += 0.5 * m;
+            sum.x += 0.5 * m;
         }
-        A.stage[(int64_t(k) - A.slot0) * NL * NL + tid] = s;
+        A.stage[(int64_t(k) - A.slot0) * NL * NL + tid] = sum;
     }
 }
 
@@ -492,6 +571,30 @@ __global__ void coupling_soft(const double* nodes, const int* pair_tgt, const in
         const double* X = T + a * 16;
         const double* Y = S + b * 16;
         out[idx] = kernel_soft(X, X + 3, X[6], Y, Y[6], kappa, eta);
+    }
+}
+
+// sound-hard: raw kernels at node pairs, {G, H}[pair][b*nq + a]; the node-wise
+// factors (measures, normals, tangents) are applied around the coupling product
+__global__ void coupling_hard(const double* nodes, const int* pair_tgt, const int* pair_src, int64_t npairs,
+                              int nq, double kappa, double2* coup) {
+    const int64_t pr = blockIdx.x;
+    if (pr >= npairs) return;
+    const double* T = nodes + int64_t(pair_tgt[pr]) * nq * 16;
+    const double* S = nodes + int64_t(pair_src[pr]) * nq * 16;
+    double2* out = coup + pr * nq * nq * 2;
+    for (int idx = threadIdx.x; idx < nq * nq; idx += blockDim.x) {
+        const int b = idx / nq, a = idx % nq;
+        const double* X = T + a * 16;
+        const double* Y = S + b * 16;
+        const double d0 = X[0] - Y[0], d1 = X[1] - Y[1], d2 = X[2] - Y[2];
+        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const double ir = 1.0 / r, kr = kappa * r;
+        double sn, cs;
+        sincos(kr, &sn, &cs);
+        const double c4 = 0.07957747154594767 * ir;
+        out[2 * idx] = make_double2(c4 * cs, c4 * sn);                                        // G
+        out[2 * idx + 1] = make_double2(c4 * ir * ir * (-cs - sn * kr), c4 * ir * ir * (cs * kr - sn));  // H
     }
 }
 
@@ -679,8 +782,8 @@ __global__ __launch_bounds__(TREE_THREADS) void back_project_leaf(const double2*
 }
 
 // y[i] (+)= sum over the leaves whose window contains i (fixed order)
-__global__ void leaf_gather(const double2* __restrict__ leafbuf, int d, int p, int L, int k, int npatch,
-                            double2* __restrict__ y, int accumulate) {
+__global__ void leaf_gather(const double2* __restrict__ leafbuf, int d, int p, int L, int k, int npatch, int kinds,
+                            double2* __restrict__ y) {
     const int64_t n2 = int64_t(npatch) * k * k;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n2) return;
@@ -698,15 +801,47 @@ __global__ void leaf_gather(const double2* __restrict__ leafbuf, int d, int p, i
             const int lu = iu - cx * s;
             if (lu < 0 || lu >= w) continue;
             const int64_t leaf = (int64_t(patch) << (2 * L)) + int64_t(cy) * n + cx;
-            acc = cadd(acc, leafbuf[leaf * w * w + lv * w + lu]);
+            for (int kd = 0; kd < kinds; ++kd)
+                acc = cadd(acc, leafbuf[(int64_t(kd) * npatch * n * n + leaf) * w * w + lv * w + lu]);
         }
     }
-    y[i] = accumulate ? cadd(y[i], acc) : acc;
+    y[i] = acc;
+}
+
+// storage types of the coupling tiles: fp64, fp32 or bf16 complex; products and
+// accumulation run in fp64 on the single-column path
+struct bf16x2 {
+    unsigned short re, im;
+};
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ double2 to_d2(bf16x2 v) {
+    return make_double2(__uint_as_float(unsigned(v.re) << 16), __uint_as_float(unsigned(v.im) << 16));
+}
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+// rounded copy of the fp64 couplings: prec 1 -> fp32 (RNE), prec 2 -> bf16 (RNE of the fp32 value)
+__global__ void round_coupling(const double2* __restrict__ in, int64_t n, int prec, void* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 f = make_float2(float(in[i].x), float(in[i].y));
+    if (prec == 1) {
+        static_cast<float2*>(out)[i] = f;
+    } else {
+        bf16x2 b;
+        b.re = f32_to_bf16_rne(f.x);
+        b.im = f32_to_bf16_rne(f.y);
+        static_cast<bf16x2*>(out)[i] = b;
+    }
 }
 
 // coupling: one workgroup per chunk of source clusters of one target
-template <int NT>
-__global__ __launch_bounds__(NT) void m2l_chunks(const double2* __restrict__ coup,
+template <int NT, class CT>
+__global__ __launch_bounds__(NT) void m2l_chunks(const CT* __restrict__ coup,
                                                  const double2* __restrict__ xh,
                                                  const int* __restrict__ far_src_g,
                                                  const int64_t* __restrict__ chunk_pair,
@@ -725,23 +860,115 @@ __global__ __launch_bounds__(NT) void m2l_chunks(const double2* __restrict__ cou
         if (a < nq) xs[a] = xh[int64_t(far_src_g[pr]) * nq + a];
         __syncthreads();
         if (a < nq) {
-            const double2* K = coup + pr * nq * nq + a;
+            const CT* K = coup + pr * nq * nq + a;
 #pragma unroll 7
-            for (int b = 0; b < nq; ++b) acc = cfma(K[int64_t(b) * nq], xs[b], acc);
+            for (int b = 0; b < nq; ++b) acc = cfma(to_d2(K[int64_t(b) * nq]), xs[b], acc);
         }
     }
     if (a < nq) part[ch * nq + a] = acc;
 }
 
-// yh[c][a] = sum over the target's chunks (fixed order); zero if none
-__global__ void m2l_reduce(const double2* part, const int* tgt_chunk_ptr, int64_t nclusters, int nq,
-                           double2* yh) {
+// sound-hard coupling: per source the 7 node-scaled moment vectors
+//   n~_c xp (c = 0..2), (y.n~) xp, v_c = F_v,c xu - F_u,c xv
+// are formed in LDS; H acts on {(y.n~) xp, n~_c xp}, G on {n~_c xp, v_c}:
+// 10 partial vectors per chunk.
+template <int NT, class CT>
+__global__ __launch_bounds__(NT) void m2l_hard_chunks(const CT* __restrict__ coup,
+                                                      const double2* __restrict__ xh, int64_t kind_stride,
+                                                      const double* __restrict__ nodes,
+                                                      const int* __restrict__ far_src_g,
+                                                      const int64_t* __restrict__ chunk_pair,
+                                                      const int* __restrict__ chunk_len, int64_t nchunk, int nq,
+                                                      double2* __restrict__ part) {
+    __shared__ double2 sv[7][NT];
+    const int64_t ch = blockIdx.x;
+    if (ch >= nchunk) return;
+    const int a = threadIdx.x;
+    const int64_t p0 = chunk_pair[ch];
+    const int len = chunk_len[ch];
+    double2 rh[4], rg[6];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) rh[v] = make_double2(0, 0);
+#pragma unroll
+    for (int v = 0; v < 6; ++v) rg[v] = make_double2(0, 0);
+    for (int i = 0; i < len; ++i) {
+        const int64_t pr = p0 + i;
+        __syncthreads();
+        if (a < nq) {
+            const int64_t src = far_src_g[pr];
+            const double* Y = nodes + (src * nq + a) * 16;
+            const double2 xp = xh[src * nq + a], xu = xh[kind_stride + src * nq + a],
+                          xv = xh[2 * kind_stride + src * nq + a];
+            const double yn = Y[0] * Y[3] + Y[1] * Y[4] + Y[2] * Y[5];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                sv[c][a] = cscale(xp, Y[3 + c]);
+                sv[4 + c][a] = make_double2(Y[11 + c] * xu.x - Y[8 + c] * xv.x, Y[11 + c] * xu.y - Y[8 + c] * xv.y);
+            }
+            sv[3][a] = cscale(xp, yn);
+        }
+        __syncthreads();
+        if (a < nq) {
+            const CT* K = coup + pr * nq * nq * 2 + 2 * a;
+            for (int b = 0; b < nq; ++b) {
+                const double2 G = to_d2(K[int64_t(b) * nq * 2]), H = to_d2(K[int64_t(b) * nq * 2 + 1]);
+                rh[0] = cfma(H, sv[3][b], rh[0]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    rh[1 + c] = cfma(H, sv[c][b], rh[1 + c]);
+                    rg[c] = cfma(G, sv[c][b], rg[c]);
+                    rg[3 + c] = cfma(G, sv[4 + c][b], rg[3 + c]);
+                }
+            }
+        }
+    }
+    if (a < nq) {
+        double2* o = part + ch * 10 * nq + a;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[v * nq] = rh[v];
+#pragma unroll
+        for (int v = 0; v < 6; ++v) o[(4 + v) * nq] = rg[v];
+    }
+}
+
+// target-side factors of the sound-hard coupling:
+//   y_p = -a R0 + a sum_c x_c R_c + i eta kappa^2 sum_c n~_c S_c
+//   y_u = -i eta sum_c F_v,c T_c,   y_v = +i eta sum_c F_u,c T_c
+// from raw[cluster][10][nq] = (R0, R_0..2, S_0..2, T_0..2)
+__global__ void m2l_finalize_hard(const double2* raw, const double* nodes, int64_t nclusters, int nq, double kappa,
+                                  double eta, int64_t kind_stride, double2* yh) {
     const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gid >= nclusters * nq) return;
     const int64_t c = gid / nq;
     const int a = int(gid % nq);
+    const double* X = nodes + gid * 16;
+    const double2* r = raw + c * 10 * nq + a;
+    double2 yp = cscale(r[0], -X[6]);
+    double2 su = make_double2(0, 0), sv = make_double2(0, 0), sn = make_double2(0, 0);
+    for (int cc = 0; cc < 3; ++cc) {
+        yp = cadd(yp, cscale(r[(1 + cc) * nq], X[6] * X[cc]));
+        sn = cadd(sn, cscale(r[(4 + cc) * nq], X[3 + cc]));
+        su = cadd(su, cscale(r[(7 + cc) * nq], X[11 + cc]));
+        sv = cadd(sv, cscale(r[(7 + cc) * nq], X[8 + cc]));
+    }
+    const double k2 = eta * kappa * kappa;
+    yp = cadd(yp, make_double2(-k2 * sn.y, k2 * sn.x));               // + i eta kappa^2 sn
+    yh[gid] = yp;
+    yh[kind_stride + gid] = make_double2(eta * su.y, -eta * su.x);    // -i eta su
+    yh[2 * kind_stride + gid] = make_double2(-eta * sv.y, eta * sv.x); // +i eta sv
+}
+
+// yh[c][a] = sum over the target's chunks (fixed order); zero if none
+// (nvec vectors per chunk / cluster, layout [chunk][nvec][nq] -> [cluster][nvec][nq])
+__global__ void m2l_reduce(const double2* part, const int* tgt_chunk_ptr, int64_t nclusters, int nq, int nvec,
+                           double2* yh) {
+    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t per = int64_t(nvec) * nq;
+    if (gid >= nclusters * per) return;
+    const int64_t c = gid / per;
+    const int64_t va = gid % per;
     double2 s = make_double2(0, 0);
-    for (int ch = tgt_chunk_ptr[c]; ch < tgt_chunk_ptr[c + 1]; ++ch) s = cadd(s, part[int64_t(ch) * nq + a]);
+    for (int ch = tgt_chunk_ptr[c]; ch < tgt_chunk_ptr[c + 1]; ++ch) s = cadd(s, part[int64_t(ch) * per + va]);
     yh[gid] = s;
 }
 
@@ -1074,7 +1301,7 @@ igb_status upload_geometry(igb_geom g) {
 // orders of the GPU rules (see near_classify for the regular ones)
 constexpr int NSING_IDENT = 7, NSING_EDGE = 8, NSING_VERTEX = 9, MASS_ORDER = 6;
 
-template <int P>
+template <int P, bool HARD>
 static igb_status near_launch(igb_op op, hipStream_t s) {
     igb_geom g = op->geom;
     constexpr int NL = (P + 1) * (P + 1);
@@ -1148,13 +1375,13 @@ static igb_status near_launch(igb_op op, hipStream_t s) {
         if (!reg.empty()) {
             A.list = d_list.as<int>();
             A.nlist = int64_t(reg.size());
-            hipLaunchKernelGGL(near_regular_soft<P>, dim3(unsigned(reg.size())), dim3(NEAR_THREADS), 0, s, A);
+            hipLaunchKernelGGL((near_regular<P, HARD>), dim3(unsigned(reg.size())), dim3(NEAR_THREADS), 0, s, A);
             IGB_HIP(hipGetLastError());
         }
         if (!sing.empty()) {
             A.list = d_list.as<int>() + reg.size();
             A.nlist = int64_t(sing.size());
-            hipLaunchKernelGGL(near_singular_soft<P>, dim3(unsigned(sing.size())), dim3(NEAR_THREADS), 0, s, A);
+            hipLaunchKernelGGL((near_singular<P, HARD>), dim3(unsigned(sing.size())), dim3(NEAR_THREADS), 0, s, A);
             IGB_HIP(hipGetLastError());
         }
         // rows touched by the chunk's target elements
@@ -1201,19 +1428,16 @@ igb_status assemble_near_device(igb_op op, hipStream_t s) {
     igb_geom g = op->geom;
     size_t* acct = &op->dev_bytes;
     igb_status st;
-    if (op->bc == IGB_HARD) {
-        set_error("assemble_nearfield: the sound-hard operator is not implemented in this build");
-        return IGB_ERR_UNSUPPORTED;
-    }
     if ((st = upload(op->d_s2_to_s0, g->s2_to_s0.data(), g->s2_to_s0.size(), acct))) return st;
     if (g->n0 > 0) {
         if ((st = upload(op->d_s0_ptr, g->s0_ptr.data(), g->s0_ptr.size(), acct))) return st;
         if ((st = upload(op->d_s0_reps, g->s0_reps.data(), g->s0_reps.size(), acct))) return st;
     }
     auto t0 = std::chrono::steady_clock::now();
+    const bool hard = op->bc == IGB_HARD;
     switch (g->p) {
-        case 1: st = near_launch<1>(op, s); break;
-        case 2: st = near_launch<2>(op, s); break;
+        case 1: st = hard ? near_launch<1, true>(op, s) : near_launch<1, false>(op, s); break;
+        case 2: st = hard ? near_launch<2, true>(op, s) : near_launch<2, false>(op, s); break;
         default:
             set_error("assemble_nearfield: spline degree p = %d not built (p = 1, 2)", g->p);
             return IGB_ERR_UNSUPPORTED;
@@ -1311,12 +1535,26 @@ igb_status assemble_far_device(igb_op op, hipStream_t s) {
     DevBuf d_ptg;
     if ((st = upload(d_ptg, ptg.data(), ptg.size(), nullptr))) return st;
     if ((st = upload(op->d_far_src, psg.data(), psg.size(), acct))) return st;
-    if ((st = alloc(op->d_coupling, size_t(op->nfar) * nq * nq * sizeof(double2), acct))) return st;
+    const bool hard = op->bc == IGB_HARD;
+    if ((st = alloc(op->d_coupling, size_t(op->nfar) * nq * nq * sizeof(double2) * (hard ? 2 : 1), acct))) return st;
     if (op->nfar > 0) {
-        hipLaunchKernelGGL(coupling_soft, dim3(unsigned(op->nfar)), dim3(256), 0, s, op->d_nodes.as<double>(),
-                           d_ptg.as<int>(), op->d_far_src.as<int>(), op->nfar, nq, op->kappa, op->eta,
-                           op->d_coupling.as<double2>());
+        if (hard)
+            hipLaunchKernelGGL(coupling_hard, dim3(unsigned(op->nfar)), dim3(256), 0, s, op->d_nodes.as<double>(),
+                               d_ptg.as<int>(), op->d_far_src.as<int>(), op->nfar, nq, op->kappa,
+                               op->d_coupling.as<double2>());
+        else
+            hipLaunchKernelGGL(coupling_soft, dim3(unsigned(op->nfar)), dim3(256), 0, s, op->d_nodes.as<double>(),
+                               d_ptg.as<int>(), op->d_far_src.as<int>(), op->nfar, nq, op->kappa, op->eta,
+                               op->d_coupling.as<double2>());
         IGB_HIP(hipGetLastError());
+        if (op->prm.precision != IGB_FP64) {
+            const int64_t ne = op->nfar * nq * nq * (hard ? 2 : 1);
+            const size_t esz = op->prm.precision == IGB_MIX_FP32 ? sizeof(float2) : sizeof(bf16x2);
+            if ((st = alloc(op->d_coupling_lo, size_t(ne) * esz, acct))) return st;
+            hipLaunchKernelGGL(round_coupling, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, s,
+                               op->d_coupling.as<double2>(), ne, op->prm.precision, op->d_coupling_lo.ptr);
+            IGB_HIP(hipGetLastError());
+        }
     }
     if ((st = upload(op->d_chunk_pair, op->chunk_pair.data(), op->chunk_pair.size(), acct))) return st;
     if ((st = upload(op->d_chunk_len, op->chunk_len.data(), op->chunk_len.size(), acct))) return st;
@@ -1333,16 +1571,19 @@ igb_status alloc_work(igb_op op, int nrhs) {
     size_t* acct = &op->dev_bytes;
     igb_status st;
     const int nq = op->nq;
+    const bool hard = op->bc == IGB_HARD;
+    const int kinds = hard ? 3 : 1, nvec = hard ? 10 : 1;
     if (!op->d_xhat.ptr) {
-        if ((st = alloc(op->d_xhat, size_t(op->nclusters) * nq * sizeof(double2), acct))) return st;
-        if ((st = alloc(op->d_yhat, size_t(op->nclusters) * nq * sizeof(double2), acct))) return st;
-        if ((st = alloc(op->d_part, std::max<size_t>(1, op->chunk_len.size()) * nq * sizeof(double2), acct)))
+        if ((st = alloc(op->d_xhat, size_t(kinds) * op->nclusters * nq * sizeof(double2), acct))) return st;
+        if ((st = alloc(op->d_yhat, size_t(kinds) * op->nclusters * nq * sizeof(double2), acct))) return st;
+        if (hard && (st = alloc(op->d_yraw, size_t(nvec) * op->nclusters * nq * sizeof(double2), acct))) return st;
+        if ((st = alloc(op->d_part, std::max<size_t>(1, op->chunk_len.size()) * nvec * nq * sizeof(double2), acct)))
             return st;
         if ((st = alloc(op->d_yfar, size_t(op->geom->n2) * sizeof(double2), acct))) return st;
         if ((st = alloc(op->d_x2, size_t(op->geom->n2) * sizeof(double2), acct))) return st;
         const int64_t w = (int64_t(1) << op->d) + op->geom->p;
-        if ((st = alloc(op->d_leafbuf, size_t(clusters_on_level(op->geom->npatch, op->L)) * w * w * sizeof(double2),
-                        acct)))
+        if ((st = alloc(op->d_leafbuf,
+                        size_t(kinds) * clusters_on_level(op->geom->npatch, op->L) * w * w * sizeof(double2), acct)))
             return st;
         // cluster offsets are needed on the device by m2m / l2l
         if ((st = upload(op->d_cluoff, op->clu_off.data(), op->clu_off.size(), acct))) return st;
@@ -1362,7 +1603,38 @@ igb_status timer_mark(igb_op op, int slot, hipStream_t s) {
     return IGB_OK;
 }
 
+template <int NT, class CT>
+static void launch_m2l_t(igb_op op, const CT* coup, double2* xh, int64_t ks, hipStream_t s) {
+    const int64_t nchunk = int64_t(op->chunk_len.size());
+    if (op->bc == IGB_HARD)
+        hipLaunchKernelGGL((m2l_hard_chunks<NT, CT>), dim3(unsigned(nchunk)), dim3(NT), 0, s, coup, xh, ks,
+                           op->d_nodes.as<double>(), op->d_far_src.as<int>(), op->d_chunk_pair.as<int64_t>(),
+                           op->d_chunk_len.as<int>(), nchunk, op->nq, op->d_part.as<double2>());
+    else
+        hipLaunchKernelGGL((m2l_chunks<NT, CT>), dim3(unsigned(nchunk)), dim3(NT), 0, s, coup, xh,
+                           op->d_far_src.as<int>(), op->d_chunk_pair.as<int64_t>(), op->d_chunk_len.as<int>(),
+                           nchunk, op->nq, op->d_part.as<double2>());
+}
+
+template <int NT>
+static void launch_m2l_nt(igb_op op, bool low, double2* xh, int64_t ks, hipStream_t s) {
+    if (!low)
+        launch_m2l_t<NT>(op, op->d_coupling.as<double2>(), xh, ks, s);
+    else if (op->prm.precision == IGB_MIX_FP32)
+        launch_m2l_t<NT>(op, op->d_coupling_lo.as<float2>(), xh, ks, s);
+    else
+        launch_m2l_t<NT>(op, op->d_coupling_lo.as<bf16x2>(), xh, ks, s);
+}
+
+static igb_status launch_m2l(igb_op op, double2* xh, int64_t ks, bool low, hipStream_t s) {
+    if (op->nq <= 64) launch_m2l_nt<64>(op, low, xh, ks, s);
+    else launch_m2l_nt<128>(op, low, xh, ks, s);
+    IGB_HIP(hipGetLastError());
+    return IGB_OK;
+}
+
 igb_status matvec_device(igb_op op, const double* x, double* y, int nrhs, int parts, hipStream_t s) {
+    const bool low = (parts & IGB_MV_LOWPREC) != 0;
     if (nrhs != 1) {
         set_error("h2_matvec: this build applies one column per call");
         return IGB_ERR_UNSUPPORTED;
@@ -1385,47 +1657,50 @@ igb_status matvec_device(igb_op op, const double* x, double* y, int nrhs, int pa
                                op->d_s2_to_s0.as<int>(), X, op->d_x2.as<double2>(), g->n2);
             x2 = op->d_x2.as<double2>();
         }
+        const int kinds = hard ? 3 : 1;
+        const int64_t ks = op->nclusters * nq;  // stride between moment kinds
+        const int du[3] = {0, 1, 0}, dv[3] = {0, 0, 1};
         const int64_t nleaf = clusters_on_level(g->npatch, L);
         const int64_t stride_kind = int64_t(1 << L) * (q + 1) * ((1 << op->d) + g->p);
         if ((st = timer_mark(op, 2, s))) return st;
-        hipLaunchKernelGGL(leaf_moments, dim3(unsigned((nleaf * nq + 255) / 256)), dim3(256), 0, s, x2,
-                           op->d_m1.as<double>(), q, op->d, g->p, L, g->k, op->clu_off[L], nleaf, xh, 0, 0,
-                           stride_kind);
-        for (int l = L - 1; l >= 0; --l) {
-            const int64_t nc = clusters_on_level(g->npatch, l);
-            hipLaunchKernelGGL(m2m_wg, dim3(unsigned(nc)), dim3(TREE_THREADS), 0, s, op->d_T.as<double>(), q, l,
-                               op->clu_off[l], op->clu_off[l + 1], xh);
+        for (int kd = 0; kd < kinds; ++kd) {
+            hipLaunchKernelGGL(leaf_moments, dim3(unsigned((nleaf * nq + 255) / 256)), dim3(256), 0, s, x2,
+                               op->d_m1.as<double>(), q, op->d, g->p, L, g->k, op->clu_off[L], nleaf, xh + kd * ks,
+                               du[kd], dv[kd], stride_kind);
+            for (int l = L - 1; l >= 0; --l) {
+                const int64_t nc = clusters_on_level(g->npatch, l);
+                hipLaunchKernelGGL(m2m_wg, dim3(unsigned(nc)), dim3(TREE_THREADS), 0, s, op->d_T.as<double>(), q, l,
+                                   op->clu_off[l], op->clu_off[l + 1], xh + kd * ks);
+            }
         }
         if ((st = timer_mark(op, 2, s))) return st;
         const int64_t nchunk = int64_t(op->chunk_len.size());
         if ((st = timer_mark(op, 0, s))) return st;
-        if (nq <= 64) {
-            hipLaunchKernelGGL(m2l_chunks<64>, dim3(unsigned(nchunk)), dim3(64), 0, s,
-                               op->d_coupling.as<double2>(), xh, op->d_far_src.as<int>(),
-                               op->d_chunk_pair.as<int64_t>(), op->d_chunk_len.as<int>(), nchunk, nq,
-                               op->d_part.as<double2>());
-        } else {
-            hipLaunchKernelGGL(m2l_chunks<128>, dim3(unsigned(nchunk)), dim3(128), 0, s,
-                               op->d_coupling.as<double2>(), xh, op->d_far_src.as<int>(),
-                               op->d_chunk_pair.as<int64_t>(), op->d_chunk_len.as<int>(), nchunk, nq,
-                               op->d_part.as<double2>());
-        }
+        if ((st = launch_m2l(op, xh, ks, low && op->prm.precision != IGB_FP64, s))) return st;
         if ((st = timer_mark(op, 0, s))) return st;
         if ((st = timer_mark(op, 3, s))) return st;
-        hipLaunchKernelGGL(m2l_reduce, dim3(unsigned((op->nclusters * nq + 255) / 256)), dim3(256), 0, s,
-                           op->d_part.as<double2>(), op->d_tgt_chunk_ptr.as<int>(), op->nclusters, nq, yh);
-        for (int l = 0; l < L; ++l) {
-            const int64_t nc = clusters_on_level(g->npatch, l);
-            hipLaunchKernelGGL(l2l_wg, dim3(unsigned(nc)), dim3(TREE_THREADS), 0, s, op->d_T.as<double>(), q, l,
-                               op->clu_off[l], op->clu_off[l + 1], yh);
-        }
+        const int nvec = hard ? 10 : 1;
+        double2* red_out = hard ? op->d_yraw.as<double2>() : yh;
+        hipLaunchKernelGGL(m2l_reduce, dim3(unsigned((op->nclusters * nq * nvec + 255) / 256)), dim3(256), 0, s,
+                           op->d_part.as<double2>(), op->d_tgt_chunk_ptr.as<int>(), op->nclusters, nq, nvec, red_out);
+        if (hard)
+            hipLaunchKernelGGL(m2l_finalize_hard, dim3(unsigned((op->nclusters * nq + 255) / 256)), dim3(256), 0, s,
+                               op->d_yraw.as<double2>(), op->d_nodes.as<double>(), op->nclusters, nq, op->kappa,
+                               op->eta, ks, yh);
         const int w = (1 << op->d) + g->p;
-        hipLaunchKernelGGL(back_project_leaf, dim3(unsigned(nleaf)), dim3(TREE_THREADS), 0, s, yh,
-                           op->d_m1.as<double>(), q, w, L, op->clu_off[L], 0, 0, stride_kind,
-                           op->d_leafbuf.as<double2>());
+        for (int kd = 0; kd < kinds; ++kd) {
+            for (int l = 0; l < L; ++l) {
+                const int64_t nc = clusters_on_level(g->npatch, l);
+                hipLaunchKernelGGL(l2l_wg, dim3(unsigned(nc)), dim3(TREE_THREADS), 0, s, op->d_T.as<double>(), q, l,
+                                   op->clu_off[l], op->clu_off[l + 1], yh + kd * ks);
+            }
+            hipLaunchKernelGGL(back_project_leaf, dim3(unsigned(nleaf)), dim3(TREE_THREADS), 0, s, yh + kd * ks,
+                               op->d_m1.as<double>(), q, w, L, op->clu_off[L], du[kd], dv[kd], stride_kind,
+                               op->d_leafbuf.as<double2>() + kd * nleaf * w * w);
+        }
         hipLaunchKernelGGL(leaf_gather, dim3(unsigned((g->n2 + 255) / 256)), dim3(256), 0, s,
-                           op->d_leafbuf.as<double2>(), op->d, g->p, L, g->k, g->npatch,
-                           op->d_yfar.as<double2>(), 0);
+                           op->d_leafbuf.as<double2>(), op->d, g->p, L, g->k, g->npatch, kinds,
+                           op->d_yfar.as<double2>());
         if ((st = timer_mark(op, 3, s))) return st;
     }
     const int64_t N = op->N;

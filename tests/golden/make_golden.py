@@ -14,6 +14,8 @@ Cases
                       far field at 64 Fibonacci directions and the Mie values.
   sphere_m5_p2_k8_rows  the m = 5, p = 2, kappa = 8 sphere workload: sampled
                       rows of the dense O1 matrix applied to the seeded vector.
+  sphere_m3_p2_k2_q4_hard / sphere_m2_p2_k1_hard  the same two small checks for
+                      the sound-hard operator (regularised W) on S^0.
 """
 from __future__ import annotations
 
@@ -65,7 +67,32 @@ def case_sphere_m5_p2_k8_rows(nrows=6):
     return dict(rows=rows.astype(np.int64), y=R @ x, rownorm1=np.abs(R).sum(1), x=x)
 
 
+def case_sphere_m3_p2_k2_q4_hard():
+    bem = G.DenseBEM(I.sphere_patches(), p=2, m=3, kappa=2.0, bc="hard")
+    H = h2.H2Oracle(bem, q=4, eta=1.6, leaf_depth=1)
+    x = I.random_complex(X_SEED, bem.n)
+    A = H.to_solution_space(H.near_matrix())
+    nz = np.argwhere(A != 0)
+    pick = nz[np.random.default_rng(ROW_SEED).choice(len(nz), 4000, replace=False)]
+    d = np.array([0.3, -0.2, 0.9])
+    return dict(x=x, y_far=H.far_apply(x), y_near=A @ x, ent_ij=pick.astype(np.int32),
+                ent_val=A[pick[:, 0], pick[:, 1]], d=d, rhs=bem.rhs(d), nfar=len(H.far))
+
+
+def case_sphere_m2_p2_k1_hard():
+    bem = G.DenseBEM(I.sphere_patches(), p=2, m=2, kappa=1.0, bc="hard")
+    A = bem.matrix()
+    d = np.array([0.0, 0.0, 1.0])
+    b = bem.rhs(d)
+    t = np.linalg.solve(A, b)
+    obs = I.fibonacci_directions(64)
+    return dict(A=A, d=d, rhs=b, t=t, obs=obs, uinf=bem.farfield(t, obs),
+                mie=mie.farfield(1.0, obs @ d, "hard"), x=I.random_complex(X_SEED, bem.n))
+
+
 CASES = {
+    "sphere_m3_p2_k2_q4_hard": case_sphere_m3_p2_k2_q4_hard,
+    "sphere_m2_p2_k1_hard": case_sphere_m2_p2_k1_hard,
     "sphere_m3_p2_k2_q4": case_sphere_m3_p2_k2_q4,
     "sphere_m2_p1_k1": case_sphere_m2_p1_k1,
     "sphere_m5_p2_k8_rows": case_sphere_m5_p2_k8_rows,

@@ -134,3 +134,18 @@ def test_budget_rejects_before_allocating():
     with pytest.raises(B.IgbError) as e:
         B.Geometry(ctx, I.sphere_patches(), 3, 2)
     assert e.value.status == -3
+
+
+def test_handles_destroyed_in_any_order():
+    """Context, geometry and operator handles are reference counted: destroying
+    the context first, then the geometry, then the operator is valid."""
+    ctx = B.Context(B.IGB_HOST_ONLY)
+    geo = B.Geometry(ctx, I.sphere_patches(), 2, 1)
+    op = B.Operator(ctx, geo, kappa=1.0, q=3, leaf_depth=0)
+    hc, hg, ho = ctx.h, geo.h, op.h
+    ctx.h = geo.h = op.h = None
+    B._lib.igb_ctx_destroy(hc)
+    B._lib.igb_geom_destroy(hg)
+    info = B.IgbOpInfo()
+    assert B._lib.igb_op_get_info(ho, B.C.byref(info)) == 0 and info.n == geo.n2
+    B._lib.igb_op_destroy(ho)
