@@ -204,8 +204,10 @@ igb_status igb_op_kernel_time(igb_op op, const char* name, int64_t* launches, do
 #define IGB_PART_ALL 3
 #define IGB_MV_LOWPREC 4   /* with IGB_MIX_* operators: far field from the rounded copy */
 /* y = A x for nrhs columns (device arrays [nrhs][n] complex).  parts selects the
- * near-field (incl. 1/2 M) and/or far-field (H^2) contributions.  x and y must
- * not overlap.  This build: nrhs = 1 per call.  Stream-ordered. */
+ * near-field (incl. 1/2 M) and/or far-field (H^2) contributions.  The columns
+ * share every pass over the couplings and the near-field matrix; each column is
+ * computed with the same operation order whatever nrhs is, so results do not
+ * depend on the batch.  x and y must not overlap.  Stream-ordered. */
 igb_status h2_matvec(igb_op op, const double* x, double* y, int nrhs, int parts, void* hip_stream);
 
 /* Right-hand sides (Sec. 4.1 load vectors of the D2N / N2D systems) for ndir
@@ -215,7 +217,9 @@ igb_status cfie_rhs(igb_op op, const double* dirs, int ndir, double* b, void* hi
 
 /* Solves the CFIE for ndir incident directions (host dirs [ndir][3]) with
  * restarted GMRES (Sec. 5.1), x0 = 0, writing the coefficients into the device
- * array coeffs [ndir][n].  Operators with IGB_MIX_* precision solve by
+ * array coeffs [ndir][n].  The directions run in lockstep: one block matvec per
+ * Arnoldi step, each column with its own Krylov basis, rotations and stopping
+ * test, so a column's solution does not depend on the other columns.  Operators with IGB_MIX_* precision solve by
  * iterative refinement: x += GMRES(A_rounded, b - A_fp64 x) until the fp64
  * residual reaches tol.  Synchronous.  IGB_WARN_NOT_CONVERGED if a column
  * stops at maxit. */

@@ -226,6 +226,7 @@ class Operator:
         return n.value, ms.value
 
     def h2_matvec(self, x, y, nrhs: int = 1, parts: int = PART_ALL, stream=None):
+        """y = A x for nrhs columns stored [nrhs][n] in x and y."""
         _check("h2_matvec", _lib.h2_matvec(self.h, _dptr(x, nrhs * self.n), _dptr(y, nrhs * self.n),
                                            nrhs, parts, _stream(stream)))
         return y

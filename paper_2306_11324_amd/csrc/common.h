@@ -131,6 +131,7 @@ struct igb_op_s {
     // solver scratch
     igb::DevBuf d_krylov, d_w, d_h, d_b;
     int krylov_cols = 0;
+    int work_cols = 0;   // columns the matvec work buffers are sized for
     double t_assembly_near = 0, t_assembly_far = 0;
     // per-kernel timing: 0 m2l, 1 spmv, 2 upward, 3 downward
     bool profile = false;

@@ -1,7 +1,8 @@
 // Restarted GMRES (Sec. 5.1: GMRES with restart 30 on the CFIE systems) on the
-// device.  Arnoldi with classical Gram-Schmidt applied twice (CGS2); all
-// vectors stay on the device, only the new Hessenberg column (<= restart+1
-// complex numbers) is read back per iteration for the Givens rotations.
+// device, for one or many right-hand sides in lockstep.  Arnoldi with classical
+// Gram-Schmidt applied twice (CGS2); all vectors stay on the device, only the
+// new Hessenberg columns (<= restart+1 complex numbers per right-hand side) are
+// read back per iteration for the Givens rotations.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -16,93 +17,99 @@ namespace {
 
 constexpr int RT = 256;
 
-// h[j] (+)= sum_i conj(V[j][i]) w[i]; one workgroup per basis vector, fixed-order tree
-__global__ __launch_bounds__(RT) void cdots(const double2* V, int64_t n, const double2* w, double2* h,
-                                            int accumulate) {
-    __shared__ double2 red[RT];
-    const int j = blockIdx.x;
-    const double2* v = V + int64_t(j) * n;
-    double2 acc = make_double2(0, 0);
-    for (int64_t i = threadIdx.x; i < n; i += RT) {
-        const double2 a = v[i], b = w[i];
-        acc.x = fma(a.x, b.x, fma(a.y, b.y, acc.x));
-        acc.y = fma(a.x, b.y, fma(-a.y, b.x, acc.y));
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = RT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            red[threadIdx.x].x += red[threadIdx.x + s].x;
-            red[threadIdx.x].y += red[threadIdx.x + s].y;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        if (accumulate) {
-            h[j].x += red[0].x;
-            h[j].y += red[0].y;
-        } else {
-            h[j] = red[0];
-        }
-    }
-}
-
-// w[i] -= sum_j c[j] V[j][i]  (c read from device memory)
-__global__ void cmaxpy(const double2* V, int nvec, int64_t n, const double2* c, double2* w) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double2 acc = w[i];
-    for (int j = 0; j < nvec; ++j) {
-        const double2 a = c[j], v = V[int64_t(j) * n + i];
-        acc.x -= a.x * v.x - a.y * v.y;
-        acc.y -= a.x * v.y + a.y * v.x;
-    }
-    w[i] = acc;
-}
-
-// out[0] = ||w||_2^2 (single workgroup, fixed order)
-__global__ __launch_bounds__(1024) void cnorm2(const double2* w, int64_t n, double* out) {
-    __shared__ double red[1024];
-    double acc = 0;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) acc = fma(w[i].x, w[i].x, fma(w[i].y, w[i].y, acc));
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = 512; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = red[0];
-}
-
-__global__ void cscale_to(const double2* w, int64_t n, double s, double2* v) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) v[i] = make_double2(w[i].x * s, w[i].y * s);
-}
-
-// x[i] += sum_j y[j] V[j][i]
-__global__ void cupdate(const double2* V, int nvec, int64_t n, const double2* y, double2* x) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double2 acc = x[i];
-    for (int j = 0; j < nvec; ++j) {
-        const double2 a = y[j], v = V[int64_t(j) * n + i];
-        acc.x += a.x * v.x - a.y * v.y;
-        acc.y += a.x * v.y + a.y * v.x;
-    }
-    x[i] = acc;
-}
-
-// r = b - r
-__global__ void csub_from(const double2* b, int64_t n, double2* r) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) r[i] = make_double2(b[i].x - r[i].x, b[i].y - r[i].y);
-}
-
 using cplx = std::complex<double>;
 
 }  // namespace
 
 namespace {
+
+// ---- multi-column Arnoldi kernels: vectors [C][n], basis [j][C][n] ----
+// h[jj*C + r] = sum_i conj(V[jj][r][i]) w[r][i]; one workgroup per (jj, r)
+__global__ __launch_bounds__(RT) void cdots_multi(const double2* V, int64_t n, int C, const double2* w, double2* h) {
+    __shared__ double2 red[RT];
+    const int jj = blockIdx.x, r = blockIdx.y;
+    const double2* v = V + (int64_t(jj) * C + r) * n;
+    const double2* x = w + int64_t(r) * n;
+    double2 acc = make_double2(0, 0);
+    for (int64_t i = threadIdx.x; i < n; i += RT) {
+        const double2 a = v[i], b = x[i];
+        acc.x = fma(a.x, b.x, fma(a.y, b.y, acc.x));
+        acc.y = fma(a.x, b.y, fma(-a.y, b.x, acc.y));
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = RT / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            red[threadIdx.x].x += red[threadIdx.x + st].x;
+            red[threadIdx.x].y += red[threadIdx.x + st].y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) h[int64_t(jj) * C + r] = red[0];
+}
+
+// w[r][i] -= sum_jj c[jj*C + r] V[jj][r][i]
+__global__ void cmaxpy_multi(const double2* V, int nvec, int64_t n, int C, const double2* c, double2* w) {
+    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= n * C) return;
+    const int r = int(gid / n);
+    const int64_t i = gid % n;
+    double2 acc = w[gid];
+    for (int j = 0; j < nvec; ++j) {
+        const double2 a = c[int64_t(j) * C + r], v = V[(int64_t(j) * C + r) * n + i];
+        acc.x -= a.x * v.x - a.y * v.y;
+        acc.y -= a.x * v.y + a.y * v.x;
+    }
+    w[gid] = acc;
+}
+
+// x[r][i] += sum_jj y[jj*C + r] V[jj][r][i]
+__global__ void cupdate_multi(const double2* V, int nvec, int64_t n, int C, const double2* y, double2* x) {
+    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= n * C) return;
+    const int r = int(gid / n);
+    const int64_t i = gid % n;
+    double2 acc = x[gid];
+    for (int j = 0; j < nvec; ++j) {
+        const double2 a = y[int64_t(j) * C + r], v = V[(int64_t(j) * C + r) * n + i];
+        acc.x += a.x * v.x - a.y * v.y;
+        acc.y += a.x * v.y + a.y * v.x;
+    }
+    x[gid] = acc;
+}
+
+// out[r] = ||w[r]||^2, one workgroup per column
+__global__ __launch_bounds__(1024) void cnorm2_multi(const double2* w, int64_t n, double* out) {
+    __shared__ double red[1024];
+    const double2* x = w + int64_t(blockIdx.x) * n;
+    double acc = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) acc = fma(x[i].x, x[i].x, fma(x[i].y, x[i].y, acc));
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// v[r][i] = w[r][i] * sc[r]
+__global__ void cscale_multi(const double2* w, int64_t n, int C, const double* sc, double2* v) {
+    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= n * C) return;
+    const double f = sc[gid / n];
+    v[gid] = make_double2(w[gid].x * f, w[gid].y * f);
+}
+
+// r = b - r ; x += d ; zero columns
+__global__ void csub_from_multi(const double2* b, int64_t nc, double2* r) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < nc) r[i] = make_double2(b[i].x - r[i].x, b[i].y - r[i].y);
+}
+__global__ void cadd_to(const double2* d, int64_t nc, double2* x) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < nc) x[i] = make_double2(x[i].x + d[i].x, x[i].y + d[i].y);
+}
 
 struct ColumnResult {
     int iters = 0;
@@ -114,150 +121,188 @@ struct ColumnResult {
 
 struct Work {
     int64_t n;
-    int m;
-    double2 *V, *w, *r, *h, *h2;
-    double* nrm;
+    int m, C;
+    double2 *V, *w, *r, *R, *D, *h, *h2, *y;
+    double *nrm, *sc;
 };
 
-igb_status ensure_work(igb_op op, int m, Work& W) {
+igb_status ensure_work(igb_op op, int m, int C, Work& W) {
     const int64_t n = op->N;
-    if (op->krylov_cols < m + 1) {
-        op->d_krylov.release();
-        op->d_w.release();
-        op->d_h.release();
-        IGB_HIP(hipMalloc(&op->d_krylov.ptr, size_t(m + 1) * n * sizeof(double2)));
-        op->d_krylov.bytes = size_t(m + 1) * n * sizeof(double2);
-        IGB_HIP(hipMalloc(&op->d_w.ptr, size_t(4) * n * sizeof(double2)));
-        op->d_w.bytes = size_t(4) * n * sizeof(double2);
-        IGB_HIP(hipMalloc(&op->d_h.ptr, size_t(2 * (m + 2)) * sizeof(double2) + 64));
-        op->d_h.bytes = size_t(2 * (m + 2)) * sizeof(double2) + 64;
-        op->dev_bytes += op->d_krylov.bytes + op->d_w.bytes + op->d_h.bytes;
-        op->krylov_cols = m + 1;
-    }
+    const size_t need_v = size_t(m + 1) * C * n * sizeof(double2);
+    const size_t need_w = size_t(4) * C * n * sizeof(double2);
+    const size_t need_h = size_t(3) * (m + 2) * C * sizeof(double2) + size_t(2) * C * sizeof(double) + 64;
+    auto grow = [&](igb::DevBuf& b, size_t bytes) -> igb_status {
+        if (b.bytes >= bytes) return IGB_OK;
+        op->dev_bytes -= std::min(op->dev_bytes, b.bytes);
+        b.release();
+        IGB_HIP(hipMalloc(&b.ptr, bytes));
+        b.bytes = bytes;
+        op->dev_bytes += bytes;
+        return IGB_OK;
+    };
+    igb_status st;
+    if ((st = grow(op->d_krylov, need_v)) || (st = grow(op->d_w, need_w)) || (st = grow(op->d_h, need_h))) return st;
     W.n = n;
     W.m = m;
+    W.C = C;
     W.V = op->d_krylov.as<double2>();
     W.w = op->d_w.as<double2>();
-    W.r = W.w + n;
+    W.r = W.w + int64_t(C) * n;
+    W.R = W.r + int64_t(C) * n;
+    W.D = W.R + int64_t(C) * n;
     W.h = op->d_h.as<double2>();
-    W.h2 = W.h + (m + 2);
-    W.nrm = reinterpret_cast<double*>(W.h2 + (m + 2));
+    W.h2 = W.h + int64_t(m + 2) * C;
+    W.y = W.h2 + int64_t(m + 2) * C;
+    W.nrm = reinterpret_cast<double*>(W.y + int64_t(m + 2) * C);
+    W.sc = W.nrm + C;
     return IGB_OK;
 }
 
-igb_status norm2(const double2* v, int64_t n, double* dev_tmp, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(cnorm2, dim3(1), dim3(1024), 0, s, v, n, dev_tmp);
-    IGB_HIP(hipMemcpyAsync(out, dev_tmp, sizeof(double), hipMemcpyDeviceToHost, s));
+igb_status norms(const double2* v, int64_t n, int C, double* dev_tmp, std::vector<double>& out, hipStream_t s) {
+    hipLaunchKernelGGL(cnorm2_multi, dim3(C), dim3(1024), 0, s, v, n, dev_tmp);
+    out.resize(C);
+    IGB_HIP(hipMemcpyAsync(out.data(), dev_tmp, C * sizeof(double), hipMemcpyDeviceToHost, s));
     IGB_HIP(hipStreamSynchronize(s));
-    *out = std::sqrt(*out);
+    for (int r = 0; r < C; ++r) out[r] = std::sqrt(out[r]);
     return IGB_OK;
 }
 
-// Restarted GMRES for one column: X = 0 initially, stop at ||B - A X|| <= tol ||B||
-// (recursive estimate) or after maxit operator applications.  `mvflags` selects
-// the operator (IGB_PART_ALL, optionally with the reduced-precision far field).
-igb_status gmres_column(igb_op op, const Work& Wk, const double2* B, double2* X, int maxit, double tol,
-                        int mvflags, hipStream_t s, ColumnResult& res) {
+// Lockstep restarted GMRES for C columns: every column runs its own Arnoldi
+// process and Givens rotations; the operator is applied to all columns at once.
+// X = 0 initially; column c stops when its recursive relative residual reaches
+// tol[c] (or after maxit Arnoldi steps).  Columns never interact, so a column's
+// iterates do not depend on which other columns share the batch.
+igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, int maxit,
+                       const std::vector<double>& tol, int mvflags, hipStream_t s, std::vector<ColumnResult>& res) {
     const int64_t n = Wk.n;
-    const int m = Wk.m;
-    const unsigned gb = unsigned((n + 255) / 256);
-    double2 *V = Wk.V, *w = Wk.w, *r = Wk.r, *h = Wk.h, *h2 = Wk.h2;
-    double* nrm = Wk.nrm;
-    IGB_HIP(hipMemsetAsync(X, 0, n * sizeof(double2), s));
-    double bnorm = 0;
+    const int m = Wk.m, C = Wk.C;
+    const unsigned gb = unsigned((n * C + 255) / 256);
+    double2 *V = Wk.V, *w = Wk.w, *r = Wk.r;
     igb_status st;
-    if ((st = norm2(B, n, nrm, &bnorm, s))) return st;
-    res = ColumnResult();
-    res.converged = bnorm == 0.0;
-    res.relres = res.true_rel = res.converged ? 0.0 : 1.0;
-    IGB_HIP(hipMemcpyAsync(r, B, n * sizeof(double2), hipMemcpyDeviceToDevice, s));
-    double rnorm = bnorm;
-    std::vector<cplx> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1);
-    std::vector<double2> hh(2 * (m + 1));
-    double nrm_h = 0;
-    while (!res.converged && res.iters < maxit) {
-        hipLaunchKernelGGL(cscale_to, dim3(gb), dim3(256), 0, s, r, n, 1.0 / rnorm, V);
-        std::fill(g.begin(), g.end(), cplx(0));
-        g[0] = rnorm;
+    IGB_HIP(hipMemsetAsync(X, 0, n * C * sizeof(double2), s));
+    std::vector<double> bnorm, rnorm, hn;
+    if ((st = norms(B, n, C, Wk.nrm, bnorm, s))) return st;
+    res.assign(C, ColumnResult());
+    for (int c = 0; c < C; ++c) {
+        res[c].converged = bnorm[c] == 0.0;
+        res[c].relres = res[c].true_rel = res[c].converged ? 0.0 : 1.0;
+    }
+    IGB_HIP(hipMemcpyAsync(r, B, n * C * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    rnorm = bnorm;
+    std::vector<std::vector<cplx>> H(C, std::vector<cplx>(size_t(m + 1) * m)), cs(C, std::vector<cplx>(m)),
+        sn(C, std::vector<cplx>(m)), g(C, std::vector<cplx>(m + 1));
+    std::vector<double2> hh(size_t(2) * (m + 1) * C), yd;
+    std::vector<double> sc(C);
+    std::vector<int> jc(C);
+    auto active = [&](int c) { return !res[c].converged && res[c].iters < maxit; };
+    for (;;) {
+        bool any = false;
+        for (int c = 0; c < C; ++c) any = any || active(c);
+        if (!any) break;
+        // start a cycle: V_0 = r / ||r|| for the active columns
+        std::vector<bool> in_cycle(C);
+        for (int c = 0; c < C; ++c) {
+            in_cycle[c] = active(c);
+            sc[c] = in_cycle[c] ? 1.0 / rnorm[c] : 0.0;
+            std::fill(g[c].begin(), g[c].end(), cplx(0));
+            g[c][0] = rnorm[c];
+            jc[c] = 0;
+        }
+        IGB_HIP(hipMemcpyAsync(Wk.sc, sc.data(), C * sizeof(double), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(cscale_multi, dim3(gb), dim3(256), 0, s, r, n, C, Wk.sc, V);
         int j = 0;
-        for (; j < m && res.iters < maxit; ++j) {
-            if ((st = matvec_device(op, reinterpret_cast<const double*>(V + int64_t(j) * n),
-                                    reinterpret_cast<double*>(w), 1, mvflags, s)))
+        for (; j < m; ++j) {
+            bool going = false;
+            for (int c = 0; c < C; ++c) going = going || (in_cycle[c] && jc[c] == j && active(c));
+            if (!going) break;
+            if ((st = matvec_device(op, reinterpret_cast<const double*>(V + int64_t(j) * C * n),
+                                    reinterpret_cast<double*>(w), C, mvflags, s)))
                 return st;
-            ++res.iters;
-            ++res.applications;
             // classical Gram-Schmidt, twice
-            hipLaunchKernelGGL(cdots, dim3(j + 1), dim3(RT), 0, s, V, n, w, h, 0);
-            hipLaunchKernelGGL(cmaxpy, dim3(gb), dim3(256), 0, s, V, j + 1, n, h, w);
-            hipLaunchKernelGGL(cdots, dim3(j + 1), dim3(RT), 0, s, V, n, w, h2, 0);
-            hipLaunchKernelGGL(cmaxpy, dim3(gb), dim3(256), 0, s, V, j + 1, n, h2, w);
-            hipLaunchKernelGGL(cnorm2, dim3(1), dim3(1024), 0, s, w, n, nrm);
+            hipLaunchKernelGGL(cdots_multi, dim3(j + 1, C), dim3(RT), 0, s, V, n, C, w, Wk.h);
+            hipLaunchKernelGGL(cmaxpy_multi, dim3(gb), dim3(256), 0, s, V, j + 1, n, C, Wk.h, w);
+            hipLaunchKernelGGL(cdots_multi, dim3(j + 1, C), dim3(RT), 0, s, V, n, C, w, Wk.h2);
+            hipLaunchKernelGGL(cmaxpy_multi, dim3(gb), dim3(256), 0, s, V, j + 1, n, C, Wk.h2, w);
             IGB_HIP(hipGetLastError());
-            IGB_HIP(hipMemcpyAsync(hh.data(), h, (j + 1) * sizeof(double2), hipMemcpyDeviceToHost, s));
-            IGB_HIP(hipMemcpyAsync(hh.data() + j + 1, h2, (j + 1) * sizeof(double2), hipMemcpyDeviceToHost, s));
-            IGB_HIP(hipMemcpyAsync(&nrm_h, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
-            IGB_HIP(hipStreamSynchronize(s));
-            const double hn = std::sqrt(nrm_h);
-            for (int i = 0; i <= j; ++i)
-                H[size_t(i) * m + j] = cplx(hh[i].x + hh[j + 1 + i].x, hh[i].y + hh[j + 1 + i].y);
-            H[size_t(j + 1) * m + j] = hn;
-            if (hn > 0)
-                hipLaunchKernelGGL(cscale_to, dim3(gb), dim3(256), 0, s, w, n, 1.0 / hn, V + int64_t(j + 1) * n);
-            // Givens rotations
-            for (int i = 0; i < j; ++i) {
-                cplx a = H[size_t(i) * m + j], bb = H[size_t(i + 1) * m + j];
-                H[size_t(i) * m + j] = cs[i] * a + sn[i] * bb;
-                H[size_t(i + 1) * m + j] = -std::conj(sn[i]) * a + cs[i] * bb;
+            IGB_HIP(hipMemcpyAsync(hh.data(), Wk.h, size_t(j + 1) * C * sizeof(double2), hipMemcpyDeviceToHost, s));
+            IGB_HIP(hipMemcpyAsync(hh.data() + size_t(j + 1) * C, Wk.h2, size_t(j + 1) * C * sizeof(double2),
+                                   hipMemcpyDeviceToHost, s));
+            if ((st = norms(w, n, C, Wk.nrm, hn, s))) return st;   // synchronises
+            for (int c = 0; c < C; ++c) {
+                sc[c] = 0.0;
+                if (!(in_cycle[c] && jc[c] == j && active(c))) continue;
+                ++res[c].iters;
+                ++res[c].applications;
+                std::vector<cplx>& Hc = H[c];
+                for (int i = 0; i <= j; ++i) {
+                    const double2 a1 = hh[size_t(i) * C + c], a2 = hh[size_t(j + 1 + i) * C + c];
+                    Hc[size_t(i) * m + j] = cplx(a1.x + a2.x, a1.y + a2.y);
+                }
+                Hc[size_t(j + 1) * m + j] = hn[c];
+                for (int i = 0; i < j; ++i) {
+                    cplx a = Hc[size_t(i) * m + j], bb = Hc[size_t(i + 1) * m + j];
+                    Hc[size_t(i) * m + j] = cs[c][i] * a + sn[c][i] * bb;
+                    Hc[size_t(i + 1) * m + j] = -std::conj(sn[c][i]) * a + cs[c][i] * bb;
+                }
+                cplx a = Hc[size_t(j) * m + j], bb = Hc[size_t(j + 1) * m + j];
+                const double rr = std::sqrt(std::norm(a) + std::norm(bb));
+                if (rr == 0) {
+                    cs[c][j] = 1;
+                    sn[c][j] = 0;
+                } else if (std::abs(a) == 0) {
+                    cs[c][j] = 0;
+                    sn[c][j] = std::conj(bb) / rr;
+                } else {
+                    cs[c][j] = std::abs(a) / rr;
+                    sn[c][j] = (a / std::abs(a)) * std::conj(bb) / rr;
+                }
+                Hc[size_t(j) * m + j] = cs[c][j] * a + sn[c][j] * bb;
+                Hc[size_t(j + 1) * m + j] = 0;
+                g[c][j + 1] = -std::conj(sn[c][j]) * g[c][j];
+                g[c][j] = cs[c][j] * g[c][j];
+                res[c].relres = std::abs(g[c][j + 1]) / bnorm[c];
+                jc[c] = j + 1;
+                if (res[c].relres <= tol[c] || hn[c] == 0) {
+                    res[c].converged = true;
+                } else {
+                    sc[c] = 1.0 / hn[c];
+                }
             }
-            cplx a = H[size_t(j) * m + j], bb = H[size_t(j + 1) * m + j];
-            double rr = std::sqrt(std::norm(a) + std::norm(bb));
-            if (rr == 0) {
-                cs[j] = 1;
-                sn[j] = 0;
-            } else if (std::abs(a) == 0) {
-                cs[j] = 0;
-                sn[j] = std::conj(bb) / rr;
-            } else {
-                cs[j] = std::abs(a) / rr;
-                sn[j] = (a / std::abs(a)) * std::conj(bb) / rr;
-            }
-            H[size_t(j) * m + j] = cs[j] * a + sn[j] * bb;
-            H[size_t(j + 1) * m + j] = 0;
-            g[j + 1] = -std::conj(sn[j]) * g[j];
-            g[j] = cs[j] * g[j];
-            res.relres = std::abs(g[j + 1]) / bnorm;
-            if (res.relres <= tol || hn == 0) {
-                ++j;
-                res.converged = true;
-                break;
-            }
+            IGB_HIP(hipMemcpyAsync(Wk.sc, sc.data(), C * sizeof(double), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(cscale_multi, dim3(gb), dim3(256), 0, s, w, n, C, Wk.sc, V + int64_t(j + 1) * C * n);
         }
-        // y = H^{-1} g (upper triangular j x j), X += V y
-        std::vector<cplx> y(j);
-        for (int i = j - 1; i >= 0; --i) {
-            cplx acc = g[i];
-            for (int kk = i + 1; kk < j; ++kk) acc -= H[size_t(i) * m + kk] * y[kk];
-            y[i] = acc / H[size_t(i) * m + i];
+        // X += V y per column (zeros beyond a column's own step count)
+        int jmax = 0;
+        for (int c = 0; c < C; ++c) jmax = std::max(jmax, in_cycle[c] ? jc[c] : 0);
+        yd.assign(size_t(std::max(jmax, 1)) * C, make_double2(0, 0));
+        for (int c = 0; c < C; ++c) {
+            if (!in_cycle[c]) continue;
+            const int jj = jc[c];
+            std::vector<cplx> y(jj);
+            for (int i = jj - 1; i >= 0; --i) {
+                cplx acc = g[c][i];
+                for (int kk = i + 1; kk < jj; ++kk) acc -= H[c][size_t(i) * m + kk] * y[kk];
+                y[i] = acc / H[c][size_t(i) * m + i];
+            }
+            for (int i = 0; i < jj; ++i) yd[size_t(i) * C + c] = make_double2(y[i].real(), y[i].imag());
         }
-        std::vector<double2> yd(j);
-        for (int i = 0; i < j; ++i) yd[i] = make_double2(y[i].real(), y[i].imag());
-        IGB_HIP(hipMemcpyAsync(h, yd.data(), j * sizeof(double2), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(cupdate, dim3(gb), dim3(256), 0, s, V, j, n, h, X);
+        if (jmax > 0) {
+            IGB_HIP(hipMemcpyAsync(Wk.y, yd.data(), size_t(jmax) * C * sizeof(double2), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(cupdate_multi, dim3(gb), dim3(256), 0, s, V, jmax, n, C, Wk.y, X);
+        }
         // residual of the same operator: r = B - A X
-        if ((st = matvec_device(op, reinterpret_cast<const double*>(X), reinterpret_cast<double*>(r), 1, mvflags, s)))
+        if ((st = matvec_device(op, reinterpret_cast<const double*>(X), reinterpret_cast<double*>(r), C, mvflags, s)))
             return st;
-        ++res.applications;
-        hipLaunchKernelGGL(csub_from, dim3(gb), dim3(256), 0, s, B, n, r);
+        hipLaunchKernelGGL(csub_from_multi, dim3(gb), dim3(256), 0, s, B, n * C, r);
         IGB_HIP(hipGetLastError());
-        if ((st = norm2(r, n, nrm, &rnorm, s))) return st;
-        res.true_rel = bnorm > 0 ? rnorm / bnorm : 0.0;
+        if ((st = norms(r, n, C, Wk.nrm, rnorm, s))) return st;
+        for (int c = 0; c < C; ++c) {
+            if (!in_cycle[c]) continue;
+            ++res[c].applications;
+            res[c].true_rel = bnorm[c] > 0 ? rnorm[c] / bnorm[c] : 0.0;
+        }
     }
     return IGB_OK;
-}
-
-__global__ void cadd_to(const double2* d, int64_t n, double2* x) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = make_double2(x[i].x + d[i].x, x[i].y + d[i].y);
 }
 
 }  // namespace
@@ -269,61 +314,79 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
     const int maxit = sp->maxit > 0 ? sp->maxit : 1000;
     const double tol = sp->tol > 0 ? sp->tol : 1e-8;
     const bool mixed = op->prm.precision != IGB_FP64;
+    const int C = ndir;
     Work W;
     igb_status st;
-    if ((st = ensure_work(op, m, W))) return st;
-    const unsigned gb = unsigned((n + 255) / 256);
+    if ((st = ensure_work(op, m, C, W))) return st;
+    const unsigned gb = unsigned((n * C + 255) / 256);
+    const double2* B = reinterpret_cast<const double2*>(b_in);
+    double2* X = reinterpret_cast<double2*>(x_out);
+    std::vector<ColumnResult> res;
     igb_solve_info out{};
-    int status = IGB_OK;
-    for (int col = 0; col < ndir; ++col) {
-        const double2* B = reinterpret_cast<const double2*>(b_in) + int64_t(col) * n;
-        double2* X = reinterpret_cast<double2*>(x_out) + int64_t(col) * n;
-        ColumnResult res;
-        if (!mixed) {
-            if ((st = gmres_column(op, W, B, X, maxit, tol, IGB_PART_ALL, s, res))) return st;
-        } else {
-            // iterative refinement: inner GMRES on the reduced-precision far field,
-            // outer residual with the fp64 operator
-            double2* R = W.w + 2 * n;   // outer residual
-            double2* D = W.w + 3 * n;   // correction
-            const double inner_min = sp->inner_tol > 0 ? sp->inner_tol
-                                     : (op->prm.precision == IGB_MIX_FP32 ? 0.0 : 1e-3);
-            const int refine_max = sp->refine_max > 0 ? sp->refine_max : 10;
-            IGB_HIP(hipMemsetAsync(X, 0, n * sizeof(double2), s));
-            IGB_HIP(hipMemcpyAsync(R, B, n * sizeof(double2), hipMemcpyDeviceToDevice, s));
-            double bnorm = 0, rnorm = 0;
-            if ((st = norm2(B, n, W.nrm, &bnorm, s))) return st;
-            rnorm = bnorm;
-            ColumnResult acc;
-            acc.converged = bnorm == 0.0;
-            acc.true_rel = acc.converged ? 0.0 : 1.0;
-            for (int outer = 0; outer < refine_max && !acc.converged && acc.iters < maxit; ++outer) {
-                const double tin = std::max(inner_min, 0.5 * tol * bnorm / rnorm);
-                ColumnResult inner;
-                if ((st = gmres_column(op, W, R, D, maxit - acc.iters, tin, IGB_PART_ALL | IGB_MV_LOWPREC, s, inner)))
-                    return st;
-                acc.iters += inner.iters;
-                acc.applications += inner.applications;
-                hipLaunchKernelGGL(cadd_to, dim3(gb), dim3(256), 0, s, D, n, X);
-                if ((st = matvec_device(op, reinterpret_cast<const double*>(X), reinterpret_cast<double*>(R), 1,
-                                        IGB_PART_ALL, s)))
-                    return st;
-                ++acc.applications;
-                hipLaunchKernelGGL(csub_from, dim3(gb), dim3(256), 0, s, B, n, R);
-                if ((st = norm2(R, n, W.nrm, &rnorm, s))) return st;
-                acc.true_rel = bnorm > 0 ? rnorm / bnorm : 0.0;
-                acc.relres = acc.true_rel;
-                acc.converged = acc.true_rel <= tol;
-                ++out.refinements;
-            }
-            res = acc;
+    if (!mixed) {
+        if ((st = gmres_block(op, W, B, X, maxit, std::vector<double>(C, tol), IGB_PART_ALL, s, res))) return st;
+    } else {
+        // iterative refinement: inner GMRES on the reduced-precision far field,
+        // outer residual with the fp64 operator; columns refine independently
+        const double inner_min = sp->inner_tol > 0 ? sp->inner_tol : (op->prm.precision == IGB_MIX_FP32 ? 0.0 : 1e-3);
+        const int refine_max = sp->refine_max > 0 ? sp->refine_max : 10;
+        // the outer residual and correction live in separate buffers from the
+        // inner solver's work vectors
+        igb::DevBuf rbuf, dbuf;
+        IGB_HIP(hipMalloc(&rbuf.ptr, size_t(n) * C * sizeof(double2)));
+        IGB_HIP(hipMalloc(&dbuf.ptr, size_t(n) * C * sizeof(double2)));
+        double2* R = rbuf.as<double2>();
+        double2* D = dbuf.as<double2>();
+        IGB_HIP(hipMemsetAsync(X, 0, n * C * sizeof(double2), s));
+        IGB_HIP(hipMemcpyAsync(R, B, n * C * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        std::vector<double> bnorm, rnorm;
+        if ((st = norms(B, n, C, W.nrm, bnorm, s))) return st;
+        rnorm = bnorm;
+        res.assign(C, ColumnResult());
+        for (int c = 0; c < C; ++c) {
+            res[c].converged = bnorm[c] == 0.0;
+            res[c].relres = res[c].true_rel = res[c].converged ? 0.0 : 1.0;
         }
-        out.iters = std::max(out.iters, res.iters);
-        out.matvecs += res.applications;
-        out.converged += res.converged ? 1 : 0;
-        out.relres = std::max(out.relres, res.relres);
-        out.relres_true = std::max(out.relres_true, res.true_rel);
-        if (!res.converged) status = IGB_WARN_NOT_CONVERGED;
+        for (int outer = 0; outer < refine_max; ++outer) {
+            // inner tolerance per column: what the column still needs, at least inner_min
+            std::vector<double> tin(C, 1.0);
+            bool any = false;
+            for (int c = 0; c < C; ++c) {
+                if (res[c].converged) {
+                    IGB_HIP(hipMemsetAsync(R + int64_t(c) * n, 0, n * sizeof(double2), s));
+                    continue;
+                }
+                any = true;
+                tin[c] = std::max(inner_min, 0.5 * tol * bnorm[c] / rnorm[c]);
+            }
+            if (!any) break;
+            std::vector<ColumnResult> inner;
+            if ((st = gmres_block(op, W, R, D, maxit, tin, IGB_PART_ALL | IGB_MV_LOWPREC, s, inner))) return st;
+            hipLaunchKernelGGL(cadd_to, dim3(gb), dim3(256), 0, s, D, n * C, X);
+            if ((st = matvec_device(op, reinterpret_cast<const double*>(X), reinterpret_cast<double*>(R), C,
+                                    IGB_PART_ALL, s)))
+                return st;
+            hipLaunchKernelGGL(csub_from_multi, dim3(gb), dim3(256), 0, s, B, n * C, R);
+            if ((st = norms(R, n, C, W.nrm, rnorm, s))) return st;
+            for (int c = 0; c < C; ++c) {
+                if (res[c].converged) continue;
+                res[c].iters += inner[c].iters;
+                res[c].applications += inner[c].applications + 1;
+                res[c].true_rel = bnorm[c] > 0 ? rnorm[c] / bnorm[c] : 0.0;
+                res[c].relres = res[c].true_rel;
+                res[c].converged = res[c].true_rel <= tol;
+            }
+            ++out.refinements;
+        }
+    }
+    int status = IGB_OK;
+    for (int c = 0; c < C; ++c) {
+        out.iters = std::max(out.iters, res[c].iters);
+        out.matvecs += res[c].applications;
+        out.converged += res[c].converged ? 1 : 0;
+        out.relres = std::max(out.relres, res[c].relres);
+        out.relres_true = std::max(out.relres_true, res[c].true_rel);
+        if (!res[c].converged) status = IGB_WARN_NOT_CONVERGED;
     }
     if (info) *info = out;
     return status;

@@ -601,28 +601,38 @@ __global__ void coupling_hard(const double* nodes, const int* pair_tgt, const in
 // --------------------------------------------------------------------------
 // H^2 matrix-vector pipeline
 // --------------------------------------------------------------------------
-// x2[i] = x0[s2_to_s0[i]]  (S^0 -> S^2 injection)
-__global__ void glue_gather(const int* s2_to_s0, const double2* x0, double2* x2, int64_t n2) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n2) x2[i] = x0[s2_to_s0[i]];
+// Multi-column layouts (ncol columns C):  vectors [C][n]; moments
+// [kind][cluster][nq][C]; M2L partials [chunk][nvec][nq][C]; leaf buffers
+// [kind][leaf][C][w*w].  Every kernel computes each column with the same
+// operation order whatever ncol is, so a column's result does not depend on
+// the batch it is computed in.
+
+// x2[r][i] = x0[r][s2_to_s0[i]]  (S^0 -> S^2 injection)
+__global__ void glue_gather(const int* s2_to_s0, const double2* x0, int64_t n0, double2* x2, int64_t n2, int ncol) {
+    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= n2 * ncol) return;
+    const int64_t r = gid / n2, i = gid % n2;
+    x2[gid] = x0[r * n0 + s2_to_s0[i]];
 }
 
-// leaf moments  xh[leaf][a] = sum_{window} m1[cy][av][iv] m1[cx][au][iu] x[patch][iv][iu]
-__global__ void leaf_moments(const double2* x, const double* m1, int q, int d, int p, int L,
-                             int k, int64_t leaf_off, int64_t nleaf, double2* xh, int deriv_u,
-                             int deriv_v, int64_t m1_stride_kind) {
+// leaf moments  xh[leaf][a][r] = sum_{window} m_v[cy][av][iv] m_u[cx][au][iu] x[r][patch][iv][iu]
+__global__ void leaf_moments(const double2* x, int64_t xstride, const double* m1, int q, int d, int p, int L,
+                             int k, int64_t leaf_off, int64_t nleaf, double2* xh, int deriv_u, int deriv_v,
+                             int64_t m1_stride_kind, int ncol) {
     const int nq = (q + 1) * (q + 1);
     const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (gid >= nleaf * nq) return;
-    const int64_t c = gid / nq;
-    const int a = int(gid % nq), au = a % (q + 1), av = a / (q + 1);
+    if (gid >= nleaf * nq * ncol) return;
+    const int r = int(gid % ncol);
+    const int64_t t = gid / ncol;
+    const int64_t c = t / nq;
+    const int a = int(t % nq), au = a % (q + 1), av = a / (q + 1);
     const int n = 1 << L, s = 1 << d, w = s + p;
     const int patch = int(c / (int64_t(n) * n));
     const int rem = int(c % (int64_t(n) * n));
     const int cy = rem / n, cx = rem % n;
     const double* mu = m1 + deriv_u * m1_stride_kind + (int64_t(cx) * (q + 1) + au) * w;
     const double* mv = m1 + deriv_v * m1_stride_kind + (int64_t(cy) * (q + 1) + av) * w;
-    const double2* X = x + int64_t(patch) * k * k + int64_t(cy) * s * k + int64_t(cx) * s;
+    const double2* X = x + r * xstride + int64_t(patch) * k * k + int64_t(cy) * s * k + int64_t(cx) * s;
     double2 acc = make_double2(0, 0);
     for (int iv = 0; iv < w; ++iv) {
         double2 row = make_double2(0, 0);
@@ -634,129 +644,140 @@ __global__ void leaf_moments(const double2* x, const double* m1, int q, int d, i
         acc.x = fma(mv[iv], row.x, acc.x);
         acc.y = fma(mv[iv], row.y, acc.y);
     }
-    xh[(leaf_off + c) * nq + a] = acc;
+    xh[((leaf_off + c) * nq + a) * ncol + r] = acc;
 }
 
 // ---- workgroup-per-cluster tree kernels (LDS staged, sum-factorised) ----
 constexpr int TREE_THREADS = 128;
 constexpr int TQ1 = QMAX + 1;
 constexpr int TNQ = TQ1 * TQ1;
+constexpr int TCB = 2;  // columns per workgroup
 
-// upward, one workgroup per parent at level l:
+// upward, one workgroup per (parent at level l, column block):
 //   x^_P[av][au] = sum_c sum_gv Tv_c[gv][av] sum_gu Tu_c[gu][au] x^_c[gv][gu]
 __global__ __launch_bounds__(TREE_THREADS) void m2m_wg(const double* __restrict__ T1, int q, int l,
-                                                       int64_t off_l, int64_t off_l1, double2* xh) {
+                                                       int64_t off_l, int64_t off_l1, double2* xh, int ncol) {
     __shared__ double T[2 * TQ1 * TQ1];
-    __shared__ double2 X[4 * TNQ];
-    __shared__ double2 tmp[4 * TNQ];
+    __shared__ double2 X[4 * TNQ * TCB];
+    __shared__ double2 tmp[4 * TNQ * TCB];
     const int q1 = q + 1, nq = q1 * q1, tid = threadIdx.x;
     const int64_t c = blockIdx.x;
+    const int c0 = blockIdx.y * TCB;
     const int n = 1 << l;
     const int patch = int(c / (int64_t(n) * n));
     const int rem = int(c % (int64_t(n) * n));
     const int cy = rem / n, cx = rem % n;
     for (int i = tid; i < 2 * q1 * q1; i += TREE_THREADS) T[i] = T1[i];
-    for (int i = tid; i < 4 * nq; i += TREE_THREADS) {
-        const int ch = i / nq, a = i % nq, bu = ch & 1, bv = ch >> 1;
+    for (int i = tid; i < 4 * nq * TCB; i += TREE_THREADS) {
+        const int cb = i % TCB, t = i / TCB, ch = t / nq, a = t % nq, bu = ch & 1, bv = ch >> 1;
         const int64_t child = off_l1 + (int64_t(patch) << (2 * (l + 1))) + (int64_t(2 * cy + bv) << (l + 1)) +
                               2 * cx + bu;
-        X[i] = xh[child * nq + a];
+        X[i] = c0 + cb < ncol ? xh[(child * nq + a) * ncol + c0 + cb] : make_double2(0, 0);
     }
     __syncthreads();
-    for (int i = tid; i < 4 * nq; i += TREE_THREADS) {
-        const int ch = i / nq, r = i % nq, gv = r / q1, au = r % q1, bu = ch & 1;
+    for (int i = tid; i < 4 * nq * TCB; i += TREE_THREADS) {
+        const int cb = i % TCB, t = i / TCB, ch = t / nq, r = t % nq, gv = r / q1, au = r % q1, bu = ch & 1;
         const double* Tu = T + bu * q1 * q1;
         double2 acc = make_double2(0, 0);
         for (int gu = 0; gu < q1; ++gu) {
-            const double t = Tu[gu * q1 + au];
-            const double2 xv = X[ch * nq + gv * q1 + gu];
-            acc.x = fma(t, xv.x, acc.x);
-            acc.y = fma(t, xv.y, acc.y);
+            const double tt = Tu[gu * q1 + au];
+            const double2 xv = X[(ch * nq + gv * q1 + gu) * TCB + cb];
+            acc.x = fma(tt, xv.x, acc.x);
+            acc.y = fma(tt, xv.y, acc.y);
         }
         tmp[i] = acc;
     }
     __syncthreads();
-    for (int a = tid; a < nq; a += TREE_THREADS) {
-        const int av = a / q1, au = a % q1;
+    for (int i = tid; i < nq * TCB; i += TREE_THREADS) {
+        const int cb = i % TCB, a = i / TCB, av = a / q1, au = a % q1;
+        if (c0 + cb >= ncol) continue;
         double2 acc = make_double2(0, 0);
         for (int ch = 0; ch < 4; ++ch) {
             const double* Tv = T + (ch >> 1) * q1 * q1;
             for (int gv = 0; gv < q1; ++gv) {
-                const double t = Tv[gv * q1 + av];
-                const double2 v = tmp[ch * nq + gv * q1 + au];
-                acc.x = fma(t, v.x, acc.x);
-                acc.y = fma(t, v.y, acc.y);
+                const double tt = Tv[gv * q1 + av];
+                const double2 v = tmp[(ch * nq + gv * q1 + au) * TCB + cb];
+                acc.x = fma(tt, v.x, acc.x);
+                acc.y = fma(tt, v.y, acc.y);
             }
         }
-        xh[(off_l + c) * nq + a] = acc;
+        xh[((off_l + c) * nq + a) * ncol + c0 + cb] = acc;
     }
 }
 
-// downward, one workgroup per parent at level l:
+// downward, one workgroup per (parent at level l, column block):
 //   y^_c[gv][gu] += sum_av Tv_c[gv][av] sum_au Tu_c[gu][au] y^_P[av][au]
 __global__ __launch_bounds__(TREE_THREADS) void l2l_wg(const double* __restrict__ T1, int q, int l,
-                                                       int64_t off_l, int64_t off_l1, double2* yh) {
+                                                       int64_t off_l, int64_t off_l1, double2* yh, int ncol) {
     __shared__ double T[2 * TQ1 * TQ1];
-    __shared__ double2 Y[TNQ];
-    __shared__ double2 tmp[2 * TNQ];
+    __shared__ double2 Y[TNQ * TCB];
+    __shared__ double2 tmp[2 * TNQ * TCB];
     const int q1 = q + 1, nq = q1 * q1, tid = threadIdx.x;
     const int64_t c = blockIdx.x;
+    const int c0 = blockIdx.y * TCB;
     const int n = 1 << l;
     const int patch = int(c / (int64_t(n) * n));
     const int rem = int(c % (int64_t(n) * n));
     const int cy = rem / n, cx = rem % n;
     for (int i = tid; i < 2 * q1 * q1; i += TREE_THREADS) T[i] = T1[i];
-    for (int i = tid; i < nq; i += TREE_THREADS) Y[i] = yh[(off_l + c) * nq + i];
+    for (int i = tid; i < nq * TCB; i += TREE_THREADS) {
+        const int cb = i % TCB, a = i / TCB;
+        Y[i] = c0 + cb < ncol ? yh[((off_l + c) * nq + a) * ncol + c0 + cb] : make_double2(0, 0);
+    }
     __syncthreads();
     // tmp[bv][gv][au] = sum_av Tv[bv][gv][av] Y[av][au]
-    for (int i = tid; i < 2 * nq; i += TREE_THREADS) {
-        const int bv = i / nq, r = i % nq, gv = r / q1, au = r % q1;
+    for (int i = tid; i < 2 * nq * TCB; i += TREE_THREADS) {
+        const int cb = i % TCB, t = i / TCB, bv = t / nq, r = t % nq, gv = r / q1, au = r % q1;
         const double* Tv = T + bv * q1 * q1;
         double2 acc = make_double2(0, 0);
         for (int av = 0; av < q1; ++av) {
-            const double t = Tv[gv * q1 + av];
-            const double2 v = Y[av * q1 + au];
-            acc.x = fma(t, v.x, acc.x);
-            acc.y = fma(t, v.y, acc.y);
+            const double tt = Tv[gv * q1 + av];
+            const double2 v = Y[(av * q1 + au) * TCB + cb];
+            acc.x = fma(tt, v.x, acc.x);
+            acc.y = fma(tt, v.y, acc.y);
         }
         tmp[i] = acc;
     }
     __syncthreads();
-    for (int i = tid; i < 4 * nq; i += TREE_THREADS) {
-        const int ch = i / nq, g = i % nq, gv = g / q1, gu = g % q1, bu = ch & 1, bv = ch >> 1;
+    for (int i = tid; i < 4 * nq * TCB; i += TREE_THREADS) {
+        const int cb = i % TCB, t = i / TCB, ch = t / nq, g = t % nq, gv = g / q1, gu = g % q1, bu = ch & 1,
+                  bv = ch >> 1;
+        if (c0 + cb >= ncol) continue;
         const double* Tu = T + bu * q1 * q1;
         double2 acc = make_double2(0, 0);
         for (int au = 0; au < q1; ++au) {
-            const double t = Tu[gu * q1 + au];
-            const double2 v = tmp[bv * nq + gv * q1 + au];
-            acc.x = fma(t, v.x, acc.x);
-            acc.y = fma(t, v.y, acc.y);
+            const double tt = Tu[gu * q1 + au];
+            const double2 v = tmp[((bv * nq) + gv * q1 + au) * TCB + cb];
+            acc.x = fma(tt, v.x, acc.x);
+            acc.y = fma(tt, v.y, acc.y);
         }
         const int64_t child = off_l1 + (int64_t(patch) << (2 * (l + 1))) + (int64_t(2 * cy + bv) << (l + 1)) +
                               2 * cx + bu;
-        double2* dst = yh + child * nq + g;
+        double2* dst = yh + (child * nq + g) * ncol + c0 + cb;
         *dst = cadd(*dst, acc);
     }
 }
 
-// back projection, one workgroup per leaf: out[lv][lu] = sum_av m_v[av][lv] sum_au m_u[au][lu] y^[av][au]
-// over the leaf's (s+p)^2 window, written to a per-leaf buffer
+// back projection, one workgroup per (leaf, column):
+//   out[lv][lu] = sum_av m_v[av][lv] sum_au m_u[au][lu] y^[av][au]
+// over the leaf's (s+p)^2 window, written to the per-leaf buffer
 constexpr int WMAX = 64 + PMAX;
 __global__ __launch_bounds__(TREE_THREADS) void back_project_leaf(const double2* __restrict__ yh,
                                                                   const double* __restrict__ m1, int q, int w,
                                                                   int L, int64_t leaf_off, int deriv_u,
-                                                                  int deriv_v, int64_t m1_stride_kind,
+                                                                  int deriv_v, int64_t m1_stride_kind, int ncol,
                                                                   double2* __restrict__ leafbuf) {
     __shared__ double2 Y[TNQ];
     __shared__ double2 tmp[TQ1 * WMAX];
     const int q1 = q + 1, nq = q1 * q1, tid = threadIdx.x;
     const int64_t c = blockIdx.x;
+    const int r = blockIdx.y;
     const int n = 1 << L;
     const int rem = int(c % (int64_t(n) * n));
     const int cy = rem / n, cx = rem % n;
     const double* mu = m1 + deriv_u * m1_stride_kind + int64_t(cx) * q1 * w;
     const double* mv = m1 + deriv_v * m1_stride_kind + int64_t(cy) * q1 * w;
-    for (int i = tid; i < nq; i += TREE_THREADS) Y[i] = yh[(leaf_off + c) * nq + i];
+    for (int i = tid; i < nq; i += TREE_THREADS) Y[i] = yh[((leaf_off + c) * nq + i) * ncol + r];
     __syncthreads();
     for (int i = tid; i < q1 * w; i += TREE_THREADS) {
         const int av = i / w, lu = i % w;
@@ -777,20 +798,22 @@ __global__ __launch_bounds__(TREE_THREADS) void back_project_leaf(const double2*
             acc.x = fma(t, tmp[av * w + lu].x, acc.x);
             acc.y = fma(t, tmp[av * w + lu].y, acc.y);
         }
-        leafbuf[c * w * w + i] = acc;
+        leafbuf[(c * ncol + r) * w * w + i] = acc;
     }
 }
 
-// y[i] (+)= sum over the leaves whose window contains i (fixed order)
+// y[r][i] = sum over kinds and the leaves whose window contains i (fixed order)
 __global__ void leaf_gather(const double2* __restrict__ leafbuf, int d, int p, int L, int k, int npatch, int kinds,
-                            double2* __restrict__ y) {
+                            int ncol, double2* __restrict__ y) {
     const int64_t n2 = int64_t(npatch) * k * k;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n2) return;
+    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= n2 * ncol) return;
+    const int64_t r = gid / n2, i = gid % n2;
     const int patch = int(i / (int64_t(k) * k));
     const int rem = int(i % (int64_t(k) * k));
     const int iv = rem / k, iu = rem % k;
     const int s = 1 << d, w = s + p, n = 1 << L;
+    const int64_t nleaf = int64_t(npatch) * n * n;
     double2 acc = make_double2(0, 0);
     const int cy0 = max(0, (iv - w + s) / s), cy1 = min(n - 1, iv / s);
     const int cx0 = max(0, (iu - w + s) / s), cx1 = min(n - 1, iu / s);
@@ -802,14 +825,14 @@ __global__ void leaf_gather(const double2* __restrict__ leafbuf, int d, int p, i
             if (lu < 0 || lu >= w) continue;
             const int64_t leaf = (int64_t(patch) << (2 * L)) + int64_t(cy) * n + cx;
             for (int kd = 0; kd < kinds; ++kd)
-                acc = cadd(acc, leafbuf[(int64_t(kd) * npatch * n * n + leaf) * w * w + lv * w + lu]);
+                acc = cadd(acc, leafbuf[((kd * nleaf + leaf) * ncol + r) * w * w + lv * w + lu]);
         }
     }
-    y[i] = acc;
+    y[gid] = acc;
 }
 
 // storage types of the coupling tiles: fp64, fp32 or bf16 complex; products and
-// accumulation run in fp64 on the single-column path
+// accumulation run in fp64 on the VALU path
 struct bf16x2 {
     unsigned short re, im;
 };
@@ -839,117 +862,149 @@ __global__ void round_coupling(const double2* __restrict__ in, int64_t n, int pr
     }
 }
 
-// coupling: one workgroup per chunk of source clusters of one target
-template <int NT, class CT>
-__global__ __launch_bounds__(NT) void m2l_chunks(const CT* __restrict__ coup,
-                                                 const double2* __restrict__ xh,
+// coupling, sound-soft: one workgroup per (chunk of source clusters of one
+// target, block of RB columns); lane a owns output row a and RB accumulators
+template <int NT, class CT, int RB>
+__global__ __launch_bounds__(NT) void m2l_chunks(const CT* __restrict__ coup, const double2* __restrict__ xh,
                                                  const int* __restrict__ far_src_g,
                                                  const int64_t* __restrict__ chunk_pair,
-                                                 const int* __restrict__ chunk_len, int64_t nchunk,
-                                                 int nq, double2* __restrict__ part) {
-    __shared__ double2 xs[NT];
+                                                 const int* __restrict__ chunk_len, int64_t nchunk, int nq, int ncol,
+                                                 double2* __restrict__ part) {
+    __shared__ double2 xs[NT * RB];
     const int64_t ch = blockIdx.x;
     if (ch >= nchunk) return;
+    const int c0 = blockIdx.y * RB;
     const int a = threadIdx.x;
     const int64_t p0 = chunk_pair[ch];
     const int len = chunk_len[ch];
-    double2 acc = make_double2(0, 0);
+    double2 acc[RB];
+#pragma unroll
+    for (int cb = 0; cb < RB; ++cb) acc[cb] = make_double2(0, 0);
     for (int i = 0; i < len; ++i) {
         const int64_t pr = p0 + i;
+        const int64_t src = far_src_g[pr];
         __syncthreads();
-        if (a < nq) xs[a] = xh[int64_t(far_src_g[pr]) * nq + a];
+        for (int idx = a; idx < nq * RB; idx += NT) {
+            const int cb = idx % RB, b = idx / RB;
+            xs[idx] = c0 + cb < ncol ? xh[(src * nq + b) * ncol + c0 + cb] : make_double2(0, 0);
+        }
         __syncthreads();
         if (a < nq) {
             const CT* K = coup + pr * nq * nq + a;
 #pragma unroll 7
-            for (int b = 0; b < nq; ++b) acc = cfma(to_d2(K[int64_t(b) * nq]), xs[b], acc);
+            for (int b = 0; b < nq; ++b) {
+                const double2 kv = to_d2(K[int64_t(b) * nq]);
+#pragma unroll
+                for (int cb = 0; cb < RB; ++cb) acc[cb] = cfma(kv, xs[b * RB + cb], acc[cb]);
+            }
         }
     }
-    if (a < nq) part[ch * nq + a] = acc;
+    if (a < nq)
+#pragma unroll
+        for (int cb = 0; cb < RB; ++cb)
+            if (c0 + cb < ncol) part[(ch * nq + a) * ncol + c0 + cb] = acc[cb];
 }
 
-// sound-hard coupling: per source the 7 node-scaled moment vectors
+// coupling, sound-hard: per source the 7 node-scaled moment vectors
 //   n~_c xp (c = 0..2), (y.n~) xp, v_c = F_v,c xu - F_u,c xv
 // are formed in LDS; H acts on {(y.n~) xp, n~_c xp}, G on {n~_c xp, v_c}:
-// 10 partial vectors per chunk.
-template <int NT, class CT>
-__global__ __launch_bounds__(NT) void m2l_hard_chunks(const CT* __restrict__ coup,
-                                                      const double2* __restrict__ xh, int64_t kind_stride,
-                                                      const double* __restrict__ nodes,
+// 10 partial vectors per chunk and column.
+template <int NT, class CT, int RB>
+__global__ __launch_bounds__(NT) void m2l_hard_chunks(const CT* __restrict__ coup, const double2* __restrict__ xh,
+                                                      int64_t kind_stride, const double* __restrict__ nodes,
                                                       const int* __restrict__ far_src_g,
                                                       const int64_t* __restrict__ chunk_pair,
                                                       const int* __restrict__ chunk_len, int64_t nchunk, int nq,
-                                                      double2* __restrict__ part) {
-    __shared__ double2 sv[7][NT];
+                                                      int ncol, double2* __restrict__ part) {
+    __shared__ double2 sv[7][NT * RB];
     const int64_t ch = blockIdx.x;
     if (ch >= nchunk) return;
+    const int c0 = blockIdx.y * RB;
     const int a = threadIdx.x;
     const int64_t p0 = chunk_pair[ch];
     const int len = chunk_len[ch];
-    double2 rh[4], rg[6];
+    double2 rh[4][RB], rg[6][RB];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) rh[v] = make_double2(0, 0);
+    for (int cb = 0; cb < RB; ++cb) {
 #pragma unroll
-    for (int v = 0; v < 6; ++v) rg[v] = make_double2(0, 0);
+        for (int v = 0; v < 4; ++v) rh[v][cb] = make_double2(0, 0);
+#pragma unroll
+        for (int v = 0; v < 6; ++v) rg[v][cb] = make_double2(0, 0);
+    }
     for (int i = 0; i < len; ++i) {
         const int64_t pr = p0 + i;
+        const int64_t src = far_src_g[pr];
         __syncthreads();
-        if (a < nq) {
-            const int64_t src = far_src_g[pr];
-            const double* Y = nodes + (src * nq + a) * 16;
-            const double2 xp = xh[src * nq + a], xu = xh[kind_stride + src * nq + a],
-                          xv = xh[2 * kind_stride + src * nq + a];
+        for (int idx = a; idx < nq * RB; idx += NT) {
+            const int cb = idx % RB, b = idx / RB;
+            const double* Y = nodes + (src * nq + b) * 16;
+            double2 xp = make_double2(0, 0), xu = xp, xv = xp;
+            if (c0 + cb < ncol) {
+                const int64_t o = (src * nq + b) * ncol + c0 + cb;
+                xp = xh[o];
+                xu = xh[kind_stride + o];
+                xv = xh[2 * kind_stride + o];
+            }
             const double yn = Y[0] * Y[3] + Y[1] * Y[4] + Y[2] * Y[5];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                sv[c][a] = cscale(xp, Y[3 + c]);
-                sv[4 + c][a] = make_double2(Y[11 + c] * xu.x - Y[8 + c] * xv.x, Y[11 + c] * xu.y - Y[8 + c] * xv.y);
+                sv[c][idx] = cscale(xp, Y[3 + c]);
+                sv[4 + c][idx] = make_double2(Y[11 + c] * xu.x - Y[8 + c] * xv.x, Y[11 + c] * xu.y - Y[8 + c] * xv.y);
             }
-            sv[3][a] = cscale(xp, yn);
+            sv[3][idx] = cscale(xp, yn);
         }
         __syncthreads();
         if (a < nq) {
             const CT* K = coup + pr * nq * nq * 2 + 2 * a;
             for (int b = 0; b < nq; ++b) {
                 const double2 G = to_d2(K[int64_t(b) * nq * 2]), H = to_d2(K[int64_t(b) * nq * 2 + 1]);
-                rh[0] = cfma(H, sv[3][b], rh[0]);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    rh[1 + c] = cfma(H, sv[c][b], rh[1 + c]);
-                    rg[c] = cfma(G, sv[c][b], rg[c]);
-                    rg[3 + c] = cfma(G, sv[4 + c][b], rg[3 + c]);
+                for (int cb = 0; cb < RB; ++cb) {
+                    const int o = b * RB + cb;
+                    rh[0][cb] = cfma(H, sv[3][o], rh[0][cb]);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        rh[1 + c][cb] = cfma(H, sv[c][o], rh[1 + c][cb]);
+                        rg[c][cb] = cfma(G, sv[c][o], rg[c][cb]);
+                        rg[3 + c][cb] = cfma(G, sv[4 + c][o], rg[3 + c][cb]);
+                    }
                 }
             }
         }
     }
-    if (a < nq) {
-        double2* o = part + ch * 10 * nq + a;
+    if (a < nq)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) o[v * nq] = rh[v];
+        for (int cb = 0; cb < RB; ++cb) {
+            if (c0 + cb >= ncol) continue;
 #pragma unroll
-        for (int v = 0; v < 6; ++v) o[(4 + v) * nq] = rg[v];
-    }
+            for (int v = 0; v < 4; ++v) part[((ch * 10 + v) * nq + a) * ncol + c0 + cb] = rh[v][cb];
+#pragma unroll
+            for (int v = 0; v < 6; ++v) part[((ch * 10 + 4 + v) * nq + a) * ncol + c0 + cb] = rg[v][cb];
+        }
 }
 
 // target-side factors of the sound-hard coupling:
 //   y_p = -a R0 + a sum_c x_c R_c + i eta kappa^2 sum_c n~_c S_c
 //   y_u = -i eta sum_c F_v,c T_c,   y_v = +i eta sum_c F_u,c T_c
-// from raw[cluster][10][nq] = (R0, R_0..2, S_0..2, T_0..2)
+// from raw[cluster][10][nq][C] = (R0, R_0..2, S_0..2, T_0..2)
 __global__ void m2l_finalize_hard(const double2* raw, const double* nodes, int64_t nclusters, int nq, double kappa,
-                                  double eta, int64_t kind_stride, double2* yh) {
+                                  double eta, int64_t kind_stride, int ncol, double2* yh) {
     const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (gid >= nclusters * nq) return;
-    const int64_t c = gid / nq;
-    const int a = int(gid % nq);
-    const double* X = nodes + gid * 16;
-    const double2* r = raw + c * 10 * nq + a;
-    double2 yp = cscale(r[0], -X[6]);
+    if (gid >= nclusters * nq * ncol) return;
+    const int r = int(gid % ncol);
+    const int64_t t = gid / ncol;
+    const int64_t c = t / nq;
+    const int a = int(t % nq);
+    const double* X = nodes + t * 16;
+    const double2* rw = raw + (c * 10 * nq + a) * ncol + r;
+    const int64_t vs = int64_t(nq) * ncol;
+    double2 yp = cscale(rw[0], -X[6]);
     double2 su = make_double2(0, 0), sv = make_double2(0, 0), sn = make_double2(0, 0);
     for (int cc = 0; cc < 3; ++cc) {
-        yp = cadd(yp, cscale(r[(1 + cc) * nq], X[6] * X[cc]));
-        sn = cadd(sn, cscale(r[(4 + cc) * nq], X[3 + cc]));
-        su = cadd(su, cscale(r[(7 + cc) * nq], X[11 + cc]));
-        sv = cadd(sv, cscale(r[(7 + cc) * nq], X[8 + cc]));
+        yp = cadd(yp, cscale(rw[(1 + cc) * vs], X[6] * X[cc]));
+        sn = cadd(sn, cscale(rw[(4 + cc) * vs], X[3 + cc]));
+        su = cadd(su, cscale(rw[(7 + cc) * vs], X[11 + cc]));
+        sv = cadd(sv, cscale(rw[(7 + cc) * vs], X[8 + cc]));
     }
     const double k2 = eta * kappa * kappa;
     yp = cadd(yp, make_double2(-k2 * sn.y, k2 * sn.x));               // + i eta kappa^2 sn
@@ -958,12 +1013,11 @@ __global__ void m2l_finalize_hard(const double2* raw, const double* nodes, int64
     yh[2 * kind_stride + gid] = make_double2(-eta * sv.y, eta * sv.x); // +i eta sv
 }
 
-// yh[c][a] = sum over the target's chunks (fixed order); zero if none
-// (nvec vectors per chunk / cluster, layout [chunk][nvec][nq] -> [cluster][nvec][nq])
-__global__ void m2l_reduce(const double2* part, const int* tgt_chunk_ptr, int64_t nclusters, int nq, int nvec,
+// sum over the target's chunks (fixed order), zero if none:
+// [chunk][per] -> [cluster][per], per = nvec * nq * ncol
+__global__ void m2l_reduce(const double2* part, const int* tgt_chunk_ptr, int64_t nclusters, int64_t per,
                            double2* yh) {
     const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t per = int64_t(nvec) * nq;
     if (gid >= nclusters * per) return;
     const int64_t c = gid / per;
     const int64_t va = gid % per;
@@ -972,38 +1026,57 @@ __global__ void m2l_reduce(const double2* part, const int* tgt_chunk_ptr, int64_
     yh[gid] = s;
 }
 
-// y[row] = sum_j val x[col] (+ far part mapped to the solution space); one wave
-// per row, lanes stride over the row, butterfly reduction (fixed order)
+// y[r][row] = sum_j val x[r][col] (+ far part mapped to the solution space); one
+// wave per row, lanes stride over the row, butterfly reduction (fixed order)
+constexpr int SPMV_RB = 4;
 __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ row_ptr,
                                                     const int* __restrict__ col,
                                                     const double2* __restrict__ val,
                                                     const double2* __restrict__ x, int64_t nrows,
-                                                    const double2* __restrict__ yfar,
+                                                    const double2* __restrict__ yfar, int64_t n2,
                                                     const int* __restrict__ s0_ptr,
-                                                    const int* __restrict__ s0_reps, int use_near,
+                                                    const int* __restrict__ s0_reps, int use_near, int ncol,
                                                     double2* __restrict__ y) {
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     if (row >= nrows) return;
-    double2 acc = make_double2(0, 0);
-    if (use_near) {
-        const int64_t b = row_ptr[row], e = row_ptr[row + 1];
-        for (int64_t idx = b + lane; idx < e; idx += 64) acc = cfma(val[idx], x[col[idx]], acc);
-    }
+    const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+    for (int c0 = 0; c0 < ncol; c0 += SPMV_RB) {
+        double2 acc[SPMV_RB];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        acc.x += __shfl_xor(acc.x, off, 64);
-        acc.y += __shfl_xor(acc.y, off, 64);
-    }
-    if (lane == 0) {
-        if (yfar) {
-            if (s0_ptr) {
-                for (int r = s0_ptr[row]; r < s0_ptr[row + 1]; ++r) acc = cadd(acc, yfar[s0_reps[r]]);
-            } else {
-                acc = cadd(acc, yfar[row]);
+        for (int cb = 0; cb < SPMV_RB; ++cb) acc[cb] = make_double2(0, 0);
+        if (use_near) {
+            for (int64_t idx = b + lane; idx < e; idx += 64) {
+                const double2 v = val[idx];
+                const int64_t cc = col[idx];
+#pragma unroll
+                for (int cb = 0; cb < SPMV_RB; ++cb)
+                    if (c0 + cb < ncol) acc[cb] = cfma(v, x[int64_t(c0 + cb) * nrows + cc], acc[cb]);
             }
         }
-        y[row] = acc;
+#pragma unroll
+        for (int cb = 0; cb < SPMV_RB; ++cb)
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                acc[cb].x += __shfl_xor(acc[cb].x, off, 64);
+                acc[cb].y += __shfl_xor(acc[cb].y, off, 64);
+            }
+        if (lane == 0) {
+#pragma unroll
+            for (int cb = 0; cb < SPMV_RB; ++cb) {
+                const int r = c0 + cb;
+                if (r >= ncol) continue;
+                double2 a = acc[cb];
+                if (yfar) {
+                    if (s0_ptr) {
+                        for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q) a = cadd(a, yfar[r * n2 + s0_reps[q]]);
+                    } else {
+                        a = cadd(a, yfar[r * n2 + row]);
+                    }
+                }
+                y[int64_t(r) * nrows + row] = a;
+            }
+        }
     }
 }
 
@@ -1566,28 +1639,34 @@ igb_status assemble_far_device(igb_op op, hipStream_t s) {
     return IGB_OK;
 }
 
-igb_status alloc_work(igb_op op, int nrhs) {
-    (void)nrhs;
+igb_status alloc_work(igb_op op, int ncol) {
     size_t* acct = &op->dev_bytes;
     igb_status st;
+    if (!op->d_cluoff.ptr) {
+        // cluster offsets are needed on the device by the tree kernels
+        if ((st = upload(op->d_cluoff, op->clu_off.data(), op->clu_off.size(), acct))) return st;
+    }
+    if (ncol <= op->work_cols) return IGB_OK;
     const int nq = op->nq;
     const bool hard = op->bc == IGB_HARD;
     const int kinds = hard ? 3 : 1, nvec = hard ? 10 : 1;
-    if (!op->d_xhat.ptr) {
-        if ((st = alloc(op->d_xhat, size_t(kinds) * op->nclusters * nq * sizeof(double2), acct))) return st;
-        if ((st = alloc(op->d_yhat, size_t(kinds) * op->nclusters * nq * sizeof(double2), acct))) return st;
-        if (hard && (st = alloc(op->d_yraw, size_t(nvec) * op->nclusters * nq * sizeof(double2), acct))) return st;
-        if ((st = alloc(op->d_part, std::max<size_t>(1, op->chunk_len.size()) * nvec * nq * sizeof(double2), acct)))
-            return st;
-        if ((st = alloc(op->d_yfar, size_t(op->geom->n2) * sizeof(double2), acct))) return st;
-        if ((st = alloc(op->d_x2, size_t(op->geom->n2) * sizeof(double2), acct))) return st;
-        const int64_t w = (int64_t(1) << op->d) + op->geom->p;
-        if ((st = alloc(op->d_leafbuf,
-                        size_t(kinds) * clusters_on_level(op->geom->npatch, op->L) * w * w * sizeof(double2), acct)))
-            return st;
-        // cluster offsets are needed on the device by m2m / l2l
-        if ((st = upload(op->d_cluoff, op->clu_off.data(), op->clu_off.size(), acct))) return st;
+    for (igb::DevBuf* b : {&op->d_xhat, &op->d_yhat, &op->d_yraw, &op->d_part, &op->d_yfar, &op->d_x2, &op->d_leafbuf}) {
+        *acct -= std::min(*acct, b->bytes);
+        b->release();
     }
+    const size_t C = size_t(ncol);
+    if ((st = alloc(op->d_xhat, C * kinds * op->nclusters * nq * sizeof(double2), acct))) return st;
+    if ((st = alloc(op->d_yhat, C * kinds * op->nclusters * nq * sizeof(double2), acct))) return st;
+    if (hard && (st = alloc(op->d_yraw, C * nvec * op->nclusters * nq * sizeof(double2), acct))) return st;
+    if ((st = alloc(op->d_part, C * std::max<size_t>(1, op->chunk_len.size()) * nvec * nq * sizeof(double2), acct)))
+        return st;
+    if ((st = alloc(op->d_yfar, C * op->geom->n2 * sizeof(double2), acct))) return st;
+    if ((st = alloc(op->d_x2, C * op->geom->n2 * sizeof(double2), acct))) return st;
+    const int64_t w = (int64_t(1) << op->d) + op->geom->p;
+    if ((st = alloc(op->d_leafbuf, C * kinds * clusters_on_level(op->geom->npatch, op->L) * w * w * sizeof(double2),
+                    acct)))
+        return st;
+    op->work_cols = ncol;
     return IGB_OK;
 }
 
@@ -1603,112 +1682,120 @@ igb_status timer_mark(igb_op op, int slot, hipStream_t s) {
     return IGB_OK;
 }
 
+// columns per coupling workgroup: the soft kernel keeps 8 accumulators per
+// lane, the hard one 10 per column
 template <int NT, class CT>
-static void launch_m2l_t(igb_op op, const CT* coup, double2* xh, int64_t ks, hipStream_t s) {
+static void launch_m2l_t(igb_op op, const CT* coup, double2* xh, int64_t ks, int ncol, hipStream_t s) {
     const int64_t nchunk = int64_t(op->chunk_len.size());
-    if (op->bc == IGB_HARD)
-        hipLaunchKernelGGL((m2l_hard_chunks<NT, CT>), dim3(unsigned(nchunk)), dim3(NT), 0, s, coup, xh, ks,
-                           op->d_nodes.as<double>(), op->d_far_src.as<int>(), op->d_chunk_pair.as<int64_t>(),
-                           op->d_chunk_len.as<int>(), nchunk, op->nq, op->d_part.as<double2>());
-    else
-        hipLaunchKernelGGL((m2l_chunks<NT, CT>), dim3(unsigned(nchunk)), dim3(NT), 0, s, coup, xh,
+    if (op->bc == IGB_HARD) {
+        constexpr int RB = 2;
+        hipLaunchKernelGGL((m2l_hard_chunks<NT, CT, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
+                           dim3(NT), 0, s, coup, xh, ks, op->d_nodes.as<double>(), op->d_far_src.as<int>(),
+                           op->d_chunk_pair.as<int64_t>(), op->d_chunk_len.as<int>(), nchunk, op->nq, ncol,
+                           op->d_part.as<double2>());
+    } else if (ncol == 1) {
+        hipLaunchKernelGGL((m2l_chunks<NT, CT, 1>), dim3(unsigned(nchunk), 1u), dim3(NT), 0, s, coup, xh,
                            op->d_far_src.as<int>(), op->d_chunk_pair.as<int64_t>(), op->d_chunk_len.as<int>(),
-                           nchunk, op->nq, op->d_part.as<double2>());
+                           nchunk, op->nq, ncol, op->d_part.as<double2>());
+    } else {
+        constexpr int RB = 8;
+        hipLaunchKernelGGL((m2l_chunks<NT, CT, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)), dim3(NT),
+                           0, s, coup, xh, op->d_far_src.as<int>(), op->d_chunk_pair.as<int64_t>(),
+                           op->d_chunk_len.as<int>(), nchunk, op->nq, ncol, op->d_part.as<double2>());
+    }
 }
 
 template <int NT>
-static void launch_m2l_nt(igb_op op, bool low, double2* xh, int64_t ks, hipStream_t s) {
+static void launch_m2l_nt(igb_op op, bool low, double2* xh, int64_t ks, int ncol, hipStream_t s) {
     if (!low)
-        launch_m2l_t<NT>(op, op->d_coupling.as<double2>(), xh, ks, s);
+        launch_m2l_t<NT>(op, op->d_coupling.as<double2>(), xh, ks, ncol, s);
     else if (op->prm.precision == IGB_MIX_FP32)
-        launch_m2l_t<NT>(op, op->d_coupling_lo.as<float2>(), xh, ks, s);
+        launch_m2l_t<NT>(op, op->d_coupling_lo.as<float2>(), xh, ks, ncol, s);
     else
-        launch_m2l_t<NT>(op, op->d_coupling_lo.as<bf16x2>(), xh, ks, s);
+        launch_m2l_t<NT>(op, op->d_coupling_lo.as<bf16x2>(), xh, ks, ncol, s);
 }
 
-static igb_status launch_m2l(igb_op op, double2* xh, int64_t ks, bool low, hipStream_t s) {
-    if (op->nq <= 64) launch_m2l_nt<64>(op, low, xh, ks, s);
-    else launch_m2l_nt<128>(op, low, xh, ks, s);
+static igb_status launch_m2l(igb_op op, double2* xh, int64_t ks, bool low, int ncol, hipStream_t s) {
+    if (op->nq <= 64) launch_m2l_nt<64>(op, low, xh, ks, ncol, s);
+    else launch_m2l_nt<128>(op, low, xh, ks, ncol, s);
     IGB_HIP(hipGetLastError());
     return IGB_OK;
 }
 
-igb_status matvec_device(igb_op op, const double* x, double* y, int nrhs, int parts, hipStream_t s) {
+static inline unsigned blocks_for(int64_t n, int t) { return unsigned((n + t - 1) / t); }
+
+igb_status matvec_device(igb_op op, const double* x, double* y, int ncol, int parts, hipStream_t s) {
     const bool low = (parts & IGB_MV_LOWPREC) != 0;
-    if (nrhs != 1) {
-        set_error("h2_matvec: this build applies one column per call");
-        return IGB_ERR_UNSUPPORTED;
-    }
     igb_status st;
-    if ((st = alloc_work(op, nrhs))) return st;
+    if ((st = alloc_work(op, ncol))) return st;
     igb_geom g = op->geom;
     const int q = op->q, nq = op->nq, L = op->L;
     const bool hard = op->bc == IGB_HARD;
     const double2* X = reinterpret_cast<const double2*>(x);
     double2* Y = reinterpret_cast<double2*>(y);
-    const int64_t* clu_off = op->d_cluoff.as<int64_t>();
     double2* xh = op->d_xhat.as<double2>();
     double2* yh = op->d_yhat.as<double2>();
+    const int64_t N = op->N;
     const bool far = (parts & IGB_PART_FAR) && op->nfar > 0;
     if (far) {
         const double2* x2 = X;
         if (hard) {
-            hipLaunchKernelGGL(glue_gather, dim3(unsigned((g->n2 + 255) / 256)), dim3(256), 0, s,
-                               op->d_s2_to_s0.as<int>(), X, op->d_x2.as<double2>(), g->n2);
+            hipLaunchKernelGGL(glue_gather, dim3(blocks_for(g->n2 * ncol, 256)), dim3(256), 0, s,
+                               op->d_s2_to_s0.as<int>(), X, N, op->d_x2.as<double2>(), g->n2, ncol);
             x2 = op->d_x2.as<double2>();
         }
         const int kinds = hard ? 3 : 1;
-        const int64_t ks = op->nclusters * nq;  // stride between moment kinds
+        const int64_t ks = op->nclusters * nq * ncol;  // stride between moment kinds
         const int du[3] = {0, 1, 0}, dv[3] = {0, 0, 1};
         const int64_t nleaf = clusters_on_level(g->npatch, L);
         const int64_t stride_kind = int64_t(1 << L) * (q + 1) * ((1 << op->d) + g->p);
+        const unsigned cblk = unsigned((ncol + TCB - 1) / TCB);
         if ((st = timer_mark(op, 2, s))) return st;
         for (int kd = 0; kd < kinds; ++kd) {
-            hipLaunchKernelGGL(leaf_moments, dim3(unsigned((nleaf * nq + 255) / 256)), dim3(256), 0, s, x2,
+            hipLaunchKernelGGL(leaf_moments, dim3(blocks_for(nleaf * nq * ncol, 256)), dim3(256), 0, s, x2, g->n2,
                                op->d_m1.as<double>(), q, op->d, g->p, L, g->k, op->clu_off[L], nleaf, xh + kd * ks,
-                               du[kd], dv[kd], stride_kind);
+                               du[kd], dv[kd], stride_kind, ncol);
             for (int l = L - 1; l >= 0; --l) {
                 const int64_t nc = clusters_on_level(g->npatch, l);
-                hipLaunchKernelGGL(m2m_wg, dim3(unsigned(nc)), dim3(TREE_THREADS), 0, s, op->d_T.as<double>(), q, l,
-                                   op->clu_off[l], op->clu_off[l + 1], xh + kd * ks);
+                hipLaunchKernelGGL(m2m_wg, dim3(unsigned(nc), cblk), dim3(TREE_THREADS), 0, s, op->d_T.as<double>(), q,
+                                   l, op->clu_off[l], op->clu_off[l + 1], xh + kd * ks, ncol);
             }
         }
         if ((st = timer_mark(op, 2, s))) return st;
-        const int64_t nchunk = int64_t(op->chunk_len.size());
         if ((st = timer_mark(op, 0, s))) return st;
-        if ((st = launch_m2l(op, xh, ks, low && op->prm.precision != IGB_FP64, s))) return st;
+        if ((st = launch_m2l(op, xh, ks, low && op->prm.precision != IGB_FP64, ncol, s))) return st;
         if ((st = timer_mark(op, 0, s))) return st;
         if ((st = timer_mark(op, 3, s))) return st;
         const int nvec = hard ? 10 : 1;
         double2* red_out = hard ? op->d_yraw.as<double2>() : yh;
-        hipLaunchKernelGGL(m2l_reduce, dim3(unsigned((op->nclusters * nq * nvec + 255) / 256)), dim3(256), 0, s,
-                           op->d_part.as<double2>(), op->d_tgt_chunk_ptr.as<int>(), op->nclusters, nq, nvec, red_out);
+        const int64_t per = int64_t(nvec) * nq * ncol;
+        hipLaunchKernelGGL(m2l_reduce, dim3(blocks_for(op->nclusters * per, 256)), dim3(256), 0, s,
+                           op->d_part.as<double2>(), op->d_tgt_chunk_ptr.as<int>(), op->nclusters, per, red_out);
         if (hard)
-            hipLaunchKernelGGL(m2l_finalize_hard, dim3(unsigned((op->nclusters * nq + 255) / 256)), dim3(256), 0, s,
+            hipLaunchKernelGGL(m2l_finalize_hard, dim3(blocks_for(op->nclusters * nq * ncol, 256)), dim3(256), 0, s,
                                op->d_yraw.as<double2>(), op->d_nodes.as<double>(), op->nclusters, nq, op->kappa,
-                               op->eta, ks, yh);
+                               op->eta, ks, ncol, yh);
         const int w = (1 << op->d) + g->p;
         for (int kd = 0; kd < kinds; ++kd) {
             for (int l = 0; l < L; ++l) {
                 const int64_t nc = clusters_on_level(g->npatch, l);
-                hipLaunchKernelGGL(l2l_wg, dim3(unsigned(nc)), dim3(TREE_THREADS), 0, s, op->d_T.as<double>(), q, l,
-                                   op->clu_off[l], op->clu_off[l + 1], yh + kd * ks);
+                hipLaunchKernelGGL(l2l_wg, dim3(unsigned(nc), cblk), dim3(TREE_THREADS), 0, s, op->d_T.as<double>(), q,
+                                   l, op->clu_off[l], op->clu_off[l + 1], yh + kd * ks, ncol);
             }
-            hipLaunchKernelGGL(back_project_leaf, dim3(unsigned(nleaf)), dim3(TREE_THREADS), 0, s, yh + kd * ks,
-                               op->d_m1.as<double>(), q, w, L, op->clu_off[L], du[kd], dv[kd], stride_kind,
-                               op->d_leafbuf.as<double2>() + kd * nleaf * w * w);
+            hipLaunchKernelGGL(back_project_leaf, dim3(unsigned(nleaf), unsigned(ncol)), dim3(TREE_THREADS), 0, s,
+                               yh + kd * ks, op->d_m1.as<double>(), q, w, L, op->clu_off[L], du[kd], dv[kd],
+                               stride_kind, ncol, op->d_leafbuf.as<double2>() + kd * nleaf * ncol * w * w);
         }
-        hipLaunchKernelGGL(leaf_gather, dim3(unsigned((g->n2 + 255) / 256)), dim3(256), 0, s,
-                           op->d_leafbuf.as<double2>(), op->d, g->p, L, g->k, g->npatch, kinds,
+        hipLaunchKernelGGL(leaf_gather, dim3(blocks_for(g->n2 * ncol, 256)), dim3(256), 0, s,
+                           op->d_leafbuf.as<double2>(), op->d, g->p, L, g->k, g->npatch, kinds, ncol,
                            op->d_yfar.as<double2>());
         if ((st = timer_mark(op, 3, s))) return st;
     }
-    const int64_t N = op->N;
     if ((st = timer_mark(op, 1, s))) return st;
-    hipLaunchKernelGGL(spmv_combine, dim3(unsigned((N * 64 + 255) / 256)), dim3(256), 0, s,
-                       op->d_rowptr.as<int64_t>(), op->d_col.as<int>(), op->d_val.as<double2>(), X, N,
-                       far ? op->d_yfar.as<double2>() : nullptr, hard ? op->d_s0_ptr.as<int>() : nullptr,
-                       hard ? op->d_s0_reps.as<int>() : nullptr, (parts & IGB_PART_NEAR) ? 1 : 0, Y);
+    hipLaunchKernelGGL(spmv_combine, dim3(blocks_for(N * 64, 256)), dim3(256), 0, s, op->d_rowptr.as<int64_t>(),
+                       op->d_col.as<int>(), op->d_val.as<double2>(), X, N, far ? op->d_yfar.as<double2>() : nullptr,
+                       g->n2, hard ? op->d_s0_ptr.as<int>() : nullptr, hard ? op->d_s0_reps.as<int>() : nullptr,
+                       (parts & IGB_PART_NEAR) ? 1 : 0, ncol, Y);
     IGB_HIP(hipGetLastError());
     if ((st = timer_mark(op, 1, s))) return st;
     return IGB_OK;
