@@ -66,6 +66,7 @@ def main():
     ap.add_argument("--workload", default="sphere_m5_p2_k8", choices=sorted(WORKLOADS))
     ap.add_argument("--matvecs", type=int, default=50, help="matvec-only timing loop length")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--block", type=int, default=16, help="directions per served block (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
@@ -98,27 +99,58 @@ def main():
 
     d = np.array([[0.0, 0.0, 1.0]])
     obs = I.fibonacci_directions(64)
-    coeff = torch.zeros(n, dtype=torch.complex128, device=dev)
-    uinf = torch.zeros(64, dtype=torch.complex128, device=dev)
 
-    def step():
-        sinfo, st = op.cfie_solve(d, coeff, tol=w["tol"], restart=30, maxit=2000)
-        op.farfield(coeff, obs, uinf)
-        return sinfo
+    def run_solves(o, dirs, steps, warmup):
+        """Timed lockstep solves of all `dirs` + far fields; returns rates."""
+        nd = len(dirs)
+        coeff = torch.zeros((nd, o.n), dtype=torch.complex128, device=dev)
+        uinf = torch.zeros((nd, 64), dtype=torch.complex128, device=dev)
+        for _ in range(warmup):
+            o.cfie_solve(dirs, coeff, tol=w["tol"], restart=30, maxit=2000)
+            o.farfield(coeff, obs, uinf, ndir=nd)
+        torch.cuda.synchronize()
+        mv, its, relt, refs = 0, 0, 0.0, 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            si, st = o.cfie_solve(dirs, coeff, tol=w["tol"], restart=30, maxit=2000)
+            o.farfield(coeff, obs, uinf, ndir=nd)
+            mv += si.matvecs
+            its = si.iters
+            relt = max(relt, si.relres_true)
+            refs = si.refinements
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        return dict(T=T, matvecs_per_s=mv / T, solves_per_s=steps * nd / T, ms_per_step=T / steps * 1e3,
+                    gmres_iters=its, relres_true=relt, refinements=refs, coeff=coeff, uinf=uinf)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    mv_total, iters = 0, []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        si = step()
-        mv_total += si.matvecs
-        iters.append(si.iters)
-    torch.cuda.synchronize()
-    T = time.perf_counter() - t0
-    value = mv_total / T
-    relres_true = si.relres_true
+    plain = run_solves(op, d, args.steps, args.warmup)
+    value = plain["matvecs_per_s"]
+    T = plain["T"]
+    iters = [plain["gmres_iters"]]
+    relres_true = plain["relres_true"]
+    uinf = plain["uinf"][0]
+
+    # served forms: a block of incident directions in lockstep, fp64 and mixed precision
+    served = {}
+    if args.block > 0:
+        dirs_b = I.random_directions(1, args.block)
+        ref_coeff = None
+        for prec_name, prec in (("fp64", B.FP64), ("fp32", B.MIX_FP32), ("bf16", B.MIX_BF16)):
+            o = op if prec == B.FP64 else B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"],
+                                                      kcap=w["kcap"], leaf_depth=w["leaf_depth"], precision=prec)
+            r = run_solves(o, dirs_b, max(1, args.steps // 2), 1)
+            c = r.pop("coeff").cpu().numpy()
+            r.pop("uinf")
+            if ref_coeff is None:
+                ref_coeff = c
+            r["solution_rel_diff_vs_fp64_block"] = float(np.abs(c - ref_coeff).max() / np.abs(ref_coeff).max())
+            r["speedup_matvecs_vs_plain_fp64"] = r["matvecs_per_s"] / value
+            r["speedup_solves_vs_plain_fp64"] = r["solves_per_s"] / plain["solves_per_s"]
+            r.pop("T")
+            served[f"{prec_name}_block{args.block}"] = r
+            if o is not op:
+                del o
+            torch.cuda.empty_cache()
 
     # matvec-only loop with HIP-event kernel timing on the launch stream
     x = torch.from_numpy(I.random_complex(12345, n)).to(dev)
@@ -139,6 +171,30 @@ def main():
     op.h2_matvec(x, y)
     torch.cuda.synchronize()
     yv = y.cpu().numpy()
+
+    # block matvec (the served form's dominant pass): same couplings, args.block columns
+    block_mv = None
+    if args.block > 0:
+        xb = torch.from_numpy(I.random_complex(777, (args.block, n))).to(dev)
+        yb = torch.zeros_like(xb)
+        op.h2_matvec(xb, yb, nrhs=args.block)
+        torch.cuda.synchronize()
+        op.profile(True)
+        nb = max(5, args.matvecs // 5)
+        t0 = time.perf_counter()
+        for _ in range(nb):
+            op.h2_matvec(xb, yb, nrhs=args.block)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / nb
+        bn, bms = op.kernel_time("m2l")
+        op.profile(False)
+        b_avg = bms / max(bn, 1) / 1e3
+        b_flops = 8.0 * info.far_pairs * info.nq * info.nq * args.block
+        b_bytes = info.far_pairs * info.nq * info.nq * 16 + info.far_pairs * info.nq * 16 * args.block
+        block_mv = {"ncol": args.block, "column_matvecs_per_s": args.block / tb, "m2l_avg_ms": b_avg * 1e3,
+                    "m2l_GBps": b_bytes / b_avg / 1e9, "m2l_TFLOPs": b_flops / b_avg / 1e12,
+                    "m2l_frac_fp64_peak": b_flops / b_avg / 78.6e12, "m2l_frac_hbm_peak": b_bytes / b_avg / 8e12}
+        del xb, yb
 
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
@@ -195,7 +251,7 @@ def main():
                    "q": w["q"], "eta_adm": w["eta_adm"], "kcap": w["kcap"], "leaf_depth": w["leaf_depth"],
                    "rhs": 1, "gmres": f"restart 30, tol {w['tol']}", "far_pairs": info.far_pairs,
                    "nnz_near": info.nnz},
-        "solves_per_s": args.steps / T,
+        "solves_per_s": plain["solves_per_s"],
         "gmres_iters": iters[-1],
         "relres_true": relres_true,
         "matvec_only_per_s": 1.0 / t_mv,
@@ -204,6 +260,8 @@ def main():
         "assembly_far_ms": info.assembly_far_ms,
         "kernel_ms": {"m2l": m2l_ms / max(m2l_n, 1), "spmv": spmv_ms / max(spmv_n, 1),
                       "upward": up_ms / max(up_n, 1), "downward": dn_ms / max(dn_n, 1)},
+        "served": served,
+        "block_matvec": block_mv,
         "err_matvec_vs_oracle_rows": err_oracle,
         "err_farfield_vs_mie": err_mie,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

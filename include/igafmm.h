@@ -76,7 +76,9 @@ typedef enum { IGB_FP64 = 0, IGB_MIX_FP32 = 1, IGB_MIX_BF16 = 2 } igb_prec;
  *   bc         IGB_SOFT: (1/2 M + K* - i eta V) on S^2 (Sec. 4.1, system D2N);
  *              IGB_HARD: (1/2 M - K - i eta W) on S^0 (Sec. 4.1, system N2D, W
  *              regularised as in Sec. 4.3)
- *   eta_c      CFIE coupling eta (Sec. 2); <= 0 selects kappa (soft) / 1/kappa (hard)
+ *   eta_c      CFIE coupling eta (Sec. 2, any real value != 0); 0 selects kappa (soft)
+ *              and -1/kappa (hard), for which every mode of the sphere operators
+ *              has a positive real part
  *   q          interpolation degree per reference direction (q+1 Chebyshev
  *              points of the first kind, Sec. 4.4), 1 <= q <= 10
  *   eta_adm    admissibility: dist(B_t,B_s) >= eta_adm * max(diam B_t, diam B_s)
@@ -104,7 +106,7 @@ typedef struct {
 typedef struct {
     double tol;      /* relative residual ||b - A x|| / ||b||, Euclidean on coefficients */
     int restart;     /* GMRES restart length (the paper uses 30, Sec. 5.1)              */
-    int maxit;       /* maximal number of Arnoldi steps per column                      */
+    int maxit;       /* maximal number of Arnoldi steps per column (over all refinements) */
     double inner_tol;/* mixed precision: lower bound of the inner relative tolerance;
                         <= 0 selects 0 (fp32) / 1e-3 (bf16)                             */
     int refine_max;  /* mixed precision: maximal refinement steps (<= 0: 10)           */
@@ -131,6 +133,8 @@ typedef struct {
     int64_t near_elem_pairs;/* element pairs integrated by quadrature              */
     int64_t nnz;            /* nonzeros of the near-field matrix                    */
     int64_t device_bytes;   /* device memory held by the operator                   */
+    int64_t estimated_bytes;/* device memory the operator needs (the budget check's
+                               size model; also on host-only contexts)             */
     double assembly_near_ms, assembly_far_ms;
 } igb_op_info;
 

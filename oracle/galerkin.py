@@ -34,7 +34,8 @@ Readings of the paper taken here (listed in the design doc):
 * far-field pattern  u_s ~ e^{i kappa |x|}/|x| u_inf, hence
                      soft u_inf(x) = -(1/4 pi) int e^{-i kappa x.y} t(y) dsigma,
                      hard u_inf(x) = -(i kappa/4 pi) int (x.n_y) e^{-i kappa x.y} g(y) dsigma;
-* default CFIE coupling eta_c = kappa (soft), 1/kappa (hard).
+* default CFIE coupling eta_c = kappa (soft), -1/kappa (hard); any real eta != 0
+  gives a uniquely solvable system.
 
 Quadrature (the paper defers to its references): tensor Gauss for regular
 pairs with the order chosen from centre distance / diameter, Duffy-type rules
@@ -60,7 +61,11 @@ OPS_HARD = ("K", "W")
 
 
 def default_eta(kappa: float, bc: str) -> float:
-    return kappa if bc == "soft" else 1.0 / kappa
+    """CFIE coupling (Sec. 2 gives none): eta = kappa for the sound-soft system
+    and eta = -1/kappa for the sound-hard one, i.e. the combination
+    (1/2 - K) + (i/kappa) W.  On the sphere every mode of these operators has a
+    positive real part (closed-form symbols), which is what restarted GMRES needs."""
+    return kappa if bc == "soft" else -1.0 / kappa
 
 
 # ---------------------------------------------------------------------------
@@ -158,7 +163,7 @@ class DenseBEM:
         self.disc = Discretization(patches, p, m)
         self.kappa = float(kappa)
         self.bc = bc
-        self.eta = default_eta(kappa, bc) if eta is None else float(eta)
+        self.eta = default_eta(kappa, bc) if eta is None or eta == 0 else float(eta)
         self.rules = rules or PairRules()
         self.corners = self.disc.element_corners()
         self.centers = self.disc.element_centers()

@@ -17,6 +17,11 @@ LIB_PATH = os.path.join(HERE, "libigafmm.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2306_11324_amd.build`")
+# PyTorch ships its own HIP runtime under the same soname as the system one.
+# Loading torch first makes the library bind to that runtime, so the process
+# holds exactly one HIP runtime (two copies do not see the same devices).
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 IGB_OK = 0
@@ -26,6 +31,7 @@ SOFT, HARD = 0, 1
 FP64, MIX_FP32, MIX_BF16 = 0, 1, 2
 PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
 MV_LOWPREC = 4
+CONTEXT_STREAM = "context"   # pass as stream=...: order the call on the context's own stream
 
 
 class IgbPatch(C.Structure):
@@ -54,7 +60,7 @@ class IgbOpInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("nelem", C.c_int64), ("n2", C.c_int64), ("nclusters", C.c_int64),
                 ("leaf_level", C.c_int), ("nq", C.c_int), ("far_pairs", C.c_int64),
                 ("far_per_level", C.c_int64 * 16), ("near_elem_pairs", C.c_int64), ("nnz", C.c_int64),
-                ("device_bytes", C.c_int64), ("assembly_near_ms", C.c_double),
+                ("device_bytes", C.c_int64), ("estimated_bytes", C.c_int64), ("assembly_near_ms", C.c_double),
                 ("assembly_far_ms", C.c_double)]
 
 
@@ -116,6 +122,8 @@ def _dptr(t, n_complex=None):
 
 
 def _stream(stream):
+    if stream == CONTEXT_STREAM:
+        return C.c_void_p(None)
     if stream is None:
         import torch
         return C.c_void_p(torch.cuda.current_stream().cuda_stream)

@@ -174,7 +174,7 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
     op->prm = *prm;
     op->bc = prm->bc;
     op->kappa = prm->kappa;
-    op->eta = prm->eta_c > 0 ? prm->eta_c : (prm->bc == IGB_SOFT ? prm->kappa : 1.0 / prm->kappa);
+    op->eta = prm->eta_c != 0 ? prm->eta_c : (prm->bc == IGB_SOFT ? prm->kappa : -1.0 / prm->kappa);
     op->q = prm->q;
     op->nq = (prm->q + 1) * (prm->q + 1);
     op->N = prm->bc == IGB_SOFT ? g->n2 : g->n0;
@@ -189,6 +189,10 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
     size_t need = size_t(op->nfar) * op->nq * op->nq * coup_elem * (prm->bc == IGB_HARD ? 2 : 1) + size_t(op->nnz) * 20 + size_t(op->N + 1) * 8 +
                   size_t(op->nclusters) * op->nq * (16 * 8 + 32) + op->near_src.size() * 4 +
                   std::min<size_t>(op->near_src.size(), size_t(1) << 22) * nl * nl * 16;
+    // matvec work vectors for one column and a GMRES(30) basis
+    need += size_t(op->nclusters) * op->nq * 16 * (prm->bc == IGB_HARD ? 16 : 2) + size_t(g->n2) * 16 * 4 +
+            size_t(35) * op->N * 16;
+    op->estimated_bytes = need;
     if (!budget_ok(ctx, need)) {
         set_error("assemble_nearfield: HBM budget exceeded (%zu + %zu > %zu bytes)", ctx->used, need, ctx->budget);
         delete op;
@@ -240,6 +244,7 @@ igb_status igb_op_get_info(igb_op op, igb_op_info* info) {
     info->near_elem_pairs = int64_t(op->near_src.size());
     info->nnz = op->nnz;
     info->device_bytes = int64_t(op->dev_bytes);
+    info->estimated_bytes = int64_t(op->estimated_bytes);
     info->assembly_near_ms = op->t_assembly_near;
     info->assembly_far_ms = op->t_assembly_far;
     return IGB_OK;

@@ -133,6 +133,7 @@ struct igb_op_s {
     int krylov_cols = 0;
     int work_cols = 0;   // columns the matvec work buffers are sized for
     double t_assembly_near = 0, t_assembly_far = 0;
+    size_t estimated_bytes = 0;
     // per-kernel timing: 0 m2l, 1 spmv, 2 upward, 3 downward
     bool profile = false;
     KernelTimer timers[4];

@@ -170,9 +170,9 @@ igb_status norms(const double2* v, int64_t n, int C, double* dev_tmp, std::vecto
 // Lockstep restarted GMRES for C columns: every column runs its own Arnoldi
 // process and Givens rotations; the operator is applied to all columns at once.
 // X = 0 initially; column c stops when its recursive relative residual reaches
-// tol[c] (or after maxit Arnoldi steps).  Columns never interact, so a column's
+// tol[c] (or after maxit[c] Arnoldi steps).  Columns never interact, so a column's
 // iterates do not depend on which other columns share the batch.
-igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, int maxit,
+igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, const std::vector<int>& maxit,
                        const std::vector<double>& tol, int mvflags, hipStream_t s, std::vector<ColumnResult>& res) {
     const int64_t n = Wk.n;
     const int m = Wk.m, C = Wk.C;
@@ -194,7 +194,7 @@ igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, 
     std::vector<double2> hh(size_t(2) * (m + 1) * C), yd;
     std::vector<double> sc(C);
     std::vector<int> jc(C);
-    auto active = [&](int c) { return !res[c].converged && res[c].iters < maxit; };
+    auto active = [&](int c) { return !res[c].converged && res[c].iters < maxit[c]; };
     for (;;) {
         bool any = false;
         for (int c = 0; c < C; ++c) any = any || active(c);
@@ -324,7 +324,9 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
     std::vector<ColumnResult> res;
     igb_solve_info out{};
     if (!mixed) {
-        if ((st = gmres_block(op, W, B, X, maxit, std::vector<double>(C, tol), IGB_PART_ALL, s, res))) return st;
+        if ((st = gmres_block(op, W, B, X, std::vector<int>(C, maxit), std::vector<double>(C, tol), IGB_PART_ALL, s,
+                              res)))
+            return st;
     } else {
         // iterative refinement: inner GMRES on the reduced-precision far field,
         // outer residual with the fp64 operator; columns refine independently
@@ -350,31 +352,55 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
         for (int outer = 0; outer < refine_max; ++outer) {
             // inner tolerance per column: what the column still needs, at least inner_min
             std::vector<double> tin(C, 1.0);
+            std::vector<int> left(C, 0);
             bool any = false;
             for (int c = 0; c < C; ++c) {
-                if (res[c].converged) {
+                if (res[c].converged || res[c].iters >= maxit) {
                     IGB_HIP(hipMemsetAsync(R + int64_t(c) * n, 0, n * sizeof(double2), s));
                     continue;
                 }
                 any = true;
                 tin[c] = std::max(inner_min, 0.5 * tol * bnorm[c] / rnorm[c]);
+                left[c] = maxit - res[c].iters;   // maxit bounds the Arnoldi steps over all refinements
             }
             if (!any) break;
             std::vector<ColumnResult> inner;
-            if ((st = gmres_block(op, W, R, D, maxit, tin, IGB_PART_ALL | IGB_MV_LOWPREC, s, inner))) return st;
+            if ((st = gmres_block(op, W, R, D, left, tin, IGB_PART_ALL | IGB_MV_LOWPREC, s, inner))) return st;
             hipLaunchKernelGGL(cadd_to, dim3(gb), dim3(256), 0, s, D, n * C, X);
             if ((st = matvec_device(op, reinterpret_cast<const double*>(X), reinterpret_cast<double*>(R), C,
                                     IGB_PART_ALL, s)))
                 return st;
             hipLaunchKernelGGL(csub_from_multi, dim3(gb), dim3(256), 0, s, B, n * C, R);
+            std::vector<double> rprev = rnorm;
             if ((st = norms(R, n, C, W.nrm, rnorm, s))) return st;
+            std::vector<double> undo(C, 0.0);
+            bool any_undo = false;
             for (int c = 0; c < C; ++c) {
-                if (res[c].converged) continue;
+                if (res[c].converged || left[c] == 0) continue;
                 res[c].iters += inner[c].iters;
                 res[c].applications += inner[c].applications + 1;
+                if (!(rnorm[c] < rprev[c])) {
+                    // the correction did not reduce the fp64 residual: take it
+                    // back and stop refining this column
+                    undo[c] = -1.0;
+                    any_undo = true;
+                    rnorm[c] = rprev[c];
+                    res[c].iters = maxit;
+                }
                 res[c].true_rel = bnorm[c] > 0 ? rnorm[c] / bnorm[c] : 0.0;
                 res[c].relres = res[c].true_rel;
                 res[c].converged = res[c].true_rel <= tol;
+            }
+            if (any_undo) {
+                // X -= D and R = B - A X for the rejected columns (recomputed for all)
+                IGB_HIP(hipMemcpyAsync(W.sc, undo.data(), C * sizeof(double), hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(cscale_multi, dim3(gb), dim3(256), 0, s, D, n, C, W.sc, D);
+                hipLaunchKernelGGL(cadd_to, dim3(gb), dim3(256), 0, s, D, n * C, X);
+                if ((st = matvec_device(op, reinterpret_cast<const double*>(X), reinterpret_cast<double*>(R), C,
+                                        IGB_PART_ALL, s)))
+                    return st;
+                hipLaunchKernelGGL(csub_from_multi, dim3(gb), dim3(256), 0, s, B, n * C, R);
+                IGB_HIP(hipStreamSynchronize(s));
             }
             ++out.refinements;
         }

@@ -210,7 +210,8 @@ igb_status tree_build(igb_op op) {
 //   bits 0..3  : 0 regular, 1 common vertex, 2 common edge, 4 identical
 //   bits 8..11 : Gauss order of the regular rule
 //   bits 16..18: square symmetry of the test element, 20..22: of the trial element
-// Regular order from the ratio centre distance / larger box diagonal.
+// Regular order from the ratio centre distance / larger box diagonal, raised
+// with kappa * diagonal.
 igb_status near_classify(igb_op op) {
     igb_geom g = op->geom;
     const int64_t E = g->nelem;
@@ -249,8 +250,14 @@ igb_status near_classify(igb_op op) {
             } else if (shared == 0) {
                 double d2 = 0;
                 for (int c = 0; c < 3; ++c) d2 += (ctr[3 * e + c] - ctr[3 * f + c]) * (ctr[3 * e + c] - ctr[3 * f + c]);
-                double ratio = std::sqrt(d2) / std::max(diag[e], diag[f]);
+                const double dmax = std::max(diag[e], diag[f]);
+                double ratio = std::sqrt(d2) / dmax;
                 int n = ratio >= 6.0 ? 4 : ratio >= 3.0 ? 5 : ratio >= 1.8 ? 6 : 7;
+                // one more point per direction for each doubling of kappa * diameter
+                // beyond 1.5 (oscillation of e^{i kappa r} across the pair)
+                const double kd = op->kappa * dmax;
+                n += (kd >= 1.5) + (kd >= 3.0) + (kd >= 6.0);
+                n = std::min(n, 7);
                 kind = n << 8;
             } else {
                 set_error("assemble_nearfield: elements share %d corners", shared);

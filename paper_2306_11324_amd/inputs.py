@@ -239,3 +239,36 @@ def geometry_for(w: dict) -> list[Patch]:
     if w["geometry"] == "sphere":
         return sphere_patches()
     return star_patches(w.get("seed", 0), star_geometry_level(w["m"]))
+
+
+# ---------------------------------------------------------------------------
+# Scattering request stream: Poisson arrivals, each request a seeded star-shaped
+# scatterer with its own level, wavenumber, incidence directions and boundary
+# condition.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class Request:
+    rid: int
+    arrival: float          # seconds after the stream starts
+    seed: int               # star scatterer seed
+    m: int
+    kappa: float
+    bc: str                 # "soft" | "hard"
+    dirs: np.ndarray        # (ndir, 3) unit incident directions
+
+
+def request_stream(n: int, rate: float, seed: int = 3, m_values=(3, 4, 5, 6), kappa_range=(1.0, 32.0),
+                   max_dirs: int = 16) -> list[Request]:
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += rng.exponential(1.0 / rate)
+        rseed = int(rng.integers(0, 10 ** 6 + 1))
+        m = int(rng.choice(m_values))
+        kappa = float(rng.uniform(*kappa_range))
+        ndir = int(rng.integers(1, max_dirs + 1))
+        bc = "soft" if rng.integers(0, 2) == 0 else "hard"
+        out.append(Request(i, t, rseed, m, kappa, bc, random_directions(rseed, ndir)))
+    return out

@@ -1,0 +1,217 @@
+"""Continuous-batching server for scattering requests.
+
+Requests (a scatterer, a wavenumber, incident directions, a boundary condition)
+arrive over time.  Each request is admitted when a slot is free and its device
+memory -- from the operator's size model, computed by a host-only plan before
+anything is allocated -- fits the remaining HBM budget.  Admitted requests run
+concurrently, one HIP stream per slot: geometry, operator assembly, the
+lockstep multi-direction CFIE solve (mixed precision with fp64 refinement) and
+the far field.  A request's result depends only on the request: every
+reduction in the library has a fixed order and slots share no state, so a
+request gives the same far field alone and in the mix.
+
+All numerical work runs in the HIP library; this module schedules.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import threading
+import time
+
+import numpy as np
+
+from . import binding as B
+from . import inputs as I
+
+
+@dataclasses.dataclass
+class ServeConfig:
+    slots: int = 4
+    hbm_budget: int = 200 * 10 ** 9
+    precision: int = B.MIX_BF16
+    p: int = 2
+    q: int = 8
+    eta_adm: float = 1.6
+    leaf_depth: int = 2
+    tol: float = 1e-8
+    nobs: int = 64
+    device: int = 0
+    # GMRES restart (the paper's 30 for both systems)
+    restart_soft: int = 30
+    restart_hard: int = 30
+    maxit: int = 1500        # Arnoldi steps per direction; a request that reaches it is reported unconverged
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float
+    done: float
+    n: int
+    est_bytes: int
+    iters: int
+    matvecs: int
+    relres_true: float
+    converged: int
+    uinf: np.ndarray      # (ndir, nobs)
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+def percentile(values, pct):
+    """Nearest-rank percentile."""
+    v = np.sort(np.asarray(values, dtype=float))
+    if len(v) == 0:
+        return float("nan")
+    k = max(1, int(np.ceil(pct / 100.0 * len(v))))
+    return float(v[k - 1])
+
+
+class Server:
+    """`solve_fn(req, slot)` and `estimate_fn(req)` replace the device work and
+    the size model (used to test the scheduler without a GPU)."""
+
+    def __init__(self, cfg: ServeConfig | None = None, solve_fn=None, estimate_fn=None):
+        self.cfg = cfg or ServeConfig()
+        self.obs = I.fibonacci_directions(self.cfg.nobs)
+        self.solve_fn = solve_fn
+        self.estimate_fn = estimate_fn
+        self.plan_ctx = B.Context(B.IGB_HOST_ONLY) if estimate_fn is None else None
+        self.ctxs = None
+        if solve_fn is None:
+            import torch
+            torch.cuda.init()      # initialise the runtime once, before worker threads use it
+            self.ctxs = [B.Context(self.cfg.device) for _ in range(self.cfg.slots)]
+        self.peak_reserved = 0
+
+    # -------------------------------------------------------------- pieces
+    def _patches(self, req: I.Request):
+        return I.star_patches(req.seed, I.star_geometry_level(req.m))
+
+    def _op_args(self, req: I.Request):
+        c = self.cfg
+        return dict(kappa=req.kappa, bc=B.SOFT if req.bc == "soft" else B.HARD, q=c.q, eta_adm=c.eta_adm,
+                    leaf_depth=c.leaf_depth, precision=c.precision)
+
+    def estimate(self, req: I.Request) -> int:
+        """Device bytes of the request (host-only plan: nothing is allocated)."""
+        geo = B.Geometry(self.plan_ctx, self._patches(req), req.m, self.cfg.p)
+        op = B.Operator(self.plan_ctx, geo, **self._op_args(req))
+        nd = len(req.dirs)
+        n = op.info.n
+        geom_bytes = geo.nelem * (16 * 4 * 8 + 8) + 4096
+        restart = self.cfg.restart_soft if req.bc == "soft" else self.cfg.restart_hard
+        krylov = nd * n * 16 * (restart + 8) * 2    # basis and work vectors, refinement buffers
+        return int(op.info.estimated_bytes + geom_bytes + krylov + nd * self.cfg.nobs * 16)
+
+    def solve(self, req: I.Request, ctx: B.Context):
+        import torch
+        geo = B.Geometry(ctx, self._patches(req), req.m, self.cfg.p)
+        op = B.Operator(ctx, geo, **self._op_args(req))
+        nd = len(req.dirs)
+        dev = torch.device("cuda", self.cfg.device)
+        coeff = torch.empty((nd, op.n), dtype=torch.complex128, device=dev)
+        uinf = torch.empty((nd, self.cfg.nobs), dtype=torch.complex128, device=dev)
+        restart = self.cfg.restart_soft if req.bc == "soft" else self.cfg.restart_hard
+        info, st = op.cfie_solve(req.dirs, coeff, tol=self.cfg.tol, restart=restart, maxit=self.cfg.maxit)
+        op.farfield(coeff, self.obs, uinf, ndir=nd, stream=B.CONTEXT_STREAM)
+        u = uinf.cpu().numpy()
+        n = op.n
+        del op, geo, coeff, uinf
+        return n, info, u
+
+    # -------------------------------------------------------------- serving
+    def run(self, requests, realtime: bool = True, log=None):
+        """Serve `requests` (sorted by arrival).  With realtime, a request
+        becomes visible at its arrival time; otherwise all are visible at once.
+        `log(result)` is called as each request completes.  Returns the
+        results in request order."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        estimate = self.estimate_fn or self.estimate
+        est = {r.rid: estimate(r) for r in reqs}
+        for r in reqs:
+            if est[r.rid] > self.cfg.hbm_budget:
+                raise ValueError(f"request {r.rid} needs {est[r.rid]} bytes, more than the whole budget")
+        lock = threading.Condition()
+        pending = collections.deque()
+        results = {}
+        state = {"free": self.cfg.hbm_budget, "arrived": 0, "errors": []}
+        t0 = time.perf_counter()
+
+        def now():
+            return time.perf_counter() - t0
+
+        def feeder():
+            for r in reqs:
+                if realtime:
+                    dt = r.arrival - now()
+                    if dt > 0:
+                        time.sleep(dt)
+                with lock:
+                    pending.append(r)
+                    state["arrived"] += 1
+                    lock.notify_all()
+
+        def worker(slot):
+            while True:
+                with lock:
+                    while True:
+                        pick = None
+                        for r in pending:                      # oldest request that fits
+                            if est[r.rid] <= state["free"]:
+                                pick = r
+                                break
+                        if pick is not None:
+                            pending.remove(pick)
+                            state["free"] -= est[pick.rid]
+                            self.peak_reserved = max(self.peak_reserved, self.cfg.hbm_budget - state["free"])
+                            break
+                        if state["arrived"] == len(reqs) and not pending:
+                            return
+                        lock.wait(0.05)
+                admitted = now()
+                try:
+                    if self.solve_fn is not None:
+                        n, info, u = self.solve_fn(pick, slot)
+                    else:
+                        n, info, u = self.solve(pick, self.ctxs[slot])
+                except Exception as exc:  # recorded, the stream continues
+                    with lock:
+                        state["errors"].append((pick.rid, repr(exc)))
+                        state["free"] += est[pick.rid]
+                        lock.notify_all()
+                    continue
+                done = now()
+                res = Result(pick.rid, pick.arrival, admitted, done, n, est[pick.rid], info.iters, info.matvecs,
+                             info.relres_true, info.converged, u)
+                with lock:
+                    results[pick.rid] = res
+                    state["free"] += est[pick.rid]
+                    lock.notify_all()
+                if log is not None:
+                    log(res)
+
+        threads = [threading.Thread(target=feeder, daemon=True)]
+        threads += [threading.Thread(target=worker, args=(i,), daemon=True) for i in range(self.cfg.slots)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        if state["errors"]:
+            raise RuntimeError(f"requests failed: {state['errors']}")
+        self.wall = now()
+        return [results[r.rid] for r in sorted(reqs, key=lambda r: r.rid)]
+
+    @staticmethod
+    def summary(results, wall):
+        lat = [r.latency for r in results]
+        cols = sum(r.uinf.shape[0] for r in results)
+        return {"requests": len(results), "wall_s": wall, "requests_per_s": len(results) / wall,
+                "direction_solves_per_s": cols / wall, "column_matvecs_per_s": sum(r.matvecs for r in results) / wall,
+                "p50_latency_s": percentile(lat, 50), "p99_latency_s": percentile(lat, 99),
+                "max_relres_true": max(r.relres_true for r in results),
+                "all_converged": all(r.converged == r.uinf.shape[0] for r in results)}

@@ -102,3 +102,17 @@ def test_optical_theorem_and_eta_independence_star():
     t2 = bem2.solve(d)
     u2 = bem2.farfield(t2, obs)
     assert np.abs(u2 - u).max() < 1e-3 * np.abs(u).max()
+
+
+@pytest.mark.parametrize("kappa", [1.0, 4.0, 16.0, 32.0])
+def test_default_coupling_keeps_sphere_modes_in_right_half_plane(kappa):
+    """The default couplings (soft eta = kappa, hard eta = -1/kappa) give CFIE
+    symbols 1/2 + K_n - i eta V_n and 1/2 - K_n - i eta W_n with positive real
+    parts for every degree n on the unit sphere; the opposite hard sign does
+    not (negative real parts from kappa = 2 on), which is why it is not used."""
+    n = np.arange(0, int(1.5 * kappa) + 40)
+    soft = 0.5 + mie.eig_K(n, kappa) - 1j * G.default_eta(kappa, "soft") * mie.eig_V(n, kappa)
+    hard = 0.5 - mie.eig_K(n, kappa) - 1j * G.default_eta(kappa, "hard") * mie.eig_W(n, kappa)
+    assert soft.real.min() > 0.4 and hard.real.min() > 0.4
+    flipped = 0.5 - mie.eig_K(n, kappa) - 1j / kappa * mie.eig_W(n, kappa)
+    assert (flipped.real < 0).any() == (kappa >= 2)
