@@ -3,9 +3,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/igafmm.h"
@@ -108,6 +111,7 @@ struct igb_op_s {
     // near field: per target element the sorted near source elements
     std::vector<int64_t> near_ptr;    // [E+1]
     std::vector<int> near_src;
+    std::vector<std::vector<int>> near_leaf;  // per leaf (local index): sorted inadmissible leaves
     std::vector<int> near_kind;       // per near pair: 0 regular (order in bits 8..), 1 vertex,
                                       // 2 edge, 4 identical; transforms in bits 16.. / 20..
     // near CSR in the solution space
@@ -169,6 +173,34 @@ igb_status gmres_device(igb_op op, const double* b, double* x, int ndir,
 igb_status timer_mark(igb_op op, int slot, hipStream_t s);
 // admissibility helpers
 inline int64_t clusters_on_level(int npatch, int l) { return int64_t(npatch) << (2 * l); }
+
+// Host threads for the plan stages: the CPUs this process may run on, at most 16.
+int host_threads();
+
+// f(i) for every i in [0, n), in blocks of `grain` handed out dynamically to
+// host_threads() threads (the calling thread is one of them).
+template <class F>
+void parallel_for(int64_t n, int64_t grain, const F& f) {
+    const int64_t blocks = (n + grain - 1) / grain;
+    const int nt = int(std::min<int64_t>(host_threads(), blocks));
+    if (nt <= 1) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    auto run = [&]() {
+        for (;;) {
+            const int64_t a = next.fetch_add(grain);
+            if (a >= n) return;
+            const int64_t b = std::min(n, a + grain);
+            for (int64_t i = a; i < b; ++i) f(i);
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(run);
+    run();
+    for (auto& t : pool) t.join();
+}
 
 // Chebyshev points of the first kind on [0,1]
 void cheb_nodes(int q, double* t);

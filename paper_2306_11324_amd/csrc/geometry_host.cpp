@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <numeric>
+#include <sched.h>
 #include <unordered_map>
 
 #include "common.h"
@@ -130,6 +131,13 @@ void set_error(const char* fmt, ...) {
 }
 
 const char* last_error() { return g_err; }
+
+int host_threads() {
+    cpu_set_t set;
+    CPU_ZERO(&set);
+    const int n = sched_getaffinity(0, sizeof(set), &set) == 0 ? CPU_COUNT(&set) : 1;
+    return std::max(1, std::min(n, 16));
+}
 
 void cheb_nodes(int q, double* t) {
     for (int k = 0; k <= q; ++k) t[k] = 0.5 * (1.0 - std::cos((2 * k + 1) * M_PI / (2 * q + 2)));

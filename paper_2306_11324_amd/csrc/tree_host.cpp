@@ -110,7 +110,8 @@ igb_status tree_build(igb_op op) {
     std::vector<std::pair<int, int>> cur, nxt;  // local indices on the current level
     for (int a = 0; a < np; ++a)
         for (int b = 0; b < np; ++b) cur.emplace_back(a, b);
-    std::vector<std::vector<int>> near_leaf(clusters_on_level(np, L));
+    std::vector<std::vector<int>>& near_leaf = op->near_leaf;
+    near_leaf.assign(clusters_on_level(np, L), std::vector<int>());
     int64_t pair_off = 0;
     for (int l = 0; l <= L; ++l) {
         const int n = 1 << l;
@@ -165,23 +166,22 @@ igb_status tree_build(igb_op op) {
         op->near_ptr[e + 1] = op->near_ptr[e] + int64_t(near_leaf[leaf].size()) * s * s;
     }
     op->near_src.resize(op->near_ptr[E]);
-    for (int64_t e = 0; e < E; ++e) {
+    parallel_for(E, 256, [&](int64_t e) {
         int j = int(e / (int64_t(nel1) * nel1));
         int rem = int(e % (int64_t(nel1) * nel1));
         int ey = rem / nel1, ex = rem % nel1;
         int leaf = int(clu_local(np, L, j, ex / s, ey / s));
-        std::vector<int> src;
-        src.reserve(near_leaf[leaf].size() * s * s);
+        int* src = op->near_src.data() + op->near_ptr[e];
+        int64_t c = 0;
         for (int sl : near_leaf[leaf]) {
             int sj = sl >> (2 * L), sr = sl & ((1 << (2 * L)) - 1);
             int scy = sr >> L, scx = sr & (nl - 1);
             for (int fy = scy * s; fy < (scy + 1) * s; ++fy)
                 for (int fx = scx * s; fx < (scx + 1) * s; ++fx)
-                    src.push_back(int((int64_t(sj) * nel1 + fy) * nel1 + fx));
+                    src[c++] = int((int64_t(sj) * nel1 + fy) * nel1 + fx);
         }
-        std::sort(src.begin(), src.end());
-        std::copy(src.begin(), src.end(), op->near_src.begin() + op->near_ptr[e]);
-    }
+        std::sort(src, src + c);
+    });
 
     // M2L work decomposition: chunks of at most CH sources of one target
     const int CH = 8;
@@ -223,7 +223,8 @@ igb_status near_classify(igb_op op) {
         diag[e] = std::sqrt(s2);
     }
     op->near_kind.resize(op->near_src.size());
-    for (int64_t e = 0; e < E; ++e) {
+    std::atomic<int> bad_shared{-1};   // first inconsistency found: shared corner count (or 2)
+    parallel_for(E, 64, [&](int64_t e) {
         for (int64_t k = op->near_ptr[e]; k < op->near_ptr[e + 1]; ++k) {
             const int64_t f = op->near_src[k];
             int shared = 0, ce[4], cf[4];
@@ -234,14 +235,14 @@ igb_status near_classify(igb_op op) {
                         cf[shared] = b;
                         ++shared;
                     }
-            int kind;
+            int kind = 0;
             if (e == f) {
                 kind = 4;
             } else if (shared == 2) {
                 int te = d4_code(ce[0], ce[1]), tf = d4_code(cf[0], cf[1]);
                 if (te < 0 || tf < 0) {
-                    set_error("assemble_nearfield: shared edge not on a side of both elements");
-                    return IGB_ERR_GEOMETRY;
+                    int expect = -1;
+                    bad_shared.compare_exchange_strong(expect, 2);
                 }
                 kind = 2 | (te << 16) | (tf << 20);
             } else if (shared == 1) {
@@ -260,11 +261,19 @@ igb_status near_classify(igb_op op) {
                 n = std::min(n, 7);
                 kind = n << 8;
             } else {
-                set_error("assemble_nearfield: elements share %d corners", shared);
-                return IGB_ERR_GEOMETRY;
+                int expect = -1;
+                bad_shared.compare_exchange_strong(expect, shared);
             }
             op->near_kind[k] = kind;
         }
+    });
+    if (bad_shared.load() == 2) {
+        set_error("assemble_nearfield: shared edge not on a side of both elements");
+        return IGB_ERR_GEOMETRY;
+    }
+    if (bad_shared.load() >= 0) {
+        set_error("assemble_nearfield: elements share %d corners", bad_shared.load());
+        return IGB_ERR_GEOMETRY;
     }
     return IGB_OK;
 }
@@ -272,56 +281,89 @@ igb_status near_classify(igb_op op) {
 // CSR pattern of the near-field matrix in the solution space: column l of row
 // r is present iff an element pair (e, f) of the near list has e in the support
 // of a representative of r and f in the support of a representative of l.
+// Every element of a leaf has the same near sources (the elements of the leaf's
+// inadmissible leaves), so a row's columns are the union, over the leaves that
+// hold its support, of the columns each leaf's near sources touch.
 igb_status near_pattern(igb_op op) {
     igb_geom g = op->geom;
-    const int p = g->p, k = g->k, nel1 = g->nel1;
+    const int p = g->p, k = g->k, nel1 = g->nel1, np = g->npatch;
+    const int L = op->L, s = 1 << op->d, nl = 1 << L;
     const bool hard = op->bc == IGB_HARD;
     const int64_t N = op->N;
-    op->row_ptr.assign(N + 1, 0);
-    std::vector<int64_t> stamp(N, -1);
-    std::vector<int> cols;
-    std::vector<std::vector<int>> rows_cols(N);
-    std::vector<int64_t> elems;
-    for (int64_t r = 0; r < N; ++r) {
-        cols.clear();
-        elems.clear();
+    const int64_t nleaf = int64_t(op->near_leaf.size());
+
+    std::vector<std::vector<int>> leaf_cols(nleaf);
+    parallel_for(nleaf, 1, [&](int64_t lf) {
+        std::vector<int>& c = leaf_cols[lf];
+        for (int sl : op->near_leaf[lf]) {
+            int sj = sl >> (2 * L), sr = sl & ((1 << (2 * L)) - 1);
+            int scy = sr >> L, scx = sr & (nl - 1);
+            for (int iy = scy * s; iy < (scy + 1) * s + p; ++iy)
+                for (int ix = scx * s; ix < (scx + 1) * s + p; ++ix) {
+                    int64_t i2 = (int64_t(sj) * k + iy) * k + ix;
+                    c.push_back(int(hard ? g->s2_to_s0[i2] : i2));
+                }
+        }
+        std::sort(c.begin(), c.end());
+        c.erase(std::unique(c.begin(), c.end()), c.end());
+    });
+
+    // leaves holding the support of row r (sorted, unique)
+    auto row_leaves = [&](int64_t r, std::vector<int>& out) {
+        out.clear();
         auto add_rep = [&](int64_t i) {
             int j = int(i / (int64_t(k) * k));
             int rem = int(i % (int64_t(k) * k));
             int iv = rem / k, iu = rem % k;
-            for (int ey = std::max(0, iv - p); ey <= std::min(iv, nel1 - 1); ++ey)
-                for (int ex = std::max(0, iu - p); ex <= std::min(iu, nel1 - 1); ++ex)
-                    elems.push_back((int64_t(j) * nel1 + ey) * nel1 + ex);
+            int y0 = std::max(0, iv - p) / s, y1 = std::min(iv, nel1 - 1) / s;
+            int x0 = std::max(0, iu - p) / s, x1 = std::min(iu, nel1 - 1) / s;
+            for (int ly = y0; ly <= y1; ++ly)
+                for (int lx = x0; lx <= x1; ++lx) out.push_back(int(clu_local(np, L, j, lx, ly)));
         };
         if (hard) {
             for (int q = g->s0_ptr[r]; q < g->s0_ptr[r + 1]; ++q) add_rep(g->s0_reps[q]);
         } else {
             add_rep(r);
         }
-        for (int64_t e : elems)
-            for (int64_t kk = op->near_ptr[e]; kk < op->near_ptr[e + 1]; ++kk) {
-                int64_t f = op->near_src[kk];
-                int j = int(f / (int64_t(nel1) * nel1));
-                int rem = int(f % (int64_t(nel1) * nel1));
-                int fy = rem / nel1, fx = rem % nel1;
-                for (int b = 0; b <= p; ++b)
-                    for (int a = 0; a <= p; ++a) {
-                        int64_t i2 = (int64_t(j) * k + fy + b) * k + fx + a;
-                        int64_t c = hard ? g->s2_to_s0[i2] : i2;
-                        if (stamp[c] != r) {
-                            stamp[c] = r;
-                            cols.push_back(int(c));
-                        }
-                    }
-            }
-        std::sort(cols.begin(), cols.end());
-        rows_cols[r] = cols;
-        op->row_ptr[r + 1] = op->row_ptr[r] + int64_t(cols.size());
-    }
+        std::sort(out.begin(), out.end());
+        out.erase(std::unique(out.begin(), out.end()), out.end());
+    };
+    // union of the leaves' column lists into `buf` (returns its length)
+    auto merge = [&](const std::vector<int>& leaves, std::vector<int>& buf, std::vector<int>& tmp) {
+        buf.assign(leaf_cols[leaves[0]].begin(), leaf_cols[leaves[0]].end());
+        for (size_t i = 1; i < leaves.size(); ++i) {
+            const std::vector<int>& c = leaf_cols[leaves[i]];
+            tmp.resize(buf.size() + c.size());
+            auto end = std::set_union(buf.begin(), buf.end(), c.begin(), c.end(), tmp.begin());
+            tmp.resize(end - tmp.begin());
+            buf.swap(tmp);
+        }
+    };
+
+    op->row_ptr.assign(N + 1, 0);
+    parallel_for(N, 256, [&](int64_t r) {
+        thread_local std::vector<int> leaves, buf, tmp;
+        row_leaves(r, leaves);
+        if (leaves.size() == 1) {
+            op->row_ptr[r + 1] = int64_t(leaf_cols[leaves[0]].size());
+        } else {
+            merge(leaves, buf, tmp);
+            op->row_ptr[r + 1] = int64_t(buf.size());
+        }
+    });
+    for (int64_t r = 0; r < N; ++r) op->row_ptr[r + 1] += op->row_ptr[r];
     op->nnz = op->row_ptr[N];
     op->col.resize(op->nnz);
-    for (int64_t r = 0; r < N; ++r)
-        std::copy(rows_cols[r].begin(), rows_cols[r].end(), op->col.begin() + op->row_ptr[r]);
+    parallel_for(N, 256, [&](int64_t r) {
+        thread_local std::vector<int> leaves, buf, tmp;
+        row_leaves(r, leaves);
+        const std::vector<int>* src = &leaf_cols[leaves[0]];
+        if (leaves.size() > 1) {
+            merge(leaves, buf, tmp);
+            src = &buf;
+        }
+        std::copy(src->begin(), src->end(), op->col.begin() + op->row_ptr[r]);
+    });
     return IGB_OK;
 }
 
