@@ -11,7 +11,13 @@ residual check) followed by the far field at 64 directions.  `value` counts
 every operator application inside the timed steps.  Operator assembly (near
 field quadrature + coupling matrices) is timed separately and reported.
 
+Beside the headline line's value: the served forms (16 directions in lockstep
+with fp64, fp32 or bf16 couplings; the reduced precisions run on the matrix
+cores inside fp64 iterative refinement), each block matvec's kernel times and
+roofline, and a continuous-batching request stream with p50/p99 latency.
+
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+                    [--block 16] [--serve 32] [--serve-rate 1.0]
 """
 from __future__ import annotations
 
@@ -58,6 +64,35 @@ def cpu_baseline(w, seconds_target=20.0):
                       f"and applied in {t_used:.1f} s, extrapolated x N/{rows_done}"}
 
 
+def serve_stream(nreq, rate):
+    """Continuous batching of a Poisson request stream: each request a seeded
+    star-shaped scatterer at level 3..6, kappa in [1, 32], 1..16 directions,
+    sound-soft or sound-hard, bf16 couplings with fp64 refinement, admitted by
+    HBM budget into 4 concurrent slots.  Latency = completion - arrival."""
+    from paper_2306_11324_amd import inputs as I
+    from paper_2306_11324_amd.serving import ServeConfig, Server
+    cfg = ServeConfig(slots=4)
+    reqs = I.request_stream(nreq, rate=rate, seed=3)
+    srv = Server(cfg)
+
+    def log(r):
+        print(f"# served request {r.rid}: N={r.n} directions={r.uinf.shape[0]} converged={r.converged} "
+              f"escalated={r.escalated} latency={r.latency:.2f}s", file=sys.stderr, flush=True)
+
+    res = srv.run(reqs, realtime=True, log=log)
+    out = Server.summary(res, srv.wall)
+    stages = {}
+    for r in res:
+        for k, v in r.stages.items():
+            stages[k] = stages.get(k, 0.0) + v
+    out.update({"arrival_rate_per_s": rate, "slots": cfg.slots, "hbm_budget_GB": cfg.hbm_budget / 1e9,
+                "precision": "bf16 couplings, fp64 near field and refinement", "q": cfg.q,
+                "leaf_depth": cfg.leaf_depth, "tol": cfg.tol, "peak_reserved_GB": srv.peak_reserved / 1e9,
+                "stage_seconds_total": stages,
+                "stream": "request_stream(seed=3): level 3..6, kappa U[1,32], 1..16 directions, soft/hard"})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +102,8 @@ def main():
     ap.add_argument("--matvecs", type=int, default=50, help="matvec-only timing loop length")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block", type=int, default=16, help="directions per served block (0: skip)")
+    ap.add_argument("--serve", type=int, default=32, help="requests in the served stream (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=1.0, help="Poisson arrival rate of the stream (1/s)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
@@ -123,6 +160,37 @@ def main():
         return dict(T=T, matvecs_per_s=mv / T, solves_per_s=steps * nd / T, ms_per_step=T / steps * 1e3,
                     gmres_iters=its, relres_true=relt, refinements=refs, coeff=coeff, uinf=uinf)
 
+    elem_bytes = {"fp64": 16, "fp32": 8, "bf16": 4}
+    mfma_peak = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
+
+    def block_matvec(o, prec_name, xb, yb, reps):
+        """Block matvec (args.block columns) timed alone; the coupling kernel's
+        algorithmic bytes are the stored tiles (q+1)^4 per far pair."""
+        parts = B.PART_ALL | (0 if prec_name == "fp64" else B.MV_LOWPREC)
+        nc = xb.shape[0]
+        o.h2_matvec(xb, yb, nrhs=nc, parts=parts)
+        torch.cuda.synchronize()
+        o.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            o.h2_matvec(xb, yb, nrhs=nc, parts=parts)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / reps
+        km = {}
+        for k in ("m2l", "spmv", "upward", "downward"):
+            cnt, ms = o.kernel_time(k)
+            km[k] = ms / max(cnt, 1)
+        o.profile(False)
+        avg = km["m2l"] / 1e3
+        nq2 = info.nq * info.nq
+        flops = 8.0 * info.far_pairs * nq2 * nc
+        byts = float(info.far_pairs * nq2 * elem_bytes[prec_name])
+        return {"ncol": nc, "column_matvecs_per_s": nc / tb, "ms_per_block_matvec": tb * 1e3, "kernel_ms": km,
+                "m2l_kernel": "m2l_chunks (vector fp64)" if prec_name == "fp64" else f"m2l_mfma ({prec_name} matrix cores)",
+                "m2l_GBps": byts / avg / 1e9, "m2l_TFLOPs": flops / avg / 1e12,
+                "m2l_frac_hbm_peak": byts / avg / (HBM_PEAK_GBS * 1e9),
+                "m2l_frac_matrix_peak": flops / avg / mfma_peak[prec_name]}
+
     plain = run_solves(op, d, args.steps, args.warmup)
     value = plain["matvecs_per_s"]
     T = plain["T"]
@@ -130,11 +198,14 @@ def main():
     relres_true = plain["relres_true"]
     uinf = plain["uinf"][0]
 
-    # served forms: a block of incident directions in lockstep, fp64 and mixed precision
-    served = {}
+    # served forms: a block of incident directions in lockstep, fp64 and mixed
+    # precision, and the block matvec alone with per-kernel HIP-event times
+    served, block_mv = {}, {}
     if args.block > 0:
         dirs_b = I.random_directions(1, args.block)
         ref_coeff = None
+        xb = torch.from_numpy(I.random_complex(777, (args.block, n))).to(dev)
+        yb = torch.zeros_like(xb)
         for prec_name, prec in (("fp64", B.FP64), ("fp32", B.MIX_FP32), ("bf16", B.MIX_BF16)):
             o = op if prec == B.FP64 else B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"],
                                                       kcap=w["kcap"], leaf_depth=w["leaf_depth"], precision=prec)
@@ -148,9 +219,11 @@ def main():
             r["speedup_solves_vs_plain_fp64"] = r["solves_per_s"] / plain["solves_per_s"]
             r.pop("T")
             served[f"{prec_name}_block{args.block}"] = r
+            block_mv[prec_name] = block_matvec(o, prec_name, xb, yb, max(5, args.matvecs // 5))
             if o is not op:
                 del o
             torch.cuda.empty_cache()
+        del xb, yb
 
     # matvec-only loop with HIP-event kernel timing on the launch stream
     x = torch.from_numpy(I.random_complex(12345, n)).to(dev)
@@ -171,30 +244,6 @@ def main():
     op.h2_matvec(x, y)
     torch.cuda.synchronize()
     yv = y.cpu().numpy()
-
-    # block matvec (the served form's dominant pass): same couplings, args.block columns
-    block_mv = None
-    if args.block > 0:
-        xb = torch.from_numpy(I.random_complex(777, (args.block, n))).to(dev)
-        yb = torch.zeros_like(xb)
-        op.h2_matvec(xb, yb, nrhs=args.block)
-        torch.cuda.synchronize()
-        op.profile(True)
-        nb = max(5, args.matvecs // 5)
-        t0 = time.perf_counter()
-        for _ in range(nb):
-            op.h2_matvec(xb, yb, nrhs=args.block)
-        torch.cuda.synchronize()
-        tb = (time.perf_counter() - t0) / nb
-        bn, bms = op.kernel_time("m2l")
-        op.profile(False)
-        b_avg = bms / max(bn, 1) / 1e3
-        b_flops = 8.0 * info.far_pairs * info.nq * info.nq * args.block
-        b_bytes = info.far_pairs * info.nq * info.nq * 16 + info.far_pairs * info.nq * 16 * args.block
-        block_mv = {"ncol": args.block, "column_matvecs_per_s": args.block / tb, "m2l_avg_ms": b_avg * 1e3,
-                    "m2l_GBps": b_bytes / b_avg / 1e9, "m2l_TFLOPs": b_flops / b_avg / 1e12,
-                    "m2l_frac_fp64_peak": b_flops / b_avg / 78.6e12, "m2l_frac_hbm_peak": b_bytes / b_avg / 8e12}
-        del xb, yb
 
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
@@ -269,6 +318,8 @@ def main():
                      "kernel": "m2l_chunks", "bytes_per_launch": m2l_bytes,
                      "avg_launch_ms": m2l_avg * 1e3},
     }
+    if args.serve > 0:
+        out["serving"] = serve_stream(args.serve, args.serve_rate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -109,16 +109,20 @@ typedef struct {
     int maxit;       /* maximal number of Arnoldi steps per column (over all refinements) */
     double inner_tol;/* mixed precision: lower bound of the inner relative tolerance;
                         <= 0 selects 0 (fp32) / 1e-3 (bf16)                             */
-    int refine_max;  /* mixed precision: maximal refinement steps (<= 0: 10)           */
+    int refine_max;  /* mixed precision: maximal refinement steps on the reduced-precision
+                        operator (<= 0: 10); a column escalated to fp64 gets up to 3 more */
 } igb_solve_params;
 
 typedef struct {
-    int iters;        /* matrix-vector products used (max over columns)            */
+    int iters;        /* Arnoldi steps (max over columns, summed over refinements)  */
     int converged;    /* number of columns that reached tol                         */
     double relres;    /* max over columns of the final recursive relative residual   */
     double relres_true; /* max over columns of ||b - A x||/||b|| recomputed at the end */
     int64_t matvecs;  /* operator applications in total (Arnoldi + residual checks) */
     int refinements;  /* mixed precision: outer refinement steps taken (all columns)  */
+    int escalated;    /* mixed precision: columns that finished on the fp64 operator
+                         because a refinement step reduced their fp64 residual by
+                         less than a factor 10                                       */
 } igb_solve_info;
 
 typedef struct {
@@ -223,10 +227,12 @@ igb_status cfie_rhs(igb_op op, const double* dirs, int ndir, double* b, void* hi
  * restarted GMRES (Sec. 5.1), x0 = 0, writing the coefficients into the device
  * array coeffs [ndir][n].  The directions run in lockstep: one block matvec per
  * Arnoldi step, each column with its own Krylov basis, rotations and stopping
- * test, so a column's solution does not depend on the other columns.  Operators with IGB_MIX_* precision solve by
- * iterative refinement: x += GMRES(A_rounded, b - A_fp64 x) until the fp64
- * residual reaches tol.  Synchronous.  IGB_WARN_NOT_CONVERGED if a column
- * stops at maxit. */
+ * test, so a column's solution does not depend on the other columns.
+ * Operators with IGB_MIX_* precision solve by iterative refinement:
+ * x += GMRES(A_rounded, b - A_fp64 x) until the fp64 residual reaches tol; a
+ * column whose step reduces that residual by less than a factor 10 continues
+ * with GMRES(A_fp64, .) (a step that does not reduce it is taken back first).
+ * Synchronous.  IGB_WARN_NOT_CONVERGED if a column stops at maxit. */
 igb_status cfie_solve(igb_op op, const double* dirs, int ndir, const igb_solve_params* sp,
                       double* coeffs, igb_solve_info* info);
 

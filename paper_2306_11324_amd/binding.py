@@ -53,7 +53,8 @@ class IgbSolveParams(C.Structure):
 
 class IgbSolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("relres", C.c_double),
-                ("relres_true", C.c_double), ("matvecs", C.c_int64), ("refinements", C.c_int)]
+                ("relres_true", C.c_double), ("matvecs", C.c_int64), ("refinements", C.c_int),
+                ("escalated", C.c_int)]
 
 
 class IgbOpInfo(C.Structure):

@@ -185,10 +185,19 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
     }
     // device bytes of the operator (checked against the budget before allocating)
     const int nl = (g->p + 1) * (g->p + 1);
-    const size_t coup_elem = 16 + (prm->precision == IGB_MIX_FP32 ? 8 : prm->precision == IGB_MIX_BF16 ? 4 : 0);
-    size_t need = size_t(op->nfar) * op->nq * op->nq * coup_elem * (prm->bc == IGB_HARD ? 2 : 1) + size_t(op->nnz) * 20 + size_t(op->N + 1) * 8 +
+    const int ntile = prm->bc == IGB_HARD ? 2 : 1;
+    size_t need = size_t(op->nfar) * op->nq * op->nq * 16 * ntile + size_t(op->nnz) * 20 + size_t(op->N + 1) * 8 +
                   size_t(op->nclusters) * op->nq * (16 * 8 + 32) + op->near_src.size() * 4 +
                   std::min<size_t>(op->near_src.size(), size_t(1) << 22) * nl * nl * 16;
+    if (prm->precision != IGB_FP64) {
+        // rounded tiles (rows padded to 16 bytes) and, per 16 columns, the rounded
+        // source vectors and fp32 partials of the matrix-core coupling
+        const size_t esz = prm->precision == IGB_MIX_FP32 ? 8 : 4, epl = 16 / esz, kb = 4 * epl;
+        const size_t ldk = (op->nq + epl - 1) / epl * epl, kbp = (op->nq + kb - 1) / kb * kb;
+        need += size_t(op->nfar) * ntile * op->nq * ldk * esz + size_t(3) * op->nq * 16 + 256;
+        need += size_t(op->nclusters) * (ntile == 2 ? 7 : 1) * 16 * kbp * esz +
+                op->chunks_mfma.len.size() * (ntile == 2 ? 10 : 1) * op->nq * 8;
+    }
     // matvec work vectors for one column and a GMRES(30) basis
     need += size_t(op->nclusters) * op->nq * 16 * (prm->bc == IGB_HARD ? 16 : 2) + size_t(g->n2) * 16 * 4 +
             size_t(35) * op->N * 16;

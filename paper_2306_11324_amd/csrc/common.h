@@ -96,6 +96,18 @@ struct FarLevel {
     std::vector<int> src;        // source cluster (local index in the level) per pair
 };
 
+// M2L work decomposition: chunks of consecutive far pairs of one target; each
+// chunk produces one partial result, summed per target in chunk order
+constexpr int M2L_CHUNK = 8;
+constexpr int M2L_CHUNK_MFMA = 32;
+struct M2LChunks {
+    std::vector<int> tgt;       // global cluster index of the chunk's target
+    std::vector<int64_t> pair;  // first pair of the chunk
+    std::vector<int> len;
+    std::vector<int> tgt_ptr;   // [nclusters+1] chunks per target (global index)
+    igb::DevBuf d_tgt, d_pair, d_len, d_tgt_ptr;
+};
+
 struct igb_op_s {
     igb_geom geom = nullptr;
     igb_op_params prm{};
@@ -118,17 +130,16 @@ struct igb_op_s {
     std::vector<int64_t> row_ptr;
     std::vector<int> col;
     int64_t nnz = 0;
-    // M2L work decomposition: chunks of at most M2L_CHUNK sources of one target
-    std::vector<int> chunk_tgt;       // global cluster index of the chunk's target
-    std::vector<int64_t> chunk_pair;  // first pair of the chunk
-    std::vector<int> chunk_len;
-    std::vector<int> tgt_chunk_ptr;   // [nclusters+1] chunks per target (global index)
+    // M2L work decompositions (vector path, matrix-core path)
+    M2LChunks chunks, chunks_mfma;
     // device data
     igb::DevBuf d_coupling, d_coupling_lo, d_nodes, d_m1, d_T;
     igb::DevBuf d_rowptr, d_col, d_val;
     igb::DevBuf d_near_ptr, d_near_src;
     igb::DevBuf d_s2_to_s0, d_s0_ptr, d_s0_reps;
-    igb::DevBuf d_chunk_tgt, d_chunk_pair, d_chunk_len, d_tgt_chunk_ptr, d_far_src;
+    igb::DevBuf d_far_src;
+    // reduced-precision path: source vectors rounded per matvec, fp32 partials
+    igb::DevBuf d_xlo, d_part_lo;
     igb::DevBuf d_xhat, d_yhat, d_yraw, d_part, d_yfar, d_x2, d_cluoff, d_leafbuf;
     size_t dev_bytes = 0;
     int64_t nclusters = 0;

@@ -329,43 +329,71 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
             return st;
     } else {
         // iterative refinement: inner GMRES on the reduced-precision far field,
-        // outer residual with the fp64 operator; columns refine independently
+        // outer residual with the fp64 operator; columns refine independently.
+        // A column whose fp64 residual falls by less than ESCALATE per step (or
+        // rises: that correction is taken back) refines from then on with the
+        // fp64 operator, solving straight to the tolerance.
+        const double ESCALATE = 0.1;
         const double inner_min = sp->inner_tol > 0 ? sp->inner_tol : (op->prm.precision == IGB_MIX_FP32 ? 0.0 : 1e-3);
         const int refine_max = sp->refine_max > 0 ? sp->refine_max : 10;
-        // the outer residual and correction live in separate buffers from the
+        // the outer residual and corrections live in separate buffers from the
         // inner solver's work vectors
-        igb::DevBuf rbuf, dbuf;
+        igb::DevBuf rbuf, dbuf, d2buf;
         IGB_HIP(hipMalloc(&rbuf.ptr, size_t(n) * C * sizeof(double2)));
         IGB_HIP(hipMalloc(&dbuf.ptr, size_t(n) * C * sizeof(double2)));
         double2* R = rbuf.as<double2>();
         double2* D = dbuf.as<double2>();
+        double2* D2 = nullptr;
         IGB_HIP(hipMemsetAsync(X, 0, n * C * sizeof(double2), s));
         IGB_HIP(hipMemcpyAsync(R, B, n * C * sizeof(double2), hipMemcpyDeviceToDevice, s));
         std::vector<double> bnorm, rnorm;
         if ((st = norms(B, n, C, W.nrm, bnorm, s))) return st;
         rnorm = bnorm;
         res.assign(C, ColumnResult());
+        std::vector<char> full(C, 0);   // column refines with the fp64 operator
         for (int c = 0; c < C; ++c) {
             res[c].converged = bnorm[c] == 0.0;
             res[c].relres = res[c].true_rel = res[c].converged ? 0.0 : 1.0;
         }
-        for (int outer = 0; outer < refine_max; ++outer) {
-            // inner tolerance per column: what the column still needs, at least inner_min
+        for (int outer = 0; outer < refine_max + 3; ++outer) {
+            // inner tolerance per column: what the column still needs, at least
+            // inner_min on the reduced-precision operator
             std::vector<double> tin(C, 1.0);
-            std::vector<int> left(C, 0);
-            bool any = false;
+            std::vector<int> left(C, 0), left_lo(C, 0), left_hi(C, 0);
+            bool any_lo = false, any_hi = false;
             for (int c = 0; c < C; ++c) {
-                if (res[c].converged || res[c].iters >= maxit) {
-                    IGB_HIP(hipMemsetAsync(R + int64_t(c) * n, 0, n * sizeof(double2), s));
-                    continue;
-                }
-                any = true;
-                tin[c] = std::max(inner_min, 0.5 * tol * bnorm[c] / rnorm[c]);
+                if (res[c].converged || res[c].iters >= maxit || (!full[c] && outer >= refine_max)) continue;
                 left[c] = maxit - res[c].iters;   // maxit bounds the Arnoldi steps over all refinements
+                const double need = 0.5 * tol * bnorm[c] / rnorm[c];
+                if (full[c]) {
+                    tin[c] = need;
+                    left_hi[c] = left[c];
+                    any_hi = true;
+                } else {
+                    tin[c] = std::max(inner_min, need);
+                    left_lo[c] = left[c];
+                    any_lo = true;
+                }
             }
-            if (!any) break;
-            std::vector<ColumnResult> inner;
-            if ((st = gmres_block(op, W, R, D, left, tin, IGB_PART_ALL | IGB_MV_LOWPREC, s, inner))) return st;
+            if (!any_lo && !any_hi) break;
+            std::vector<ColumnResult> inner(C), part;
+            if (any_lo) {
+                if ((st = gmres_block(op, W, R, D, left_lo, tin, IGB_PART_ALL | IGB_MV_LOWPREC, s, part))) return st;
+                for (int c = 0; c < C; ++c)
+                    if (left_lo[c]) inner[c] = part[c];
+            } else {
+                IGB_HIP(hipMemsetAsync(D, 0, n * C * sizeof(double2), s));
+            }
+            if (any_hi) {
+                if (!D2) {
+                    IGB_HIP(hipMalloc(&d2buf.ptr, size_t(n) * C * sizeof(double2)));
+                    D2 = d2buf.as<double2>();
+                }
+                if ((st = gmres_block(op, W, R, D2, left_hi, tin, IGB_PART_ALL, s, part))) return st;
+                for (int c = 0; c < C; ++c)
+                    if (left_hi[c]) inner[c] = part[c];
+                hipLaunchKernelGGL(cadd_to, dim3(gb), dim3(256), 0, s, D2, n * C, D);
+            }
             hipLaunchKernelGGL(cadd_to, dim3(gb), dim3(256), 0, s, D, n * C, X);
             if ((st = matvec_device(op, reinterpret_cast<const double*>(X), reinterpret_cast<double*>(R), C,
                                     IGB_PART_ALL, s)))
@@ -376,16 +404,18 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
             std::vector<double> undo(C, 0.0);
             bool any_undo = false;
             for (int c = 0; c < C; ++c) {
-                if (res[c].converged || left[c] == 0) continue;
+                if (left[c] == 0) continue;
                 res[c].iters += inner[c].iters;
                 res[c].applications += inner[c].applications + 1;
                 if (!(rnorm[c] < rprev[c])) {
-                    // the correction did not reduce the fp64 residual: take it
-                    // back and stop refining this column
+                    // the correction did not reduce the fp64 residual: take it back
                     undo[c] = -1.0;
                     any_undo = true;
                     rnorm[c] = rprev[c];
-                    res[c].iters = maxit;
+                    if (full[c]) res[c].iters = maxit;   // no further remedy
+                    full[c] = 1;
+                } else if (!full[c] && rnorm[c] > ESCALATE * rprev[c]) {
+                    full[c] = 1;
                 }
                 res[c].true_rel = bnorm[c] > 0 ? rnorm[c] / bnorm[c] : 0.0;
                 res[c].relres = res[c].true_rel;
@@ -404,6 +434,7 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
             }
             ++out.refinements;
         }
+        for (int c = 0; c < C; ++c) out.escalated += full[c] ? 1 : 0;
     }
     int status = IGB_OK;
     for (int c = 0; c < C; ++c) {

@@ -847,19 +847,257 @@ __device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
     return (unsigned short)(u >> 16);
 }
 
-// rounded copy of the fp64 couplings: prec 1 -> fp32 (RNE), prec 2 -> bf16 (RNE of the fp32 value)
-__global__ void round_coupling(const double2* __restrict__ in, int64_t n, int prec, void* __restrict__ out) {
+// ---------------------------------------------------------------------------
+// Reduced-precision coupling on the matrix cores
+//
+// The complex products y[a][c] += sum_b K[a][b] x[b][c] of one coupling tile
+// run as one real GEMM with fp32 accumulation: the tile, row-major with (re,
+// im) adjacent, is the A operand A'[a][2b + r]; the B operand comes from the
+// compact source vector, (Re x, -Im x) along k for Re y and (Im x, Re x) for
+// Im y.  Both operands are stored in 16-byte chunks of EPL consecutive
+// elements (element = bf16 or fp32 complex) so that the 16 lanes of a lane
+// group, which hold 16 consecutive rows (A) or columns (B) of one chunk, read
+// 256 contiguous bytes:
+//   tiles    [pair][tile][chunk kc < nkc][row a < nq][EPL], nkc = ceil(nq/EPL),
+//            zeros beyond nq (tile 0: soft kernel or hard G, tile 1: hard H)
+//   vectors  [cluster][vec][chunk < kbp/EPL][col < ncolp][EPL], kbp = nq
+//            rounded up to the k block, ncolp = ncol rounded up to 16, zeros
+//            beyond nq and ncol
+// The last k block may reach up to three chunks past a tile (into the next
+// tile, or the zeroed slack after the last one); the B operand is zero there.
+// ---------------------------------------------------------------------------
+template <class LT> __device__ __forceinline__ LT round_to(double2 v);
+template <> __device__ __forceinline__ float2 round_to<float2>(double2 v) { return make_float2(float(v.x), float(v.y)); }
+template <> __device__ __forceinline__ bf16x2 round_to<bf16x2>(double2 v) {
+    bf16x2 b;
+    b.re = f32_to_bf16_rne(float(v.x));   // RNE of the fp32 value
+    b.im = f32_to_bf16_rne(float(v.y));
+    return b;
+}
+
+// rounded tiles from the fp64 couplings [pair][b][a][tile]
+template <class LT>
+__global__ void round_coupling_tiles(const double2* __restrict__ in, int64_t nfar, int nq, int nkc, int ntile,
+                                     LT* __restrict__ out) {
+    constexpr int EPL = 16 / sizeof(LT);
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float2 f = make_float2(float(in[i].x), float(in[i].y));
-    if (prec == 1) {
-        static_cast<float2*>(out)[i] = f;
-    } else {
-        bf16x2 b;
-        b.re = f32_to_bf16_rne(f.x);
-        b.im = f32_to_bf16_rne(f.y);
-        static_cast<bf16x2*>(out)[i] = b;
+    if (i >= nfar * ntile * nkc * nq * EPL) return;
+    const int e = int(i % EPL);
+    int64_t r = i / EPL;
+    const int a = int(r % nq);
+    r /= nq;
+    const int kc = int(r % nkc);
+    r /= nkc;
+    const int t = int(r % ntile);
+    const int64_t pr = r / ntile;
+    const int b = kc * EPL + e;
+    const double2 v = b < nq ? in[(pr * nq * nq + int64_t(b) * nq + a) * ntile + t] : make_double2(0, 0);
+    out[i] = round_to<LT>(v);
+}
+
+// rounded source vectors of the coupling, per matvec.  Soft: the moments x.
+// Hard (NV = 7): n~_c xp (c = 0..2), (y.n~) xp, F_v,c xu - F_u,c xv (c = 0..2)
+// at the cluster's nodes, from the three moment kinds xp, xu, xv.
+template <int NV, class LT>
+__global__ void round_vectors(const double2* __restrict__ xh, int64_t ks, const double* __restrict__ nodes,
+                              int64_t nclusters, int nq, int kbp, int ncol, int ncolp, LT* __restrict__ out) {
+    constexpr int EPL = 16 / sizeof(LT);
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= nclusters * NV * ncolp * kbp) return;
+    const int e = int(i % EPL);
+    int64_t r = i / EPL;
+    const int c = int(r % ncolp);
+    r /= ncolp;
+    const int nch = kbp / EPL;
+    const int kc = int(r % nch);
+    r /= nch;
+    const int v = int(r % NV);
+    const int64_t cl = r / NV;
+    const int b = kc * EPL + e;
+    double2 val = make_double2(0, 0);
+    if (b < nq && c < ncol) {
+        const int64_t o = (cl * nq + b) * ncol + c;
+        if (NV == 1) {
+            val = xh[o];
+        } else {
+            const double* Y = nodes + (cl * nq + b) * 16;
+            if (v < 3) {
+                val = cscale(xh[o], Y[3 + v]);
+            } else if (v == 3) {
+                val = cscale(xh[o], Y[0] * Y[3] + Y[1] * Y[4] + Y[2] * Y[5]);
+            } else {
+                const int cc = v - 4;
+                const double2 xu = xh[ks + o], xv = xh[2 * ks + o];
+                val = make_double2(Y[11 + cc] * xu.x - Y[8 + cc] * xv.x, Y[11 + cc] * xu.y - Y[8 + cc] * xv.y);
+            }
+        }
     }
+    out[i] = round_to<LT>(val);
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+
+// One k block of one 16x16 output tile.  Each lane holds 16 bytes of A (row
+// lane%16) and of B (column lane%16); lane group g = lane/16 holds the k
+// entries g*KB/4 .. of the block.  Any assignment of k to register slots is
+// valid as long as A and B use the same one, which they do by construction.
+struct MfmaBf16 {
+    using LT = bf16x2;
+    static constexpr int EPL = 4;    // complex elements per lane load
+    static constexpr int KB = 16;    // complex elements per k block (k = 32)
+    static __device__ __forceinline__ f32x4 step(uint4 a, uint4 b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8v, a), __builtin_bit_cast(bf16x8v, b),
+                                                       c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ uint4 re_part(uint4 x) {   // (re, im) -> (re, -im)
+        return make_uint4(x.x ^ 0x80000000u, x.y ^ 0x80000000u, x.z ^ 0x80000000u, x.w ^ 0x80000000u);
+    }
+    static __device__ __forceinline__ uint4 im_part(uint4 x) {   // (re, im) -> (im, re)
+        return make_uint4((x.x >> 16) | (x.x << 16), (x.y >> 16) | (x.y << 16), (x.z >> 16) | (x.z << 16),
+                          (x.w >> 16) | (x.w << 16));
+    }
+};
+struct MfmaF32 {
+    using LT = float2;
+    static constexpr int EPL = 2;
+    static constexpr int KB = 8;     // four 16x16x4 steps
+    static __device__ __forceinline__ f32x4 step(uint4 a, uint4 b, f32x4 c) {
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+        return c;
+    }
+    static __device__ __forceinline__ uint4 re_part(uint4 x) {   // (re0, im0, re1, im1) -> (re0, -im0, re1, -im1)
+        return make_uint4(x.x, x.y ^ 0x80000000u, x.z, x.w ^ 0x80000000u);
+    }
+    static __device__ __forceinline__ uint4 im_part(uint4 x) {   // -> (im0, re0, im1, re1)
+        return make_uint4(x.y, x.x, x.w, x.z);
+    }
+};
+
+// chunk handled by workgroup w: consecutive chunks on the same XCD (workgroups
+// are dealt to the 8 XCDs round robin), so neighbouring targets share L2
+__device__ __forceinline__ int64_t xcd_chunk(int64_t w, int64_t n) {
+    const int64_t per = n / 8, rem = n % 8, x = w % 8, i = w / 8;
+    return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
+// reduced-precision layout sizes
+static inline int lo_kb(igb_op op) { return op->prm.precision == IGB_MIX_FP32 ? MfmaF32::KB : MfmaBf16::KB; }
+static inline int lo_epl(igb_op op) { return op->prm.precision == IGB_MIX_FP32 ? MfmaF32::EPL : MfmaBf16::EPL; }
+static inline int lo_nkc(igb_op op) { return (op->nq + lo_epl(op) - 1) / lo_epl(op); }
+static inline int lo_kbp(igb_op op) { return (op->nq + lo_kb(op) - 1) / lo_kb(op) * lo_kb(op); }
+static inline size_t lo_esz(igb_op op) { return op->prm.precision == IGB_MIX_FP32 ? sizeof(float2) : sizeof(bf16x2); }
+// zeroed bytes after the last tile: the last k block reaches at most three
+// chunks (of nq rows) past a tile
+static inline size_t lo_slack(igb_op op) { return size_t(3) * op->nq * 16 + 256; }
+
+// Coupling of one chunk (consecutive far pairs of one target) for 16 columns
+// on the matrix cores: wave w owns output rows 16w..16w+15.  Soft: one tile,
+// one vector.  Hard: H acts on vectors {3, 0, 1, 2}, G on {0, 1, 2, 4, 5, 6},
+// giving the 10 partial vectors of the vector-path kernel in the same order.
+template <class OPS, bool HARD>
+__global__ __launch_bounds__(512) void m2l_mfma(const typename OPS::LT* __restrict__ coup, int nkc,
+                                                const typename OPS::LT* __restrict__ xlo, int kbp, int ncolp,
+                                                const int* __restrict__ far_src_g,
+                                                const int64_t* __restrict__ chunk_pair,
+                                                const int* __restrict__ chunk_len, int64_t nchunk, int nq, int ncol,
+                                                float2* __restrict__ part) {
+    constexpr int NT = HARD ? 2 : 1, NVS = HARD ? 7 : 1, NVO = HARD ? 10 : 1;
+    constexpr int KB = OPS::KB, EPL = OPS::EPL;
+    const int64_t ch = xcd_chunk(blockIdx.x, nchunk);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    // A row of this lane; rows past nq re-read the last row (their outputs are
+    // not stored, and an output row depends only on its own A row)
+    const int a = min(wave * 16 + li, nq - 1);
+    const int c0 = blockIdx.y * 16;
+    const int64_t p0 = chunk_pair[ch];
+    const int len = chunk_len[ch];
+    const int nkb = (nq + KB - 1) / KB;
+    const int64_t tile_el = int64_t(nkc) * nq * EPL;
+    f32x4 acc[NVO][2];
+#pragma unroll
+    for (int v = 0; v < NVO; ++v) acc[v][0] = acc[v][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // steps j = (pair i, k block kb) in order; KU steps issue their loads
+    // before any of their products, so each wave keeps KU blocks in flight
+    constexpr int KU = HARD ? 1 : 4;
+    const int nstep = len * nkb;
+    // the chunk's source clusters, lane i holding pair i (len <= 64), read back
+    // with readlane: no dependent scalar load inside the loop
+    const int srcv = lane < len ? far_src_g[p0 + lane] : 0;
+    const int64_t vstride = int64_t(ncolp) * kbp;
+    // addresses: a uniform part per step (scalar unit) plus a per-lane 32-bit
+    // offset fixed for the whole kernel
+    using LT = typename OPS::LT;
+    const unsigned offA = unsigned((g * nq + a) * EPL);
+    const unsigned offB = unsigned((g * ncolp + c0 + li) * EPL);
+    // next step to load: pair ni, k block nkbi.  Past the last step the loads
+    // repeat the last step's (in bounds, unused): every load is issued
+    // unconditionally, so the compiler can wait for exactly the buffer a group
+    // of products needs while the other buffer's loads stay in flight.
+    int ni = 0, nkbi = 0;
+    auto load = [&](uint4 (&A)[KU][NT], uint4 (&X)[KU][NVS]) {
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int i = ni, kb = nkbi;
+            const bool last = ni == len - 1 && nkbi == nkb - 1;
+            nkbi = last ? nkbi : (nkbi + 1 == nkb ? 0 : nkbi + 1);
+            ni = last ? ni : (nkbi == 0 ? ni + 1 : ni);
+            const int src = __builtin_amdgcn_readlane(srcv, i);
+            const LT* Au = coup + (p0 + i) * (NT * tile_el) + kb * (4 * nq * EPL);
+            const LT* Bu = xlo + int64_t(src) * (NVS * vstride) + kb * (4 * ncolp * EPL);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) A[u][t] = *reinterpret_cast<const uint4*>(Au + t * tile_el + offA);
+#pragma unroll
+            for (int v = 0; v < NVS; ++v) X[u][v] = *reinterpret_cast<const uint4*>(Bu + v * vstride + offB);
+        }
+    };
+    auto compute = [&](int j0, const uint4 (&A)[KU][NT], const uint4 (&X)[KU][NVS]) {
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            if (j0 + u >= nstep) break;
+            if (!HARD) {
+                acc[0][0] = OPS::step(A[u][0], OPS::re_part(X[u][0]), acc[0][0]);
+                acc[0][1] = OPS::step(A[u][0], OPS::im_part(X[u][0]), acc[0][1]);
+            } else {
+                constexpr int hv[4] = {3, 0, 1, 2};
+                constexpr int gv[6] = {0, 1, 2, 4, 5, 6};
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    acc[jj][0] = OPS::step(A[u][1], OPS::re_part(X[u][hv[jj]]), acc[jj][0]);
+                    acc[jj][1] = OPS::step(A[u][1], OPS::im_part(X[u][hv[jj]]), acc[jj][1]);
+                }
+#pragma unroll
+                for (int jj = 0; jj < 6; ++jj) {
+                    acc[4 + jj][0] = OPS::step(A[u][0], OPS::re_part(X[u][gv[jj]]), acc[4 + jj][0]);
+                    acc[4 + jj][1] = OPS::step(A[u][0], OPS::im_part(X[u][gv[jj]]), acc[4 + jj][1]);
+                }
+            }
+        }
+    };
+    // two register buffers: the next group's loads are in flight while the
+    // current group's products run
+    uint4 A0[KU][NT], X0[KU][NVS], A1[KU][NT], X1[KU][NVS];
+    load(A0, X0);
+    for (int j0 = 0; j0 < nstep; j0 += 2 * KU) {
+        load(A1, X1);
+        compute(j0, A0, X0);
+        load(A0, X0);
+        compute(j0 + KU, A1, X1);
+    }
+    // lane holds column li, rows 4g..4g+3 of each 16x16 tile
+    const int c = c0 + li;
+    if (c >= ncol) return;
+#pragma unroll
+    for (int v = 0; v < NVO; ++v)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ar = wave * 16 + 4 * g + r;
+            if (ar < nq) part[((ch * NVO + v) * nq + ar) * ncol + c] = make_float2(acc[v][0][r], acc[v][1][r]);
+        }
 }
 
 // coupling, sound-soft: one workgroup per (chunk of source clusters of one
@@ -1015,14 +1253,14 @@ __global__ void m2l_finalize_hard(const double2* raw, const double* nodes, int64
 
 // sum over the target's chunks (fixed order), zero if none:
 // [chunk][per] -> [cluster][per], per = nvec * nq * ncol
-__global__ void m2l_reduce(const double2* part, const int* tgt_chunk_ptr, int64_t nclusters, int64_t per,
-                           double2* yh) {
+template <class PT>
+__global__ void m2l_reduce(const PT* part, const int* tgt_chunk_ptr, int64_t nclusters, int64_t per, double2* yh) {
     const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gid >= nclusters * per) return;
     const int64_t c = gid / per;
     const int64_t va = gid % per;
     double2 s = make_double2(0, 0);
-    for (int ch = tgt_chunk_ptr[c]; ch < tgt_chunk_ptr[c + 1]; ++ch) s = cadd(s, part[int64_t(ch) * per + va]);
+    for (int ch = tgt_chunk_ptr[c]; ch < tgt_chunk_ptr[c + 1]; ++ch) s = cadd(s, to_d2(part[int64_t(ch) * per + va]));
     yh[gid] = s;
 }
 
@@ -1621,18 +1859,29 @@ igb_status assemble_far_device(igb_op op, hipStream_t s) {
                                op->d_coupling.as<double2>());
         IGB_HIP(hipGetLastError());
         if (op->prm.precision != IGB_FP64) {
-            const int64_t ne = op->nfar * nq * nq * (hard ? 2 : 1);
-            const size_t esz = op->prm.precision == IGB_MIX_FP32 ? sizeof(float2) : sizeof(bf16x2);
-            if ((st = alloc(op->d_coupling_lo, size_t(ne) * esz, acct))) return st;
-            hipLaunchKernelGGL(round_coupling, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, s,
-                               op->d_coupling.as<double2>(), ne, op->prm.precision, op->d_coupling_lo.ptr);
+            const int ntile = hard ? 2 : 1;
+            const bool f32 = op->prm.precision == IGB_MIX_FP32;
+            const int nkc = lo_nkc(op);
+            const int64_t ne = op->nfar * ntile * nkc * nq * lo_epl(op);
+            const size_t esz = lo_esz(op), slack = lo_slack(op);
+            if ((st = alloc(op->d_coupling_lo, size_t(ne) * esz + slack, acct))) return st;
+            IGB_HIP(hipMemsetAsync(static_cast<char*>(op->d_coupling_lo.ptr) + size_t(ne) * esz, 0, slack, s));
+            if (f32)
+                hipLaunchKernelGGL(round_coupling_tiles<float2>, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, s,
+                                   op->d_coupling.as<double2>(), op->nfar, nq, nkc, ntile,
+                                   op->d_coupling_lo.as<float2>());
+            else
+                hipLaunchKernelGGL(round_coupling_tiles<bf16x2>, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, s,
+                                   op->d_coupling.as<double2>(), op->nfar, nq, nkc, ntile,
+                                   op->d_coupling_lo.as<bf16x2>());
             IGB_HIP(hipGetLastError());
         }
     }
-    if ((st = upload(op->d_chunk_pair, op->chunk_pair.data(), op->chunk_pair.size(), acct))) return st;
-    if ((st = upload(op->d_chunk_len, op->chunk_len.data(), op->chunk_len.size(), acct))) return st;
-    if ((st = upload(op->d_tgt_chunk_ptr, op->tgt_chunk_ptr.data(), op->tgt_chunk_ptr.size(), acct))) return st;
-    if ((st = upload(op->d_chunk_tgt, op->chunk_tgt.data(), op->chunk_tgt.size(), acct))) return st;
+    for (M2LChunks* c : {&op->chunks, &op->chunks_mfma}) {
+        if ((st = upload(c->d_pair, c->pair.data(), c->pair.size(), acct))) return st;
+        if ((st = upload(c->d_len, c->len.data(), c->len.size(), acct))) return st;
+        if ((st = upload(c->d_tgt_ptr, c->tgt_ptr.data(), c->tgt_ptr.size(), acct))) return st;
+    }
     IGB_HIP(hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
     op->t_assembly_far = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -1650,7 +1899,8 @@ igb_status alloc_work(igb_op op, int ncol) {
     const int nq = op->nq;
     const bool hard = op->bc == IGB_HARD;
     const int kinds = hard ? 3 : 1, nvec = hard ? 10 : 1;
-    for (igb::DevBuf* b : {&op->d_xhat, &op->d_yhat, &op->d_yraw, &op->d_part, &op->d_yfar, &op->d_x2, &op->d_leafbuf}) {
+    for (igb::DevBuf* b : {&op->d_xhat, &op->d_yhat, &op->d_yraw, &op->d_part, &op->d_yfar, &op->d_x2, &op->d_leafbuf,
+                           &op->d_xlo, &op->d_part_lo}) {
         *acct -= std::min(*acct, b->bytes);
         b->release();
     }
@@ -1658,8 +1908,16 @@ igb_status alloc_work(igb_op op, int ncol) {
     if ((st = alloc(op->d_xhat, C * kinds * op->nclusters * nq * sizeof(double2), acct))) return st;
     if ((st = alloc(op->d_yhat, C * kinds * op->nclusters * nq * sizeof(double2), acct))) return st;
     if (hard && (st = alloc(op->d_yraw, C * nvec * op->nclusters * nq * sizeof(double2), acct))) return st;
-    if ((st = alloc(op->d_part, C * std::max<size_t>(1, op->chunk_len.size()) * nvec * nq * sizeof(double2), acct)))
+    if ((st = alloc(op->d_part, C * std::max<size_t>(1, op->chunks.len.size()) * nvec * nq * sizeof(double2), acct)))
         return st;
+    if (op->prm.precision != IGB_FP64) {
+        const size_t ncolp = (C + 15) / 16 * 16;
+        if ((st = alloc(op->d_xlo, size_t(op->nclusters) * (hard ? 7 : 1) * ncolp * lo_kbp(op) * lo_esz(op), acct)))
+            return st;
+        if ((st = alloc(op->d_part_lo, C * std::max<size_t>(1, op->chunks_mfma.len.size()) * nvec * nq * sizeof(float2),
+                        acct)))
+            return st;
+    }
     if ((st = alloc(op->d_yfar, C * op->geom->n2 * sizeof(double2), acct))) return st;
     if ((st = alloc(op->d_x2, C * op->geom->n2 * sizeof(double2), acct))) return st;
     const int64_t w = (int64_t(1) << op->d) + op->geom->p;
@@ -1682,42 +1940,71 @@ igb_status timer_mark(igb_op op, int slot, hipStream_t s) {
     return IGB_OK;
 }
 
-// columns per coupling workgroup: the soft kernel keeps 8 accumulators per
-// lane, the hard one 10 per column
-template <int NT, class CT>
-static void launch_m2l_t(igb_op op, const CT* coup, double2* xh, int64_t ks, int ncol, hipStream_t s) {
-    const int64_t nchunk = int64_t(op->chunk_len.size());
+// vector path (fp64 couplings): the soft kernel keeps 8 accumulators per lane,
+// the hard one 10 per column
+template <int NT>
+static void launch_m2l_fp64(igb_op op, double2* xh, int64_t ks, int ncol, hipStream_t s) {
+    const double2* coup = op->d_coupling.as<double2>();
+    const M2LChunks& C = op->chunks;
+    const int64_t nchunk = int64_t(C.len.size());
     if (op->bc == IGB_HARD) {
         constexpr int RB = 2;
-        hipLaunchKernelGGL((m2l_hard_chunks<NT, CT, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
+        hipLaunchKernelGGL((m2l_hard_chunks<NT, double2, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
                            dim3(NT), 0, s, coup, xh, ks, op->d_nodes.as<double>(), op->d_far_src.as<int>(),
-                           op->d_chunk_pair.as<int64_t>(), op->d_chunk_len.as<int>(), nchunk, op->nq, ncol,
-                           op->d_part.as<double2>());
+                           C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol, op->d_part.as<double2>());
     } else if (ncol == 1) {
-        hipLaunchKernelGGL((m2l_chunks<NT, CT, 1>), dim3(unsigned(nchunk), 1u), dim3(NT), 0, s, coup, xh,
-                           op->d_far_src.as<int>(), op->d_chunk_pair.as<int64_t>(), op->d_chunk_len.as<int>(),
-                           nchunk, op->nq, ncol, op->d_part.as<double2>());
+        hipLaunchKernelGGL((m2l_chunks<NT, double2, 1>), dim3(unsigned(nchunk), 1u), dim3(NT), 0, s, coup, xh,
+                           op->d_far_src.as<int>(), C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol,
+                           op->d_part.as<double2>());
     } else {
         constexpr int RB = 8;
-        hipLaunchKernelGGL((m2l_chunks<NT, CT, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)), dim3(NT),
-                           0, s, coup, xh, op->d_far_src.as<int>(), op->d_chunk_pair.as<int64_t>(),
-                           op->d_chunk_len.as<int>(), nchunk, op->nq, ncol, op->d_part.as<double2>());
+        hipLaunchKernelGGL((m2l_chunks<NT, double2, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
+                           dim3(NT), 0, s, coup, xh, op->d_far_src.as<int>(), C.d_pair.as<int64_t>(), C.d_len.as<int>(),
+                           nchunk, op->nq, ncol, op->d_part.as<double2>());
     }
 }
 
-template <int NT>
-static void launch_m2l_nt(igb_op op, bool low, double2* xh, int64_t ks, int ncol, hipStream_t s) {
-    if (!low)
-        launch_m2l_t<NT>(op, op->d_coupling.as<double2>(), xh, ks, ncol, s);
-    else if (op->prm.precision == IGB_MIX_FP32)
-        launch_m2l_t<NT>(op, op->d_coupling_lo.as<float2>(), xh, ks, ncol, s);
-    else
-        launch_m2l_t<NT>(op, op->d_coupling_lo.as<bf16x2>(), xh, ks, ncol, s);
+// matrix-core path (reduced-precision couplings)
+template <class OPS, bool HARD>
+static void launch_m2l_lo_t(igb_op op, const double2* xh, int64_t ks, int ncol, hipStream_t s) {
+    using LT = typename OPS::LT;
+    const M2LChunks& C = op->chunks_mfma;
+    const int64_t nchunk = int64_t(C.len.size());
+    const int ncolp = (ncol + 15) / 16 * 16, kbp = lo_kbp(op), nq = op->nq;
+    const int64_t nv = op->nclusters * (HARD ? 7 : 1) * ncolp * kbp;
+    hipLaunchKernelGGL((round_vectors<HARD ? 7 : 1, LT>), dim3(unsigned((nv + 255) / 256)), dim3(256), 0, s, xh, ks,
+                       op->d_nodes.as<double>(), op->nclusters, nq, kbp, ncol, ncolp, op->d_xlo.as<LT>());
+    (void)timer_mark(op, 0, s);
+    if (nchunk > 0)
+        hipLaunchKernelGGL((m2l_mfma<OPS, HARD>), dim3(unsigned(nchunk), unsigned(ncolp / 16)),
+                           dim3(64 * ((nq + 15) / 16)), 0, s, op->d_coupling_lo.as<LT>(), lo_nkc(op),
+                           op->d_xlo.as<LT>(), kbp, ncolp, op->d_far_src.as<int>(), C.d_pair.as<int64_t>(),
+                           C.d_len.as<int>(), nchunk, nq, ncol, op->d_part_lo.as<float2>());
+    (void)timer_mark(op, 0, s);
 }
 
-static igb_status launch_m2l(igb_op op, double2* xh, int64_t ks, bool low, int ncol, hipStream_t s) {
-    if (op->nq <= 64) launch_m2l_nt<64>(op, low, xh, ks, ncol, s);
-    else launch_m2l_nt<128>(op, low, xh, ks, ncol, s);
+// coupling partials [chunk][nvec][nq][ncol] of the far pairs; returns whether
+// the partials are the fp32 ones of the matrix-core path
+static igb_status launch_m2l(igb_op op, double2* xh, int64_t ks, bool low, int ncol, hipStream_t s, bool& lo) {
+    lo = low && op->prm.precision != IGB_FP64;
+    const bool hard = op->bc == IGB_HARD;
+    if (!lo) {
+        if ((op->nq + 63) / 64 * 64 > 128) {
+            set_error("h2_matvec: interpolation degree too large for the coupling kernel");
+            return IGB_ERR_ARG;
+        }
+        igb_status st;
+        if ((st = timer_mark(op, 0, s))) return st;
+        if (op->nq <= 64) launch_m2l_fp64<64>(op, xh, ks, ncol, s);
+        else launch_m2l_fp64<128>(op, xh, ks, ncol, s);
+        if ((st = timer_mark(op, 0, s))) return st;
+    } else if (op->prm.precision == IGB_MIX_FP32) {
+        if (hard) launch_m2l_lo_t<MfmaF32, true>(op, xh, ks, ncol, s);
+        else launch_m2l_lo_t<MfmaF32, false>(op, xh, ks, ncol, s);
+    } else {
+        if (hard) launch_m2l_lo_t<MfmaBf16, true>(op, xh, ks, ncol, s);
+        else launch_m2l_lo_t<MfmaBf16, false>(op, xh, ks, ncol, s);
+    }
     IGB_HIP(hipGetLastError());
     return IGB_OK;
 }
@@ -1762,15 +2049,19 @@ igb_status matvec_device(igb_op op, const double* x, double* y, int ncol, int pa
             }
         }
         if ((st = timer_mark(op, 2, s))) return st;
-        if ((st = timer_mark(op, 0, s))) return st;
-        if ((st = launch_m2l(op, xh, ks, low && op->prm.precision != IGB_FP64, ncol, s))) return st;
-        if ((st = timer_mark(op, 0, s))) return st;
+        bool lo = false;
+        if ((st = launch_m2l(op, xh, ks, low, ncol, s, lo))) return st;
         if ((st = timer_mark(op, 3, s))) return st;
         const int nvec = hard ? 10 : 1;
         double2* red_out = hard ? op->d_yraw.as<double2>() : yh;
         const int64_t per = int64_t(nvec) * nq * ncol;
-        hipLaunchKernelGGL(m2l_reduce, dim3(blocks_for(op->nclusters * per, 256)), dim3(256), 0, s,
-                           op->d_part.as<double2>(), op->d_tgt_chunk_ptr.as<int>(), op->nclusters, per, red_out);
+        if (lo)
+            hipLaunchKernelGGL(m2l_reduce<float2>, dim3(blocks_for(op->nclusters * per, 256)), dim3(256), 0, s,
+                               op->d_part_lo.as<float2>(), op->chunks_mfma.d_tgt_ptr.as<int>(), op->nclusters, per,
+                               red_out);
+        else
+            hipLaunchKernelGGL(m2l_reduce<double2>, dim3(blocks_for(op->nclusters * per, 256)), dim3(256), 0, s,
+                               op->d_part.as<double2>(), op->chunks.d_tgt_ptr.as<int>(), op->nclusters, per, red_out);
         if (hard)
             hipLaunchKernelGGL(m2l_finalize_hard, dim3(blocks_for(op->nclusters * nq * ncol, 256)), dim3(256), 0, s,
                                op->d_yraw.as<double2>(), op->d_nodes.as<double>(), op->nclusters, nq, op->kappa,

@@ -44,6 +44,30 @@ int d4_code(int c0, int c1 /* -1: unused */) {
 
 }  // namespace
 
+// Splits every target's far list (pairs sorted by target within a level) into
+// chunks of at most `ch` consecutive pairs.
+static void build_chunks(igb_op op, int ch, M2LChunks& out) {
+    const int np = op->geom->npatch;
+    out.tgt.clear();
+    out.pair.clear();
+    out.len.clear();
+    out.tgt_ptr.assign(op->nclusters + 1, 0);
+    for (int l = 0; l <= op->L; ++l) {
+        const FarLevel& F = op->far[l];
+        const int64_t nc = clusters_on_level(np, l);
+        for (int64_t t = 0; t < nc; ++t) {
+            const int a = F.tgt_ptr[t], b = F.tgt_ptr[t + 1];
+            for (int c = a; c < b; c += ch) {
+                out.tgt.push_back(int(op->clu_off[l] + t));
+                out.pair.push_back(F.pair_off + c);
+                out.len.push_back(std::min(ch, b - c));
+                out.tgt_ptr[op->clu_off[l] + t + 1]++;
+            }
+        }
+    }
+    for (int64_t i = 0; i < op->nclusters; ++i) out.tgt_ptr[i + 1] += out.tgt_ptr[i];
+}
+
 igb_status tree_build(igb_op op) {
     igb_geom g = op->geom;
     const int np = g->npatch, m = g->m, nel1 = g->nel1;
@@ -183,26 +207,10 @@ igb_status tree_build(igb_op op) {
         std::sort(src, src + c);
     });
 
-    // M2L work decomposition: chunks of at most CH sources of one target
-    const int CH = 8;
-    op->chunk_tgt.clear();
-    op->chunk_pair.clear();
-    op->chunk_len.clear();
-    op->tgt_chunk_ptr.assign(op->nclusters + 1, 0);
-    for (int l = 0; l <= L; ++l) {
-        const FarLevel& F = op->far[l];
-        const int64_t nc = clusters_on_level(np, l);
-        for (int64_t t = 0; t < nc; ++t) {
-            int a = F.tgt_ptr[t], b = F.tgt_ptr[t + 1];
-            for (int c = a; c < b; c += CH) {
-                op->chunk_tgt.push_back(int(op->clu_off[l] + t));
-                op->chunk_pair.push_back(F.pair_off + c);
-                op->chunk_len.push_back(std::min(CH, b - c));
-                op->tgt_chunk_ptr[op->clu_off[l] + t + 1]++;
-            }
-        }
-    }
-    for (int64_t i = 0; i < op->nclusters; ++i) op->tgt_chunk_ptr[i + 1] += op->tgt_chunk_ptr[i];
+    // M2L work decompositions: chunks of at most M2L_CHUNK (vector path) and
+    // M2L_CHUNK_MFMA (matrix-core path) sources of one target
+    build_chunks(op, M2L_CHUNK, op->chunks);
+    build_chunks(op, M2L_CHUNK_MFMA, op->chunks_mfma);
     return IGB_OK;
 }
 

@@ -55,7 +55,9 @@ class Result:
     matvecs: int
     relres_true: float
     converged: int
+    escalated: int        # directions finished on the fp64 operator
     uinf: np.ndarray      # (ndir, nobs)
+    stages: dict = dataclasses.field(default_factory=dict)   # seconds per stage
 
     @property
     def latency(self) -> float:
@@ -109,20 +111,29 @@ class Server:
         return int(op.info.estimated_bytes + geom_bytes + krylov + nd * self.cfg.nobs * 16)
 
     def solve(self, req: I.Request, ctx: B.Context):
+        """Returns (n, solve info, far field [ndir][nobs], stage seconds)."""
         import torch
+        t0 = time.perf_counter()
         geo = B.Geometry(ctx, self._patches(req), req.m, self.cfg.p)
+        t1 = time.perf_counter()
         op = B.Operator(ctx, geo, **self._op_args(req))
+        t2 = time.perf_counter()
         nd = len(req.dirs)
         dev = torch.device("cuda", self.cfg.device)
         coeff = torch.empty((nd, op.n), dtype=torch.complex128, device=dev)
         uinf = torch.empty((nd, self.cfg.nobs), dtype=torch.complex128, device=dev)
         restart = self.cfg.restart_soft if req.bc == "soft" else self.cfg.restart_hard
         info, st = op.cfie_solve(req.dirs, coeff, tol=self.cfg.tol, restart=restart, maxit=self.cfg.maxit)
+        t3 = time.perf_counter()
         op.farfield(coeff, self.obs, uinf, ndir=nd, stream=B.CONTEXT_STREAM)
         u = uinf.cpu().numpy()
+        t4 = time.perf_counter()
+        oi = op.info
+        stages = {"geometry": t1 - t0, "assembly": t2 - t1, "assembly_near_gpu": oi.assembly_near_ms * 1e-3,
+                  "assembly_far_gpu": oi.assembly_far_ms * 1e-3, "solve": t3 - t2, "farfield": t4 - t3}
         n = op.n
         del op, geo, coeff, uinf
-        return n, info, u
+        return n, info, u, stages
 
     # -------------------------------------------------------------- serving
     def run(self, requests, realtime: bool = True, log=None):
@@ -176,9 +187,9 @@ class Server:
                 admitted = now()
                 try:
                     if self.solve_fn is not None:
-                        n, info, u = self.solve_fn(pick, slot)
+                        n, info, u, *rest = self.solve_fn(pick, slot)
                     else:
-                        n, info, u = self.solve(pick, self.ctxs[slot])
+                        n, info, u, *rest = self.solve(pick, self.ctxs[slot])
                 except Exception as exc:  # recorded, the stream continues
                     with lock:
                         state["errors"].append((pick.rid, repr(exc)))
@@ -187,7 +198,8 @@ class Server:
                     continue
                 done = now()
                 res = Result(pick.rid, pick.arrival, admitted, done, n, est[pick.rid], info.iters, info.matvecs,
-                             info.relres_true, info.converged, u)
+                             info.relres_true, info.converged, getattr(info, "escalated", 0), u,
+                             rest[0] if rest else {})
                 with lock:
                     results[pick.rid] = res
                     state["free"] += est[pick.rid]
@@ -214,4 +226,5 @@ class Server:
                 "direction_solves_per_s": cols / wall, "column_matvecs_per_s": sum(r.matvecs for r in results) / wall,
                 "p50_latency_s": percentile(lat, 50), "p99_latency_s": percentile(lat, 99),
                 "max_relres_true": max(r.relres_true for r in results),
+                "escalated_directions": sum(r.escalated for r in results),
                 "all_converged": all(r.converged == r.uinf.shape[0] for r in results)}
