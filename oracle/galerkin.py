@@ -332,11 +332,19 @@ class DenseBEM:
         s2_to_s0, n0 = disc.s0_map()
         reps = np.nonzero(np.isin(s2_to_s0, rows))[0]
         parts = self.operator_rows_s2(reps)
-        P = disc.glue_matrix()
         R = np.zeros((len(rows), len(reps)))
         for k, r in enumerate(rows):
             R[k, s2_to_s0[reps] == r] = 1.0
-        parts = {k: R @ v @ P for k, v in parts.items()}
+
+        def glue(v):
+            # (R v) P with P the S^0 -> S^2 gluing matrix, without forming P:
+            # column i of R v adds to column s2_to_s0[i]
+            rv = R @ v
+            out = np.zeros((rv.shape[0], n0), dtype=rv.dtype)
+            np.add.at(out, (slice(None), s2_to_s0), rv)
+            return out
+
+        parts = {k: glue(v) for k, v in parts.items()}
         return self._combine(parts)
 
     # ------------------------------------------------------------ rhs / far field

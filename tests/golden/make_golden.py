@@ -16,6 +16,10 @@ Cases
                       rows of the dense O1 matrix applied to the seeded vector.
   sphere_m3_p2_k2_q4_hard / sphere_m2_p2_k1_hard  the same two small checks for
                       the sound-hard operator (regularised W) on S^0.
+  star_m6_p2_k16_rows  seed-0 star, m = 6, p = 2, kappa = 16, soft: sampled rows
+                      of the dense O1 matrix applied to the seeded vector.
+  star_m7_p2_k32_hard_rows  seed-0 star, m = 7, p = 2, kappa = 32, hard (S^0):
+                      the same for four rows.
 """
 from __future__ import annotations
 
@@ -90,12 +94,30 @@ def case_sphere_m2_p2_k1_hard():
                 mie=mie.farfield(1.0, obs @ d, "hard"), x=I.random_complex(X_SEED, bem.n))
 
 
+def _star_rows(m, kappa, bc, nrows):
+    bem = G.DenseBEM(I.star_patches(0, I.star_geometry_level(m)), p=2, m=m, kappa=kappa, bc=bc)
+    x = I.random_complex(X_SEED, bem.n)
+    rows = np.sort(np.random.default_rng(ROW_SEED).choice(bem.n, nrows, replace=False))
+    R = bem.rows(rows)
+    return dict(rows=rows.astype(np.int64), y=R @ x, rownorm1=np.abs(R).sum(1), x=x)
+
+
+def case_star_m6_p2_k16_rows():
+    return _star_rows(6, 16.0, "soft", 6)
+
+
+def case_star_m7_p2_k32_hard_rows():
+    return _star_rows(7, 32.0, "hard", 4)
+
+
 CASES = {
     "sphere_m3_p2_k2_q4_hard": case_sphere_m3_p2_k2_q4_hard,
     "sphere_m2_p2_k1_hard": case_sphere_m2_p2_k1_hard,
     "sphere_m3_p2_k2_q4": case_sphere_m3_p2_k2_q4,
     "sphere_m2_p1_k1": case_sphere_m2_p1_k1,
     "sphere_m5_p2_k8_rows": case_sphere_m5_p2_k8_rows,
+    "star_m6_p2_k16_rows": case_star_m6_p2_k16_rows,
+    "star_m7_p2_k32_hard_rows": case_star_m7_p2_k32_hard_rows,
 }
 
 
