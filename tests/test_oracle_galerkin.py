@@ -116,3 +116,14 @@ def test_default_coupling_keeps_sphere_modes_in_right_half_plane(kappa):
     assert soft.real.min() > 0.4 and hard.real.min() > 0.4
     flipped = 0.5 - mie.eig_K(n, kappa) - 1j / kappa * mie.eig_W(n, kappa)
     assert (flipped.real < 0).any() == (kappa >= 2)
+
+
+@pytest.mark.parametrize("bc", ["soft", "hard"])
+def test_sampled_rows_equal_dense_matrix_rows(bc):
+    """The sampled-row path used for large sizes (hard: S^0 gluing by index
+    accumulation) reproduces rows of the dense matrix."""
+    bem = G.DenseBEM(inputs.sphere_patches(), p=2, m=1, kappa=1.5, bc=bc)
+    A = bem.matrix()
+    rows = np.array([0, 7, bem.n // 2, bem.n - 1])
+    R = bem.rows(rows)
+    assert np.abs(R - A[rows]).max() < 1e-12 * np.abs(A).max()
