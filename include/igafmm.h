@@ -87,11 +87,22 @@ typedef enum { IGB_FP64 = 0, IGB_MIX_FP32 = 1, IGB_MIX_BF16 = 2 } igb_prec;
  *   kcap       if > 0, a block is admissible only if kappa*max(diam) <= kcap
  *   leaf_depth clusters stop at 4^leaf_depth elements (leaf level m - leaf_depth),
  *              0 <= leaf_depth <= 6
- *   precision  far-field coupling storage: IGB_FP64; IGB_MIX_FP32 / IGB_MIX_BF16 keep
- *              the fp64 couplings and add a copy rounded (RNE) to fp32 / bf16 that
- *              cfie_solve uses inside iterative refinement (inner GMRES on the
- *              rounded far field, outer residual in fp64) and h2_matvec uses with
- *              IGB_MV_LOWPREC; near field, Arnoldi and residuals stay fp64 */
+ *   precision  far-field coupling storage: IGB_FP64; IGB_MIX_FP32 / IGB_MIX_BF16 add
+ *              couplings rounded (RNE) to fp32 / bf16 that cfie_solve uses inside
+ *              iterative refinement (inner GMRES on the rounded far field with fp32
+ *              accumulation on the matrix cores, outer residual in fp64) and
+ *              h2_matvec uses with IGB_MV_LOWPREC; near field, Arnoldi and residuals
+ *              stay fp64
+ *   far_on_the_fly  0: the fp64 couplings are stored ((q+1)^4 complex per far pair,
+ *              two for IGB_HARD); 1: none are stored and every fp64 far-field
+ *              product (fp64 matvecs, refinement residuals) evaluates the kernel at
+ *              the node pairs as it goes: the same interpolated operator (to
+ *              rounding), no coupling memory, bound by fp64 arithmetic
+ *   quad_extra Gauss points per direction added to the default near-field rules
+ *              (regular pairs: 4..7 by distance / size, raised with kappa * size,
+ *              here at most 10; touching pairs: 7 / 8 / 9 for identical / edge /
+ *              vertex, here at most 12), 0 <= quad_extra <= 3: accuracy of the
+ *              near field against assembly time */
 typedef struct {
     double kappa;
     int bc;
@@ -101,6 +112,8 @@ typedef struct {
     double kcap;
     int leaf_depth;
     int precision;
+    int far_on_the_fly;
+    int quad_extra;
 } igb_op_params;
 
 typedef struct {

@@ -160,6 +160,14 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
         set_error("assemble_nearfield: precision must be IGB_FP64, IGB_MIX_FP32 or IGB_MIX_BF16");
         return IGB_ERR_ARG;
     }
+    if (prm->far_on_the_fly != 0 && prm->far_on_the_fly != 1) {
+        set_error("assemble_nearfield: far_on_the_fly must be 0 or 1");
+        return IGB_ERR_ARG;
+    }
+    if (prm->quad_extra < 0 || prm->quad_extra > 3) {
+        set_error("assemble_nearfield: need 0 <= quad_extra <= 3");
+        return IGB_ERR_ARG;
+    }
     if (prm->bc == IGB_HARD && g->p < 1) {
         set_error("assemble_nearfield: sound-hard needs S^0, i.e. p >= 1");
         return IGB_ERR_ARG;
@@ -186,7 +194,8 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
     // device bytes of the operator (checked against the budget before allocating)
     const int nl = (g->p + 1) * (g->p + 1);
     const int ntile = prm->bc == IGB_HARD ? 2 : 1;
-    size_t need = size_t(op->nfar) * op->nq * op->nq * 16 * ntile + size_t(op->nnz) * 20 + size_t(op->N + 1) * 8 +
+    const size_t fp64_tiles = prm->far_on_the_fly ? 0 : size_t(op->nfar) * op->nq * op->nq * 16 * ntile;
+    size_t need = fp64_tiles + size_t(op->nnz) * 20 + size_t(op->N + 1) * 8 +
                   size_t(op->nclusters) * op->nq * (16 * 8 + 32) + op->near_src.size() * 4 +
                   std::min<size_t>(op->near_src.size(), size_t(1) << 22) * nl * nl * 16;
     if (prm->precision != IGB_FP64) {

@@ -156,7 +156,7 @@ __device__ __forceinline__ double2 kernel_soft(const double* X, const double* NX
 // Near field: regular element pairs (tensor Gauss of order n on both elements)
 // --------------------------------------------------------------------------
 constexpr int NEAR_THREADS = 256;
-constexpr int NGMAX = 10;
+constexpr int NGMAX = 12;
 
 struct NearArgs {
     const double* bez;
@@ -243,17 +243,16 @@ __device__ __forceinline__ void point_data(const ElemRef& R, const double* Cu, c
 }
 
 // --------------------------------------------------------------------------
-// Near field: regular element pairs, tensor Gauss of order n (<= 7) on both
-// elements.  Kernel values are produced in chunks of CI test points in LDS;
+// Near field: regular element pairs, tensor Gauss of order n (n*n <= MAXQ) on
+// both elements.  Kernel values are produced in chunks of CI test points in LDS;
 // thread items (j, a) accumulate T[j][a] = sum_i w phi_a(x_i) k(x_i, y_j);
 // finally B[a][b] = sum_j T[j][a] . w phi_b(y_j).
 // --------------------------------------------------------------------------
-template <int P, bool HARD>
+template <int P, bool HARD, int MAXQ>
 __global__ __launch_bounds__(NEAR_THREADS) void near_regular(NearArgs A) {
     constexpr int NL = (P + 1) * (P + 1);
     constexpr int NV = HARD ? 4 : 1;
     constexpr int NK = HARD ? 2 : 1;
-    constexpr int MAXQ = 49;
     constexpr int CI = 8;
     constexpr int BUF = (CI * MAXQ * NK > MAXQ * NL * NV) ? CI * MAXQ * NK : MAXQ * NL * NV;
     constexpr int ITEMS = (MAXQ * NL + NEAR_THREADS - 1) / NEAR_THREADS;
@@ -574,6 +573,19 @@ __global__ void coupling_soft(const double* nodes, const int* pair_tgt, const in
     }
 }
 
+// sound-hard raw kernels at a node pair: G = e^{i kappa r}/(4 pi r) and
+// H = G (i kappa r - 1)/r^2 (so grad_y G = H (y - x))
+__device__ __forceinline__ void kernel_gh(const double* X, const double* Y, double kappa, double2& G, double2& H) {
+    const double d0 = X[0] - Y[0], d1 = X[1] - Y[1], d2 = X[2] - Y[2];
+    const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double ir = 1.0 / r, kr = kappa * r;
+    double sn, cs;
+    sincos(kr, &sn, &cs);
+    const double c4 = 0.07957747154594767 * ir;
+    G = make_double2(c4 * cs, c4 * sn);
+    H = make_double2(c4 * ir * ir * (-cs - sn * kr), c4 * ir * ir * (cs * kr - sn));
+}
+
 // sound-hard: raw kernels at node pairs, {G, H}[pair][b*nq + a]; the node-wise
 // factors (measures, normals, tangents) are applied around the coupling product
 __global__ void coupling_hard(const double* nodes, const int* pair_tgt, const int* pair_src, int64_t npairs,
@@ -585,16 +597,7 @@ __global__ void coupling_hard(const double* nodes, const int* pair_tgt, const in
     double2* out = coup + pr * nq * nq * 2;
     for (int idx = threadIdx.x; idx < nq * nq; idx += blockDim.x) {
         const int b = idx / nq, a = idx % nq;
-        const double* X = T + a * 16;
-        const double* Y = S + b * 16;
-        const double d0 = X[0] - Y[0], d1 = X[1] - Y[1], d2 = X[2] - Y[2];
-        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        const double ir = 1.0 / r, kr = kappa * r;
-        double sn, cs;
-        sincos(kr, &sn, &cs);
-        const double c4 = 0.07957747154594767 * ir;
-        out[2 * idx] = make_double2(c4 * cs, c4 * sn);                                        // G
-        out[2 * idx + 1] = make_double2(c4 * ir * ir * (-cs - sn * kr), c4 * ir * ir * (cs * kr - sn));  // H
+        kernel_gh(T + a * 16, S + b * 16, kappa, out[2 * idx], out[2 * idx + 1]);
     }
 }
 
@@ -875,23 +878,36 @@ template <> __device__ __forceinline__ bf16x2 round_to<bf16x2>(double2 v) {
     return b;
 }
 
-// rounded tiles from the fp64 couplings [pair][b][a][tile]
-template <class LT>
-__global__ void round_coupling_tiles(const double2* __restrict__ in, int64_t nfar, int nq, int nkc, int ntile,
-                                     LT* __restrict__ out) {
-    constexpr int EPL = 16 / sizeof(LT);
+// rounded tiles in matrix-core order, each entry evaluated in fp64 by the same
+// functions as the fp64 tiles and rounded once (no fp64 tiles needed)
+template <class LT, bool HARD>
+__global__ void coupling_lo(const double* __restrict__ nodes, const int* __restrict__ pair_tgt,
+                            const int* __restrict__ pair_src, int64_t nfar, int nq, int nkc, double kappa, double eta,
+                            LT* __restrict__ out) {
+    constexpr int EPL = 16 / sizeof(LT), NT = HARD ? 2 : 1;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= nfar * ntile * nkc * nq * EPL) return;
+    if (i >= nfar * NT * nkc * nq * EPL) return;
     const int e = int(i % EPL);
     int64_t r = i / EPL;
     const int a = int(r % nq);
     r /= nq;
     const int kc = int(r % nkc);
     r /= nkc;
-    const int t = int(r % ntile);
-    const int64_t pr = r / ntile;
+    const int t = int(r % NT);
+    const int64_t pr = r / NT;
     const int b = kc * EPL + e;
-    const double2 v = b < nq ? in[(pr * nq * nq + int64_t(b) * nq + a) * ntile + t] : make_double2(0, 0);
+    double2 v = make_double2(0, 0);
+    if (b < nq) {
+        const double* X = nodes + (int64_t(pair_tgt[pr]) * nq + a) * 16;
+        const double* Y = nodes + (int64_t(pair_src[pr]) * nq + b) * 16;
+        if (HARD) {
+            double2 G, H;
+            kernel_gh(X, Y, kappa, G, H);
+            v = t == 0 ? G : H;
+        } else {
+            v = kernel_soft(X, X + 3, X[6], Y, Y[6], kappa, eta);
+        }
+    }
     out[i] = round_to<LT>(v);
 }
 
@@ -1100,6 +1116,244 @@ __global__ __launch_bounds__(512) void m2l_mfma(const typename OPS::LT* __restri
         }
 }
 
+// Sound-soft coupling on the matrix cores with B reuse: the 4 waves of a
+// workgroup take every 4th pair of the chunk, and each wave computes all MT
+// row tiles of its pairs, so one B fragment per k block serves MT products.
+// The waves' sums meet in LDS and are added in wave order (fixed).
+template <class OPS, int MT>
+__global__ __launch_bounds__(256) void m2l_mfma_soft(const typename OPS::LT* __restrict__ coup, int nkc,
+                                                     const typename OPS::LT* __restrict__ xlo, int kbp, int ncolp,
+                                                     const int* __restrict__ far_src_g,
+                                                     const int64_t* __restrict__ chunk_pair,
+                                                     const int* __restrict__ chunk_len, int64_t nchunk, int nq,
+                                                     int ncol, float2* __restrict__ part) {
+    using LT = typename OPS::LT;
+    constexpr int KB = OPS::KB, EPL = OPS::EPL, NW = 4;
+    __shared__ f32x4 red[NW - 1][MT][2][64];
+    const int64_t ch = xcd_chunk(blockIdx.x, nchunk);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    const int c0 = blockIdx.y * 16;
+    const int64_t p0 = chunk_pair[ch];
+    const int len = chunk_len[ch];
+    const int nkb = (nq + KB - 1) / KB;
+    const int64_t tile_el = int64_t(nkc) * nq * EPL;
+    const int64_t vstride = int64_t(ncolp) * kbp;
+    const int srcv = lane < len ? far_src_g[p0 + lane] : 0;
+    // lane offsets: rows past nq re-read row nq-1 (outputs not stored)
+    unsigned offA[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) offA[mt] = unsigned((g * nq + min(mt * 16 + li, nq - 1)) * EPL);
+    const unsigned offB = unsigned((g * ncolp + c0 + li) * EPL);
+    f32x4 acc[MT][2];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt][0] = acc[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // this wave's steps: pairs wave, wave+4, ..., k blocks 0..nkb-1; loads past
+    // the last step repeat it (in bounds, unused) so they are unconditional
+    const int npair = len > wave ? (len - wave + NW - 1) / NW : 0;
+    const int nstep = npair * nkb;
+    int ni = 0, nkbi = 0;
+    auto load = [&](uint4 (&A)[MT], uint4& X) {
+        const int i = wave + NW * min(ni, max(npair - 1, 0)), kb = nkbi;
+        const bool last = ni >= npair - 1 && nkbi == nkb - 1;
+        nkbi = last ? nkbi : (nkbi + 1 == nkb ? 0 : nkbi + 1);
+        ni = last ? ni : (nkbi == 0 ? ni + 1 : ni);
+        const int ic = min(i, len - 1);
+        const int src = __builtin_amdgcn_readlane(srcv, ic);
+        const LT* Au = coup + (p0 + ic) * tile_el + kb * (4 * nq * EPL);
+        const LT* Bu = xlo + int64_t(src) * vstride + kb * (4 * ncolp * EPL);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) A[mt] = *reinterpret_cast<const uint4*>(Au + offA[mt]);
+        X = *reinterpret_cast<const uint4*>(Bu + offB);
+    };
+    auto compute = [&](const uint4 (&A)[MT], const uint4& X) {
+        const uint4 xr = OPS::re_part(X), xi = OPS::im_part(X);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            acc[mt][0] = OPS::step(A[mt], xr, acc[mt][0]);
+            acc[mt][1] = OPS::step(A[mt], xi, acc[mt][1]);
+        }
+    };
+    if (nstep > 0) {
+        uint4 A0[MT], A1[MT], X0, X1;
+        load(A0, X0);
+        for (int j = 0; j < nstep; j += 2) {
+            load(A1, X1);
+            compute(A0, X0);
+            if (j + 1 >= nstep) break;
+            load(A0, X0);
+            compute(A1, X1);
+        }
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            red[wave - 1][mt][0][lane] = acc[mt][0];
+            red[wave - 1][mt][1][lane] = acc[mt][1];
+        }
+    }
+    __syncthreads();
+    if (wave > 0) return;
+    const int c = c0 + li;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        f32x4 s0 = acc[mt][0], s1 = acc[mt][1];
+#pragma unroll
+        for (int w = 0; w < NW - 1; ++w) {
+            s0 += red[w][mt][0][lane];
+            s1 += red[w][mt][1][lane];
+        }
+        if (c >= ncol) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ar = mt * 16 + 4 * g + r;
+            if (ar < nq) part[(ch * nq + ar) * ncol + c] = make_float2(s0[r], s1[r]);
+        }
+    }
+}
+
+// fp64 coupling without stored tiles: the kernel is evaluated at every node
+// pair as the product runs (source node geometry and moments staged in LDS,
+// the target node in registers).  Same operator as the stored tiles up to
+// rounding; partials and their reduction as in the stored-tile kernels.
+template <int NT, int RB>
+__global__ __launch_bounds__(NT) void m2l_otf_soft(const double* __restrict__ nodes, const double2* __restrict__ xh,
+                                                   const int* __restrict__ far_src_g,
+                                                   const int* __restrict__ chunk_tgt,
+                                                   const int64_t* __restrict__ chunk_pair,
+                                                   const int* __restrict__ chunk_len, int64_t nchunk, int nq, int ncol,
+                                                   double kappa, double eta, double2* __restrict__ part) {
+    __shared__ double ys[NT][8];
+    __shared__ double2 xs[NT * RB];
+    const int64_t ch = blockIdx.x;
+    if (ch >= nchunk) return;
+    const int c0 = blockIdx.y * RB;
+    const int a = threadIdx.x;
+    const int64_t p0 = chunk_pair[ch];
+    const int len = chunk_len[ch];
+    double X[7];
+    if (a < nq) {
+        const double* T = nodes + (int64_t(chunk_tgt[ch]) * nq + a) * 16;
+#pragma unroll
+        for (int i = 0; i < 7; ++i) X[i] = T[i];
+    }
+    double2 acc[RB];
+#pragma unroll
+    for (int cb = 0; cb < RB; ++cb) acc[cb] = make_double2(0, 0);
+    for (int i = 0; i < len; ++i) {
+        const int64_t src = far_src_g[p0 + i];
+        __syncthreads();
+        if (a < nq) {
+            const double* Y = nodes + (src * nq + a) * 16;
+#pragma unroll
+            for (int j = 0; j < 7; ++j) ys[a][j] = Y[j];
+        }
+        for (int idx = a; idx < nq * RB; idx += NT) {
+            const int cb = idx % RB, b = idx / RB;
+            xs[idx] = c0 + cb < ncol ? xh[(src * nq + b) * ncol + c0 + cb] : make_double2(0, 0);
+        }
+        __syncthreads();
+        if (a < nq) {
+            for (int b = 0; b < nq; ++b) {
+                const double2 kv = kernel_soft(X, X + 3, X[6], ys[b], ys[b][6], kappa, eta);
+#pragma unroll
+                for (int cb = 0; cb < RB; ++cb) acc[cb] = cfma(kv, xs[b * RB + cb], acc[cb]);
+            }
+        }
+    }
+    if (a < nq)
+#pragma unroll
+        for (int cb = 0; cb < RB; ++cb)
+            if (c0 + cb < ncol) part[(ch * nq + a) * ncol + c0 + cb] = acc[cb];
+}
+
+template <int NT, int RB>
+__global__ __launch_bounds__(NT) void m2l_otf_hard(const double* __restrict__ nodes, const double2* __restrict__ xh,
+                                                   int64_t kind_stride, const int* __restrict__ far_src_g,
+                                                   const int* __restrict__ chunk_tgt,
+                                                   const int64_t* __restrict__ chunk_pair,
+                                                   const int* __restrict__ chunk_len, int64_t nchunk, int nq, int ncol,
+                                                   double kappa, double2* __restrict__ part) {
+    __shared__ double ys[NT][3];
+    __shared__ double2 sv[7][NT * RB];
+    const int64_t ch = blockIdx.x;
+    if (ch >= nchunk) return;
+    const int c0 = blockIdx.y * RB;
+    const int a = threadIdx.x;
+    const int64_t p0 = chunk_pair[ch];
+    const int len = chunk_len[ch];
+    double X[3];
+    if (a < nq) {
+        const double* T = nodes + (int64_t(chunk_tgt[ch]) * nq + a) * 16;
+        X[0] = T[0];
+        X[1] = T[1];
+        X[2] = T[2];
+    }
+    double2 rh[4][RB], rg[6][RB];
+#pragma unroll
+    for (int cb = 0; cb < RB; ++cb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) rh[v][cb] = make_double2(0, 0);
+#pragma unroll
+        for (int v = 0; v < 6; ++v) rg[v][cb] = make_double2(0, 0);
+    }
+    for (int i = 0; i < len; ++i) {
+        const int64_t src = far_src_g[p0 + i];
+        __syncthreads();
+        if (a < nq) {
+            const double* Y = nodes + (src * nq + a) * 16;
+            ys[a][0] = Y[0];
+            ys[a][1] = Y[1];
+            ys[a][2] = Y[2];
+        }
+        for (int idx = a; idx < nq * RB; idx += NT) {
+            const int cb = idx % RB, b = idx / RB;
+            const double* Y = nodes + (src * nq + b) * 16;
+            double2 xp = make_double2(0, 0), xu = xp, xv = xp;
+            if (c0 + cb < ncol) {
+                const int64_t o = (src * nq + b) * ncol + c0 + cb;
+                xp = xh[o];
+                xu = xh[kind_stride + o];
+                xv = xh[2 * kind_stride + o];
+            }
+            const double yn = Y[0] * Y[3] + Y[1] * Y[4] + Y[2] * Y[5];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                sv[c][idx] = cscale(xp, Y[3 + c]);
+                sv[4 + c][idx] = make_double2(Y[11 + c] * xu.x - Y[8 + c] * xv.x, Y[11 + c] * xu.y - Y[8 + c] * xv.y);
+            }
+            sv[3][idx] = cscale(xp, yn);
+        }
+        __syncthreads();
+        if (a < nq) {
+            for (int b = 0; b < nq; ++b) {
+                double2 G, H;
+                kernel_gh(X, ys[b], kappa, G, H);
+#pragma unroll
+                for (int cb = 0; cb < RB; ++cb) {
+                    const int o = b * RB + cb;
+                    rh[0][cb] = cfma(H, sv[3][o], rh[0][cb]);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        rh[1 + c][cb] = cfma(H, sv[c][o], rh[1 + c][cb]);
+                        rg[c][cb] = cfma(G, sv[c][o], rg[c][cb]);
+                        rg[3 + c][cb] = cfma(G, sv[4 + c][o], rg[3 + c][cb]);
+                    }
+                }
+            }
+        }
+    }
+    if (a < nq)
+#pragma unroll
+        for (int cb = 0; cb < RB; ++cb) {
+            if (c0 + cb >= ncol) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) part[((ch * 10 + v) * nq + a) * ncol + c0 + cb] = rh[v][cb];
+#pragma unroll
+            for (int v = 0; v < 6; ++v) part[((ch * 10 + 4 + v) * nq + a) * ncol + c0 + cb] = rg[v][cb];
+        }
+}
+
 // coupling, sound-soft: one workgroup per (chunk of source clusters of one
 // target, block of RB columns); lane a owns output row a and RB accumulators
 template <int NT, class CT, int RB>
@@ -1266,7 +1520,10 @@ __global__ void m2l_reduce(const PT* part, const int* tgt_chunk_ptr, int64_t ncl
 
 // y[r][row] = sum_j val x[r][col] (+ far part mapped to the solution space); one
 // wave per row, lanes stride over the row, butterfly reduction (fixed order)
-constexpr int SPMV_RB = 4;
+// (RB columns per pass; consecutive nonzeros of a row mostly have consecutive
+// columns, so the lanes' x reads coalesce.  Each column's operations and
+// their order do not depend on RB.)
+template <int RB>
 __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ row_ptr,
                                                     const int* __restrict__ col,
                                                     const double2* __restrict__ val,
@@ -1279,21 +1536,21 @@ __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ 
     const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     if (row >= nrows) return;
     const int64_t b = row_ptr[row], e = row_ptr[row + 1];
-    for (int c0 = 0; c0 < ncol; c0 += SPMV_RB) {
-        double2 acc[SPMV_RB];
+    for (int c0 = 0; c0 < ncol; c0 += RB) {
+        double2 acc[RB];
 #pragma unroll
-        for (int cb = 0; cb < SPMV_RB; ++cb) acc[cb] = make_double2(0, 0);
+        for (int cb = 0; cb < RB; ++cb) acc[cb] = make_double2(0, 0);
         if (use_near) {
             for (int64_t idx = b + lane; idx < e; idx += 64) {
                 const double2 v = val[idx];
                 const int64_t cc = col[idx];
 #pragma unroll
-                for (int cb = 0; cb < SPMV_RB; ++cb)
+                for (int cb = 0; cb < RB; ++cb)
                     if (c0 + cb < ncol) acc[cb] = cfma(v, x[int64_t(c0 + cb) * nrows + cc], acc[cb]);
             }
         }
 #pragma unroll
-        for (int cb = 0; cb < SPMV_RB; ++cb)
+        for (int cb = 0; cb < RB; ++cb)
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) {
                 acc[cb].x += __shfl_xor(acc[cb].x, off, 64);
@@ -1301,7 +1558,7 @@ __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ 
             }
         if (lane == 0) {
 #pragma unroll
-            for (int cb = 0; cb < SPMV_RB; ++cb) {
+            for (int cb = 0; cb < RB; ++cb) {
                 const int r = c0 + cb;
                 if (r >= ncol) continue;
                 double2 a = acc[cb];
@@ -1630,7 +1887,8 @@ static igb_status near_launch(igb_op op, hipStream_t s) {
     if ((st = upload(d_kind, op->near_kind.data(), op->near_kind.size(), nullptr))) return st;
     std::vector<double> gl = gauss_table();
     if ((st = upload(d_gl, gl.data(), gl.size(), nullptr))) return st;
-    const int ord[3] = {NSING_VERTEX, NSING_EDGE, NSING_IDENT};
+    const int ord[3] = {NSING_VERTEX + op->prm.quad_extra, NSING_EDGE + op->prm.quad_extra,
+                        NSING_IDENT + op->prm.quad_extra};
     NearArgs A{};
     for (int c = 0; c < 3; ++c) {
         std::vector<double> r = duffy_rule(c, ord[c]);
@@ -1686,7 +1944,12 @@ static igb_status near_launch(igb_op op, hipStream_t s) {
         if (!reg.empty()) {
             A.list = d_list.as<int>();
             A.nlist = int64_t(reg.size());
-            hipLaunchKernelGGL((near_regular<P, HARD>), dim3(unsigned(reg.size())), dim3(NEAR_THREADS), 0, s, A);
+            if (op->prm.quad_extra == 0)
+                hipLaunchKernelGGL((near_regular<P, HARD, 49>), dim3(unsigned(reg.size())), dim3(NEAR_THREADS), 0, s,
+                                   A);
+            else
+                hipLaunchKernelGGL((near_regular<P, HARD, 100>), dim3(unsigned(reg.size())), dim3(NEAR_THREADS), 0, s,
+                                   A);
             IGB_HIP(hipGetLastError());
         }
         if (!sing.empty()) {
@@ -1847,8 +2110,10 @@ igb_status assemble_far_device(igb_op op, hipStream_t s) {
     if ((st = upload(d_ptg, ptg.data(), ptg.size(), nullptr))) return st;
     if ((st = upload(op->d_far_src, psg.data(), psg.size(), acct))) return st;
     const bool hard = op->bc == IGB_HARD;
-    if ((st = alloc(op->d_coupling, size_t(op->nfar) * nq * nq * sizeof(double2) * (hard ? 2 : 1), acct))) return st;
-    if (op->nfar > 0) {
+    const bool otf = op->prm.far_on_the_fly != 0;
+    if (!otf && (st = alloc(op->d_coupling, size_t(op->nfar) * nq * nq * sizeof(double2) * (hard ? 2 : 1), acct)))
+        return st;
+    if (op->nfar > 0 && !otf) {
         if (hard)
             hipLaunchKernelGGL(coupling_hard, dim3(unsigned(op->nfar)), dim3(256), 0, s, op->d_nodes.as<double>(),
                                d_ptg.as<int>(), op->d_far_src.as<int>(), op->nfar, nq, op->kappa,
@@ -1858,26 +2123,35 @@ igb_status assemble_far_device(igb_op op, hipStream_t s) {
                                d_ptg.as<int>(), op->d_far_src.as<int>(), op->nfar, nq, op->kappa, op->eta,
                                op->d_coupling.as<double2>());
         IGB_HIP(hipGetLastError());
-        if (op->prm.precision != IGB_FP64) {
-            const int ntile = hard ? 2 : 1;
-            const bool f32 = op->prm.precision == IGB_MIX_FP32;
-            const int nkc = lo_nkc(op);
-            const int64_t ne = op->nfar * ntile * nkc * nq * lo_epl(op);
-            const size_t esz = lo_esz(op), slack = lo_slack(op);
-            if ((st = alloc(op->d_coupling_lo, size_t(ne) * esz + slack, acct))) return st;
-            IGB_HIP(hipMemsetAsync(static_cast<char*>(op->d_coupling_lo.ptr) + size_t(ne) * esz, 0, slack, s));
-            if (f32)
-                hipLaunchKernelGGL(round_coupling_tiles<float2>, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, s,
-                                   op->d_coupling.as<double2>(), op->nfar, nq, nkc, ntile,
-                                   op->d_coupling_lo.as<float2>());
-            else
-                hipLaunchKernelGGL(round_coupling_tiles<bf16x2>, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, s,
-                                   op->d_coupling.as<double2>(), op->nfar, nq, nkc, ntile,
-                                   op->d_coupling_lo.as<bf16x2>());
-            IGB_HIP(hipGetLastError());
-        }
+    }
+    if (op->nfar > 0 && op->prm.precision != IGB_FP64) {
+        const int ntile = hard ? 2 : 1;
+        const bool f32 = op->prm.precision == IGB_MIX_FP32;
+        const int nkc = lo_nkc(op);
+        const int64_t ne = op->nfar * ntile * nkc * nq * lo_epl(op);
+        const size_t esz = lo_esz(op), slack = lo_slack(op);
+        if ((st = alloc(op->d_coupling_lo, size_t(ne) * esz + slack, acct))) return st;
+        IGB_HIP(hipMemsetAsync(static_cast<char*>(op->d_coupling_lo.ptr) + size_t(ne) * esz, 0, slack, s));
+        const dim3 grid(unsigned((ne + 255) / 256)), blk(256);
+        const double* nd = op->d_nodes.as<double>();
+        const int* pt = d_ptg.as<int>();
+        const int* ps = op->d_far_src.as<int>();
+        if (f32 && hard)
+            hipLaunchKernelGGL((coupling_lo<float2, true>), grid, blk, 0, s, nd, pt, ps, op->nfar, nq, nkc, op->kappa,
+                               op->eta, op->d_coupling_lo.as<float2>());
+        else if (f32)
+            hipLaunchKernelGGL((coupling_lo<float2, false>), grid, blk, 0, s, nd, pt, ps, op->nfar, nq, nkc, op->kappa,
+                               op->eta, op->d_coupling_lo.as<float2>());
+        else if (hard)
+            hipLaunchKernelGGL((coupling_lo<bf16x2, true>), grid, blk, 0, s, nd, pt, ps, op->nfar, nq, nkc, op->kappa,
+                               op->eta, op->d_coupling_lo.as<bf16x2>());
+        else
+            hipLaunchKernelGGL((coupling_lo<bf16x2, false>), grid, blk, 0, s, nd, pt, ps, op->nfar, nq, nkc,
+                               op->kappa, op->eta, op->d_coupling_lo.as<bf16x2>());
+        IGB_HIP(hipGetLastError());
     }
     for (M2LChunks* c : {&op->chunks, &op->chunks_mfma}) {
+        if ((st = upload(c->d_tgt, c->tgt.data(), c->tgt.size(), acct))) return st;
         if ((st = upload(c->d_pair, c->pair.data(), c->pair.size(), acct))) return st;
         if ((st = upload(c->d_len, c->len.data(), c->len.size(), acct))) return st;
         if ((st = upload(c->d_tgt_ptr, c->tgt_ptr.data(), c->tgt_ptr.size(), acct))) return st;
@@ -1947,6 +2221,24 @@ static void launch_m2l_fp64(igb_op op, double2* xh, int64_t ks, int ncol, hipStr
     const double2* coup = op->d_coupling.as<double2>();
     const M2LChunks& C = op->chunks;
     const int64_t nchunk = int64_t(C.len.size());
+    if (nchunk == 0) return;
+    if (op->prm.far_on_the_fly) {
+        const double* nd = op->d_nodes.as<double>();
+        if (op->bc == IGB_HARD) {
+            constexpr int RB = 4;
+            hipLaunchKernelGGL((m2l_otf_hard<NT, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
+                               dim3(NT), 0, s, nd, xh, ks, op->d_far_src.as<int>(), C.d_tgt.as<int>(),
+                               C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol, op->kappa,
+                               op->d_part.as<double2>());
+        } else {
+            constexpr int RB = 8;
+            hipLaunchKernelGGL((m2l_otf_soft<NT, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
+                               dim3(NT), 0, s, nd, xh, op->d_far_src.as<int>(), C.d_tgt.as<int>(),
+                               C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol, op->kappa, op->eta,
+                               op->d_part.as<double2>());
+        }
+        return;
+    }
     if (op->bc == IGB_HARD) {
         constexpr int RB = 2;
         hipLaunchKernelGGL((m2l_hard_chunks<NT, double2, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
@@ -1975,7 +2267,26 @@ static void launch_m2l_lo_t(igb_op op, const double2* xh, int64_t ks, int ncol, 
     hipLaunchKernelGGL((round_vectors<HARD ? 7 : 1, LT>), dim3(unsigned((nv + 255) / 256)), dim3(256), 0, s, xh, ks,
                        op->d_nodes.as<double>(), op->nclusters, nq, kbp, ncol, ncolp, op->d_xlo.as<LT>());
     (void)timer_mark(op, 0, s);
-    if (nchunk > 0)
+    if (!HARD && nchunk > 0) {
+        const dim3 grid(unsigned(nchunk), unsigned(ncolp / 16));
+        const LT* cp = op->d_coupling_lo.as<LT>();
+        const LT* xp = op->d_xlo.as<LT>();
+        float2* pp = op->d_part_lo.as<float2>();
+#define IGB_SOFT_MT(MTV)                                                                                          \
+    hipLaunchKernelGGL((m2l_mfma_soft<OPS, MTV>), grid, dim3(256), 0, s, cp, lo_nkc(op), xp, kbp, ncolp,           \
+                       op->d_far_src.as<int>(), C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, nq, ncol, pp)
+        switch ((nq + 15) / 16) {
+            case 1: IGB_SOFT_MT(1); break;
+            case 2: IGB_SOFT_MT(2); break;
+            case 3: IGB_SOFT_MT(3); break;
+            case 4: IGB_SOFT_MT(4); break;
+            case 5: IGB_SOFT_MT(5); break;
+            case 6: IGB_SOFT_MT(6); break;
+            case 7: IGB_SOFT_MT(7); break;
+            default: IGB_SOFT_MT(8); break;
+        }
+#undef IGB_SOFT_MT
+    } else if (nchunk > 0)
         hipLaunchKernelGGL((m2l_mfma<OPS, HARD>), dim3(unsigned(nchunk), unsigned(ncolp / 16)),
                            dim3(64 * ((nq + 15) / 16)), 0, s, op->d_coupling_lo.as<LT>(), lo_nkc(op),
                            op->d_xlo.as<LT>(), kbp, ncolp, op->d_far_src.as<int>(), C.d_pair.as<int64_t>(),
@@ -2083,10 +2394,18 @@ igb_status matvec_device(igb_op op, const double* x, double* y, int ncol, int pa
         if ((st = timer_mark(op, 3, s))) return st;
     }
     if ((st = timer_mark(op, 1, s))) return st;
-    hipLaunchKernelGGL(spmv_combine, dim3(blocks_for(N * 64, 256)), dim3(256), 0, s, op->d_rowptr.as<int64_t>(),
-                       op->d_col.as<int>(), op->d_val.as<double2>(), X, N, far ? op->d_yfar.as<double2>() : nullptr,
-                       g->n2, hard ? op->d_s0_ptr.as<int>() : nullptr, hard ? op->d_s0_reps.as<int>() : nullptr,
-                       (parts & IGB_PART_NEAR) ? 1 : 0, ncol, Y);
+    const double2* yfar = far ? op->d_yfar.as<double2>() : nullptr;
+    const int* s0p = hard ? op->d_s0_ptr.as<int>() : nullptr;
+    const int* s0r = hard ? op->d_s0_reps.as<int>() : nullptr;
+    const int use_near = (parts & IGB_PART_NEAR) ? 1 : 0;
+    const dim3 sg(blocks_for(N * 64, 256)), sb(256);
+    const int64_t* rp = op->d_rowptr.as<int64_t>();
+    const int* cl = op->d_col.as<int>();
+    const double2* vl = op->d_val.as<double2>();
+    if (ncol == 1)
+        hipLaunchKernelGGL(spmv_combine<1>, sg, sb, 0, s, rp, cl, vl, X, N, yfar, g->n2, s0p, s0r, use_near, ncol, Y);
+    else
+        hipLaunchKernelGGL(spmv_combine<4>, sg, sb, 0, s, rp, cl, vl, X, N, yfar, g->n2, s0p, s0r, use_near, ncol, Y);
     IGB_HIP(hipGetLastError());
     if ((st = timer_mark(op, 1, s))) return st;
     return IGB_OK;

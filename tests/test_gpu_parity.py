@@ -123,14 +123,15 @@ def test_level2_sphere_matvec_solve_farfield(bc):
 
 
 @functools.lru_cache(maxsize=None)
-def lowprec_operator(prec, bc="soft", m=3, kappa=2.0, q=4, d=1):
+def lowprec_operator(prec, bc="soft", m=3, kappa=2.0, q=4, d=1, otf=False):
     from paper_2306_11324_amd import inputs as I
     b = B()
-    print(f"case: sphere m={m} p=2 kappa={kappa} q={q} leaf_depth={d} bc={bc} precision={prec}", flush=True)
+    print(f"case: sphere m={m} p=2 kappa={kappa} q={q} leaf_depth={d} bc={bc} precision={prec} "
+          f"far_on_the_fly={otf}", flush=True)
     geo = b.Geometry(ctx(), I.sphere_patches(), m, 2)
-    p = b.MIX_FP32 if prec == "fp32" else b.MIX_BF16
+    p = {"fp64": b.FP64, "fp32": b.MIX_FP32, "bf16": b.MIX_BF16}[prec]
     op = b.Operator(ctx(), geo, kappa=kappa, q=q, leaf_depth=d, precision=p,
-                    bc=b.SOFT if bc == "soft" else b.HARD)
+                    bc=b.SOFT if bc == "soft" else b.HARD, far_on_the_fly=otf)
     return geo, op
 
 
@@ -180,6 +181,45 @@ def test_lowprec_far_product_against_oracle(prec, bc):
     err = rel(ylo, G["y_far"])
     print(f"{prec} {bc}: rel err vs oracle far product {err:.2e}", flush=True)
     assert err < (1e-6 if prec == "fp32" else 2e-2)
+
+
+@BCS
+def test_on_the_fly_far_field_equals_stored_tiles(bc):
+    """fp64 far field evaluated at the node pairs as it goes (no stored tiles)
+    against the stored-tile product and the oracle's step-by-step far product;
+    the rounded tiles, computed from node geometry either way, give bitwise the
+    same reduced-precision product; 5 columns at once equal one at a time."""
+    from paper_2306_11324_amd import inputs as I
+    b = B()
+    G = gold(SMALL[bc])
+    geo, ref = operator(3, 2, 2.0, 4, 1, bc=bc)
+    geo2, otf = lowprec_operator("bf16", bc, otf=True)
+    geo3, lo = lowprec_operator("bf16", bc)
+    assert otf.info.device_bytes < lo.info.device_bytes
+    x = G["x"]
+    y_ref = apply(ref, x, b.PART_FAR)
+    y_otf = apply(otf, x, b.PART_FAR)
+    e1, e2 = rel(y_otf, y_ref), rel(y_otf, G["y_far"])
+    print(f"{bc}: on the fly vs stored {e1:.2e}, vs oracle {e2:.2e}", flush=True)
+    assert e1 < 1e-13 and e2 < 1e-11
+    assert np.array_equal(apply(otf, x, b.PART_FAR | b.MV_LOWPREC), apply(lo, x, b.PART_FAR | b.MV_LOWPREC))
+    X = I.random_complex(99, (5, otf.n))
+    xd = torch.from_numpy(X).cuda()
+    yd = torch.zeros_like(xd)
+    otf.h2_matvec(xd, yd, nrhs=5)
+    torch.cuda.synchronize()
+    Yb = yd.cpu().numpy()
+    for c in range(5):
+        assert np.array_equal(apply(otf, X[c].copy(), b.PART_ALL), Yb[c]), c
+    d = np.array([0.0, 0.0, 1.0])
+    t64 = torch.zeros(ref.n, dtype=torch.complex128, device="cuda")
+    ref.cfie_solve(d, t64, tol=1e-10)
+    tmx = torch.zeros_like(t64)
+    info, st = otf.cfie_solve(d, tmx, tol=1e-10)
+    diff = float(rel(tmx.cpu().numpy(), t64.cpu().numpy()))
+    print(f"{bc}: bf16 + on-the-fly fp64 residual: relres_true {info.relres_true:.2e}, refinements "
+          f"{info.refinements}, solution difference {diff:.2e}", flush=True)
+    assert st == 0 and info.relres_true <= 1e-10 and diff < 1e-7
 
 
 def test_slow_refinement_escalates_to_fp64():
