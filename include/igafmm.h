@@ -12,15 +12,15 @@
  *     column-major in the sense [ncol][n]: each column contiguous.
  *   - "host" pointers are read or written synchronously.  "device" pointers
  *     must point to device memory of the context's GPU; calls that take a
- *     hip_stream argument are ordered on that stream (NULL = the context's own
- *     stream) and return before the device work completes.
+ *     hip_stream argument are ordered on that stream (NULL = the device's null
+ *     stream, IGB_CONTEXT_STREAM = the context's own non-blocking stream) and
+ *     return before the device work completes.
  *   - The caller owns every buffer it passes; the library copies what it keeps.
  *     Handles own their device memory until destroyed; they may be destroyed in
  *     any order (an operator keeps its geometry, a geometry its context alive
- *     until the last dependent handle is destroyed).  Assembled operators are
- *     immutable: concurrent igb_h2_matvec calls on one operator from different
- *     streams are allowed; calls that share an operator's internal work
- *     vectors (h2_matvec, cfie_solve) must not overlap on the same operator.
+ *     until the last dependent handle is destroyed).  Calls on one operator
+ *     (h2_matvec, cfie_solve) use its internal work vectors and must not
+ *     overlap; different operators may run concurrently on different streams.
  *
  * Numbering (patch-major):
  *   elements  e = patch*4^m + ey*2^m + ex  covering [ex,ex+1]x[ey,ey+1]/2^m of the
@@ -45,6 +45,9 @@ extern "C" {
 
 typedef int igb_status;
 #define IGB_OK 0
+/* hip_stream value selecting the context's own stream */
+#define IGB_CONTEXT_STREAM ((void*)(~(uintptr_t)0))
+
 #define IGB_ERR_ARG (-1)       /* invalid argument                                   */
 #define IGB_ERR_GEOMETRY (-2)  /* invalid knots / weights / non-conforming patches   */
 #define IGB_ERR_BUDGET (-3)    /* the context's HBM budget would be exceeded          */
@@ -124,6 +127,8 @@ typedef struct {
                         <= 0 selects 0 (fp32) / 1e-3 (bf16)                             */
     int refine_max;  /* mixed precision: maximal refinement steps on the reduced-precision
                         operator (<= 0: 10); a column escalated to fp64 gets up to 3 more */
+    int verbose;     /* 1: one line on stderr per restart cycle and refinement step
+                        (Arnoldi steps, largest relative residual, elapsed seconds)   */
 } igb_solve_params;
 
 typedef struct {
@@ -219,6 +224,17 @@ igb_status igb_op_near_pairs(igb_op op, int64_t* ptr, int32_t* src, int32_t* kin
  * and total milliseconds, then clears that kernel's record. */
 igb_status igb_op_profile(igb_op op, int enable);
 igb_status igb_op_kernel_time(igb_op op, const char* name, int64_t* launches, double* total_ms);
+
+/* HIP graphs for the matvec (off by default): with enable = 1, each distinct
+ * (x, y, nrhs, parts, stream) of h2_matvec and of the matvecs inside
+ * cfie_solve is captured once from a non-null stream into a HIP graph of
+ * kernel launches and replayed afterwards, which removes the host launch cost
+ * of the ~20 kernels per application.  Capture puts the stream in capture
+ * mode for the length of one launch sequence: enable it only while no other
+ * host thread of the process issues work to the null stream or synchronous
+ * copies (HIP refuses those during a capture).  Captures are dropped when the
+ * operator's work buffers grow and when graphs are disabled. */
+igb_status igb_op_use_graphs(igb_op op, int enable);
 
 #define IGB_PART_NEAR 1
 #define IGB_PART_FAR 2

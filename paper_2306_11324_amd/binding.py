@@ -48,7 +48,7 @@ class IgbOpParams(C.Structure):
 
 class IgbSolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("inner_tol", C.c_double),
-                ("refine_max", C.c_int)]
+                ("refine_max", C.c_int), ("verbose", C.c_int)]
 
 
 class IgbSolveInfo(C.Structure):
@@ -86,6 +86,7 @@ _SIGS = {
                              C.POINTER(IgbSolveInfo)]),
     "farfield": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double), C.c_int, _P, _P]),
     "igb_op_profile": (C.c_int, [_P, C.c_int]),
+    "igb_op_use_graphs": (C.c_int, [_P, C.c_int]),
     "igb_op_kernel_time": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "igb_last_error": (C.c_char_p, []),
 }
@@ -124,7 +125,7 @@ def _dptr(t, n_complex=None):
 
 def _stream(stream):
     if stream == CONTEXT_STREAM:
-        return C.c_void_p(None)
+        return C.c_void_p(2 ** 64 - 1)   # IGB_CONTEXT_STREAM
     if stream is None:
         import torch
         return C.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -228,6 +229,10 @@ class Operator:
     def profile(self, enable: bool = True):
         _check("igb_op_profile", _lib.igb_op_profile(self.h, 1 if enable else 0))
 
+    def use_graphs(self, enable: bool = True):
+        """Capture the matvec into HIP graphs (single-threaded use; see the header)."""
+        _check("igb_op_use_graphs", _lib.igb_op_use_graphs(self.h, 1 if enable else 0))
+
     def kernel_time(self, name: str):
         """(launches, total ms) of the named kernel since the last query."""
         n = C.c_int64()
@@ -246,9 +251,10 @@ class Operator:
         _check("cfie_rhs", _lib.cfie_rhs(self.h, pd, d.shape[0], _dptr(b, d.shape[0] * self.n), _stream(stream)))
         return b
 
-    def cfie_solve(self, dirs, coeffs, tol=1e-8, restart=30, maxit=1000, inner_tol=0.0, refine_max=0):
+    def cfie_solve(self, dirs, coeffs, tol=1e-8, restart=30, maxit=1000, inner_tol=0.0, refine_max=0,
+                   verbose=False):
         d, pd = _dbl(np.atleast_2d(dirs))
-        sp = IgbSolveParams(tol, restart, maxit, inner_tol, refine_max)
+        sp = IgbSolveParams(tol, restart, maxit, inner_tol, refine_max, 1 if verbose else 0)
         info = IgbSolveInfo()
         st = _check("cfie_solve", _lib.cfie_solve(self.h, pd, d.shape[0], C.byref(sp),
                                                   _dptr(coeffs, d.shape[0] * self.n), C.byref(info)),

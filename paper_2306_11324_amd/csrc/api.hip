@@ -16,7 +16,7 @@ using namespace igb;
 
 namespace {
 
-hipStream_t pick(igb_ctx ctx, void* s) { return s ? static_cast<hipStream_t>(s) : ctx->stream; }
+hipStream_t pick(igb_ctx ctx, void* s) { return s == IGB_CONTEXT_STREAM ? ctx->stream : static_cast<hipStream_t>(s); }
 
 bool host_only(igb_ctx ctx) { return ctx->device == IGB_HOST_ONLY; }
 
@@ -194,10 +194,17 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
     // device bytes of the operator (checked against the budget before allocating)
     const int nl = (g->p + 1) * (g->p + 1);
     const int ntile = prm->bc == IGB_HARD ? 2 : 1;
-    const size_t fp64_tiles = prm->far_on_the_fly ? 0 : size_t(op->nfar) * op->nq * op->nq * 16 * ntile;
+    const size_t fp64_tiles =
+        prm->far_on_the_fly ? 0 : size_t(op->nfar) * op->nq * op->nq * 16 * ntile + size_t(3) * op->nq * 16 + 256;
     size_t need = fp64_tiles + size_t(op->nnz) * 20 + size_t(op->N + 1) * 8 +
                   size_t(op->nclusters) * op->nq * (16 * 8 + 32) + op->near_src.size() * 4 +
                   std::min<size_t>(op->near_src.size(), size_t(1) << 22) * nl * nl * 16;
+    if (prm->precision == IGB_FP64 && !prm->far_on_the_fly) {
+        // per 16 columns: source vectors and fp64 partials of the matrix-core coupling
+        const size_t kbp = (op->nq + 3) / 4 * 4;
+        need += size_t(op->nclusters) * (ntile == 2 ? 7 : 1) * 16 * kbp * 16 +
+                op->chunks_mfma.len.size() * (ntile == 2 ? 10 : 1) * op->nq * 16;
+    }
     if (prm->precision != IGB_FP64) {
         // rounded tiles (rows padded to 16 bytes) and, per 16 columns, the rounded
         // source vectors and fp32 partials of the matrix-core coupling
@@ -330,6 +337,16 @@ igb_status igb_op_profile(igb_op op, int enable) {
     }
     op->profile = enable != 0;
     for (auto& t : op->timers) t.used = 0;
+    return IGB_OK;
+}
+
+igb_status igb_op_use_graphs(igb_op op, int enable) {
+    if (!op) {
+        set_error("igb_op_use_graphs: NULL argument");
+        return IGB_ERR_ARG;
+    }
+    op->use_graphs = enable != 0;
+    if (!op->use_graphs) op->clear_graphs();
     return IGB_OK;
 }
 

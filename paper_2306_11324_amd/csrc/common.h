@@ -152,7 +152,25 @@ struct igb_op_s {
     // per-kernel timing: 0 m2l, 1 spmv, 2 upward, 3 downward
     bool profile = false;
     KernelTimer timers[4];
+    // matvec launch sequences captured as HIP graphs, keyed by
+    // (x, y, columns, parts, stream); cleared when the work buffers change
+    struct GraphKey {
+        const void* x;
+        void* y;
+        int ncol, parts;
+        hipStream_t s;
+        bool operator==(const GraphKey& o) const {
+            return x == o.x && y == o.y && ncol == o.ncol && parts == o.parts && s == o.s;
+        }
+    };
+    std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
+    bool use_graphs = false;
+    void clear_graphs() {
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+        graphs.clear();
+    }
     ~igb_op_s() {
+        clear_graphs();
         for (auto& t : timers)
             for (hipEvent_t e : t.pool) (void)hipEventDestroy(e);
     }

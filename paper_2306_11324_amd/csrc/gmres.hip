@@ -5,8 +5,10 @@
 // read back per iteration for the Givens rotations.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <vector>
 
 #include "common.h"
@@ -18,6 +20,16 @@ namespace {
 constexpr int RT = 256;
 
 using cplx = std::complex<double>;
+
+// progress lines of a verbose solve (stderr)
+struct SolveLog {
+    bool on = false;
+    const char* phase = "";
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double elapsed() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
 
 }  // namespace
 
@@ -173,7 +185,8 @@ igb_status norms(const double2* v, int64_t n, int C, double* dev_tmp, std::vecto
 // tol[c] (or after maxit[c] Arnoldi steps).  Columns never interact, so a column's
 // iterates do not depend on which other columns share the batch.
 igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, const std::vector<int>& maxit,
-                       const std::vector<double>& tol, int mvflags, hipStream_t s, std::vector<ColumnResult>& res) {
+                       const std::vector<double>& tol, int mvflags, hipStream_t s, std::vector<ColumnResult>& res,
+                       const SolveLog& log) {
     const int64_t n = Wk.n;
     const int m = Wk.m, C = Wk.C;
     const unsigned gb = unsigned((n * C + 255) / 256);
@@ -296,11 +309,19 @@ igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, 
         hipLaunchKernelGGL(csub_from_multi, dim3(gb), dim3(256), 0, s, B, n * C, r);
         IGB_HIP(hipGetLastError());
         if ((st = norms(r, n, C, Wk.nrm, rnorm, s))) return st;
+        int nact = 0, steps = 0;
+        double worst = 0;
         for (int c = 0; c < C; ++c) {
             if (!in_cycle[c]) continue;
             ++res[c].applications;
             res[c].true_rel = bnorm[c] > 0 ? rnorm[c] / bnorm[c] : 0.0;
+            ++nact;
+            steps = std::max(steps, res[c].iters);
+            worst = std::max(worst, res[c].true_rel);
         }
+        if (log.on)
+            fprintf(stderr, "[igafmm] %s cycle: %d columns, %d Arnoldi steps, largest relative residual %.2e, %.1f s\n",
+                    log.phase, nact, steps, worst, log.elapsed());
     }
     return IGB_OK;
 }
@@ -315,6 +336,8 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
     const double tol = sp->tol > 0 ? sp->tol : 1e-8;
     const bool mixed = op->prm.precision != IGB_FP64;
     const int C = ndir;
+    SolveLog log;
+    log.on = sp->verbose != 0;
     Work W;
     igb_status st;
     if ((st = ensure_work(op, m, C, W))) return st;
@@ -324,8 +347,9 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
     std::vector<ColumnResult> res;
     igb_solve_info out{};
     if (!mixed) {
+        log.phase = "fp64";
         if ((st = gmres_block(op, W, B, X, std::vector<int>(C, maxit), std::vector<double>(C, tol), IGB_PART_ALL, s,
-                              res)))
+                              res, log)))
             return st;
     } else {
         // iterative refinement: inner GMRES on the reduced-precision far field,
@@ -378,7 +402,9 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
             if (!any_lo && !any_hi) break;
             std::vector<ColumnResult> inner(C), part;
             if (any_lo) {
-                if ((st = gmres_block(op, W, R, D, left_lo, tin, IGB_PART_ALL | IGB_MV_LOWPREC, s, part))) return st;
+                log.phase = "inner (reduced precision)";
+                if ((st = gmres_block(op, W, R, D, left_lo, tin, IGB_PART_ALL | IGB_MV_LOWPREC, s, part, log)))
+                    return st;
                 for (int c = 0; c < C; ++c)
                     if (left_lo[c]) inner[c] = part[c];
             } else {
@@ -389,7 +415,8 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
                     IGB_HIP(hipMalloc(&d2buf.ptr, size_t(n) * C * sizeof(double2)));
                     D2 = d2buf.as<double2>();
                 }
-                if ((st = gmres_block(op, W, R, D2, left_hi, tin, IGB_PART_ALL, s, part))) return st;
+                log.phase = "inner (fp64)";
+                if ((st = gmres_block(op, W, R, D2, left_hi, tin, IGB_PART_ALL, s, part, log))) return st;
                 for (int c = 0; c < C; ++c)
                     if (left_hi[c]) inner[c] = part[c];
                 hipLaunchKernelGGL(cadd_to, dim3(gb), dim3(256), 0, s, D2, n * C, D);
@@ -433,6 +460,17 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
                 IGB_HIP(hipStreamSynchronize(s));
             }
             ++out.refinements;
+            if (log.on) {
+                int nconv = 0, nesc = 0;
+                double worst = 0;
+                for (int c = 0; c < C; ++c) {
+                    nconv += res[c].converged ? 1 : 0;
+                    nesc += full[c] ? 1 : 0;
+                    worst = std::max(worst, res[c].true_rel);
+                }
+                fprintf(stderr, "[igafmm] refinement %d: %d of %d columns converged, %d on fp64, largest true "
+                        "relative residual %.2e, %.1f s\n", outer + 1, nconv, C, nesc, worst, log.elapsed());
+            }
         }
         for (int c = 0; c < C; ++c) out.escalated += full[c] ? 1 : 0;
     }

@@ -560,16 +560,16 @@ __global__ void node_geometry(const double* bez, const int* pg, int nel1, int np
 // coupling[pair][b*nq + a] = k(x_a of target, y_b of source)
 __global__ void coupling_soft(const double* nodes, const int* pair_tgt, const int* pair_src,
                               int64_t npairs, int nq, double kappa, double eta, double2* coup) {
-    const int64_t pr = blockIdx.x;
-    if (pr >= npairs) return;
-    const double* T = nodes + int64_t(pair_tgt[pr]) * nq * 16;
-    const double* S = nodes + int64_t(pair_src[pr]) * nq * 16;
-    double2* out = coup + pr * nq * nq;
-    for (int idx = threadIdx.x; idx < nq * nq; idx += blockDim.x) {
-        const int b = idx / nq, a = idx % nq;
-        const double* X = T + a * 16;
-        const double* Y = S + b * 16;
-        out[idx] = kernel_soft(X, X + 3, X[6], Y, Y[6], kappa, eta);
+    for (int64_t pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
+        const double* T = nodes + int64_t(pair_tgt[pr]) * nq * 16;
+        const double* S = nodes + int64_t(pair_src[pr]) * nq * 16;
+        double2* out = coup + pr * nq * nq;
+        for (int idx = threadIdx.x; idx < nq * nq; idx += blockDim.x) {
+            const int b = idx / nq, a = idx % nq;
+            const double* X = T + a * 16;
+            const double* Y = S + b * 16;
+            out[idx] = kernel_soft(X, X + 3, X[6], Y, Y[6], kappa, eta);
+        }
     }
 }
 
@@ -586,18 +586,19 @@ __device__ __forceinline__ void kernel_gh(const double* X, const double* Y, doub
     H = make_double2(c4 * ir * ir * (-cs - sn * kr), c4 * ir * ir * (cs * kr - sn));
 }
 
-// sound-hard: raw kernels at node pairs, {G, H}[pair][b*nq + a]; the node-wise
-// factors (measures, normals, tangents) are applied around the coupling product
+// sound-hard: raw kernels at node pairs, two tiles per pair, G[b*nq + a] then
+// H[b*nq + a]; the node-wise factors (measures, normals, tangents) are applied
+// around the coupling product
 __global__ void coupling_hard(const double* nodes, const int* pair_tgt, const int* pair_src, int64_t npairs,
                               int nq, double kappa, double2* coup) {
-    const int64_t pr = blockIdx.x;
-    if (pr >= npairs) return;
-    const double* T = nodes + int64_t(pair_tgt[pr]) * nq * 16;
-    const double* S = nodes + int64_t(pair_src[pr]) * nq * 16;
-    double2* out = coup + pr * nq * nq * 2;
-    for (int idx = threadIdx.x; idx < nq * nq; idx += blockDim.x) {
-        const int b = idx / nq, a = idx % nq;
-        kernel_gh(T + a * 16, S + b * 16, kappa, out[2 * idx], out[2 * idx + 1]);
+    for (int64_t pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
+        const double* T = nodes + int64_t(pair_tgt[pr]) * nq * 16;
+        const double* S = nodes + int64_t(pair_src[pr]) * nq * 16;
+        double2* out = coup + pr * nq * nq * 2;
+        for (int idx = threadIdx.x; idx < nq * nq; idx += blockDim.x) {
+            const int b = idx / nq, a = idx % nq;
+            kernel_gh(T + a * 16, S + b * 16, kappa, out[idx], out[nq * nq + idx]);
+        }
     }
 }
 
@@ -871,6 +872,7 @@ __device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
 // ---------------------------------------------------------------------------
 template <class LT> __device__ __forceinline__ LT round_to(double2 v);
 template <> __device__ __forceinline__ float2 round_to<float2>(double2 v) { return make_float2(float(v.x), float(v.y)); }
+template <> __device__ __forceinline__ double2 round_to<double2>(double2 v) { return v; }
 template <> __device__ __forceinline__ bf16x2 round_to<bf16x2>(double2 v) {
     bf16x2 b;
     b.re = f32_to_bf16_rne(float(v.x));   // RNE of the fp32 value
@@ -885,8 +887,10 @@ __global__ void coupling_lo(const double* __restrict__ nodes, const int* __restr
                             const int* __restrict__ pair_src, int64_t nfar, int nq, int nkc, double kappa, double eta,
                             LT* __restrict__ out) {
     constexpr int EPL = 16 / sizeof(LT), NT = HARD ? 2 : 1;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= nfar * NT * nkc * nq * EPL) return;
+    const int64_t total = nfar * NT * nkc * nq * EPL;
+    // grid-stride: the tiles of a large operator exceed the 2^32 threads of a grid
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
     const int e = int(i % EPL);
     int64_t r = i / EPL;
     const int a = int(r % nq);
@@ -909,6 +913,7 @@ __global__ void coupling_lo(const double* __restrict__ nodes, const int* __restr
         }
     }
     out[i] = round_to<LT>(v);
+    }
 }
 
 // rounded source vectors of the coupling, per matvec.  Soft: the moments x.
@@ -960,6 +965,10 @@ typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
 // valid as long as A and B use the same one, which they do by construction.
 struct MfmaBf16 {
     using LT = bf16x2;
+    using ACC = f32x4;
+    using PT = float2;
+    // output row of register r in lane group g (column = lane % 16)
+    static __device__ __forceinline__ int orow(int g, int r) { return 4 * g + r; }
     static constexpr int EPL = 4;    // complex elements per lane load
     static constexpr int KB = 16;    // complex elements per k block (k = 32)
     static __device__ __forceinline__ f32x4 step(uint4 a, uint4 b, f32x4 c) {
@@ -976,6 +985,9 @@ struct MfmaBf16 {
 };
 struct MfmaF32 {
     using LT = float2;
+    using ACC = f32x4;
+    using PT = float2;
+    static __device__ __forceinline__ int orow(int g, int r) { return 4 * g + r; }
     static constexpr int EPL = 2;
     static constexpr int KB = 8;     // four 16x16x4 steps
     static __device__ __forceinline__ f32x4 step(uint4 a, uint4 b, f32x4 c) {
@@ -993,6 +1005,44 @@ struct MfmaF32 {
     }
 };
 
+// fp64: one complex (16 bytes) per lane and k block of 4 complex; each lane
+// group's complex supplies the re part to the first 16x16x4 step and the im
+// part to the second
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+struct MfmaF64 {
+    using LT = double2;
+    using ACC = f64x4;
+    using PT = double2;
+    // the fp64 16x16x4 instruction interleaves its output rows across registers
+    static __device__ __forceinline__ int orow(int g, int r) { return g + 4 * r; }
+    static constexpr int EPL = 1;
+    static constexpr int KB = 4;
+    static __device__ __forceinline__ double lo(uint4 v) {
+        return __longlong_as_double((long long)(((unsigned long long)v.y << 32) | v.x));
+    }
+    static __device__ __forceinline__ double hi(uint4 v) {
+        return __longlong_as_double((long long)(((unsigned long long)v.w << 32) | v.z));
+    }
+    static __device__ __forceinline__ f64x4 step(uint4 a, uint4 b, f64x4 c) {
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(lo(a), lo(b), c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(hi(a), hi(b), c, 0, 0, 0);
+        return c;
+    }
+    static __device__ __forceinline__ uint4 re_part(uint4 x) {   // (re, im) -> (re, -im)
+        return make_uint4(x.x, x.y, x.z, x.w ^ 0x80000000u);
+    }
+    static __device__ __forceinline__ uint4 im_part(uint4 x) {   // -> (im, re)
+        return make_uint4(x.z, x.w, x.x, x.y);
+    }
+};
+template <class PT> __device__ __forceinline__ PT make_pt(double re, double im);
+template <> __device__ __forceinline__ float2 make_pt<float2>(double re, double im) {
+    return make_float2(float(re), float(im));
+}
+template <> __device__ __forceinline__ double2 make_pt<double2>(double re, double im) {
+    return make_double2(re, im);
+}
+
 // chunk handled by workgroup w: consecutive chunks on the same XCD (workgroups
 // are dealt to the 8 XCDs round robin), so neighbouring targets share L2
 __device__ __forceinline__ int64_t xcd_chunk(int64_t w, int64_t n) {
@@ -1000,12 +1050,25 @@ __device__ __forceinline__ int64_t xcd_chunk(int64_t w, int64_t n) {
     return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
 }
 
-// reduced-precision layout sizes
-static inline int lo_kb(igb_op op) { return op->prm.precision == IGB_MIX_FP32 ? MfmaF32::KB : MfmaBf16::KB; }
-static inline int lo_epl(igb_op op) { return op->prm.precision == IGB_MIX_FP32 ? MfmaF32::EPL : MfmaBf16::EPL; }
+// matrix-core layout sizes of the operator's own precision (fp64 operators use
+// the fp64 tiles [pair][tile][b][a], which are the chunk layout with EPL = 1)
+static inline int lo_kb(igb_op op) {
+    return op->prm.precision == IGB_MIX_FP32 ? MfmaF32::KB : op->prm.precision == IGB_MIX_BF16 ? MfmaBf16::KB : MfmaF64::KB;
+}
+static inline int lo_epl(igb_op op) {
+    return op->prm.precision == IGB_MIX_FP32 ? MfmaF32::EPL
+                                              : op->prm.precision == IGB_MIX_BF16 ? MfmaBf16::EPL : MfmaF64::EPL;
+}
 static inline int lo_nkc(igb_op op) { return (op->nq + lo_epl(op) - 1) / lo_epl(op); }
 static inline int lo_kbp(igb_op op) { return (op->nq + lo_kb(op) - 1) / lo_kb(op) * lo_kb(op); }
-static inline size_t lo_esz(igb_op op) { return op->prm.precision == IGB_MIX_FP32 ? sizeof(float2) : sizeof(bf16x2); }
+static inline size_t lo_esz(igb_op op) {
+    return op->prm.precision == IGB_MIX_FP32 ? sizeof(float2)
+                                              : op->prm.precision == IGB_MIX_BF16 ? sizeof(bf16x2) : sizeof(double2);
+}
+// the matrix-core coupling serves the operator's own precision; an fp64
+// operator with tiles uses it for every product
+static inline bool mf_fp64(igb_op op) { return op->prm.precision == IGB_FP64 && !op->prm.far_on_the_fly; }
+constexpr int MF64_MIN_COLS = 16;
 // zeroed bytes after the last tile: the last k block reaches at most three
 // chunks (of nq rows) past a tile
 static inline size_t lo_slack(igb_op op) { return size_t(3) * op->nq * 16 + 256; }
@@ -1020,7 +1083,7 @@ __global__ __launch_bounds__(512) void m2l_mfma(const typename OPS::LT* __restri
                                                 const int* __restrict__ far_src_g,
                                                 const int64_t* __restrict__ chunk_pair,
                                                 const int* __restrict__ chunk_len, int64_t nchunk, int nq, int ncol,
-                                                float2* __restrict__ part) {
+                                                typename OPS::PT* __restrict__ part) {
     constexpr int NT = HARD ? 2 : 1, NVS = HARD ? 7 : 1, NVO = HARD ? 10 : 1;
     constexpr int KB = OPS::KB, EPL = OPS::EPL;
     const int64_t ch = xcd_chunk(blockIdx.x, nchunk);
@@ -1034,9 +1097,10 @@ __global__ __launch_bounds__(512) void m2l_mfma(const typename OPS::LT* __restri
     const int len = chunk_len[ch];
     const int nkb = (nq + KB - 1) / KB;
     const int64_t tile_el = int64_t(nkc) * nq * EPL;
-    f32x4 acc[NVO][2];
+    using ACC = typename OPS::ACC;
+    ACC acc[NVO][2];
 #pragma unroll
-    for (int v = 0; v < NVO; ++v) acc[v][0] = acc[v][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int v = 0; v < NVO; ++v) acc[v][0] = acc[v][1] = ACC{0, 0, 0, 0};
     // steps j = (pair i, k block kb) in order; KU steps issue their loads
     // before any of their products, so each wave keeps KU blocks in flight
     constexpr int KU = HARD ? 1 : 4;
@@ -1104,15 +1168,16 @@ __global__ __launch_bounds__(512) void m2l_mfma(const typename OPS::LT* __restri
         load(A0, X0);
         compute(j0 + KU, A1, X1);
     }
-    // lane holds column li, rows 4g..4g+3 of each 16x16 tile
+    // lane holds column li and rows OPS::orow(g, 0..3) of each 16x16 tile
     const int c = c0 + li;
     if (c >= ncol) return;
 #pragma unroll
     for (int v = 0; v < NVO; ++v)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int ar = wave * 16 + 4 * g + r;
-            if (ar < nq) part[((ch * NVO + v) * nq + ar) * ncol + c] = make_float2(acc[v][0][r], acc[v][1][r]);
+            const int ar = wave * 16 + OPS::orow(g, r);
+            if (ar < nq)
+                part[((ch * NVO + v) * nq + ar) * ncol + c] = make_pt<typename OPS::PT>(acc[v][0][r], acc[v][1][r]);
         }
 }
 
@@ -1126,10 +1191,11 @@ __global__ __launch_bounds__(256) void m2l_mfma_soft(const typename OPS::LT* __r
                                                      const int* __restrict__ far_src_g,
                                                      const int64_t* __restrict__ chunk_pair,
                                                      const int* __restrict__ chunk_len, int64_t nchunk, int nq,
-                                                     int ncol, float2* __restrict__ part) {
+                                                     int ncol, typename OPS::PT* __restrict__ part) {
     using LT = typename OPS::LT;
     constexpr int KB = OPS::KB, EPL = OPS::EPL, NW = 4;
-    __shared__ f32x4 red[NW - 1][MT][2][64];
+    using ACC = typename OPS::ACC;
+    __shared__ ACC red[NW - 1][MT][2][64];
     const int64_t ch = xcd_chunk(blockIdx.x, nchunk);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, g = lane >> 4;
@@ -1145,9 +1211,9 @@ __global__ __launch_bounds__(256) void m2l_mfma_soft(const typename OPS::LT* __r
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) offA[mt] = unsigned((g * nq + min(mt * 16 + li, nq - 1)) * EPL);
     const unsigned offB = unsigned((g * ncolp + c0 + li) * EPL);
-    f32x4 acc[MT][2];
+    ACC acc[MT][2];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) acc[mt][0] = acc[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < MT; ++mt) acc[mt][0] = acc[mt][1] = ACC{0, 0, 0, 0};
     // this wave's steps: pairs wave, wave+4, ..., k blocks 0..nkb-1; loads past
     // the last step repeat it (in bounds, unused) so they are unconditional
     const int npair = len > wave ? (len - wave + NW - 1) / NW : 0;
@@ -1197,7 +1263,7 @@ __global__ __launch_bounds__(256) void m2l_mfma_soft(const typename OPS::LT* __r
     const int c = c0 + li;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-        f32x4 s0 = acc[mt][0], s1 = acc[mt][1];
+        ACC s0 = acc[mt][0], s1 = acc[mt][1];
 #pragma unroll
         for (int w = 0; w < NW - 1; ++w) {
             s0 += red[w][mt][0][lane];
@@ -1206,8 +1272,8 @@ __global__ __launch_bounds__(256) void m2l_mfma_soft(const typename OPS::LT* __r
         if (c >= ncol) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int ar = mt * 16 + 4 * g + r;
-            if (ar < nq) part[(ch * nq + ar) * ncol + c] = make_float2(s0[r], s1[r]);
+            const int ar = mt * 16 + OPS::orow(g, r);
+            if (ar < nq) part[(ch * nq + ar) * ncol + c] = make_pt<typename OPS::PT>(s0[r], s1[r]);
         }
     }
 }
@@ -1447,9 +1513,9 @@ __global__ __launch_bounds__(NT) void m2l_hard_chunks(const CT* __restrict__ cou
         }
         __syncthreads();
         if (a < nq) {
-            const CT* K = coup + pr * nq * nq * 2 + 2 * a;
+            const CT* K = coup + pr * nq * nq * 2 + a;
             for (int b = 0; b < nq; ++b) {
-                const double2 G = to_d2(K[int64_t(b) * nq * 2]), H = to_d2(K[int64_t(b) * nq * 2 + 1]);
+                const double2 G = to_d2(K[int64_t(b) * nq]), H = to_d2(K[int64_t(nq + b) * nq]);
 #pragma unroll
                 for (int cb = 0; cb < RB; ++cb) {
                     const int o = b * RB + cb;
@@ -2111,15 +2177,21 @@ igb_status assemble_far_device(igb_op op, hipStream_t s) {
     if ((st = upload(op->d_far_src, psg.data(), psg.size(), acct))) return st;
     const bool hard = op->bc == IGB_HARD;
     const bool otf = op->prm.far_on_the_fly != 0;
-    if (!otf && (st = alloc(op->d_coupling, size_t(op->nfar) * nq * nq * sizeof(double2) * (hard ? 2 : 1), acct)))
-        return st;
+    const size_t fp64_tile_bytes = size_t(op->nfar) * nq * nq * sizeof(double2) * (hard ? 2 : 1);
+    if (!otf) {
+        // slack after the last tile for the matrix-core k-block overrun (fp64 operators)
+        if ((st = alloc(op->d_coupling, fp64_tile_bytes + lo_slack(op), acct))) return st;
+        IGB_HIP(hipMemsetAsync(static_cast<char*>(op->d_coupling.ptr) + fp64_tile_bytes, 0, lo_slack(op), s));
+    }
     if (op->nfar > 0 && !otf) {
         if (hard)
-            hipLaunchKernelGGL(coupling_hard, dim3(unsigned(op->nfar)), dim3(256), 0, s, op->d_nodes.as<double>(),
+            hipLaunchKernelGGL(coupling_hard, dim3(unsigned(std::min<int64_t>(op->nfar, 1 << 20))), dim3(256), 0, s,
+                               op->d_nodes.as<double>(),
                                d_ptg.as<int>(), op->d_far_src.as<int>(), op->nfar, nq, op->kappa,
                                op->d_coupling.as<double2>());
         else
-            hipLaunchKernelGGL(coupling_soft, dim3(unsigned(op->nfar)), dim3(256), 0, s, op->d_nodes.as<double>(),
+            hipLaunchKernelGGL(coupling_soft, dim3(unsigned(std::min<int64_t>(op->nfar, 1 << 20))), dim3(256), 0, s,
+                               op->d_nodes.as<double>(),
                                d_ptg.as<int>(), op->d_far_src.as<int>(), op->nfar, nq, op->kappa, op->eta,
                                op->d_coupling.as<double2>());
         IGB_HIP(hipGetLastError());
@@ -2132,7 +2204,7 @@ igb_status assemble_far_device(igb_op op, hipStream_t s) {
         const size_t esz = lo_esz(op), slack = lo_slack(op);
         if ((st = alloc(op->d_coupling_lo, size_t(ne) * esz + slack, acct))) return st;
         IGB_HIP(hipMemsetAsync(static_cast<char*>(op->d_coupling_lo.ptr) + size_t(ne) * esz, 0, slack, s));
-        const dim3 grid(unsigned((ne + 255) / 256)), blk(256);
+        const dim3 grid(unsigned(std::min<int64_t>((ne + 255) / 256, int64_t(1) << 20))), blk(256);
         const double* nd = op->d_nodes.as<double>();
         const int* pt = d_ptg.as<int>();
         const int* ps = op->d_far_src.as<int>();
@@ -2173,6 +2245,7 @@ igb_status alloc_work(igb_op op, int ncol) {
     const int nq = op->nq;
     const bool hard = op->bc == IGB_HARD;
     const int kinds = hard ? 3 : 1, nvec = hard ? 10 : 1;
+    op->clear_graphs();   // captured launches refer to the buffers released here
     for (igb::DevBuf* b : {&op->d_xhat, &op->d_yhat, &op->d_yraw, &op->d_part, &op->d_yfar, &op->d_x2, &op->d_leafbuf,
                            &op->d_xlo, &op->d_part_lo}) {
         *acct -= std::min(*acct, b->bytes);
@@ -2184,12 +2257,12 @@ igb_status alloc_work(igb_op op, int ncol) {
     if (hard && (st = alloc(op->d_yraw, C * nvec * op->nclusters * nq * sizeof(double2), acct))) return st;
     if ((st = alloc(op->d_part, C * std::max<size_t>(1, op->chunks.len.size()) * nvec * nq * sizeof(double2), acct)))
         return st;
-    if (op->prm.precision != IGB_FP64) {
+    if (op->prm.precision != IGB_FP64 || mf_fp64(op)) {
         const size_t ncolp = (C + 15) / 16 * 16;
+        const size_t pt = op->prm.precision == IGB_FP64 ? sizeof(double2) : sizeof(float2);
         if ((st = alloc(op->d_xlo, size_t(op->nclusters) * (hard ? 7 : 1) * ncolp * lo_kbp(op) * lo_esz(op), acct)))
             return st;
-        if ((st = alloc(op->d_part_lo, C * std::max<size_t>(1, op->chunks_mfma.len.size()) * nvec * nq * sizeof(float2),
-                        acct)))
+        if ((st = alloc(op->d_part_lo, C * std::max<size_t>(1, op->chunks_mfma.len.size()) * nvec * nq * pt, acct)))
             return st;
     }
     if ((st = alloc(op->d_yfar, C * op->geom->n2 * sizeof(double2), acct))) return st;
@@ -2267,11 +2340,12 @@ static void launch_m2l_lo_t(igb_op op, const double2* xh, int64_t ks, int ncol, 
     hipLaunchKernelGGL((round_vectors<HARD ? 7 : 1, LT>), dim3(unsigned((nv + 255) / 256)), dim3(256), 0, s, xh, ks,
                        op->d_nodes.as<double>(), op->nclusters, nq, kbp, ncol, ncolp, op->d_xlo.as<LT>());
     (void)timer_mark(op, 0, s);
+    using PT = typename OPS::PT;
+    const LT* cp = op->prm.precision == IGB_FP64 ? op->d_coupling.as<LT>() : op->d_coupling_lo.as<LT>();
     if (!HARD && nchunk > 0) {
         const dim3 grid(unsigned(nchunk), unsigned(ncolp / 16));
-        const LT* cp = op->d_coupling_lo.as<LT>();
         const LT* xp = op->d_xlo.as<LT>();
-        float2* pp = op->d_part_lo.as<float2>();
+        PT* pp = op->d_part_lo.as<PT>();
 #define IGB_SOFT_MT(MTV)                                                                                          \
     hipLaunchKernelGGL((m2l_mfma_soft<OPS, MTV>), grid, dim3(256), 0, s, cp, lo_nkc(op), xp, kbp, ncolp,           \
                        op->d_far_src.as<int>(), C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, nq, ncol, pp)
@@ -2288,18 +2362,25 @@ static void launch_m2l_lo_t(igb_op op, const double2* xh, int64_t ks, int ncol, 
 #undef IGB_SOFT_MT
     } else if (nchunk > 0)
         hipLaunchKernelGGL((m2l_mfma<OPS, HARD>), dim3(unsigned(nchunk), unsigned(ncolp / 16)),
-                           dim3(64 * ((nq + 15) / 16)), 0, s, op->d_coupling_lo.as<LT>(), lo_nkc(op),
-                           op->d_xlo.as<LT>(), kbp, ncolp, op->d_far_src.as<int>(), C.d_pair.as<int64_t>(),
-                           C.d_len.as<int>(), nchunk, nq, ncol, op->d_part_lo.as<float2>());
+                           dim3(64 * ((nq + 15) / 16)), 0, s, cp, lo_nkc(op), op->d_xlo.as<LT>(), kbp, ncolp,
+                           op->d_far_src.as<int>(), C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, nq, ncol,
+                           op->d_part_lo.as<PT>());
     (void)timer_mark(op, 0, s);
 }
 
-// coupling partials [chunk][nvec][nq][ncol] of the far pairs; returns whether
-// the partials are the fp32 ones of the matrix-core path
-static igb_status launch_m2l(igb_op op, double2* xh, int64_t ks, bool low, int ncol, hipStream_t s, bool& lo) {
-    lo = low && op->prm.precision != IGB_FP64;
+// coupling partials [chunk][nvec][nq][ncol] of the far pairs.  kind: 0 fp64
+// partials of the vector path, 1 fp32 partials of the matrix-core path at
+// reduced precision, 2 fp64 partials of the matrix-core path
+static igb_status launch_m2l(igb_op op, double2* xh, int64_t ks, bool low, int ncol, hipStream_t s, int& kind) {
+    const bool lo = low && op->prm.precision != IGB_FP64;
     const bool hard = op->bc == IGB_HARD;
-    if (!lo) {
+    // fp64: the matrix cores pay off for blocks of at least MF64_MIN_COLS
+    // columns; a single column is HBM-bound on the vector path
+    kind = lo ? 1 : (mf_fp64(op) && ncol >= MF64_MIN_COLS) ? 2 : 0;
+    if (kind == 2) {
+        if (hard) launch_m2l_lo_t<MfmaF64, true>(op, xh, ks, ncol, s);
+        else launch_m2l_lo_t<MfmaF64, false>(op, xh, ks, ncol, s);
+    } else if (!lo) {
         if ((op->nq + 63) / 64 * 64 > 128) {
             set_error("h2_matvec: interpolation degree too large for the coupling kernel");
             return IGB_ERR_ARG;
@@ -2322,10 +2403,49 @@ static igb_status launch_m2l(igb_op op, double2* xh, int64_t ks, bool low, int n
 
 static inline unsigned blocks_for(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 
+static igb_status matvec_launches(igb_op op, const double* x, double* y, int ncol, int parts, hipStream_t s);
+
+// y = A x: the launch sequence is captured once per (x, y, columns, parts,
+// stream) into a HIP graph and replayed; it holds kernel launches only (no
+// memsets, no allocation).  Kernel timing (profile mode) launches directly.
 igb_status matvec_device(igb_op op, const double* x, double* y, int ncol, int parts, hipStream_t s) {
-    const bool low = (parts & IGB_MV_LOWPREC) != 0;
     igb_status st;
     if ((st = alloc_work(op, ncol))) return st;
+    if (!op->use_graphs || op->profile || s == nullptr) return matvec_launches(op, x, y, ncol, parts, s);
+    const igb_op_s::GraphKey key{x, y, ncol, parts, s};
+    for (auto& gr : op->graphs)
+        if (gr.first == key) {
+            IGB_HIP(hipGraphLaunch(gr.second, s));
+            return IGB_OK;
+        }
+    if (op->graphs.size() >= 512) op->clear_graphs();
+    hipGraph_t graph = nullptr;
+    IGB_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    st = matvec_launches(op, x, y, ncol, parts, s);
+    const hipError_t ce = hipStreamEndCapture(s, &graph);
+    if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (ce != hipSuccess) {
+        set_error("h2_matvec: graph capture failed: %s", hipGetErrorString(ce));
+        return IGB_ERR_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+        set_error("h2_matvec: graph instantiation failed: %s", hipGetErrorString(ie));
+        return IGB_ERR_HIP;
+    }
+    op->graphs.emplace_back(key, exec);
+    IGB_HIP(hipGraphLaunch(exec, s));
+    return IGB_OK;
+}
+
+static igb_status matvec_launches(igb_op op, const double* x, double* y, int ncol, int parts, hipStream_t s) {
+    const bool low = (parts & IGB_MV_LOWPREC) != 0;
+    igb_status st;
     igb_geom g = op->geom;
     const int q = op->q, nq = op->nq, L = op->L;
     const bool hard = op->bc == IGB_HARD;
@@ -2360,15 +2480,19 @@ igb_status matvec_device(igb_op op, const double* x, double* y, int ncol, int pa
             }
         }
         if ((st = timer_mark(op, 2, s))) return st;
-        bool lo = false;
-        if ((st = launch_m2l(op, xh, ks, low, ncol, s, lo))) return st;
+        int pkind = 0;
+        if ((st = launch_m2l(op, xh, ks, low, ncol, s, pkind))) return st;
         if ((st = timer_mark(op, 3, s))) return st;
         const int nvec = hard ? 10 : 1;
         double2* red_out = hard ? op->d_yraw.as<double2>() : yh;
         const int64_t per = int64_t(nvec) * nq * ncol;
-        if (lo)
+        if (pkind == 1)
             hipLaunchKernelGGL(m2l_reduce<float2>, dim3(blocks_for(op->nclusters * per, 256)), dim3(256), 0, s,
                                op->d_part_lo.as<float2>(), op->chunks_mfma.d_tgt_ptr.as<int>(), op->nclusters, per,
+                               red_out);
+        else if (pkind == 2)
+            hipLaunchKernelGGL(m2l_reduce<double2>, dim3(blocks_for(op->nclusters * per, 256)), dim3(256), 0, s,
+                               op->d_part_lo.as<double2>(), op->chunks_mfma.d_tgt_ptr.as<int>(), op->nclusters, per,
                                red_out);
         else
             hipLaunchKernelGGL(m2l_reduce<double2>, dim3(blocks_for(op->nclusters * per, 256)), dim3(256), 0, s,

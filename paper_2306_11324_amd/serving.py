@@ -29,7 +29,8 @@ from . import inputs as I
 class ServeConfig:
     slots: int = 4
     hbm_budget: int = 200 * 10 ** 9
-    precision: int = B.MIX_BF16
+    precision: int = B.MIX_BF16          # sound-soft requests
+    precision_hard: int = B.MIX_FP32     # sound-hard: the split G/H coupling cancels, bf16 is too coarse
     p: int = 2
     q: int = 8
     eta_adm: float = 1.6
@@ -97,7 +98,7 @@ class Server:
     def _op_args(self, req: I.Request):
         c = self.cfg
         return dict(kappa=req.kappa, bc=B.SOFT if req.bc == "soft" else B.HARD, q=c.q, eta_adm=c.eta_adm,
-                    leaf_depth=c.leaf_depth, precision=c.precision)
+                    leaf_depth=c.leaf_depth, precision=c.precision if req.bc == "soft" else c.precision_hard)
 
     def estimate(self, req: I.Request) -> int:
         """Device bytes of the request (host-only plan: nothing is allocated)."""

@@ -1,0 +1,125 @@
+"""Full-size cases on the seeded star (radius 1 + 0.1 * sum of real spherical
+harmonics of degree <= 4, seed 0), checked against sampled rows of the dense
+fp64 oracle (tests/golden/star_*_rows.npz) and against invariants that hold
+at any size: the optical theorem and far-field reciprocity.
+
+  * level 6 (24,576 elements, N = 26,136), degree 2, kappa = 16, sound-soft,
+    q = 8, 64 incident directions solved in lockstep, fp64;
+  * level 7 (98,304 elements, N = 99,848), degree 2, kappa = 32, sound-hard
+    (regularised W), q = 8, bf16 couplings on the matrix cores with the fp64
+    far field evaluated on the fly for the refinement residual, 16 directions.
+
+Both need the kappa * diameter cap on admissible blocks: without it the
+coarse blocks are several wavelengths across and nine Chebyshev points per
+direction do not resolve the kernel.  The cap sets the compression error,
+stated two ways against the oracle rows: relative to the operator (|dy_r| /
+(||A_r||_1 ||x||_inf)) and relative to this y (|dy| / max|y|; a random x
+gives a y 50-300 times below the operator bound by cancellation).  The
+oracle rows themselves agree with higher-order quadrature to 1e-13.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def row_errors(y, g):
+    yr = y[g["rows"]]
+    e_norm = float(np.max(np.abs(yr - g["y"]) / (g["rownorm1"] * np.abs(g["x"]).max())))
+    e_rel = float(np.max(np.abs(yr - g["y"])) / np.max(np.abs(g["y"])))
+    return e_norm, e_rel
+
+
+def farfield_checks(op, coeff, dirs, kappa, nobs=16384):
+    """Optical theorem per direction (equal-weight Fibonacci quadrature of
+    |u_inf|^2 on the unit sphere; the forward lobe is ~1/(kappa a) wide, so
+    the lattice must be fine enough to resolve it) and reciprocity
+    u_inf(-d_i; d_j) = u_inf(-d_j; d_i)."""
+    from paper_2306_11324_amd import inputs as I
+    nd = len(dirs)
+    obs = I.fibonacci_directions(nobs)
+    u = torch.zeros((nd, nobs), dtype=torch.complex128, device="cuda")
+    op.farfield(coeff, obs, u, ndir=nd)
+    fwd = torch.zeros((nd, nd), dtype=torch.complex128, device="cuda")
+    op.farfield(coeff, dirs, fwd, ndir=nd)
+    back = torch.zeros((nd, nd), dtype=torch.complex128, device="cuda")
+    op.farfield(coeff, -dirs, back, ndir=nd)
+    torch.cuda.synchronize()
+    u, fwd, back = u.cpu().numpy(), np.diag(fwd.cpu().numpy()), back.cpu().numpy()
+    lhs = 4 * np.pi * np.mean(np.abs(u) ** 2, axis=1)
+    rhs = 4 * np.pi / kappa * fwd.imag
+    opt = float(np.max(np.abs(lhs - rhs) / np.abs(rhs)))
+    recip = float(np.max(np.abs(back - back.T)) / np.max(np.abs(back)))
+    return opt, recip
+
+
+def test_star_level6_soft_rows_and_64_direction_solve():
+    from paper_2306_11324_amd import binding as B
+    from paper_2306_11324_amd import inputs as I
+    g = dict(np.load(os.path.join(GOLD, "star_m6_p2_k16_rows.npz")))
+    print("case: star seed 0, m=6, p=2, kappa=16, soft, q=8, leaf depth 3, kcap 5, fp64, 64 directions",
+          flush=True)
+    ctx = B.Context(0)
+    geo = B.Geometry(ctx, I.star_patches(0, I.star_geometry_level(6)), 6, 2)
+    op = B.Operator(ctx, geo, kappa=16.0, q=8, eta_adm=1.6, leaf_depth=3, kcap=5.0)
+    x = torch.from_numpy(g["x"]).cuda()
+    y = torch.zeros_like(x)
+    op.h2_matvec(x, y)
+    torch.cuda.synchronize()
+    e_norm, e_rel = row_errors(y.cpu().numpy(), g)
+    print(f"matvec vs oracle rows: operator-relative {e_norm:.2e}, vector-relative {e_rel:.2e}", flush=True)
+    assert e_norm < 1e-6 and e_rel < 5e-5
+    dirs = I.random_directions(1, 64)
+    coeff = torch.zeros((64, op.n), dtype=torch.complex128, device="cuda")
+    info, st = op.cfie_solve(dirs, coeff, tol=1e-8, restart=30, maxit=3000, verbose=True)
+    print(f"64 directions: iters {info.iters}, converged {info.converged}, relres_true {info.relres_true:.2e}",
+          flush=True)
+    assert st == 0 and info.converged == 64 and info.relres_true <= 1e-8
+    opt, recip = farfield_checks(op, coeff, dirs, 16.0)
+    print(f"optical theorem {opt:.2e}, reciprocity {recip:.2e}", flush=True)
+    assert opt < 1e-3 and recip < 1e-3
+
+
+def test_star_level7_hard_bf16_rows_and_16_direction_solve():
+    from paper_2306_11324_amd import binding as B
+    from paper_2306_11324_amd import inputs as I
+    path = os.path.join(GOLD, "star_m7_p2_k32_hard_rows.npz")
+    g = dict(np.load(path))
+    print("case: star seed 0, m=7, p=2, kappa=32, hard, q=8, leaf depth 3, kcap 8, bf16 tiles, "
+          "fp64 far field on the fly, 16 directions", flush=True)
+    ctx = B.Context(0)
+    geo = B.Geometry(ctx, I.star_patches(0, I.star_geometry_level(7)), 7, 2)
+    op = B.Operator(ctx, geo, kappa=32.0, bc=B.HARD, q=8, eta_adm=1.6, leaf_depth=3, kcap=8.0,
+                    precision=B.MIX_BF16, far_on_the_fly=True)
+    print(f"operator: far pairs {op.info.far_pairs}, nnz {op.info.nnz}, device {op.info.device_bytes / 1e9:.1f} GB, "
+          f"assembly near {op.info.assembly_near_ms:.0f} ms far {op.info.assembly_far_ms:.0f} ms", flush=True)
+    x = torch.from_numpy(g["x"]).cuda()
+    y = torch.zeros_like(x)
+    op.h2_matvec(x, y)
+    torch.cuda.synchronize()
+    e_norm, e_rel = row_errors(y.cpu().numpy(), g)
+    print(f"fp64 matvec vs oracle rows: operator-relative {e_norm:.2e}, vector-relative {e_rel:.2e}", flush=True)
+    assert e_norm < 1e-6 and e_rel < 1e-5
+    y.zero_()
+    op.h2_matvec(x, y, parts=B.PART_ALL | B.MV_LOWPREC)
+    torch.cuda.synchronize()
+    b_norm, b_rel = row_errors(y.cpu().numpy(), g)
+    print(f"bf16 matvec vs oracle rows: operator-relative {b_norm:.2e}, vector-relative {b_rel:.2e}", flush=True)
+    assert b_rel < 1e-2
+    dirs = I.random_directions(2, 16)
+    coeff = torch.zeros((16, op.n), dtype=torch.complex128, device="cuda")
+    info, st = op.cfie_solve(dirs, coeff, tol=1e-8, restart=30, maxit=3000, verbose=True)
+    print(f"16 directions: iters {info.iters}, converged {info.converged}, refinements {info.refinements}, "
+          f"escalated {info.escalated}, relres_true {info.relres_true:.2e}", flush=True)
+    assert st == 0 and info.converged == 16 and info.relres_true <= 1e-8
+    opt, recip = farfield_checks(op, coeff, dirs, 32.0)
+    print(f"optical theorem {opt:.2e}, reciprocity {recip:.2e}", flush=True)
+    assert opt < 1e-3 and recip < 1e-3

@@ -222,6 +222,43 @@ def test_on_the_fly_far_field_equals_stored_tiles(bc):
     assert st == 0 and info.relres_true <= 1e-10 and diff < 1e-7
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_graph_replays_equal_direct_launches(prec):
+    """On the context's stream the matvec is captured once into a HIP graph and
+    replayed; on the null stream it launches directly.  Every replay, with new
+    vector contents and eager torch work between replays, equals the direct
+    result bitwise (hard operator: the longest launch sequence)."""
+    from paper_2306_11324_amd import inputs as I
+    b = B()
+    if prec == "fp64":
+        geo, op = operator(3, 2, 2.0, 4, 1, bc="hard")
+        parts = b.PART_ALL
+    else:
+        geo, op = lowprec_operator("bf16", "hard")
+        parts = b.PART_ALL | b.MV_LOWPREC
+    op.use_graphs(True)
+    x = torch.zeros((3, op.n), dtype=torch.complex128, device="cuda")
+    y_graph = torch.zeros_like(x)
+    y_direct = torch.zeros_like(x)
+    for rep in range(4):
+        x.copy_(torch.from_numpy(I.random_complex(100 + rep, (3, op.n))))
+        torch.cuda.synchronize()
+        op.h2_matvec(x, y_graph, nrhs=3, parts=parts, stream=b.CONTEXT_STREAM)
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 20, device="cuda").sum()       # eager work between replays
+        op.h2_matvec(x, y_direct, nrhs=3, parts=parts, stream=0)
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        assert torch.equal(y_graph, y_direct), rep
+    d = I.random_directions(7, 2)
+    t_graph = torch.zeros((2, op.n), dtype=torch.complex128, device="cuda")
+    info_g, _ = op.cfie_solve(d, t_graph, tol=1e-10)
+    op.use_graphs(False)
+    t_direct = torch.zeros_like(t_graph)
+    info_d, _ = op.cfie_solve(d, t_direct, tol=1e-10)
+    assert info_g.iters == info_d.iters and torch.equal(t_graph, t_direct)
+
+
 def test_slow_refinement_escalates_to_fp64():
     """A bf16 refinement whose steps barely reduce the fp64 residual (forced here
     with an inner tolerance of 0.5) switches those columns to the fp64 operator;
