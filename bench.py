@@ -35,6 +35,13 @@ sys.path.insert(0, ROOT)
 METRIC = "H2 matvecs/s and CFIE solves/s vs plain FP64 at 1e-6 rel err; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the coupling kernels on the sphere_m5_p2_k8 workload,
+# from two rocprofv3 passes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0; the factors
+# make a plain 1 GiB device copy read and write 1 GiB), taken for the kernels
+# as they stand: profiles/m2l_sphere_m5_p2_k8_hbm_counters.md.  To be reset
+# to None whenever one of these kernels changes.
+MEASURED_TRAFFIC = {"m2l_chunks": 2.165e9, "fp64": 2.608e9, "fp32": 1.281e9, "bf16": 0.644e9}
+
 WORKLOADS = {
     "sphere_m5_p2_k8": dict(geometry="sphere", m=5, p=2, kappa=8.0, q=6, eta_adm=1.6, leaf_depth=2,
                             kcap=0.0, tol=1e-8, golden="sphere_m5_p2_k8_rows"),
@@ -187,6 +194,8 @@ def main():
         flops = 8.0 * info.far_pairs * nq2 * nc
         byts = float(info.far_pairs * nq2 * elem_bytes[prec_name])
         return {"ncol": nc, "column_matvecs_per_s": nc / tb, "ms_per_block_matvec": tb * 1e3, "kernel_ms": km,
+                "m2l_algorithmic_bytes": byts,
+                "m2l_traffic_bytes": MEASURED_TRAFFIC.get(prec_name) if args.workload == "sphere_m5_p2_k8" else None,
                 "m2l_kernel": "m2l_chunks (vector fp64)" if prec_name == "fp64" else f"m2l_mfma ({prec_name} matrix cores)",
                 "m2l_GBps": byts / avg / 1e9, "m2l_TFLOPs": flops / avg / 1e12,
                 "m2l_frac_hbm_peak": byts / avg / (HBM_PEAK_GBS * 1e9),
@@ -327,7 +336,8 @@ def main():
         "err_matvec_vs_oracle_rows": err_oracle,
         "err_farfield_vs_mie": err_mie,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": MEASURED_TRAFFIC["m2l_chunks"] if args.workload == "sphere_m5_p2_k8" else None,
                      "kernel": "m2l_chunks", "bytes_per_launch": m2l_bytes,
                      "avg_launch_ms": m2l_avg * 1e3},
     }

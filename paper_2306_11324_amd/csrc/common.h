@@ -99,7 +99,7 @@ struct FarLevel {
 // M2L work decomposition: chunks of consecutive far pairs of one target; each
 // chunk produces one partial result, summed per target in chunk order
 constexpr int M2L_CHUNK = 8;
-constexpr int M2L_CHUNK_MFMA = 32;
+constexpr int M2L_CHUNK_MFMA = 16;
 struct M2LChunks {
     std::vector<int> tgt;       // global cluster index of the chunk's target
     std::vector<int64_t> pair;  // first pair of the chunk
