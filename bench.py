@@ -74,8 +74,7 @@ def cpu_baseline(w, seconds_target=20.0):
 def serve_stream(nreq, rate):
     """Continuous batching of a Poisson request stream: each request a seeded
     star-shaped scatterer at level 3..6, kappa in [1, 32], 1..16 directions,
-    sound-soft or sound-hard, bf16 (soft) / fp32 (hard) couplings with fp64
-    refinement, admitted by
+    sound-soft or sound-hard, bf16 couplings with fp64 refinement, admitted by
     HBM budget into 4 concurrent slots.  Latency = completion - arrival."""
     from paper_2306_11324_amd import inputs as I
     from paper_2306_11324_amd.serving import ServeConfig, Server
@@ -94,7 +93,7 @@ def serve_stream(nreq, rate):
         for k, v in r.stages.items():
             stages[k] = stages.get(k, 0.0) + v
     out.update({"arrival_rate_per_s": rate, "slots": cfg.slots, "hbm_budget_GB": cfg.hbm_budget / 1e9,
-                "precision": "soft: bf16 couplings, hard: fp32 couplings; fp64 near field and refinement", "q": cfg.q,
+                "precision": "bf16 couplings, fp64 near field and refinement", "q": cfg.q,
                 "leaf_depth": cfg.leaf_depth, "tol": cfg.tol, "peak_reserved_GB": srv.peak_reserved / 1e9,
                 "stage_seconds_total": stages,
                 "stream": "request_stream(seed=3): level 3..6, kappa U[1,32], 1..16 directions, soft/hard"})

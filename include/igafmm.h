@@ -101,11 +101,11 @@ typedef enum { IGB_FP64 = 0, IGB_MIX_FP32 = 1, IGB_MIX_BF16 = 2 } igb_prec;
  *              product (fp64 matvecs, refinement residuals) evaluates the kernel at
  *              the node pairs as it goes: the same interpolated operator (to
  *              rounding), no coupling memory, bound by fp64 arithmetic
- *   quad_extra Gauss points per direction added to the default near-field rules
- *              (regular pairs: 4..7 by distance / size, raised with kappa * size,
- *              here at most 10; touching pairs: 7 / 8 / 9 for identical / edge /
- *              vertex, here at most 12), 0 <= quad_extra <= 3: accuracy of the
- *              near field against assembly time */
+ *   quad_extra Gauss points per direction added to (negative: removed from) the
+ *              default near-field rules (regular pairs: 4..7 by distance / size,
+ *              raised with kappa * size, at least 2 and at most 10; touching pairs:
+ *              7 / 8 / 9 for identical / edge / vertex, at most 12),
+ *              -2 <= quad_extra <= 3: accuracy of the near field against assembly time */
 typedef struct {
     double kappa;
     int bc;

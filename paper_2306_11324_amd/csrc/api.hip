@@ -164,8 +164,8 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
         set_error("assemble_nearfield: far_on_the_fly must be 0 or 1");
         return IGB_ERR_ARG;
     }
-    if (prm->quad_extra < 0 || prm->quad_extra > 3) {
-        set_error("assemble_nearfield: need 0 <= quad_extra <= 3");
+    if (prm->quad_extra < -2 || prm->quad_extra > 3) {
+        set_error("assemble_nearfield: need -2 <= quad_extra <= 3");
         return IGB_ERR_ARG;
     }
     if (prm->bc == IGB_HARD && g->p < 1) {

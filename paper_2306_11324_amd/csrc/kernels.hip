@@ -2015,7 +2015,7 @@ static igb_status near_launch(igb_op op, hipStream_t s) {
         if (!reg.empty()) {
             A.list = d_list.as<int>();
             A.nlist = int64_t(reg.size());
-            if (op->prm.quad_extra == 0)
+            if (op->prm.quad_extra <= 0)
                 hipLaunchKernelGGL((near_regular<P, HARD, 49>), dim3(unsigned(reg.size())), dim3(NEAR_THREADS), 0, s,
                                    A);
             else

@@ -266,7 +266,7 @@ igb_status near_classify(igb_op op) {
                 // beyond 1.5 (oscillation of e^{i kappa r} across the pair)
                 const double kd = op->kappa * dmax;
                 n += (kd >= 1.5) + (kd >= 3.0) + (kd >= 6.0);
-                n = std::min(n, 7) + op->prm.quad_extra;
+                n = std::max(2, std::min(n, 7) + op->prm.quad_extra);
                 kind = n << 8;
             } else {
                 int expect = -1;
