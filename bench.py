@@ -202,6 +202,19 @@ def main():
 
     plain = run_solves(op, d, args.steps, args.warmup)
     value = plain["matvecs_per_s"]
+    # scattered field of the plain solution at points on the radius-2 sphere
+    pot_pts = 2.0 * I.fibonacci_directions(4096)
+    pot_u = torch.zeros(len(pot_pts), dtype=torch.complex128, device=dev)
+    op.potential(plain["coeff"], pot_pts, pot_u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op.potential(plain["coeff"], pot_pts, pot_u)
+    torch.cuda.synchronize()
+    t_pot = time.perf_counter() - t0
+    pot_evals = len(pot_pts) * info.nelem * 64
+    potential = {"points": len(pot_pts), "seconds": t_pot, "points_per_s": len(pot_pts) / t_pot,
+                 "kernel_evaluations_per_s": pot_evals / t_pot,
+                 "note": "u_s at 4096 points on |x| = 2, 8 x 8 Gauss points on each of the elements"}
     op.use_graphs(True)
     plain_graphs = run_solves(op, d, args.steps, args.warmup)
     op.use_graphs(False)
@@ -330,6 +343,7 @@ def main():
         "assembly_far_ms": info.assembly_far_ms,
         "kernel_ms": {"m2l": m2l_ms / max(m2l_n, 1), "spmv": spmv_ms / max(spmv_n, 1),
                       "upward": up_ms / max(up_n, 1), "downward": dn_ms / max(dn_n, 1)},
+        "potential": potential,
         "served": served,
         "block_matvec": block_mv,
         "err_matvec_vs_oracle_rows": err_oracle,

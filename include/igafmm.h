@@ -273,6 +273,19 @@ igb_status cfie_solve(igb_op op, const double* dirs, int ndir, const igb_solve_p
 igb_status farfield(igb_op op, const double* coeffs, int ndir, const double* obs, int nobs,
                     double* uinf, void* hip_stream);
 
+/* Scattered field at points off the boundary (the representation formulas of
+ * Sec. 2 with the potentials' signs read as u = u_inc + u_s, u_s = -V t for
+ * IGB_SOFT and u_s = D g for IGB_HARD):
+ *   soft  u_s(x) = -int G(x,y) t(y) dsigma_y,
+ *   hard  u_s(x) =  int dG(x,y)/dn_y g(y) dsigma_y,   G = e^{i kappa r}/(4 pi r),
+ * for ndir coefficient vectors (device coeffs [ndir][n]) at npts points (host
+ * points [npts][3]) into device u [ndir][npts], by tensor Gauss quadrature
+ * (8 x 8 points) on every element.  Accurate for points at least about one
+ * element diameter from the surface (no near-singular correction is applied
+ * closer in).  IGB_ERR_ARG for non-finite points.  Synchronous. */
+igb_status potential(igb_op op, const double* coeffs, int ndir, const double* points, int npts, double* u,
+                     void* hip_stream);
+
 const char* igb_last_error(void);
 
 #ifdef __cplusplus

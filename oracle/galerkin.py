@@ -392,6 +392,34 @@ class DenseBEM:
             u = -1j * k * np.einsum("oeq,oeq,eq->o", ph, xn, dens * wq) / (4 * np.pi)
         return u
 
+    def potential(self, coeffs, points, n: int = 10) -> np.ndarray:
+        """Scattered field at points off the boundary from the representation
+        formulas (Sec. 2 and the readings above): soft u_s(x) = -int G(x,y)
+        t(y) dsigma_y, hard u_s(x) = int dG(x,y)/dn_y g(y) dsigma_y with
+        G = e^{i kappa r}/(4 pi r), r = |x - y|, so that dG/dn_y =
+        G (i kappa r - 1)/r^2 (y - x).n_y; tensor Gauss of order n on every
+        element (for points well away from the surface)."""
+        disc = self.disc
+        c = np.asarray(coeffs, dtype=np.complex128)
+        if self.bc == "hard":
+            c = disc.glue_matrix() @ c
+        P = np.atleast_2d(np.asarray(points, dtype=np.float64))
+        pts, w = qd.tensor2(n)
+        E = disc.nelem
+        dd = disc.eval_on_elements(np.arange(E), np.broadcast_to(pts, (E,) + pts.shape))
+        dens = np.einsum("eqa,ea->eq", dd["phi"], c[disc.el_dofs]) * (w[None, :] * disc.h ** 2)
+        k = self.kappa
+        out = np.zeros(len(P), dtype=np.complex128)
+        for i, x in enumerate(P):
+            dy = dd["X"] - x                      # y - x
+            r = np.linalg.norm(dy, axis=-1)
+            G = np.exp(1j * k * r) / (4 * np.pi * r)
+            if self.bc == "soft":
+                out[i] = -np.sum(G * dd["a"] * dens)
+            else:
+                out[i] = np.sum(G * (1j * k * r - 1) / r ** 2 * np.einsum("eqc,eqc->eq", dy, dd["nt"]) * dens)
+        return out
+
     def solve(self, d) -> np.ndarray:
         """LU solve of the dense system (LAPACK zgesv through numpy)."""
         return np.linalg.solve(self.matrix(), self.rhs(d))

@@ -85,6 +85,7 @@ _SIGS = {
     "cfie_solve": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int, C.POINTER(IgbSolveParams), _P,
                              C.POINTER(IgbSolveInfo)]),
     "farfield": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double), C.c_int, _P, _P]),
+    "potential": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double), C.c_int, _P, _P]),
     "igb_op_profile": (C.c_int, [_P, C.c_int]),
     "igb_op_use_graphs": (C.c_int, [_P, C.c_int]),
     "igb_op_kernel_time": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
@@ -266,6 +267,13 @@ class Operator:
         _check("farfield", _lib.farfield(self.h, _dptr(coeffs, ndir * self.n), ndir, po, o.shape[0],
                                          _dptr(uinf, ndir * o.shape[0]), _stream(stream)))
         return uinf
+
+    def potential(self, coeffs, points, u, ndir: int = 1, stream=None):
+        """Scattered field u [ndir][npts] at host points [npts][3] off the boundary."""
+        pt, pp = _dbl(np.atleast_2d(points))
+        _check("potential", _lib.potential(self.h, _dptr(coeffs, ndir * self.n), ndir, pp, pt.shape[0],
+                                           _dptr(u, ndir * pt.shape[0]), _stream(stream)))
+        return u
 
     def __del__(self, _destroy=_lib.igb_op_destroy):
         if getattr(self, "h", None):

@@ -430,4 +430,15 @@ igb_status farfield(igb_op op, const double* coeffs, int ndir, const double* obs
     return farfield_device(op, coeffs, ndir, obs, nobs, uinf, pick(op->geom->ctx, hip_stream));
 }
 
+igb_status potential(igb_op op, const double* coeffs, int ndir, const double* points, int npts, double* u,
+                     void* hip_stream) {
+    if (!op || !coeffs || !points || !u || ndir < 1 || npts < 1) {
+        set_error("potential: invalid argument");
+        return IGB_ERR_ARG;
+    }
+    if (igb_status st = need_device(op, "potential")) return st;
+    IGB_HIP(hipSetDevice(op->geom->ctx->device));
+    return potential_device(op, coeffs, ndir, points, npts, u, pick(op->geom->ctx, hip_stream));
+}
+
 }  // extern "C"

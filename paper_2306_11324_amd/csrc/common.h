@@ -195,6 +195,9 @@ igb_status matvec_device(igb_op op, const double* x, double* y, int nrhs, int pa
 igb_status rhs_device(igb_op op, const double* dirs, int ndir, double* b, hipStream_t s);
 igb_status farfield_device(igb_op op, const double* coeffs, int ndir, const double* obs,
                            int nobs, double* uinf, hipStream_t s);
+igb_status potential_device(igb_op op, const double* coeffs, int ndir, const double* points, int npt, double* u,
+                            hipStream_t s);
+constexpr int POTENTIAL_ORDER = 8;   // Gauss points per direction and element
 igb_status gmres_device(igb_op op, const double* b, double* x, int ndir,
                         const igb_solve_params* sp, igb_solve_info* info, hipStream_t s);
 

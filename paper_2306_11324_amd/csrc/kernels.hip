@@ -1806,6 +1806,45 @@ __global__ __launch_bounds__(256) void farfield_sum(const double* geo, const dou
     }
 }
 
+// scattered field at points off the boundary: soft u = -sum G a w dens,
+// hard u = sum G (i kappa r - 1)/r^2 ((y - x).n~) w dens; one workgroup per
+// (point, direction), fixed-order tree reduction
+__global__ __launch_bounds__(256) void potential_sum(const double* geo, const double2* dens, int64_t npts,
+                                                     const double* pts, int npt, double kappa, int hard,
+                                                     double2* u) {
+    __shared__ double2 red[256];
+    const int o = blockIdx.x, dir = blockIdx.y;
+    const double* x = pts + 3 * o;
+    const double2* D = dens + int64_t(dir) * npts;
+    double2 acc = make_double2(0, 0);
+    for (int64_t i = threadIdx.x; i < npts; i += 256) {
+        const double* g = geo + i * 8;
+        const double d0 = g[0] - x[0], d1 = g[1] - x[1], d2 = g[2] - x[2];   // y - x
+        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const double ir = 1.0 / r, kr = kappa * r;
+        double sn, cs;
+        sincos(kr, &sn, &cs);
+        const double c4 = 0.07957747154594767 * ir;   // 1/(4 pi r)
+        double2 k;
+        if (hard) {
+            const double dn = (d0 * g[3] + d1 * g[4] + d2 * g[5]) * ir * ir * g[7];
+            // G (i kappa r - 1) = c4 (cs + i sn)(-1 + i kr)
+            k = make_double2(c4 * dn * (-cs - sn * kr), c4 * dn * (cs * kr - sn));
+        } else {
+            const double wa = -c4 * g[6] * g[7];
+            k = make_double2(wa * cs, wa * sn);
+        }
+        acc = cfma(k, D[i], acc);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) u[int64_t(dir) * npt + o] = red[0];
+}
+
 // ==========================================================================
 // host launchers
 // ==========================================================================
@@ -2631,6 +2670,49 @@ igb_status farfield_device(igb_op op, const double* coeffs, int ndir, const doub
     hipLaunchKernelGGL(farfield_sum, dim3(unsigned(nobs), unsigned(ndir)), dim3(256), 0, s, d_geo.as<double>(),
                        d_dens.as<double2>(), npts, d_obs.as<double>(), nobs, op->kappa, hard ? 1 : 0,
                        reinterpret_cast<double2*>(uinf));
+    IGB_HIP(hipGetLastError());
+    IGB_HIP(hipStreamSynchronize(s));
+    return IGB_OK;
+}
+
+igb_status potential_device(igb_op op, const double* coeffs, int ndir, const double* points, int npt, double* u,
+                            hipStream_t s) {
+    igb_geom g = op->geom;
+    for (int i = 0; i < 3 * npt; ++i)
+        if (!std::isfinite(points[i])) {
+            set_error("potential: point %d is not finite", i / 3);
+            return IGB_ERR_ARG;
+        }
+    igb_status st;
+    const int nqd = POTENTIAL_ORDER;
+    const int64_t npts = g->nelem * nqd * nqd;
+    DevBuf d_pts, d_gl, d_geo, d_dens;
+    std::vector<double> gl = gauss_table();
+    if ((st = upload(d_pts, points, size_t(3) * npt, nullptr))) return st;
+    if ((st = upload(d_gl, gl.data(), gl.size(), nullptr))) return st;
+    if ((st = alloc(d_geo, size_t(npts) * 8 * sizeof(double), nullptr))) return st;
+    if ((st = alloc(d_dens, size_t(ndir) * npts * sizeof(double2), nullptr))) return st;
+    QuadGeoArgs A{g->d_bez.as<double>(), g->d_pg.as<int>(), g->d_C1.as<double>(), d_gl.as<double>(),
+                  g->nel1, g->p, nqd, g->nelem};
+    const bool hard = op->bc == IGB_HARD;
+    const double2* C = reinterpret_cast<const double2*>(coeffs);
+    const int* s2s0 = hard ? op->d_s2_to_s0.as<int>() : nullptr;
+    switch (g->p) {
+        case 1:
+            hipLaunchKernelGGL(density_points<1>, dim3(unsigned((npts + 255) / 256)), dim3(256), 0, s, A, C, ndir,
+                               op->N, s2s0, g->k, d_geo.as<double>(), d_dens.as<double2>());
+            break;
+        case 2:
+            hipLaunchKernelGGL(density_points<2>, dim3(unsigned((npts + 255) / 256)), dim3(256), 0, s, A, C, ndir,
+                               op->N, s2s0, g->k, d_geo.as<double>(), d_dens.as<double2>());
+            break;
+        default:
+            set_error("potential: p = %d not built", g->p);
+            return IGB_ERR_UNSUPPORTED;
+    }
+    hipLaunchKernelGGL(potential_sum, dim3(unsigned(npt), unsigned(ndir)), dim3(256), 0, s, d_geo.as<double>(),
+                       d_dens.as<double2>(), npts, d_pts.as<double>(), npt, op->kappa, hard ? 1 : 0,
+                       reinterpret_cast<double2*>(u));
     IGB_HIP(hipGetLastError());
     IGB_HIP(hipStreamSynchronize(s));
     return IGB_OK;

@@ -16,6 +16,9 @@ Cases
                       rows of the dense O1 matrix applied to the seeded vector.
   sphere_m3_p2_k2_q4_hard / sphere_m2_p2_k1_hard  the same two small checks for
                       the sound-hard operator (regularised W) on S^0.
+  sphere_m2_k1_potential  scattered field at 72 points (r = 1.5, 2, 3) of the
+                      dense LU solutions on the level-2 sphere (soft p = 1, hard
+                      p = 2, kappa = 1), and the Mie series there.
   star_m6_p2_k16_rows  seed-0 star, m = 6, p = 2, kappa = 16, soft: sampled rows
                       of the dense O1 matrix applied to the seeded vector.
   star_m7_p2_k32_hard_rows  seed-0 star, m = 7, p = 2, kappa = 32, hard (S^0):
@@ -94,6 +97,21 @@ def case_sphere_m2_p2_k1_hard():
                 mie=mie.farfield(1.0, obs @ d, "hard"), x=I.random_complex(X_SEED, bem.n))
 
 
+def case_sphere_m2_k1_potential():
+    out = {}
+    d = np.array([0.0, 0.0, 1.0])
+    pts = np.concatenate([r * I.fibonacci_directions(24) for r in (1.5, 2.0, 3.0)])
+    for bc, p in (("soft", 1), ("hard", 2)):
+        bem = G.DenseBEM(I.sphere_patches(), p=p, m=2, kappa=1.0, bc=bc)
+        t = bem.solve(d)
+        out[f"{bc}_t"] = t
+        out[f"{bc}_pot"] = bem.potential(t, pts)
+        out[f"{bc}_mie"] = mie.scattered(1.0, pts, d, bc)
+    out["pts"] = pts
+    out["d"] = d
+    return out
+
+
 def _star_rows(m, kappa, bc, nrows):
     bem = G.DenseBEM(I.star_patches(0, I.star_geometry_level(m)), p=2, m=m, kappa=kappa, bc=bc)
     x = I.random_complex(X_SEED, bem.n)
@@ -117,6 +135,7 @@ CASES = {
     "sphere_m2_p1_k1": case_sphere_m2_p1_k1,
     "sphere_m5_p2_k8_rows": case_sphere_m5_p2_k8_rows,
     "star_m6_p2_k16_rows": case_star_m6_p2_k16_rows,
+    "sphere_m2_k1_potential": case_sphere_m2_k1_potential,
     "star_m7_p2_k32_hard_rows": case_star_m7_p2_k32_hard_rows,
 }
 

@@ -259,6 +259,26 @@ def test_graph_replays_equal_direct_launches(prec):
     assert info_g.iters == info_d.iters and torch.equal(t_graph, t_direct)
 
 
+@BCS
+def test_potential_matches_oracle_and_mie(bc):
+    """Scattered field off the boundary from the oracle's own solution
+    coefficients (level-2 sphere, kappa = 1) at 72 points 0.5-2 radii outside:
+    the GPU quadrature (8 x 8 per element) against the oracle's (10 x 10), and
+    both against the Mie series within the discretisation error."""
+    b = B()
+    G = gold("sphere_m2_k1_potential")
+    p = 1 if bc == "soft" else 2
+    geo, op = operator(2, p, 1.0, 8, 0, bc=bc)
+    t = torch.from_numpy(G[f"{bc}_t"]).cuda()
+    u = torch.zeros(len(G["pts"]), dtype=torch.complex128, device="cuda")
+    op.potential(t, G["pts"], u)
+    torch.cuda.synchronize()
+    u = u.cpu().numpy()
+    e_or, e_mie = rel(u, G[f"{bc}_pot"]), rel(u, G[f"{bc}_mie"])
+    print(f"{bc}: potential vs oracle {e_or:.2e}, vs Mie {e_mie:.2e}", flush=True)
+    assert e_or < 1e-8 and e_mie < 1e-3
+
+
 def test_slow_refinement_escalates_to_fp64():
     """A bf16 refinement whose steps barely reduce the fp64 residual (forced here
     with an inner tolerance of 0.5) switches those columns to the fp64 operator;

@@ -127,3 +127,35 @@ def test_sampled_rows_equal_dense_matrix_rows(bc):
     rows = np.array([0, 7, bem.n // 2, bem.n - 1])
     R = bem.rows(rows)
     assert np.abs(R - A[rows]).max() < 1e-12 * np.abs(A).max()
+
+
+def test_mie_scattered_field_tends_to_far_field():
+    """The Mie series of the scattered field, times r e^{-i kappa r} at large r,
+    approaches the far-field series (independent forms of the same solution)."""
+    d = np.array([0.0, 0.0, 1.0])
+    xh = inputs.fibonacci_directions(16)
+    for bc in ("soft", "hard"):
+        R = 2.0e4
+        u = mie.scattered(2.0, R * xh, d, bc) * R * np.exp(-2.0j * R)
+        ref = mie.farfield(2.0, xh @ d, bc)
+        assert np.abs(u - ref).max() < 1e-3 * np.abs(ref).max(), bc
+
+
+@pytest.mark.parametrize("bc,p,m", [("soft", 1, 2), ("hard", 3, 1)])
+def test_potential_matches_mie_outside_sphere(bc, p, m):
+    """Scattered field of the discrete solution at points 0.5, 1 and 2 radii
+    outside the sphere against the Mie series (within the discretisation error
+    the far field shows, 1e-3); at large distance it tends to the discrete far
+    field."""
+    bem = G.DenseBEM(inputs.sphere_patches(), p=p, m=m, kappa=1.0, bc=bc)
+    d = np.array([0.0, 0.0, 1.0])
+    t = bem.solve(d)
+    xh = inputs.fibonacci_directions(24)
+    pts = np.concatenate([r * xh for r in (1.5, 2.0, 3.0)])
+    u = bem.potential(t, pts)
+    ref = mie.scattered(1.0, pts, d, bc)
+    assert np.abs(u - ref).max() < 1e-3 * np.abs(ref).max()
+    R = 1.0e4
+    far = bem.potential(t, R * xh) * R * np.exp(-1.0j * R)
+    uinf = bem.farfield(t, xh)
+    assert np.abs(far - uinf).max() < 1e-3 * np.abs(uinf).max()
