@@ -18,6 +18,12 @@ roofline, and a continuous-batching request stream with p50/p99 latency.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
                     [--block 16] [--serve 32] [--serve-rate 1.0]
+
+`--convergence` instead runs the convergence benchmark of Sec. 5.2 (torus,
+kappa = 2.5, incidence along x, scattered field at 100 points on the radius-5
+sphere; soft p = 0..3, hard p = 1..3, m = 0..--conv-mmax) and prints one JSON
+line per solve and a final one with the l-infinity errors against the finest,
+highest-degree solution of each boundary condition and the observed orders.
 """
 from __future__ import annotations
 
@@ -100,6 +106,64 @@ def serve_stream(nreq, rate):
     return out
 
 
+def convergence_study(mmax, q, quad_extra, bcs=("soft", "hard"), out_path=None):
+    import torch
+
+    from paper_2306_11324_amd import binding as B
+    from paper_2306_11324_amd import inputs as I
+    ctx = B.Context(0)
+    dev = torch.device("cuda:0")
+    d = np.array([[1.0, 0.0, 0.0]])
+    pts = 5.0 * I.fibonacci_directions(100)
+    patches = I.torus_patches(2.0, 0.5)
+    series = [(bc, p) for bc in bcs for p in range(0 if bc == "soft" else 1, 4)]
+    vals, lines = {}, []
+    sink = open(out_path, "w") if out_path else None
+    for bc, p in series:
+        for m in range(mmax + 1):
+            t0 = time.perf_counter()
+            geo = B.Geometry(ctx, patches, m, p)
+            op = B.Operator(ctx, geo, kappa=2.5, bc=B.SOFT if bc == "soft" else B.HARD, q=q, eta_adm=1.6,
+                            leaf_depth=3, quad_extra=quad_extra)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            coeff = torch.zeros((1, op.n), dtype=torch.complex128, device=dev)
+            info, st = op.cfie_solve(d, coeff, tol=1e-12, restart=50, maxit=3000)
+            u = torch.zeros((1, len(pts)), dtype=torch.complex128, device=dev)
+            op.potential(coeff, pts, u)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            vals[(bc, p, m)] = u.cpu().numpy()[0]
+            rec = dict(bc=bc, p=p, m=m, n=op.n, status=st, iters=info.iters, converged=info.converged,
+                       relres_true=info.relres_true, assembly_s=t1 - t0, solve_s=t2 - t1)
+            lines.append(rec)
+            print(json.dumps(rec), flush=True)
+            if sink:
+                sink.write(json.dumps(dict(rec, u_re=vals[(bc, p, m)].real.tolist(),
+                                           u_im=vals[(bc, p, m)].imag.tolist())) + "\n")
+                sink.flush()
+            del op, geo
+    summary = {}
+    for bc in bcs:
+        pmax = 3
+        ref = vals[(bc, pmax, mmax)]
+        for p in range(0 if bc == "soft" else 1, 4):
+            errs = [float(np.abs(vals[(bc, p, m)] - ref).max()) for m in range(mmax + 1)]
+            if p == pmax:
+                errs[-1] = None
+            eoc = [None if (a is None or b is None or b == 0) else float(np.log2(a / b))
+                   for a, b in zip(errs[:-1], errs[1:])]
+            summary[f"{bc}_p{p}"] = dict(err=errs, eoc=eoc, expected=2 * p + 2 if bc == "soft" else 2 * p + 1)
+    out = {"study": "torus convergence", "kappa": 2.5, "q": q, "quad_extra": quad_extra, "mmax": mmax,
+           "points": "100 on |x| = 5",
+           "reference": "finest level, p = 3, same boundary condition", "series": summary}
+    print(json.dumps(out), flush=True)
+    if sink:
+        sink.write(json.dumps(out) + "\n")
+        sink.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +175,13 @@ def main():
     ap.add_argument("--block", type=int, default=16, help="directions per served block (0: skip)")
     ap.add_argument("--serve", type=int, default=32, help="requests in the served stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=1.0, help="Poisson arrival rate of the stream (1/s)")
+    ap.add_argument("--convergence", action="store_true", help="run the torus convergence benchmark instead")
+    ap.add_argument("--conv-mmax", type=int, default=6)
+    ap.add_argument("--conv-q", type=int, default=8)
+    ap.add_argument("--conv-quad-extra", type=int, default=2,
+                    help="raise every near-field quadrature order (the default orders leave a floor near 2e-7)")
+    ap.add_argument("--conv-bc", default="soft,hard")
+    ap.add_argument("--conv-out", default=None, help="also write the study's JSON lines to this file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
@@ -118,6 +189,11 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
                                    "described in DESIGN.md but not built)"}))
         sys.exit(2)
+
+    if args.convergence:
+        convergence_study(args.conv_mmax, args.conv_q, args.conv_quad_extra, tuple(args.conv_bc.split(",")),
+                          args.conv_out)
+        return
 
     import torch
 

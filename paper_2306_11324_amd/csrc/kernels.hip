@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_regular(NearArgs A) {
     constexpr int NV = HARD ? 4 : 1;
     constexpr int NK = HARD ? 2 : 1;
     constexpr int CI = 8;
-    constexpr int BUF = (CI * MAXQ * NK > MAXQ * NL * NV) ? CI * MAXQ * NK : MAXQ * NL * NV;
+    constexpr int BUF = (CI * MAXQ * NK > MAXQ * NL) ? CI * MAXQ * NK : MAXQ * NL;
     constexpr int ITEMS = (MAXQ * NL + NEAR_THREADS - 1) / NEAR_THREADS;
     __shared__ double xg[MAXQ][7];
     __shared__ double yg[MAXQ][7];
@@ -318,28 +319,28 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_regular(NearArgs A) {
         }
         __syncthreads();
     }
-    // T[j][a][v] into LDS
+    // one component v at a time: T[j][a] into LDS, then B[a][b] += sum_j T[j][a] py[j][b][v]
+    // (keeps the buffer at MAXQ * NL entries, which the degree-3 hypersingular case needs)
+    const int a = tid / NL, b = tid % NL;
+    double2 sum = make_double2(0, 0);
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-        const int w = tid + it * NEAR_THREADS;
-        if (w < nn * NL)
+    for (int v = 0; v < NV; ++v) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) buf[w * NV + v] = acc[it][v];
-    }
-    __syncthreads();
-    if (tid < NL * NL) {
-        const int a = tid / NL, b = tid % NL;
-        double2 sum = make_double2(0, 0);
-        for (int j = 0; j < nn; ++j)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const double2 t = buf[(j * NL + a) * NV + v];
+        for (int it = 0; it < ITEMS; ++it) {
+            const int w = tid + it * NEAR_THREADS;
+            if (w < nn * NL) buf[w] = acc[it][v];
+        }
+        __syncthreads();
+        if (tid < NL * NL)
+            for (int j = 0; j < nn; ++j) {
+                const double2 t = buf[j * NL + a];
                 const double y = py[j][b * NV + v];
                 sum.x = fma(t.x, y, sum.x);
                 sum.y = fma(t.y, y, sum.y);
             }
-        A.stage[(int64_t(k) - A.slot0) * NL * NL + tid] = sum;
+        __syncthreads();
     }
+    if (tid < NL * NL) A.stage[(int64_t(k) - A.slot0) * NL * NL + tid] = sum;
 }
 
 // --------------------------------------------------------------------------
@@ -1976,6 +1977,20 @@ igb_status upload_geometry(igb_geom g) {
     return IGB_OK;
 }
 
+// f(std::integral_constant<int, P>) for the degree p = 0..PMAX of the discrete spaces
+template <class F>
+static igb_status with_degree(int p, const char* who, F&& f) {
+    switch (p) {
+        case 0: return f(std::integral_constant<int, 0>{});
+        case 1: return f(std::integral_constant<int, 1>{});
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 3: return f(std::integral_constant<int, 3>{});
+        default:
+            set_error("%s: spline degree p = %d not built (0 <= p <= %d)", who, p, PMAX);
+            return IGB_ERR_UNSUPPORTED;
+    }
+}
+
 // orders of the GPU rules (see near_classify for the regular ones)
 constexpr int NSING_IDENT = 7, NSING_EDGE = 8, NSING_VERTEX = 9, MASS_ORDER = 6;
 
@@ -2119,13 +2134,13 @@ igb_status assemble_near_device(igb_op op, hipStream_t s) {
     }
     auto t0 = std::chrono::steady_clock::now();
     const bool hard = op->bc == IGB_HARD;
-    switch (g->p) {
-        case 1: st = hard ? near_launch<1, true>(op, s) : near_launch<1, false>(op, s); break;
-        case 2: st = hard ? near_launch<2, true>(op, s) : near_launch<2, false>(op, s); break;
-        default:
-            set_error("assemble_nearfield: spline degree p = %d not built (p = 1, 2)", g->p);
-            return IGB_ERR_UNSUPPORTED;
-    }
+    st = with_degree(g->p, "assemble_nearfield", [&](auto deg) {
+        constexpr int P = decltype(deg)::value;
+        if constexpr (P == 0)
+            return near_launch<0, false>(op, s);  // S^0 needs p >= 1: checked at the entry point
+        else
+            return hard ? near_launch<P, true>(op, s) : near_launch<P, false>(op, s);
+    });
     auto t1 = std::chrono::steady_clock::now();
     op->t_assembly_near = std::chrono::duration<double, std::milli>(t1 - t0).count();
     return st;
@@ -2606,23 +2621,15 @@ igb_status rhs_device(igb_op op, const double* dirs, int ndir, double* b, hipStr
     const int* s0p = hard ? op->d_s0_ptr.as<int>() : nullptr;
     const int* s0r = hard ? op->d_s0_reps.as<int>() : nullptr;
     double2* B = reinterpret_cast<double2*>(b);
-    switch (g->p) {
-        case 1:
-            hipLaunchKernelGGL(rhs_elements<1>, grid1, dim3(128), 0, s, A, d_dirs.as<double>(), ndir, op->kappa,
-                               op->eta, hard ? 1 : 0, d_loc.as<double2>());
-            hipLaunchKernelGGL(rhs_gather<1>, grid2, dim3(256), 0, s, d_loc.as<double2>(), ndir, g->nelem,
-                               g->nel1, g->k, op->N, s0p, s0r, B);
-            break;
-        case 2:
-            hipLaunchKernelGGL(rhs_elements<2>, grid1, dim3(128), 0, s, A, d_dirs.as<double>(), ndir, op->kappa,
-                               op->eta, hard ? 1 : 0, d_loc.as<double2>());
-            hipLaunchKernelGGL(rhs_gather<2>, grid2, dim3(256), 0, s, d_loc.as<double2>(), ndir, g->nelem,
-                               g->nel1, g->k, op->N, s0p, s0r, B);
-            break;
-        default:
-            set_error("cfie_rhs: p = %d not built", g->p);
-            return IGB_ERR_UNSUPPORTED;
-    }
+    if ((st = with_degree(g->p, "cfie_rhs", [&](auto deg) {
+             constexpr int P = decltype(deg)::value;
+             hipLaunchKernelGGL(rhs_elements<P>, grid1, dim3(128), 0, s, A, d_dirs.as<double>(), ndir, op->kappa,
+                                op->eta, hard ? 1 : 0, d_loc.as<double2>());
+             hipLaunchKernelGGL(rhs_gather<P>, grid2, dim3(256), 0, s, d_loc.as<double2>(), ndir, g->nelem,
+                                g->nel1, g->k, op->N, s0p, s0r, B);
+             return IGB_OK;
+         })))
+        return st;
     IGB_HIP(hipGetLastError());
     IGB_HIP(hipStreamSynchronize(s));  // temporaries are freed on return
     return IGB_OK;
@@ -2654,19 +2661,13 @@ igb_status farfield_device(igb_op op, const double* coeffs, int ndir, const doub
     const bool hard = op->bc == IGB_HARD;
     const double2* C = reinterpret_cast<const double2*>(coeffs);
     const int* s2s0 = hard ? op->d_s2_to_s0.as<int>() : nullptr;
-    switch (g->p) {
-        case 1:
-            hipLaunchKernelGGL(density_points<1>, dim3(unsigned((npts + 255) / 256)), dim3(256), 0, s, A, C, ndir,
-                               op->N, s2s0, g->k, d_geo.as<double>(), d_dens.as<double2>());
-            break;
-        case 2:
-            hipLaunchKernelGGL(density_points<2>, dim3(unsigned((npts + 255) / 256)), dim3(256), 0, s, A, C, ndir,
-                               op->N, s2s0, g->k, d_geo.as<double>(), d_dens.as<double2>());
-            break;
-        default:
-            set_error("farfield: p = %d not built", g->p);
-            return IGB_ERR_UNSUPPORTED;
-    }
+    if ((st = with_degree(g->p, "farfield", [&](auto deg) {
+             constexpr int P = decltype(deg)::value;
+             hipLaunchKernelGGL(density_points<P>, dim3(unsigned((npts + 255) / 256)), dim3(256), 0, s, A, C,
+                                ndir, op->N, s2s0, g->k, d_geo.as<double>(), d_dens.as<double2>());
+             return IGB_OK;
+         })))
+        return st;
     hipLaunchKernelGGL(farfield_sum, dim3(unsigned(nobs), unsigned(ndir)), dim3(256), 0, s, d_geo.as<double>(),
                        d_dens.as<double2>(), npts, d_obs.as<double>(), nobs, op->kappa, hard ? 1 : 0,
                        reinterpret_cast<double2*>(uinf));
@@ -2697,19 +2698,13 @@ igb_status potential_device(igb_op op, const double* coeffs, int ndir, const dou
     const bool hard = op->bc == IGB_HARD;
     const double2* C = reinterpret_cast<const double2*>(coeffs);
     const int* s2s0 = hard ? op->d_s2_to_s0.as<int>() : nullptr;
-    switch (g->p) {
-        case 1:
-            hipLaunchKernelGGL(density_points<1>, dim3(unsigned((npts + 255) / 256)), dim3(256), 0, s, A, C, ndir,
-                               op->N, s2s0, g->k, d_geo.as<double>(), d_dens.as<double2>());
-            break;
-        case 2:
-            hipLaunchKernelGGL(density_points<2>, dim3(unsigned((npts + 255) / 256)), dim3(256), 0, s, A, C, ndir,
-                               op->N, s2s0, g->k, d_geo.as<double>(), d_dens.as<double2>());
-            break;
-        default:
-            set_error("potential: p = %d not built", g->p);
-            return IGB_ERR_UNSUPPORTED;
-    }
+    if ((st = with_degree(g->p, "potential", [&](auto deg) {
+             constexpr int P = decltype(deg)::value;
+             hipLaunchKernelGGL(density_points<P>, dim3(unsigned((npts + 255) / 256)), dim3(256), 0, s, A, C,
+                                ndir, op->N, s2s0, g->k, d_geo.as<double>(), d_dens.as<double2>());
+             return IGB_OK;
+         })))
+        return st;
     hipLaunchKernelGGL(potential_sum, dim3(unsigned(npt), unsigned(ndir)), dim3(256), 0, s, d_geo.as<double>(),
                        d_dens.as<double2>(), npts, d_pts.as<double>(), npt, op->kappa, hard ? 1 : 0,
                        reinterpret_cast<double2*>(u));

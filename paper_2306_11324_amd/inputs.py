@@ -136,6 +136,39 @@ def sphere_patches(radius: float = 1.0) -> list[Patch]:
 
 
 # ---------------------------------------------------------------------------
+# Torus (major radius R, minor radius r) as 4 x 4 rational biquadratic Bezier
+# patches: each the tensor product of a quarter arc of the major circle (u)
+# and one of the minor circle (v), which represents the torus exactly; u then
+# v runs with the outward normal d_u F x d_v F.
+# ---------------------------------------------------------------------------
+
+def _quarter_arc(k: int):
+    """Control points (unit circle) and weights of the k-th quarter arc."""
+    a0, a1 = k * math.pi / 2, (k + 1) * math.pi / 2
+    pts = np.array([[math.cos(a0), math.sin(a0)],
+                    [math.cos(a0) + math.cos(a1), math.sin(a0) + math.sin(a1)],
+                    [math.cos(a1), math.sin(a1)]])
+    return pts, np.array([1.0, math.sqrt(0.5), 1.0])
+
+
+def torus_patches(R: float = 2.0, r: float = 0.5) -> list[Patch]:
+    knots = _open_uniform_knots(2, 1)
+    out = []
+    for j in range(4):            # minor circle (v)
+        mp, mw = _quarter_arc(j)
+        for i in range(4):        # major circle (u)
+            Mp, Mw = _quarter_arc(i)
+            net = np.zeros((3, 3, 4))
+            for b in range(3):
+                for a in range(3):
+                    rad = R + r * mp[b, 0]
+                    net[b, a, :3] = (rad * Mp[a, 0], rad * Mp[a, 1], r * mp[b, 1])
+                    net[b, a, 3] = Mw[a] * mw[b]
+            out.append(Patch(2, 2, knots.copy(), knots.copy(), net))
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Seeded smooth star-shaped scatterer r(s) = 1 + 0.1 * sum_{l<=4} c_lm Y_lm(s),
 # c_lm ~ N(0,1) drawn in (l, m = -l..l) order.  Each cube face carries a
 # degree-2 B-spline patch on 2^g uniform spans whose control points are the

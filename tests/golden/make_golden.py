@@ -19,6 +19,10 @@ Cases
   sphere_m2_k1_potential  scattered field at 72 points (r = 1.5, 2, 3) of the
                       dense LU solutions on the level-2 sphere (soft p = 1, hard
                       p = 2, kappa = 1), and the Mie series there.
+  torus_m2_k2p5_potential  the torus (R = 2, r = 0.5, 16 patches), m = 2,
+                      kappa = 2.5, d = (1, 0, 0): dense LU solutions (soft p = 1,
+                      hard p = 2) and their scattered field at 100 Fibonacci
+                      points on the radius-5 sphere (Sec. 5.2's set-up).
   star_m6_p2_k16_rows  seed-0 star, m = 6, p = 2, kappa = 16, soft: sampled rows
                       of the dense O1 matrix applied to the seeded vector.
   star_m7_p2_k32_hard_rows  seed-0 star, m = 7, p = 2, kappa = 32, hard (S^0):
@@ -112,6 +116,20 @@ def case_sphere_m2_k1_potential():
     return out
 
 
+def case_torus_m2_k2p5_potential():
+    out = {}
+    d = np.array([1.0, 0.0, 0.0])
+    pts = 5.0 * I.fibonacci_directions(100)
+    for bc, p in (("soft", 1), ("hard", 2)):
+        bem = G.DenseBEM(I.torus_patches(), p=p, m=2, kappa=2.5, bc=bc)
+        t = bem.solve(d)
+        out[f"{bc}_t"] = t
+        out[f"{bc}_pot"] = bem.potential(t, pts)
+    out["pts"] = pts
+    out["d"] = d
+    return out
+
+
 def _star_rows(m, kappa, bc, nrows):
     bem = G.DenseBEM(I.star_patches(0, I.star_geometry_level(m)), p=2, m=m, kappa=kappa, bc=bc)
     x = I.random_complex(X_SEED, bem.n)
@@ -137,6 +155,7 @@ CASES = {
     "star_m6_p2_k16_rows": case_star_m6_p2_k16_rows,
     "sphere_m2_k1_potential": case_sphere_m2_k1_potential,
     "star_m7_p2_k32_hard_rows": case_star_m7_p2_k32_hard_rows,
+    "torus_m2_k2p5_potential": case_torus_m2_k2p5_potential,
 }
 
 

@@ -54,3 +54,29 @@ def test_s0_dimension_on_star():
     disc = Discretization(inputs.star_patches(3, 2), 2, 3)
     k = 2 ** 3 + 2
     assert disc.s0_map()[1] == 6 * (k - 2) ** 2 + 12 * (k - 2) + 8
+
+
+def test_torus_exact_volume_area_closed_outward():
+    """16 rational biquadratic patches reproduce the torus (R = 2, r = 0.5)
+    exactly: every point on (sqrt(x^2+y^2) - R)^2 + z^2 = r^2, volume
+    2 pi^2 R r^2, area 4 pi^2 R r, normal along the minor-circle radius."""
+    R, r = 2.0, 0.5
+    vol, area, d = _volume_area(inputs.torus_patches(R, r), n=16)
+    X = d["X"]
+    rho = np.hypot(X[..., 0], X[..., 1])
+    assert np.abs((rho - R) ** 2 + X[..., 2] ** 2 - r * r).max() < 1e-13
+    assert abs(vol - 2 * np.pi ** 2 * R * r * r) < 1e-10
+    assert abs(area - 4 * np.pi ** 2 * R * r) < 1e-10
+    core = np.stack([R * X[..., 0] / rho, R * X[..., 1] / rho, 0 * rho], -1)
+    nt = d["nt"] / np.linalg.norm(d["nt"], axis=-1, keepdims=True)
+    assert np.abs(np.einsum("eqc,eqc->eq", X - core, nt) - r).max() < 1e-12
+
+
+@pytest.mark.parametrize("m,p", [(0, 1), (1, 2), (2, 3)])
+def test_dimensions_on_torus(m, p):
+    """Genus one: the glued space is (4 (k - 1))^2-dimensional (every vertex,
+    edge and face of the 4 x 4 periodic patch grid is shared)."""
+    disc = Discretization(inputs.torus_patches(), p, m)
+    k = 2 ** m + p
+    assert disc.n2 == 16 * k * k
+    assert disc.s0_map()[1] == 16 * (k - 1) ** 2
