@@ -102,9 +102,15 @@ typedef enum { IGB_FP64 = 0, IGB_MIX_FP32 = 1, IGB_MIX_BF16 = 2 } igb_prec;
  *              the node pairs as it goes: the same interpolated operator (to
  *              rounding), no coupling memory, bound by fp64 arithmetic
  *   quad_extra Gauss points per direction added to (negative: removed from) the
- *              default near-field rules (regular pairs: 4..7 by distance / size,
- *              raised with kappa * size, at least 2 and at most 10; touching pairs:
- *              7 / 8 / 9 for identical / edge / vertex, at most 12),
+ *              default near-field rules (regular pairs: per element and direction
+ *              4..12 by centre distance / extent in that direction, raised with
+ *              kappa * size, at least 2 and at most 12, at most 100 points per
+ *              element; touching pairs:
+ *              7 / 8 / 9 for identical / edge / vertex, raised with kappa times the
+ *              largest element size and with the largest element aspect ratio,
+ *              at most 16); values > 0 also raise the rules of the right-hand
+ *              side, far field and potential (base 6, 6 and 8, raised with
+ *              kappa * element size, at most 16),
  *              -2 <= quad_extra <= 3: accuracy of the near field against assembly time */
 typedef struct {
     double kappa;
@@ -211,9 +217,11 @@ igb_status igb_op_far_blocks(igb_op op, int32_t* out);
 
 /* Near element pairs (host arrays): ptr[nelem+1], src[near_elem_pairs] sorted per
  * target element, kind[near_elem_pairs] = quadrature class (bits 0-3: 0 regular,
- * 1 common vertex, 2 common edge, 4 identical; bits 8-11: Gauss order of a
- * regular pair; bits 16-18 / 20-22: square symmetries bringing the pair into
- * the canonical touching configuration).  Works on host-only contexts. */
+ * 1 common vertex, 2 common edge, 4 identical; regular pairs: bits 8-11 /
+ * 12-15 Gauss orders along u / v on the test element, bits 16-19 / 20-23 on
+ * the trial element; touching pairs: bits 16-18 / 20-22 square symmetries
+ * bringing the pair into the canonical configuration).  Works on host-only
+ * contexts. */
 igb_status igb_op_near_pairs(igb_op op, int64_t* ptr, int32_t* src, int32_t* kind);
 
 /* Per-kernel timing with HIP events recorded on the launch stream around the
@@ -280,7 +288,8 @@ igb_status farfield(igb_op op, const double* coeffs, int ndir, const double* obs
  *   hard  u_s(x) =  int dG(x,y)/dn_y g(y) dsigma_y,   G = e^{i kappa r}/(4 pi r),
  * for ndir coefficient vectors (device coeffs [ndir][n]) at npts points (host
  * points [npts][3]) into device u [ndir][npts], by tensor Gauss quadrature
- * (8 x 8 points) on every element.  Accurate for points at least about one
+ * on every element (8 x 8 points, more for elements large against the
+ * wavelength or quad_extra > 0).  Accurate for points at least about one
  * element diameter from the surface (no near-singular correction is applied
  * closer in).  IGB_ERR_ARG for non-finite points.  Synchronous. */
 igb_status potential(igb_op op, const double* coeffs, int ndir, const double* points, int npts, double* u,

@@ -114,6 +114,8 @@ struct igb_op_s {
     int bc = 0;
     double kappa = 0, eta = 0;
     int q = 0, nq = 0, L = 0, d = 0;
+    double kd_elem = 0;           // kappa * largest element box diagonal
+    double aspect_max = 1;        // largest ratio of an element's extents along u and v
     int64_t N = 0;
     // cluster indexing: level l holds npatch * 4^l clusters starting at clu_off[l]
     std::vector<int64_t> clu_off;
@@ -197,7 +199,18 @@ igb_status farfield_device(igb_op op, const double* coeffs, int ndir, const doub
                            int nobs, double* uinf, hipStream_t s);
 igb_status potential_device(igb_op op, const double* coeffs, int ndir, const double* points, int npt, double* u,
                             hipStream_t s);
-constexpr int POTENTIAL_ORDER = 8;   // Gauss points per direction and element
+// Extra Gauss points per direction for a wavenumber-scaled size kd = kappa * diameter:
+// one more for each doubling of kd beyond 1.5 (oscillation of e^{i kappa r} across it).
+inline int kd_boost(double kd) { return (kd >= 1.5) + (kd >= 3.0) + (kd >= 6.0); }
+constexpr int REG_POINTS_MAX = 100;  // Gauss points per element of a regular near pair
+// Extra points per direction of the touching-pair rules for elements much longer
+// in one direction than in the other (the rules see the singularity through the
+// reference square, where such an element squeezes it along one axis).
+inline int aspect_boost(double a) { return (a >= 2.0) + (a >= 3.0) + (a >= 5.0); }
+// Gauss orders per direction and element of the surface integrals that carry
+// no singularity: right-hand side and far field (base 6), potential off the
+// boundary (base 8); raised with kappa * element size and quad_extra > 0.
+int smooth_order(igb_op op, int base);
 igb_status gmres_device(igb_op op, const double* b, double* x, int ndir,
                         const igb_solve_params* sp, igb_solve_info* info, hipStream_t s);
 

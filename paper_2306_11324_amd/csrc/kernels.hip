@@ -157,7 +157,7 @@ __device__ __forceinline__ double2 kernel_soft(const double* X, const double* NX
 // Near field: regular element pairs (tensor Gauss of order n on both elements)
 // --------------------------------------------------------------------------
 constexpr int NEAR_THREADS = 256;
-constexpr int NGMAX = 12;
+constexpr int NGMAX = 16;
 
 struct NearArgs {
     const double* bez;
@@ -244,10 +244,11 @@ __device__ __forceinline__ void point_data(const ElemRef& R, const double* Cu, c
 }
 
 // --------------------------------------------------------------------------
-// Near field: regular element pairs, tensor Gauss of order n (n*n <= MAXQ) on
-// both elements.  Kernel values are produced in chunks of CI test points in LDS;
-// thread items (j, a) accumulate T[j][a] = sum_i w phi_a(x_i) k(x_i, y_j);
-// finally B[a][b] = sum_j T[j][a] . w phi_b(y_j).
+// Near field: regular element pairs, tensor Gauss rules of orders (nu, nv) on
+// each element (nu * nv <= MAXQ points; the orders may differ between the two
+// elements and between directions).  Kernel values are produced in chunks of
+// CI test points in LDS; thread items (j, a) accumulate
+// T[j][a] = sum_i w phi_a(x_i) k(x_i, y_j); finally B[a][b] = sum_j T[j][a] . w phi_b(y_j).
 // --------------------------------------------------------------------------
 template <int P, bool HARD, int MAXQ>
 __global__ __launch_bounds__(NEAR_THREADS) void near_regular(NearArgs A) {
@@ -267,18 +268,21 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_regular(NearArgs A) {
     if (item >= A.nlist) return;
     const int k = A.list[item];
     const int e = A.pair_e[k], f = A.pair_f[k];
-    const int n = (A.pair_kind[k] >> 8) & 15;
-    const int nn = n * n;
-    const double* gx = A.gl + n * 2 * NGMAX;
-    const double* gw = gx + NGMAX;
+    const int kind = A.pair_kind[k];
+    const int nxu = (kind >> 8) & 15, nxv = (kind >> 12) & 15, nyu = (kind >> 16) & 15, nyv = (kind >> 20) & 15;
+    const int nx = nxu * nxv, ny = nyu * nyv;
     const int tid = threadIdx.x;
 
-    if (tid < 2 * nn) {
-        const bool isx = tid < nn;
-        const int i = isx ? tid : tid - nn;
+    if (tid < nx + ny) {
+        const bool isx = tid < nx;
+        const int i = isx ? tid : tid - nx;
+        const int nu = isx ? nxu : nyu, nv = isx ? nxv : nyv;
+        const double* gu = A.gl + nu * 2 * NGMAX;
+        const double* gv = A.gl + nv * 2 * NGMAX;
         const ElemRef R = elem_ref(A.bez, A.pg, A.nel1, isx ? e : f);
-        point_data<P, HARD>(R, A.C1 + R.ex * (P + 1) * (P + 1), A.C1 + R.ey * (P + 1) * (P + 1), gx[i % n],
-                            gx[i / n], gw[i % n] * gw[i / n], isx ? xg[i] : yg[i], isx ? px[i] : py[i]);
+        point_data<P, HARD>(R, A.C1 + R.ex * (P + 1) * (P + 1), A.C1 + R.ey * (P + 1) * (P + 1), gu[i % nu],
+                            gv[i / nu], gu[NGMAX + i % nu] * gv[NGMAX + i / nu], isx ? xg[i] : yg[i],
+                            isx ? px[i] : py[i]);
     }
     __syncthreads();
 
@@ -287,10 +291,10 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_regular(NearArgs A) {
     for (int it = 0; it < ITEMS; ++it)
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[it][v] = make_double2(0, 0);
-    for (int i0 = 0; i0 < nn; i0 += CI) {
-        const int ci = min(CI, nn - i0);
-        for (int idx = tid; idx < ci * nn; idx += NEAR_THREADS) {
-            const int i = i0 + idx / nn, j = idx % nn;
+    for (int i0 = 0; i0 < nx; i0 += CI) {
+        const int ci = min(CI, nx - i0);
+        for (int idx = tid; idx < ci * ny; idx += NEAR_THREADS) {
+            const int i = i0 + idx / ny, j = idx % ny;
             const KVal kv = kernel_pair<HARD>(xg[i], xg[i] + 3, xg[i][6], yg[j], yg[j] + 3, yg[j][6], A.kappa, A.eta);
             buf[idx * NK] = kv.s;
             if (HARD) buf[idx * NK + 1] = kv.g;
@@ -299,15 +303,15 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_regular(NearArgs A) {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
             const int w = tid + it * NEAR_THREADS;
-            if (w < nn * NL) {
+            if (w < ny * NL) {
                 const int j = w / NL, a = w % NL;
                 for (int ii = 0; ii < ci; ++ii) {
                     const double* pxv = &px[i0 + ii][a * NV];
-                    const double2 ks = buf[(ii * nn + j) * NK];
+                    const double2 ks = buf[(ii * ny + j) * NK];
                     acc[it][0].x = fma(pxv[0], ks.x, acc[it][0].x);
                     acc[it][0].y = fma(pxv[0], ks.y, acc[it][0].y);
                     if (HARD) {
-                        const double2 kg = buf[(ii * nn + j) * NK + 1];
+                        const double2 kg = buf[(ii * ny + j) * NK + 1];
 #pragma unroll
                         for (int v = 1; v < NV; ++v) {
                             acc[it][v].x = fma(pxv[v], kg.x, acc[it][v].x);
@@ -328,11 +332,11 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_regular(NearArgs A) {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
             const int w = tid + it * NEAR_THREADS;
-            if (w < nn * NL) buf[w] = acc[it][v];
+            if (w < ny * NL) buf[w] = acc[it][v];
         }
         __syncthreads();
         if (tid < NL * NL)
-            for (int j = 0; j < nn; ++j) {
+            for (int j = 0; j < ny; ++j) {
                 const double2 t = buf[j * NL + a];
                 const double y = py[j][b * NV + v];
                 sum.x = fma(t.x, y, sum.x);
@@ -1908,6 +1912,7 @@ std::vector<double> gauss_table() {
 
 void gauss01_host(int n, std::vector<double>& x, std::vector<double>& w) {
     static std::vector<double> tab = gauss_table();
+    n = std::max(1, std::min(n, NGMAX));
     x.assign(tab.begin() + n * 2 * NGMAX, tab.begin() + n * 2 * NGMAX + n);
     w.assign(tab.begin() + n * 2 * NGMAX + NGMAX, tab.begin() + n * 2 * NGMAX + NGMAX + n);
 }
@@ -2012,8 +2017,9 @@ static igb_status near_launch(igb_op op, hipStream_t s) {
     if ((st = upload(d_kind, op->near_kind.data(), op->near_kind.size(), nullptr))) return st;
     std::vector<double> gl = gauss_table();
     if ((st = upload(d_gl, gl.data(), gl.size(), nullptr))) return st;
-    const int ord[3] = {NSING_VERTEX + op->prm.quad_extra, NSING_EDGE + op->prm.quad_extra,
-                        NSING_IDENT + op->prm.quad_extra};
+    const int raise = op->prm.quad_extra + kd_boost(op->kd_elem) + aspect_boost(op->aspect_max);
+    const int ord[3] = {std::min(NGMAX, NSING_VERTEX + raise), std::min(NGMAX, NSING_EDGE + raise),
+                        std::min(NGMAX, NSING_IDENT + raise)};
     NearArgs A{};
     for (int c = 0; c < 3; ++c) {
         std::vector<double> r = duffy_rule(c, ord[c]);
@@ -2048,7 +2054,10 @@ static igb_status near_launch(igb_op op, hipStream_t s) {
     A.stage = d_stage.as<double2>();
     const bool hard = op->bc == IGB_HARD;
     int64_t e0 = 0;
-    std::vector<int> reg, sing;
+    std::vector<int> reg, reg_big, sing;
+    auto points = [](int kind) {
+        return std::max(((kind >> 8) & 15) * ((kind >> 12) & 15), ((kind >> 16) & 15) * ((kind >> 20) & 15));
+    };
     while (e0 < E) {
         int64_t e1 = e0;
         while (e1 < E && op->near_ptr[e1 + 1] - op->near_ptr[e0] <= max_slots) ++e1;
@@ -2058,27 +2067,35 @@ static igb_status near_launch(igb_op op, hipStream_t s) {
         }
         const int64_t k0 = op->near_ptr[e0], k1 = op->near_ptr[e1];
         reg.clear();
+        reg_big.clear();
         sing.clear();
-        for (int64_t k = k0; k < k1; ++k) ((op->near_kind[k] & 15) == 0 ? reg : sing).push_back(int(k));
+        for (int64_t k = k0; k < k1; ++k) {
+            const int kind = op->near_kind[k];
+            ((kind & 15) != 0 ? sing : points(kind) <= 49 ? reg : reg_big).push_back(int(k));
+        }
         A.slot0 = k0;
-        // regular pairs at the front of the list buffer, touching pairs behind them
+        // regular pairs with at most 49 points per element, then the larger regular
+        // rules, then the touching pairs
         std::vector<int> lst(reg);
+        lst.insert(lst.end(), reg_big.begin(), reg_big.end());
         lst.insert(lst.end(), sing.begin(), sing.end());
         if (!lst.empty())
             IGB_HIP(hipMemcpyAsync(d_list.ptr, lst.data(), lst.size() * sizeof(int), hipMemcpyHostToDevice, s));
         if (!reg.empty()) {
             A.list = d_list.as<int>();
             A.nlist = int64_t(reg.size());
-            if (op->prm.quad_extra <= 0)
-                hipLaunchKernelGGL((near_regular<P, HARD, 49>), dim3(unsigned(reg.size())), dim3(NEAR_THREADS), 0, s,
-                                   A);
-            else
-                hipLaunchKernelGGL((near_regular<P, HARD, 100>), dim3(unsigned(reg.size())), dim3(NEAR_THREADS), 0, s,
-                                   A);
+            hipLaunchKernelGGL((near_regular<P, HARD, 49>), dim3(unsigned(reg.size())), dim3(NEAR_THREADS), 0, s, A);
+            IGB_HIP(hipGetLastError());
+        }
+        if (!reg_big.empty()) {
+            A.list = d_list.as<int>() + reg.size();
+            A.nlist = int64_t(reg_big.size());
+            hipLaunchKernelGGL((near_regular<P, HARD, REG_POINTS_MAX>), dim3(unsigned(reg_big.size())),
+                               dim3(NEAR_THREADS), 0, s, A);
             IGB_HIP(hipGetLastError());
         }
         if (!sing.empty()) {
-            A.list = d_list.as<int>() + reg.size();
+            A.list = d_list.as<int>() + reg.size() + reg_big.size();
             A.nlist = int64_t(sing.size());
             hipLaunchKernelGGL((near_singular<P, HARD>), dim3(unsigned(sing.size())), dim3(NEAR_THREADS), 0, s, A);
             IGB_HIP(hipGetLastError());
@@ -2594,6 +2611,10 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
     return IGB_OK;
 }
 
+int smooth_order(igb_op op, int base) {
+    return std::min(NGMAX, base + kd_boost(op->kd_elem) + std::max(0, op->prm.quad_extra));
+}
+
 igb_status rhs_device(igb_op op, const double* dirs, int ndir, double* b, hipStream_t s) {
     igb_geom g = op->geom;
     std::vector<double> dn(3 * ndir);
@@ -2614,7 +2635,7 @@ igb_status rhs_device(igb_op op, const double* dirs, int ndir, double* b, hipStr
     const int NL = (g->p + 1) * (g->p + 1);
     if ((st = alloc(d_loc, size_t(ndir) * g->nelem * NL * sizeof(double2), nullptr))) return st;
     QuadGeoArgs A{g->d_bez.as<double>(), g->d_pg.as<int>(), g->d_C1.as<double>(), d_gl.as<double>(),
-                  g->nel1, g->p, 6, g->nelem};
+                  g->nel1, g->p, smooth_order(op, 6), g->nelem};
     const bool hard = op->bc == IGB_HARD;
     dim3 grid1(unsigned((g->nelem + 127) / 128), unsigned(ndir));
     dim3 grid2(unsigned((op->N + 255) / 256), unsigned(ndir));
@@ -2648,7 +2669,7 @@ igb_status farfield_device(igb_op op, const double* coeffs, int ndir, const doub
         for (int c = 0; c < 3; ++c) on[3 * i + c] = obs[3 * i + c] / nr;
     }
     igb_status st;
-    const int nqd = 6;
+    const int nqd = smooth_order(op, 6);
     const int64_t npts = g->nelem * nqd * nqd;
     DevBuf d_obs, d_gl, d_geo, d_dens;
     std::vector<double> gl = gauss_table();
@@ -2685,7 +2706,7 @@ igb_status potential_device(igb_op op, const double* coeffs, int ndir, const dou
             return IGB_ERR_ARG;
         }
     igb_status st;
-    const int nqd = POTENTIAL_ORDER;
+    const int nqd = smooth_order(op, 8);
     const int64_t npts = g->nelem * nqd * nqd;
     DevBuf d_pts, d_gl, d_geo, d_dens;
     std::vector<double> gl = gauss_table();

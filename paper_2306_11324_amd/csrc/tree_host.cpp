@@ -214,22 +214,48 @@ igb_status tree_build(igb_op op) {
     return IGB_OK;
 }
 
+// Gauss order per direction of a regular pair's tensor rule on one element:
+// from r = centre distance / (sqrt 2 * the element's extent in that direction),
+// so that a square element gets the same order in both directions and an
+// element much longer in one direction gets more points along it.
+static int regular_order(double r) {
+    return r >= 6.0 ? 4 : r >= 3.0 ? 5 : r >= 1.8 ? 6 : r >= 1.2 ? 7 : r >= 0.8 ? 8 : r >= 0.5 ? 10 : 12;
+}
+
 // Quadrature class of every near element pair:
 //   bits 0..3  : 0 regular, 1 common vertex, 2 common edge, 4 identical
-//   bits 8..11 : Gauss order of the regular rule
-//   bits 16..18: square symmetry of the test element, 20..22: of the trial element
-// Regular order from the ratio centre distance / larger box diagonal, raised
-// with kappa * diagonal.
+//   regular:  bits 8..11 / 12..15: Gauss orders along u / v on the test element,
+//             bits 16..19 / 20..23: the same on the trial element
+//   touching: bits 16..18: square symmetry of the test element, 20..22: of the trial element
+// Regular orders per direction (regular_order), raised with kappa * diagonal and
+// quad_extra, each in [2, 12] and at most REG_POINTS_MAX points per element (the
+// shorter direction gives way).
 igb_status near_classify(igb_op op) {
     igb_geom g = op->geom;
     const int64_t E = g->nelem;
-    std::vector<double> ctr(E * 3), diag(E);
+    std::vector<double> ctr(E * 3), diag(E), side(E * 2);
     for (int64_t e = 0; e < E; ++e) {
         eval_element_host(g, e, 0.5, 0.5, &ctr[3 * e], nullptr, nullptr);
+        double a[3], b[3], c[3], d[3], du = 0, dv = 0;
+        eval_element_host(g, e, 0.0, 0.5, a, nullptr, nullptr);
+        eval_element_host(g, e, 1.0, 0.5, b, nullptr, nullptr);
+        eval_element_host(g, e, 0.5, 0.0, c, nullptr, nullptr);
+        eval_element_host(g, e, 0.5, 1.0, d, nullptr, nullptr);
+        for (int k = 0; k < 3; ++k) {
+            du += (b[k] - a[k]) * (b[k] - a[k]);
+            dv += (d[k] - c[k]) * (d[k] - c[k]);
+        }
+        side[2 * e] = std::sqrt(du);
+        side[2 * e + 1] = std::sqrt(dv);
         double s2 = 0;
         for (int c = 0; c < 3; ++c) s2 += (g->hi[3 * e + c] - g->lo[3 * e + c]) * (g->hi[3 * e + c] - g->lo[3 * e + c]);
         diag[e] = std::sqrt(s2);
     }
+    op->kd_elem = op->kappa * *std::max_element(diag.begin(), diag.end());
+    op->aspect_max = 1;
+    for (int64_t e = 0; e < E; ++e)
+        op->aspect_max = std::max(op->aspect_max, std::max(side[2 * e], side[2 * e + 1]) /
+                                                      std::max(1e-300, std::min(side[2 * e], side[2 * e + 1])));
     op->near_kind.resize(op->near_src.size());
     std::atomic<int> bad_shared{-1};   // first inconsistency found: shared corner count (or 2)
     parallel_for(E, 64, [&](int64_t e) {
@@ -260,14 +286,26 @@ igb_status near_classify(igb_op op) {
                 double d2 = 0;
                 for (int c = 0; c < 3; ++c) d2 += (ctr[3 * e + c] - ctr[3 * f + c]) * (ctr[3 * e + c] - ctr[3 * f + c]);
                 const double dmax = std::max(diag[e], diag[f]);
-                double ratio = std::sqrt(d2) / dmax;
-                int n = ratio >= 6.0 ? 4 : ratio >= 3.0 ? 5 : ratio >= 1.8 ? 6 : 7;
-                // one more point per direction for each doubling of kappa * diameter
-                // beyond 1.5 (oscillation of e^{i kappa r} across the pair)
-                const double kd = op->kappa * dmax;
-                n += (kd >= 1.5) + (kd >= 3.0) + (kd >= 6.0);
-                n = std::max(2, std::min(n, 7) + op->prm.quad_extra);
-                kind = n << 8;
+                const double dist = std::sqrt(d2);
+                // raised with kappa * diameter (oscillation of e^{i kappa r} across the pair)
+                const int raise = kd_boost(op->kappa * dmax) + op->prm.quad_extra;
+                int ord[4];
+                for (int x = 0; x < 2; ++x) {
+                    const int64_t el = x ? f : e;
+                    int nu = regular_order(dist / (std::sqrt(2.0) * side[2 * el])) + raise;
+                    int nv = regular_order(dist / (std::sqrt(2.0) * side[2 * el + 1])) + raise;
+                    nu = std::max(2, std::min(nu, 12));
+                    nv = std::max(2, std::min(nv, 12));
+                    if (nu * nv > REG_POINTS_MAX) {
+                        if (nu >= nv)
+                            nv = REG_POINTS_MAX / nu;
+                        else
+                            nu = REG_POINTS_MAX / nv;
+                    }
+                    ord[2 * x] = nu;
+                    ord[2 * x + 1] = nv;
+                }
+                kind = (ord[0] << 8) | (ord[1] << 12) | (ord[2] << 16) | (ord[3] << 20);
             } else {
                 int expect = -1;
                 bad_shared.compare_exchange_strong(expect, shared);
