@@ -4,8 +4,9 @@ points on the radius-5 sphere.
 
   * against the dense fp64 oracle (tests/golden/torus_k2p5_potential.npz):
     solution coefficients and scattered field, soft p = 1 on level 2 and hard
-    p = 2 on level 1, with the default quadrature orders (which rise with
-    kappa times the element size) and with three more points per direction;
+    p = 2 on level 1, with the default quadrature orders (which follow the
+    3-5 : 1 aspect ratio of the torus elements and kappa times their size) and
+    with three more points per direction;
   * the convergence rates the paper reports for the CFIE (l-infinity error of
     the scattered field O(h^{2p+2}) sound-soft, O(h^{2p+1}) sound-hard) on
     levels 2..4 against the level-5, degree-3 solution of the same boundary
@@ -55,7 +56,7 @@ def test_torus_against_dense_oracle(bc, p, m, quad_extra):
     ec = np.abs(c - g[f"{bc}_t"]).max() / np.abs(g[f"{bc}_t"]).max()
     eu = np.abs(u - g[f"{bc}_pot"]).max() / np.abs(g[f"{bc}_pot"]).max()
     print(f"coefficients {ec:.2e}, scattered field {eu:.2e} (relative to max)", flush=True)
-    assert ec < (2e-5 if quad_extra == 0 else 1e-6) and eu < (5e-6 if quad_extra == 0 else 1e-6)
+    assert ec < 1e-6 and eu < 3e-7
 
 
 @pytest.mark.parametrize("bc", ["soft", "hard"])
