@@ -106,7 +106,7 @@ def serve_stream(nreq, rate):
     return out
 
 
-def convergence_study(mmax, q, quad_extra, bcs=("soft", "hard"), out_path=None):
+def convergence_study(mmax, q, quad_extra, bcs=("soft", "hard"), out_path=None, reference="cfie"):
     import torch
 
     from paper_2306_11324_amd import binding as B
@@ -119,44 +119,49 @@ def convergence_study(mmax, q, quad_extra, bcs=("soft", "hard"), out_path=None):
     series = [(bc, p) for bc in bcs for p in range(0 if bc == "soft" else 1, 4)]
     vals, lines = {}, []
     sink = open(out_path, "w") if out_path else None
-    for bc, p in series:
-        for m in range(mmax + 1):
-            t0 = time.perf_counter()
-            geo = B.Geometry(ctx, patches, m, p)
-            op = B.Operator(ctx, geo, kappa=2.5, bc=B.SOFT if bc == "soft" else B.HARD, q=q, eta_adm=1.6,
-                            leaf_depth=3, quad_extra=quad_extra)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            coeff = torch.zeros((1, op.n), dtype=torch.complex128, device=dev)
-            info, st = op.cfie_solve(d, coeff, tol=1e-12, restart=50, maxit=3000)
-            u = torch.zeros((1, len(pts)), dtype=torch.complex128, device=dev)
-            op.potential(coeff, pts, u)
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            vals[(bc, p, m)] = u.cpu().numpy()[0]
-            rec = dict(bc=bc, p=p, m=m, n=op.n, status=st, iters=info.iters, converged=info.converged,
-                       relres_true=info.relres_true, assembly_s=t1 - t0, solve_s=t2 - t1)
-            lines.append(rec)
-            print(json.dumps(rec), flush=True)
-            if sink:
-                sink.write(json.dumps(dict(rec, u_re=vals[(bc, p, m)].real.tolist(),
-                                           u_im=vals[(bc, p, m)].imag.tolist())) + "\n")
-                sink.flush()
-            del op, geo
+    runs = [(bc, p, m, "cfie") for bc, p in series for m in range(mmax + 1)]
+    if reference == "single_layer":
+        runs += [(bc, 3, mmax, "single_layer") for bc in bcs]
+    for bc, p, m, form in runs:
+        t0 = time.perf_counter()
+        geo = B.Geometry(ctx, patches, m, p)
+        op = B.Operator(ctx, geo, kappa=2.5, bc=B.SOFT if bc == "soft" else B.HARD, q=q, eta_adm=1.6,
+                        leaf_depth=3, quad_extra=quad_extra,
+                        formulation=B.SINGLE_LAYER if form == "single_layer" else B.CFIE)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        coeff = torch.zeros((1, op.n), dtype=torch.complex128, device=dev)
+        info, st = op.cfie_solve(d, coeff, tol=1e-12, restart=50, maxit=3000)
+        u = torch.zeros((1, len(pts)), dtype=torch.complex128, device=dev)
+        op.potential(coeff, pts, u)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        key = (bc, p, m) if form == "cfie" else (bc, "single_layer")
+        vals[key] = u.cpu().numpy()[0]
+        rec = dict(bc=bc, p=p, m=m, formulation=form, n=op.n, status=st, iters=info.iters, converged=info.converged,
+                   relres_true=info.relres_true, assembly_s=t1 - t0, solve_s=t2 - t1)
+        lines.append(rec)
+        print(json.dumps(rec), flush=True)
+        if sink:
+            sink.write(json.dumps(dict(rec, u_re=vals[key].real.tolist(), u_im=vals[key].imag.tolist())) + "\n")
+            sink.flush()
+        del op, geo
     summary = {}
     for bc in bcs:
         pmax = 3
-        ref = vals[(bc, pmax, mmax)]
+        ref = vals[(bc, pmax, mmax)] if reference == "cfie" else vals[(bc, "single_layer")]
         for p in range(0 if bc == "soft" else 1, 4):
             errs = [float(np.abs(vals[(bc, p, m)] - ref).max()) for m in range(mmax + 1)]
-            if p == pmax:
+            if p == pmax and reference == "cfie":
                 errs[-1] = None
             eoc = [None if (a is None or b is None or b == 0) else float(np.log2(a / b))
                    for a, b in zip(errs[:-1], errs[1:])]
             summary[f"{bc}_p{p}"] = dict(err=errs, eoc=eoc, expected=2 * p + 2 if bc == "soft" else 2 * p + 1)
     out = {"study": "torus convergence", "kappa": 2.5, "q": q, "quad_extra": quad_extra, "mmax": mmax,
            "points": "100 on |x| = 5",
-           "reference": "finest level, p = 3, same boundary condition", "series": summary}
+           "reference": ("finest level, p = 3, same boundary condition" if reference == "cfie" else
+                         "single-layer formulation, finest level, p = 3, same boundary condition"),
+           "series": summary}
     print(json.dumps(out), flush=True)
     if sink:
         sink.write(json.dumps(out) + "\n")
@@ -181,6 +186,8 @@ def main():
     ap.add_argument("--conv-quad-extra", type=int, default=2,
                     help="raise every near-field quadrature order (the default orders leave a floor near 2e-7)")
     ap.add_argument("--conv-bc", default="soft,hard")
+    ap.add_argument("--conv-reference", default="cfie", choices=["cfie", "single_layer"],
+                    help="reference solution: the finest CFIE solution or the single-layer one (as the paper)")
     ap.add_argument("--conv-out", default=None, help="also write the study's JSON lines to this file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
@@ -192,7 +199,7 @@ def main():
 
     if args.convergence:
         convergence_study(args.conv_mmax, args.conv_q, args.conv_quad_extra, tuple(args.conv_bc.split(",")),
-                          args.conv_out)
+                          args.conv_out, args.conv_reference)
         return
 
     import torch

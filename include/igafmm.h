@@ -73,6 +73,7 @@ typedef struct {
 
 typedef enum { IGB_SOFT = 0, IGB_HARD = 1 } igb_bc;
 typedef enum { IGB_FP64 = 0, IGB_MIX_FP32 = 1, IGB_MIX_BF16 = 2 } igb_prec;
+typedef enum { IGB_CFIE = 0, IGB_SINGLE_LAYER = 1 } igb_formulation;
 
 /* Operator parameters.
  *   kappa      wavenumber (> 0)
@@ -111,7 +112,14 @@ typedef enum { IGB_FP64 = 0, IGB_MIX_FP32 = 1, IGB_MIX_BF16 = 2 } igb_prec;
  *              at most 16); values > 0 also raise the rules of the right-hand
  *              side, far field and potential (base 6, 6 and 8, raised with
  *              kappa * element size, at most 16),
- *              -2 <= quad_extra <= 3: accuracy of the near field against assembly time */
+ *              -2 <= quad_extra <= 3: accuracy of the near field against assembly time
+ *   formulation IGB_CFIE: the systems above (direct, Sec. 4.1); IGB_SINGLE_LAYER:
+ *              the indirect single-layer ansatz u_s = -S t with t on S^2 (Sec. 5.2
+ *              compares against such solutions): IGB_SOFT solves V t = <u_inc, psi>,
+ *              IGB_HARD the adjoint double-layer equation (K* - 1/2 M) t =
+ *              <d_n u_inc, psi>; solutions, far fields and potentials then use the
+ *              sound-soft representation for both; eta_c is ignored.  Neither is
+ *              uniquely solvable at the interior Dirichlet eigenvalues of kappa. */
 typedef struct {
     double kappa;
     int bc;
@@ -123,6 +131,7 @@ typedef struct {
     int precision;
     int far_on_the_fly;
     int quad_extra;
+    int formulation;
 } igb_op_params;
 
 typedef struct {

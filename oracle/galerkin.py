@@ -35,7 +35,14 @@ Readings of the paper taken here (listed in the design doc):
                      soft u_inf(x) = -(1/4 pi) int e^{-i kappa x.y} t(y) dsigma,
                      hard u_inf(x) = -(i kappa/4 pi) int (x.n_y) e^{-i kappa x.y} g(y) dsigma;
 * default CFIE coupling eta_c = kappa (soft), -1/kappa (hard); any real eta != 0
-  gives a uniquely solvable system.
+  gives a uniquely solvable system;
+* indirect comparison solutions (Sec. 5.2 compares its CFIE results with
+  solutions of "an indirect formulation using a single layer or adjoint double
+  layer ansatz"), read as the single-layer ansatz u_s = -S t with t on S^2:
+  soft V t = <u_inc, psi> (the trace of u_s equals -u_inc), hard
+  (K* - 1/2 M) t = <d_n u_inc, psi> (the exterior normal derivative of S t is
+  (K* - 1/2) t, and d_n u_s = -d_n u_inc); the representation, far field and
+  potential are then the sound-soft ones for both.
 
 Quadrature (the paper defers to its references): tensor Gauss for regular
 pairs with the order chosen from centre distance / diameter, Duffy-type rules
@@ -159,23 +166,28 @@ class DenseBEM:
 
     def __init__(self, patches, p: int, m: int, kappa: float, bc: str = "soft",
                  eta: float | None = None, rules: PairRules | None = None,
-                 workers: int | None = None):
+                 workers: int | None = None, formulation: str = "cfie"):
+        if formulation not in ("cfie", "single_layer"):
+            raise ValueError("formulation must be 'cfie' or 'single_layer'")
         self.disc = Discretization(patches, p, m)
         self.kappa = float(kappa)
         self.bc = bc
+        self.formulation = formulation
+        # operator family: "soft" = S^2 with V, K* and the single-layer representation
+        self.family = "soft" if (bc == "soft" or formulation == "single_layer") else "hard"
         self.eta = default_eta(kappa, bc) if eta is None or eta == 0 else float(eta)
         self.rules = rules or PairRules()
         self.corners = self.disc.element_corners()
         self.centers = self.disc.element_centers()
         c = self.corners
         self.diam = np.max(np.linalg.norm(c[:, :, None, :] - c[:, None, :, :], axis=-1), axis=(1, 2))
-        self.ops = OPS_SOFT if bc == "soft" else OPS_HARD
+        self.ops = OPS_SOFT if self.family == "soft" else OPS_HARD
         self.workers = workers if workers is not None else min(8, len(os.sched_getaffinity(0)))
 
     # ------------------------------------------------------------ dimensions
     @property
     def n(self) -> int:
-        return self.disc.n2 if self.bc == "soft" else self.disc.s0_map()[1]
+        return self.disc.n2 if self.family == "soft" else self.disc.s0_map()[1]
 
     # -------------------------------------------------------- classification
     def classify(self, e: int):
@@ -307,6 +319,10 @@ class DenseBEM:
             yield from ex.map(self._one_target, targets, [ops] * len(targets))
 
     def _combine(self, parts):
+        if self.formulation == "single_layer":
+            if self.bc == "soft":
+                return parts["V"]
+            return -0.5 * parts["M"] + parts["Kstar"]
         if self.bc == "soft":
             return 0.5 * parts["M"] + parts["Kstar"] - 1j * self.eta * parts["V"]
         return 0.5 * parts["M"] - parts["K"] - 1j * self.eta * parts["W"]
@@ -315,7 +331,7 @@ class DenseBEM:
         """Full dense matrices in the solution space: dict op -> (n, n)."""
         disc = self.disc
         parts = self.operator_rows_s2(np.arange(disc.n2))
-        if self.bc == "hard":
+        if self.family == "hard":
             P = disc.glue_matrix()
             parts = {k: P.T @ v @ P for k, v in parts.items()}
         return parts
@@ -327,7 +343,7 @@ class DenseBEM:
         """Rows of the CFIE matrix in the solution space (S^2 soft, S^0 hard)."""
         disc = self.disc
         rows = np.asarray(rows)
-        if self.bc == "soft":
+        if self.family == "soft":
             return self._combine(self.operator_rows_s2(rows))
         s2_to_s0, n0 = disc.s0_map()
         reps = np.nonzero(np.isin(s2_to_s0, rows))[0]
@@ -359,14 +375,16 @@ class DenseBEM:
         k = self.kappa
         uinc = np.exp(1j * k * dd["X"] @ d)
         dn_a = 1j * k * (dd["nt"] @ d) * uinc          # a * d_n u_inc
-        if self.bc == "soft":
+        if self.formulation == "single_layer":
+            f = dd["a"] * uinc if self.bc == "soft" else dn_a
+        elif self.bc == "soft":
             f = dn_a - 1j * self.eta * dd["a"] * uinc
         else:
             f = dd["a"] * uinc - 1j * self.eta * dn_a
         loc = np.einsum("eq,q,eqa->ea", f, w, dd["phi"]) * disc.h ** 2
         b = np.zeros(disc.n2, dtype=np.complex128)
         np.add.at(b, disc.el_dofs.ravel(), loc.ravel())
-        if self.bc == "hard":
+        if self.family == "hard":
             b = disc.glue_matrix().T @ b
         return b
 
@@ -374,7 +392,7 @@ class DenseBEM:
         """Far-field pattern u_inf at unit directions obs for solution coeffs."""
         disc = self.disc
         c = np.asarray(coeffs, dtype=np.complex128)
-        if self.bc == "hard":
+        if self.family == "hard":
             c = disc.glue_matrix() @ c
         obs = np.asarray(obs, dtype=np.float64)
         obs = obs / np.linalg.norm(obs, axis=1, keepdims=True)
@@ -385,7 +403,7 @@ class DenseBEM:
         k = self.kappa
         ph = np.exp(-1j * k * np.einsum("eqc,oc->oeq", dd["X"], obs))
         wq = w[None, :] * disc.h ** 2
-        if self.bc == "soft":
+        if self.family == "soft":
             u = -np.einsum("oeq,eq,eq->o", ph, dens * dd["a"], np.broadcast_to(wq, dens.shape)) / (4 * np.pi)
         else:
             xn = np.einsum("eqc,oc->oeq", dd["nt"], obs)
@@ -401,7 +419,7 @@ class DenseBEM:
         element (for points well away from the surface)."""
         disc = self.disc
         c = np.asarray(coeffs, dtype=np.complex128)
-        if self.bc == "hard":
+        if self.family == "hard":
             c = disc.glue_matrix() @ c
         P = np.atleast_2d(np.asarray(points, dtype=np.float64))
         pts, w = qd.tensor2(n)
@@ -414,7 +432,7 @@ class DenseBEM:
             dy = dd["X"] - x                      # y - x
             r = np.linalg.norm(dy, axis=-1)
             G = np.exp(1j * k * r) / (4 * np.pi * r)
-            if self.bc == "soft":
+            if self.family == "soft":
                 out[i] = -np.sum(G * dd["a"] * dens)
             else:
                 out[i] = np.sum(G * (1j * k * r - 1) / r ** 2 * np.einsum("eqc,eqc->eq", dy, dd["nt"]) * dens)

@@ -70,6 +70,8 @@ class Cluster:
 class H2Oracle:
     def __init__(self, bem: DenseBEM, q: int, eta: float = 1.6, leaf_depth: int = 2,
                  kcap: float = 0.0, coupling_kernel=None):
+        if bem.formulation != "cfie":
+            raise ValueError("H2Oracle follows the CFIE operators only")
         self.bem = bem
         self.disc = disc = bem.disc
         self.q, self.eta, self.kcap = q, eta, kcap

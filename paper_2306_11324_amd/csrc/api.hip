@@ -168,7 +168,11 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
         set_error("assemble_nearfield: need -2 <= quad_extra <= 3");
         return IGB_ERR_ARG;
     }
-    if (prm->bc == IGB_HARD && g->p < 1) {
+    if (prm->formulation != IGB_CFIE && prm->formulation != IGB_SINGLE_LAYER) {
+        set_error("assemble_nearfield: formulation must be IGB_CFIE or IGB_SINGLE_LAYER");
+        return IGB_ERR_ARG;
+    }
+    if (prm->bc == IGB_HARD && prm->formulation == IGB_CFIE && g->p < 1) {
         set_error("assemble_nearfield: sound-hard needs S^0, i.e. p >= 1");
         return IGB_ERR_ARG;
     }
@@ -180,12 +184,34 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
     }
     op->geom = g;
     op->prm = *prm;
-    op->bc = prm->bc;
     op->kappa = prm->kappa;
-    op->eta = prm->eta_c != 0 ? prm->eta_c : (prm->bc == IGB_SOFT ? prm->kappa : -1.0 / prm->kappa);
+    if (prm->formulation == IGB_SINGLE_LAYER) {
+        // u_s = -S t on S^2: V t = u_inc (soft), (K* - 1/2) t = d_n u_inc (hard)
+        op->bc = IGB_SOFT;
+        op->eta = 0;
+        const bool soft = prm->bc == IGB_SOFT;
+        op->mix = SoftMix{soft ? 0.0 : 1.0, make_double2(soft ? 1.0 : 0.0, 0.0)};
+        op->cm = make_double2(soft ? 0.0 : -0.5, 0.0);
+        op->rn = make_double2(soft ? 0.0 : 1.0, 0.0);
+        op->rd = make_double2(soft ? 1.0 : 0.0, 0.0);
+    } else {
+        op->bc = prm->bc;
+        op->eta = prm->eta_c != 0 ? prm->eta_c : (prm->bc == IGB_SOFT ? prm->kappa : -1.0 / prm->kappa);
+        op->cm = make_double2(0.5, 0.0);
+        if (prm->bc == IGB_SOFT) {
+            // (1/2 M + K* - i eta V) t = <d_n u_inc - i eta u_inc, psi>
+            op->mix = SoftMix{1.0, make_double2(0.0, -op->eta)};
+            op->rn = make_double2(1.0, 0.0);
+            op->rd = make_double2(0.0, -op->eta);
+        } else {
+            // (1/2 M - K - i eta W) g = <u_inc - i eta d_n u_inc, psi>
+            op->rn = make_double2(0.0, -op->eta);
+            op->rd = make_double2(1.0, 0.0);
+        }
+    }
     op->q = prm->q;
     op->nq = (prm->q + 1) * (prm->q + 1);
-    op->N = prm->bc == IGB_SOFT ? g->n2 : g->n0;
+    op->N = op->bc == IGB_SOFT ? g->n2 : g->n0;
     igb_status st;
     if ((st = tree_build(op)) || (st = near_classify(op)) || (st = near_pattern(op))) {
         delete op;
@@ -193,7 +219,7 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
     }
     // device bytes of the operator (checked against the budget before allocating)
     const int nl = (g->p + 1) * (g->p + 1);
-    const int ntile = prm->bc == IGB_HARD ? 2 : 1;
+    const int ntile = op->bc == IGB_HARD ? 2 : 1;
     const size_t fp64_tiles =
         prm->far_on_the_fly ? 0 : size_t(op->nfar) * op->nq * op->nq * 16 * ntile + size_t(3) * op->nq * 16 + 256;
     size_t need = fp64_tiles + size_t(op->nnz) * 20 + size_t(op->N + 1) * 8 +
@@ -215,7 +241,7 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
                 op->chunks_mfma.len.size() * (ntile == 2 ? 10 : 1) * op->nq * 8;
     }
     // matvec work vectors for one column and a GMRES(30) basis
-    need += size_t(op->nclusters) * op->nq * 16 * (prm->bc == IGB_HARD ? 16 : 2) + size_t(g->n2) * 16 * 4 +
+    need += size_t(op->nclusters) * op->nq * 16 * (op->bc == IGB_HARD ? 16 : 2) + size_t(g->n2) * 16 * 4 +
             size_t(35) * op->N * 16;
     op->estimated_bytes = need;
     if (!budget_ok(ctx, need)) {

@@ -21,6 +21,12 @@ constexpr int NBZ = (PGMAX + 1) * (PGMAX + 1);
 constexpr int QMAX = 10;        // interpolation degree
 constexpr int NLOCMAX = (PMAX + 1) * (PMAX + 1);
 
+// Kernel of the sound-soft family of operators: ck K* + cv V (complex cv)
+struct SoftMix {
+    double ck;
+    double2 cv;
+};
+
 // thread-local error message set by every failing entry point
 void set_error(const char* fmt, ...);
 
@@ -111,8 +117,12 @@ struct M2LChunks {
 struct igb_op_s {
     igb_geom geom = nullptr;
     igb_op_params prm{};
-    int bc = 0;
+    int bc = 0;                   // operator family: IGB_SOFT (S^2, V and K*) or IGB_HARD (S^0, K and W)
     double kappa = 0, eta = 0;
+    // system (cm M + ck K* + cv V) t = <(rn d_n + rd) u_inc, psi> of the soft family, or
+    // (cm M - K - i eta W) g = <(rn d_n + rd) u_inc, psi> of the hard one
+    igb::SoftMix mix{1.0, {0.0, 0.0}};
+    double2 cm{0.5, 0.0}, rn{1.0, 0.0}, rd{0.0, 0.0};
     int q = 0, nq = 0, L = 0, d = 0;
     double kd_elem = 0;           // kappa * largest element box diagonal
     double aspect_max = 1;        // largest ratio of an element's extents along u and v

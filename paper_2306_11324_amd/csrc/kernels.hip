@@ -134,11 +134,13 @@ __device__ __forceinline__ ElemRef elem_ref(const double* bez, const int* pg, in
     return r;
 }
 
-// The pulled-back sound-soft CFIE kernel  a_y H (x-y).n~_x - i eta a_x a_y G
+// The pulled-back kernel of the sound-soft family  ck a_y H (x-y).n~_x + cv a_x a_y G
 // with G = e^{i kappa r}/(4 pi r), H = G (i kappa r - 1)/r^2 (Sec. 4.2, eq. of
-// the pulled-back kernel, applied to K* and V of the D2N system).
+// the pulled-back kernel, applied to K* and V): ck = 1, cv = -i eta for the
+// CFIE of the D2N system, cv = 1 (V alone) or ck = 1, cv = 0 (K* alone) for the
+// single-layer formulations.
 __device__ __forceinline__ double2 kernel_soft(const double* X, const double* NX, double ax,
-                                               const double* Y, double ay, double kappa, double eta) {
+                                               const double* Y, double ay, double kappa, SoftMix mix) {
     const double d0 = X[0] - Y[0], d1 = X[1] - Y[1], d2 = X[2] - Y[2];
     const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
     const double r = sqrt(r2);
@@ -147,10 +149,11 @@ __device__ __forceinline__ double2 kernel_soft(const double* X, const double* NX
     double sn, cs;
     sincos(kr, &sn, &cs);
     const double dn = d0 * NX[0] + d1 * NX[1] + d2 * NX[2];
-    const double c4 = 0.07957747154594767 * ir;  // 1/(4 pi r)
-    const double h = ay * dn * ir * ir * c4;       // a_y (x-y).n~_x / (4 pi r^3)
-    const double v = eta * ax * ay * c4;
-    return make_double2(h * (-cs - sn * kr) + v * sn, h * (cs * kr - sn) - v * cs);
+    const double c4 = 0.07957747154594767 * ir;        // 1/(4 pi r)
+    const double h = mix.ck * ay * dn * ir * ir * c4;   // ck a_y (x-y).n~_x / (4 pi r^3)
+    const double v = ax * ay * c4;
+    return make_double2(h * (-cs - sn * kr) + v * (mix.cv.x * cs - mix.cv.y * sn),
+                        h * (cs * kr - sn) + v * (mix.cv.x * sn + mix.cv.y * cs));
 }
 
 // --------------------------------------------------------------------------
@@ -172,7 +175,9 @@ struct NearArgs {
     int64_t slot0;           // staging slot = pair - slot0
     double2* stage;          // [slots][nloc*nloc]
     int nel1;
-    double kappa, eta;
+    double kappa, eta;       // eta: coupling of the sound-hard CFIE
+    SoftMix mix;             // kernel of the sound-soft family
+    double2 cm;              // multiple of the mass matrix added on identical pairs
     // singular rules: per class (0 vertex, 1 edge, 2 identical) points (s1,s2,r1,r2,w)
     const double* rule[3];
     int rule_n[3];
@@ -180,7 +185,7 @@ struct NearArgs {
 };
 
 // Kernel values at one point pair (element-local coordinates, n~ unnormalised):
-//   soft: s = a_y H (x-y).n~_x - i eta a_x a_y G                      (K* - i eta V)
+//   soft: s = ck a_y H (x-y).n~_x + cv a_x a_y G                      (ck K* + cv V)
 //   hard: s = a_x H (x-y).n~_y + i eta kappa^2 G n~_x.n~_y            (-K, kappa^2 part of -i eta W)
 //         g = -i eta G, multiplying the curl product c_i(x).c_j(y)    (curl part of -i eta W)
 struct KVal {
@@ -189,10 +194,10 @@ struct KVal {
 
 template <bool HARD>
 __device__ __forceinline__ KVal kernel_pair(const double* X, const double* NX, double ax, const double* Y,
-                                            const double* NY, double ay, double kappa, double eta) {
+                                            const double* NY, double ay, double kappa, double eta, SoftMix mix) {
     KVal k;
     if (!HARD) {
-        k.s = kernel_soft(X, NX, ax, Y, ay, kappa, eta);
+        k.s = kernel_soft(X, NX, ax, Y, ay, kappa, mix);
         k.g = make_double2(0, 0);
         return k;
     }
@@ -295,7 +300,8 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_regular(NearArgs A) {
         const int ci = min(CI, nx - i0);
         for (int idx = tid; idx < ci * ny; idx += NEAR_THREADS) {
             const int i = i0 + idx / ny, j = idx % ny;
-            const KVal kv = kernel_pair<HARD>(xg[i], xg[i] + 3, xg[i][6], yg[j], yg[j] + 3, yg[j][6], A.kappa, A.eta);
+            const KVal kv = kernel_pair<HARD>(xg[i], xg[i] + 3, xg[i][6], yg[j], yg[j] + 3, yg[j][6], A.kappa, A.eta,
+                                                 A.mix);
             buf[idx * NK] = kv.s;
             if (HARD) buf[idx * NK + 1] = kv.g;
         }
@@ -394,7 +400,7 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_singular(NearArgs A) {
                 double gxv[7], gyv[7];
                 point_data<P, HARD>(Re, Ce_u, Ce_v, s, t, 1.0, gxv, px[tid]);
                 point_data<P, HARD>(Rf, Cf_u, Cf_v, u, v, 1.0, gyv, py[tid]);
-                KVal kv = kernel_pair<HARD>(gxv, gxv + 3, gxv[6], gyv, gyv + 3, gyv[6], A.kappa, A.eta);
+                KVal kv = kernel_pair<HARD>(gxv, gxv + 3, gxv[6], gyv, gyv + 3, gyv[6], A.kappa, A.eta, A.mix);
                 kv.s = cscale(kv.s, r[4]);
                 kv.g = cscale(kv.g, r[4]);
                 kq[tid] = kv;
@@ -430,8 +436,8 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_singular(NearArgs A) {
     if (tid < NL * NL) {
         double2 sum = make_double2(0, 0);
         for (int g2 = 0; g2 < SPLIT; ++g2) sum = cadd(sum, red[g2 * NL * NL + tid]);
-        if (cls == 4) {
-            // + 1/2 mass matrix on the identical pair: int phi_a phi_b a
+        if (cls == 4 && (A.cm.x != 0 || A.cm.y != 0)) {
+            // + cm times the mass matrix on the identical pair: int phi_a phi_b a
             const int n = A.mass_order;
             const double* gx = A.gl + n * 2 * NGMAX;
             const double* gw = gx + NGMAX;
@@ -449,7 +455,8 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_singular(NearArgs A) {
                 const double pb = bv[ob / (P + 1)] * bu[ob % (P + 1)];
                 m += gw[i % n] * gw[i / n] * sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]) * pa * pb;
             }
-            sum.x += 0.5 * m;
+            sum.x += A.cm.x * m;
+            sum.y += A.cm.y * m;
         }
         A.stage[(int64_t(k) - A.slot0) * NL * NL + tid] = sum;
     }
@@ -564,7 +571,7 @@ __global__ void node_geometry(const double* bez, const int* pg, int nel1, int np
 
 // coupling[pair][b*nq + a] = k(x_a of target, y_b of source)
 __global__ void coupling_soft(const double* nodes, const int* pair_tgt, const int* pair_src,
-                              int64_t npairs, int nq, double kappa, double eta, double2* coup) {
+                              int64_t npairs, int nq, double kappa, SoftMix mix, double2* coup) {
     for (int64_t pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
         const double* T = nodes + int64_t(pair_tgt[pr]) * nq * 16;
         const double* S = nodes + int64_t(pair_src[pr]) * nq * 16;
@@ -573,7 +580,7 @@ __global__ void coupling_soft(const double* nodes, const int* pair_tgt, const in
             const int b = idx / nq, a = idx % nq;
             const double* X = T + a * 16;
             const double* Y = S + b * 16;
-            out[idx] = kernel_soft(X, X + 3, X[6], Y, Y[6], kappa, eta);
+            out[idx] = kernel_soft(X, X + 3, X[6], Y, Y[6], kappa, mix);
         }
     }
 }
@@ -890,7 +897,7 @@ template <> __device__ __forceinline__ bf16x2 round_to<bf16x2>(double2 v) {
 // functions as the fp64 tiles and rounded once (no fp64 tiles needed)
 template <class LT, bool HARD>
 __global__ void coupling_lo(const double* __restrict__ nodes, const int* __restrict__ pair_tgt,
-                            const int* __restrict__ pair_src, int64_t nfar, int nq, int nkc, double kappa, double eta,
+                            const int* __restrict__ pair_src, int64_t nfar, int nq, int nkc, double kappa, SoftMix mix,
                             LT* __restrict__ out) {
     constexpr int EPL = 16 / sizeof(LT), NT = HARD ? 2 : 1;
     const int64_t total = nfar * NT * nkc * nq * EPL;
@@ -915,7 +922,7 @@ __global__ void coupling_lo(const double* __restrict__ nodes, const int* __restr
             kernel_gh(X, Y, kappa, G, H);
             v = t == 0 ? G : H;
         } else {
-            v = kernel_soft(X, X + 3, X[6], Y, Y[6], kappa, eta);
+            v = kernel_soft(X, X + 3, X[6], Y, Y[6], kappa, mix);
         }
     }
     out[i] = round_to<LT>(v);
@@ -1297,7 +1304,7 @@ __global__ __launch_bounds__(NT) void m2l_otf_soft(const double* __restrict__ no
                                                    const int* __restrict__ chunk_tgt,
                                                    const int64_t* __restrict__ chunk_pair,
                                                    const int* __restrict__ chunk_len, int64_t nchunk, int nq, int ncol,
-                                                   double kappa, double eta, double2* __restrict__ part) {
+                                                   double kappa, SoftMix mix, double2* __restrict__ part) {
     __shared__ double ys[NT][8];
     __shared__ double2 xs[NT * RB];
     const int64_t ch = blockIdx.x;
@@ -1330,7 +1337,7 @@ __global__ __launch_bounds__(NT) void m2l_otf_soft(const double* __restrict__ no
         __syncthreads();
         if (a < nq) {
             for (int b = 0; b < nq; ++b) {
-                const double2 kv = kernel_soft(X, X + 3, X[6], ys[b], ys[b][6], kappa, eta);
+                const double2 kv = kernel_soft(X, X + 3, X[6], ys[b], ys[b][6], kappa, mix);
 #pragma unroll
                 for (int cb = 0; cb < RB; ++cb) acc[cb] = cfma(kv, xs[b * RB + cb], acc[cb]);
             }
@@ -1663,10 +1670,11 @@ struct QuadGeoArgs {
     int64_t nelem;
 };
 
-// per element: sum_g w_g f(x_g) phi_a(x_g) for each direction; f from the BC
+// per element: sum_g w_g f(x_g) phi_a(x_g) for each direction, with
+// f a = (rn d_n + rd) u_inc a = (rn i kappa d.n~ + rd a) u_inc
 template <int P>
-__global__ void rhs_elements(QuadGeoArgs A, const double* dirs, int ndir, double kappa, double eta,
-                             int hard, double2* loc /* [ndir][E][NL] */) {
+__global__ void rhs_elements(QuadGeoArgs A, const double* dirs, int ndir, double kappa, double2 rn, double2 rd,
+                             double2* loc /* [ndir][E][NL] */) {
     constexpr int NL = (P + 1) * (P + 1);
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int dir = blockIdx.y;
@@ -1689,15 +1697,10 @@ __global__ void rhs_elements(QuadGeoArgs A, const double* dirs, int ndir, double
         const double dn = d[0] * nt[0] + d[1] * nt[1] + d[2] * nt[2];
         double sn, cs;
         sincos(kappa * dx, &sn, &cs);
-        // soft: (i kappa d.n~ - i eta a) u_inc ; hard: (a + eta kappa d.n~) u_inc
-        double2 fval;
-        if (hard) {
-            const double c = a + eta * kappa * dn;
-            fval = make_double2(c * cs, c * sn);
-        } else {
-            const double c = kappa * dn - eta * a;  // i c u_inc
-            fval = make_double2(-c * sn, c * cs);
-        }
+        // c = rn i kappa d.n~ + rd a; f = c u_inc
+        const double kd = kappa * dn;
+        const double2 c = make_double2(-rn.y * kd + rd.x * a, rn.x * kd + rd.y * a);
+        const double2 fval = make_double2(c.x * cs - c.y * sn, c.x * sn + c.y * cs);
         double bu[P + 1], bv[P + 1];
         eval_basis1<P>(A.C1 + R.ex * (P + 1) * (P + 1), s, bu, nullptr);
         eval_basis1<P>(A.C1 + R.ey * (P + 1) * (P + 1), t, bv, nullptr);
@@ -2044,6 +2047,8 @@ static igb_status near_launch(igb_op op, hipStream_t s) {
     A.nel1 = g->nel1;
     A.kappa = op->kappa;
     A.eta = op->eta;
+    A.mix = op->mix;
+    A.cm = op->cm;
     A.mass_order = MASS_ORDER;
 
     // chunks of target elements with a bounded staging buffer
@@ -2268,7 +2273,7 @@ igb_status assemble_far_device(igb_op op, hipStream_t s) {
         else
             hipLaunchKernelGGL(coupling_soft, dim3(unsigned(std::min<int64_t>(op->nfar, 1 << 20))), dim3(256), 0, s,
                                op->d_nodes.as<double>(),
-                               d_ptg.as<int>(), op->d_far_src.as<int>(), op->nfar, nq, op->kappa, op->eta,
+                               d_ptg.as<int>(), op->d_far_src.as<int>(), op->nfar, nq, op->kappa, op->mix,
                                op->d_coupling.as<double2>());
         IGB_HIP(hipGetLastError());
     }
@@ -2286,16 +2291,16 @@ igb_status assemble_far_device(igb_op op, hipStream_t s) {
         const int* ps = op->d_far_src.as<int>();
         if (f32 && hard)
             hipLaunchKernelGGL((coupling_lo<float2, true>), grid, blk, 0, s, nd, pt, ps, op->nfar, nq, nkc, op->kappa,
-                               op->eta, op->d_coupling_lo.as<float2>());
+                               op->mix, op->d_coupling_lo.as<float2>());
         else if (f32)
             hipLaunchKernelGGL((coupling_lo<float2, false>), grid, blk, 0, s, nd, pt, ps, op->nfar, nq, nkc, op->kappa,
-                               op->eta, op->d_coupling_lo.as<float2>());
+                               op->mix, op->d_coupling_lo.as<float2>());
         else if (hard)
             hipLaunchKernelGGL((coupling_lo<bf16x2, true>), grid, blk, 0, s, nd, pt, ps, op->nfar, nq, nkc, op->kappa,
-                               op->eta, op->d_coupling_lo.as<bf16x2>());
+                               op->mix, op->d_coupling_lo.as<bf16x2>());
         else
             hipLaunchKernelGGL((coupling_lo<bf16x2, false>), grid, blk, 0, s, nd, pt, ps, op->nfar, nq, nkc,
-                               op->kappa, op->eta, op->d_coupling_lo.as<bf16x2>());
+                               op->kappa, op->mix, op->d_coupling_lo.as<bf16x2>());
         IGB_HIP(hipGetLastError());
     }
     for (M2LChunks* c : {&op->chunks, &op->chunks_mfma}) {
@@ -2383,7 +2388,7 @@ static void launch_m2l_fp64(igb_op op, double2* xh, int64_t ks, int ncol, hipStr
             constexpr int RB = 8;
             hipLaunchKernelGGL((m2l_otf_soft<NT, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
                                dim3(NT), 0, s, nd, xh, op->d_far_src.as<int>(), C.d_tgt.as<int>(),
-                               C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol, op->kappa, op->eta,
+                               C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol, op->kappa, op->mix,
                                op->d_part.as<double2>());
         }
         return;
@@ -2645,7 +2650,7 @@ igb_status rhs_device(igb_op op, const double* dirs, int ndir, double* b, hipStr
     if ((st = with_degree(g->p, "cfie_rhs", [&](auto deg) {
              constexpr int P = decltype(deg)::value;
              hipLaunchKernelGGL(rhs_elements<P>, grid1, dim3(128), 0, s, A, d_dirs.as<double>(), ndir, op->kappa,
-                                op->eta, hard ? 1 : 0, d_loc.as<double2>());
+                                op->rn, op->rd, d_loc.as<double2>());
              hipLaunchKernelGGL(rhs_gather<P>, grid2, dim3(256), 0, s, d_loc.as<double2>(), ndir, g->nelem,
                                 g->nel1, g->k, op->N, s0p, s0r, B);
              return IGB_OK;

@@ -30,6 +30,11 @@ Cases
                       near 1e-6; with these orders a further raise (regular
                       12/15/18, touching 16) moves the level-1 soft solution by
                       3.6e-8 (relative, coefficients) and its field by 1.1e-8.
+  sphere_m2_k1_single_layer  the indirect single-layer formulations on the
+                      level-2 sphere, p = 1, kappa = 1, d = (0, 0, 1): dense LU
+                      solutions (soft V t = u_inc, hard (K* - 1/2) t = d_n u_inc)
+                      and their scattered field at the 72 points of
+                      sphere_m2_k1_potential.
   star_m6_p2_k16_rows  seed-0 star, m = 6, p = 2, kappa = 16, soft: sampled rows
                       of the dense O1 matrix applied to the seeded vector.
   star_m7_p2_k32_hard_rows  seed-0 star, m = 7, p = 2, kappa = 32, hard (S^0):
@@ -123,6 +128,20 @@ def case_sphere_m2_k1_potential():
     return out
 
 
+def case_sphere_m2_k1_single_layer():
+    out = {}
+    d = np.array([0.0, 0.0, 1.0])
+    pts = np.concatenate([r * I.fibonacci_directions(24) for r in (1.5, 2.0, 3.0)])
+    for bc in ("soft", "hard"):
+        bem = G.DenseBEM(I.sphere_patches(), p=1, m=2, kappa=1.0, bc=bc, formulation="single_layer")
+        t = bem.solve(d)
+        out[f"{bc}_t"] = t
+        out[f"{bc}_pot"] = bem.potential(t, pts)
+    out["pts"] = pts
+    out["d"] = d
+    return out
+
+
 TORUS_RULES = dict(n_far=10, n_mid=12, n_near=14, n_sing=13)
 
 
@@ -166,6 +185,7 @@ CASES = {
     "sphere_m2_k1_potential": case_sphere_m2_k1_potential,
     "star_m7_p2_k32_hard_rows": case_star_m7_p2_k32_hard_rows,
     "torus_k2p5_potential": case_torus_k2p5_potential,
+    "sphere_m2_k1_single_layer": case_sphere_m2_k1_single_layer,
 }
 
 

@@ -159,3 +159,36 @@ def test_potential_matches_mie_outside_sphere(bc, p, m):
     far = bem.potential(t, R * xh) * R * np.exp(-1.0j * R)
     uinf = bem.farfield(t, xh)
     assert np.abs(far - uinf).max() < 1e-3 * np.abs(uinf).max()
+
+
+@pytest.mark.parametrize("bc,p,m", [("soft", 1, 2), ("hard", 1, 2)])
+def test_single_layer_formulations_match_mie(bc, p, m):
+    """Indirect single-layer ansatz u_s = -S t (soft: V t = u_inc, hard:
+    (K* - 1/2) t = d_n u_inc) on the sphere, kappa = 1: far field and scattered
+    field within 1e-3 of the Mie series of the same boundary condition (a wrong
+    sign of the mass term, of the right-hand side or of the representation
+    fails this by O(1))."""
+    bem = G.DenseBEM(inputs.sphere_patches(), p=p, m=m, kappa=1.0, bc=bc, formulation="single_layer")
+    assert bem.n == bem.disc.n2
+    d = np.array([0.0, 0.0, 1.0])
+    t = bem.solve(d)
+    obs = inputs.fibonacci_directions(64)
+    ref = mie.farfield(1.0, obs @ d, bc)
+    assert np.abs(bem.farfield(t, obs) - ref).max() / np.abs(ref).max() < 1e-3
+    pts = 2.0 * inputs.fibonacci_directions(24)
+    ref = mie.scattered(1.0, pts, d, bc)
+    assert np.abs(bem.potential(t, pts) - ref).max() < 1e-3 * np.abs(ref).max()
+
+
+def test_single_layer_hard_operator_is_kstar_minus_half_mass():
+    """The hard single-layer matrix is K* - 1/2 M on S^2 and the soft one V:
+    on the sphere their actions on the constant mode are the Mie symbols
+    lambda(K*) - 1/2 and lambda(V) of degree 0 (mass-weighted)."""
+    bem_h = G.DenseBEM(inputs.sphere_patches(), p=0, m=2, kappa=1.0, bc="hard", formulation="single_layer")
+    bem_s = G.DenseBEM(inputs.sphere_patches(), p=0, m=2, kappa=1.0, bc="soft", formulation="single_layer")
+    parts = bem_s.operator_matrices()
+    one = np.ones(bem_s.n)
+    mass1 = parts["M"] @ one
+    for bem, lam in ((bem_h, mie.eig_K(0, 1.0) - 0.5), (bem_s, mie.eig_V(0, 1.0))):
+        y = bem._combine(parts) @ one
+        assert np.abs(y - lam * mass1).max() < 3e-3 * np.abs(lam * mass1).max()
