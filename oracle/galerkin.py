@@ -36,9 +36,9 @@ Readings of the paper taken here (listed in the design doc):
                      hard u_inf(x) = -(i kappa/4 pi) int (x.n_y) e^{-i kappa x.y} g(y) dsigma;
 * default CFIE coupling eta_c = kappa (soft), -1/kappa (hard); any real eta != 0
   gives a uniquely solvable system;
-* indirect comparison solutions (Sec. 5.2 compares its CFIE results with
-  solutions of "an indirect formulation using a single layer or adjoint double
-  layer ansatz"), read as the single-layer ansatz u_s = -S t with t on S^2:
+* indirect comparison solutions (Sec. 5.2 measures its CFIE results against
+  indirect solutions from a single-layer or adjoint-double-layer ansatz, without
+  equations), read as the single-layer ansatz u_s = -S t with t on S^2:
   soft V t = <u_inc, psi> (the trace of u_s equals -u_inc), hard
   (K* - 1/2 M) t = <d_n u_inc, psi> (the exterior normal derivative of S t is
   (K* - 1/2) t, and d_n u_s = -d_n u_inc); the representation, far field and
