@@ -73,7 +73,14 @@ typedef struct {
 
 typedef enum { IGB_SOFT = 0, IGB_HARD = 1 } igb_bc;
 typedef enum { IGB_FP64 = 0, IGB_MIX_FP32 = 1, IGB_MIX_BF16 = 2 } igb_prec;
-typedef enum { IGB_CFIE = 0, IGB_SINGLE_LAYER = 1 } igb_formulation;
+typedef enum {
+    IGB_CFIE = 0,
+    IGB_SINGLE_LAYER = 1,
+    IGB_OP_V = 2,
+    IGB_OP_KSTAR = 3,
+    IGB_OP_K = 4,
+    IGB_OP_W = 5
+} igb_formulation;
 
 /* Operator parameters.
  *   kappa      wavenumber (> 0)
@@ -119,7 +126,18 @@ typedef enum { IGB_CFIE = 0, IGB_SINGLE_LAYER = 1 } igb_formulation;
  *              IGB_HARD the adjoint double-layer equation (K* - 1/2 M) t =
  *              <d_n u_inc, psi>; solutions, far fields and potentials then use the
  *              sound-soft representation for both; eta_c is ignored.  Neither is
- *              uniquely solvable at the interior Dirichlet eigenvalues of kappa. */
+ *              uniquely solvable at the interior Dirichlet eigenvalues of kappa.
+ *              IGB_OP_V / IGB_OP_KSTAR (on S^2) and IGB_OP_K / IGB_OP_W (regularised,
+ *              on S^0): the single Galerkin matrix of that boundary integral operator
+ *              (Sec. 4.1-4.3) as its own H^2 matrix, for h2_matvec only (cfie_rhs,
+ *              cfie_solve, farfield and potential return IGB_ERR_ARG); bc is ignored
+ *   separate   0: one H^2 matrix of the combined kernel (default); 1 (IGB_CFIE only):
+ *              one H^2 matrix per operator as in Sec. 5.1's set-up (soft: 1/2 M + K*
+ *              and V; hard: 1/2 M - K and W), each with its own near field and
+ *              couplings, applied as a lazy sum; the same system up to rounding at
+ *              twice the coupling memory and traffic.  igb_op_near_csr,
+ *              igb_op_far_blocks, igb_op_near_pairs, igb_op_profile and
+ *              igb_op_kernel_time return IGB_ERR_ARG on such an operator. */
 typedef struct {
     double kappa;
     int bc;
@@ -132,6 +150,7 @@ typedef struct {
     int far_on_the_fly;
     int quad_extra;
     int formulation;
+    int separate;
 } igb_op_params;
 
 typedef struct {

@@ -29,7 +29,7 @@ IGB_WARN_NOT_CONVERGED = 1
 IGB_HOST_ONLY = -1
 SOFT, HARD = 0, 1
 FP64, MIX_FP32, MIX_BF16 = 0, 1, 2
-CFIE, SINGLE_LAYER = 0, 1
+CFIE, SINGLE_LAYER, OP_V, OP_KSTAR, OP_K, OP_W = 0, 1, 2, 3, 4, 5
 PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
 MV_LOWPREC = 4
 CONTEXT_STREAM = "context"   # pass as stream=...: order the call on the context's own stream
@@ -45,7 +45,7 @@ class IgbOpParams(C.Structure):
     _fields_ = [("kappa", C.c_double), ("bc", C.c_int), ("eta_c", C.c_double), ("q", C.c_int),
                 ("eta_adm", C.c_double), ("kcap", C.c_double), ("leaf_depth", C.c_int),
                 ("precision", C.c_int), ("far_on_the_fly", C.c_int), ("quad_extra", C.c_int),
-                ("formulation", C.c_int)]
+                ("formulation", C.c_int), ("separate", C.c_int)]
 
 
 class IgbSolveParams(C.Structure):
@@ -190,10 +190,10 @@ class Operator:
     def __init__(self, ctx: Context, geom: Geometry, kappa: float, bc: int = SOFT, eta_c: float = 0.0,
                  q: int = 6, eta_adm: float = 1.6, kcap: float = 0.0, leaf_depth: int = 2,
                  precision: int = FP64, far_on_the_fly: bool = False, quad_extra: int = 0,
-                 formulation: int = CFIE):
+                 formulation: int = CFIE, separate: bool = False):
         self.ctx, self.geom = ctx, geom
         self.params = IgbOpParams(kappa, bc, eta_c, q, eta_adm, kcap, leaf_depth, precision,
-                                  1 if far_on_the_fly else 0, quad_extra, formulation)
+                                  1 if far_on_the_fly else 0, quad_extra, formulation, 1 if separate else 0)
         h = _P()
         _check("assemble_nearfield", _lib.assemble_nearfield(ctx.h, geom.h, C.byref(self.params), C.byref(h)))
         self.h = h

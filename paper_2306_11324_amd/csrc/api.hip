@@ -28,6 +28,24 @@ igb_status need_device(igb_op op, const char* what) {
     return IGB_OK;
 }
 
+// entry points that need a right-hand side / representation (not single operators)
+static igb_status need_system(igb_op op, const char* what) {
+    if (!op->system) {
+        set_error("%s: the operator is a single boundary integral operator (IGB_OP_*), not a system", what);
+        return IGB_ERR_ARG;
+    }
+    return IGB_OK;
+}
+
+// entry points that read one H^2 matrix's internals
+static igb_status need_single_matrix(igb_op op, const char* what) {
+    if (!op->sum_parts.empty()) {
+        set_error("%s: not available on an operator stored as separate H^2 matrices", what);
+        return IGB_ERR_ARG;
+    }
+    return IGB_OK;
+}
+
 bool budget_ok(igb_ctx ctx, size_t add) {
     return ctx->budget == 0 || ctx->used + add <= ctx->budget;
 }
@@ -144,39 +162,67 @@ igb_status igb_geom_dims(igb_geom g, int64_t dims[3]) {
     return IGB_OK;
 }
 
-igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm, igb_op* out) {
-    if (!ctx || !g || !prm || !out) {
-        set_error("assemble_nearfield: NULL argument");
-        return IGB_ERR_ARG;
+// Coefficients of one assembled operator (see the system in igb_op_s)
+struct Coefs {
+    int family;
+    double eta;
+    SoftMix mix;
+    HardMix hmix;
+    double2 cm, rn, rd;
+    bool system;   // a right-hand side and a representation exist (not for single operators)
+};
+
+static Coefs coefs_for(const igb_op_params* prm) {
+    Coefs c{};
+    c.system = true;
+    c.hmix = HardMix{make_double2(0, 0), make_double2(0, 0)};
+    c.mix = SoftMix{0.0, make_double2(0, 0)};
+    c.cm = c.rn = c.rd = make_double2(0, 0);
+    const bool soft = prm->bc == IGB_SOFT;
+    switch (prm->formulation) {
+        case IGB_SINGLE_LAYER:
+            // u_s = -S t on S^2: V t = u_inc (soft), (K* - 1/2) t = d_n u_inc (hard)
+            c.family = IGB_SOFT;
+            c.mix = SoftMix{soft ? 0.0 : 1.0, make_double2(soft ? 1.0 : 0.0, 0.0)};
+            c.cm = make_double2(soft ? 0.0 : -0.5, 0.0);
+            c.rn = make_double2(soft ? 0.0 : 1.0, 0.0);
+            c.rd = make_double2(soft ? 1.0 : 0.0, 0.0);
+            break;
+        case IGB_OP_V:
+        case IGB_OP_KSTAR:
+            c.family = IGB_SOFT;
+            c.mix = SoftMix{prm->formulation == IGB_OP_KSTAR ? 1.0 : 0.0,
+                            make_double2(prm->formulation == IGB_OP_V ? 1.0 : 0.0, 0.0)};
+            c.system = false;
+            break;
+        case IGB_OP_K:
+        case IGB_OP_W:
+            c.family = IGB_HARD;
+            c.hmix = HardMix{make_double2(prm->formulation == IGB_OP_K ? 1.0 : 0.0, 0.0),
+                             make_double2(prm->formulation == IGB_OP_W ? 1.0 : 0.0, 0.0)};
+            c.system = false;
+            break;
+        default:  // IGB_CFIE
+            c.family = prm->bc;
+            c.eta = prm->eta_c != 0 ? prm->eta_c : (soft ? prm->kappa : -1.0 / prm->kappa);
+            c.cm = make_double2(0.5, 0.0);
+            if (soft) {
+                // (1/2 M + K* - i eta V) t = <d_n u_inc - i eta u_inc, psi>
+                c.mix = SoftMix{1.0, make_double2(0.0, -c.eta)};
+                c.rn = make_double2(1.0, 0.0);
+                c.rd = make_double2(0.0, -c.eta);
+            } else {
+                // (1/2 M - K - i eta W) g = <u_inc - i eta d_n u_inc, psi>
+                c.hmix = HardMix{make_double2(-1.0, 0.0), make_double2(0.0, -c.eta)};
+                c.rn = make_double2(0.0, -c.eta);
+                c.rd = make_double2(1.0, 0.0);
+            }
     }
-    if (!(prm->kappa > 0) || prm->q < 1 || prm->q > QMAX || !(prm->eta_adm > 0) || prm->leaf_depth < 0 ||
-        prm->leaf_depth > 6 ||
-        (prm->bc != IGB_SOFT && prm->bc != IGB_HARD)) {
-        set_error("assemble_nearfield: need kappa > 0, 1 <= q <= %d, eta_adm > 0, 0 <= leaf_depth <= 6, bc soft/hard",
-                  QMAX);
-        return IGB_ERR_ARG;
-    }
-    if (prm->precision != IGB_FP64 && prm->precision != IGB_MIX_FP32 && prm->precision != IGB_MIX_BF16) {
-        set_error("assemble_nearfield: precision must be IGB_FP64, IGB_MIX_FP32 or IGB_MIX_BF16");
-        return IGB_ERR_ARG;
-    }
-    if (prm->far_on_the_fly != 0 && prm->far_on_the_fly != 1) {
-        set_error("assemble_nearfield: far_on_the_fly must be 0 or 1");
-        return IGB_ERR_ARG;
-    }
-    if (prm->quad_extra < -2 || prm->quad_extra > 3) {
-        set_error("assemble_nearfield: need -2 <= quad_extra <= 3");
-        return IGB_ERR_ARG;
-    }
-    if (prm->formulation != IGB_CFIE && prm->formulation != IGB_SINGLE_LAYER) {
-        set_error("assemble_nearfield: formulation must be IGB_CFIE or IGB_SINGLE_LAYER");
-        return IGB_ERR_ARG;
-    }
-    if (prm->bc == IGB_HARD && prm->formulation == IGB_CFIE && g->p < 1) {
-        set_error("assemble_nearfield: sound-hard needs S^0, i.e. p >= 1");
-        return IGB_ERR_ARG;
-    }
-    if (!host_only(ctx)) IGB_HIP(hipSetDevice(ctx->device));
+    return c;
+}
+
+// One H^2 matrix: tree, near field, couplings (everything but the composite case)
+static igb_status build_one(igb_ctx ctx, igb_geom g, const igb_op_params* prm, const Coefs& c, igb_op* out) {
     igb_op op = new (std::nothrow) igb_op_s();
     if (!op) {
         set_error("assemble_nearfield: out of host memory");
@@ -185,30 +231,14 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
     op->geom = g;
     op->prm = *prm;
     op->kappa = prm->kappa;
-    if (prm->formulation == IGB_SINGLE_LAYER) {
-        // u_s = -S t on S^2: V t = u_inc (soft), (K* - 1/2) t = d_n u_inc (hard)
-        op->bc = IGB_SOFT;
-        op->eta = 0;
-        const bool soft = prm->bc == IGB_SOFT;
-        op->mix = SoftMix{soft ? 0.0 : 1.0, make_double2(soft ? 1.0 : 0.0, 0.0)};
-        op->cm = make_double2(soft ? 0.0 : -0.5, 0.0);
-        op->rn = make_double2(soft ? 0.0 : 1.0, 0.0);
-        op->rd = make_double2(soft ? 1.0 : 0.0, 0.0);
-    } else {
-        op->bc = prm->bc;
-        op->eta = prm->eta_c != 0 ? prm->eta_c : (prm->bc == IGB_SOFT ? prm->kappa : -1.0 / prm->kappa);
-        op->cm = make_double2(0.5, 0.0);
-        if (prm->bc == IGB_SOFT) {
-            // (1/2 M + K* - i eta V) t = <d_n u_inc - i eta u_inc, psi>
-            op->mix = SoftMix{1.0, make_double2(0.0, -op->eta)};
-            op->rn = make_double2(1.0, 0.0);
-            op->rd = make_double2(0.0, -op->eta);
-        } else {
-            // (1/2 M - K - i eta W) g = <u_inc - i eta d_n u_inc, psi>
-            op->rn = make_double2(0.0, -op->eta);
-            op->rd = make_double2(1.0, 0.0);
-        }
-    }
+    op->bc = c.family;
+    op->eta = c.eta;
+    op->mix = c.mix;
+    op->hmix = c.hmix;
+    op->cm = c.cm;
+    op->rn = c.rn;
+    op->rd = c.rd;
+    op->system = c.system;
     op->q = prm->q;
     op->nq = (prm->q + 1) * (prm->q + 1);
     op->N = op->bc == IGB_SOFT ? g->n2 : g->n0;
@@ -265,6 +295,97 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
     return IGB_OK;
 }
 
+
+igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm, igb_op* out) {
+    if (!ctx || !g || !prm || !out) {
+        set_error("assemble_nearfield: NULL argument");
+        return IGB_ERR_ARG;
+    }
+    if (!(prm->kappa > 0) || prm->q < 1 || prm->q > QMAX || !(prm->eta_adm > 0) || prm->leaf_depth < 0 ||
+        prm->leaf_depth > 6 ||
+        (prm->bc != IGB_SOFT && prm->bc != IGB_HARD)) {
+        set_error("assemble_nearfield: need kappa > 0, 1 <= q <= %d, eta_adm > 0, 0 <= leaf_depth <= 6, bc soft/hard",
+                  QMAX);
+        return IGB_ERR_ARG;
+    }
+    if (prm->precision != IGB_FP64 && prm->precision != IGB_MIX_FP32 && prm->precision != IGB_MIX_BF16) {
+        set_error("assemble_nearfield: precision must be IGB_FP64, IGB_MIX_FP32 or IGB_MIX_BF16");
+        return IGB_ERR_ARG;
+    }
+    if (prm->far_on_the_fly != 0 && prm->far_on_the_fly != 1) {
+        set_error("assemble_nearfield: far_on_the_fly must be 0 or 1");
+        return IGB_ERR_ARG;
+    }
+    if (prm->quad_extra < -2 || prm->quad_extra > 3) {
+        set_error("assemble_nearfield: need -2 <= quad_extra <= 3");
+        return IGB_ERR_ARG;
+    }
+    if (prm->formulation < IGB_CFIE || prm->formulation > IGB_OP_W) {
+        set_error("assemble_nearfield: formulation must be IGB_CFIE, IGB_SINGLE_LAYER or IGB_OP_V / _KSTAR / _K / _W");
+        return IGB_ERR_ARG;
+    }
+    if (prm->separate != 0 && (prm->separate != 1 || prm->formulation != IGB_CFIE)) {
+        set_error("assemble_nearfield: separate must be 0, or 1 with IGB_CFIE");
+        return IGB_ERR_ARG;
+    }
+    const Coefs c = coefs_for(prm);
+    if (c.family == IGB_HARD && g->p < 1) {
+        set_error("assemble_nearfield: the sound-hard operators need S^0, i.e. p >= 1");
+        return IGB_ERR_ARG;
+    }
+    if (!host_only(ctx)) IGB_HIP(hipSetDevice(ctx->device));
+    if (!prm->separate) return build_one(ctx, g, prm, c, out);
+
+    // One H^2 matrix per operator of the CFIE (soft: 1/2 M + K* and V; hard: 1/2 M - K
+    // and W), applied as the lazy sum part_0 + coef_1 part_1 (coef_1 = -i eta)
+    Coefs c0 = c, c1 = c;
+    c0.system = c1.system = false;
+    c1.cm = make_double2(0, 0);
+    if (c.family == IGB_SOFT) {
+        c0.mix = SoftMix{1.0, make_double2(0, 0)};
+        c1.mix = SoftMix{0.0, make_double2(1.0, 0)};
+    } else {
+        c0.hmix = HardMix{make_double2(-1.0, 0), make_double2(0, 0)};
+        c1.hmix = HardMix{make_double2(0, 0), make_double2(1.0, 0)};
+    }
+    igb_op p0 = nullptr, p1 = nullptr;
+    igb_status st;
+    if ((st = build_one(ctx, g, prm, c0, &p0))) return st;
+    if ((st = build_one(ctx, g, prm, c1, &p1))) {
+        igb_op_destroy(p0);
+        return st;
+    }
+    igb_op op = new (std::nothrow) igb_op_s();
+    if (!op) {
+        igb_op_destroy(p0);
+        igb_op_destroy(p1);
+        set_error("assemble_nearfield: out of host memory");
+        return IGB_ERR_ARG;
+    }
+    op->geom = g;
+    op->prm = *prm;
+    op->kappa = prm->kappa;
+    op->bc = c.family;
+    op->eta = c.eta;
+    op->mix = c.mix;
+    op->hmix = c.hmix;
+    op->cm = c.cm;
+    op->rn = c.rn;
+    op->rd = c.rd;
+    op->system = true;
+    op->q = p0->q;
+    op->nq = p0->nq;
+    op->N = p0->N;
+    op->kd_elem = p0->kd_elem;
+    op->aspect_max = p0->aspect_max;
+    op->sum_parts = {p0, p1};
+    op->sum_coef = {make_double2(1.0, 0.0), make_double2(0.0, -c.eta)};
+    op->estimated_bytes = p0->estimated_bytes + p1->estimated_bytes;
+    ++g->refs;
+    *out = op;
+    return IGB_OK;
+}
+
 void igb_op_destroy(igb_op op) {
     if (!op) return;
     igb_geom g = op->geom;
@@ -273,6 +394,8 @@ void igb_op_destroy(igb_op op) {
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
     }
+    for (igb_op part : op->sum_parts) igb_op_destroy(part);
+    op->sum_parts.clear();
     ctx->used -= std::min(ctx->used, op->dev_bytes);
     delete op;
     geom_release(g);
@@ -284,6 +407,26 @@ igb_status igb_op_get_info(igb_op op, igb_op_info* info) {
         return IGB_ERR_ARG;
     }
     std::memset(info, 0, sizeof(*info));
+    if (!op->sum_parts.empty()) {
+        // separate H^2 matrices: the tree of the first, sizes and times summed over all
+        igb_op_get_info(op->sum_parts.front(), info);
+        info->n = op->N;
+        info->far_pairs = info->near_elem_pairs = info->nnz = 0;
+        info->device_bytes = int64_t(op->dev_bytes);
+        info->estimated_bytes = int64_t(op->estimated_bytes);
+        info->assembly_near_ms = info->assembly_far_ms = 0;
+        for (igb_op part : op->sum_parts) {
+            igb_op_info pi;
+            igb_op_get_info(part, &pi);
+            info->far_pairs += pi.far_pairs;
+            info->near_elem_pairs += pi.near_elem_pairs;
+            info->nnz += pi.nnz;
+            info->device_bytes += pi.device_bytes;
+            info->assembly_near_ms += pi.assembly_near_ms;
+            info->assembly_far_ms += pi.assembly_far_ms;
+        }
+        return IGB_OK;
+    }
     info->n = op->N;
     info->nelem = op->geom->nelem;
     info->n2 = op->geom->n2;
@@ -306,6 +449,7 @@ igb_status igb_op_near_csr(igb_op op, int64_t* row_ptr, int32_t* col, double* va
         set_error("igb_op_near_csr: NULL argument");
         return IGB_ERR_ARG;
     }
+    if (igb_status st0 = need_single_matrix(op, "igb_op_near_csr")) return st0;
     igb_status st = need_device(op, "igb_op_near_csr");
     if (st) return st;
     IGB_HIP(hipSetDevice(op->geom->ctx->device));
@@ -320,6 +464,7 @@ igb_status igb_op_far_blocks(igb_op op, int32_t* out) {
         set_error("igb_op_far_blocks: NULL argument");
         return IGB_ERR_ARG;
     }
+    if (igb_status st0 = need_single_matrix(op, "igb_op_far_blocks")) return st0;
     int64_t i = 0;
     for (int l = 0; l <= op->L; ++l) {
         const FarLevel& F = op->far[l];
@@ -341,6 +486,7 @@ igb_status igb_op_near_pairs(igb_op op, int64_t* ptr, int32_t* src, int32_t* kin
         set_error("igb_op_near_pairs: NULL argument");
         return IGB_ERR_ARG;
     }
+    if (igb_status st0 = need_single_matrix(op, "igb_op_near_pairs")) return st0;
     std::memcpy(ptr, op->near_ptr.data(), op->near_ptr.size() * sizeof(int64_t));
     std::memcpy(src, op->near_src.data(), op->near_src.size() * sizeof(int32_t));
     std::memcpy(kind, op->near_kind.data(), op->near_kind.size() * sizeof(int32_t));
@@ -361,6 +507,7 @@ igb_status igb_op_profile(igb_op op, int enable) {
         set_error("igb_op_profile: NULL argument");
         return IGB_ERR_ARG;
     }
+    if (igb_status st0 = need_single_matrix(op, "igb_op_profile")) return st0;
     op->profile = enable != 0;
     for (auto& t : op->timers) t.used = 0;
     return IGB_OK;
@@ -373,6 +520,7 @@ igb_status igb_op_use_graphs(igb_op op, int enable) {
     }
     op->use_graphs = enable != 0;
     if (!op->use_graphs) op->clear_graphs();
+    for (igb_op part : op->sum_parts) igb_op_use_graphs(part, enable);
     return IGB_OK;
 }
 
@@ -381,6 +529,7 @@ igb_status igb_op_kernel_time(igb_op op, const char* name, int64_t* launches, do
         set_error("igb_op_kernel_time: NULL argument");
         return IGB_ERR_ARG;
     }
+    if (igb_status st0 = need_single_matrix(op, "igb_op_kernel_time")) return st0;
     static const char* names[4] = {"m2l", "spmv", "upward", "downward"};
     int slot = -1;
     for (int i = 0; i < 4; ++i)
@@ -423,6 +572,7 @@ igb_status cfie_rhs(igb_op op, const double* dirs, int ndir, double* b, void* hi
         return IGB_ERR_ARG;
     }
     if (igb_status st = need_device(op, "cfie_rhs")) return st;
+    if (igb_status st1 = need_system(op, "cfie_rhs")) return st1;
     IGB_HIP(hipSetDevice(op->geom->ctx->device));
     return rhs_device(op, dirs, ndir, b, pick(op->geom->ctx, hip_stream));
 }
@@ -434,6 +584,7 @@ igb_status cfie_solve(igb_op op, const double* dirs, int ndir, const igb_solve_p
         return IGB_ERR_ARG;
     }
     if (igb_status st0 = need_device(op, "cfie_solve")) return st0;
+    if (igb_status st1 = need_system(op, "cfie_solve")) return st1;
     IGB_HIP(hipSetDevice(op->geom->ctx->device));
     hipStream_t s = op->geom->ctx->stream;
     igb::DevBuf b;
@@ -452,6 +603,7 @@ igb_status farfield(igb_op op, const double* coeffs, int ndir, const double* obs
         return IGB_ERR_ARG;
     }
     if (igb_status st = need_device(op, "farfield")) return st;
+    if (igb_status st1 = need_system(op, "farfield")) return st1;
     IGB_HIP(hipSetDevice(op->geom->ctx->device));
     return farfield_device(op, coeffs, ndir, obs, nobs, uinf, pick(op->geom->ctx, hip_stream));
 }
@@ -463,6 +615,7 @@ igb_status potential(igb_op op, const double* coeffs, int ndir, const double* po
         return IGB_ERR_ARG;
     }
     if (igb_status st = need_device(op, "potential")) return st;
+    if (igb_status st1 = need_system(op, "potential")) return st1;
     IGB_HIP(hipSetDevice(op->geom->ctx->device));
     return potential_device(op, coeffs, ndir, points, npts, u, pick(op->geom->ctx, hip_stream));
 }

@@ -27,6 +27,12 @@ struct SoftMix {
     double2 cv;
 };
 
+// Kernel of the sound-hard family: ck K + cw W (complex ck, cw)
+struct HardMix {
+    double2 ck;
+    double2 cw;
+};
+
 // thread-local error message set by every failing entry point
 void set_error(const char* fmt, ...);
 
@@ -120,8 +126,9 @@ struct igb_op_s {
     int bc = 0;                   // operator family: IGB_SOFT (S^2, V and K*) or IGB_HARD (S^0, K and W)
     double kappa = 0, eta = 0;
     // system (cm M + ck K* + cv V) t = <(rn d_n + rd) u_inc, psi> of the soft family, or
-    // (cm M - K - i eta W) g = <(rn d_n + rd) u_inc, psi> of the hard one
+    // (cm M + ck K + cw W) g = <(rn d_n + rd) u_inc, psi> of the hard one (mix / hmix)
     igb::SoftMix mix{1.0, {0.0, 0.0}};
+    igb::HardMix hmix{{-1.0, 0.0}, {0.0, 0.0}};
     double2 cm{0.5, 0.0}, rn{1.0, 0.0}, rd{0.0, 0.0};
     int q = 0, nq = 0, L = 0, d = 0;
     double kd_elem = 0;           // kappa * largest element box diagonal
@@ -157,6 +164,13 @@ struct igb_op_s {
     int64_t nclusters = 0;
     // solver scratch
     igb::DevBuf d_krylov, d_w, d_h, d_b;
+    // false for a single boundary integral operator (no right-hand side or representation)
+    bool system = true;
+    // lazy sum y = sum_i sum_coef[i] sum_parts[i] x of separately stored H^2 matrices
+    // (owned; empty for an operator with its own near and far field)
+    std::vector<igb_op_s*> sum_parts;
+    std::vector<double2> sum_coef;
+    igb::DevBuf d_sum_tmp;
     int krylov_cols = 0;
     int work_cols = 0;   // columns the matvec work buffers are sized for
     double t_assembly_near = 0, t_assembly_far = 0;

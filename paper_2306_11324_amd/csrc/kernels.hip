@@ -177,6 +177,7 @@ struct NearArgs {
     int nel1;
     double kappa, eta;       // eta: coupling of the sound-hard CFIE
     SoftMix mix;             // kernel of the sound-soft family
+    HardMix hmix;            // kernel of the sound-hard family
     double2 cm;              // multiple of the mass matrix added on identical pairs
     // singular rules: per class (0 vertex, 1 edge, 2 identical) points (s1,s2,r1,r2,w)
     const double* rule[3];
@@ -186,15 +187,16 @@ struct NearArgs {
 
 // Kernel values at one point pair (element-local coordinates, n~ unnormalised):
 //   soft: s = ck a_y H (x-y).n~_x + cv a_x a_y G                      (ck K* + cv V)
-//   hard: s = a_x H (x-y).n~_y + i eta kappa^2 G n~_x.n~_y            (-K, kappa^2 part of -i eta W)
-//         g = -i eta G, multiplying the curl product c_i(x).c_j(y)    (curl part of -i eta W)
+//   hard: s = ck a_x H (y-x).n~_y - cw kappa^2 G n~_x.n~_y            (ck K, kappa^2 part of cw W)
+//         g = cw G, multiplying the curl product c_i(x).c_j(y)         (curl part of cw W)
+//         (the CFIE: ck = -1, cw = -i eta)
 struct KVal {
     double2 s, g;
 };
 
 template <bool HARD>
 __device__ __forceinline__ KVal kernel_pair(const double* X, const double* NX, double ax, const double* Y,
-                                            const double* NY, double ay, double kappa, double eta, SoftMix mix) {
+                                            const double* NY, double ay, double kappa, SoftMix mix, HardMix hmix) {
     KVal k;
     if (!HARD) {
         k.s = kernel_soft(X, NX, ax, Y, ay, kappa, mix);
@@ -210,10 +212,14 @@ __device__ __forceinline__ KVal kernel_pair(const double* X, const double* NX, d
     const double c4 = 0.07957747154594767 * ir;
     const double dny = d0 * NY[0] + d1 * NY[1] + d2 * NY[2];
     const double nn = NX[0] * NY[0] + NX[1] * NY[1] + NX[2] * NY[2];
-    const double h = ax * dny * ir * ir * c4;
-    const double v = eta * kappa * kappa * nn * c4;
-    k.s = make_double2(h * (-cs - sn * kr) - v * sn, h * (cs * kr - sn) + v * cs);
-    k.g = make_double2(eta * c4 * sn, -eta * c4 * cs);
+    // K kernel a_x H (y-x).n~_y = kn (cs + i sn) (i kr - 1), kn = -a_x (x-y).n~_y / (4 pi r^3)
+    const double kn = -ax * dny * ir * ir * c4;
+    const double2 kk = make_double2(kn * (-cs - sn * kr), kn * (cs * kr - sn));
+    const double v = -kappa * kappa * nn * c4;   // W's kappa^2 part: v (cs + i sn)
+    const double2 w = make_double2(v * cs, v * sn);
+    const double2 g = make_double2(c4 * cs, c4 * sn);
+    k.s = cadd(cmul(hmix.ck, kk), cmul(hmix.cw, w));
+    k.g = cmul(hmix.cw, g);
     return k;
 }
 
@@ -300,8 +306,8 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_regular(NearArgs A) {
         const int ci = min(CI, nx - i0);
         for (int idx = tid; idx < ci * ny; idx += NEAR_THREADS) {
             const int i = i0 + idx / ny, j = idx % ny;
-            const KVal kv = kernel_pair<HARD>(xg[i], xg[i] + 3, xg[i][6], yg[j], yg[j] + 3, yg[j][6], A.kappa, A.eta,
-                                                 A.mix);
+            const KVal kv = kernel_pair<HARD>(xg[i], xg[i] + 3, xg[i][6], yg[j], yg[j] + 3, yg[j][6], A.kappa, A.mix,
+                                                 A.hmix);
             buf[idx * NK] = kv.s;
             if (HARD) buf[idx * NK + 1] = kv.g;
         }
@@ -400,7 +406,7 @@ __global__ __launch_bounds__(NEAR_THREADS) void near_singular(NearArgs A) {
                 double gxv[7], gyv[7];
                 point_data<P, HARD>(Re, Ce_u, Ce_v, s, t, 1.0, gxv, px[tid]);
                 point_data<P, HARD>(Rf, Cf_u, Cf_v, u, v, 1.0, gyv, py[tid]);
-                KVal kv = kernel_pair<HARD>(gxv, gxv + 3, gxv[6], gyv, gyv + 3, gyv[6], A.kappa, A.eta, A.mix);
+                KVal kv = kernel_pair<HARD>(gxv, gxv + 3, gxv[6], gyv, gyv + 3, gyv[6], A.kappa, A.mix, A.hmix);
                 kv.s = cscale(kv.s, r[4]);
                 kv.g = cscale(kv.g, r[4]);
                 kq[tid] = kv;
@@ -1562,7 +1568,7 @@ __global__ __launch_bounds__(NT) void m2l_hard_chunks(const CT* __restrict__ cou
 //   y_u = -i eta sum_c F_v,c T_c,   y_v = +i eta sum_c F_u,c T_c
 // from raw[cluster][10][nq][C] = (R0, R_0..2, S_0..2, T_0..2)
 __global__ void m2l_finalize_hard(const double2* raw, const double* nodes, int64_t nclusters, int nq, double kappa,
-                                  double eta, int64_t kind_stride, int ncol, double2* yh) {
+                                  HardMix hmix, int64_t kind_stride, int ncol, double2* yh) {
     const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gid >= nclusters * nq * ncol) return;
     const int r = int(gid % ncol);
@@ -1580,11 +1586,11 @@ __global__ void m2l_finalize_hard(const double2* raw, const double* nodes, int64
         su = cadd(su, cscale(rw[(7 + cc) * vs], X[11 + cc]));
         sv = cadd(sv, cscale(rw[(7 + cc) * vs], X[8 + cc]));
     }
-    const double k2 = eta * kappa * kappa;
-    yp = cadd(yp, make_double2(-k2 * sn.y, k2 * sn.x));               // + i eta kappa^2 sn
-    yh[gid] = yp;
-    yh[kind_stride + gid] = make_double2(eta * su.y, -eta * su.x);    // -i eta su
-    yh[2 * kind_stride + gid] = make_double2(-eta * sv.y, eta * sv.x); // +i eta sv
+    // yp is the -K part: ck K = -ck yp; W: -kappa^2 sn (normal part), su - sv (curl part)
+    const double2 mck = make_double2(-hmix.ck.x, -hmix.ck.y);
+    yh[gid] = cadd(cmul(mck, yp), cscale(cmul(hmix.cw, sn), -kappa * kappa));
+    yh[kind_stride + gid] = cmul(hmix.cw, su);
+    yh[2 * kind_stride + gid] = cscale(cmul(hmix.cw, sv), -1.0);
 }
 
 // sum over the target's chunks (fixed order), zero if none:
@@ -2048,6 +2054,7 @@ static igb_status near_launch(igb_op op, hipStream_t s) {
     A.kappa = op->kappa;
     A.eta = op->eta;
     A.mix = op->mix;
+    A.hmix = op->hmix;
     A.cm = op->cm;
     A.mass_order = MASS_ORDER;
 
@@ -2489,8 +2496,41 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
 // y = A x: the launch sequence is captured once per (x, y, columns, parts,
 // stream) into a HIP graph and replayed; it holds kernel launches only (no
 // memsets, no allocation).  Kernel timing (profile mode) launches directly.
+// y += c t over n complex entries
+__global__ void caxpy(double2* __restrict__ y, const double2* __restrict__ t, double2 c, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = cfma(c, t[i], y[i]);
+}
+
+// Lazy sum of separately stored H^2 matrices: y = A_0 x, then y += c_i (A_i x) in order
+static igb_status matvec_sum(igb_op op, const double* x, double* y, int ncol, int parts, hipStream_t s) {
+    igb_status st;
+    const int64_t n = int64_t(ncol) * op->N;
+    if (op->sum_coef.front().x != 1.0 || op->sum_coef.front().y != 0.0) {
+        set_error("h2_matvec: the first part of a lazy sum must have coefficient 1");
+        return IGB_ERR_ARG;
+    }
+    if ((st = matvec_device(op->sum_parts.front(), x, y, ncol, parts, s))) return st;
+    if (op->sum_parts.size() < 2) return IGB_OK;
+    if (op->d_sum_tmp.bytes < size_t(n) * sizeof(double2)) {
+        // grows with the column count; freed with the operator
+        op->dev_bytes -= std::min(op->dev_bytes, op->d_sum_tmp.bytes);
+        op->d_sum_tmp.release();
+        if ((st = alloc(op->d_sum_tmp, size_t(n) * sizeof(double2), &op->dev_bytes))) return st;
+    }
+    double2* t = op->d_sum_tmp.as<double2>();
+    for (size_t i = 1; i < op->sum_parts.size(); ++i) {
+        if ((st = matvec_device(op->sum_parts[i], x, reinterpret_cast<double*>(t), ncol, parts, s))) return st;
+        hipLaunchKernelGGL(caxpy, dim3(blocks_for(n, 256)), dim3(256), 0, s, reinterpret_cast<double2*>(y), t,
+                           op->sum_coef[i], n);
+        IGB_HIP(hipGetLastError());
+    }
+    return IGB_OK;
+}
+
 igb_status matvec_device(igb_op op, const double* x, double* y, int ncol, int parts, hipStream_t s) {
     igb_status st;
+    if (!op->sum_parts.empty()) return matvec_sum(op, x, y, ncol, parts, s);
     if ((st = alloc_work(op, ncol))) return st;
     if (!op->use_graphs || op->profile || s == nullptr) return matvec_launches(op, x, y, ncol, parts, s);
     const igb_op_s::GraphKey key{x, y, ncol, parts, s};
@@ -2581,7 +2621,7 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
         if (hard)
             hipLaunchKernelGGL(m2l_finalize_hard, dim3(blocks_for(op->nclusters * nq * ncol, 256)), dim3(256), 0, s,
                                op->d_yraw.as<double2>(), op->d_nodes.as<double>(), op->nclusters, nq, op->kappa,
-                               op->eta, ks, ncol, yh);
+                               op->hmix, ks, ncol, yh);
         const int w = (1 << op->d) + g->p;
         for (int kd = 0; kd < kinds; ++kd) {
             for (int l = 0; l < L; ++l) {
@@ -2644,8 +2684,9 @@ igb_status rhs_device(igb_op op, const double* dirs, int ndir, double* b, hipStr
     const bool hard = op->bc == IGB_HARD;
     dim3 grid1(unsigned((g->nelem + 127) / 128), unsigned(ndir));
     dim3 grid2(unsigned((op->N + 255) / 256), unsigned(ndir));
-    const int* s0p = hard ? op->d_s0_ptr.as<int>() : nullptr;
-    const int* s0r = hard ? op->d_s0_reps.as<int>() : nullptr;
+    const igb_op sp = op->sum_parts.empty() ? op : op->sum_parts.front();   // holds the space maps
+    const int* s0p = hard ? sp->d_s0_ptr.as<int>() : nullptr;
+    const int* s0r = hard ? sp->d_s0_reps.as<int>() : nullptr;
     double2* B = reinterpret_cast<double2*>(b);
     if ((st = with_degree(g->p, "cfie_rhs", [&](auto deg) {
              constexpr int P = decltype(deg)::value;
@@ -2686,7 +2727,8 @@ igb_status farfield_device(igb_op op, const double* coeffs, int ndir, const doub
                   g->nel1, g->p, nqd, g->nelem};
     const bool hard = op->bc == IGB_HARD;
     const double2* C = reinterpret_cast<const double2*>(coeffs);
-    const int* s2s0 = hard ? op->d_s2_to_s0.as<int>() : nullptr;
+    const igb_op sp = op->sum_parts.empty() ? op : op->sum_parts.front();   // holds the space maps
+    const int* s2s0 = hard ? sp->d_s2_to_s0.as<int>() : nullptr;
     if ((st = with_degree(g->p, "farfield", [&](auto deg) {
              constexpr int P = decltype(deg)::value;
              hipLaunchKernelGGL(density_points<P>, dim3(unsigned((npts + 255) / 256)), dim3(256), 0, s, A, C,
@@ -2723,7 +2765,8 @@ igb_status potential_device(igb_op op, const double* coeffs, int ndir, const dou
                   g->nel1, g->p, nqd, g->nelem};
     const bool hard = op->bc == IGB_HARD;
     const double2* C = reinterpret_cast<const double2*>(coeffs);
-    const int* s2s0 = hard ? op->d_s2_to_s0.as<int>() : nullptr;
+    const igb_op sp = op->sum_parts.empty() ? op : op->sum_parts.front();   // holds the space maps
+    const int* s2s0 = hard ? sp->d_s2_to_s0.as<int>() : nullptr;
     if ((st = with_degree(g->p, "potential", [&](auto deg) {
              constexpr int P = decltype(deg)::value;
              hipLaunchKernelGGL(density_points<P>, dim3(unsigned((npts + 255) / 256)), dim3(256), 0, s, A, C,

@@ -35,6 +35,9 @@ Cases
                       solutions (soft V t = u_inc, hard (K* - 1/2) t = d_n u_inc)
                       and their scattered field at the 72 points of
                       sphere_m2_k1_potential.
+  sphere_m2_k1_operators  the single Galerkin matrices on the level-2 sphere,
+                      kappa = 1, applied to the seeded vector: V and K* on S^2
+                      (p = 1), K and the regularised W on S^0 (p = 2).
   star_m6_p2_k16_rows  seed-0 star, m = 6, p = 2, kappa = 16, soft: sampled rows
                       of the dense O1 matrix applied to the seeded vector.
   star_m7_p2_k32_hard_rows  seed-0 star, m = 7, p = 2, kappa = 32, hard (S^0):
@@ -142,6 +145,19 @@ def case_sphere_m2_k1_single_layer():
     return out
 
 
+def case_sphere_m2_k1_operators():
+    out = {}
+    for bc, p, ops in (("soft", 1, ("V", "Kstar")), ("hard", 2, ("K", "W"))):
+        bem = G.DenseBEM(I.sphere_patches(), p=p, m=2, kappa=1.0, bc=bc)
+        x = I.random_complex(X_SEED, bem.n)
+        mats = bem.operator_matrices()
+        out[f"{bc}_x"] = x
+        for name in ops:
+            out[f"{name}_y"] = mats[name] @ x
+            out[f"{name}_rownorm1"] = np.abs(mats[name]).sum(1)
+    return out
+
+
 TORUS_RULES = dict(n_far=10, n_mid=12, n_near=14, n_sing=13)
 
 
@@ -186,6 +202,7 @@ CASES = {
     "star_m7_p2_k32_hard_rows": case_star_m7_p2_k32_hard_rows,
     "torus_k2p5_potential": case_torus_k2p5_potential,
     "sphere_m2_k1_single_layer": case_sphere_m2_k1_single_layer,
+    "sphere_m2_k1_operators": case_sphere_m2_k1_operators,
 }
 
 

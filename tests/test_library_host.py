@@ -149,3 +149,28 @@ def test_handles_destroyed_in_any_order():
     info = B.IgbOpInfo()
     assert B._lib.igb_op_get_info(ho, B.C.byref(info)) == 0 and info.n == geo.n2
     B._lib.igb_op_destroy(ho)
+
+
+def test_separate_matrices_and_single_operators_on_host(hctx):
+    """Separate H^2 matrices: two trees of the fused operator's partition (twice
+    the far pairs), inspection of one matrix's internals refused; single
+    operators take their family's space whatever bc says; bad combinations are
+    rejected before anything is built."""
+    geo = B.Geometry(hctx, I.sphere_patches(), 3, 2)
+    fused = B.Operator(hctx, geo, kappa=2.0, q=4, leaf_depth=1)
+    sep = B.Operator(hctx, geo, kappa=2.0, q=4, leaf_depth=1, separate=True)
+    assert sep.n == fused.n and sep.info.far_pairs == 2 * fused.info.far_pairs
+    assert sep.info.nnz == 2 * fused.info.nnz
+    with pytest.raises(B.IgbError):
+        sep.near_pairs()
+    hard = B.Operator(hctx, geo, kappa=2.0, bc=B.HARD, q=4, leaf_depth=1, separate=True)
+    assert hard.n == geo.n0
+    assert B.Operator(hctx, geo, kappa=2.0, bc=B.SOFT, q=4, leaf_depth=1, formulation=B.OP_W).n == geo.n0
+    assert B.Operator(hctx, geo, kappa=2.0, bc=B.HARD, q=4, leaf_depth=1, formulation=B.OP_V).n == geo.n2
+    with pytest.raises(B.IgbError):
+        B.Operator(hctx, geo, kappa=2.0, q=4, leaf_depth=1, formulation=B.SINGLE_LAYER, separate=True)
+    with pytest.raises(B.IgbError):
+        B.Operator(hctx, geo, kappa=2.0, q=4, leaf_depth=1, formulation=7)
+    g0 = B.Geometry(hctx, I.sphere_patches(), 2, 0)
+    with pytest.raises(B.IgbError):
+        B.Operator(hctx, g0, kappa=2.0, q=4, leaf_depth=1, formulation=B.OP_K)
