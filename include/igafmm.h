@@ -323,6 +323,21 @@ igb_status farfield(igb_op op, const double* coeffs, int ndir, const double* obs
 igb_status potential(igb_op op, const double* coeffs, int ndir, const double* points, int npts, double* u,
                      void* hip_stream);
 
+/* The same scattered field evaluated with the H^2 structure of the operator
+ * (Sec. 4.4's interpolation applied to the representation formula, Sec. 2):
+ * the points are sorted into the boxes of an octree (at most 128 points each);
+ * a source cluster admissible for a box (the operator's eta_adm, boxes of the
+ * points and of the clusters' control points, and kappa * max(diam) at most
+ * the operator's kcap, or q/2 if kcap is 0) acts through its moments on the
+ * (q+1)^3 tensor Chebyshev nodes of the box, interpolated to the points; the
+ * elements of the box's inadmissible leaf clusters are summed directly as in
+ * potential().  Error against potential(): the interpolation error of q on
+ * the box side and the cluster side.  Arguments, layout, ownership and errors
+ * as for potential(); the operator's matvec work buffers are used, so this
+ * must not overlap other calls on the operator.  Synchronous. */
+igb_status potential_h2(igb_op op, const double* coeffs, int ndir, const double* points, int npts, double* u,
+                        void* hip_stream);
+
 const char* igb_last_error(void);
 
 #ifdef __cplusplus

@@ -88,6 +88,7 @@ _SIGS = {
                              C.POINTER(IgbSolveInfo)]),
     "farfield": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double), C.c_int, _P, _P]),
     "potential": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double), C.c_int, _P, _P]),
+    "potential_h2": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double), C.c_int, _P, _P]),
     "igb_op_profile": (C.c_int, [_P, C.c_int]),
     "igb_op_use_graphs": (C.c_int, [_P, C.c_int]),
     "igb_op_kernel_time": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
@@ -276,6 +277,13 @@ class Operator:
         pt, pp = _dbl(np.atleast_2d(points))
         _check("potential", _lib.potential(self.h, _dptr(coeffs, ndir * self.n), ndir, pp, pt.shape[0],
                                            _dptr(u, ndir * pt.shape[0]), _stream(stream)))
+        return u
+
+    def potential_h2(self, coeffs, points, u, ndir: int = 1, stream=None):
+        """potential() through the H^2 structure (octree boxes, interpolated far part)."""
+        pt, pp = _dbl(np.atleast_2d(points))
+        _check("potential_h2", _lib.potential_h2(self.h, _dptr(coeffs, ndir * self.n), ndir, pp, pt.shape[0],
+                                                 _dptr(u, ndir * pt.shape[0]), _stream(stream)))
         return u
 
     def __del__(self, _destroy=_lib.igb_op_destroy):

@@ -620,4 +620,16 @@ igb_status potential(igb_op op, const double* coeffs, int ndir, const double* po
     return potential_device(op, coeffs, ndir, points, npts, u, pick(op->geom->ctx, hip_stream));
 }
 
+igb_status potential_h2(igb_op op, const double* coeffs, int ndir, const double* points, int npts, double* u,
+                     void* hip_stream) {
+    if (!op || !coeffs || !points || !u || ndir < 1 || npts < 1) {
+        set_error("potential_h2: invalid argument");
+        return IGB_ERR_ARG;
+    }
+    if (igb_status st = need_device(op, "potential_h2")) return st;
+    if (igb_status st1 = need_system(op, "potential_h2")) return st1;
+    IGB_HIP(hipSetDevice(op->geom->ctx->device));
+    return potential_h2_device(op, coeffs, ndir, points, npts, u, pick(op->geom->ctx, hip_stream));
+}
+
 }  // extern "C"

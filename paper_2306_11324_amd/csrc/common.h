@@ -235,6 +235,21 @@ inline int aspect_boost(double a) { return (a >= 2.0) + (a >= 3.0) + (a >= 5.0);
 // no singularity: right-hand side and far field (base 6), potential off the
 // boundary (base 8); raised with kappa * element size and quad_extra > 0.
 int smooth_order(igb_op op, int base);
+// H^2 evaluation of the scattered field at many points (host plan): points sorted
+// into target boxes of an octree (at most POT_LEAF_POINTS each), and per box the
+// admissible source clusters (far, interpolated on (q+1)^3 box nodes) and the
+// inadmissible leaf clusters (near, direct quadrature).
+constexpr int POT_LEAF_POINTS = 128;
+struct PotentialPlan {
+    std::vector<int> perm;                 // points by box: perm[i] = caller's index
+    std::vector<int> box_ptr;              // [nbox+1] into perm
+    std::vector<double> box_lo, box_hi;    // [nbox][3] interpolation boxes
+    std::vector<int> far_ptr, far_src;     // per box: global ids of admissible clusters
+    std::vector<int> near_ptr, near_leaf;  // per box: leaf clusters (index on the leaf level)
+};
+igb_status potential_plan(igb_op op, const double* points, int npts, PotentialPlan& P);
+igb_status potential_h2_device(igb_op op, const double* coeffs, int ndir, const double* points, int npt, double* u,
+                               hipStream_t s);
 igb_status gmres_device(igb_op op, const double* b, double* x, int ndir,
                         const igb_solve_params* sp, igb_solve_info* info, hipStream_t s);
 

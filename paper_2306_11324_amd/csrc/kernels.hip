@@ -1859,6 +1859,146 @@ __global__ __launch_bounds__(256) void potential_sum(const double* geo, const do
     if (threadIdx.x == 0) u[int64_t(dir) * npt + o] = red[0];
 }
 
+// kernel of the representation at one point pair, surface data g = (y, n~, a, w):
+// soft -G a w, hard G (i kappa r - 1)/r^2 ((y - x).n~) w (potential_sum's terms)
+__device__ __forceinline__ double2 repr_kernel(const double* x, const double* g, double kappa, int hard) {
+    const double d0 = g[0] - x[0], d1 = g[1] - x[1], d2 = g[2] - x[2];   // y - x
+    const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double ir = 1.0 / r, kr = kappa * r;
+    double sn, cs;
+    sincos(kr, &sn, &cs);
+    const double c4 = 0.07957747154594767 * ir;
+    if (hard) {
+        const double dn = (d0 * g[3] + d1 * g[4] + d2 * g[5]) * ir * ir * g[7];
+        return make_double2(c4 * dn * (-cs - sn * kr), c4 * dn * (cs * kr - sn));
+    }
+    const double wa = -c4 * g[6] * g[7];
+    return make_double2(wa * cs, wa * sn);
+}
+
+// H^2 potential, far part: local expansion of every target box on its (q+1)^3
+// Chebyshev nodes from the moments of its admissible source clusters, the
+// kernel evaluated at node pairs (source nodes carry a and n~ like the
+// coupling tiles).  One workgroup per (box, column); fixed summation order.
+constexpr int POT_NODES_PER_THREAD = 6;   // (q+1)^3 <= 1331 for q <= 10
+__global__ __launch_bounds__(256) void pot_box_m2l(const double* __restrict__ nodes, const double2* __restrict__ xh,
+                                                   int q, const double* __restrict__ box_lo,
+                                                   const double* __restrict__ box_hi, const double* __restrict__ tch,
+                                                   const int* __restrict__ far_ptr, const int* __restrict__ far_src,
+                                                   int ncol, double kappa, int hard, double2* __restrict__ lbox) {
+    __shared__ double ys[(QMAX + 1) * (QMAX + 1)][8];
+    __shared__ double2 xs[(QMAX + 1) * (QMAX + 1)];
+    const int b = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+    const int q1 = q + 1, nq = q1 * q1, n3 = nq * q1;
+    double X[POT_NODES_PER_THREAD][3];
+    double2 acc[POT_NODES_PER_THREAD];
+#pragma unroll
+    for (int k = 0; k < POT_NODES_PER_THREAD; ++k) {
+        acc[k] = make_double2(0, 0);
+        const int a = tid + k * 256;
+        const int ia[3] = {a % q1, (a / q1) % q1, a / nq};
+        for (int c = 0; c < 3; ++c)
+            X[k][c] = a < n3 ? box_lo[3 * b + c] + (box_hi[3 * b + c] - box_lo[3 * b + c]) * tch[ia[c]] : 0.0;
+    }
+    for (int f = far_ptr[b]; f < far_ptr[b + 1]; ++f) {
+        const int64_t sc = far_src[f];
+        __syncthreads();
+        if (tid < nq) {
+            const double* Y = nodes + (sc * nq + tid) * 16;
+            ys[tid][0] = Y[0]; ys[tid][1] = Y[1]; ys[tid][2] = Y[2];
+            ys[tid][3] = Y[3]; ys[tid][4] = Y[4]; ys[tid][5] = Y[5];
+            ys[tid][6] = Y[6]; ys[tid][7] = 1.0;
+            xs[tid] = xh[(sc * nq + tid) * ncol + r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < POT_NODES_PER_THREAD; ++k) {
+            if (tid + k * 256 >= n3) break;
+            for (int j = 0; j < nq; ++j) acc[k] = cfma(repr_kernel(X[k], ys[j], kappa, hard), xs[j], acc[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < POT_NODES_PER_THREAD; ++k) {
+        const int a = tid + k * 256;
+        if (a < n3) lbox[(int64_t(b) * n3 + a) * ncol + r] = acc[k];
+    }
+}
+
+// one point of pot_l2p_near: interpolated box expansion (lx, or none) + near leaves
+__device__ void pot_point(const double* __restrict__ pts, int pi, int b, const double* __restrict__ box_lo,
+                          const double* __restrict__ box_hi, const double* __restrict__ tch, int q,
+                          const double2* lx, const int* __restrict__ near_ptr, const int* __restrict__ near_leaf,
+                          int d, int L, int nel1, int nqp, const double* __restrict__ geo,
+                          const double2* __restrict__ D, double kappa, int hard, double2* __restrict__ u) {
+    const int q1 = q + 1;
+    const bool has_far = lx != nullptr;
+    const double x[3] = {pts[3 * pi], pts[3 * pi + 1], pts[3 * pi + 2]};
+    double2 acc = make_double2(0, 0);
+    if (has_far) {
+        double w[3][QMAX + 1];
+        for (int c = 0; c < 3; ++c) {
+            const double lo = box_lo[3 * b + c], hi = box_hi[3 * b + c];
+            const double t = (x[c] - lo) / (hi - lo);
+            for (int k = 0; k < q1; ++k) {
+                double v = 1;
+                for (int j = 0; j < q1; ++j)
+                    if (j != k) v *= (t - tch[j]) / (tch[k] - tch[j]);
+                w[c][k] = v;
+            }
+        }
+        for (int az = 0; az < q1; ++az)
+            for (int ay = 0; ay < q1; ++ay) {
+                double2 row = make_double2(0, 0);
+                for (int ax = 0; ax < q1; ++ax) {
+                    const double2 v = lx[(az * q1 + ay) * q1 + ax];
+                    row.x = fma(w[0][ax], v.x, row.x);
+                    row.y = fma(w[0][ax], v.y, row.y);
+                }
+                const double wyz = w[1][ay] * w[2][az];
+                acc.x = fma(wyz, row.x, acc.x);
+                acc.y = fma(wyz, row.y, acc.y);
+            }
+    }
+    const int n = 1 << L, s = 1 << d;
+    for (int f = near_ptr[b]; f < near_ptr[b + 1]; ++f) {
+        const int64_t loc = near_leaf[f];
+        const int64_t patch = loc / (int64_t(n) * n);
+        const int cy = int((loc / n) % n), cx = int(loc % n);
+        for (int ey = cy * s; ey < cy * s + s; ++ey)
+            for (int ex = cx * s; ex < cx * s + s; ++ex) {
+                const int64_t e = (patch * nel1 + ey) * nel1 + ex;
+                for (int g = 0; g < nqp; ++g) {
+                    const int64_t gi = e * nqp + g;
+                    acc = cfma(repr_kernel(x, geo + gi * 8, kappa, hard), D[gi], acc);
+                }
+            }
+    }
+    u[pi] = acc;
+}
+
+// H^2 potential, per point: the box expansion interpolated at the point (tensor
+// Lagrange on the box's Chebyshev nodes) plus direct quadrature over the
+// elements of the box's inadmissible leaf clusters.  One workgroup per (box,
+// column); the threads stride over the box's points.
+__global__ __launch_bounds__(POT_LEAF_POINTS) void pot_l2p_near(
+    const double* __restrict__ pts, const int* __restrict__ perm, const int* __restrict__ box_ptr,
+    const double* __restrict__ box_lo, const double* __restrict__ box_hi, const double* __restrict__ tch, int q,
+    const double2* __restrict__ lbox, int ncol, const int* __restrict__ near_ptr, const int* __restrict__ near_leaf,
+    int d, int L, int nel1, int nqp, const double* __restrict__ geo, const double2* __restrict__ dens, int64_t nqtot,
+    double kappa, int hard, int npt, double2* __restrict__ u) {
+    __shared__ double2 lx[(QMAX + 1) * (QMAX + 1) * (QMAX + 1)];
+    const int b = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+    const int q1 = q + 1, n3 = q1 * q1 * q1;
+    const bool has_far = lbox != nullptr;
+    if (has_far)
+        for (int a = tid; a < n3; a += POT_LEAF_POINTS) lx[a] = lbox[(int64_t(b) * n3 + a) * ncol + r];
+    __syncthreads();
+    // (a box at the depth cap may hold more points than threads)
+    for (int i = box_ptr[b] + tid; i < box_ptr[b + 1]; i += POT_LEAF_POINTS)
+        pot_point(pts, perm[i], b, box_lo, box_hi, tch, q, has_far ? lx : nullptr, near_ptr, near_leaf, d, L, nel1,
+                  nqp, geo, dens + int64_t(r) * nqtot, kappa, hard, u + int64_t(r) * npt);
+}
+
 // ==========================================================================
 // host launchers
 // ==========================================================================
@@ -2779,6 +2919,93 @@ igb_status potential_device(igb_op op, const double* coeffs, int ndir, const dou
                        reinterpret_cast<double2*>(u));
     IGB_HIP(hipGetLastError());
     IGB_HIP(hipStreamSynchronize(s));
+    return IGB_OK;
+}
+
+
+igb_status potential_h2_device(igb_op op, const double* coeffs, int ndir, const double* points, int npt, double* u,
+                               hipStream_t s) {
+    for (int i = 0; i < 3 * npt; ++i)
+        if (!std::isfinite(points[i])) {
+            set_error("potential_h2: point %d is not finite", i / 3);
+            return IGB_ERR_ARG;
+        }
+    // the tree, moments and source nodes live on the first part of a separate-form operator
+    const igb_op sp = op->sum_parts.empty() ? op : op->sum_parts.front();
+    igb_geom g = sp->geom;
+    const bool hard = op->bc == IGB_HARD;
+    igb_status st;
+    PotentialPlan P;
+    if ((st = potential_plan(sp, points, npt, P))) return st;
+    const int nbox = int(P.box_ptr.size()) - 1;
+    if (nbox == 0) return IGB_OK;
+    const int q = sp->q, q1 = q + 1, nq = sp->nq, n3 = nq * q1, L = sp->L;
+    const double2* C = reinterpret_cast<const double2*>(coeffs);
+    // source moments (value kind) of every cluster: leaf moments, then upward
+    if ((st = alloc_work(sp, ndir))) return st;
+    const double2* x2 = C;
+    if (hard) {
+        hipLaunchKernelGGL(glue_gather, dim3(blocks_for(g->n2 * ndir, 256)), dim3(256), 0, s,
+                           sp->d_s2_to_s0.as<int>(), C, sp->N, sp->d_x2.as<double2>(), g->n2, ndir);
+        x2 = sp->d_x2.as<double2>();
+    }
+    double2* xh = sp->d_xhat.as<double2>();
+    const int64_t nleaf = clusters_on_level(g->npatch, L);
+    const int64_t stride_kind = int64_t(1 << L) * q1 * ((1 << sp->d) + g->p);
+    hipLaunchKernelGGL(leaf_moments, dim3(blocks_for(nleaf * nq * ndir, 256)), dim3(256), 0, s, x2, g->n2,
+                       sp->d_m1.as<double>(), q, sp->d, g->p, L, g->k, sp->clu_off[L], nleaf, xh, 0, 0, stride_kind,
+                       ndir);
+    const unsigned cblk = unsigned((ndir + TCB - 1) / TCB);
+    for (int l = L - 1; l >= 0; --l)
+        hipLaunchKernelGGL(m2m_wg, dim3(unsigned(clusters_on_level(g->npatch, l)), cblk), dim3(TREE_THREADS), 0, s,
+                           sp->d_T.as<double>(), q, l, sp->clu_off[l], sp->clu_off[l + 1], xh, ndir);
+    IGB_HIP(hipGetLastError());
+    // boundary density and geometry at the quadrature points (near part)
+    const int nqd = smooth_order(op, 8);
+    const int64_t nqtot = g->nelem * nqd * nqd;
+    DevBuf d_gl, d_geo, d_dens, d_pts, d_perm, d_bptr, d_blo, d_bhi, d_tch, d_fptr, d_fsrc, d_nptr, d_nleaf, d_lbox;
+    std::vector<double> gl = gauss_table();
+    if ((st = upload(d_gl, gl.data(), gl.size(), nullptr))) return st;
+    if ((st = alloc(d_geo, size_t(nqtot) * 8 * sizeof(double), nullptr))) return st;
+    if ((st = alloc(d_dens, size_t(ndir) * nqtot * sizeof(double2), nullptr))) return st;
+    QuadGeoArgs A{g->d_bez.as<double>(), g->d_pg.as<int>(), g->d_C1.as<double>(), d_gl.as<double>(),
+                  g->nel1, g->p, nqd, g->nelem};
+    const int* s2s0 = hard ? sp->d_s2_to_s0.as<int>() : nullptr;
+    if ((st = with_degree(g->p, "potential_h2", [&](auto deg) {
+             constexpr int PD = decltype(deg)::value;
+             hipLaunchKernelGGL(density_points<PD>, dim3(unsigned((nqtot + 255) / 256)), dim3(256), 0, s, A, C,
+                                ndir, op->N, s2s0, g->k, d_geo.as<double>(), d_dens.as<double2>());
+             return IGB_OK;
+         })))
+        return st;
+    std::vector<double> t(q1);
+    cheb_nodes(q, t.data());
+    if ((st = upload(d_pts, points, size_t(3) * npt, nullptr)) || (st = upload(d_perm, P.perm.data(), P.perm.size(), nullptr)) ||
+        (st = upload(d_bptr, P.box_ptr.data(), P.box_ptr.size(), nullptr)) ||
+        (st = upload(d_blo, P.box_lo.data(), P.box_lo.size(), nullptr)) ||
+        (st = upload(d_bhi, P.box_hi.data(), P.box_hi.size(), nullptr)) ||
+        (st = upload(d_tch, t.data(), t.size(), nullptr)) ||
+        (st = upload(d_fptr, P.far_ptr.data(), P.far_ptr.size(), nullptr)) ||
+        (st = upload(d_nptr, P.near_ptr.data(), P.near_ptr.size(), nullptr)))
+        return st;
+    if (!P.far_src.empty() && (st = upload(d_fsrc, P.far_src.data(), P.far_src.size(), nullptr))) return st;
+    if (!P.near_leaf.empty() && (st = upload(d_nleaf, P.near_leaf.data(), P.near_leaf.size(), nullptr))) return st;
+    const bool any_far = !P.far_src.empty();
+    if (any_far) {
+        if ((st = alloc(d_lbox, size_t(nbox) * n3 * ndir * sizeof(double2), nullptr))) return st;
+        hipLaunchKernelGGL(pot_box_m2l, dim3(unsigned(nbox), unsigned(ndir)), dim3(256), 0, s,
+                           sp->d_nodes.as<double>(), xh, q, d_blo.as<double>(), d_bhi.as<double>(), d_tch.as<double>(),
+                           d_fptr.as<int>(), d_fsrc.as<int>(), ndir, op->kappa, hard ? 1 : 0,
+                           d_lbox.as<double2>());
+        IGB_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(pot_l2p_near, dim3(unsigned(nbox), unsigned(ndir)), dim3(POT_LEAF_POINTS), 0, s,
+                       d_pts.as<double>(), d_perm.as<int>(), d_bptr.as<int>(), d_blo.as<double>(), d_bhi.as<double>(),
+                       d_tch.as<double>(), q, any_far ? d_lbox.as<double2>() : nullptr, ndir, d_nptr.as<int>(),
+                       d_nleaf.as<int>(), sp->d, L, g->nel1, nqd * nqd, d_geo.as<double>(), d_dens.as<double2>(),
+                       nqtot, op->kappa, hard ? 1 : 0, npt, reinterpret_cast<double2*>(u));
+    IGB_HIP(hipGetLastError());
+    IGB_HIP(hipStreamSynchronize(s));   // temporaries are freed on return
     return IGB_OK;
 }
 

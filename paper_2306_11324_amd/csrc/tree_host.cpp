@@ -413,4 +413,139 @@ igb_status near_pattern(igb_op op) {
     return IGB_OK;
 }
 
+
+// --------------------------------------------------------------------------
+// Target boxes and interaction lists of the H^2 potential evaluation
+// --------------------------------------------------------------------------
+igb_status potential_plan(igb_op op, const double* pts, int npts, PotentialPlan& P) {
+    const int np = op->geom->npatch, L = op->L;
+    P.perm.resize(npts);
+    for (int i = 0; i < npts; ++i) P.perm[i] = i;
+    P.box_ptr.assign(1, 0);
+    P.box_lo.clear();
+    P.box_hi.clear();
+    if (npts == 0) {
+        P.far_ptr.assign(1, 0);
+        P.near_ptr.assign(1, 0);
+        P.far_src.clear();
+        P.near_leaf.clear();
+        return IGB_OK;
+    }
+    double glo[3], ghi[3];
+    for (int c = 0; c < 3; ++c) glo[c] = ghi[c] = pts[c];
+    for (int i = 0; i < npts; ++i)
+        for (int c = 0; c < 3; ++c) {
+            glo[c] = std::min(glo[c], pts[3 * i + c]);
+            ghi[c] = std::max(ghi[c], pts[3 * i + c]);
+        }
+    double side = 0;
+    for (int c = 0; c < 3; ++c) side = std::max(side, ghi[c] - glo[c]);
+    if (!(side > 0)) side = 1.0;
+    // octree of cubes over index ranges (depth-first, children in octant order)
+    struct Node {
+        int b, e, depth;
+        double lo[3], h;
+    };
+    std::vector<Node> stack{Node{0, npts, 0, {glo[0], glo[1], glo[2]}, side}};
+    while (!stack.empty()) {
+        Node nd = stack.back();
+        stack.pop_back();
+        if (nd.e - nd.b <= POT_LEAF_POINTS || nd.depth >= 20) {
+            // interpolation box: the points' own box, each side at least 1e-3 of the cube
+            double lo[3], hi[3];
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = 1e300;
+                hi[c] = -1e300;
+            }
+            for (int i = nd.b; i < nd.e; ++i)
+                for (int c = 0; c < 3; ++c) {
+                    lo[c] = std::min(lo[c], pts[3 * P.perm[i] + c]);
+                    hi[c] = std::max(hi[c], pts[3 * P.perm[i] + c]);
+                }
+            for (int c = 0; c < 3; ++c) {
+                const double mid = 0.5 * (lo[c] + hi[c]), half = std::max(0.5 * (hi[c] - lo[c]), 5e-4 * nd.h);
+                P.box_lo.push_back(mid - half);
+                P.box_hi.push_back(mid + half);
+            }
+            P.box_ptr.push_back(nd.e);
+            continue;
+        }
+        const double h = 0.5 * nd.h;
+        auto oct = [&](int i) {
+            int o = 0;
+            for (int c = 0; c < 3; ++c)
+                if (pts[3 * i + c] >= nd.lo[c] + h) o |= 1 << c;
+            return o;
+        };
+        // stable partition of [b, e) into the 8 octants
+        int cnt[9] = {0};
+        for (int i = nd.b; i < nd.e; ++i) ++cnt[oct(P.perm[i]) + 1];
+        for (int o = 0; o < 8; ++o) cnt[o + 1] += cnt[o];
+        std::vector<int> tmp(nd.e - nd.b);
+        int pos[8];
+        for (int o = 0; o < 8; ++o) pos[o] = cnt[o];
+        for (int i = nd.b; i < nd.e; ++i) tmp[pos[oct(P.perm[i])]++] = P.perm[i];
+        std::copy(tmp.begin(), tmp.end(), P.perm.begin() + nd.b);
+        // pushed in reverse so that octant 0 is taken first (boxes in octant order)
+        for (int o = 7; o >= 0; --o) {
+            if (cnt[o + 1] == cnt[o]) continue;
+            Node ch{nd.b + cnt[o], nd.b + cnt[o + 1], nd.depth + 1,
+                    {nd.lo[0] + ((o & 1) ? h : 0), nd.lo[1] + ((o & 2) ? h : 0), nd.lo[2] + ((o & 4) ? h : 0)}, h};
+            stack.push_back(ch);
+        }
+    }
+    const int64_t nbox = int64_t(P.box_ptr.size()) - 1;
+    // interaction lists: descend the source cluster tree from the patches.  A pair
+    // is interpolated only if both sides span at most kcap radians of e^{i kappa r}
+    // (the operator's kcap, else q / 2: q + 1 Chebyshev points per direction)
+    const double kcap = op->prm.kcap > 0 ? op->prm.kcap : 0.5 * op->q;
+    std::vector<std::vector<int>> far(nbox), near(nbox);
+    parallel_for(nbox, 16, [&](int64_t b) {
+        const double* lt = &P.box_lo[3 * b];
+        const double* ht = &P.box_hi[3 * b];
+        double dt2 = 0;
+        for (int c = 0; c < 3; ++c) dt2 += (ht[c] - lt[c]) * (ht[c] - lt[c]);
+        std::vector<std::pair<int, int64_t>> st;   // (level, index on the level)
+        for (int j = 0; j < np; ++j) st.push_back({0, j});
+        while (!st.empty()) {
+            const int l = st.back().first;
+            const int64_t loc = st.back().second;
+            st.pop_back();
+            const int64_t gid = op->clu_off[l] + loc;
+            const double *ls = &op->clo[3 * gid], *hs = &op->chi[3 * gid];
+            double gap2 = 0, ds2 = 0;
+            for (int c = 0; c < 3; ++c) {
+                const double gp = std::max(0.0, std::max(ls[c] - ht[c], lt[c] - hs[c]));
+                gap2 += gp * gp;
+                ds2 += (hs[c] - ls[c]) * (hs[c] - ls[c]);
+            }
+            const double dm = std::max(std::sqrt(dt2), std::sqrt(ds2));
+            if (std::sqrt(gap2) >= op->prm.eta_adm * dm && op->kappa * dm <= kcap) {
+                far[b].push_back(int(gid));
+            } else if (l == L) {
+                near[b].push_back(int(loc));
+            } else {
+                const int n = 1 << l;
+                const int64_t j = loc >> (2 * l);
+                const int cy = int((loc >> l) & (n - 1)), cx = int(loc & (n - 1));
+                for (int a = 3; a >= 0; --a)
+                    st.push_back({l + 1, clu_local(np, l + 1, int(j), 2 * cx + (a & 1), 2 * cy + (a >> 1))});
+            }
+        }
+    });
+    P.far_ptr.assign(nbox + 1, 0);
+    P.near_ptr.assign(nbox + 1, 0);
+    for (int64_t b = 0; b < nbox; ++b) {
+        P.far_ptr[b + 1] = P.far_ptr[b] + int(far[b].size());
+        P.near_ptr[b + 1] = P.near_ptr[b] + int(near[b].size());
+    }
+    P.far_src.resize(P.far_ptr[nbox]);
+    P.near_leaf.resize(P.near_ptr[nbox]);
+    for (int64_t b = 0; b < nbox; ++b) {
+        std::copy(far[b].begin(), far[b].end(), P.far_src.begin() + P.far_ptr[b]);
+        std::copy(near[b].begin(), near[b].end(), P.near_leaf.begin() + P.near_ptr[b]);
+    }
+    return IGB_OK;
+}
+
 }  // namespace igb
