@@ -298,6 +298,25 @@ def main():
     potential = {"points": len(pot_pts), "seconds": t_pot, "points_per_s": len(pot_pts) / t_pot,
                  "kernel_evaluations_per_s": pot_evals / t_pot,
                  "note": "u_s at 4096 points on |x| = 2, 8 x 8 Gauss points on each of the elements"}
+    # direct summation against the H^2 evaluation on a seeded shell of 200,000 points
+    rng = np.random.default_rng(2024)
+    sh = rng.normal(size=(200000, 3))
+    sh = sh / np.linalg.norm(sh, axis=1, keepdims=True) * rng.uniform(1.2, 4.0, size=(200000, 1))
+    shell = {}
+    ush = {}
+    for name, f in (("direct", op.potential), ("h2", op.potential_h2)):
+        uu = torch.zeros(len(sh), dtype=torch.complex128, device=dev)
+        f(plain["coeff"], sh[:4096], uu[:4096])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f(plain["coeff"], sh, uu)
+        torch.cuda.synchronize()
+        shell[f"{name}_seconds"] = time.perf_counter() - t0
+        ush[name] = uu.cpu().numpy()
+    shell["h2_rel_diff_vs_direct"] = float(np.abs(ush["h2"] - ush["direct"]).max() / np.abs(ush["direct"]).max())
+    shell["h2_speedup"] = shell["direct_seconds"] / shell["h2_seconds"]
+    shell["note"] = "200,000 seeded points in 1.2 <= |x| <= 4 (potential vs potential_h2, host plan included)"
+    potential["shell_200k"] = shell
     op.use_graphs(True)
     plain_graphs = run_solves(op, d, args.steps, args.warmup)
     op.use_graphs(False)

@@ -441,6 +441,9 @@ igb_status potential_plan(igb_op op, const double* pts, int npts, PotentialPlan&
     double side = 0;
     for (int c = 0; c < 3; ++c) side = std::max(side, ghi[c] - glo[c]);
     if (!(side > 0)) side = 1.0;
+    // A box-cluster pair is interpolated only if both sides span at most kcap radians
+    // of e^{i kappa r} (the operator's kcap, else q / 2: q + 1 Chebyshev points per direction)
+    const double kcap = op->prm.kcap > 0 ? op->prm.kcap : 0.5 * op->q;
     // octree of cubes over index ranges (depth-first, children in octant order)
     struct Node {
         int b, e, depth;
@@ -450,6 +453,8 @@ igb_status potential_plan(igb_op op, const double* pts, int npts, PotentialPlan&
     while (!stack.empty()) {
         Node nd = stack.back();
         stack.pop_back();
+        // (smaller boxes at high kappa, so that more of them can interpolate, cost
+        // more per point on the m = 5 sphere at kappa = 8 than they save)
         if (nd.e - nd.b <= POT_LEAF_POINTS || nd.depth >= 20) {
             // interpolation box: the points' own box, each side at least 1e-3 of the cube
             double lo[3], hi[3];
@@ -495,10 +500,7 @@ igb_status potential_plan(igb_op op, const double* pts, int npts, PotentialPlan&
         }
     }
     const int64_t nbox = int64_t(P.box_ptr.size()) - 1;
-    // interaction lists: descend the source cluster tree from the patches.  A pair
-    // is interpolated only if both sides span at most kcap radians of e^{i kappa r}
-    // (the operator's kcap, else q / 2: q + 1 Chebyshev points per direction)
-    const double kcap = op->prm.kcap > 0 ? op->prm.kcap : 0.5 * op->q;
+    // interaction lists: descend the source cluster tree from the patches
     std::vector<std::vector<int>> far(nbox), near(nbox);
     parallel_for(nbox, 16, [&](int64_t b) {
         const double* lt = &P.box_lo[3 * b];
