@@ -102,8 +102,9 @@ typedef enum {
  *              couplings rounded (RNE) to fp32 / bf16 that cfie_solve uses inside
  *              iterative refinement (inner GMRES on the rounded far field with fp32
  *              accumulation on the matrix cores, outer residual in fp64) and
- *              h2_matvec uses with IGB_MV_LOWPREC; near field, Arnoldi and residuals
- *              stay fp64
+ *              h2_matvec uses with IGB_MV_LOWPREC; Arnoldi and residuals stay fp64,
+ *              and so does the near field, except that IGB_MIX_BF16 keeps an fp32 copy
+ *              that IGB_MV_LOWPREC products use (fp32 columns, products and row sums)
  *   far_on_the_fly  0: the fp64 couplings are stored ((q+1)^4 complex per far pair,
  *              two for IGB_HARD); 1: none are stored and every fp64 far-field
  *              product (fp64 matvecs, refinement residuals) evaluates the kernel at

@@ -154,6 +154,9 @@ struct igb_op_s {
     // device data
     igb::DevBuf d_coupling, d_coupling_lo, d_nodes, d_m1, d_T;
     igb::DevBuf d_rowptr, d_col, d_val;
+    // bf16 operators: fp32 near-field values and fp32 copies of the columns for the
+    // near product of the inner (refinement) matvecs
+    igb::DevBuf d_val_lo, d_xnear_lo;
     igb::DevBuf d_near_ptr, d_near_src;
     igb::DevBuf d_s2_to_s0, d_s0_ptr, d_s0_reps;
     igb::DevBuf d_far_src;

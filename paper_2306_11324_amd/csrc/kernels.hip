@@ -1160,7 +1160,7 @@ __global__ __launch_bounds__(512) void m2l_mfma(const typename OPS::LT* __restri
 #pragma unroll
         for (int u = 0; u < KU; ++u) {
             if (j0 + u >= nstep) break;
-            if (!HARD) {
+            if constexpr (!HARD) {
                 acc[0][0] = OPS::step(A[u][0], OPS::re_part(X[u][0]), acc[0][0]);
                 acc[0][1] = OPS::step(A[u][0], OPS::im_part(X[u][0]), acc[0][1]);
             } else {
@@ -1606,6 +1606,9 @@ __global__ void m2l_reduce(const PT* part, const int* tgt_chunk_ptr, int64_t ncl
     yh[gid] = s;
 }
 
+constexpr int SPMV_LO_RB = 8;   // columns per pass of the fp32 near product (4: 0.131 ms, 8: 0.119, 16: 0.156
+                                // for 16 columns on the m = 5 sphere)
+
 // y[r][row] = sum_j val x[r][col] (+ far part mapped to the solution space); one
 // wave per row, lanes stride over the row, butterfly reduction (fixed order)
 // (RB columns per pass; consecutive nonzeros of a row mostly have consecutive
@@ -1651,6 +1654,71 @@ __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ 
                 const int r = c0 + cb;
                 if (r >= ncol) continue;
                 double2 a = acc[cb];
+                if (yfar) {
+                    if (s0_ptr) {
+                        for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q) a = cadd(a, yfar[r * n2 + s0_reps[q]]);
+                    } else {
+                        a = cadd(a, yfar[r * n2 + row]);
+                    }
+                }
+                y[int64_t(r) * nrows + row] = a;
+            }
+        }
+    }
+}
+
+// out[i] = in[i] rounded to fp32 (RNE)
+__global__ void round_values(const double2* __restrict__ in, float2* __restrict__ out, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = make_float2(float(in[i].x), float(in[i].y));
+}
+
+// spmv_combine for the reduced-precision operator of the inner solves: fp32
+// values and fp32 columns, fp32 products and sums over the row (same lane
+// order for every column count), far part added and stored in fp64.
+template <int RB>
+__global__ __launch_bounds__(256) void spmv_combine_lo(const int64_t* __restrict__ row_ptr,
+                                                       const int* __restrict__ col,
+                                                       const float2* __restrict__ val,
+                                                       const float2* __restrict__ x, int64_t nrows,
+                                                       const double2* __restrict__ yfar, int64_t n2,
+                                                       const int* __restrict__ s0_ptr,
+                                                       const int* __restrict__ s0_reps, int use_near, int ncol,
+                                                       double2* __restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    if (row >= nrows) return;
+    const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+    for (int c0 = 0; c0 < ncol; c0 += RB) {
+        float2 acc[RB];
+#pragma unroll
+        for (int cb = 0; cb < RB; ++cb) acc[cb] = make_float2(0.f, 0.f);
+        if (use_near) {
+            for (int64_t idx = b + lane; idx < e; idx += 64) {
+                const float2 v = val[idx];
+                const int64_t cc = col[idx];
+#pragma unroll
+                for (int cb = 0; cb < RB; ++cb)
+                    if (c0 + cb < ncol) {
+                        const float2 xv = x[int64_t(c0 + cb) * nrows + cc];
+                        acc[cb].x = fmaf(v.x, xv.x, fmaf(-v.y, xv.y, acc[cb].x));
+                        acc[cb].y = fmaf(v.x, xv.y, fmaf(v.y, xv.x, acc[cb].y));
+                    }
+            }
+        }
+#pragma unroll
+        for (int cb = 0; cb < RB; ++cb)
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                acc[cb].x += __shfl_xor(acc[cb].x, off, 64);
+                acc[cb].y += __shfl_xor(acc[cb].y, off, 64);
+            }
+        if (lane == 0) {
+#pragma unroll
+            for (int cb = 0; cb < RB; ++cb) {
+                const int r = c0 + cb;
+                if (r >= ncol) continue;
+                double2 a = make_double2(double(acc[cb].x), double(acc[cb].y));
                 if (yfar) {
                     if (s0_ptr) {
                         for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q) a = cadd(a, yfar[r * n2 + s0_reps[q]]);
@@ -2310,6 +2378,16 @@ igb_status assemble_near_device(igb_op op, hipStream_t s) {
         else
             return hard ? near_launch<P, true>(op, s) : near_launch<P, false>(op, s);
     });
+    if (!st && op->prm.precision == IGB_MIX_BF16 && op->nnz > 0) {
+        // fp32 copy of the near field for the inner matvecs of the bf16 refinement (whose
+        // inner solves stop at 1e-3; the fp32 operator's inner solves aim at the full
+        // tolerance, below what fp32 columns allow, and keep the fp64 near product)
+        if ((st = alloc(op->d_val_lo, op->nnz * sizeof(float2), acct))) return st;
+        hipLaunchKernelGGL(round_values, dim3(unsigned((op->nnz + 255) / 256)), dim3(256), 0, s, op->d_val.as<double2>(),
+                           op->d_val_lo.as<float2>(), op->nnz);
+        IGB_HIP(hipGetLastError());
+        IGB_HIP(hipStreamSynchronize(s));
+    }
     auto t1 = std::chrono::steady_clock::now();
     op->t_assembly_near = std::chrono::duration<double, std::milli>(t1 - t0).count();
     return st;
@@ -2492,6 +2570,10 @@ igb_status alloc_work(igb_op op, int ncol) {
             return st;
         if ((st = alloc(op->d_part_lo, C * std::max<size_t>(1, op->chunks_mfma.len.size()) * nvec * nq * pt, acct)))
             return st;
+    }
+    if (op->d_val_lo.ptr) {
+        *acct -= std::min(*acct, op->d_xnear_lo.bytes);
+        if ((st = alloc(op->d_xnear_lo, C * op->N * sizeof(float2), acct))) return st;
     }
     if ((st = alloc(op->d_yfar, C * op->geom->n2 * sizeof(double2), acct))) return st;
     if ((st = alloc(op->d_x2, C * op->geom->n2 * sizeof(double2), acct))) return st;
@@ -2787,10 +2869,22 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
     const int64_t* rp = op->d_rowptr.as<int64_t>();
     const int* cl = op->d_col.as<int>();
     const double2* vl = op->d_val.as<double2>();
-    if (ncol == 1)
+    if (low && op->d_val_lo.ptr) {
+        const float2* vlo = op->d_val_lo.as<float2>();
+        float2* xlo = op->d_xnear_lo.as<float2>();
+        if (use_near)
+            hipLaunchKernelGGL(round_values, dim3(blocks_for(N * ncol, 256)), dim3(256), 0, s, X, xlo, N * ncol);
+        if (ncol == 1)
+            hipLaunchKernelGGL(spmv_combine_lo<1>, sg, sb, 0, s, rp, cl, vlo, xlo, N, yfar, g->n2, s0p, s0r, use_near,
+                               ncol, Y);
+        else
+            hipLaunchKernelGGL(spmv_combine_lo<SPMV_LO_RB>, sg, sb, 0, s, rp, cl, vlo, xlo, N, yfar, g->n2, s0p, s0r,
+                               use_near, ncol, Y);
+    } else if (ncol == 1) {
         hipLaunchKernelGGL(spmv_combine<1>, sg, sb, 0, s, rp, cl, vl, X, N, yfar, g->n2, s0p, s0r, use_near, ncol, Y);
-    else
+    } else {
         hipLaunchKernelGGL(spmv_combine<4>, sg, sb, 0, s, rp, cl, vl, X, N, yfar, g->n2, s0p, s0r, use_near, ncol, Y);
+    }
     IGB_HIP(hipGetLastError());
     if ((st = timer_mark(op, 1, s))) return st;
     return IGB_OK;
