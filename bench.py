@@ -46,7 +46,7 @@ HBM_PEAK_GBS = 8000.0
 # make a plain 1 GiB device copy read and write 1 GiB), taken for the kernels
 # as they stand: profiles/m2l_sphere_m5_p2_k8_hbm_counters.md.  To be reset
 # to None whenever one of these kernels changes.
-MEASURED_TRAFFIC = {"m2l_chunks": 2.165e9, "fp64": 2.608e9, "fp32": 1.281e9, "bf16": 0.644e9}
+MEASURED_TRAFFIC = {"m2l_chunks_wave": 2.147e9, "fp64": 2.608e9, "fp32": 1.281e9, "bf16": 0.644e9}
 
 WORKLOADS = {
     "sphere_m5_p2_k8": dict(geometry="sphere", m=5, p=2, kappa=8.0, q=6, eta_adm=1.6, leaf_depth=2,
@@ -278,7 +278,8 @@ def main():
         return {"ncol": nc, "column_matvecs_per_s": nc / tb, "ms_per_block_matvec": tb * 1e3, "kernel_ms": km,
                 "m2l_algorithmic_bytes": byts,
                 "m2l_traffic_bytes": MEASURED_TRAFFIC.get(prec_name) if args.workload == "sphere_m5_p2_k8" else None,
-                "m2l_kernel": "m2l_chunks (vector fp64)" if prec_name == "fp64" else f"m2l_mfma ({prec_name} matrix cores)",
+                "m2l_kernel": "m2l_mfma_soft (fp64 matrix cores)" if prec_name == "fp64" else
+                              f"m2l_mfma_soft ({prec_name} matrix cores)",
                 "m2l_GBps": byts / avg / 1e9, "m2l_TFLOPs": flops / avg / 1e12,
                 "m2l_frac_hbm_peak": byts / avg / (HBM_PEAK_GBS * 1e9),
                 "m2l_frac_matrix_peak": flops / avg / mfma_peak[prec_name]}
@@ -465,8 +466,8 @@ def main():
         "err_farfield_vs_mie": err_mie,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": MEASURED_TRAFFIC["m2l_chunks"] if args.workload == "sphere_m5_p2_k8" else None,
-                     "kernel": "m2l_chunks", "bytes_per_launch": m2l_bytes,
+                     "traffic": MEASURED_TRAFFIC["m2l_chunks_wave"] if args.workload == "sphere_m5_p2_k8" else None,
+                     "kernel": "m2l_chunks_wave", "bytes_per_launch": m2l_bytes,
                      "avg_launch_ms": m2l_avg * 1e3},
     }
     if args.serve > 0:

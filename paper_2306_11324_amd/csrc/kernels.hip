@@ -1485,6 +1485,45 @@ __global__ __launch_bounds__(NT) void m2l_chunks(const CT* __restrict__ coup, co
             if (c0 + cb < ncol) part[(ch * nq + a) * ncol + c0 + cb] = acc[cb];
 }
 
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const long long u = __double_as_longlong(v);
+    const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(u & 0xffffffffll), l));
+    const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(u >> 32), l));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// coupling, sound-soft, one column, nq <= 64: one wave per chunk.  The source
+// moments sit one per lane and reach all lanes by readlane (no LDS, no
+// barrier); the next source's moments load while the current tile streams.
+// Same products in the same order as m2l_chunks.
+__global__ __launch_bounds__(64) void m2l_chunks_wave(const double2* __restrict__ coup,
+                                                      const double2* __restrict__ xh,
+                                                      const int* __restrict__ far_src_g,
+                                                      const int64_t* __restrict__ chunk_pair,
+                                                      const int* __restrict__ chunk_len, int64_t nchunk, int nq,
+                                                      double2* __restrict__ part) {
+    const int64_t ch = blockIdx.x;
+    if (ch >= nchunk) return;
+    const int a = threadIdx.x;
+    const int ac = a < nq ? a : nq - 1;   // idle lanes repeat the last row (never stored)
+    const int64_t p0 = chunk_pair[ch];
+    const int len = chunk_len[ch];
+    double2 acc = make_double2(0, 0);
+    double2 xn = xh[int64_t(far_src_g[p0]) * nq + ac];
+    for (int i = 0; i < len; ++i) {
+        const double2 xv = xn;
+        if (i + 1 < len) xn = xh[int64_t(far_src_g[p0 + i + 1]) * nq + ac];
+        const double2* K = coup + (p0 + i) * nq * nq + ac;
+#pragma unroll 7
+        for (int b = 0; b < nq; ++b) {
+            const double2 kv = K[int64_t(b) * nq];
+            const double2 xb = make_double2(readlane_d(xv.x, b), readlane_d(xv.y, b));
+            acc = cfma(kv, xb, acc);
+        }
+    }
+    if (a < nq) part[ch * nq + a] = acc;
+}
+
 // coupling, sound-hard: per source the 7 node-scaled moment vectors
 //   n~_c xp (c = 0..2), (y.n~) xp, v_c = F_v,c xu - F_u,c xv
 // are formed in LDS; H acts on {(y.n~) xp, n~_c xp}, G on {n~_c xp, v_c}:
@@ -2627,6 +2666,9 @@ static void launch_m2l_fp64(igb_op op, double2* xh, int64_t ks, int ncol, hipStr
         hipLaunchKernelGGL((m2l_hard_chunks<NT, double2, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
                            dim3(NT), 0, s, coup, xh, ks, op->d_nodes.as<double>(), op->d_far_src.as<int>(),
                            C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol, op->d_part.as<double2>());
+    } else if (ncol == 1 && op->nq <= 64) {
+        hipLaunchKernelGGL(m2l_chunks_wave, dim3(unsigned(nchunk)), dim3(64), 0, s, coup, xh, op->d_far_src.as<int>(),
+                           C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, op->d_part.as<double2>());
     } else if (ncol == 1) {
         hipLaunchKernelGGL((m2l_chunks<NT, double2, 1>), dim3(unsigned(nchunk), 1u), dim3(NT), 0, s, coup, xh,
                            op->d_far_src.as<int>(), C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol,
