@@ -2031,79 +2031,107 @@ __global__ __launch_bounds__(256) void pot_box_m2l(const double* __restrict__ no
     }
 }
 
-// one point of pot_l2p_near: interpolated box expansion (lx, or none) + near leaves
-__device__ void pot_point(const double* __restrict__ pts, int pi, int b, const double* __restrict__ box_lo,
-                          const double* __restrict__ box_hi, const double* __restrict__ tch, int q,
-                          const double2* lx, const int* __restrict__ near_ptr, const int* __restrict__ near_leaf,
-                          int d, int L, int nel1, int nqp, const double* __restrict__ geo,
-                          const double2* __restrict__ D, double kappa, int hard, double2* __restrict__ u) {
+// Interpolated box expansion lx (on the box's (q+1)^3 Chebyshev nodes) at point x
+__device__ double2 pot_l2p(const double* x, const double* lo, const double* hi, const double* __restrict__ tch,
+                           int q, const double2* lx) {
     const int q1 = q + 1;
-    const bool has_far = lx != nullptr;
-    const double x[3] = {pts[3 * pi], pts[3 * pi + 1], pts[3 * pi + 2]};
-    double2 acc = make_double2(0, 0);
-    if (has_far) {
-        double w[3][QMAX + 1];
-        for (int c = 0; c < 3; ++c) {
-            const double lo = box_lo[3 * b + c], hi = box_hi[3 * b + c];
-            const double t = (x[c] - lo) / (hi - lo);
-            for (int k = 0; k < q1; ++k) {
-                double v = 1;
-                for (int j = 0; j < q1; ++j)
-                    if (j != k) v *= (t - tch[j]) / (tch[k] - tch[j]);
-                w[c][k] = v;
-            }
+    double w[3][QMAX + 1];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double t = (x[c] - lo[c]) / (hi[c] - lo[c]);
+#pragma unroll
+        for (int k = 0; k <= QMAX; ++k) {
+            double v = 1;
+#pragma unroll
+            for (int j = 0; j <= QMAX; ++j)
+                if (j != k && j < q1) v *= (t - tch[j]) / (tch[k < q1 ? k : 0] - tch[j]);
+            w[c][k] = k < q1 ? v : 0.0;
         }
-        for (int az = 0; az < q1; ++az)
-            for (int ay = 0; ay < q1; ++ay) {
-                double2 row = make_double2(0, 0);
-                for (int ax = 0; ax < q1; ++ax) {
+    }
+    double2 acc = make_double2(0, 0);
+    for (int az = 0; az < q1; ++az)
+        for (int ay = 0; ay < q1; ++ay) {
+            double2 row = make_double2(0, 0);
+#pragma unroll
+            for (int ax = 0; ax <= QMAX; ++ax)
+                if (ax < q1) {
                     const double2 v = lx[(az * q1 + ay) * q1 + ax];
                     row.x = fma(w[0][ax], v.x, row.x);
                     row.y = fma(w[0][ax], v.y, row.y);
                 }
-                const double wyz = w[1][ay] * w[2][az];
-                acc.x = fma(wyz, row.x, acc.x);
-                acc.y = fma(wyz, row.y, acc.y);
+            double wy = 0, wz = 0;
+#pragma unroll
+            for (int k = 0; k <= QMAX; ++k) {
+                if (k == ay) wy = w[1][k];
+                if (k == az) wz = w[2][k];
             }
-    }
-    const int n = 1 << L, s = 1 << d;
-    for (int f = near_ptr[b]; f < near_ptr[b + 1]; ++f) {
-        const int64_t loc = near_leaf[f];
-        const int64_t patch = loc / (int64_t(n) * n);
-        const int cy = int((loc / n) % n), cx = int(loc % n);
-        for (int ey = cy * s; ey < cy * s + s; ++ey)
-            for (int ex = cx * s; ex < cx * s + s; ++ex) {
-                const int64_t e = (patch * nel1 + ey) * nel1 + ex;
-                for (int g = 0; g < nqp; ++g) {
-                    const int64_t gi = e * nqp + g;
-                    acc = cfma(repr_kernel(x, geo + gi * 8, kappa, hard), D[gi], acc);
-                }
-            }
-    }
-    u[pi] = acc;
+            const double wyz = wy * wz;
+            acc.x = fma(wyz, row.x, acc.x);
+            acc.y = fma(wyz, row.y, acc.y);
+        }
+    return acc;
 }
 
 // H^2 potential, per point: the box expansion interpolated at the point (tensor
 // Lagrange on the box's Chebyshev nodes) plus direct quadrature over the
-// elements of the box's inadmissible leaf clusters.  One workgroup per (box,
-// column); the threads stride over the box's points.
+// elements of the box's inadmissible leaf clusters, whose quadrature points are
+// staged in LDS a tile at a time and shared by the box's points.  One
+// workgroup per (box, column), one point per thread (more points in rounds).
+constexpr int POT_TILE = 256;   // quadrature points per LDS tile
 __global__ __launch_bounds__(POT_LEAF_POINTS) void pot_l2p_near(
     const double* __restrict__ pts, const int* __restrict__ perm, const int* __restrict__ box_ptr,
     const double* __restrict__ box_lo, const double* __restrict__ box_hi, const double* __restrict__ tch, int q,
     const double2* __restrict__ lbox, int ncol, const int* __restrict__ near_ptr, const int* __restrict__ near_leaf,
     int d, int L, int nel1, int nqp, const double* __restrict__ geo, const double2* __restrict__ dens, int64_t nqtot,
     double kappa, int hard, int npt, double2* __restrict__ u) {
-    __shared__ double2 lx[(QMAX + 1) * (QMAX + 1) * (QMAX + 1)];
+    // the box expansion and the quadrature tiles share the LDS (one after the other)
+    constexpr int LX = (QMAX + 1) * (QMAX + 1) * (QMAX + 1), TL = POT_TILE * 5;
+    __shared__ double2 smem[LX > TL ? LX : TL];
+    double2* lx = smem;
+    double(*tg)[8] = reinterpret_cast<double(*)[8]>(smem);     // [POT_TILE][8]
+    double2* td = smem + POT_TILE * 4;                           // [POT_TILE]
     const int b = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
     const int q1 = q + 1, n3 = q1 * q1 * q1;
     const bool has_far = lbox != nullptr;
-    if (has_far)
-        for (int a = tid; a < n3; a += POT_LEAF_POINTS) lx[a] = lbox[(int64_t(b) * n3 + a) * ncol + r];
-    __syncthreads();
+    const double2* D = dens + int64_t(r) * nqtot;
+    const int n = 1 << L, s = 1 << d, per_leaf = s * s * nqp;
+    const int p0 = box_ptr[b], p1 = box_ptr[b + 1];
     // (a box at the depth cap may hold more points than threads)
-    for (int i = box_ptr[b] + tid; i < box_ptr[b + 1]; i += POT_LEAF_POINTS)
-        pot_point(pts, perm[i], b, box_lo, box_hi, tch, q, has_far ? lx : nullptr, near_ptr, near_leaf, d, L, nel1,
-                  nqp, geo, dens + int64_t(r) * nqtot, kappa, hard, u + int64_t(r) * npt);
+    for (int base = p0; base < p1; base += POT_LEAF_POINTS) {
+        const int i = base + tid;
+        const bool mine = i < p1;
+        const int pi = mine ? perm[i] : 0;
+        const double x[3] = {pts[3 * pi], pts[3 * pi + 1], pts[3 * pi + 2]};
+        double2 acc = make_double2(0, 0);
+        __syncthreads();   // the previous round's tiles consumed
+        if (has_far) {
+            for (int a = tid; a < n3; a += POT_LEAF_POINTS) lx[a] = lbox[(int64_t(b) * n3 + a) * ncol + r];
+            __syncthreads();
+            if (mine) acc = pot_l2p(x, box_lo + 3 * b, box_hi + 3 * b, tch, q, lx);
+            __syncthreads();   // lx consumed before the tiles overwrite it
+        }
+        for (int f = near_ptr[b]; f < near_ptr[b + 1]; ++f) {
+            const int64_t loc = near_leaf[f];
+            const int64_t patch = loc / (int64_t(n) * n);
+            const int cy = int((loc / n) % n), cx = int(loc % n);
+            for (int t0 = 0; t0 < per_leaf; t0 += POT_TILE) {
+                const int cnt = min(POT_TILE, per_leaf - t0);
+                for (int k = tid; k < cnt; k += POT_LEAF_POINTS) {
+                    const int li = t0 + k, el = li / nqp, g = li % nqp;
+                    const int64_t e = (patch * nel1 + cy * s + el / s) * nel1 + cx * s + el % s;
+                    const int64_t gi = e * nqp + g;
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) tg[k][c] = geo[gi * 8 + c];
+                    td[k] = D[gi];
+                }
+                __syncthreads();
+                if (mine)
+                    for (int k = 0; k < cnt; ++k) acc = cfma(repr_kernel(x, tg[k], kappa, hard), td[k], acc);
+                __syncthreads();
+            }
+        }
+        if (mine) u[int64_t(r) * npt + pi] = acc;
+    }
 }
 
 // ==========================================================================
