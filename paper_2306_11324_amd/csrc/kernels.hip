@@ -638,6 +638,54 @@ __global__ void glue_gather(const int* s2_to_s0, const double2* x0, int64_t n0, 
 }
 
 // leaf moments  xh[leaf][a][r] = sum_{window} m_v[cy][av][iv] m_u[cx][au][iu] x[r][patch][iv][iu]
+// leaf_moments with one workgroup per (leaf, column): the leaf's B-spline
+// window and moment tables in LDS, sum-factorised (rows over u, then v) in the
+// same order as leaf_moments, for windows of at most LM_W coefficients per side.
+constexpr int LM_W = 20;
+__global__ __launch_bounds__(64) void leaf_moments_wg(const double2* __restrict__ x, int64_t xstride,
+                                                      const double* __restrict__ m1, int q, int d, int p, int L,
+                                                      int k, int64_t leaf_off, double2* __restrict__ xh,
+                                                      int deriv_u, int deriv_v, int64_t m1_stride_kind, int ncol) {
+    __shared__ double2 X[LM_W * LM_W];
+    __shared__ double2 tmp[LM_W * (QMAX + 1)];
+    __shared__ double mu[(QMAX + 1) * LM_W], mv[(QMAX + 1) * LM_W];
+    const int q1 = q + 1, nq = q1 * q1, tid = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    const int r = blockIdx.y;
+    const int n = 1 << L, s = 1 << d, w = s + p;
+    const int patch = int(c / (int64_t(n) * n));
+    const int rem = int(c % (int64_t(n) * n));
+    const int cy = rem / n, cx = rem % n;
+    const double2* Xg = x + r * xstride + int64_t(patch) * k * k + int64_t(cy) * s * k + int64_t(cx) * s;
+    for (int i = tid; i < w * w; i += 64) X[i] = Xg[int64_t(i / w) * k + i % w];
+    for (int i = tid; i < q1 * w; i += 64) {
+        mu[i] = m1[deriv_u * m1_stride_kind + int64_t(cx) * q1 * w + i];
+        mv[i] = m1[deriv_v * m1_stride_kind + int64_t(cy) * q1 * w + i];
+    }
+    __syncthreads();
+    for (int i = tid; i < w * q1; i += 64) {
+        const int iv = i / q1, au = i % q1;
+        double2 row = make_double2(0, 0);
+        for (int iu = 0; iu < w; ++iu) {
+            const double2 xv = X[iv * w + iu];
+            row.x = fma(mu[au * w + iu], xv.x, row.x);
+            row.y = fma(mu[au * w + iu], xv.y, row.y);
+        }
+        tmp[i] = row;
+    }
+    __syncthreads();
+    for (int a = tid; a < nq; a += 64) {
+        const int au = a % q1, av = a / q1;
+        double2 acc = make_double2(0, 0);
+        for (int iv = 0; iv < w; ++iv) {
+            const double2 row = tmp[iv * q1 + au];
+            acc.x = fma(mv[av * w + iv], row.x, acc.x);
+            acc.y = fma(mv[av * w + iv], row.y, acc.y);
+        }
+        xh[((leaf_off + c) * nq + a) * ncol + r] = acc;
+    }
+}
+
 __global__ void leaf_moments(const double2* x, int64_t xstride, const double* m1, int q, int d, int p, int L,
                              int k, int64_t leaf_off, int64_t nleaf, double2* xh, int deriv_u, int deriv_v,
                              int64_t m1_stride_kind, int ncol) {
@@ -2788,6 +2836,23 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
 // y = A x: the launch sequence is captured once per (x, y, columns, parts,
 // stream) into a HIP graph and replayed; it holds kernel launches only (no
 // memsets, no allocation).  Kernel timing (profile mode) launches directly.
+// leaf moments of one kind (derivative flags du, dv) of ncol columns into xh
+static void launch_leaf_moments(igb_op op, const double2* x2, double2* xh, int du, int dv, int ncol, hipStream_t s) {
+    igb_geom g = op->geom;
+    const int q = op->q, L = op->L, nq = op->nq;
+    const int64_t nleaf = clusters_on_level(g->npatch, L);
+    const int w = (1 << op->d) + g->p;
+    const int64_t stride_kind = int64_t(1 << L) * (q + 1) * w;
+    if (w <= LM_W)
+        hipLaunchKernelGGL(leaf_moments_wg, dim3(unsigned(nleaf), unsigned(ncol)), dim3(64), 0, s, x2, g->n2,
+                           op->d_m1.as<double>(), q, op->d, g->p, L, g->k, op->clu_off[L], xh, du, dv, stride_kind,
+                           ncol);
+    else
+        hipLaunchKernelGGL(leaf_moments, dim3(blocks_for(nleaf * nq * ncol, 256)), dim3(256), 0, s, x2, g->n2,
+                           op->d_m1.as<double>(), q, op->d, g->p, L, g->k, op->clu_off[L], nleaf, xh, du, dv,
+                           stride_kind, ncol);
+}
+
 // y += c t over n complex entries
 __global__ void caxpy(double2* __restrict__ y, const double2* __restrict__ t, double2 c, int64_t n) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -2883,9 +2948,7 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
         const unsigned cblk = unsigned((ncol + TCB - 1) / TCB);
         if ((st = timer_mark(op, 2, s))) return st;
         for (int kd = 0; kd < kinds; ++kd) {
-            hipLaunchKernelGGL(leaf_moments, dim3(blocks_for(nleaf * nq * ncol, 256)), dim3(256), 0, s, x2, g->n2,
-                               op->d_m1.as<double>(), q, op->d, g->p, L, g->k, op->clu_off[L], nleaf, xh + kd * ks,
-                               du[kd], dv[kd], stride_kind, ncol);
+            launch_leaf_moments(op, x2, xh + kd * ks, du[kd], dv[kd], ncol, s);
             for (int l = L - 1; l >= 0; --l) {
                 const int64_t nc = clusters_on_level(g->npatch, l);
                 hipLaunchKernelGGL(m2m_wg, dim3(unsigned(nc), cblk), dim3(TREE_THREADS), 0, s, op->d_T.as<double>(), q,
@@ -3116,9 +3179,8 @@ igb_status potential_h2_device(igb_op op, const double* coeffs, int ndir, const 
     double2* xh = sp->d_xhat.as<double2>();
     const int64_t nleaf = clusters_on_level(g->npatch, L);
     const int64_t stride_kind = int64_t(1 << L) * q1 * ((1 << sp->d) + g->p);
-    hipLaunchKernelGGL(leaf_moments, dim3(blocks_for(nleaf * nq * ndir, 256)), dim3(256), 0, s, x2, g->n2,
-                       sp->d_m1.as<double>(), q, sp->d, g->p, L, g->k, sp->clu_off[L], nleaf, xh, 0, 0, stride_kind,
-                       ndir);
+    launch_leaf_moments(sp, x2, xh, 0, 0, ndir, s);
+    (void)stride_kind;
     const unsigned cblk = unsigned((ndir + TCB - 1) / TCB);
     for (int l = L - 1; l >= 0; --l)
         hipLaunchKernelGGL(m2m_wg, dim3(unsigned(clusters_on_level(g->npatch, l)), cblk), dim3(TREE_THREADS), 0, s,
