@@ -166,7 +166,7 @@ struct igb_op_s {
     size_t dev_bytes = 0;
     int64_t nclusters = 0;
     // solver scratch
-    igb::DevBuf d_krylov, d_w, d_h, d_b;
+    igb::DevBuf d_krylov, d_w, d_h, d_b, d_dotpart;
     // false for a single boundary integral operator (no right-hand side or representation)
     bool system = true;
     // lazy sum y = sum_i sum_coef[i] sum_parts[i] x of separately stored H^2 matrices

@@ -36,14 +36,18 @@ struct SolveLog {
 namespace {
 
 // ---- multi-column Arnoldi kernels: vectors [C][n], basis [j][C][n] ----
-// h[jj*C + r] = sum_i conj(V[jj][r][i]) w[r][i]; one workgroup per (jj, r)
-__global__ __launch_bounds__(RT) void cdots_multi(const double2* V, int64_t n, int C, const double2* w, double2* h) {
+// Inner products in two passes: partial sums over segments of DOT_SEG entries,
+// one workgroup per (jj, segment, r), then the segments summed in order.
+constexpr int DOT_SEG = 1024;
+__global__ __launch_bounds__(RT) void cdots_seg(const double2* V, int64_t n, int C, int nseg, const double2* w,
+                                                double2* part) {
     __shared__ double2 red[RT];
-    const int jj = blockIdx.x, r = blockIdx.y;
+    const int jj = blockIdx.x, sg = blockIdx.y, r = blockIdx.z;
     const double2* v = V + (int64_t(jj) * C + r) * n;
     const double2* x = w + int64_t(r) * n;
     double2 acc = make_double2(0, 0);
-    for (int64_t i = threadIdx.x; i < n; i += RT) {
+    const int64_t i1 = min(n, int64_t(sg + 1) * DOT_SEG);
+    for (int64_t i = int64_t(sg) * DOT_SEG + threadIdx.x; i < i1; i += RT) {
         const double2 a = v[i], b = x[i];
         acc.x = fma(a.x, b.x, fma(a.y, b.y, acc.x));
         acc.y = fma(a.x, b.y, fma(-a.y, b.x, acc.y));
@@ -57,7 +61,19 @@ __global__ __launch_bounds__(RT) void cdots_multi(const double2* V, int64_t n, i
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) h[int64_t(jj) * C + r] = red[0];
+    if (threadIdx.x == 0) part[(int64_t(jj) * C + r) * nseg + sg] = red[0];
+}
+
+__global__ void cdots_fin(const double2* part, int nvec, int C, int nseg, double2* h) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nvec * C) return;
+    double2 acc = make_double2(0, 0);
+    for (int sg = 0; sg < nseg; ++sg) {
+        const double2 v = part[int64_t(t) * nseg + sg];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    h[t] = acc;
 }
 
 // w[r][i] -= sum_jj c[jj*C + r] V[jj][r][i]
@@ -133,8 +149,8 @@ struct ColumnResult {
 
 struct Work {
     int64_t n;
-    int m, C;
-    double2 *V, *w, *r, *R, *D, *h, *h2, *y;
+    int m, C, nseg;
+    double2 *V, *w, *r, *R, *D, *h, *h2, *y, *part;
     double *nrm, *sc;
 };
 
@@ -153,7 +169,13 @@ igb_status ensure_work(igb_op op, int m, int C, Work& W) {
         return IGB_OK;
     };
     igb_status st;
-    if ((st = grow(op->d_krylov, need_v)) || (st = grow(op->d_w, need_w)) || (st = grow(op->d_h, need_h))) return st;
+    const int nseg = int((n + DOT_SEG - 1) / DOT_SEG);
+    const size_t need_p = size_t(m + 1) * C * nseg * sizeof(double2);
+    if ((st = grow(op->d_krylov, need_v)) || (st = grow(op->d_w, need_w)) || (st = grow(op->d_h, need_h)) ||
+        (st = grow(op->d_dotpart, need_p)))
+        return st;
+    W.nseg = nseg;
+    W.part = op->d_dotpart.as<double2>();
     W.n = n;
     W.m = m;
     W.C = C;
@@ -190,6 +212,7 @@ igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, 
     const int64_t n = Wk.n;
     const int m = Wk.m, C = Wk.C;
     const unsigned gb = unsigned((n * C + 255) / 256);
+    const unsigned gb64 = unsigned((n * C + 63) / 64);
     double2 *V = Wk.V, *w = Wk.w, *r = Wk.r;
     igb_status st;
     IGB_HIP(hipMemsetAsync(X, 0, n * C * sizeof(double2), s));
@@ -232,10 +255,13 @@ igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, 
                                     reinterpret_cast<double*>(w), C, mvflags, s)))
                 return st;
             // classical Gram-Schmidt, twice
-            hipLaunchKernelGGL(cdots_multi, dim3(j + 1, C), dim3(RT), 0, s, V, n, C, w, Wk.h);
-            hipLaunchKernelGGL(cmaxpy_multi, dim3(gb), dim3(256), 0, s, V, j + 1, n, C, Wk.h, w);
-            hipLaunchKernelGGL(cdots_multi, dim3(j + 1, C), dim3(RT), 0, s, V, n, C, w, Wk.h2);
-            hipLaunchKernelGGL(cmaxpy_multi, dim3(gb), dim3(256), 0, s, V, j + 1, n, C, Wk.h2, w);
+            const unsigned gd = unsigned(((j + 1) * C + 255) / 256);
+            hipLaunchKernelGGL(cdots_seg, dim3(j + 1, Wk.nseg, C), dim3(RT), 0, s, V, n, C, Wk.nseg, w, Wk.part);
+            hipLaunchKernelGGL(cdots_fin, dim3(gd), dim3(256), 0, s, Wk.part, j + 1, C, Wk.nseg, Wk.h);
+            hipLaunchKernelGGL(cmaxpy_multi, dim3(gb64), dim3(64), 0, s, V, j + 1, n, C, Wk.h, w);
+            hipLaunchKernelGGL(cdots_seg, dim3(j + 1, Wk.nseg, C), dim3(RT), 0, s, V, n, C, Wk.nseg, w, Wk.part);
+            hipLaunchKernelGGL(cdots_fin, dim3(gd), dim3(256), 0, s, Wk.part, j + 1, C, Wk.nseg, Wk.h2);
+            hipLaunchKernelGGL(cmaxpy_multi, dim3(gb64), dim3(64), 0, s, V, j + 1, n, C, Wk.h2, w);
             IGB_HIP(hipGetLastError());
             IGB_HIP(hipMemcpyAsync(hh.data(), Wk.h, size_t(j + 1) * C * sizeof(double2), hipMemcpyDeviceToHost, s));
             IGB_HIP(hipMemcpyAsync(hh.data() + size_t(j + 1) * C, Wk.h2, size_t(j + 1) * C * sizeof(double2),
