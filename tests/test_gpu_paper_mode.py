@@ -84,3 +84,33 @@ def test_separate_matrices_equal_fused_operator(bc):
     e = float(np.abs(sol[True] - sol[False]).max() / np.abs(sol[False]).max())
     print(f"far field separate vs fused {e:.2e}", flush=True)
     assert e < 1e-9
+
+
+def test_separate_matrices_in_bf16_refinement_and_potential():
+    """The separate form with bf16 couplings inside fp64 refinement reaches the
+    fp64 tolerance like the fused form, and its scattered field (direct and H^2
+    evaluation, which read the first matrix's tree) equals the fused one's."""
+    from paper_2306_11324_amd import binding as B
+    from paper_2306_11324_amd import inputs as I
+    print("case: sphere m=4 p=2 kappa=4 q=6 leaf depth 2 soft bf16: separate vs fused", flush=True)
+    ctx = B.Context(0)
+    geo = B.Geometry(ctx, I.sphere_patches(), 4, 2)
+    d = I.random_directions(5, 2)
+    pts = 2.5 * I.fibonacci_directions(500)
+    out = {}
+    for sep in (False, True):
+        op = B.Operator(ctx, geo, kappa=4.0, q=6, leaf_depth=2, precision=B.MIX_BF16, separate=sep)
+        c = torch.zeros((2, op.n), dtype=torch.complex128, device="cuda")
+        info, st = op.cfie_solve(d, c, tol=1e-10, restart=30, maxit=1000)
+        assert st == 0 and info.converged == 2 and info.relres_true <= 1e-10
+        u = torch.zeros((2, len(pts)), dtype=torch.complex128, device="cuda")
+        uh = torch.zeros_like(u)
+        op.potential(c, pts, u, ndir=2)
+        op.potential_h2(c, pts, uh, ndir=2)
+        torch.cuda.synchronize()
+        out[sep] = (u.cpu().numpy(), uh.cpu().numpy())
+        del op
+    e = float(np.abs(out[True][0] - out[False][0]).max() / np.abs(out[False][0]).max())
+    eh = float(np.abs(out[True][1] - out[True][0]).max() / np.abs(out[True][0]).max())
+    print(f"separate vs fused field {e:.2e}; H^2 vs direct on the separate form {eh:.2e}", flush=True)
+    assert e < 1e-8 and eh < 1e-5
