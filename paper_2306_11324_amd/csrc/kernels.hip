@@ -1975,47 +1975,8 @@ __global__ __launch_bounds__(256) void farfield_sum(const double* geo, const dou
     }
 }
 
-// scattered field at points off the boundary: soft u = -sum G a w dens,
-// hard u = sum G (i kappa r - 1)/r^2 ((y - x).n~) w dens; one workgroup per
-// (point, direction), fixed-order tree reduction
-__global__ __launch_bounds__(256) void potential_sum(const double* geo, const double2* dens, int64_t npts,
-                                                     const double* pts, int npt, double kappa, int hard,
-                                                     double2* u) {
-    __shared__ double2 red[256];
-    const int o = blockIdx.x, dir = blockIdx.y;
-    const double* x = pts + 3 * o;
-    const double2* D = dens + int64_t(dir) * npts;
-    double2 acc = make_double2(0, 0);
-    for (int64_t i = threadIdx.x; i < npts; i += 256) {
-        const double* g = geo + i * 8;
-        const double d0 = g[0] - x[0], d1 = g[1] - x[1], d2 = g[2] - x[2];   // y - x
-        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        const double ir = 1.0 / r, kr = kappa * r;
-        double sn, cs;
-        sincos(kr, &sn, &cs);
-        const double c4 = 0.07957747154594767 * ir;   // 1/(4 pi r)
-        double2 k;
-        if (hard) {
-            const double dn = (d0 * g[3] + d1 * g[4] + d2 * g[5]) * ir * ir * g[7];
-            // G (i kappa r - 1) = c4 (cs + i sn)(-1 + i kr)
-            k = make_double2(c4 * dn * (-cs - sn * kr), c4 * dn * (cs * kr - sn));
-        } else {
-            const double wa = -c4 * g[6] * g[7];
-            k = make_double2(wa * cs, wa * sn);
-        }
-        acc = cfma(k, D[i], acc);
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if (threadIdx.x < st) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + st]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) u[int64_t(dir) * npt + o] = red[0];
-}
-
 // kernel of the representation at one point pair, surface data g = (y, n~, a, w):
-// soft -G a w, hard G (i kappa r - 1)/r^2 ((y - x).n~) w (potential_sum's terms)
+// soft -G a w, hard G (i kappa r - 1)/r^2 ((y - x).n~) w (used by both potential evaluations)
 __device__ __forceinline__ double2 repr_kernel(const double* x, const double* g, double kappa, int hard) {
     const double d0 = g[0] - x[0], d1 = g[1] - x[1], d2 = g[2] - x[2];   // y - x
     const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
@@ -2029,6 +1990,27 @@ __device__ __forceinline__ double2 repr_kernel(const double* x, const double* g,
     }
     const double wa = -c4 * g[6] * g[7];
     return make_double2(wa * cs, wa * sn);
+}
+
+// scattered field at points off the boundary: soft u = -sum G a w dens,
+// hard u = sum G (i kappa r - 1)/r^2 ((y - x).n~) w dens; one workgroup per
+// (point, direction), fixed-order tree reduction
+__global__ __launch_bounds__(256) void potential_sum(const double* geo, const double2* dens, int64_t npts,
+                                                     const double* pts, int npt, double kappa, int hard,
+                                                     double2* u) {
+    __shared__ double2 red[256];
+    const int o = blockIdx.x, dir = blockIdx.y;
+    const double* x = pts + 3 * o;
+    const double2* D = dens + int64_t(dir) * npts;
+    double2 acc = make_double2(0, 0);
+    for (int64_t i = threadIdx.x; i < npts; i += 256) acc = cfma(repr_kernel(x, geo + i * 8, kappa, hard), D[i], acc);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) u[int64_t(dir) * npt + o] = red[0];
 }
 
 // H^2 potential, far part: local expansion of every target box on its (q+1)^3
@@ -3177,10 +3159,7 @@ igb_status potential_h2_device(igb_op op, const double* coeffs, int ndir, const 
         x2 = sp->d_x2.as<double2>();
     }
     double2* xh = sp->d_xhat.as<double2>();
-    const int64_t nleaf = clusters_on_level(g->npatch, L);
-    const int64_t stride_kind = int64_t(1 << L) * q1 * ((1 << sp->d) + g->p);
     launch_leaf_moments(sp, x2, xh, 0, 0, ndir, s);
-    (void)stride_kind;
     const unsigned cblk = unsigned((ndir + TCB - 1) / TCB);
     for (int l = L - 1; l >= 0; --l)
         hipLaunchKernelGGL(m2m_wg, dim3(unsigned(clusters_on_level(g->npatch, l)), cblk), dim3(TREE_THREADS), 0, s,
