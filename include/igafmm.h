@@ -138,7 +138,14 @@ typedef enum {
  *              couplings, applied as a lazy sum; the same system up to rounding at
  *              twice the coupling memory and traffic.  igb_op_near_csr,
  *              igb_op_far_blocks, igb_op_near_pairs, igb_op_profile and
- *              igb_op_kernel_time return IGB_ERR_ARG on such an operator. */
+ *              igb_op_kernel_time return IGB_ERR_ARG on such an operator.
+ *   far_recompress_tol  0: off.  > 0 (at most 1e-2; sound-soft family, stored fp64
+ *              couplings, q <= 7): each coupling tile K is also factored as a sum of
+ *              rank-one terms u v^T by cross approximation with complete pivoting,
+ *              stopped when no entry of K - sum u v^T exceeds tol * max|K|; the
+ *              one-column fp64 products (h2_matvec with nrhs = 1, single-direction
+ *              solves and residuals) then stream the factors instead of the tiles.
+ *              Products of several columns keep using the tiles. */
 typedef struct {
     double kappa;
     int bc;
@@ -152,6 +159,7 @@ typedef struct {
     int quad_extra;
     int formulation;
     int separate;
+    double far_recompress_tol;
 } igb_op_params;
 
 typedef struct {

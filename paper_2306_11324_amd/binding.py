@@ -45,7 +45,7 @@ class IgbOpParams(C.Structure):
     _fields_ = [("kappa", C.c_double), ("bc", C.c_int), ("eta_c", C.c_double), ("q", C.c_int),
                 ("eta_adm", C.c_double), ("kcap", C.c_double), ("leaf_depth", C.c_int),
                 ("precision", C.c_int), ("far_on_the_fly", C.c_int), ("quad_extra", C.c_int),
-                ("formulation", C.c_int), ("separate", C.c_int)]
+                ("formulation", C.c_int), ("separate", C.c_int), ("far_recompress_tol", C.c_double)]
 
 
 class IgbSolveParams(C.Structure):
@@ -191,10 +191,11 @@ class Operator:
     def __init__(self, ctx: Context, geom: Geometry, kappa: float, bc: int = SOFT, eta_c: float = 0.0,
                  q: int = 6, eta_adm: float = 1.6, kcap: float = 0.0, leaf_depth: int = 2,
                  precision: int = FP64, far_on_the_fly: bool = False, quad_extra: int = 0,
-                 formulation: int = CFIE, separate: bool = False):
+                 formulation: int = CFIE, separate: bool = False, recompress_tol: float = 0.0):
         self.ctx, self.geom = ctx, geom
         self.params = IgbOpParams(kappa, bc, eta_c, q, eta_adm, kcap, leaf_depth, precision,
-                                  1 if far_on_the_fly else 0, quad_extra, formulation, 1 if separate else 0)
+                                  1 if far_on_the_fly else 0, quad_extra, formulation, 1 if separate else 0,
+                                  recompress_tol)
         h = _P()
         _check("assemble_nearfield", _lib.assemble_nearfield(ctx.h, geom.h, C.byref(self.params), C.byref(h)))
         self.h = h

@@ -271,6 +271,8 @@ static igb_status build_one(igb_ctx ctx, igb_geom g, const igb_op_params* prm, c
         need += size_t(op->nclusters) * (ntile == 2 ? 7 : 1) * 16 * kbp * esz +
                 op->chunks_mfma.len.size() * (ntile == 2 ? 10 : 1) * op->nq * 8;
     }
+    // recompressed couplings: at most the tiles' size at the tolerances of interest
+    if (prm->far_recompress_tol > 0) need += size_t(op->nfar) * op->nq * op->nq * 16 + size_t(op->nfar) * 12;
     // matvec work vectors for one column and a GMRES(30) basis
     need += size_t(op->nclusters) * op->nq * 16 * (op->bc == IGB_HARD ? 16 : 2) + size_t(g->n2) * 16 * 4 +
             size_t(35) * op->N * 16;
@@ -329,7 +331,16 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
         set_error("assemble_nearfield: separate must be 0, or 1 with IGB_CFIE");
         return IGB_ERR_ARG;
     }
+    if (!(prm->far_recompress_tol >= 0 && prm->far_recompress_tol <= 1e-2)) {
+        set_error("assemble_nearfield: need 0 <= far_recompress_tol <= 1e-2");
+        return IGB_ERR_ARG;
+    }
     const Coefs c = coefs_for(prm);
+    if (prm->far_recompress_tol > 0 && (c.family != IGB_SOFT || prm->far_on_the_fly || prm->q > 7)) {
+        set_error("assemble_nearfield: far_recompress_tol needs a sound-soft-family operator with stored couplings "
+                  "and q <= 7");
+        return IGB_ERR_UNSUPPORTED;
+    }
     if (c.family == IGB_HARD && g->p < 1) {
         set_error("assemble_nearfield: the sound-hard operators need S^0, i.e. p >= 1");
         return IGB_ERR_ARG;

@@ -153,6 +153,10 @@ struct igb_op_s {
     M2LChunks chunks, chunks_mfma;
     // device data
     igb::DevBuf d_coupling, d_coupling_lo, d_nodes, d_m1, d_T;
+    // recompressed couplings (far_recompress_tol > 0): per far pair the rank, the offset of
+    // its factors (complex entries) and the factors u_k [k][nq], v_k^T [nq][rank]
+    igb::DevBuf d_lr, d_lr_rank, d_lr_off;
+    int64_t lr_entries = 0;
     igb::DevBuf d_rowptr, d_col, d_val;
     // bf16 operators: fp32 near-field values and fp32 copies of the columns for the
     // near product of the inner (refinement) matvecs

@@ -1572,6 +1572,122 @@ __global__ __launch_bounds__(64) void m2l_chunks_wave(const double2* __restrict_
     if (a < nq) part[ch * nq + a] = acc;
 }
 
+// Recompression of one fp64 coupling tile, K(a, b) stored at [b*nq + a] (a target,
+// b source), by cross approximation with complete pivoting: the residual's
+// largest entry R(a*, b*) gives the term u v^T with u(a) = R(a, b*) / R(a*, b*)
+// and v(b) = R(a*, b); stop when no residual entry exceeds tol * max|K|.  Pass 1
+// (fac == nullptr) writes the number of terms; pass 2 repeats the same steps and
+// writes u_k at fac[off + k*nq + a] and v_k transposed at fac[off + K*nq + b*K + k].
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+__global__ __launch_bounds__(256) void tile_aca(const double2* __restrict__ coup, int64_t npairs, int nq, double tol,
+                                                int* __restrict__ rank, const int64_t* __restrict__ off,
+                                                double2* __restrict__ fac) {
+    __shared__ double2 R[64 * 64];
+    __shared__ double2 cu[64], cv[64];
+    __shared__ double rv[256];
+    __shared__ int ri[256];
+    const int tid = threadIdx.x, n2 = nq * nq;
+    for (int64_t p = blockIdx.x; p < npairs; p += gridDim.x) {
+        __syncthreads();
+        for (int i = tid; i < n2; i += 256) R[i] = coup[p * n2 + i];
+        const int kmax = fac ? rank[p] : nq;
+        const int64_t o = fac ? off[p] : 0;
+        double amax2 = -1;
+        for (int k = 0;; ++k) {
+            // largest |R|^2, lowest index on ties
+            double best = -1;
+            int bi = 0;
+            __syncthreads();
+            for (int i = tid; i < n2; i += 256) {
+                const double m = R[i].x * R[i].x + R[i].y * R[i].y;
+                if (m > best) {
+                    best = m;
+                    bi = i;
+                }
+            }
+            rv[tid] = best;
+            ri[tid] = bi;
+            __syncthreads();
+            for (int st = 128; st > 0; st >>= 1) {
+                if (tid < st && (rv[tid + st] > rv[tid] || (rv[tid + st] == rv[tid] && ri[tid + st] < ri[tid]))) {
+                    rv[tid] = rv[tid + st];
+                    ri[tid] = ri[tid + st];
+                }
+                __syncthreads();
+            }
+            const double m2 = rv[0];
+            const int piv = ri[0];
+            if (k == 0) amax2 = m2;
+            if (!(m2 > tol * tol * amax2) || k >= kmax) {
+                if (!fac && tid == 0) rank[p] = k;
+                break;
+            }
+            const int bs = piv / nq, as = piv % nq;
+            const double2 pv = R[piv];
+            for (int i = tid; i < nq; i += 256) {
+                cu[i] = cdiv(R[bs * nq + i], pv);
+                cv[i] = R[i * nq + as];
+            }
+            __syncthreads();
+            for (int i = tid; i < n2; i += 256) {
+                const double2 t = cmul(cu[i % nq], cv[i / nq]);
+                R[i] = make_double2(R[i].x - t.x, R[i].y - t.y);
+            }
+            if (fac)
+                for (int i = tid; i < nq; i += 256) {
+                    fac[o + int64_t(k) * nq + i] = cu[i];
+                    fac[o + int64_t(kmax) * nq + int64_t(i) * kmax + k] = cv[i];
+                }
+        }
+    }
+}
+
+// coupling, sound-soft, one column, from the recompressed tiles: per pair
+// t_k = sum_b v_k(b) x(b) (lane k, v^T rows read contiguously) and
+// y(a) += sum_k u_k(a) t_k (lane a), the moments and t reaching the lanes by
+// readlane; one wave per chunk as in m2l_chunks_wave.
+__global__ __launch_bounds__(64) void m2l_chunks_lowrank(const double2* __restrict__ fac,
+                                                         const int* __restrict__ rank,
+                                                         const int64_t* __restrict__ off,
+                                                         const double2* __restrict__ xh,
+                                                         const int* __restrict__ far_src_g,
+                                                         const int64_t* __restrict__ chunk_pair,
+                                                         const int* __restrict__ chunk_len, int64_t nchunk, int nq,
+                                                         double2* __restrict__ part) {
+    const int64_t ch = blockIdx.x;
+    if (ch >= nchunk) return;
+    const int a = threadIdx.x;
+    const int ac = a < nq ? a : nq - 1;
+    const int64_t p0 = chunk_pair[ch];
+    const int len = chunk_len[ch];
+    double2 acc = make_double2(0, 0);
+    double2 xn = xh[int64_t(far_src_g[p0]) * nq + ac];
+    for (int i = 0; i < len; ++i) {
+        const double2 xv = xn;
+        if (i + 1 < len) xn = xh[int64_t(far_src_g[p0 + i + 1]) * nq + ac];
+        const int64_t pr = p0 + i;
+        const int K = rank[pr];
+        if (K == 0) continue;
+        const double2* U = fac + off[pr];
+        const double2* VT = U + int64_t(K) * nq;
+        const int kc = a < K ? a : K - 1;   // idle lanes repeat the last term (never read)
+        double2 t = make_double2(0, 0);
+        for (int b = 0; b < nq; ++b) {
+            const double2 xb = make_double2(readlane_d(xv.x, b), readlane_d(xv.y, b));
+            t = cfma(VT[int64_t(b) * K + kc], xb, t);
+        }
+        for (int k = 0; k < K; ++k) {
+            const double2 tk = make_double2(readlane_d(t.x, k), readlane_d(t.y, k));
+            acc = cfma(U[int64_t(k) * nq + ac], tk, acc);
+        }
+    }
+    if (a < nq) part[ch * nq + a] = acc;
+}
+
 // coupling, sound-hard: per source the 7 node-scaled moment vectors
 //   n~_c xp (c = 0..2), (y.n~) xp, v_c = F_v,c xu - F_u,c xv
 // are formed in LDS; H acts on {(y.n~) xp, n~_c xp}, G on {n~_c xp, v_c}:
@@ -2599,6 +2715,30 @@ igb_status assemble_far_device(igb_op op, hipStream_t s) {
                                op->d_coupling.as<double2>());
         IGB_HIP(hipGetLastError());
     }
+    if (op->nfar > 0 && !otf && !hard && op->prm.far_recompress_tol > 0) {
+        // factors of every tile: count the terms, lay them out, then write them
+        if ((st = alloc(op->d_lr_rank, size_t(op->nfar) * sizeof(int), acct))) return st;
+        const dim3 grid(unsigned(std::min<int64_t>(op->nfar, 1 << 16)));
+        hipLaunchKernelGGL(tile_aca, grid, dim3(256), 0, s, op->d_coupling.as<double2>(), op->nfar, nq,
+                           op->prm.far_recompress_tol, op->d_lr_rank.as<int>(), nullptr, nullptr);
+        IGB_HIP(hipGetLastError());
+        std::vector<int> rk(op->nfar);
+        IGB_HIP(hipMemcpyAsync(rk.data(), op->d_lr_rank.ptr, rk.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+        IGB_HIP(hipStreamSynchronize(s));
+        std::vector<int64_t> off(op->nfar);
+        int64_t tot = 0;
+        for (int64_t i = 0; i < op->nfar; ++i) {
+            off[i] = tot;
+            tot += int64_t(2) * rk[i] * nq;
+        }
+        op->lr_entries = tot;
+        if ((st = upload(op->d_lr_off, off.data(), off.size(), acct))) return st;
+        if ((st = alloc(op->d_lr, size_t(std::max<int64_t>(tot, 1)) * sizeof(double2), acct))) return st;
+        hipLaunchKernelGGL(tile_aca, grid, dim3(256), 0, s, op->d_coupling.as<double2>(), op->nfar, nq,
+                           op->prm.far_recompress_tol, op->d_lr_rank.as<int>(), op->d_lr_off.as<int64_t>(),
+                           op->d_lr.as<double2>());
+        IGB_HIP(hipGetLastError());
+    }
     if (op->nfar > 0 && op->prm.precision != IGB_FP64) {
         const int ntile = hard ? 2 : 1;
         const bool f32 = op->prm.precision == IGB_MIX_FP32;
@@ -2724,6 +2864,10 @@ static void launch_m2l_fp64(igb_op op, double2* xh, int64_t ks, int ncol, hipStr
         hipLaunchKernelGGL((m2l_hard_chunks<NT, double2, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
                            dim3(NT), 0, s, coup, xh, ks, op->d_nodes.as<double>(), op->d_far_src.as<int>(),
                            C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol, op->d_part.as<double2>());
+    } else if (ncol == 1 && op->d_lr.ptr) {
+        hipLaunchKernelGGL(m2l_chunks_lowrank, dim3(unsigned(nchunk)), dim3(64), 0, s, op->d_lr.as<double2>(),
+                           op->d_lr_rank.as<int>(), op->d_lr_off.as<int64_t>(), xh, op->d_far_src.as<int>(),
+                           C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, op->d_part.as<double2>());
     } else if (ncol == 1 && op->nq <= 64) {
         hipLaunchKernelGGL(m2l_chunks_wave, dim3(unsigned(nchunk)), dim3(64), 0, s, coup, xh, op->d_far_src.as<int>(),
                            C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, op->d_part.as<double2>());
