@@ -174,3 +174,14 @@ def test_separate_matrices_and_single_operators_on_host(hctx):
     g0 = B.Geometry(hctx, I.sphere_patches(), 2, 0)
     with pytest.raises(B.IgbError):
         B.Operator(hctx, g0, kappa=2.0, q=4, leaf_depth=1, formulation=B.OP_K)
+
+
+def test_recompression_parameter_is_validated(hctx):
+    geo = B.Geometry(hctx, I.sphere_patches(), 3, 2)
+    B.Operator(hctx, geo, kappa=2.0, q=4, leaf_depth=1, recompress_tol=1e-8)
+    for kw in (dict(recompress_tol=-1e-8), dict(recompress_tol=0.5), dict(recompress_tol=1e-8, bc=B.HARD),
+               dict(recompress_tol=1e-8, q=8), dict(recompress_tol=1e-8, far_on_the_fly=True)):
+        args = dict(kappa=2.0, q=4, leaf_depth=1)
+        args.update(kw)
+        with pytest.raises(B.IgbError):
+            B.Operator(hctx, geo, **args)
