@@ -127,6 +127,13 @@ def test_compute_on_host_only_context_fails_loudly(hctx):
     op = B.Operator(hctx, geo, kappa=1.0, q=2, leaf_depth=0)
     st = B._lib.h2_matvec(op.h, B.C.c_void_p(8), B.C.c_void_p(16), 1, 3, None)
     assert st == -1
+    pts = (B.C.c_double * 3)(2.0, 0.0, 0.0)
+    for fn in (B._lib.potential, B._lib.potential_h2):
+        assert fn(op.h, B.C.c_void_p(8), 1, pts, 1, B.C.c_void_p(16), None) == -1
+    # single operators have no right-hand side or representation, on any context
+    V = B.Operator(hctx, geo, kappa=1.0, q=2, leaf_depth=0, formulation=B.OP_V)
+    dirs = (B.C.c_double * 3)(0.0, 0.0, 1.0)
+    assert B._lib.cfie_rhs(V.h, dirs, 1, B.C.c_void_p(16), None) == -1
 
 
 def test_budget_rejects_before_allocating():
