@@ -14,7 +14,10 @@ field quadrature + coupling matrices) is timed separately and reported.
 Beside the headline line's value: the served forms (16 directions in lockstep
 with fp64, fp32 or bf16 couplings; the reduced precisions run on the matrix
 cores inside fp64 iterative refinement), each block matvec's kernel times and
-roofline, and a continuous-batching request stream with p50/p99 latency.
+roofline, a continuous-batching request stream with p50/p99 latency, the same
+solves with one H^2 matrix per operator (`paper_mode`) and with recompressed
+coupling tiles (`recompressed`), and the scattered field at points off the
+boundary by direct summation and by the H^2 evaluation (`potential`).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
                     [--block 16] [--serve 32] [--serve-rate 1.0]
@@ -23,7 +26,9 @@ roofline, and a continuous-batching request stream with p50/p99 latency.
 kappa = 2.5, incidence along x, scattered field at 100 points on the radius-5
 sphere; soft p = 0..3, hard p = 1..3, m = 0..--conv-mmax) and prints one JSON
 line per solve and a final one with the l-infinity errors against the finest,
-highest-degree solution of each boundary condition and the observed orders.
+highest-degree solution of each boundary condition (or, with
+`--conv-reference single_layer`, the single-layer solution) and the observed
+orders.
 """
 from __future__ import annotations
 
