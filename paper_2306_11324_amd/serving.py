@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import math
 import threading
 import time
 
@@ -46,6 +47,9 @@ class ServeConfig:
     restart_soft: int = 30
     restart_hard: int = 30
     maxit: int = 1500        # Arnoldi steps per direction; a request that reaches it is reported unconverged
+    # autotuned operator shapes (leaf depth, stored / on-the-fly couplings) per request class;
+    # classes without an entry use leaf_depth and stored couplings
+    tune_cache: object = None
 
 
 @dataclasses.dataclass
@@ -101,9 +105,17 @@ class Server:
 
     def _op_args(self, req: I.Request):
         c = self.cfg
-        return dict(kappa=req.kappa, bc=B.SOFT if req.bc == "soft" else B.HARD, q=c.q, eta_adm=c.eta_adm,
-                    leaf_depth=c.leaf_depth, precision=c.precision if req.bc == "soft" else c.precision_hard,
+        bc = B.SOFT if req.bc == "soft" else B.HARD
+        prec = c.precision if req.bc == "soft" else c.precision_hard
+        args = dict(kappa=req.kappa, bc=bc, q=c.q, eta_adm=c.eta_adm, leaf_depth=c.leaf_depth, precision=prec,
                     quad_extra=c.quad_extra)
+        if c.tune_cache is not None:
+            from . import autotune as T
+            ch = c.tune_cache.get(T.TuneKey(T.device_arch(), req.m, c.p, c.q, bc, prec,
+                                            round(math.log2(req.kappa)), T.nrhs_bucket(len(req.dirs))))
+            if ch is not None:
+                args.update(leaf_depth=ch.leaf_depth, far_on_the_fly=ch.far_on_the_fly)
+        return args
 
     def estimate(self, req: I.Request) -> int:
         """Device bytes of the request (host-only plan: nothing is allocated)."""

@@ -1,0 +1,56 @@
+"""Autotuner over leaf depth and stored / on-the-fly couplings: every candidate
+keeps the accuracy against the dense oracle rows (same admissibility and q),
+the choice is the cheapest measured candidate, and the cache round-trips
+through its JSON file and is what the server's operator arguments use."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_tuned_shape_is_cheapest_and_accurate(tmp_path):
+    from paper_2306_11324_amd import autotune as T
+    from paper_2306_11324_amd import binding as B
+    from paper_2306_11324_amd import inputs as I
+    g = dict(np.load(os.path.join(GOLD, "sphere_m5_p2_k8_rows.npz")))
+    print("case: sphere m=5 p=2 kappa=8 q=6 fp64, one column, leaf depths 1-3, stored / on the fly", flush=True)
+    ctx = B.Context(0)
+    geo = B.Geometry(ctx, I.sphere_patches(), 5, 2)
+    cache = T.TuneCache(str(tmp_path / "tune.json"))
+    best, measured = T.tune(ctx, geo, 5, 2, 1, 8.0, q=6, leaf_depths=(1, 2, 3), cache=cache, reps=3)
+    for c in measured:
+        print(f"  d={c.leaf_depth} otf={c.far_on_the_fly}: matvec {c.matvec_ms:.3f} ms, assembly "
+              f"{c.assembly_ms:.0f} ms, {c.device_bytes / 1e9:.2f} GB", flush=True)
+    assert len(measured) >= 4
+    cost = [c.assembly_ms + 200 * c.matvec_ms for c in measured]
+    assert best.assembly_ms + 200 * best.matvec_ms == min(cost)
+    # every candidate is as accurate as the default against the oracle rows
+    x = torch.from_numpy(g["x"]).cuda()
+    for c in measured:
+        op = B.Operator(ctx, geo, kappa=8.0, q=6, leaf_depth=c.leaf_depth, far_on_the_fly=c.far_on_the_fly)
+        y = torch.zeros_like(x)
+        op.h2_matvec(x, y)
+        torch.cuda.synchronize()
+        yr = y.cpu().numpy()[g["rows"]]
+        e = float(np.max(np.abs(yr - g["y"]) / (g["rownorm1"] * np.abs(g["x"]).max())))
+        assert e < 1e-6, (c, e)
+        del op
+    # the cache round-trips and answers without measuring
+    again = T.TuneCache(str(tmp_path / "tune.json"))
+    best2, measured2 = T.tune(ctx, geo, 5, 2, 1, 8.0, q=6, cache=again)
+    assert measured2 == [] and best2 == best
+    # the server's operator arguments take the cached shape for the request's class
+    from paper_2306_11324_amd import serving as S
+    req = I.Request(rid=0, arrival=0.0, seed=0, m=5, kappa=8.0, bc="soft", dirs=np.array([[0.0, 0.0, 1.0]]))
+    srv = S.Server.__new__(S.Server)
+    srv.cfg = S.ServeConfig(p=2, q=6, precision=B.FP64, tune_cache=again)
+    args = srv._op_args(req)
+    assert args["leaf_depth"] == best.leaf_depth and args["far_on_the_fly"] == best.far_on_the_fly
