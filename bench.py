@@ -338,6 +338,19 @@ def main():
         "note": "separate H^2 matrices of 1/2 M + K* and V, applied as a lazy sum, against the fused kernel"}
     del op_sep, sep
     torch.cuda.empty_cache()
+    # the autotuner's view of this workload class: leaf depth for one fp64 column and for
+    # 16 bf16 columns (the headline keeps leaf depth 2: at this size deeper leaves turn the
+    # operator into a mostly dense near field)
+    from paper_2306_11324_amd import autotune as T
+    tuned = {}
+    for label, prec, nc in (("fp64_1col", B.FP64, 1), ("bf16_16col", B.MIX_BF16, 16)):
+        best, cand = T.tune(ctx, geo, w["m"], w["p"], nc, w["kappa"], q=w["q"], precision=prec,
+                            eta_adm=w["eta_adm"], leaf_depths=(2, 3, 4), on_the_fly=(False,), reps=5)
+        tuned[label] = {"choice_leaf_depth": best.leaf_depth,
+                        "candidates": [{"leaf_depth": c.leaf_depth, "matvec_ms": c.matvec_ms,
+                                        "assembly_ms": c.assembly_ms, "device_bytes": c.device_bytes}
+                                       for c in cand]}
+    torch.cuda.empty_cache()
     # the same solves with the coupling tiles recompressed (cross approximation, 1e-8 relative)
     op_lr = B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"], kcap=w["kcap"],
                        leaf_depth=w["leaf_depth"], recompress_tol=1e-8)
@@ -468,6 +481,7 @@ def main():
                    "note": "same solves with the matvec captured into HIP graphs (igb_op_use_graphs)"},
         "paper_mode": paper_mode,
         "recompressed": recompressed,
+        "autotune": tuned,
         "gmres_iters": iters[-1],
         "relres_true": relres_true,
         "matvec_only_per_s": 1.0 / t_mv,
