@@ -104,7 +104,8 @@ typedef enum {
  *              accumulation on the matrix cores, outer residual in fp64) and
  *              h2_matvec uses with IGB_MV_LOWPREC; Arnoldi and residuals stay fp64,
  *              and so does the near field, except that IGB_MIX_BF16 keeps an fp32 copy
- *              that IGB_MV_LOWPREC products use (fp32 columns, products and row sums)
+ *              that IGB_MV_LOWPREC products use (fp32 columns, products and row sums,
+ *              on the matrix cores in tiles of rows over a common column list)
  *   far_on_the_fly  0: the fp64 couplings are stored ((q+1)^4 complex per far pair,
  *              two for IGB_HARD); 1: none are stored and every fp64 far-field
  *              product (fp64 matvecs, refinement residuals) evaluates the kernel at

@@ -261,7 +261,9 @@ static igb_status build_one(igb_ctx ctx, igb_geom g, const igb_op_params* prm, c
         need += size_t(op->nclusters) * (ntile == 2 ? 7 : 1) * 16 * kbp * 16 +
                 op->chunks_mfma.len.size() * (ntile == 2 ? 10 : 1) * op->nq * 16;
     }
-    if (prm->precision == IGB_MIX_BF16) need += size_t(op->nnz) * 8 + size_t(op->N) * 8;   // fp32 near field
+    if (prm->precision == IGB_MIX_BF16)   // fp32 near field in tiles, fp32 columns
+        need += size_t(op->near_tile_vals) * 8 + op->near_tiles.size() * sizeof(NearTile) +
+                op->near_tile_cols.size() * 4 + size_t(op->N) * 8 * 16;
     if (prm->precision != IGB_FP64) {
         // rounded tiles (rows padded to 16 bytes) and, per 16 columns, the rounded
         // source vectors and fp32 partials of the matrix-core coupling

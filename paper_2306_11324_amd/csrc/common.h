@@ -120,6 +120,21 @@ struct M2LChunks {
     igb::DevBuf d_tgt, d_pair, d_len, d_tgt_ptr;
 };
 
+// Near rows whose supports lie in the same leaves have the same column list.
+// Up to 16 rows of such groups form a tile over the union of their column
+// lists; its values are stored [k block][row][8] (zeros where a row lacks a
+// column and past the list's end, padded to a multiple of 8), the A operand
+// of the matrix-core near product.
+constexpr int NEAR_TILE_ROWS = 16;
+constexpr int NEAR_TILE_K = 8;
+constexpr double NEAR_TILE_FILL = 0.35;   // union at most 35% longer than the longest member list
+struct NearTile {
+    int64_t val_off;   // first complex entry of the tile in the tile layout
+    int64_t col_off;   // first entry of the tile's column list (sorted)
+    int ncols, nrows;
+    int rows[NEAR_TILE_ROWS];
+};
+
 struct igb_op_s {
     igb_geom geom = nullptr;
     igb_op_params prm{};
@@ -149,6 +164,10 @@ struct igb_op_s {
     std::vector<int64_t> row_ptr;
     std::vector<int> col;
     int64_t nnz = 0;
+    // bf16 operators: the near rows in tiles of up to 16 rows over a common column list
+    std::vector<NearTile> near_tiles;
+    std::vector<int> near_tile_cols;  // the tiles' column lists
+    int64_t near_tile_vals = 0;       // complex entries of the tile layout
     // M2L work decompositions (vector path, matrix-core path)
     M2LChunks chunks, chunks_mfma;
     // device data
@@ -160,7 +179,7 @@ struct igb_op_s {
     igb::DevBuf d_rowptr, d_col, d_val;
     // bf16 operators: fp32 near-field values and fp32 copies of the columns for the
     // near product of the inner (refinement) matvecs
-    igb::DevBuf d_val_lo, d_xnear_lo;
+    igb::DevBuf d_val_lo, d_xnear_lo, d_near_tiles, d_near_tile_cols;
     igb::DevBuf d_near_ptr, d_near_src;
     igb::DevBuf d_s2_to_s0, d_s0_ptr, d_s0_reps;
     igb::DevBuf d_far_src;

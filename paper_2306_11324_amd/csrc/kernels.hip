@@ -1809,9 +1809,6 @@ __global__ void m2l_reduce(const PT* part, const int* tgt_chunk_ptr, int64_t ncl
     yh[gid] = s;
 }
 
-constexpr int SPMV_LO_RB = 8;   // columns per pass of the fp32 near product (4: 0.131 ms, 8: 0.119, 16: 0.156
-                                // for 16 columns on the m = 5 sphere)
-
 // y[r][row] = sum_j val x[r][col] (+ far part mapped to the solution space); one
 // wave per row, lanes stride over the row, butterfly reduction (fixed order)
 // (RB columns per pass; consecutive nonzeros of a row mostly have consecutive
@@ -1870,68 +1867,144 @@ __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ 
     }
 }
 
-// out[i] = in[i] rounded to fp32 (RNE)
-__global__ void round_values(const double2* __restrict__ in, float2* __restrict__ out, int64_t n) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = make_float2(float(in[i].x), float(in[i].y));
+// fp32 tile layout of the near field: tile t holds its rows' values as
+// [k block][row][8] over the tile's column list (zero where the row has no
+// entry and past the list's end), rounded (RNE) from the fp64 CSR values.
+// One thread per row walks the tile's list and the row's (both sorted; the
+// tile's list holds the row's).
+__global__ void near_tile_values(const NearTile* __restrict__ tiles, const int* __restrict__ tcol,
+                                 const int64_t* __restrict__ row_ptr, const int* __restrict__ col,
+                                 const double2* __restrict__ val, float2* __restrict__ vt) {
+    const NearTile& T = tiles[blockIdx.x];
+    const int i = threadIdx.x;
+    if (i >= T.nrows) return;
+    const int nr = T.nrows, nc = T.ncols;
+    const int* tc = tcol + T.col_off;
+    const int r = T.rows[i];
+    int64_t q = row_ptr[r];
+    const int64_t qe = row_ptr[r + 1];
+    const int nk = (nc + NEAR_TILE_K - 1) / NEAR_TILE_K * NEAR_TILE_K;
+    for (int k = 0; k < nk; ++k) {
+        float2 v = make_float2(0.f, 0.f);
+        if (k < nc && q < qe && col[q] == tc[k]) {
+            const double2 d = val[q++];
+            v = make_float2(float(d.x), float(d.y));
+        }
+        vt[T.val_off + (int64_t(k / NEAR_TILE_K) * nr + i) * NEAR_TILE_K + k % NEAR_TILE_K] = v;
+    }
 }
 
-// spmv_combine for the reduced-precision operator of the inner solves: fp32
-// values and fp32 columns, fp32 products and sums over the row (same lane
-// order for every column count), far part added and stored in fp64.
-template <int RB>
-__global__ __launch_bounds__(256) void spmv_combine_lo(const int64_t* __restrict__ row_ptr,
-                                                       const int* __restrict__ col,
-                                                       const float2* __restrict__ val,
-                                                       const float2* __restrict__ x, int64_t nrows,
+// x^T for the tile product: xt[b][row][16] = x[16 b + c][row] rounded to fp32
+// (zero for columns past ncol)
+__global__ void round_columns_t(const double2* __restrict__ x, int64_t nrows, int ncol, int ncb,
+                                float2* __restrict__ xt) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= int64_t(ncb) * nrows * 16) return;
+    const int c = int(i / (nrows * 16)) * 16 + int(i % 16);
+    const int64_t row = (i / 16) % nrows;
+    float2 v = make_float2(0.f, 0.f);
+    if (c < ncol) {
+        const double2 d = x[int64_t(c) * nrows + row];
+        v = make_float2(float(d.x), float(d.y));
+    }
+    xt[i] = v;
+}
+
+// Near product of the reduced-precision operator (inner matvecs of the bf16
+// refinement) on the matrix cores: for one tile of rows and 16 columns,
+// Y = V X with the tile values V over the tile's column list (rows past nrows
+// are zero) as the A operand and the fp32 columns gathered by that list as
+// the B operand, fp32 products and sums.  The 16 waves take every 16th k
+// block of 8 columns and meet in LDS in wave order (fixed); the far part is
+// added and stored in fp64.  Each output column depends only on its own input column,
+// in an order fixed by the tile, so blocks of any width give bitwise the
+// results of one column at a time.
+constexpr int NEAR_TILE_CHUNK = 2048;   // column indices staged in LDS at a time (multiple of 32)
+constexpr int NEAR_TILE_WAVES = 16;
+__global__ __launch_bounds__(64 * NEAR_TILE_WAVES) void near_tiles_mfma(const NearTile* __restrict__ tiles, int64_t ntile,
+                                                       const int* __restrict__ tcol, const float2* __restrict__ vt,
+                                                       const float2* __restrict__ xt, int64_t nrows,
                                                        const double2* __restrict__ yfar, int64_t n2,
                                                        const int* __restrict__ s0_ptr,
                                                        const int* __restrict__ s0_reps, int use_near, int ncol,
                                                        double2* __restrict__ y) {
-    const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-    if (row >= nrows) return;
-    const int64_t b = row_ptr[row], e = row_ptr[row + 1];
-    for (int c0 = 0; c0 < ncol; c0 += RB) {
-        float2 acc[RB];
-#pragma unroll
-        for (int cb = 0; cb < RB; ++cb) acc[cb] = make_float2(0.f, 0.f);
-        if (use_near) {
-            for (int64_t idx = b + lane; idx < e; idx += 64) {
-                const float2 v = val[idx];
-                const int64_t cc = col[idx];
-#pragma unroll
-                for (int cb = 0; cb < RB; ++cb)
-                    if (c0 + cb < ncol) {
-                        const float2 xv = x[int64_t(c0 + cb) * nrows + cc];
-                        acc[cb].x = fmaf(v.x, xv.x, fmaf(-v.y, xv.y, acc[cb].x));
-                        acc[cb].y = fmaf(v.x, xv.y, fmaf(v.y, xv.x, acc[cb].y));
-                    }
+    constexpr int NW = NEAR_TILE_WAVES;
+    __shared__ f32x4 red[NW - 1][2][64];
+    __shared__ int cidx[NEAR_TILE_CHUNK];
+    const int64_t t = xcd_chunk(blockIdx.x, ntile);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    const NearTile& T = tiles[t];
+    const int nr = T.nrows, nc = T.ncols;
+    const int nkb = (nc + NEAR_TILE_K - 1) / NEAR_TILE_K;
+    const float2* xb = xt + int64_t(blockIdx.y) * nrows * 16 + li;
+    const int* cl = tcol + T.col_off;
+    const float2* va = vt + T.val_off + li * NEAR_TILE_K + 2 * g;
+    const int64_t kbstride = int64_t(nr) * NEAR_TILE_K;
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    auto load = [&](int kb, int kl, uint4& A, uint4& X) {
+        A = make_uint4(0u, 0u, 0u, 0u);
+        if (li < nr) A = *reinterpret_cast<const uint4*>(va + kb * kbstride);
+        const float2 xa = xb[int64_t(cidx[kl + 2 * g]) * 16];
+        const float2 xc = xb[int64_t(cidx[kl + 2 * g + 1]) * 16];
+        X = make_uint4(__float_as_uint(xa.x), __float_as_uint(xa.y), __float_as_uint(xc.x), __float_as_uint(xc.y));
+    };
+    auto compute = [&](const uint4& A, const uint4& X) {
+        acc0 = MfmaF32::step(A, MfmaF32::re_part(X), acc0);
+        acc1 = MfmaF32::step(A, MfmaF32::im_part(X), acc1);
+    };
+    if (use_near) {
+        // chunks of columns: indices to LDS (columns past the list repeat its last
+        // one; their values are zero), then each wave's k blocks kb = wave mod 16
+        // in increasing order, two loads in flight (16 waves per tile: a few
+        // hundred tiles must keep the chip's loads in flight)
+        for (int k0 = 0; k0 < nkb * NEAR_TILE_K; k0 += NEAR_TILE_CHUNK) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < NEAR_TILE_CHUNK; i += blockDim.x) cidx[i] = cl[min(k0 + i, nc - 1)];
+            __syncthreads();
+            const int kb0 = k0 / NEAR_TILE_K, kb1 = min(nkb, kb0 + NEAR_TILE_CHUNK / NEAR_TILE_K);
+            int kb = kb0 + wave;
+            for (; kb + NW < kb1; kb += 2 * NW) {
+                uint4 A0, X0, A1, X1;
+                load(kb, (kb - kb0) * NEAR_TILE_K, A0, X0);
+                load(kb + NW, (kb + NW - kb0) * NEAR_TILE_K, A1, X1);
+                compute(A0, X0);
+                compute(A1, X1);
+            }
+            if (kb < kb1) {
+                uint4 A0, X0;
+                load(kb, (kb - kb0) * NEAR_TILE_K, A0, X0);
+                compute(A0, X0);
             }
         }
+    }
+    if (wave > 0) {
+        red[wave - 1][0][lane] = acc0;
+        red[wave - 1][1][lane] = acc1;
+    }
+    __syncthreads();
+    if (wave > 0) return;
 #pragma unroll
-        for (int cb = 0; cb < RB; ++cb)
+    for (int w = 0; w < NW - 1; ++w) {
+        acc0 += red[w][0][lane];
+        acc1 += red[w][1][lane];
+    }
+    const int c = blockIdx.y * 16 + li;
+    if (c >= ncol) return;
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                acc[cb].x += __shfl_xor(acc[cb].x, off, 64);
-                acc[cb].y += __shfl_xor(acc[cb].y, off, 64);
-            }
-        if (lane == 0) {
-#pragma unroll
-            for (int cb = 0; cb < RB; ++cb) {
-                const int r = c0 + cb;
-                if (r >= ncol) continue;
-                double2 a = make_double2(double(acc[cb].x), double(acc[cb].y));
-                if (yfar) {
-                    if (s0_ptr) {
-                        for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q) a = cadd(a, yfar[r * n2 + s0_reps[q]]);
-                    } else {
-                        a = cadd(a, yfar[r * n2 + row]);
-                    }
-                }
-                y[int64_t(r) * nrows + row] = a;
+    for (int r = 0; r < 4; ++r) {
+        const int i = MfmaF32::orow(g, r);
+        if (i >= nr) continue;
+        const int row = T.rows[i];
+        double2 a = make_double2(double(acc0[r]), double(acc1[r]));
+        if (yfar) {
+            if (s0_ptr) {
+                for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q) a = cadd(a, yfar[int64_t(c) * n2 + s0_reps[q]]);
+            } else {
+                a = cadd(a, yfar[int64_t(c) * n2 + row]);
             }
         }
+        y[int64_t(c) * nrows + row] = a;
     }
 }
 
@@ -2594,10 +2667,15 @@ igb_status assemble_near_device(igb_op op, hipStream_t s) {
     if (!st && op->prm.precision == IGB_MIX_BF16 && op->nnz > 0) {
         // fp32 copy of the near field for the inner matvecs of the bf16 refinement (whose
         // inner solves stop at 1e-3; the fp32 operator's inner solves aim at the full
-        // tolerance, below what fp32 columns allow, and keep the fp64 near product)
-        if ((st = alloc(op->d_val_lo, op->nnz * sizeof(float2), acct))) return st;
-        hipLaunchKernelGGL(round_values, dim3(unsigned((op->nnz + 255) / 256)), dim3(256), 0, s, op->d_val.as<double2>(),
-                           op->d_val_lo.as<float2>(), op->nnz);
+        // tolerance, below what fp32 columns allow, and keep the fp64 near product),
+        // in the tile layout of the matrix-core near product
+        const int64_t nt = int64_t(op->near_tiles.size());
+        if ((st = upload(op->d_near_tiles, op->near_tiles.data(), op->near_tiles.size(), acct))) return st;
+        if ((st = upload(op->d_near_tile_cols, op->near_tile_cols.data(), op->near_tile_cols.size(), acct))) return st;
+        if ((st = alloc(op->d_val_lo, size_t(op->near_tile_vals) * sizeof(float2), acct))) return st;
+        hipLaunchKernelGGL(near_tile_values, dim3(unsigned(nt)), dim3(64), 0, s, op->d_near_tiles.as<NearTile>(),
+                           op->d_near_tile_cols.as<int>(), op->d_rowptr.as<int64_t>(), op->d_col.as<int>(),
+                           op->d_val.as<double2>(), op->d_val_lo.as<float2>());
         IGB_HIP(hipGetLastError());
         IGB_HIP(hipStreamSynchronize(s));
     }
@@ -2810,7 +2888,7 @@ igb_status alloc_work(igb_op op, int ncol) {
     }
     if (op->d_val_lo.ptr) {
         *acct -= std::min(*acct, op->d_xnear_lo.bytes);
-        if ((st = alloc(op->d_xnear_lo, C * op->N * sizeof(float2), acct))) return st;
+        if ((st = alloc(op->d_xnear_lo, (C + 15) / 16 * 16 * op->N * sizeof(float2), acct))) return st;
     }
     if ((st = alloc(op->d_yfar, C * op->geom->n2 * sizeof(double2), acct))) return st;
     if ((st = alloc(op->d_x2, C * op->geom->n2 * sizeof(double2), acct))) return st;
@@ -3129,16 +3207,16 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
     const int* cl = op->d_col.as<int>();
     const double2* vl = op->d_val.as<double2>();
     if (low && op->d_val_lo.ptr) {
-        const float2* vlo = op->d_val_lo.as<float2>();
-        float2* xlo = op->d_xnear_lo.as<float2>();
+        const int ncb = (ncol + 15) / 16;
+        float2* xt = op->d_xnear_lo.as<float2>();
         if (use_near)
-            hipLaunchKernelGGL(round_values, dim3(blocks_for(N * ncol, 256)), dim3(256), 0, s, X, xlo, N * ncol);
-        if (ncol == 1)
-            hipLaunchKernelGGL(spmv_combine_lo<1>, sg, sb, 0, s, rp, cl, vlo, xlo, N, yfar, g->n2, s0p, s0r, use_near,
-                               ncol, Y);
-        else
-            hipLaunchKernelGGL(spmv_combine_lo<SPMV_LO_RB>, sg, sb, 0, s, rp, cl, vlo, xlo, N, yfar, g->n2, s0p, s0r,
-                               use_near, ncol, Y);
+            hipLaunchKernelGGL(round_columns_t, dim3(blocks_for(int64_t(ncb) * N * 16, 256)), dim3(256), 0, s, X, N,
+                               ncol, ncb, xt);
+        hipLaunchKernelGGL(near_tiles_mfma, dim3(unsigned(op->near_tiles.size()), unsigned(ncb)),
+                           dim3(64 * NEAR_TILE_WAVES), 0, s,
+                           op->d_near_tiles.as<NearTile>(), int64_t(op->near_tiles.size()),
+                           op->d_near_tile_cols.as<int>(),
+                           op->d_val_lo.as<float2>(), xt, N, yfar, g->n2, s0p, s0r, use_near, ncol, Y);
     } else if (ncol == 1) {
         hipLaunchKernelGGL(spmv_combine<1>, sg, sb, 0, s, rp, cl, vl, X, N, yfar, g->n2, s0p, s0r, use_near, ncol, Y);
     } else {

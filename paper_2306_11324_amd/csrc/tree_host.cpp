@@ -3,6 +3,7 @@
 // pattern of the near-field matrix.
 #include <algorithm>
 #include <cmath>
+#include <map>
 
 #include "common.h"
 
@@ -410,6 +411,65 @@ igb_status near_pattern(igb_op op) {
         }
         std::copy(src->begin(), src->end(), op->col.begin() + op->row_ptr[r]);
     });
+
+    // bf16 operators: rows with the same leaves (hence the same column list) form
+    // groups, taken in order of their first row; up to 16 rows of neighbouring
+    // groups share a tile whose columns are the union of theirs, as long as the
+    // union stays within NEAR_TILE_FILL of the longest member list (the rows'
+    // missing columns are stored as zeros; fewer, fuller tiles gather x less often)
+    op->near_tiles.clear();
+    op->near_tile_cols.clear();
+    op->near_tile_vals = 0;
+    if (op->prm.precision == IGB_MIX_BF16) {
+        std::map<std::vector<int>, std::vector<int>> groups;
+        std::vector<int> leaves;
+        for (int64_t r = 0; r < N; ++r) {
+            row_leaves(r, leaves);
+            groups[leaves].push_back(int(r));
+        }
+        std::vector<const std::vector<int>*> order;
+        for (const auto& kv : groups) order.push_back(&kv.second);
+        std::sort(order.begin(), order.end(),
+                  [](const std::vector<int>* a, const std::vector<int>* b) { return a->front() < b->front(); });
+        std::vector<int> rows, cols, tmp;
+        size_t longest = 0;
+        auto emit = [&]() {
+            if (rows.empty()) return;
+            NearTile t{};
+            t.val_off = op->near_tile_vals;
+            t.col_off = int64_t(op->near_tile_cols.size());
+            t.ncols = int(cols.size());
+            t.nrows = int(rows.size());
+            for (int i = 0; i < NEAR_TILE_ROWS; ++i) t.rows[i] = i < t.nrows ? rows[i] : -1;
+            op->near_tile_cols.insert(op->near_tile_cols.end(), cols.begin(), cols.end());
+            op->near_tile_vals += int64_t((t.ncols + NEAR_TILE_K - 1) / NEAR_TILE_K) * t.nrows * NEAR_TILE_K;
+            op->near_tiles.push_back(t);
+            rows.clear();
+            cols.clear();
+            longest = 0;
+        };
+        for (const std::vector<int>* g : order) {
+            const int* c0 = op->col.data() + op->row_ptr[g->front()];
+            const size_t nc = size_t(op->row_ptr[g->front() + 1] - op->row_ptr[g->front()]);
+            for (size_t i0 = 0; i0 < g->size(); i0 += NEAR_TILE_ROWS) {
+                const size_t nr = std::min<size_t>(NEAR_TILE_ROWS, g->size() - i0);
+                if (!rows.empty()) {
+                    tmp.resize(cols.size() + nc);
+                    tmp.resize(std::set_union(cols.begin(), cols.end(), c0, c0 + nc, tmp.begin()) - tmp.begin());
+                    const size_t lim = size_t(double(std::max(longest, nc)) * (1.0 + NEAR_TILE_FILL));
+                    if (rows.size() + nr <= size_t(NEAR_TILE_ROWS) && tmp.size() <= lim) {
+                        cols.swap(tmp);
+                    } else {
+                        emit();
+                    }
+                }
+                if (rows.empty()) cols.assign(c0, c0 + nc);
+                rows.insert(rows.end(), g->begin() + i0, g->begin() + i0 + nr);
+                longest = std::max(longest, nc);
+            }
+        }
+        emit();
+    }
     return IGB_OK;
 }
 
