@@ -171,7 +171,7 @@ struct igb_op_s {
     // M2L work decompositions (vector path, matrix-core path)
     M2LChunks chunks, chunks_mfma;
     // device data
-    igb::DevBuf d_coupling, d_coupling_lo, d_nodes, d_m1, d_T;
+    igb::DevBuf d_coupling, d_coupling_lo, d_nodes, d_m1, d_T, d_Tc;
     // recompressed couplings (far_recompress_tol > 0): per far pair the rank, the offset of
     // its factors (complex entries) and the factors u_k [k][nq], v_k^T [nq][rank]
     igb::DevBuf d_lr, d_lr_rank, d_lr_off;

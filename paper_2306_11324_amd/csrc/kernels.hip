@@ -775,80 +775,74 @@ __global__ __launch_bounds__(TREE_THREADS) void m2m_wg(const double* __restrict_
     }
 }
 
-// downward, one workgroup per (parent at level l, column block):
-//   y^_c[gv][gu] += sum_av Tv_c[gv][av] sum_au Tu_c[gu][au] y^_P[av][au]
-__global__ __launch_bounds__(TREE_THREADS) void l2l_wg(const double* __restrict__ T1, int q, int l,
-                                                       int64_t off_l, int64_t off_l1, double2* yh, int ncol) {
-    __shared__ double T[2 * TQ1 * TQ1];
-    __shared__ double2 Y[TNQ * TCB];
-    __shared__ double2 tmp[2 * TNQ * TCB];
-    const int q1 = q + 1, nq = q1 * q1, tid = threadIdx.x;
-    const int64_t c = blockIdx.x;
-    const int c0 = blockIdx.y * TCB;
-    const int n = 1 << l;
-    const int patch = int(c / (int64_t(n) * n));
-    const int rem = int(c % (int64_t(n) * n));
-    const int cy = rem / n, cx = rem % n;
-    for (int i = tid; i < 2 * q1 * q1; i += TREE_THREADS) T[i] = T1[i];
-    for (int i = tid; i < nq * TCB; i += TREE_THREADS) {
-        const int cb = i % TCB, a = i / TCB;
-        Y[i] = c0 + cb < ncol ? yh[((off_l + c) * nq + a) * ncol + c0 + cb] : make_double2(0, 0);
-    }
-    __syncthreads();
-    // tmp[bv][gv][au] = sum_av Tv[bv][gv][av] Y[av][au]
-    for (int i = tid; i < 2 * nq * TCB; i += TREE_THREADS) {
-        const int cb = i % TCB, t = i / TCB, bv = t / nq, r = t % nq, gv = r / q1, au = r % q1;
-        const double* Tv = T + bv * q1 * q1;
-        double2 acc = make_double2(0, 0);
-        for (int av = 0; av < q1; ++av) {
-            const double tt = Tv[gv * q1 + av];
-            const double2 v = Y[(av * q1 + au) * TCB + cb];
-            acc.x = fma(tt, v.x, acc.x);
-            acc.y = fma(tt, v.y, acc.y);
-        }
-        tmp[i] = acc;
-    }
-    __syncthreads();
-    for (int i = tid; i < 4 * nq * TCB; i += TREE_THREADS) {
-        const int cb = i % TCB, t = i / TCB, ch = t / nq, g = t % nq, gv = g / q1, gu = g % q1, bu = ch & 1,
-                  bv = ch >> 1;
-        if (c0 + cb >= ncol) continue;
-        const double* Tu = T + bu * q1 * q1;
-        double2 acc = make_double2(0, 0);
-        for (int au = 0; au < q1; ++au) {
-            const double tt = Tu[gu * q1 + au];
-            const double2 v = tmp[((bv * nq) + gv * q1 + au) * TCB + cb];
-            acc.x = fma(tt, v.x, acc.x);
-            acc.y = fma(tt, v.y, acc.y);
-        }
-        const int64_t child = off_l1 + (int64_t(patch) << (2 * (l + 1))) + (int64_t(2 * cy + bv) << (l + 1)) +
-                              2 * cx + bu;
-        double2* dst = yh + (child * nq + g) * ncol + c0 + cb;
-        *dst = cadd(*dst, acc);
-    }
-}
+constexpr int WMAX = 64 + PMAX;   // widest leaf window (s + p)
 
-// back projection, one workgroup per (leaf, column):
+// downward pass and back projection in one launch, one workgroup per (leaf,
+// column): the leaf's local expansion collects every ancestor's,
+//   y^_leaf += (Tv ⊗ Tu)_(delta, pos) y^_A   for the ancestors A, nearest first,
+// with the composite transfers Tc[delta][pos][g][a] = L_a((pos + t_g) / 2^delta)
+// (the ancestor's Lagrange basis at the leaf's nodes, delta levels down at
+// offset pos; interpolating a degree-q expansion again at finer nodes is
+// exact, so this equals the level-by-level pass), then is back projected
+// onto the leaf's (s+p)^2 window:
 //   out[lv][lu] = sum_av m_v[av][lv] sum_au m_u[au][lu] y^[av][au]
-// over the leaf's (s+p)^2 window, written to the per-leaf buffer
-constexpr int WMAX = 64 + PMAX;
-__global__ __launch_bounds__(TREE_THREADS) void back_project_leaf(const double2* __restrict__ yh,
+__global__ __launch_bounds__(TREE_THREADS) void down_project_leaf(const double2* __restrict__ yh,
+                                                                  const double* __restrict__ Tc,
+                                                                  const int64_t* __restrict__ clu_off,
                                                                   const double* __restrict__ m1, int q, int w,
-                                                                  int L, int64_t leaf_off, int deriv_u,
-                                                                  int deriv_v, int64_t m1_stride_kind, int ncol,
+                                                                  int L, int deriv_u, int deriv_v,
+                                                                  int64_t m1_stride_kind, int ncol,
                                                                   double2* __restrict__ leafbuf) {
-    __shared__ double2 Y[TNQ];
-    __shared__ double2 tmp[TQ1 * WMAX];
+    __shared__ double2 Y[TNQ], YA[TNQ], tmp[TNQ];
+    __shared__ double Mu[TQ1 * TQ1], Mv[TQ1 * TQ1];
+    __shared__ double2 tb[TQ1 * WMAX];
     const int q1 = q + 1, nq = q1 * q1, tid = threadIdx.x;
     const int64_t c = blockIdx.x;
     const int r = blockIdx.y;
     const int n = 1 << L;
+    const int patch = int(c / (int64_t(n) * n));
     const int rem = int(c % (int64_t(n) * n));
     const int cy = rem / n, cx = rem % n;
+    for (int i = tid; i < nq; i += TREE_THREADS) Y[i] = yh[((clu_off[L] + c) * nq + i) * ncol + r];
+    for (int l = L - 1; l >= 0; --l) {
+        const int dl = L - l, msk = (1 << dl) - 1;
+        const int64_t A = clu_off[l] + (int64_t(patch) << (2 * l)) + (int64_t(cy >> dl) << l) + (cx >> dl);
+        const double* Tu = Tc + int64_t((1 << dl) - 2 + (cx & msk)) * q1 * q1;
+        const double* Tv = Tc + int64_t((1 << dl) - 2 + (cy & msk)) * q1 * q1;
+        __syncthreads();   // previous ancestor's YA / tmp consumed
+        for (int i = tid; i < nq; i += TREE_THREADS) {
+            YA[i] = yh[(A * nq + i) * ncol + r];
+            Mu[i] = Tu[i];
+            Mv[i] = Tv[i];
+        }
+        __syncthreads();
+        // tmp[av][gu] = sum_au Tu[gu][au] y^_A[av][au]
+        for (int i = tid; i < nq; i += TREE_THREADS) {
+            const int av = i / q1, gu = i % q1;
+            double2 acc = make_double2(0, 0);
+            for (int au = 0; au < q1; ++au) {
+                const double t = Mu[gu * q1 + au];
+                acc.x = fma(t, YA[av * q1 + au].x, acc.x);
+                acc.y = fma(t, YA[av * q1 + au].y, acc.y);
+            }
+            tmp[i] = acc;
+        }
+        __syncthreads();
+        // y^[gv][gu] += sum_av Tv[gv][av] tmp[av][gu]
+        for (int i = tid; i < nq; i += TREE_THREADS) {
+            const int gv = i / q1, gu = i % q1;
+            double2 acc = make_double2(0, 0);
+            for (int av = 0; av < q1; ++av) {
+                const double t = Mv[gv * q1 + av];
+                acc.x = fma(t, tmp[av * q1 + gu].x, acc.x);
+                acc.y = fma(t, tmp[av * q1 + gu].y, acc.y);
+            }
+            Y[i] = cadd(Y[i], acc);
+        }
+    }
+    __syncthreads();
     const double* mu = m1 + deriv_u * m1_stride_kind + int64_t(cx) * q1 * w;
     const double* mv = m1 + deriv_v * m1_stride_kind + int64_t(cy) * q1 * w;
-    for (int i = tid; i < nq; i += TREE_THREADS) Y[i] = yh[((leaf_off + c) * nq + i) * ncol + r];
-    __syncthreads();
     for (int i = tid; i < q1 * w; i += TREE_THREADS) {
         const int av = i / w, lu = i % w;
         double2 acc = make_double2(0, 0);
@@ -857,7 +851,7 @@ __global__ __launch_bounds__(TREE_THREADS) void back_project_leaf(const double2*
             acc.x = fma(t, Y[av * q1 + au].x, acc.x);
             acc.y = fma(t, Y[av * q1 + au].y, acc.y);
         }
-        tmp[i] = acc;
+        tb[i] = acc;
     }
     __syncthreads();
     for (int i = tid; i < w * w; i += TREE_THREADS) {
@@ -865,8 +859,8 @@ __global__ __launch_bounds__(TREE_THREADS) void back_project_leaf(const double2*
         double2 acc = make_double2(0, 0);
         for (int av = 0; av < q1; ++av) {
             const double t = mv[av * w + lv];
-            acc.x = fma(t, tmp[av * w + lu].x, acc.x);
-            acc.y = fma(t, tmp[av * w + lu].y, acc.y);
+            acc.x = fma(t, tb[av * w + lu].x, acc.x);
+            acc.y = fma(t, tb[av * w + lu].y, acc.y);
         }
         leafbuf[(c * ncol + r) * w * w + i] = acc;
     }
@@ -2746,6 +2740,18 @@ igb_status assemble_far_device(igb_op op, hipStream_t s) {
             }
     }
     if ((st = upload(op->d_T, T1.data(), T1.size(), acct))) return st;
+    {
+        // composite downward transfers: delta = 1..L levels down at offset pos,
+        // Tc[2^delta - 2 + pos][g][a] = L_a((pos + t_g) / 2^delta)
+        std::vector<double> Tc(size_t((int64_t(2) << L) - 2) * q1 * q1 + 1);
+        for (int dl = 1; dl <= L; ++dl)
+            for (int pos = 0; pos < (1 << dl); ++pos)
+                for (int gg = 0; gg < q1; ++gg)
+                    for (int a = 0; a < q1; ++a)
+                        Tc[((int64_t((1 << dl) - 2 + pos) * q1 + gg) * q1 + a)] =
+                            lag(a, (pos + t[gg]) / double(1 << dl));
+        if ((st = upload(op->d_Tc, Tc.data(), Tc.size(), acct))) return st;
+    }
     if ((st = upload(op->d_m1, m1.data(), m1.size(), acct))) return st;
     DevBuf d_t, d_cluoff;
     if ((st = upload(d_t, t.data(), t.size(), nullptr))) return st;
@@ -3182,16 +3188,11 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
                                op->d_yraw.as<double2>(), op->d_nodes.as<double>(), op->nclusters, nq, op->kappa,
                                op->hmix, ks, ncol, yh);
         const int w = (1 << op->d) + g->p;
-        for (int kd = 0; kd < kinds; ++kd) {
-            for (int l = 0; l < L; ++l) {
-                const int64_t nc = clusters_on_level(g->npatch, l);
-                hipLaunchKernelGGL(l2l_wg, dim3(unsigned(nc), cblk), dim3(TREE_THREADS), 0, s, op->d_T.as<double>(), q,
-                                   l, op->clu_off[l], op->clu_off[l + 1], yh + kd * ks, ncol);
-            }
-            hipLaunchKernelGGL(back_project_leaf, dim3(unsigned(nleaf), unsigned(ncol)), dim3(TREE_THREADS), 0, s,
-                               yh + kd * ks, op->d_m1.as<double>(), q, w, L, op->clu_off[L], du[kd], dv[kd],
-                               stride_kind, ncol, op->d_leafbuf.as<double2>() + kd * nleaf * ncol * w * w);
-        }
+        for (int kd = 0; kd < kinds; ++kd)
+            hipLaunchKernelGGL(down_project_leaf, dim3(unsigned(nleaf), unsigned(ncol)), dim3(TREE_THREADS), 0, s,
+                               yh + kd * ks, op->d_Tc.as<double>(), op->d_cluoff.as<int64_t>(),
+                               op->d_m1.as<double>(), q, w, L, du[kd], dv[kd], stride_kind, ncol,
+                               op->d_leafbuf.as<double2>() + kd * nleaf * ncol * w * w);
         hipLaunchKernelGGL(leaf_gather, dim3(blocks_for(g->n2 * ncol, 256)), dim3(256), 0, s,
                            op->d_leafbuf.as<double2>(), op->d, g->p, L, g->k, g->npatch, kinds, ncol,
                            op->d_yfar.as<double2>());
