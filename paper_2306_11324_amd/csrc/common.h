@@ -221,7 +221,10 @@ struct igb_op_s {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
         graphs.clear();
     }
+    void* h_pin = nullptr;            // pinned host buffer of the GMRES Hessenberg steps
+    size_t h_pin_bytes = 0;
     ~igb_op_s() {
+        if (h_pin) (void)hipHostFree(h_pin);
         clear_graphs();
         for (auto& t : timers)
             for (hipEvent_t e : t.pool) (void)hipEventDestroy(e);

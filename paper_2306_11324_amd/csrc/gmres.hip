@@ -129,6 +129,16 @@ __global__ void cscale_multi(const double2* w, int64_t n, int C, const double* s
     v[gid] = make_double2(w[gid].x * f, w[gid].y * f);
 }
 
+// v[r][i] = w[r][i] / sqrt(nrm2[r]) (0 for a zero column): the next Arnoldi
+// vector, normalised on the device so that no scale factors travel per step
+__global__ void cscale_by_norm(const double2* w, int64_t n, int C, const double* nrm2, double2* v) {
+    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= n * C) return;
+    const double q = nrm2[gid / n];
+    const double f = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+    v[gid] = make_double2(w[gid].x * f, w[gid].y * f);
+}
+
 // r = b - r ; x += d ; zero columns
 __global__ void csub_from_multi(const double2* b, int64_t nc, double2* r) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -152,6 +162,7 @@ struct Work {
     int m, C, nseg;
     double2 *V, *w, *r, *R, *D, *h, *h2, *y, *part;
     double *nrm, *sc;
+    double2* hp;   // pinned host copy of h, h2 and the squared norms
 };
 
 igb_status ensure_work(igb_op op, int m, int C, Work& W) {
@@ -184,11 +195,20 @@ igb_status ensure_work(igb_op op, int m, int C, Work& W) {
     W.r = W.w + int64_t(C) * n;
     W.R = W.r + int64_t(C) * n;
     W.D = W.R + int64_t(C) * n;
+    // h, h2 and the squared norms are contiguous: one copy to the host per Arnoldi step
     W.h = op->d_h.as<double2>();
     W.h2 = W.h + int64_t(m + 2) * C;
-    W.y = W.h2 + int64_t(m + 2) * C;
-    W.nrm = reinterpret_cast<double*>(W.y + int64_t(m + 2) * C);
+    W.nrm = reinterpret_cast<double*>(W.h2 + int64_t(m + 2) * C);
     W.sc = W.nrm + C;
+    W.y = reinterpret_cast<double2*>(W.sc + C);
+    if (op->h_pin_bytes < need_h) {
+        if (op->h_pin) (void)hipHostFree(op->h_pin);
+        op->h_pin = nullptr;
+        op->h_pin_bytes = 0;
+        IGB_HIP(hipHostMalloc(&op->h_pin, need_h, hipHostMallocDefault));
+        op->h_pin_bytes = need_h;
+    }
+    W.hp = static_cast<double2*>(op->h_pin);
     return IGB_OK;
 }
 
@@ -227,7 +247,7 @@ igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, 
     rnorm = bnorm;
     std::vector<std::vector<cplx>> H(C, std::vector<cplx>(size_t(m + 1) * m)), cs(C, std::vector<cplx>(m)),
         sn(C, std::vector<cplx>(m)), g(C, std::vector<cplx>(m + 1));
-    std::vector<double2> hh(size_t(2) * (m + 1) * C), yd;
+    std::vector<double2> yd;
     std::vector<double> sc(C);
     std::vector<int> jc(C);
     auto active = [&](int c) { return !res[c].converged && res[c].iters < maxit[c]; };
@@ -262,19 +282,27 @@ igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, 
             hipLaunchKernelGGL(cdots_seg, dim3(j + 1, Wk.nseg, C), dim3(RT), 0, s, V, n, C, Wk.nseg, w, Wk.part);
             hipLaunchKernelGGL(cdots_fin, dim3(gd), dim3(256), 0, s, Wk.part, j + 1, C, Wk.nseg, Wk.h2);
             hipLaunchKernelGGL(cmaxpy_multi, dim3(gb64), dim3(64), 0, s, V, j + 1, n, C, Wk.h2, w);
+            // ||w||^2 and the next basis vector on the device, then one copy of
+            // the step's Hessenberg entries and norms to the host
+            hipLaunchKernelGGL(cnorm2_multi, dim3(C), dim3(1024), 0, s, w, n, Wk.nrm);
+            hipLaunchKernelGGL(cscale_by_norm, dim3(gb), dim3(256), 0, s, w, n, C, Wk.nrm,
+                               V + int64_t(j + 1) * C * n);
             IGB_HIP(hipGetLastError());
-            IGB_HIP(hipMemcpyAsync(hh.data(), Wk.h, size_t(j + 1) * C * sizeof(double2), hipMemcpyDeviceToHost, s));
-            IGB_HIP(hipMemcpyAsync(hh.data() + size_t(j + 1) * C, Wk.h2, size_t(j + 1) * C * sizeof(double2),
-                                   hipMemcpyDeviceToHost, s));
-            if ((st = norms(w, n, C, Wk.nrm, hn, s))) return st;   // synchronises
+            const size_t hcopy = size_t(2) * (m + 2) * C * sizeof(double2) + size_t(C) * sizeof(double);
+            IGB_HIP(hipMemcpyAsync(Wk.hp, Wk.h, hcopy, hipMemcpyDeviceToHost, s));
+            IGB_HIP(hipStreamSynchronize(s));
+            const double2* hp1 = Wk.hp;
+            const double2* hp2 = Wk.hp + int64_t(m + 2) * C;
+            const double* hpn = reinterpret_cast<const double*>(Wk.hp + int64_t(2) * (m + 2) * C);
+            hn.resize(C);
+            for (int c = 0; c < C; ++c) hn[c] = std::sqrt(hpn[c]);
             for (int c = 0; c < C; ++c) {
-                sc[c] = 0.0;
                 if (!(in_cycle[c] && jc[c] == j && active(c))) continue;
                 ++res[c].iters;
                 ++res[c].applications;
                 std::vector<cplx>& Hc = H[c];
                 for (int i = 0; i <= j; ++i) {
-                    const double2 a1 = hh[size_t(i) * C + c], a2 = hh[size_t(j + 1 + i) * C + c];
+                    const double2 a1 = hp1[size_t(i) * C + c], a2 = hp2[size_t(i) * C + c];
                     Hc[size_t(i) * m + j] = cplx(a1.x + a2.x, a1.y + a2.y);
                 }
                 Hc[size_t(j + 1) * m + j] = hn[c];
@@ -301,14 +329,8 @@ igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, 
                 g[c][j] = cs[c][j] * g[c][j];
                 res[c].relres = std::abs(g[c][j + 1]) / bnorm[c];
                 jc[c] = j + 1;
-                if (res[c].relres <= tol[c] || hn[c] == 0) {
-                    res[c].converged = true;
-                } else {
-                    sc[c] = 1.0 / hn[c];
-                }
+                if (res[c].relres <= tol[c] || hn[c] == 0) res[c].converged = true;
             }
-            IGB_HIP(hipMemcpyAsync(Wk.sc, sc.data(), C * sizeof(double), hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(cscale_multi, dim3(gb), dim3(256), 0, s, w, n, C, Wk.sc, V + int64_t(j + 1) * C * n);
         }
         // X += V y per column (zeros beyond a column's own step count)
         int jmax = 0;
