@@ -775,10 +775,8 @@ __global__ __launch_bounds__(TREE_THREADS) void m2m_wg(const double* __restrict_
     }
 }
 
-constexpr int WMAX = 64 + PMAX;   // widest leaf window (s + p)
-
-// downward pass and back projection in one launch, one workgroup per (leaf,
-// column): the leaf's local expansion collects every ancestor's,
+// downward pass and back projection in one launch, one workgroup per leaf and
+// block of columns: the leaf's local expansion collects every ancestor's,
 //   y^_leaf += (Tv ⊗ Tu)_(delta, pos) y^_A   for the ancestors A, nearest first,
 // with the composite transfers Tc[delta][pos][g][a] = L_a((pos + t_g) / 2^delta)
 // (the ancestor's Lagrange basis at the leaf's nodes, delta levels down at
@@ -786,56 +784,65 @@ constexpr int WMAX = 64 + PMAX;   // widest leaf window (s + p)
 // exact, so this equals the level-by-level pass), then is back projected
 // onto the leaf's (s+p)^2 window:
 //   out[lv][lu] = sum_av m_v[av][lv] sum_au m_u[au][lu] y^[av][au]
-__global__ __launch_bounds__(TREE_THREADS) void down_project_leaf(const double2* __restrict__ yh,
-                                                                  const double* __restrict__ Tc,
-                                                                  const int64_t* __restrict__ clu_off,
-                                                                  const double* __restrict__ m1, int q, int w,
-                                                                  int L, int deriv_u, int deriv_v,
-                                                                  int64_t m1_stride_kind, int ncol,
-                                                                  double2* __restrict__ leafbuf) {
-    __shared__ double2 Y[TNQ], YA[TNQ], tmp[TNQ];
+// (cb columns per workgroup share the transfers' loads; each column's
+// operations and their order do not depend on cb.  Dynamic LDS: y^, the
+// ancestor's y^ and the half-transferred values, cb x (q+1)^2 each, then the
+// half-projected values cb x (q+1) x w; node-major, columns fastest.)
+__global__ __launch_bounds__(256) void down_project_leaf(const double2* __restrict__ yh,
+                                                         const double* __restrict__ Tc,
+                                                         const int64_t* __restrict__ clu_off,
+                                                         const double* __restrict__ m1, int q, int w, int L,
+                                                         int deriv_u, int deriv_v, int64_t m1_stride_kind,
+                                                         int ncol, int cb, double2* __restrict__ leafbuf) {
+    extern __shared__ double2 dyn[];
     __shared__ double Mu[TQ1 * TQ1], Mv[TQ1 * TQ1];
-    __shared__ double2 tb[TQ1 * WMAX];
-    const int q1 = q + 1, nq = q1 * q1, tid = threadIdx.x;
+    const int q1 = q + 1, nq = q1 * q1, tid = threadIdx.x, nt = blockDim.x;
     const int64_t c = blockIdx.x;
-    const int r = blockIdx.y;
+    const int r0 = blockIdx.y * cb, nr = min(cb, ncol - r0);
+    double2* Y = dyn;
+    double2* YA = Y + cb * nq;
+    double2* tmp = YA + cb * nq;
+    double2* tb = tmp + cb * nq;
     const int n = 1 << L;
     const int patch = int(c / (int64_t(n) * n));
     const int rem = int(c % (int64_t(n) * n));
     const int cy = rem / n, cx = rem % n;
-    for (int i = tid; i < nq; i += TREE_THREADS) Y[i] = yh[((clu_off[L] + c) * nq + i) * ncol + r];
+    for (int i = tid; i < nq * nr; i += nt)
+        Y[i] = yh[((clu_off[L] + c) * nq + i / nr) * ncol + r0 + i % nr];
     for (int l = L - 1; l >= 0; --l) {
         const int dl = L - l, msk = (1 << dl) - 1;
         const int64_t A = clu_off[l] + (int64_t(patch) << (2 * l)) + (int64_t(cy >> dl) << l) + (cx >> dl);
         const double* Tu = Tc + int64_t((1 << dl) - 2 + (cx & msk)) * q1 * q1;
         const double* Tv = Tc + int64_t((1 << dl) - 2 + (cy & msk)) * q1 * q1;
         __syncthreads();   // previous ancestor's YA / tmp consumed
-        for (int i = tid; i < nq; i += TREE_THREADS) {
-            YA[i] = yh[(A * nq + i) * ncol + r];
+        for (int i = tid; i < nq * nr; i += nt) YA[i] = yh[(A * nq + i / nr) * ncol + r0 + i % nr];
+        for (int i = tid; i < nq; i += nt) {
             Mu[i] = Tu[i];
             Mv[i] = Tv[i];
         }
         __syncthreads();
         // tmp[av][gu] = sum_au Tu[gu][au] y^_A[av][au]
-        for (int i = tid; i < nq; i += TREE_THREADS) {
-            const int av = i / q1, gu = i % q1;
+        for (int i = tid; i < nq * nr; i += nt) {
+            const int k = i % nr, e = i / nr, av = e / q1, gu = e % q1;
             double2 acc = make_double2(0, 0);
             for (int au = 0; au < q1; ++au) {
                 const double t = Mu[gu * q1 + au];
-                acc.x = fma(t, YA[av * q1 + au].x, acc.x);
-                acc.y = fma(t, YA[av * q1 + au].y, acc.y);
+                const double2 v = YA[(av * q1 + au) * nr + k];
+                acc.x = fma(t, v.x, acc.x);
+                acc.y = fma(t, v.y, acc.y);
             }
             tmp[i] = acc;
         }
         __syncthreads();
         // y^[gv][gu] += sum_av Tv[gv][av] tmp[av][gu]
-        for (int i = tid; i < nq; i += TREE_THREADS) {
-            const int gv = i / q1, gu = i % q1;
+        for (int i = tid; i < nq * nr; i += nt) {
+            const int k = i % nr, e = i / nr, gv = e / q1, gu = e % q1;
             double2 acc = make_double2(0, 0);
             for (int av = 0; av < q1; ++av) {
                 const double t = Mv[gv * q1 + av];
-                acc.x = fma(t, tmp[av * q1 + gu].x, acc.x);
-                acc.y = fma(t, tmp[av * q1 + gu].y, acc.y);
+                const double2 v = tmp[(av * q1 + gu) * nr + k];
+                acc.x = fma(t, v.x, acc.x);
+                acc.y = fma(t, v.y, acc.y);
             }
             Y[i] = cadd(Y[i], acc);
         }
@@ -843,27 +850,38 @@ __global__ __launch_bounds__(TREE_THREADS) void down_project_leaf(const double2*
     __syncthreads();
     const double* mu = m1 + deriv_u * m1_stride_kind + int64_t(cx) * q1 * w;
     const double* mv = m1 + deriv_v * m1_stride_kind + int64_t(cy) * q1 * w;
-    for (int i = tid; i < q1 * w; i += TREE_THREADS) {
-        const int av = i / w, lu = i % w;
+    for (int i = tid; i < q1 * w * nr; i += nt) {
+        const int k = i % nr, e = i / nr, av = e / w, lu = e % w;
         double2 acc = make_double2(0, 0);
         for (int au = 0; au < q1; ++au) {
             const double t = mu[au * w + lu];
-            acc.x = fma(t, Y[av * q1 + au].x, acc.x);
-            acc.y = fma(t, Y[av * q1 + au].y, acc.y);
+            const double2 v = Y[(av * q1 + au) * nr + k];
+            acc.x = fma(t, v.x, acc.x);
+            acc.y = fma(t, v.y, acc.y);
         }
         tb[i] = acc;
     }
     __syncthreads();
-    for (int i = tid; i < w * w; i += TREE_THREADS) {
-        const int lv = i / w, lu = i % w;
+    for (int i = tid; i < w * w * nr; i += nt) {
+        const int k = i / (w * w), e = i % (w * w), lv = e / w, lu = e % w;
         double2 acc = make_double2(0, 0);
         for (int av = 0; av < q1; ++av) {
             const double t = mv[av * w + lv];
-            acc.x = fma(t, tb[av * w + lu].x, acc.x);
-            acc.y = fma(t, tb[av * w + lu].y, acc.y);
+            const double2 v = tb[(av * w + lu) * nr + k];
+            acc.x = fma(t, v.x, acc.x);
+            acc.y = fma(t, v.y, acc.y);
         }
-        leafbuf[(c * ncol + r) * w * w + i] = acc;
+        leafbuf[(c * ncol + r0 + k) * w * w + e] = acc;
     }
+}
+
+// columns per workgroup of down_project_leaf: up to 8, within 48 KB of dynamic LDS
+static inline int down_cols(int ncol, int q1, int w, size_t& lds) {
+    int cb = std::min(ncol, 8);
+    auto bytes = [&](int k) { return size_t(k) * (3 * q1 * q1 + q1 * w) * sizeof(double2); };
+    while (cb > 1 && bytes(cb) > 48 * 1024) cb /= 2;
+    lds = bytes(cb);
+    return cb;
 }
 
 // y[r][i] = sum over kinds and the leaves whose window contains i (fixed order)
@@ -3188,11 +3206,13 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
                                op->d_yraw.as<double2>(), op->d_nodes.as<double>(), op->nclusters, nq, op->kappa,
                                op->hmix, ks, ncol, yh);
         const int w = (1 << op->d) + g->p;
+        size_t dlds = 0;
+        const int dcb = down_cols(ncol, q + 1, w, dlds);
         for (int kd = 0; kd < kinds; ++kd)
-            hipLaunchKernelGGL(down_project_leaf, dim3(unsigned(nleaf), unsigned(ncol)), dim3(TREE_THREADS), 0, s,
-                               yh + kd * ks, op->d_Tc.as<double>(), op->d_cluoff.as<int64_t>(),
-                               op->d_m1.as<double>(), q, w, L, du[kd], dv[kd], stride_kind, ncol,
-                               op->d_leafbuf.as<double2>() + kd * nleaf * ncol * w * w);
+            hipLaunchKernelGGL(down_project_leaf, dim3(unsigned(nleaf), unsigned((ncol + dcb - 1) / dcb)),
+                               dim3(dcb >= 4 ? 256 : TREE_THREADS), dlds, s, yh + kd * ks, op->d_Tc.as<double>(),
+                               op->d_cluoff.as<int64_t>(), op->d_m1.as<double>(), q, w, L, du[kd], dv[kd],
+                               stride_kind, ncol, dcb, op->d_leafbuf.as<double2>() + kd * nleaf * ncol * w * w);
         hipLaunchKernelGGL(leaf_gather, dim3(blocks_for(g->n2 * ncol, 256)), dim3(256), 0, s,
                            op->d_leafbuf.as<double2>(), op->d, g->p, L, g->k, g->npatch, kinds, ncol,
                            op->d_yfar.as<double2>());
