@@ -37,7 +37,8 @@ namespace {
 
 // ---- multi-column Arnoldi kernels: vectors [C][n], basis [j][C][n] ----
 // Inner products in two passes: partial sums over segments of DOT_SEG entries,
-// one workgroup per (jj, segment, r), then the segments summed in order.
+// one workgroup per (jj, segment, r), then the segments summed in order
+// (by cmaxpy_fin, which uses them).
 constexpr int DOT_SEG = 1024;
 __global__ __launch_bounds__(RT) void cdots_seg(const double2* V, int64_t n, int C, int nseg, const double2* w,
                                                 double2* part) {
@@ -64,27 +65,36 @@ __global__ __launch_bounds__(RT) void cdots_seg(const double2* V, int64_t n, int
     if (threadIdx.x == 0) part[(int64_t(jj) * C + r) * nseg + sg] = red[0];
 }
 
-__global__ void cdots_fin(const double2* part, int nvec, int C, int nseg, double2* h) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nvec * C) return;
-    double2 acc = make_double2(0, 0);
-    for (int sg = 0; sg < nseg; ++sg) {
-        const double2 v = part[int64_t(t) * nseg + sg];
-        acc.x += v.x;
-        acc.y += v.y;
+// w[r][i] -= sum_jj h[jj*C + r] V[jj][r][i], with h the dot products summed from
+// their segment partials (in segment order) by each workgroup for the columns
+// its 64 entries touch (64 / n + 2 at most); the workgroup holding a column's
+// first entry also stores that column's h for the host.
+__global__ __launch_bounds__(64) void cmaxpy_fin(const double2* V, int nvec, int64_t n, int C, const double2* part,
+                                                 int nseg, double2* h, double2* w) {
+    extern __shared__ double2 hs[];   // [columns touched][nvec]
+    const int64_t g0 = int64_t(blockIdx.x) * 64;
+    const int rlo = int(g0 / n);
+    const int rhi = int(min(g0 + 63, n * C - 1) / n);
+    for (int t = threadIdx.x; t < (rhi - rlo + 1) * nvec; t += 64) {
+        const int r = rlo + t / nvec, jj = t % nvec;
+        double2 acc = make_double2(0, 0);
+        for (int sg = 0; sg < nseg; ++sg) {
+            const double2 v = part[(int64_t(jj) * C + r) * nseg + sg];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        hs[t] = acc;
+        if (int64_t(r) * n >= g0 && int64_t(r) * n < g0 + 64) h[int64_t(jj) * C + r] = acc;
     }
-    h[t] = acc;
-}
-
-// w[r][i] -= sum_jj c[jj*C + r] V[jj][r][i]
-__global__ void cmaxpy_multi(const double2* V, int nvec, int64_t n, int C, const double2* c, double2* w) {
-    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    __syncthreads();
+    const int64_t gid = g0 + threadIdx.x;
     if (gid >= n * C) return;
     const int r = int(gid / n);
     const int64_t i = gid % n;
+    const double2* hc = hs + (r - rlo) * nvec;
     double2 acc = w[gid];
     for (int j = 0; j < nvec; ++j) {
-        const double2 a = c[int64_t(j) * C + r], v = V[(int64_t(j) * C + r) * n + i];
+        const double2 a = hc[j], v = V[(int64_t(j) * C + r) * n + i];
         acc.x -= a.x * v.x - a.y * v.y;
         acc.y -= a.x * v.y + a.y * v.x;
     }
@@ -275,13 +285,11 @@ igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, 
                                     reinterpret_cast<double*>(w), C, mvflags, s)))
                 return st;
             // classical Gram-Schmidt, twice
-            const unsigned gd = unsigned(((j + 1) * C + 255) / 256);
+            const size_t hlds = size_t(std::min<int64_t>(C, 63 / n + 2)) * (j + 1) * sizeof(double2);
             hipLaunchKernelGGL(cdots_seg, dim3(j + 1, Wk.nseg, C), dim3(RT), 0, s, V, n, C, Wk.nseg, w, Wk.part);
-            hipLaunchKernelGGL(cdots_fin, dim3(gd), dim3(256), 0, s, Wk.part, j + 1, C, Wk.nseg, Wk.h);
-            hipLaunchKernelGGL(cmaxpy_multi, dim3(gb64), dim3(64), 0, s, V, j + 1, n, C, Wk.h, w);
+            hipLaunchKernelGGL(cmaxpy_fin, dim3(gb64), dim3(64), hlds, s, V, j + 1, n, C, Wk.part, Wk.nseg, Wk.h, w);
             hipLaunchKernelGGL(cdots_seg, dim3(j + 1, Wk.nseg, C), dim3(RT), 0, s, V, n, C, Wk.nseg, w, Wk.part);
-            hipLaunchKernelGGL(cdots_fin, dim3(gd), dim3(256), 0, s, Wk.part, j + 1, C, Wk.nseg, Wk.h2);
-            hipLaunchKernelGGL(cmaxpy_multi, dim3(gb64), dim3(64), 0, s, V, j + 1, n, C, Wk.h2, w);
+            hipLaunchKernelGGL(cmaxpy_fin, dim3(gb64), dim3(64), hlds, s, V, j + 1, n, C, Wk.part, Wk.nseg, Wk.h2, w);
             // ||w||^2 and the next basis vector on the device, then one copy of
             // the step's Hessenberg entries and norms to the host
             hipLaunchKernelGGL(cnorm2_multi, dim3(C), dim3(1024), 0, s, w, n, Wk.nrm);
