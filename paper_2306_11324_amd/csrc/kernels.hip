@@ -775,8 +775,54 @@ __global__ __launch_bounds__(TREE_THREADS) void m2m_wg(const double* __restrict_
     }
 }
 
+// y[r][i] = sum over kinds and the leaves whose window contains i (fixed order)
+__global__ void leaf_gather(const double2* __restrict__ leafbuf, int d, int p, int L, int k, int npatch, int kinds,
+                            int ncol, double2* __restrict__ y) {
+    const int64_t n2 = int64_t(npatch) * k * k;
+    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= n2 * ncol) return;
+    const int64_t r = gid / n2, i = gid % n2;
+    const int patch = int(i / (int64_t(k) * k));
+    const int rem = int(i % (int64_t(k) * k));
+    const int iv = rem / k, iu = rem % k;
+    const int s = 1 << d, w = s + p, n = 1 << L;
+    const int64_t nleaf = int64_t(npatch) * n * n;
+    double2 acc = make_double2(0, 0);
+    const int cy0 = max(0, (iv - w + s) / s), cy1 = min(n - 1, iv / s);
+    const int cx0 = max(0, (iu - w + s) / s), cx1 = min(n - 1, iu / s);
+    for (int cy = cy0; cy <= cy1; ++cy) {
+        const int lv = iv - cy * s;
+        if (lv < 0 || lv >= w) continue;
+        for (int cx = cx0; cx <= cx1; ++cx) {
+            const int lu = iu - cx * s;
+            if (lu < 0 || lu >= w) continue;
+            const int64_t leaf = (int64_t(patch) << (2 * L)) + int64_t(cy) * n + cx;
+            for (int kd = 0; kd < kinds; ++kd)
+                acc = cadd(acc, leafbuf[((kd * nleaf + leaf) * ncol + r) * w * w + lv * w + lu]);
+        }
+    }
+    y[gid] = acc;
+}
+
+// storage types of the coupling tiles: fp64, fp32 or bf16 complex; products and
+// accumulation run in fp64 on the VALU path
+struct bf16x2 {
+    unsigned short re, im;
+};
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ double2 to_d2(bf16x2 v) {
+    return make_double2(__uint_as_float(unsigned(v.re) << 16), __uint_as_float(unsigned(v.im) << 16));
+}
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
 // downward pass and back projection in one launch, one workgroup per leaf and
-// block of columns: the leaf's local expansion collects every ancestor's,
+// block of columns: the leaf's local expansion collects every ancestor's
+// (each read as the sum of its coupling partials when those are given),
 //   y^_leaf += (Tv ⊗ Tu)_(delta, pos) y^_A   for the ancestors A, nearest first,
 // with the composite transfers Tc[delta][pos][g][a] = L_a((pos + t_g) / 2^delta)
 // (the ancestor's Lagrange basis at the leaf's nodes, delta levels down at
@@ -788,7 +834,10 @@ __global__ __launch_bounds__(TREE_THREADS) void m2m_wg(const double* __restrict_
 // operations and their order do not depend on cb.  Dynamic LDS: y^, the
 // ancestor's y^ and the half-transferred values, cb x (q+1)^2 each, then the
 // half-projected values cb x (q+1) x w; node-major, columns fastest.)
+template <class PT>
 __global__ __launch_bounds__(256) void down_project_leaf(const double2* __restrict__ yh,
+                                                         const PT* __restrict__ part,
+                                                         const int* __restrict__ chunk_ptr,
                                                          const double* __restrict__ Tc,
                                                          const int64_t* __restrict__ clu_off,
                                                          const double* __restrict__ m1, int q, int w, int L,
@@ -807,15 +856,23 @@ __global__ __launch_bounds__(256) void down_project_leaf(const double2* __restri
     const int patch = int(c / (int64_t(n) * n));
     const int rem = int(c % (int64_t(n) * n));
     const int cy = rem / n, cx = rem % n;
-    for (int i = tid; i < nq * nr; i += nt)
-        Y[i] = yh[((clu_off[L] + c) * nq + i / nr) * ncol + r0 + i % nr];
+    // y^ of cluster X at node e, column r: the sum of its coupling chunks' partials
+    // (in chunk order, as m2l_reduce forms it) or, without partials, y^ itself
+    auto yget = [&](int64_t X, int e, int r) {
+        if (!part) return yh[(X * nq + e) * ncol + r];
+        double2 acc = make_double2(0, 0);
+        for (int ch = chunk_ptr[X]; ch < chunk_ptr[X + 1]; ++ch)
+            acc = cadd(acc, to_d2(part[(int64_t(ch) * nq + e) * ncol + r]));
+        return acc;
+    };
+    for (int i = tid; i < nq * nr; i += nt) Y[i] = yget(clu_off[L] + c, i / nr, r0 + i % nr);
     for (int l = L - 1; l >= 0; --l) {
         const int dl = L - l, msk = (1 << dl) - 1;
         const int64_t A = clu_off[l] + (int64_t(patch) << (2 * l)) + (int64_t(cy >> dl) << l) + (cx >> dl);
         const double* Tu = Tc + int64_t((1 << dl) - 2 + (cx & msk)) * q1 * q1;
         const double* Tv = Tc + int64_t((1 << dl) - 2 + (cy & msk)) * q1 * q1;
         __syncthreads();   // previous ancestor's YA / tmp consumed
-        for (int i = tid; i < nq * nr; i += nt) YA[i] = yh[(A * nq + i / nr) * ncol + r0 + i % nr];
+        for (int i = tid; i < nq * nr; i += nt) YA[i] = yget(A, i / nr, r0 + i % nr);
         for (int i = tid; i < nq; i += nt) {
             Mu[i] = Tu[i];
             Mv[i] = Tv[i];
@@ -884,50 +941,6 @@ static inline int down_cols(int ncol, int q1, int w, size_t& lds) {
     return cb;
 }
 
-// y[r][i] = sum over kinds and the leaves whose window contains i (fixed order)
-__global__ void leaf_gather(const double2* __restrict__ leafbuf, int d, int p, int L, int k, int npatch, int kinds,
-                            int ncol, double2* __restrict__ y) {
-    const int64_t n2 = int64_t(npatch) * k * k;
-    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (gid >= n2 * ncol) return;
-    const int64_t r = gid / n2, i = gid % n2;
-    const int patch = int(i / (int64_t(k) * k));
-    const int rem = int(i % (int64_t(k) * k));
-    const int iv = rem / k, iu = rem % k;
-    const int s = 1 << d, w = s + p, n = 1 << L;
-    const int64_t nleaf = int64_t(npatch) * n * n;
-    double2 acc = make_double2(0, 0);
-    const int cy0 = max(0, (iv - w + s) / s), cy1 = min(n - 1, iv / s);
-    const int cx0 = max(0, (iu - w + s) / s), cx1 = min(n - 1, iu / s);
-    for (int cy = cy0; cy <= cy1; ++cy) {
-        const int lv = iv - cy * s;
-        if (lv < 0 || lv >= w) continue;
-        for (int cx = cx0; cx <= cx1; ++cx) {
-            const int lu = iu - cx * s;
-            if (lu < 0 || lu >= w) continue;
-            const int64_t leaf = (int64_t(patch) << (2 * L)) + int64_t(cy) * n + cx;
-            for (int kd = 0; kd < kinds; ++kd)
-                acc = cadd(acc, leafbuf[((kd * nleaf + leaf) * ncol + r) * w * w + lv * w + lu]);
-        }
-    }
-    y[gid] = acc;
-}
-
-// storage types of the coupling tiles: fp64, fp32 or bf16 complex; products and
-// accumulation run in fp64 on the VALU path
-struct bf16x2 {
-    unsigned short re, im;
-};
-__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
-__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
-__device__ __forceinline__ double2 to_d2(bf16x2 v) {
-    return make_double2(__uint_as_float(unsigned(v.re) << 16), __uint_as_float(unsigned(v.im) << 16));
-}
-__device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
-    unsigned u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
 
 // ---------------------------------------------------------------------------
 // Reduced-precision coupling on the matrix cores
@@ -3188,9 +3201,11 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
         if ((st = launch_m2l(op, xh, ks, low, ncol, s, pkind))) return st;
         if ((st = timer_mark(op, 3, s))) return st;
         const int nvec = hard ? 10 : 1;
-        double2* red_out = hard ? op->d_yraw.as<double2>() : yh;
+        double2* red_out = op->d_yraw.as<double2>();
         const int64_t per = int64_t(nvec) * nq * ncol;
-        if (pkind == 1)
+        if (!hard) {
+            // sound-soft: the downward kernel sums the chunk partials itself
+        } else if (pkind == 1)
             hipLaunchKernelGGL(m2l_reduce<float2>, dim3(blocks_for(op->nclusters * per, 256)), dim3(256), 0, s,
                                op->d_part_lo.as<float2>(), op->chunks_mfma.d_tgt_ptr.as<int>(), op->nclusters, per,
                                red_out);
@@ -3208,11 +3223,27 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
         const int w = (1 << op->d) + g->p;
         size_t dlds = 0;
         const int dcb = down_cols(ncol, q + 1, w, dlds);
-        for (int kd = 0; kd < kinds; ++kd)
-            hipLaunchKernelGGL(down_project_leaf, dim3(unsigned(nleaf), unsigned((ncol + dcb - 1) / dcb)),
-                               dim3(dcb >= 4 ? 256 : TREE_THREADS), dlds, s, yh + kd * ks, op->d_Tc.as<double>(),
-                               op->d_cluoff.as<int64_t>(), op->d_m1.as<double>(), q, w, L, du[kd], dv[kd],
-                               stride_kind, ncol, dcb, op->d_leafbuf.as<double2>() + kd * nleaf * ncol * w * w);
+        const dim3 dgrid(unsigned(nleaf), unsigned((ncol + dcb - 1) / dcb)), dblock(dcb >= 4 ? 256 : TREE_THREADS);
+        const double* Tc = op->d_Tc.as<double>();
+        const int64_t* cof = op->d_cluoff.as<int64_t>();
+        const double* m1 = op->d_m1.as<double>();
+        double2* lb = op->d_leafbuf.as<double2>();
+        if (hard) {
+            for (int kd = 0; kd < kinds; ++kd)
+                hipLaunchKernelGGL(down_project_leaf<double2>, dgrid, dblock, dlds, s, yh + kd * ks,
+                                   static_cast<const double2*>(nullptr), static_cast<const int*>(nullptr), Tc, cof, m1,
+                                   q, w, L, du[kd], dv[kd], stride_kind, ncol, dcb, lb + kd * nleaf * ncol * w * w);
+        } else if (pkind == 1) {
+            hipLaunchKernelGGL(down_project_leaf<float2>, dgrid, dblock, dlds, s, yh, op->d_part_lo.as<float2>(),
+                               op->chunks_mfma.d_tgt_ptr.as<int>(), Tc, cof, m1, q, w, L, 0, 0, stride_kind, ncol,
+                               dcb, lb);
+        } else {
+            const bool lo = pkind == 2;
+            hipLaunchKernelGGL(down_project_leaf<double2>, dgrid, dblock, dlds, s, yh,
+                               lo ? op->d_part_lo.as<double2>() : op->d_part.as<double2>(),
+                               (lo ? op->chunks_mfma : op->chunks).d_tgt_ptr.as<int>(), Tc, cof, m1, q, w, L, 0, 0,
+                               stride_kind, ncol, dcb, lb);
+        }
         hipLaunchKernelGGL(leaf_gather, dim3(blocks_for(g->n2 * ncol, 256)), dim3(256), 0, s,
                            op->d_leafbuf.as<double2>(), op->d, g->p, L, g->k, g->npatch, kinds, ncol,
                            op->d_yfar.as<double2>());
