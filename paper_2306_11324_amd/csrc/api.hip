@@ -252,7 +252,8 @@ static igb_status build_one(igb_ctx ctx, igb_geom g, const igb_op_params* prm, c
     const int ntile = op->bc == IGB_HARD ? 2 : 1;
     const size_t fp64_tiles =
         prm->far_on_the_fly ? 0 : size_t(op->nfar) * op->nq * op->nq * 16 * ntile + size_t(3) * op->nq * 16 + 256;
-    size_t need = fp64_tiles + size_t(op->nnz) * 20 + size_t(op->N + 1) * 8 +
+    size_t need = fp64_tiles + size_t(op->nnz) * 20 + size_t(op->N + 1) * 8 + op->near_dcol.size() * 4 +
+                  op->row_coff.size() * 8 +
                   size_t(op->nclusters) * op->nq * (16 * 8 + 32) + op->near_src.size() * 4 +
                   std::min<size_t>(op->near_src.size(), size_t(1) << 22) * nl * nl * 16;
     if (prm->precision == IGB_FP64 && !prm->far_on_the_fly) {

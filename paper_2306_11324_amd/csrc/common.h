@@ -164,6 +164,10 @@ struct igb_op_s {
     std::vector<int64_t> row_ptr;
     std::vector<int> col;
     int64_t nnz = 0;
+    // rows with the same leaves have the same columns: each such list once (near_dcol)
+    // and per row the offset of its list (the near products read columns from here)
+    std::vector<int> near_dcol;
+    std::vector<int64_t> row_coff;
     // bf16 operators: the near rows in tiles of up to 16 rows over a common column list
     std::vector<NearTile> near_tiles;
     std::vector<int> near_tile_cols;  // the tiles' column lists
@@ -176,7 +180,7 @@ struct igb_op_s {
     // its factors (complex entries) and the factors u_k [k][nq], v_k^T [nq][rank]
     igb::DevBuf d_lr, d_lr_rank, d_lr_off;
     int64_t lr_entries = 0;
-    igb::DevBuf d_rowptr, d_col, d_val;
+    igb::DevBuf d_rowptr, d_col, d_val, d_dcol, d_row_coff;
     // bf16 operators: fp32 near-field values and fp32 copies of the columns for the
     // near product of the inner (refinement) matvecs
     igb::DevBuf d_val_lo, d_xnear_lo, d_near_tiles, d_near_tile_cols;

@@ -1835,13 +1835,16 @@ __global__ void m2l_reduce(const PT* part, const int* tgt_chunk_ptr, int64_t ncl
 }
 
 // y[r][row] = sum_j val x[r][col] (+ far part mapped to the solution space); one
-// wave per row, lanes stride over the row, butterfly reduction (fixed order)
+// wave per row, lanes stride over the row, butterfly reduction (fixed order).
+// Columns come from the row's group list (rows with the same leaves share one),
+// so the index reads mostly hit the caches and HBM streams the values alone.
 // (RB columns per pass; consecutive nonzeros of a row mostly have consecutive
 // columns, so the lanes' x reads coalesce.  Each column's operations and
 // their order do not depend on RB.  On the m = 5 sphere with 16 columns,
 // 4 per pass ran in 0.15 ms, 8 in 0.19 ms and 16 in 0.24 ms.)
 template <int RB>
 __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ row_ptr,
+                                                    const int64_t* __restrict__ row_coff,
                                                     const int* __restrict__ col,
                                                     const double2* __restrict__ val,
                                                     const double2* __restrict__ x, int64_t nrows,
@@ -1853,6 +1856,7 @@ __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ 
     const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     if (row >= nrows) return;
     const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+    const int64_t cbase = row_coff[row] - b;   // the row's shared column list, indexed like its values
     for (int c0 = 0; c0 < ncol; c0 += RB) {
         double2 acc[RB];
 #pragma unroll
@@ -1860,7 +1864,7 @@ __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ 
         if (use_near) {
             for (int64_t idx = b + lane; idx < e; idx += 64) {
                 const double2 v = val[idx];
-                const int64_t cc = col[idx];
+                const int64_t cc = col[cbase + idx];
 #pragma unroll
                 for (int cb = 0; cb < RB; ++cb)
                     if (c0 + cb < ncol) acc[cb] = cfma(v, x[int64_t(c0 + cb) * nrows + cc], acc[cb]);
@@ -2559,6 +2563,8 @@ static igb_status near_launch(igb_op op, hipStream_t s) {
     if ((st = upload(op->d_near_src, op->near_src.data(), op->near_src.size(), acct))) return st;
     if ((st = upload(op->d_rowptr, op->row_ptr.data(), op->row_ptr.size(), acct))) return st;
     if ((st = upload(op->d_col, op->col.data(), op->col.size(), acct))) return st;
+    if ((st = upload(op->d_dcol, op->near_dcol.data(), op->near_dcol.size(), acct))) return st;
+    if ((st = upload(op->d_row_coff, op->row_coff.data(), op->row_coff.size(), acct))) return st;
     if ((st = alloc(op->d_val, op->nnz * sizeof(double2), acct))) return st;
     IGB_HIP(hipMemsetAsync(op->d_val.ptr, 0, op->nnz * sizeof(double2), s));
 
@@ -3256,7 +3262,8 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
     const int use_near = (parts & IGB_PART_NEAR) ? 1 : 0;
     const dim3 sg(blocks_for(N * 64, 256)), sb(256);
     const int64_t* rp = op->d_rowptr.as<int64_t>();
-    const int* cl = op->d_col.as<int>();
+    const int64_t* rco = op->d_row_coff.as<int64_t>();
+    const int* dcl = op->d_dcol.as<int>();
     const double2* vl = op->d_val.as<double2>();
     if (low && op->d_val_lo.ptr) {
         const int ncb = (ncol + 15) / 16;
@@ -3270,9 +3277,11 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
                            op->d_near_tile_cols.as<int>(),
                            op->d_val_lo.as<float2>(), xt, N, yfar, g->n2, s0p, s0r, use_near, ncol, Y);
     } else if (ncol == 1) {
-        hipLaunchKernelGGL(spmv_combine<1>, sg, sb, 0, s, rp, cl, vl, X, N, yfar, g->n2, s0p, s0r, use_near, ncol, Y);
+        hipLaunchKernelGGL(spmv_combine<1>, sg, sb, 0, s, rp, rco, dcl, vl, X, N, yfar, g->n2, s0p, s0r, use_near,
+                           ncol, Y);
     } else {
-        hipLaunchKernelGGL(spmv_combine<4>, sg, sb, 0, s, rp, cl, vl, X, N, yfar, g->n2, s0p, s0r, use_near, ncol, Y);
+        hipLaunchKernelGGL(spmv_combine<4>, sg, sb, 0, s, rp, rco, dcl, vl, X, N, yfar, g->n2, s0p, s0r, use_near,
+                           ncol, Y);
     }
     IGB_HIP(hipGetLastError());
     if ((st = timer_mark(op, 1, s))) return st;

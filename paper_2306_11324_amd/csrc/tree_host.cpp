@@ -420,17 +420,28 @@ igb_status near_pattern(igb_op op) {
     op->near_tiles.clear();
     op->near_tile_cols.clear();
     op->near_tile_vals = 0;
-    if (op->prm.precision == IGB_MIX_BF16) {
-        std::map<std::vector<int>, std::vector<int>> groups;
+    std::map<std::vector<int>, std::vector<int>> groups;
+    {
         std::vector<int> leaves;
         for (int64_t r = 0; r < N; ++r) {
             row_leaves(r, leaves);
             groups[leaves].push_back(int(r));
         }
-        std::vector<const std::vector<int>*> order;
-        for (const auto& kv : groups) order.push_back(&kv.second);
-        std::sort(order.begin(), order.end(),
-                  [](const std::vector<int>* a, const std::vector<int>* b) { return a->front() < b->front(); });
+    }
+    std::vector<const std::vector<int>*> order;
+    for (const auto& kv : groups) order.push_back(&kv.second);
+    std::sort(order.begin(), order.end(),
+              [](const std::vector<int>* a, const std::vector<int>* b) { return a->front() < b->front(); });
+    // each group's column list once; every row points at its group's list
+    op->near_dcol.clear();
+    op->row_coff.assign(N, 0);
+    for (const std::vector<int>* g : order) {
+        const int64_t off = int64_t(op->near_dcol.size());
+        op->near_dcol.insert(op->near_dcol.end(), op->col.begin() + op->row_ptr[g->front()],
+                             op->col.begin() + op->row_ptr[g->front() + 1]);
+        for (int r : *g) op->row_coff[r] = off;
+    }
+    if (op->prm.precision == IGB_MIX_BF16) {
         std::vector<int> rows, cols, tmp;
         size_t longest = 0;
         auto emit = [&]() {
