@@ -20,7 +20,7 @@ H = G (i kappa r - 1)/r^2 (so grad_y G = H (y - x)):
     W     : G [ c_i(x) . c_j(y) - kappa^2 (n~_x . n~_y) psi_i psi_j ],
             c = d_u psi d_v F - d_v psi d_u F   (the surface curl times a, Sec. 4.3)
 
-Readings of the paper taken here (listed in the design doc):
+Readings of the paper taken here:
 
 * the curl term of the regularised W uses c_i(x).c_j(y) -- the printed closed
   form's "K^{-1}" and the missing surface measures are read as adj(K)^T and the
