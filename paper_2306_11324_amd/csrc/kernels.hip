@@ -721,58 +721,75 @@ __global__ void leaf_moments(const double2* x, int64_t xstride, const double* m1
 constexpr int TREE_THREADS = 128;
 constexpr int TQ1 = QMAX + 1;
 constexpr int TNQ = TQ1 * TQ1;
-constexpr int TCB = 2;  // columns per workgroup
 
-// upward, one workgroup per (parent at level l, column block):
+// upward, one workgroup per (parent at level l, block of cb columns):
 //   x^_P[av][au] = sum_c sum_gv Tv_c[gv][av] sum_gu Tu_c[gu][au] x^_c[gv][gu]
-__global__ __launch_bounds__(TREE_THREADS) void m2m_wg(const double* __restrict__ T1, int q, int l,
-                                                       int64_t off_l, int64_t off_l1, double2* xh, int ncol) {
+// (dynamic LDS: the children's moments and the half-transferred values,
+// 4 (q+1)^2 cb each, columns fastest; each column's operations and their order
+// do not depend on cb)
+__global__ __launch_bounds__(256) void m2m_wg(const double* __restrict__ T1, int q, int l, int64_t off_l,
+                                              int64_t off_l1, double2* xh, int ncol, int cb) {
+    extern __shared__ double2 dyn[];
     __shared__ double T[2 * TQ1 * TQ1];
-    __shared__ double2 X[4 * TNQ * TCB];
-    __shared__ double2 tmp[4 * TNQ * TCB];
-    const int q1 = q + 1, nq = q1 * q1, tid = threadIdx.x;
+    const int q1 = q + 1, nq = q1 * q1, tid = threadIdx.x, nt = blockDim.x;
+    double2* X = dyn;
+    double2* tmp = dyn + 4 * nq * cb;
     const int64_t c = blockIdx.x;
-    const int c0 = blockIdx.y * TCB;
+    const int c0 = blockIdx.y * cb;
     const int n = 1 << l;
     const int patch = int(c / (int64_t(n) * n));
     const int rem = int(c % (int64_t(n) * n));
     const int cy = rem / n, cx = rem % n;
-    for (int i = tid; i < 2 * q1 * q1; i += TREE_THREADS) T[i] = T1[i];
-    for (int i = tid; i < 4 * nq * TCB; i += TREE_THREADS) {
-        const int cb = i % TCB, t = i / TCB, ch = t / nq, a = t % nq, bu = ch & 1, bv = ch >> 1;
+    for (int i = tid; i < 2 * q1 * q1; i += nt) T[i] = T1[i];
+    for (int i = tid; i < 4 * nq * cb; i += nt) {
+        const int k = i % cb, t = i / cb, ch = t / nq, a = t % nq, bu = ch & 1, bv = ch >> 1;
         const int64_t child = off_l1 + (int64_t(patch) << (2 * (l + 1))) + (int64_t(2 * cy + bv) << (l + 1)) +
                               2 * cx + bu;
-        X[i] = c0 + cb < ncol ? xh[(child * nq + a) * ncol + c0 + cb] : make_double2(0, 0);
+        X[i] = c0 + k < ncol ? xh[(child * nq + a) * ncol + c0 + k] : make_double2(0, 0);
     }
     __syncthreads();
-    for (int i = tid; i < 4 * nq * TCB; i += TREE_THREADS) {
-        const int cb = i % TCB, t = i / TCB, ch = t / nq, r = t % nq, gv = r / q1, au = r % q1, bu = ch & 1;
+    for (int i = tid; i < 4 * nq * cb; i += nt) {
+        const int k = i % cb, t = i / cb, ch = t / nq, r = t % nq, gv = r / q1, au = r % q1, bu = ch & 1;
         const double* Tu = T + bu * q1 * q1;
         double2 acc = make_double2(0, 0);
         for (int gu = 0; gu < q1; ++gu) {
             const double tt = Tu[gu * q1 + au];
-            const double2 xv = X[(ch * nq + gv * q1 + gu) * TCB + cb];
+            const double2 xv = X[(ch * nq + gv * q1 + gu) * cb + k];
             acc.x = fma(tt, xv.x, acc.x);
             acc.y = fma(tt, xv.y, acc.y);
         }
         tmp[i] = acc;
     }
     __syncthreads();
-    for (int i = tid; i < nq * TCB; i += TREE_THREADS) {
-        const int cb = i % TCB, a = i / TCB, av = a / q1, au = a % q1;
-        if (c0 + cb >= ncol) continue;
+    for (int i = tid; i < nq * cb; i += nt) {
+        const int k = i % cb, a = i / cb, av = a / q1, au = a % q1;
+        if (c0 + k >= ncol) continue;
         double2 acc = make_double2(0, 0);
         for (int ch = 0; ch < 4; ++ch) {
             const double* Tv = T + (ch >> 1) * q1 * q1;
             for (int gv = 0; gv < q1; ++gv) {
                 const double tt = Tv[gv * q1 + av];
-                const double2 v = tmp[(ch * nq + gv * q1 + au) * TCB + cb];
+                const double2 v = tmp[(ch * nq + gv * q1 + au) * cb + k];
                 acc.x = fma(tt, v.x, acc.x);
                 acc.y = fma(tt, v.y, acc.y);
             }
         }
-        xh[((off_l + c) * nq + a) * ncol + c0 + cb] = acc;
+        xh[((off_l + c) * nq + a) * ncol + c0 + k] = acc;
     }
+}
+
+// the upward pass above the leaves: m2m_wg level by level, up to 8 columns per
+// workgroup within 48 KB of dynamic LDS
+static void launch_m2m_levels(const double* T1, int q, int L, int npatch, const std::vector<int64_t>& clu_off,
+                              double2* xh, int ncol, hipStream_t s) {
+    const int nq = (q + 1) * (q + 1);
+    int cb = std::min(ncol, 8);
+    while (cb > 2 && size_t(8) * nq * cb * sizeof(double2) > 48 * 1024) cb /= 2;
+    const size_t lds = size_t(8) * nq * cb * sizeof(double2);
+    const unsigned cblk = unsigned((ncol + cb - 1) / cb);
+    for (int l = L - 1; l >= 0; --l)
+        hipLaunchKernelGGL(m2m_wg, dim3(unsigned(clusters_on_level(npatch, l)), cblk), dim3(cb >= 4 ? 256 : TREE_THREADS),
+                           lds, s, T1, q, l, clu_off[l], clu_off[l + 1], xh, ncol, cb);
 }
 
 // y[r][i] = sum over kinds and the leaves whose window contains i (fixed order)
@@ -3192,15 +3209,10 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
         const int du[3] = {0, 1, 0}, dv[3] = {0, 0, 1};
         const int64_t nleaf = clusters_on_level(g->npatch, L);
         const int64_t stride_kind = int64_t(1 << L) * (q + 1) * ((1 << op->d) + g->p);
-        const unsigned cblk = unsigned((ncol + TCB - 1) / TCB);
         if ((st = timer_mark(op, 2, s))) return st;
         for (int kd = 0; kd < kinds; ++kd) {
             launch_leaf_moments(op, x2, xh + kd * ks, du[kd], dv[kd], ncol, s);
-            for (int l = L - 1; l >= 0; --l) {
-                const int64_t nc = clusters_on_level(g->npatch, l);
-                hipLaunchKernelGGL(m2m_wg, dim3(unsigned(nc), cblk), dim3(TREE_THREADS), 0, s, op->d_T.as<double>(), q,
-                                   l, op->clu_off[l], op->clu_off[l + 1], xh + kd * ks, ncol);
-            }
+            launch_m2m_levels(op->d_T.as<double>(), q, L, g->npatch, op->clu_off, xh + kd * ks, ncol, s);
         }
         if ((st = timer_mark(op, 2, s))) return st;
         int pkind = 0;
@@ -3443,10 +3455,7 @@ igb_status potential_h2_device(igb_op op, const double* coeffs, int ndir, const 
     }
     double2* xh = sp->d_xhat.as<double2>();
     launch_leaf_moments(sp, x2, xh, 0, 0, ndir, s);
-    const unsigned cblk = unsigned((ndir + TCB - 1) / TCB);
-    for (int l = L - 1; l >= 0; --l)
-        hipLaunchKernelGGL(m2m_wg, dim3(unsigned(clusters_on_level(g->npatch, l)), cblk), dim3(TREE_THREADS), 0, s,
-                           sp->d_T.as<double>(), q, l, sp->clu_off[l], sp->clu_off[l + 1], xh, ndir);
+    launch_m2m_levels(sp->d_T.as<double>(), q, L, g->npatch, sp->clu_off, xh, ndir, s);
     IGB_HIP(hipGetLastError());
     // boundary density and geometry at the quadrature points (near part)
     const int nqd = smooth_order(op, 8);
