@@ -173,6 +173,7 @@ class H2Oracle:
         the lower/upper half of the parent interval."""
         return lagrange(self.t, 0.5 * (child_bit + self.t))
 
+    @functools.lru_cache(maxsize=None)
     def leaf_moment_1d(self, level: int, c: int, deriv: bool = False) -> np.ndarray:
         """m[b, i] = int_{cluster interval} L_b(t) b_i(t) dt over the whole knot
         vector's basis (or b_i' for the derivative moments)."""
@@ -186,20 +187,28 @@ class H2Oracle:
             val, der = bspline.basis_and_derivative(disc.knots, disc.p, t)
             L = lagrange(self.t, t * 2 ** level - c)
             out += np.einsum("g,gb,gi->bi", w * disc.h, L, der if deriv else val)
+        out.flags.writeable = False   # cached: shared by every caller
         return out
 
-    def cluster_moment(self, c: Cluster, kind=(0, 0)) -> np.ndarray:
-        """Moment matrix (nq, n2) of cluster c computed directly (not through the
-        transfers): int_c L_a(x^) d^kind psi_j(x^) dx^."""
+    def cluster_moment_patch(self, c: Cluster, kind=(0, 0)) -> np.ndarray:
+        """The moments of cluster c against the B-splines of its own patch
+        (nq, k^2), computed directly (not through the transfers):
+        int_c L_a(x^) d^kind psi_j(x^) dx^.  Every other S^2 function vanishes
+        on the cluster."""
         mu = self.leaf_moment_1d(c.level, c.cx, kind[0] == 1)
         mv = self.leaf_moment_1d(c.level, c.cy, kind[1] == 1)
         k = self.disc.k
+        return np.einsum("ai,bj->baji", mu, mv).reshape(self.nq, k * k)
+
+    def cluster_moment(self, c: Cluster, kind=(0, 0)) -> np.ndarray:
+        """Moment matrix (nq, n2) of cluster c (zero outside its patch)."""
+        k = self.disc.k
         M = np.zeros((self.nq, self.disc.n2))
-        blk = np.einsum("ai,bj->baji", mu, mv).reshape(self.nq, k * k)
-        M[:, c.patch * k * k:(c.patch + 1) * k * k] = blk
+        M[:, c.patch * k * k:(c.patch + 1) * k * k] = self.cluster_moment_patch(c, kind)
         return M
 
     # ------------------------------------------------------------ kernels at nodes
+    @functools.lru_cache(maxsize=None)
     def node_geometry(self, c: Cluster):
         X = self.nodes(c)
         mp = self.disc.maps[c.patch]
@@ -244,11 +253,14 @@ class H2Oracle:
         for a in range(2):
             for b in range(2):
                 kinds[("d", a, b)] = ((1, 0) if a == 0 else (0, 1), (1, 0) if b == 0 else (0, 1))
+        kk = self.disc.k ** 2
         for t, s in self.far:
             K = self.coupling(t, s)
+            rt = slice(t.patch * kk, (t.patch + 1) * kk)
+            rs = slice(s.patch * kk, (s.patch + 1) * kk)
             for key, mat in K.items():
                 kt, ks = kinds[key]
-                A += self.cluster_moment(t, kt).T @ mat @ self.cluster_moment(s, ks)
+                A[rt, rs] += self.cluster_moment_patch(t, kt).T @ mat @ self.cluster_moment_patch(s, ks)
         return A
 
     def near_pairs(self):

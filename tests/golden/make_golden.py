@@ -9,6 +9,9 @@ Cases
   sphere_m3_p2_k2_q4  sphere, m = 3, p = 2, kappa = 2, soft, q = 4, eta = 1.6,
                       leaf depth 1: O2 far product, O1 near product, sampled
                       near entries, right-hand side, for the seeded vector x.
+  sphere_m3_p2_k2_q4_block  the same operators (soft on S^2, hard on S^0): O2's
+                      far product of 20 seeded columns, one column at a time
+                      (blocks of 16 and more columns run another code path).
   sphere_m2_p1_k1     the m = 2, p = 1, kappa = 1 sphere workload: dense O1
                       matrix, right-hand side for d = (0,0,1), LU solution,
                       far field at 64 Fibonacci directions and the Mie values.
@@ -72,6 +75,17 @@ def case_sphere_m3_p2_k2_q4():
     d = np.array([0.3, -0.2, 0.9])
     return dict(x=x, y_far=H.far_apply(x), y_near=A @ x, ent_ij=pick.astype(np.int32),
                 ent_val=A[pick[:, 0], pick[:, 1]], d=d, rhs=bem.rhs(d), nfar=len(H.far))
+
+
+def case_sphere_m3_p2_k2_q4_block(ncol=20):
+    out = {}
+    for bc in ("soft", "hard"):
+        bem = G.DenseBEM(I.sphere_patches(), p=2, m=3, kappa=2.0, bc=bc)
+        H = h2.H2Oracle(bem, q=4, eta=1.6, leaf_depth=1)
+        X = I.random_complex(X_SEED + 1, (ncol, bem.n))
+        out[f"{bc}_X"] = X
+        out[f"{bc}_Y_far"] = np.stack([H.far_apply(x) for x in X])
+    return out
 
 
 def case_sphere_m2_p1_k1():
@@ -195,6 +209,7 @@ CASES = {
     "sphere_m3_p2_k2_q4_hard": case_sphere_m3_p2_k2_q4_hard,
     "sphere_m2_p2_k1_hard": case_sphere_m2_p2_k1_hard,
     "sphere_m3_p2_k2_q4": case_sphere_m3_p2_k2_q4,
+    "sphere_m3_p2_k2_q4_block": case_sphere_m3_p2_k2_q4_block,
     "sphere_m2_p1_k1": case_sphere_m2_p1_k1,
     "sphere_m5_p2_k8_rows": case_sphere_m5_p2_k8_rows,
     "star_m6_p2_k16_rows": case_star_m6_p2_k16_rows,

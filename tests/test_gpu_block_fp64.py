@@ -1,0 +1,124 @@
+"""fp64 blocks on the matrix cores against the oracle (Sec. 4.4 coupling,
+many incident directions as one block product).
+
+An fp64 operator with stored couplings applies the coupling of blocks of 16 or
+more columns with v_mfma_f64_16x16x4 (soft: m2l_mfma_soft, hard: m2l_mfma with
+both G and H tiles); smaller blocks run the vector kernels.  The two paths sum
+the same products in different orders, so:
+
+* every column of a 16- or 20-column block (one full 16-column tile and a
+  ragged tile of 4) matches O2's step-by-step far product (stored in
+  tests/golden/sphere_m3_p2_k2_q4_block.npz, one column at a time) to 1e-11
+  relative to max |y|, as the single-column path does;
+* a column computed in a block of >= 16 equals the same column in any other
+  block of >= 16 bitwise, and differs from the column computed alone by
+  rounding only: at most 1e-12 relative to max |y| (the sums run over
+  ~5,000 tiles of 25 x 25 products, so fp64 reordering moves them by ~1e-15);
+* lockstep solves of 16 directions on the level-2 spheres reproduce the
+  oracle's dense LU solution and far field of the one direction it stores.
+"""
+import functools
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+BCS = pytest.mark.parametrize("bc", ["soft", "hard"])
+
+
+def gold(name):
+    return dict(np.load(os.path.join(GOLD, name + ".npz")))
+
+
+@functools.lru_cache(maxsize=None)
+def B():
+    from paper_2306_11324_amd import binding
+    return binding
+
+
+@functools.lru_cache(maxsize=None)
+def ctx():
+    return B().Context(0)
+
+
+@functools.lru_cache(maxsize=None)
+def operator(m, p, kappa, q, d, bc):
+    from paper_2306_11324_amd import inputs as I
+    print(f"case: sphere m={m} p={p} kappa={kappa} q={q} leaf_depth={d} bc={bc} fp64 stored tiles", flush=True)
+    geo = B().Geometry(ctx(), I.sphere_patches(), m, p)
+    op = B().Operator(ctx(), geo, kappa=kappa, q=q, leaf_depth=d, bc=B().SOFT if bc == "soft" else B().HARD)
+    return geo, op
+
+
+def apply_block(op, X, parts):
+    xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    yd = torch.zeros_like(xd)
+    op.h2_matvec(xd, yd, nrhs=X.shape[0], parts=parts)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@BCS
+@pytest.mark.parametrize("ncol", [16, 20])
+def test_fp64_matrix_core_block_matches_oracle(bc, ncol):
+    g = gold("sphere_m3_p2_k2_q4_block")
+    X, Yref = g[f"{bc}_X"][:ncol], g[f"{bc}_Y_far"][:ncol]
+    geo, op = operator(3, 2, 2.0, 4, 1, bc)
+    assert op.n == X.shape[1]
+    Y = apply_block(op, X, B().PART_FAR)
+    errs = [rel(Y[c], Yref[c]) for c in range(ncol)]
+    alone = [rel(apply_block(op, X[c:c + 1], B().PART_FAR)[0], Y[c]) for c in range(ncol)]
+    print(f"{bc} {ncol} columns: max rel err vs oracle {max(errs):.2e}; block vs alone {max(alone):.2e}", flush=True)
+    assert max(errs) < 1e-11, errs
+    assert max(alone) < 1e-12, alone
+    assert max(alone) > 0, "the block did not take the matrix-core path"
+
+
+@BCS
+def test_blocks_of_16_or_more_agree_bitwise(bc):
+    """Columns 0..15 of a 20-column block equal the 16-column block, and the
+    last 4 equal a 17-column block whose last column is each of them."""
+    g = gold("sphere_m3_p2_k2_q4_block")
+    X = g[f"{bc}_X"]
+    geo, op = operator(3, 2, 2.0, 4, 1, bc)
+    Y20 = apply_block(op, X, B().PART_ALL)
+    Y16 = apply_block(op, X[:16], B().PART_ALL)
+    assert np.array_equal(Y20[:16], Y16)
+    for c in range(16, 20):
+        Y17 = apply_block(op, np.concatenate([X[:16], X[c:c + 1]]), B().PART_ALL)
+        assert np.array_equal(Y17[16], Y20[c]), c
+
+
+LEVEL2 = {"soft": ("sphere_m2_p1_k1", 1), "hard": ("sphere_m2_p2_k1_hard", 2)}
+
+
+@BCS
+def test_sixteen_direction_fp64_solve_matches_oracle_lu(bc):
+    """16 directions in lockstep (matrix-core coupling at every Arnoldi step):
+    the direction the oracle stores (d = (0, 0, 1), placed in column 5) matches
+    its dense LU solution and far field (H^2 error at q = 8 ~1e-8), and Mie."""
+    from paper_2306_11324_amd import inputs as I
+    name, p = LEVEL2[bc]
+    g = gold(name)
+    geo, op = operator(2, p, 1.0, 8, 0, bc)
+    dirs = I.random_directions(11, 16)
+    dirs[5] = g["d"]
+    T = torch.zeros((16, op.n), dtype=torch.complex128, device="cuda")
+    info, st = op.cfie_solve(dirs, T, tol=1e-12, restart=30, maxit=600)
+    assert st == 0 and info.converged == 16 and info.relres_true < 1e-11, (info.iters, info.relres_true)
+    u = torch.zeros(len(g["obs"]), dtype=torch.complex128, device="cuda")
+    op.farfield(T[5], g["obs"], u)
+    torch.cuda.synchronize()
+    u = u.cpu().numpy()
+    e_t, e_u, e_mie = rel(T[5].cpu().numpy(), g["t"]), rel(u, g["uinf"]), rel(u, g["mie"])
+    print(f"{bc}: 16-direction fp64 block, column 5 vs LU {e_t:.2e}, far field vs LU {e_u:.2e}, vs Mie "
+          f"{e_mie:.2e}", flush=True)
+    assert e_t < 1e-6 and e_u < 1e-6 and e_mie < 1e-3

@@ -105,3 +105,117 @@ def test_block_error_decays_geometrically_in_q():
     assert errs[-1] < 1e-6
     for a, b in zip(errs[:-1], errs[1:]):
         assert b < a / 8, errs
+
+
+# ---------------------------------------------------------------- sound hard
+# The hard operator (1/2 M - K - i eta W on S^0, Sec. 4.1 and 4.3) adds the
+# derivative moments of Sec. 4.4 (d_u psi, d_v psi against the curl factors
+# of the regularised W) and the gluing S^0 -> S^2.  These pins check that
+# branch of O2 against O1 and against itself, on the CPU.
+
+@functools.lru_cache(maxsize=None)
+def bem_m3_hard():
+    return G.DenseBEM(inputs.sphere_patches(), p=1, m=3, kappa=2.0, bc="hard")
+
+
+def test_recursion_matches_direct_moments_hard():
+    """Upward / coupling / downward passes with the three moment kinds (plain,
+    d_u, d_v) and the gluing equal the far field built from directly
+    integrated plain and derivative cluster moments."""
+    bem = bem_m3_hard()
+    H = h2.H2Oracle(bem, q=3, eta=1.6, leaf_depth=1)
+    assert len(H.far) > 0
+    x = inputs.random_complex(12345, bem.n)
+    y = H.far_apply(x)
+    ref = H.to_solution_space(H.far_matrix()) @ x
+    assert np.abs(y - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def _exact_far_blocks_hard(H, bem, far):
+    """O1's -K - i eta W on the given far blocks, in the S^2 element basis."""
+    disc = bem.disc
+    out = []
+    for t, s in far:
+        A = np.zeros((disc.n2, disc.n2), dtype=np.complex128)
+        es = H.cluster_elements(s)
+        for e in H.cluster_elements(t):
+            blk = bem.element_row_blocks(int(e), sources=es)
+            comb = -blk["K"] - 1j * bem.eta * blk["W"]
+            for f in es:
+                A[np.ix_(disc.el_dofs[e], disc.el_dofs[f])] += comb[f]
+        out.append(A)
+    return out
+
+
+def _h2_block_hard(H, t, s):
+    """Sum over the coupling kinds of M_t(kind)^T K M_s(kind) (S^2 basis)."""
+    kinds = {"pp": ((0, 0), (0, 0))}
+    for a in range(2):
+        for b in range(2):
+            kinds[("d", a, b)] = ((1, 0) if a == 0 else (0, 1), (1, 0) if b == 0 else (0, 1))
+    A = 0.0
+    for key, mat in H.coupling(t, s).items():
+        kt, ks = kinds[key]
+        A = A + H.cluster_moment(t, kt).T @ mat @ H.cluster_moment(s, ks)
+    return A
+
+
+def test_block_error_decays_geometrically_in_q_hard():
+    """Interpolated hard blocks (both parts of the regularised W: the curl term
+    on derivative moments and the kappa^2 term, plus K) approach O1's blocks
+    geometrically in q.  A dropped term, a sign slip or a transposed
+    derivative kind leaves an O(1) error that does not decay."""
+    bem = bem_m3_hard()
+    H0 = h2.H2Oracle(bem, q=2, eta=1.6, leaf_depth=1)
+    far = H0.far[:: max(1, len(H0.far) // 6)][:6]
+    exact = _exact_far_blocks_hard(H0, bem, far)
+    errs = []
+    for q in (2, 4, 6, 8):
+        H = h2.H2Oracle(bem, q=q, eta=1.6, leaf_depth=1)
+        e = 0.0
+        for (t, s), A in zip(far, exact):
+            Ah = _h2_block_hard(H, t, s)
+            e = max(e, np.linalg.norm(Ah - A) / np.linalg.norm(A))
+        errs.append(e)
+    assert errs[-1] < 1e-6, errs
+    for a, b in zip(errs[:-1], errs[1:]):
+        assert b < a / 8, errs
+
+
+def test_hard_far_operator_decays_in_q():
+    """The whole far part of the hard H^2 matrix (every admissible block, glued
+    to S^0) against O1's -K - i eta W integrated on the same element pairs, on
+    the level-2 sphere, p = 2, kappa = 1, leaf depth 0: the error falls by orders
+    of magnitude from q = 4 to q = 8 and ends near rounding."""
+    bem = G.DenseBEM(inputs.sphere_patches(), p=2, m=2, kappa=1.0, bc="hard")
+    disc = bem.disc
+    H4 = h2.H2Oracle(bem, q=4, eta=1.6, leaf_depth=0)
+    assert len(H4.far) > 0
+    far_src = {}
+    for t, s in H4.far:
+        es = H4.cluster_elements(s)
+        for e in H4.cluster_elements(t):
+            far_src.setdefault(int(e), []).extend(int(f) for f in es)
+    F = np.zeros((disc.n2, disc.n2), dtype=np.complex128)
+    for e, fs in far_src.items():
+        blk = bem.element_row_blocks(e, sources=fs)
+        comb = -blk["K"] - 1j * bem.eta * blk["W"]
+        for f in fs:
+            F[np.ix_(disc.el_dofs[e], disc.el_dofs[f])] += comb[f]
+    F = H4.to_solution_space(F)
+    errs = []
+    for q in (4, 6, 8):
+        H = h2.H2Oracle(bem, q=q, eta=1.6, leaf_depth=0)
+        assert H.far == H4.far
+        Fh = H.to_solution_space(H.far_matrix())
+        errs.append(np.abs(Fh - F).max() / np.abs(F).max())
+    assert errs[0] < 1e-5 and errs[-1] < 1e-10, errs
+    assert errs[1] < errs[0] / 30 and errs[2] < errs[1] / 30, errs
+
+
+def test_no_admissible_blocks_gives_dense_hard():
+    bem = G.DenseBEM(inputs.sphere_patches(), p=1, m=1, kappa=1.0, bc="hard")
+    H = h2.H2Oracle(bem, q=2, eta=1e12, leaf_depth=1)
+    assert len(H.far) == 0
+    A = bem.matrix()
+    assert np.abs(H.matrix() - A).max() < 1e-14 * np.abs(A).max()
