@@ -185,6 +185,8 @@ typedef struct {
     int escalated;    /* mixed precision: columns that finished on the fp64 operator
                          because a refinement step reduced their fp64 residual by
                          less than a factor 10                                       */
+    double seconds;   /* wall time of cfie_solve (right-hand sides, GMRES, residual
+                         checks), host clock                                         */
 } igb_solve_info;
 
 typedef struct {
@@ -199,8 +201,10 @@ typedef struct {
     int64_t near_elem_pairs;/* element pairs integrated by quadrature              */
     int64_t nnz;            /* nonzeros of the near-field matrix                    */
     int64_t device_bytes;   /* device memory held by the operator                   */
-    int64_t estimated_bytes;/* device memory the operator needs (the budget check's
-                               size model; also on host-only contexts)             */
+    int64_t estimated_bytes;/* device memory the operator holds after assembly and
+                               a one-direction solve (size model; also on host-only
+                               contexts); assemble_nearfield checks the budget
+                               against this plus its own transient staging buffers */
     double assembly_near_ms, assembly_far_ms;
 } igb_op_info;
 
@@ -245,6 +249,19 @@ igb_status igb_geom_s0_map(igb_geom g, int32_t* s2_to_s0);
 igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm, igb_op* out);
 void igb_op_destroy(igb_op op);
 igb_status igb_op_get_info(igb_op op, igb_op_info* info);
+/* Dimension N of the solution space (dim S^2 soft, dim S^0 hard); -1 for NULL. */
+int64_t igb_op_ndof(igb_op op);
+/* Device bytes the operator holds now (data and grown work buffers); -1 for NULL. */
+int64_t igb_op_bytes(igb_op op);
+
+/* Size model of a solve: *bytes = device memory the operator holds after
+ * cfie_solve with ndir directions and GMRES restart `restart` (0 = 30): its data
+ * (estimated_bytes of igb_op_info without the one-column work), the matvec work
+ * vectors of ndir columns and the solver's buffers (Krylov bases, right-hand
+ * sides, refinement residual and corrections).  cfie_solve checks the budget
+ * against this model before any work and returns IGB_ERR_BUDGET if the growth
+ * would not fit.  Works on host-only contexts (admission planning). */
+igb_status igb_op_solve_bytes(igb_op op, int ndir, int restart, int64_t* bytes);
 
 /* Near-field matrix in CSR (solution space) copied to host arrays of sizes
  * n+1, nnz, 2*nnz (sizes from igb_op_get_info). */
@@ -286,11 +303,23 @@ igb_status igb_op_use_graphs(igb_op op, int enable);
 #define IGB_PART_FAR 2
 #define IGB_PART_ALL 3
 #define IGB_MV_LOWPREC 4   /* with IGB_MIX_* operators: far field from the rounded copy */
-/* y = A x for nrhs columns (device arrays [nrhs][n] complex).  parts selects the
+#define IGB_MV_HOST 8      /* x and y are host arrays; the call is synchronous          */
+/* y = A x for nrhs columns (device arrays [nrhs][n] complex; with IGB_MV_HOST in
+ * parts, host arrays: x is copied to operator-owned device buffers, the product
+ * runs on hip_stream, y is copied back and the call returns when y is written --
+ * the timing then includes the PCIe copies).  parts selects the
  * near-field (incl. 1/2 M) and/or far-field (H^2) contributions.  The columns
- * share every pass over the couplings and the near-field matrix; each column is
- * computed with the same operation order whatever nrhs is, so results do not
- * depend on the batch.  x and y must not overlap.  Stream-ordered. */
+ * share every pass over the couplings and the near-field matrix.  Batch
+ * invariance: a column's result does not depend on the other columns, with one
+ * exception -- IGB_FP64 operators with stored couplings run the coupling of
+ * blocks of 16 or more columns on the fp64 matrix cores, which sum the same
+ * products in another order than the single-column vector kernels.  Results of
+ * blocks of 1..15 columns are bitwise equal to single-column results, results of
+ * blocks of >= 16 columns bitwise equal to those of any other block of >= 16,
+ * and the two differ by rounding (<= 1e-12 relative to max|y| of the column;
+ * ~1e-15 measured).  Reduced-precision products (IGB_MV_LOWPREC) use the matrix
+ * cores for every block size and are batch invariant bitwise.  x and y must not
+ * overlap.  Stream-ordered. */
 igb_status h2_matvec(igb_op op, const double* x, double* y, int nrhs, int parts, void* hip_stream);
 
 /* Right-hand sides (Sec. 4.1 load vectors of the D2N / N2D systems) for ndir
@@ -302,7 +331,10 @@ igb_status cfie_rhs(igb_op op, const double* dirs, int ndir, double* b, void* hi
  * restarted GMRES (Sec. 5.1), x0 = 0, writing the coefficients into the device
  * array coeffs [ndir][n].  The directions run in lockstep: one block matvec per
  * Arnoldi step, each column with its own Krylov basis, rotations and stopping
- * test, so a column's solution does not depend on the other columns.
+ * test, so a column's solution does not depend on the other columns (with the
+ * exception stated at h2_matvec: IGB_FP64 operators with stored couplings solve
+ * ndir >= 16 with matrix-core couplings, whose iterates differ from those of
+ * smaller batches by rounding; within either range they agree bitwise).
  * Operators with IGB_MIX_* precision solve by iterative refinement:
  * x += GMRES(A_rounded, b - A_fp64 x) until the fp64 residual reaches tol; a
  * column whose step reduces that residual by less than a factor 10 continues

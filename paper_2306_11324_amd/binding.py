@@ -32,6 +32,7 @@ FP64, MIX_FP32, MIX_BF16 = 0, 1, 2
 CFIE, SINGLE_LAYER, OP_V, OP_KSTAR, OP_K, OP_W = 0, 1, 2, 3, 4, 5
 PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
 MV_LOWPREC = 4
+MV_HOST = 8
 CONTEXT_STREAM = "context"   # pass as stream=...: order the call on the context's own stream
 
 
@@ -56,7 +57,7 @@ class IgbSolveParams(C.Structure):
 class IgbSolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("relres", C.c_double),
                 ("relres_true", C.c_double), ("matvecs", C.c_int64), ("refinements", C.c_int),
-                ("escalated", C.c_int)]
+                ("escalated", C.c_int), ("seconds", C.c_double)]
 
 
 class IgbOpInfo(C.Structure):
@@ -79,6 +80,9 @@ _SIGS = {
     "assemble_nearfield": (C.c_int, [_P, _P, C.POINTER(IgbOpParams), C.POINTER(_P)]),
     "igb_op_destroy": (None, [_P]),
     "igb_op_get_info": (C.c_int, [_P, C.POINTER(IgbOpInfo)]),
+    "igb_op_ndof": (C.c_int64, [_P]),
+    "igb_op_bytes": (C.c_int64, [_P]),
+    "igb_op_solve_bytes": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int64)]),
     "igb_op_near_csr": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "igb_op_far_blocks": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "igb_op_near_pairs": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
@@ -125,6 +129,17 @@ def _dptr(t, n_complex=None):
     if n_complex is not None and t.numel() < n_complex:
         raise ValueError(f"tensor has {t.numel()} elements, need {n_complex}")
     return C.c_void_p(t.data_ptr())
+
+
+def _hptr(a, n_complex, writable):
+    """Host address of a C-contiguous complex128 numpy array."""
+    if not isinstance(a, np.ndarray) or a.dtype != np.complex128 or not a.flags.c_contiguous:
+        raise TypeError("expected a C-contiguous complex128 numpy array")
+    if writable and not a.flags.writeable:
+        raise ValueError("output array is read-only")
+    if a.size < n_complex:
+        raise ValueError(f"array has {a.size} elements, need {n_complex}")
+    return C.c_void_p(a.ctypes.data)
 
 
 def _stream(stream):
@@ -207,6 +222,15 @@ class Operator:
         _check("igb_op_get_info", _lib.igb_op_get_info(self.h, C.byref(info)))
         return info
 
+    def solve_bytes(self, ndir: int, restart: int = 30) -> int:
+        """Device bytes the operator holds after a solve of ndir directions (size model)."""
+        b = C.c_int64()
+        _check("igb_op_solve_bytes", _lib.igb_op_solve_bytes(self.h, ndir, restart, C.byref(b)))
+        return b.value
+
+    def held_bytes(self) -> int:
+        return int(_lib.igb_op_bytes(self.h))
+
     def near_csr(self):
         n, nnz = self.info.n, self.info.nnz
         rp = np.zeros(n + 1, dtype=np.int64)
@@ -247,9 +271,13 @@ class Operator:
         return n.value, ms.value
 
     def h2_matvec(self, x, y, nrhs: int = 1, parts: int = PART_ALL, stream=None):
-        """y = A x for nrhs columns stored [nrhs][n] in x and y."""
-        _check("h2_matvec", _lib.h2_matvec(self.h, _dptr(x, nrhs * self.n), _dptr(y, nrhs * self.n),
-                                           nrhs, parts, _stream(stream)))
+        """y = A x for nrhs columns stored [nrhs][n] in x and y: complex128 torch
+        tensors on the GPU, or (with MV_HOST in parts) numpy arrays on the host."""
+        if parts & MV_HOST:
+            xs, ys = _hptr(x, nrhs * self.n, False), _hptr(y, nrhs * self.n, True)
+        else:
+            xs, ys = _dptr(x, nrhs * self.n), _dptr(y, nrhs * self.n)
+        _check("h2_matvec", _lib.h2_matvec(self.h, xs, ys, nrhs, parts, _stream(stream)))
         return y
 
     def cfie_rhs(self, dirs, b, stream=None):

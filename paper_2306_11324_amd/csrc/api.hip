@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -10,6 +11,39 @@
 
 namespace igb {
 const char* last_error();
+
+igb_ctx_s*& alloc_ctx() {
+    thread_local igb_ctx_s* c = nullptr;
+    return c;
+}
+
+bool charge(igb_ctx_s* c, size_t bytes) {
+    size_t cur = c->used.load();
+    do {
+        if (c->budget != 0 && cur + bytes > c->budget) return false;
+    } while (!c->used.compare_exchange_weak(cur, cur + bytes));
+    return true;
+}
+
+igb_status dev_malloc(DevBuf& b, size_t bytes, const char* who) {
+    b.release();
+    if (bytes == 0) return IGB_OK;
+    igb_ctx_s* c = alloc_ctx();
+    if (c && !charge(c, bytes)) {
+        set_error("%s: HBM budget exceeded (%zu held + %zu > %zu bytes)", who, c->used.load(), bytes, c->budget);
+        return IGB_ERR_BUDGET;
+    }
+    const hipError_t e = hipMalloc(&b.ptr, bytes);
+    if (e != hipSuccess) {
+        if (c) uncharge(c, bytes);
+        b.ptr = nullptr;
+        set_error("%s: hipMalloc of %zu bytes: %s", who, bytes, hipGetErrorString(e));
+        return IGB_ERR_HIP;
+    }
+    b.bytes = bytes;
+    b.ctx = c;
+    return IGB_OK;
+}
 }
 
 using namespace igb;
@@ -46,8 +80,15 @@ static igb_status need_single_matrix(igb_op op, const char* what) {
     return IGB_OK;
 }
 
+// device bytes held by an operator (its parts, for a lazy sum)
+size_t op_held_bytes(igb_op op) {
+    size_t b = op->dev_bytes;
+    for (igb_op p : op->sum_parts) b += p->dev_bytes;
+    return b;
+}
+
 bool budget_ok(igb_ctx ctx, size_t add) {
-    return ctx->budget == 0 || ctx->used + add <= ctx->budget;
+    return ctx->budget == 0 || ctx->used.load() + add <= ctx->budget;
 }
 
 }  // namespace
@@ -107,14 +148,13 @@ void ctx_release(igb_ctx ctx) {
 void geom_release(igb_geom g) {
     if (!g || --g->refs > 0) return;
     igb_ctx ctx = g->ctx;
-    if (ctx) ctx->used -= std::min(ctx->used, g->dev_bytes);
     delete g;
     ctx_release(ctx);
 }
 
 void igb_ctx_destroy(igb_ctx ctx) { ctx_release(ctx); }
 
-size_t igb_ctx_used_bytes(igb_ctx ctx) { return ctx ? ctx->used : 0; }
+size_t igb_ctx_used_bytes(igb_ctx ctx) { return ctx ? ctx->used.load() : 0; }
 
 igb_status build_geometry(igb_ctx ctx, const igb_patch* patches, int npatch, int level_m, int degree_p,
                           igb_geom* out) {
@@ -122,6 +162,7 @@ igb_status build_geometry(igb_ctx ctx, const igb_patch* patches, int npatch, int
         set_error("build_geometry: NULL argument");
         return IGB_ERR_ARG;
     }
+    AllocScope scope(ctx);
     if (!host_only(ctx)) IGB_HIP(hipSetDevice(ctx->device));
     igb_geom g = new (std::nothrow) igb_geom_s();
     if (!g) {
@@ -136,14 +177,13 @@ igb_status build_geometry(igb_ctx ctx, const igb_patch* patches, int npatch, int
     const size_t need = g->bez.size() * 8 + g->pg.size() * 4 + g->C1.size() * 8;
     if (!budget_ok(ctx, need)) {
         delete g;
-        set_error("build_geometry: HBM budget exceeded (%zu + %zu > %zu bytes)", ctx->used, need, ctx->budget);
+        set_error("build_geometry: HBM budget exceeded (%zu + %zu > %zu bytes)", ctx->used.load(), need, ctx->budget);
         return IGB_ERR_BUDGET;
     }
     if (!host_only(ctx) && (st = upload_geometry(g))) {
         delete g;
         return st;
     }
-    ctx->used += g->dev_bytes;
     ++ctx->refs;
     *out = g;
     return IGB_OK;
@@ -254,34 +294,29 @@ static igb_status build_one(igb_ctx ctx, igb_geom g, const igb_op_params* prm, c
         prm->far_on_the_fly ? 0 : size_t(op->nfar) * op->nq * op->nq * 16 * ntile + size_t(3) * op->nq * 16 + 256;
     size_t need = fp64_tiles + size_t(op->nnz) * 20 + size_t(op->N + 1) * 8 + op->near_dcol.size() * 4 +
                   op->row_coff.size() * 8 +
-                  size_t(op->nclusters) * op->nq * (16 * 8 + 32) + op->near_src.size() * 4 +
-                  std::min<size_t>(op->near_src.size(), size_t(1) << 22) * nl * nl * 16;
-    if (prm->precision == IGB_FP64 && !prm->far_on_the_fly) {
-        // per 16 columns: source vectors and fp64 partials of the matrix-core coupling
-        const size_t kbp = (op->nq + 3) / 4 * 4;
-        need += size_t(op->nclusters) * (ntile == 2 ? 7 : 1) * 16 * kbp * 16 +
-                op->chunks_mfma.len.size() * (ntile == 2 ? 10 : 1) * op->nq * 16;
-    }
-    if (prm->precision == IGB_MIX_BF16)   // fp32 near field in tiles, fp32 columns
+                  size_t(op->nclusters) * op->nq * (16 * 8 + 32) + op->near_src.size() * 4;
+    // held during assembly only: the staged element blocks and the near pair lists
+    const size_t transient = std::min<size_t>(op->near_src.size(), size_t(1) << 22) * nl * nl * 16 +
+                             op->near_src.size() * 12 + (size_t(1) << 20);
+    if (prm->precision == IGB_MIX_BF16)   // fp32 near field in tiles
         need += size_t(op->near_tile_vals) * 8 + op->near_tiles.size() * sizeof(NearTile) +
-                op->near_tile_cols.size() * 4 + size_t(op->N) * 8 * 16;
+                op->near_tile_cols.size() * 4;
     if (prm->precision != IGB_FP64) {
-        // rounded tiles (rows padded to 16 bytes) and, per 16 columns, the rounded
-        // source vectors and fp32 partials of the matrix-core coupling
-        const size_t esz = prm->precision == IGB_MIX_FP32 ? 8 : 4, epl = 16 / esz, kb = 4 * epl;
-        const size_t ldk = (op->nq + epl - 1) / epl * epl, kbp = (op->nq + kb - 1) / kb * kb;
+        // rounded tiles (rows padded to 16 bytes)
+        const size_t esz = prm->precision == IGB_MIX_FP32 ? 8 : 4, epl = 16 / esz;
+        const size_t ldk = (op->nq + epl - 1) / epl * epl;
         need += size_t(op->nfar) * ntile * op->nq * ldk * esz + size_t(3) * op->nq * 16 + 256;
-        need += size_t(op->nclusters) * (ntile == 2 ? 7 : 1) * 16 * kbp * esz +
-                op->chunks_mfma.len.size() * (ntile == 2 ? 10 : 1) * op->nq * 8;
     }
     // recompressed couplings: at most the tiles' size at the tolerances of interest
     if (prm->far_recompress_tol > 0) need += size_t(op->nfar) * op->nq * op->nq * 16 + size_t(op->nfar) * 12;
-    // matvec work vectors for one column and a GMRES(30) basis
-    need += size_t(op->nclusters) * op->nq * 16 * (op->bc == IGB_HARD ? 16 : 2) + size_t(g->n2) * 16 * 4 +
-            size_t(35) * op->N * 16;
+    op->estimated_data = need;
+    // plus the matvec work vectors of one column and a GMRES(30) solve of one column
+    // (more columns: igb_op_solve_bytes)
+    need += work_sizes(op, 1).total() + solve_buffer_bytes(op, 30, 1);
     op->estimated_bytes = need;
-    if (!budget_ok(ctx, need)) {
-        set_error("assemble_nearfield: HBM budget exceeded (%zu + %zu > %zu bytes)", ctx->used, need, ctx->budget);
+    if (!budget_ok(ctx, need + transient)) {
+        set_error("assemble_nearfield: HBM budget exceeded (%zu + %zu > %zu bytes)", ctx->used.load(),
+                  need + transient, ctx->budget);
         delete op;
         return IGB_ERR_BUDGET;
     }
@@ -295,7 +330,6 @@ static igb_status build_one(igb_ctx ctx, igb_geom g, const igb_op_params* prm, c
         delete op;
         return st;
     }
-    ctx->used += op->dev_bytes;
     ++g->refs;
     *out = op;
     return IGB_OK;
@@ -348,6 +382,7 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
         set_error("assemble_nearfield: the sound-hard operators need S^0, i.e. p >= 1");
         return IGB_ERR_ARG;
     }
+    AllocScope scope(ctx);
     if (!host_only(ctx)) IGB_HIP(hipSetDevice(ctx->device));
     if (!prm->separate) return build_one(ctx, g, prm, c, out);
 
@@ -395,7 +430,8 @@ igb_status assemble_nearfield(igb_ctx ctx, igb_geom g, const igb_op_params* prm,
     op->aspect_max = p0->aspect_max;
     op->sum_parts = {p0, p1};
     op->sum_coef = {make_double2(1.0, 0.0), make_double2(0.0, -c.eta)};
-    op->estimated_bytes = p0->estimated_bytes + p1->estimated_bytes;
+    op->estimated_data = p0->estimated_data + p1->estimated_data;
+    op->estimated_bytes = solve_model_bytes(op, 30, 1);
     ++g->refs;
     *out = op;
     return IGB_OK;
@@ -411,7 +447,6 @@ void igb_op_destroy(igb_op op) {
     }
     for (igb_op part : op->sum_parts) igb_op_destroy(part);
     op->sum_parts.clear();
-    ctx->used -= std::min(ctx->used, op->dev_bytes);
     delete op;
     geom_release(g);
 }
@@ -456,6 +491,19 @@ igb_status igb_op_get_info(igb_op op, igb_op_info* info) {
     info->estimated_bytes = int64_t(op->estimated_bytes);
     info->assembly_near_ms = op->t_assembly_near;
     info->assembly_far_ms = op->t_assembly_far;
+    return IGB_OK;
+}
+
+int64_t igb_op_ndof(igb_op op) { return op ? op->N : -1; }
+
+int64_t igb_op_bytes(igb_op op) { return op ? int64_t(op_held_bytes(op)) : -1; }
+
+igb_status igb_op_solve_bytes(igb_op op, int ndir, int restart, int64_t* bytes) {
+    if (!op || !bytes || ndir < 1 || restart < 0) {
+        set_error("igb_op_solve_bytes: invalid argument");
+        return IGB_ERR_ARG;
+    }
+    *bytes = int64_t(solve_model_bytes(op, restart > 0 ? restart : 30, ndir));
     return IGB_OK;
 }
 
@@ -568,7 +616,7 @@ igb_status igb_op_kernel_time(igb_op op, const char* name, int64_t* launches, do
 }
 
 igb_status h2_matvec(igb_op op, const double* x, double* y, int nrhs, int parts, void* hip_stream) {
-    if (!op || !x || !y || nrhs < 1 || (parts & 3) == 0 || parts > 7) {
+    if (!op || !x || !y || nrhs < 1 || (parts & 3) == 0 || parts > 15) {
         set_error("h2_matvec: invalid argument");
         return IGB_ERR_ARG;
     }
@@ -577,8 +625,21 @@ igb_status h2_matvec(igb_op op, const double* x, double* y, int nrhs, int parts,
         return IGB_ERR_ARG;
     }
     if (igb_status st = need_device(op, "h2_matvec")) return st;
+    AllocScope scope(op->geom->ctx);
     IGB_HIP(hipSetDevice(op->geom->ctx->device));
-    return matvec_device(op, x, y, nrhs, parts, pick(op->geom->ctx, hip_stream));
+    hipStream_t s = pick(op->geom->ctx, hip_stream);
+    if (!(parts & IGB_MV_HOST)) return matvec_device(op, x, y, nrhs, parts, s);
+    // host columns: stage through operator-owned device buffers
+    const size_t bytes = size_t(nrhs) * op->N * 16;
+    igb_status st;
+    if ((st = op_reserve(op, op->d_hx, bytes, "h2_matvec")) || (st = op_reserve(op, op->d_hy, bytes, "h2_matvec")))
+        return st;
+    IGB_HIP(hipMemcpyAsync(op->d_hx.ptr, x, bytes, hipMemcpyHostToDevice, s));
+    if ((st = matvec_device(op, op->d_hx.as<double>(), op->d_hy.as<double>(), nrhs, parts & ~IGB_MV_HOST, s)))
+        return st;
+    IGB_HIP(hipMemcpyAsync(y, op->d_hy.ptr, bytes, hipMemcpyDeviceToHost, s));
+    IGB_HIP(hipStreamSynchronize(s));
+    return IGB_OK;
 }
 
 igb_status cfie_rhs(igb_op op, const double* dirs, int ndir, double* b, void* hip_stream) {
@@ -587,6 +648,7 @@ igb_status cfie_rhs(igb_op op, const double* dirs, int ndir, double* b, void* hi
         return IGB_ERR_ARG;
     }
     if (igb_status st = need_device(op, "cfie_rhs")) return st;
+    AllocScope scope(op->geom->ctx);
     if (igb_status st1 = need_system(op, "cfie_rhs")) return st1;
     IGB_HIP(hipSetDevice(op->geom->ctx->device));
     return rhs_device(op, dirs, ndir, b, pick(op->geom->ctx, hip_stream));
@@ -598,16 +660,31 @@ igb_status cfie_solve(igb_op op, const double* dirs, int ndir, const igb_solve_p
         set_error("cfie_solve: invalid argument");
         return IGB_ERR_ARG;
     }
-    if (igb_status st0 = need_device(op, "cfie_solve")) return st0;
     if (igb_status st1 = need_system(op, "cfie_solve")) return st1;
+    {
+        // the solve's growth, from the size model, against the budget before any work
+        igb_ctx ctx = op->geom->ctx;
+        const size_t model = solve_model_bytes(op, sp->restart > 0 ? sp->restart : 30, ndir);
+        const size_t held = host_only(ctx) ? 0 : op_held_bytes(op);
+        const size_t grow = model > held ? model - held : 0;
+        if (!budget_ok(ctx, grow)) {
+            set_error("cfie_solve: HBM budget exceeded by %d directions (%zu held + %zu > %zu bytes)", ndir,
+                      ctx->used.load(), grow, ctx->budget);
+            return IGB_ERR_BUDGET;
+        }
+    }
+    if (igb_status st0 = need_device(op, "cfie_solve")) return st0;
+    AllocScope scope(op->geom->ctx);
     IGB_HIP(hipSetDevice(op->geom->ctx->device));
     hipStream_t s = op->geom->ctx->stream;
-    igb::DevBuf b;
-    IGB_HIP(hipMalloc(&b.ptr, size_t(ndir) * op->N * 16));
-    igb_status st = rhs_device(op, dirs, ndir, b.as<double>(), s);
+    const auto t_start = std::chrono::steady_clock::now();
+    // right-hand sides in an operator-owned buffer (kept for later solves)
+    igb_status st = op_reserve(op, op->d_b, size_t(ndir) * op->N * 16, "cfie_solve");
     if (st) return st;
-    st = gmres_device(op, b.as<double>(), coeffs, ndir, sp, info, s);
+    if ((st = rhs_device(op, dirs, ndir, op->d_b.as<double>(), s))) return st;
+    st = gmres_device(op, op->d_b.as<double>(), coeffs, ndir, sp, info, s);
     IGB_HIP(hipStreamSynchronize(s));
+    if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     return st;
 }
 
@@ -618,6 +695,7 @@ igb_status farfield(igb_op op, const double* coeffs, int ndir, const double* obs
         return IGB_ERR_ARG;
     }
     if (igb_status st = need_device(op, "farfield")) return st;
+    AllocScope scope(op->geom->ctx);
     if (igb_status st1 = need_system(op, "farfield")) return st1;
     IGB_HIP(hipSetDevice(op->geom->ctx->device));
     return farfield_device(op, coeffs, ndir, obs, nobs, uinf, pick(op->geom->ctx, hip_stream));
@@ -630,6 +708,7 @@ igb_status potential(igb_op op, const double* coeffs, int ndir, const double* po
         return IGB_ERR_ARG;
     }
     if (igb_status st = need_device(op, "potential")) return st;
+    AllocScope scope(op->geom->ctx);
     if (igb_status st1 = need_system(op, "potential")) return st1;
     IGB_HIP(hipSetDevice(op->geom->ctx->device));
     return potential_device(op, coeffs, ndir, points, npts, u, pick(op->geom->ctx, hip_stream));
@@ -642,6 +721,7 @@ igb_status potential_h2(igb_op op, const double* coeffs, int ndir, const double*
         return IGB_ERR_ARG;
     }
     if (igb_status st = need_device(op, "potential_h2")) return st;
+    AllocScope scope(op->geom->ctx);
     if (igb_status st1 = need_system(op, "potential_h2")) return st1;
     IGB_HIP(hipSetDevice(op->geom->ctx->device));
     return potential_h2_device(op, coeffs, ndir, points, npts, u, pick(op->geom->ctx, hip_stream));

@@ -46,33 +46,65 @@ void set_error(const char* fmt, ...);
         }                                                                          \
     } while (0)
 
-// ----------------------------------------------------------------------------
-// device memory owned by a handle; freed in the destructor
-// ----------------------------------------------------------------------------
-struct DevBuf {
-    void* ptr = nullptr;
-    size_t bytes = 0;
-    DevBuf() = default;
-    DevBuf(const DevBuf&) = delete;
-    DevBuf& operator=(const DevBuf&) = delete;
-    ~DevBuf() { release(); }
-    void release() {
-        if (ptr) (void)hipFree(ptr);
-        ptr = nullptr;
-        bytes = 0;
-    }
-    template <class T> T* as() const { return static_cast<T*>(ptr); }
-};
-
 }  // namespace igb
 
 struct igb_ctx_s {
     int refs = 1;        // the caller's handle + one per live geometry
     int device = 0;
     size_t budget = 0;   // bytes the library may hold on this device (0 = no limit)
-    size_t used = 0;     // bytes currently held by live geometries / operators
+    // bytes currently held on the device: every allocation of the context's
+    // geometries and operators (tables, work vectors, Krylov bases, temporaries)
+    std::atomic<size_t> used{0};
     hipStream_t stream = nullptr;
 };
+
+namespace igb {
+
+// HBM budget accounting.  Every device allocation of the library is charged to
+// a context: the one whose entry point runs on this thread (set by AllocScope
+// at each entry point); the buffer remembers it and credits the bytes back
+// when released.  charge() fails, changing nothing, if the budget would be
+// exceeded.
+igb_ctx_s*& alloc_ctx();
+struct AllocScope {
+    igb_ctx_s* prev;
+    explicit AllocScope(igb_ctx_s* c) : prev(alloc_ctx()) { alloc_ctx() = c; }
+    ~AllocScope() { alloc_ctx() = prev; }
+};
+bool charge(igb_ctx_s* c, size_t bytes);
+inline void uncharge(igb_ctx_s* c, size_t bytes) { c->used.fetch_sub(bytes); }
+
+// ----------------------------------------------------------------------------
+// device memory owned by a handle; freed in the destructor
+// ----------------------------------------------------------------------------
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    igb_ctx_s* ctx = nullptr;   // context charged for the bytes
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        if (ctx) uncharge(ctx, bytes);
+        ptr = nullptr;
+        bytes = 0;
+        ctx = nullptr;
+    }
+    template <class T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+// Releases b, then allocates `bytes` charged to alloc_ctx(): IGB_ERR_BUDGET
+// (message naming `who`) if that context's budget would be exceeded,
+// IGB_ERR_HIP if hipMalloc fails; b is empty after either.
+igb_status dev_malloc(DevBuf& b, size_t bytes, const char* who);
+// As dev_malloc, but keeps b when it already holds at least `bytes`.
+inline igb_status dev_reserve(DevBuf& b, size_t bytes, const char* who) {
+    return b.bytes >= bytes && b.ptr ? IGB_OK : dev_malloc(b, bytes, who);
+}
+
+}  // namespace igb
 
 // Per-element data of a discretised geometry.
 struct igb_geom_s {
@@ -192,8 +224,12 @@ struct igb_op_s {
     igb::DevBuf d_xhat, d_yhat, d_yraw, d_part, d_yfar, d_x2, d_cluoff, d_leafbuf;
     size_t dev_bytes = 0;
     int64_t nclusters = 0;
-    // solver scratch
-    igb::DevBuf d_krylov, d_w, d_h, d_b, d_dotpart;
+    // solver scratch (kept between solves, grown on demand): Krylov basis and
+    // work vectors, Hessenberg steps, right-hand sides, refinement residual and
+    // corrections
+    igb::DevBuf d_krylov, d_w, d_h, d_b, d_dotpart, d_ref_r, d_ref_d, d_ref_d2;
+    // device copies of host columns (h2_matvec with IGB_MV_HOST)
+    igb::DevBuf d_hx, d_hy;
     // false for a single boundary integral operator (no right-hand side or representation)
     bool system = true;
     // lazy sum y = sum_i sum_coef[i] sum_parts[i] x of separately stored H^2 matrices
@@ -204,7 +240,8 @@ struct igb_op_s {
     int krylov_cols = 0;
     int work_cols = 0;   // columns the matvec work buffers are sized for
     double t_assembly_near = 0, t_assembly_far = 0;
-    size_t estimated_bytes = 0;
+    size_t estimated_bytes = 0;   // data + one-column work vectors + a GMRES(30) basis for one column
+    size_t estimated_data = 0;    // operator data alone (tables, near field, couplings)
     // per-kernel timing: 0 m2l, 1 spmv, 2 upward, 3 downward
     bool profile = false;
     KernelTimer timers[4];
@@ -237,6 +274,15 @@ struct igb_op_s {
 
 namespace igb {
 
+// dev_reserve for a buffer owned by the operator, keeping its byte count
+inline igb_status op_reserve(igb_op op, DevBuf& b, size_t bytes, const char* who) {
+    if (b.bytes >= bytes && b.ptr) return IGB_OK;
+    op->dev_bytes -= std::min(op->dev_bytes, b.bytes);
+    const igb_status st = dev_malloc(b, bytes, who);
+    op->dev_bytes += b.bytes;
+    return st;
+}
+
 // host stages
 igb_status geometry_build(igb_ctx ctx, const igb_patch* patches, int npatch, int m, int p,
                           igb_geom g);
@@ -249,6 +295,17 @@ igb_status upload_geometry(igb_geom g);
 igb_status assemble_near_device(igb_op op, hipStream_t s);
 igb_status assemble_far_device(igb_op op, hipStream_t s);
 igb_status alloc_work(igb_op op, int nrhs);
+// bytes of the matvec work buffers for ncol columns (alloc_work's sizes)
+struct WorkSizes {
+    enum { XHAT, YHAT, YRAW, PART, XLO, PART_LO, XNEAR_LO, YFAR, X2, LEAFBUF, COUNT };
+    size_t b[COUNT];
+    size_t total() const {
+        size_t t = 0;
+        for (size_t v : b) t += v;
+        return t;
+    }
+};
+WorkSizes work_sizes(const igb_op_s* op, int ncol);
 igb_status matvec_device(igb_op op, const double* x, double* y, int nrhs, int parts,
                          hipStream_t s);
 igb_status rhs_device(igb_op op, const double* dirs, int ndir, double* b, hipStream_t s);
@@ -285,6 +342,13 @@ igb_status potential_h2_device(igb_op op, const double* coeffs, int ndir, const 
                                hipStream_t s);
 igb_status gmres_device(igb_op op, const double* b, double* x, int ndir,
                         const igb_solve_params* sp, igb_solve_info* info, hipStream_t s);
+// bytes of cfie_solve's own buffers for ndir columns and restart m: Krylov basis,
+// work vectors, Hessenberg steps, inner-product partials, right-hand sides and
+// (reduced-precision operators) the refinement residual and corrections
+size_t solve_buffer_bytes(const igb_op_s* op, int m, int ndir);
+// device bytes an operator holds after cfie_solve(ndir, restart m): its data,
+// the matvec work vectors of ndir columns and solve_buffer_bytes
+size_t solve_model_bytes(const igb_op_s* op, int m, int ndir);
 
 // kernel timing helpers (no-ops unless op->profile)
 igb_status timer_mark(igb_op op, int slot, hipStream_t s);

@@ -175,25 +175,42 @@ struct Work {
     double2* hp;   // pinned host copy of h, h2 and the squared norms
 };
 
+struct SolveSizes {
+    size_t krylov, w, h, dotpart, rhs, ref;   // ref: each of the three refinement buffers
+};
+SolveSizes solve_sizes(const igb_op_s* op, int m, int C) {
+    const size_t n = size_t(op->N);
+    const size_t nseg = (n + DOT_SEG - 1) / DOT_SEG;
+    SolveSizes z;
+    z.krylov = size_t(m + 1) * C * n * sizeof(double2);
+    z.w = size_t(4) * C * n * sizeof(double2);
+    z.h = size_t(3) * (m + 2) * C * sizeof(double2) + size_t(2) * C * sizeof(double) + 64;
+    z.dotpart = size_t(m + 1) * C * nseg * sizeof(double2);
+    z.rhs = size_t(C) * n * sizeof(double2);
+    z.ref = op->prm.precision != IGB_FP64 ? size_t(C) * n * sizeof(double2) : 0;
+    return z;
+}
+
 igb_status ensure_work(igb_op op, int m, int C, Work& W) {
     const int64_t n = op->N;
-    const size_t need_v = size_t(m + 1) * C * n * sizeof(double2);
-    const size_t need_w = size_t(4) * C * n * sizeof(double2);
-    const size_t need_h = size_t(3) * (m + 2) * C * sizeof(double2) + size_t(2) * C * sizeof(double) + 64;
-    auto grow = [&](igb::DevBuf& b, size_t bytes) -> igb_status {
-        if (b.bytes >= bytes) return IGB_OK;
-        op->dev_bytes -= std::min(op->dev_bytes, b.bytes);
-        b.release();
-        IGB_HIP(hipMalloc(&b.ptr, bytes));
-        b.bytes = bytes;
-        op->dev_bytes += bytes;
-        return IGB_OK;
-    };
+    const SolveSizes z = solve_sizes(op, m, C);
+    const size_t need_h = z.h;
+    // the budget check covers the whole growth before anything is released
+    igb_ctx ctx = op->geom->ctx;
+    size_t grow_by = 0;
+    for (auto bs : {std::make_pair(&op->d_krylov, z.krylov), std::make_pair(&op->d_w, z.w),
+                    std::make_pair(&op->d_h, z.h), std::make_pair(&op->d_dotpart, z.dotpart)})
+        grow_by += bs.first->bytes >= bs.second ? 0 : bs.second - bs.first->bytes;
+    if (ctx->budget != 0 && ctx->used.load() + grow_by > ctx->budget) {
+        set_error("cfie_solve: HBM budget exceeded by the Krylov bases of %d columns (%zu held + %zu > %zu bytes)", C,
+                  ctx->used.load(), grow_by, ctx->budget);
+        return IGB_ERR_BUDGET;
+    }
     igb_status st;
     const int nseg = int((n + DOT_SEG - 1) / DOT_SEG);
-    const size_t need_p = size_t(m + 1) * C * nseg * sizeof(double2);
-    if ((st = grow(op->d_krylov, need_v)) || (st = grow(op->d_w, need_w)) || (st = grow(op->d_h, need_h)) ||
-        (st = grow(op->d_dotpart, need_p)))
+    if ((st = op_reserve(op, op->d_krylov, z.krylov, "cfie_solve")) || (st = op_reserve(op, op->d_w, z.w, "cfie_solve")) ||
+        (st = op_reserve(op, op->d_h, z.h, "cfie_solve")) ||
+        (st = op_reserve(op, op->d_dotpart, z.dotpart, "cfie_solve")))
         return st;
     W.nseg = nseg;
     W.part = op->d_dotpart.as<double2>();
@@ -234,8 +251,11 @@ igb_status norms(const double2* v, int64_t n, int C, double* dev_tmp, std::vecto
 // Lockstep restarted GMRES for C columns: every column runs its own Arnoldi
 // process and Givens rotations; the operator is applied to all columns at once.
 // X = 0 initially; column c stops when its recursive relative residual reaches
-// tol[c] (or after maxit[c] Arnoldi steps).  Columns never interact, so a column's
-// iterates do not depend on which other columns share the batch.
+// tol[c] (or after maxit[c] Arnoldi steps).  Columns never interact; the block
+// matvec always covers all C columns, so a column's iterates depend on the batch
+// only through the matvec's code path: fp64 operators with stored couplings
+// take the matrix-core coupling for C >= 16 (another summation order, equal to
+// the vector path up to rounding), every other case is bitwise batch invariant.
 igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, const std::vector<int>& maxit,
                        const std::vector<double>& tol, int mvflags, hipStream_t s, std::vector<ColumnResult>& res,
                        const SolveLog& log) {
@@ -384,6 +404,18 @@ igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, 
 
 }  // namespace
 
+size_t solve_buffer_bytes(const igb_op_s* op, int m, int ndir) {
+    const SolveSizes z = solve_sizes(op, m, ndir);
+    return z.krylov + z.w + z.h + z.dotpart + z.rhs + 3 * z.ref;
+}
+
+size_t solve_model_bytes(const igb_op_s* op, int m, int ndir) {
+    size_t b = solve_buffer_bytes(op, m, ndir);
+    if (op->sum_parts.empty()) return b + op->estimated_data + work_sizes(op, ndir).total();
+    for (const igb_op_s* p : op->sum_parts) b += p->estimated_data + work_sizes(p, ndir).total();
+    return b + size_t(ndir) * op->N * sizeof(double2);   // the lazy sum's column buffer
+}
+
 igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, const igb_solve_params* sp,
                         igb_solve_info* info, hipStream_t s) {
     const int64_t n = op->N;
@@ -418,11 +450,12 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
         const int refine_max = sp->refine_max > 0 ? sp->refine_max : 10;
         // the outer residual and corrections live in separate buffers from the
         // inner solver's work vectors
-        igb::DevBuf rbuf, dbuf, d2buf;
-        IGB_HIP(hipMalloc(&rbuf.ptr, size_t(n) * C * sizeof(double2)));
-        IGB_HIP(hipMalloc(&dbuf.ptr, size_t(n) * C * sizeof(double2)));
-        double2* R = rbuf.as<double2>();
-        double2* D = dbuf.as<double2>();
+        const size_t colbytes = size_t(n) * C * sizeof(double2);
+        if ((st = op_reserve(op, op->d_ref_r, colbytes, "cfie_solve")) ||
+            (st = op_reserve(op, op->d_ref_d, colbytes, "cfie_solve")))
+            return st;
+        double2* R = op->d_ref_r.as<double2>();
+        double2* D = op->d_ref_d.as<double2>();
         double2* D2 = nullptr;
         IGB_HIP(hipMemsetAsync(X, 0, n * C * sizeof(double2), s));
         IGB_HIP(hipMemcpyAsync(R, B, n * C * sizeof(double2), hipMemcpyDeviceToDevice, s));
@@ -468,8 +501,8 @@ igb_status gmres_device(igb_op op, const double* b_in, double* x_out, int ndir, 
             }
             if (any_hi) {
                 if (!D2) {
-                    IGB_HIP(hipMalloc(&d2buf.ptr, size_t(n) * C * sizeof(double2)));
-                    D2 = d2buf.as<double2>();
+                    if ((st = op_reserve(op, op->d_ref_d2, colbytes, "cfie_solve"))) return st;
+                    D2 = op->d_ref_d2.as<double2>();
                 }
                 log.phase = "inner (fp64)";
                 if ((st = gmres_block(op, W, R, D2, left_hi, tin, IGB_PART_ALL, s, part, log))) return st;

@@ -2404,23 +2404,20 @@ __global__ __launch_bounds__(POT_LEAF_POINTS) void pot_l2p_near(
 // ==========================================================================
 namespace {
 
+// device buffers, charged to the calling entry point's context (dev_malloc);
+// acct (if given) also counts them for the handle that owns them
 template <class T>
 igb_status upload(DevBuf& b, const T* src, size_t n, size_t* acct) {
-    b.release();
+    if (igb_status st = dev_malloc(b, n * sizeof(T), "device upload")) return st;
     if (n == 0) return IGB_OK;
-    IGB_HIP(hipMalloc(&b.ptr, n * sizeof(T)));
-    b.bytes = n * sizeof(T);
     if (acct) *acct += b.bytes;
     if (src) IGB_HIP(hipMemcpy(b.ptr, src, n * sizeof(T), hipMemcpyHostToDevice));
     return IGB_OK;
 }
 
 igb_status alloc(DevBuf& b, size_t bytes, size_t* acct) {
-    b.release();
-    if (bytes == 0) return IGB_OK;
-    IGB_HIP(hipMalloc(&b.ptr, bytes));
-    b.bytes = bytes;
-    if (acct) *acct += bytes;
+    if (igb_status st = dev_malloc(b, bytes, "device allocation")) return st;
+    if (acct) *acct += b.bytes;
     return IGB_OK;
 }
 
@@ -2915,6 +2912,43 @@ igb_status assemble_far_device(igb_op op, hipStream_t s) {
     return IGB_OK;
 }
 
+// Matvec work buffers of an operator for ncol columns, in bytes (0: not used):
+// cluster moments x^ / y^ (and the raw hard coupling results), coupling
+// partials of the vector and matrix-core paths, rounded source vectors, the
+// fp32 near-product columns of bf16 operators, the S^2 far-field result and
+// glued input, and the leaves' B-spline windows.
+WorkSizes work_sizes(const igb_op_s* op, int ncol) {
+    WorkSizes w{};
+    const size_t C = size_t(ncol), nq = size_t(op->nq);
+    const bool hard = op->bc == IGB_HARD;
+    const size_t kinds = hard ? 3 : 1, nvec = hard ? 10 : 1;
+    w.b[WorkSizes::XHAT] = C * kinds * op->nclusters * nq * sizeof(double2);
+    w.b[WorkSizes::YHAT] = w.b[WorkSizes::XHAT];
+    w.b[WorkSizes::YRAW] = hard ? C * nvec * op->nclusters * nq * sizeof(double2) : 0;
+    w.b[WorkSizes::PART] = C * std::max<size_t>(1, op->chunks.len.size()) * nvec * nq * sizeof(double2);
+    if (op->prm.precision != IGB_FP64 || mf_fp64(const_cast<igb_op>(op))) {
+        const size_t ncolp = (C + 15) / 16 * 16;
+        const size_t pt = op->prm.precision == IGB_FP64 ? sizeof(double2) : sizeof(float2);
+        igb_op o = const_cast<igb_op>(op);
+        w.b[WorkSizes::XLO] = size_t(op->nclusters) * (hard ? 7 : 1) * ncolp * lo_kbp(o) * lo_esz(o);
+        w.b[WorkSizes::PART_LO] = C * std::max<size_t>(1, op->chunks_mfma.len.size()) * nvec * nq * pt;
+    }
+    if (op->prm.precision == IGB_MIX_BF16 && op->nnz > 0)
+        w.b[WorkSizes::XNEAR_LO] = (C + 15) / 16 * 16 * op->N * sizeof(float2);
+    w.b[WorkSizes::YFAR] = C * op->geom->n2 * sizeof(double2);
+    w.b[WorkSizes::X2] = w.b[WorkSizes::YFAR];
+    const size_t win = (size_t(1) << op->d) + op->geom->p;
+    w.b[WorkSizes::LEAFBUF] = C * kinds * clusters_on_level(op->geom->npatch, op->L) * win * win * sizeof(double2);
+    return w;
+}
+
+static igb::DevBuf* work_buf(igb_op op, int i) {
+    igb::DevBuf* bufs[WorkSizes::COUNT] = {&op->d_xhat, &op->d_yhat, &op->d_yraw,  &op->d_part, &op->d_xlo,
+                                           &op->d_part_lo, &op->d_xnear_lo, &op->d_yfar, &op->d_x2,
+                                           &op->d_leafbuf};
+    return bufs[i];
+}
+
 igb_status alloc_work(igb_op op, int ncol) {
     size_t* acct = &op->dev_bytes;
     igb_status st;
@@ -2923,39 +2957,25 @@ igb_status alloc_work(igb_op op, int ncol) {
         if ((st = upload(op->d_cluoff, op->clu_off.data(), op->clu_off.size(), acct))) return st;
     }
     if (ncol <= op->work_cols) return IGB_OK;
-    const int nq = op->nq;
-    const bool hard = op->bc == IGB_HARD;
-    const int kinds = hard ? 3 : 1, nvec = hard ? 10 : 1;
+    const WorkSizes w = work_sizes(op, ncol);
+    // the budget check covers the whole growth before anything is released
+    size_t held = 0;
+    for (int i = 0; i < WorkSizes::COUNT; ++i) held += work_buf(op, i)->bytes;
+    igb_ctx ctx = op->geom->ctx;
+    if (ctx->budget != 0 && w.total() > held && ctx->used.load() + (w.total() - held) > ctx->budget) {
+        set_error("h2_matvec: HBM budget exceeded by the work vectors of %d columns (%zu held + %zu > %zu bytes)",
+                  ncol, ctx->used.load(), w.total() - held, ctx->budget);
+        return IGB_ERR_BUDGET;
+    }
     op->clear_graphs();   // captured launches refer to the buffers released here
-    for (igb::DevBuf* b : {&op->d_xhat, &op->d_yhat, &op->d_yraw, &op->d_part, &op->d_yfar, &op->d_x2, &op->d_leafbuf,
-                           &op->d_xlo, &op->d_part_lo}) {
+    op->work_cols = 0;    // until every buffer is in place
+    for (int i = 0; i < WorkSizes::COUNT; ++i) {
+        igb::DevBuf* b = work_buf(op, i);
         *acct -= std::min(*acct, b->bytes);
         b->release();
     }
-    const size_t C = size_t(ncol);
-    if ((st = alloc(op->d_xhat, C * kinds * op->nclusters * nq * sizeof(double2), acct))) return st;
-    if ((st = alloc(op->d_yhat, C * kinds * op->nclusters * nq * sizeof(double2), acct))) return st;
-    if (hard && (st = alloc(op->d_yraw, C * nvec * op->nclusters * nq * sizeof(double2), acct))) return st;
-    if ((st = alloc(op->d_part, C * std::max<size_t>(1, op->chunks.len.size()) * nvec * nq * sizeof(double2), acct)))
-        return st;
-    if (op->prm.precision != IGB_FP64 || mf_fp64(op)) {
-        const size_t ncolp = (C + 15) / 16 * 16;
-        const size_t pt = op->prm.precision == IGB_FP64 ? sizeof(double2) : sizeof(float2);
-        if ((st = alloc(op->d_xlo, size_t(op->nclusters) * (hard ? 7 : 1) * ncolp * lo_kbp(op) * lo_esz(op), acct)))
-            return st;
-        if ((st = alloc(op->d_part_lo, C * std::max<size_t>(1, op->chunks_mfma.len.size()) * nvec * nq * pt, acct)))
-            return st;
-    }
-    if (op->d_val_lo.ptr) {
-        *acct -= std::min(*acct, op->d_xnear_lo.bytes);
-        if ((st = alloc(op->d_xnear_lo, (C + 15) / 16 * 16 * op->N * sizeof(float2), acct))) return st;
-    }
-    if ((st = alloc(op->d_yfar, C * op->geom->n2 * sizeof(double2), acct))) return st;
-    if ((st = alloc(op->d_x2, C * op->geom->n2 * sizeof(double2), acct))) return st;
-    const int64_t w = (int64_t(1) << op->d) + op->geom->p;
-    if ((st = alloc(op->d_leafbuf, C * kinds * clusters_on_level(op->geom->npatch, op->L) * w * w * sizeof(double2),
-                    acct)))
-        return st;
+    for (int i = 0; i < WorkSizes::COUNT; ++i)
+        if (w.b[i] && (st = alloc(*work_buf(op, i), w.b[i], acct))) return st;
     op->work_cols = ncol;
     return IGB_OK;
 }
@@ -3133,12 +3153,8 @@ static igb_status matvec_sum(igb_op op, const double* x, double* y, int ncol, in
     }
     if ((st = matvec_device(op->sum_parts.front(), x, y, ncol, parts, s))) return st;
     if (op->sum_parts.size() < 2) return IGB_OK;
-    if (op->d_sum_tmp.bytes < size_t(n) * sizeof(double2)) {
-        // grows with the column count; freed with the operator
-        op->dev_bytes -= std::min(op->dev_bytes, op->d_sum_tmp.bytes);
-        op->d_sum_tmp.release();
-        if ((st = alloc(op->d_sum_tmp, size_t(n) * sizeof(double2), &op->dev_bytes))) return st;
-    }
+    // grows with the column count; freed with the operator
+    if ((st = op_reserve(op, op->d_sum_tmp, size_t(n) * sizeof(double2), "h2_matvec"))) return st;
     double2* t = op->d_sum_tmp.as<double2>();
     for (size_t i = 1; i < op->sum_parts.size(); ++i) {
         if ((st = matvec_device(op->sum_parts[i], x, reinterpret_cast<double*>(t), ncol, parts, s))) return st;

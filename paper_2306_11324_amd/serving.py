@@ -122,11 +122,12 @@ class Server:
         geo = B.Geometry(self.plan_ctx, self._patches(req), req.m, self.cfg.p)
         op = B.Operator(self.plan_ctx, geo, **self._op_args(req))
         nd = len(req.dirs)
-        n = op.info.n
         geom_bytes = geo.nelem * (16 * 4 * 8 + 8) + 4096
         restart = self.cfg.restart_soft if req.bc == "soft" else self.cfg.restart_hard
-        krylov = nd * n * 16 * (restart + 8) * 2    # basis and work vectors, refinement buffers
-        return int(op.info.estimated_bytes + geom_bytes + krylov + nd * self.cfg.nobs * 16)
+        # the library's size model of the operator after an nd-direction solve
+        # (data, matvec work vectors, Krylov bases, refinement buffers), plus the
+        # far-field output and temporaries
+        return int(op.solve_bytes(nd, restart) + geom_bytes + 4 * nd * self.cfg.nobs * 16 + (1 << 20))
 
     def solve(self, req: I.Request, ctx: B.Context):
         """Returns (n, solve info, far field [ndir][nobs], stage seconds)."""

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "igafmm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return set(re.findall(r"^\s*(?:igb_status|void|size_t|const char\*)\s+(\w+)\s*\(", src, flags=re.M))
+    return set(re.findall(r"^\s*(?:igb_status|void|size_t|int64_t|const char\*)\s+(\w+)\s*\(", src, flags=re.M))
 
 
 def test_exports_every_declared_symbol():
@@ -141,6 +141,37 @@ def test_budget_rejects_before_allocating():
     with pytest.raises(B.IgbError) as e:
         B.Geometry(ctx, I.sphere_patches(), 3, 2)
     assert e.value.status == -3
+
+
+@pytest.mark.parametrize("bc,prec", [("soft", "fp64"), ("hard", "bf16")])
+def test_budget_rejects_a_solve_that_would_not_fit(bc, prec):
+    """cfie_solve checks its growth (matvec work vectors of ndir columns, Krylov
+    bases, right-hand sides, refinement buffers: the solve size model) against
+    the budget before any work: with a budget halfway between the models of a
+    one-direction and a 2048-direction solve, 2048 directions are rejected with
+    IGB_ERR_BUDGET; one direction passes the check and then fails as any
+    compute call on a host-only context does (IGB_ERR_ARG)."""
+    probe = B.Context(B.IGB_HOST_ONLY)
+    args = dict(kappa=2.0, q=4, leaf_depth=1, bc=B.SOFT if bc == "soft" else B.HARD,
+                precision=B.FP64 if prec == "fp64" else B.MIX_BF16)
+    geo0 = B.Geometry(probe, I.sphere_patches(), 3, 2)
+    op0 = B.Operator(probe, geo0, **args)
+    ndir = 2048
+    one, many = op0.solve_bytes(1), op0.solve_bytes(ndir)
+    assert one == op0.info.estimated_bytes
+    assert many > one + (ndir - 1) * 31 * op0.n * 16        # at least ndir Krylov bases of 31 vectors
+    assert B._lib.igb_op_ndof(op0.h) == op0.n and B._lib.igb_op_bytes(op0.h) == 0
+    ctx = B.Context(B.IGB_HOST_ONLY, hbm_budget=(one + many) // 2)
+    geo = B.Geometry(ctx, I.sphere_patches(), 3, 2)
+    op = B.Operator(ctx, geo, **args)
+    coeffs = B.C.c_void_p(16)   # never dereferenced: both calls stop before any work
+    sp = B.IgbSolveParams(1e-8, 30, 100, 0.0, 0, 0)
+    info = B.IgbSolveInfo()
+    dirs = np.ascontiguousarray(I.random_directions(3, ndir))
+    pd = dirs.ctypes.data_as(B.C.POINTER(B.C.c_double))
+    assert B._lib.cfie_solve(op.h, pd, ndir, B.C.byref(sp), coeffs, B.C.byref(info)) == -3
+    assert "budget" in B._lib.igb_last_error().decode()
+    assert B._lib.cfie_solve(op.h, pd, 1, B.C.byref(sp), coeffs, B.C.byref(info)) == -1
 
 
 def test_handles_destroyed_in_any_order():
