@@ -322,6 +322,26 @@ igb_status igb_op_use_graphs(igb_op op, int enable);
  * overlap.  Stream-ordered. */
 igb_status h2_matvec(igb_op op, const double* x, double* y, int nrhs, int parts, void* hip_stream);
 
+/* Allocation-free variant of h2_matvec, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, layout and results as h2_matvec (device arrays
+ * only: IGB_MV_HOST is rejected), computed by the same kernels, but the matvec
+ * work buffers (cluster moments, coupling partials, rounded source vectors,
+ * far-field result) are carved out of one static device array of
+ * IGB_NOALLOC_SCRATCH_BYTES per GPU, which every context creation on that GPU
+ * locates once and which the process holds until it ends.  The call allocates
+ * nothing (no hipMalloc, no library routine that allocates) and uses no HIP
+ * graph.  Limits and errors: IGB_ERR_ARG if the work buffers of nrhs columns
+ * exceed the scratch (e.g. the level-5 sphere at q = 6 fits 16 fp64 columns),
+ * if per-kernel profiling is enabled on the operator, or for invalid
+ * arguments; IGB_ERR_UNSUPPORTED for operators stored as separate H^2
+ * matrices.  Every call on one GPU shares that GPU's scratch (it keeps the last
+ * call's contents; nothing in it needs to start at zero): calls that overlap on
+ * one GPU -- on different streams, or from different host threads without
+ * ordering -- race and give wrong results.  Stream-ordered like h2_matvec. */
+#define IGB_NOALLOC_SCRATCH_BYTES (256u << 20)
+igb_status h2_matvec_noalloc(igb_op op, const double* x, double* y, int nrhs, int parts, void* hip_stream);
+
 /* Right-hand sides (Sec. 4.1 load vectors of the D2N / N2D systems) for ndir
  * incident plane waves e^{i kappa <d,x>} (host dirs [ndir][3], normalised here;
  * error if |d| < 1e-12) into the device array b [ndir][n].  Stream-ordered. */

@@ -87,6 +87,7 @@ _SIGS = {
     "igb_op_far_blocks": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "igb_op_near_pairs": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "h2_matvec": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, _P]),
+    "h2_matvec_noalloc": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, _P]),
     "cfie_rhs": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int, _P, _P]),
     "cfie_solve": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int, C.POINTER(IgbSolveParams), _P,
                              C.POINTER(IgbSolveInfo)]),
@@ -278,6 +279,13 @@ class Operator:
         else:
             xs, ys = _dptr(x, nrhs * self.n), _dptr(y, nrhs * self.n)
         _check("h2_matvec", _lib.h2_matvec(self.h, xs, ys, nrhs, parts, _stream(stream)))
+        return y
+
+    def h2_matvec_noalloc(self, x, y, nrhs: int = 1, parts: int = PART_ALL, stream=None):
+        """h2_matvec with the work buffers in the library's per-GPU scratch array
+        (allocates nothing; calls overlapping on one GPU race)."""
+        _check("h2_matvec_noalloc", _lib.h2_matvec_noalloc(self.h, _dptr(x, nrhs * self.n),
+                                                           _dptr(y, nrhs * self.n), nrhs, parts, _stream(stream)))
         return y
 
     def cfie_rhs(self, dirs, b, stream=None):

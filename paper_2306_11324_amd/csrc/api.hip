@@ -127,6 +127,11 @@ igb_status igb_ctx_create(int device, size_t hbm_budget_bytes, igb_ctx* out) {
     }
     c->device = device;
     c->budget = hbm_budget_bytes;
+    // locate this device's matvec scratch array (h2_matvec_noalloc) once
+    if (igb_status st = scratch_init(device)) {
+        delete c;
+        return st;
+    }
     hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete c;
@@ -640,6 +645,28 @@ igb_status h2_matvec(igb_op op, const double* x, double* y, int nrhs, int parts,
     IGB_HIP(hipMemcpyAsync(y, op->d_hy.ptr, bytes, hipMemcpyDeviceToHost, s));
     IGB_HIP(hipStreamSynchronize(s));
     return IGB_OK;
+}
+
+igb_status h2_matvec_noalloc(igb_op op, const double* x, double* y, int nrhs, int parts, void* hip_stream) {
+    if (!op || !x || !y || nrhs < 1 || (parts & 3) == 0 || parts > 7) {
+        set_error("h2_matvec_noalloc: invalid argument (device arrays only; IGB_MV_HOST is not accepted)");
+        return IGB_ERR_ARG;
+    }
+    if (x == y) {
+        set_error("h2_matvec_noalloc: x and y must not overlap");
+        return IGB_ERR_ARG;
+    }
+    if (igb_status st = need_device(op, "h2_matvec_noalloc")) return st;
+    if (!op->sum_parts.empty()) {
+        set_error("h2_matvec_noalloc: not available on an operator stored as separate H^2 matrices");
+        return IGB_ERR_UNSUPPORTED;
+    }
+    if (op->profile) {
+        set_error("h2_matvec_noalloc: per-kernel profiling is enabled on the operator (it records events)");
+        return IGB_ERR_ARG;
+    }
+    IGB_HIP(hipSetDevice(op->geom->ctx->device));
+    return matvec_noalloc(op, x, y, nrhs, parts, pick(op->geom->ctx, hip_stream));
 }
 
 igb_status cfie_rhs(igb_op op, const double* dirs, int ndir, double* b, void* hip_stream) {

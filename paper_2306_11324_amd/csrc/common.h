@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -306,6 +307,19 @@ struct WorkSizes {
     }
 };
 WorkSizes work_sizes(const igb_op_s* op, int ncol);
+// device addresses of the matvec work buffers (the operator's own, or carved out
+// of the per-device scratch array by the allocation-free matvec)
+struct MatvecWork {
+    double2 *xhat = nullptr, *yhat = nullptr, *yraw = nullptr, *part = nullptr;
+    void *xlo = nullptr, *part_lo = nullptr;
+    float2* xnear_lo = nullptr;
+    double2 *yfar = nullptr, *x2 = nullptr, *leafbuf = nullptr;
+};
+constexpr int SCRATCH_MAX_DEVICES = 64;
+// takes the device address of the scratch array of the current device (once per device)
+igb_status scratch_init(int device);
+// y = A x with the work buffers in the scratch array; allocates nothing
+igb_status matvec_noalloc(igb_op op, const double* x, double* y, int ncol, int parts, hipStream_t s);
 igb_status matvec_device(igb_op op, const double* x, double* y, int nrhs, int parts,
                          hipStream_t s);
 igb_status rhs_device(igb_op op, const double* dirs, int ndir, double* b, hipStream_t s);

@@ -2995,7 +2995,7 @@ igb_status timer_mark(igb_op op, int slot, hipStream_t s) {
 // vector path (fp64 couplings): the soft kernel keeps 8 accumulators per lane,
 // the hard one 10 per column
 template <int NT>
-static void launch_m2l_fp64(igb_op op, double2* xh, int64_t ks, int ncol, hipStream_t s) {
+static void launch_m2l_fp64(igb_op op, const MatvecWork& W, double2* xh, int64_t ks, int ncol, hipStream_t s) {
     const double2* coup = op->d_coupling.as<double2>();
     const M2LChunks& C = op->chunks;
     const int64_t nchunk = int64_t(C.len.size());
@@ -3007,13 +3007,13 @@ static void launch_m2l_fp64(igb_op op, double2* xh, int64_t ks, int ncol, hipStr
             hipLaunchKernelGGL((m2l_otf_hard<NT, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
                                dim3(NT), 0, s, nd, xh, ks, op->d_far_src.as<int>(), C.d_tgt.as<int>(),
                                C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol, op->kappa,
-                               op->d_part.as<double2>());
+                               W.part);
         } else {
             constexpr int RB = 8;
             hipLaunchKernelGGL((m2l_otf_soft<NT, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
                                dim3(NT), 0, s, nd, xh, op->d_far_src.as<int>(), C.d_tgt.as<int>(),
                                C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol, op->kappa, op->mix,
-                               op->d_part.as<double2>());
+                               W.part);
         }
         return;
     }
@@ -3021,43 +3021,43 @@ static void launch_m2l_fp64(igb_op op, double2* xh, int64_t ks, int ncol, hipStr
         constexpr int RB = 2;
         hipLaunchKernelGGL((m2l_hard_chunks<NT, double2, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
                            dim3(NT), 0, s, coup, xh, ks, op->d_nodes.as<double>(), op->d_far_src.as<int>(),
-                           C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol, op->d_part.as<double2>());
+                           C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol, W.part);
     } else if (ncol == 1 && op->d_lr.ptr) {
         hipLaunchKernelGGL(m2l_chunks_lowrank, dim3(unsigned(nchunk)), dim3(64), 0, s, op->d_lr.as<double2>(),
                            op->d_lr_rank.as<int>(), op->d_lr_off.as<int64_t>(), xh, op->d_far_src.as<int>(),
-                           C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, op->d_part.as<double2>());
+                           C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, W.part);
     } else if (ncol == 1 && op->nq <= 64) {
         hipLaunchKernelGGL(m2l_chunks_wave, dim3(unsigned(nchunk)), dim3(64), 0, s, coup, xh, op->d_far_src.as<int>(),
-                           C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, op->d_part.as<double2>());
+                           C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, W.part);
     } else if (ncol == 1) {
         hipLaunchKernelGGL((m2l_chunks<NT, double2, 1>), dim3(unsigned(nchunk), 1u), dim3(NT), 0, s, coup, xh,
                            op->d_far_src.as<int>(), C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol,
-                           op->d_part.as<double2>());
+                           W.part);
     } else {
         constexpr int RB = 8;
         hipLaunchKernelGGL((m2l_chunks<NT, double2, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
                            dim3(NT), 0, s, coup, xh, op->d_far_src.as<int>(), C.d_pair.as<int64_t>(), C.d_len.as<int>(),
-                           nchunk, op->nq, ncol, op->d_part.as<double2>());
+                           nchunk, op->nq, ncol, W.part);
     }
 }
 
 // matrix-core path (reduced-precision couplings)
 template <class OPS, bool HARD>
-static void launch_m2l_lo_t(igb_op op, const double2* xh, int64_t ks, int ncol, hipStream_t s) {
+static void launch_m2l_lo_t(igb_op op, const MatvecWork& W, const double2* xh, int64_t ks, int ncol, hipStream_t s) {
     using LT = typename OPS::LT;
     const M2LChunks& C = op->chunks_mfma;
     const int64_t nchunk = int64_t(C.len.size());
     const int ncolp = (ncol + 15) / 16 * 16, kbp = lo_kbp(op), nq = op->nq;
     const int64_t nv = op->nclusters * (HARD ? 7 : 1) * ncolp * kbp;
     hipLaunchKernelGGL((round_vectors<HARD ? 7 : 1, LT>), dim3(unsigned((nv + 255) / 256)), dim3(256), 0, s, xh, ks,
-                       op->d_nodes.as<double>(), op->nclusters, nq, kbp, ncol, ncolp, op->d_xlo.as<LT>());
+                       op->d_nodes.as<double>(), op->nclusters, nq, kbp, ncol, ncolp, static_cast<LT*>(W.xlo));
     (void)timer_mark(op, 0, s);
     using PT = typename OPS::PT;
     const LT* cp = op->prm.precision == IGB_FP64 ? op->d_coupling.as<LT>() : op->d_coupling_lo.as<LT>();
     if (!HARD && nchunk > 0) {
         const dim3 grid(unsigned(nchunk), unsigned(ncolp / 16));
-        const LT* xp = op->d_xlo.as<LT>();
-        PT* pp = op->d_part_lo.as<PT>();
+        const LT* xp = static_cast<LT*>(W.xlo);
+        PT* pp = static_cast<PT*>(W.part_lo);
 #define IGB_SOFT_MT(MTV)                                                                                          \
     hipLaunchKernelGGL((m2l_mfma_soft<OPS, MTV>), grid, dim3(256), 0, s, cp, lo_nkc(op), xp, kbp, ncolp,           \
                        op->d_far_src.as<int>(), C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, nq, ncol, pp)
@@ -3074,24 +3074,24 @@ static void launch_m2l_lo_t(igb_op op, const double2* xh, int64_t ks, int ncol, 
 #undef IGB_SOFT_MT
     } else if (nchunk > 0)
         hipLaunchKernelGGL((m2l_mfma<OPS, HARD>), dim3(unsigned(nchunk), unsigned(ncolp / 16)),
-                           dim3(64 * ((nq + 15) / 16)), 0, s, cp, lo_nkc(op), op->d_xlo.as<LT>(), kbp, ncolp,
+                           dim3(64 * ((nq + 15) / 16)), 0, s, cp, lo_nkc(op), static_cast<LT*>(W.xlo), kbp, ncolp,
                            op->d_far_src.as<int>(), C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, nq, ncol,
-                           op->d_part_lo.as<PT>());
+                           static_cast<PT*>(W.part_lo));
     (void)timer_mark(op, 0, s);
 }
 
 // coupling partials [chunk][nvec][nq][ncol] of the far pairs.  kind: 0 fp64
 // partials of the vector path, 1 fp32 partials of the matrix-core path at
 // reduced precision, 2 fp64 partials of the matrix-core path
-static igb_status launch_m2l(igb_op op, double2* xh, int64_t ks, bool low, int ncol, hipStream_t s, int& kind) {
+static igb_status launch_m2l(igb_op op, const MatvecWork& W, double2* xh, int64_t ks, bool low, int ncol, hipStream_t s, int& kind) {
     const bool lo = low && op->prm.precision != IGB_FP64;
     const bool hard = op->bc == IGB_HARD;
     // fp64: the matrix cores pay off for blocks of at least MF64_MIN_COLS
     // columns; a single column is HBM-bound on the vector path
     kind = lo ? 1 : (mf_fp64(op) && ncol >= MF64_MIN_COLS) ? 2 : 0;
     if (kind == 2) {
-        if (hard) launch_m2l_lo_t<MfmaF64, true>(op, xh, ks, ncol, s);
-        else launch_m2l_lo_t<MfmaF64, false>(op, xh, ks, ncol, s);
+        if (hard) launch_m2l_lo_t<MfmaF64, true>(op, W, xh, ks, ncol, s);
+        else launch_m2l_lo_t<MfmaF64, false>(op, W, xh, ks, ncol, s);
     } else if (!lo) {
         if ((op->nq + 63) / 64 * 64 > 128) {
             set_error("h2_matvec: interpolation degree too large for the coupling kernel");
@@ -3099,15 +3099,15 @@ static igb_status launch_m2l(igb_op op, double2* xh, int64_t ks, bool low, int n
         }
         igb_status st;
         if ((st = timer_mark(op, 0, s))) return st;
-        if (op->nq <= 64) launch_m2l_fp64<64>(op, xh, ks, ncol, s);
-        else launch_m2l_fp64<128>(op, xh, ks, ncol, s);
+        if (op->nq <= 64) launch_m2l_fp64<64>(op, W, xh, ks, ncol, s);
+        else launch_m2l_fp64<128>(op, W, xh, ks, ncol, s);
         if ((st = timer_mark(op, 0, s))) return st;
     } else if (op->prm.precision == IGB_MIX_FP32) {
-        if (hard) launch_m2l_lo_t<MfmaF32, true>(op, xh, ks, ncol, s);
-        else launch_m2l_lo_t<MfmaF32, false>(op, xh, ks, ncol, s);
+        if (hard) launch_m2l_lo_t<MfmaF32, true>(op, W, xh, ks, ncol, s);
+        else launch_m2l_lo_t<MfmaF32, false>(op, W, xh, ks, ncol, s);
     } else {
-        if (hard) launch_m2l_lo_t<MfmaBf16, true>(op, xh, ks, ncol, s);
-        else launch_m2l_lo_t<MfmaBf16, false>(op, xh, ks, ncol, s);
+        if (hard) launch_m2l_lo_t<MfmaBf16, true>(op, W, xh, ks, ncol, s);
+        else launch_m2l_lo_t<MfmaBf16, false>(op, W, xh, ks, ncol, s);
     }
     IGB_HIP(hipGetLastError());
     return IGB_OK;
@@ -3115,7 +3115,8 @@ static igb_status launch_m2l(igb_op op, double2* xh, int64_t ks, bool low, int n
 
 static inline unsigned blocks_for(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 
-static igb_status matvec_launches(igb_op op, const double* x, double* y, int ncol, int parts, hipStream_t s);
+static igb_status matvec_launches(igb_op op, const MatvecWork& W, const double* x, double* y, int ncol, int parts,
+                                  hipStream_t s);
 
 // y = A x: the launch sequence is captured once per (x, y, columns, parts,
 // stream) into a HIP graph and replayed; it holds kernel launches only (no
@@ -3165,11 +3166,99 @@ static igb_status matvec_sum(igb_op op, const double* x, double* y, int ncol, in
     return IGB_OK;
 }
 
+// the operator's own work buffers
+static MatvecWork own_work(igb_op op) {
+    MatvecWork W;
+    W.xhat = op->d_xhat.as<double2>();
+    W.yhat = op->d_yhat.as<double2>();
+    W.yraw = op->d_yraw.as<double2>();
+    W.part = op->d_part.as<double2>();
+    W.xlo = op->d_xlo.ptr;
+    W.part_lo = op->d_part_lo.ptr;
+    W.xnear_lo = op->d_xnear_lo.as<float2>();
+    W.yfar = op->d_yfar.as<double2>();
+    W.x2 = op->d_x2.as<double2>();
+    W.leafbuf = op->d_leafbuf.as<double2>();
+    return W;
+}
+
+// ---------------------------------------------------------------------------
+// Work buffers without allocation: one file-scope device array per GPU.  In
+// host code `scratch` names a host-side stand-in, so host code uses only the
+// device address that hipGetSymbolAddress returned for the current device,
+// taken once per device at context creation (scratch_init).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[IGB_NOALLOC_SCRATCH_BYTES];
+static std::mutex scratch_mu;
+static void* scratch_dev[SCRATCH_MAX_DEVICES];
+
+igb_status scratch_init(int device) {
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) {
+        set_error("igb_ctx_create: device %d beyond the %d devices the matvec scratch supports", device,
+                  SCRATCH_MAX_DEVICES);
+        return IGB_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (scratch_dev[device]) return IGB_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));   // device `device` is current
+    if (e != hipSuccess || !ptr) {
+        set_error("igb_ctx_create: hipGetSymbolAddress of the matvec scratch failed: %s", hipGetErrorString(e));
+        return IGB_ERR_HIP;
+    }
+    scratch_dev[device] = ptr;
+    return IGB_OK;
+}
+
+igb_status matvec_noalloc(igb_op op, const double* x, double* y, int ncol, int parts, hipStream_t s) {
+    const int dev = op->geom->ctx->device;
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(scratch_mu);
+        base = dev >= 0 && dev < SCRATCH_MAX_DEVICES ? scratch_dev[dev] : nullptr;
+    }
+    if (!base) {
+        set_error("h2_matvec_noalloc: no scratch address for device %d (context not created on it)", dev);
+        return IGB_ERR_ARG;
+    }
+    if (!op->d_cluoff.ptr) {
+        set_error("h2_matvec_noalloc: operator not assembled on the device");
+        return IGB_ERR_ARG;
+    }
+    // carve the work buffers out of the scratch, each 256-byte aligned
+    const WorkSizes w = work_sizes(op, ncol);
+    size_t off[WorkSizes::COUNT], end = 0;
+    for (int i = 0; i < WorkSizes::COUNT; ++i) {
+        off[i] = end;
+        end += (w.b[i] + 255) / 256 * 256;
+    }
+    if (end > IGB_NOALLOC_SCRATCH_BYTES) {
+        set_error("h2_matvec_noalloc: %d columns need %zu bytes of work buffers, more than the %zu-byte scratch",
+                  ncol, end, size_t(IGB_NOALLOC_SCRATCH_BYTES));
+        return IGB_ERR_ARG;
+    }
+    unsigned char* b = static_cast<unsigned char*>(base);
+    auto at = [&](int i) -> void* { return w.b[i] ? static_cast<void*>(b + off[i]) : nullptr; };
+    MatvecWork W;
+    W.xhat = static_cast<double2*>(at(WorkSizes::XHAT));
+    W.yhat = static_cast<double2*>(at(WorkSizes::YHAT));
+    W.yraw = static_cast<double2*>(at(WorkSizes::YRAW));
+    W.part = static_cast<double2*>(at(WorkSizes::PART));
+    W.xlo = at(WorkSizes::XLO);
+    W.part_lo = at(WorkSizes::PART_LO);
+    W.xnear_lo = static_cast<float2*>(at(WorkSizes::XNEAR_LO));
+    W.yfar = static_cast<double2*>(at(WorkSizes::YFAR));
+    W.x2 = static_cast<double2*>(at(WorkSizes::X2));
+    W.leafbuf = static_cast<double2*>(at(WorkSizes::LEAFBUF));
+    return matvec_launches(op, W, x, y, ncol, parts, s);
+}
+
 igb_status matvec_device(igb_op op, const double* x, double* y, int ncol, int parts, hipStream_t s) {
     igb_status st;
     if (!op->sum_parts.empty()) return matvec_sum(op, x, y, ncol, parts, s);
     if ((st = alloc_work(op, ncol))) return st;
-    if (!op->use_graphs || op->profile || s == nullptr) return matvec_launches(op, x, y, ncol, parts, s);
+    const MatvecWork W = own_work(op);
+    if (!op->use_graphs || op->profile || s == nullptr) return matvec_launches(op, W, x, y, ncol, parts, s);
     const igb_op_s::GraphKey key{x, y, ncol, parts, s};
     for (auto& gr : op->graphs)
         if (gr.first == key) {
@@ -3179,7 +3268,7 @@ igb_status matvec_device(igb_op op, const double* x, double* y, int ncol, int pa
     if (op->graphs.size() >= 512) op->clear_graphs();
     hipGraph_t graph = nullptr;
     IGB_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    st = matvec_launches(op, x, y, ncol, parts, s);
+    st = matvec_launches(op, W, x, y, ncol, parts, s);
     const hipError_t ce = hipStreamEndCapture(s, &graph);
     if (st) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -3201,7 +3290,8 @@ igb_status matvec_device(igb_op op, const double* x, double* y, int ncol, int pa
     return IGB_OK;
 }
 
-static igb_status matvec_launches(igb_op op, const double* x, double* y, int ncol, int parts, hipStream_t s) {
+static igb_status matvec_launches(igb_op op, const MatvecWork& W, const double* x, double* y, int ncol, int parts,
+                                  hipStream_t s) {
     const bool low = (parts & IGB_MV_LOWPREC) != 0;
     igb_status st;
     igb_geom g = op->geom;
@@ -3209,16 +3299,16 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
     const bool hard = op->bc == IGB_HARD;
     const double2* X = reinterpret_cast<const double2*>(x);
     double2* Y = reinterpret_cast<double2*>(y);
-    double2* xh = op->d_xhat.as<double2>();
-    double2* yh = op->d_yhat.as<double2>();
+    double2* xh = W.xhat;
+    double2* yh = W.yhat;
     const int64_t N = op->N;
     const bool far = (parts & IGB_PART_FAR) && op->nfar > 0;
     if (far) {
         const double2* x2 = X;
         if (hard) {
             hipLaunchKernelGGL(glue_gather, dim3(blocks_for(g->n2 * ncol, 256)), dim3(256), 0, s,
-                               op->d_s2_to_s0.as<int>(), X, N, op->d_x2.as<double2>(), g->n2, ncol);
-            x2 = op->d_x2.as<double2>();
+                               op->d_s2_to_s0.as<int>(), X, N, W.x2, g->n2, ncol);
+            x2 = W.x2;
         }
         const int kinds = hard ? 3 : 1;
         const int64_t ks = op->nclusters * nq * ncol;  // stride between moment kinds
@@ -3232,27 +3322,27 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
         }
         if ((st = timer_mark(op, 2, s))) return st;
         int pkind = 0;
-        if ((st = launch_m2l(op, xh, ks, low, ncol, s, pkind))) return st;
+        if ((st = launch_m2l(op, W, xh, ks, low, ncol, s, pkind))) return st;
         if ((st = timer_mark(op, 3, s))) return st;
         const int nvec = hard ? 10 : 1;
-        double2* red_out = op->d_yraw.as<double2>();
+        double2* red_out = W.yraw;
         const int64_t per = int64_t(nvec) * nq * ncol;
         if (!hard) {
             // sound-soft: the downward kernel sums the chunk partials itself
         } else if (pkind == 1)
             hipLaunchKernelGGL(m2l_reduce<float2>, dim3(blocks_for(op->nclusters * per, 256)), dim3(256), 0, s,
-                               op->d_part_lo.as<float2>(), op->chunks_mfma.d_tgt_ptr.as<int>(), op->nclusters, per,
+                               static_cast<float2*>(W.part_lo), op->chunks_mfma.d_tgt_ptr.as<int>(), op->nclusters, per,
                                red_out);
         else if (pkind == 2)
             hipLaunchKernelGGL(m2l_reduce<double2>, dim3(blocks_for(op->nclusters * per, 256)), dim3(256), 0, s,
-                               op->d_part_lo.as<double2>(), op->chunks_mfma.d_tgt_ptr.as<int>(), op->nclusters, per,
+                               static_cast<double2*>(W.part_lo), op->chunks_mfma.d_tgt_ptr.as<int>(), op->nclusters, per,
                                red_out);
         else
             hipLaunchKernelGGL(m2l_reduce<double2>, dim3(blocks_for(op->nclusters * per, 256)), dim3(256), 0, s,
-                               op->d_part.as<double2>(), op->chunks.d_tgt_ptr.as<int>(), op->nclusters, per, red_out);
+                               W.part, op->chunks.d_tgt_ptr.as<int>(), op->nclusters, per, red_out);
         if (hard)
             hipLaunchKernelGGL(m2l_finalize_hard, dim3(blocks_for(op->nclusters * nq * ncol, 256)), dim3(256), 0, s,
-                               op->d_yraw.as<double2>(), op->d_nodes.as<double>(), op->nclusters, nq, op->kappa,
+                               W.yraw, op->d_nodes.as<double>(), op->nclusters, nq, op->kappa,
                                op->hmix, ks, ncol, yh);
         const int w = (1 << op->d) + g->p;
         size_t dlds = 0;
@@ -3261,30 +3351,30 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
         const double* Tc = op->d_Tc.as<double>();
         const int64_t* cof = op->d_cluoff.as<int64_t>();
         const double* m1 = op->d_m1.as<double>();
-        double2* lb = op->d_leafbuf.as<double2>();
+        double2* lb = W.leafbuf;
         if (hard) {
             for (int kd = 0; kd < kinds; ++kd)
                 hipLaunchKernelGGL(down_project_leaf<double2>, dgrid, dblock, dlds, s, yh + kd * ks,
                                    static_cast<const double2*>(nullptr), static_cast<const int*>(nullptr), Tc, cof, m1,
                                    q, w, L, du[kd], dv[kd], stride_kind, ncol, dcb, lb + kd * nleaf * ncol * w * w);
         } else if (pkind == 1) {
-            hipLaunchKernelGGL(down_project_leaf<float2>, dgrid, dblock, dlds, s, yh, op->d_part_lo.as<float2>(),
+            hipLaunchKernelGGL(down_project_leaf<float2>, dgrid, dblock, dlds, s, yh, static_cast<float2*>(W.part_lo),
                                op->chunks_mfma.d_tgt_ptr.as<int>(), Tc, cof, m1, q, w, L, 0, 0, stride_kind, ncol,
                                dcb, lb);
         } else {
             const bool lo = pkind == 2;
             hipLaunchKernelGGL(down_project_leaf<double2>, dgrid, dblock, dlds, s, yh,
-                               lo ? op->d_part_lo.as<double2>() : op->d_part.as<double2>(),
+                               lo ? static_cast<double2*>(W.part_lo) : W.part,
                                (lo ? op->chunks_mfma : op->chunks).d_tgt_ptr.as<int>(), Tc, cof, m1, q, w, L, 0, 0,
                                stride_kind, ncol, dcb, lb);
         }
         hipLaunchKernelGGL(leaf_gather, dim3(blocks_for(g->n2 * ncol, 256)), dim3(256), 0, s,
-                           op->d_leafbuf.as<double2>(), op->d, g->p, L, g->k, g->npatch, kinds, ncol,
-                           op->d_yfar.as<double2>());
+                           W.leafbuf, op->d, g->p, L, g->k, g->npatch, kinds, ncol,
+                           W.yfar);
         if ((st = timer_mark(op, 3, s))) return st;
     }
     if ((st = timer_mark(op, 1, s))) return st;
-    const double2* yfar = far ? op->d_yfar.as<double2>() : nullptr;
+    const double2* yfar = far ? W.yfar : nullptr;
     const int* s0p = hard ? op->d_s0_ptr.as<int>() : nullptr;
     const int* s0r = hard ? op->d_s0_reps.as<int>() : nullptr;
     const int use_near = (parts & IGB_PART_NEAR) ? 1 : 0;
@@ -3295,7 +3385,7 @@ static igb_status matvec_launches(igb_op op, const double* x, double* y, int nco
     const double2* vl = op->d_val.as<double2>();
     if (low && op->d_val_lo.ptr) {
         const int ncb = (ncol + 15) / 16;
-        float2* xt = op->d_xnear_lo.as<float2>();
+        float2* xt = W.xnear_lo;
         if (use_near)
             hipLaunchKernelGGL(round_columns_t, dim3(blocks_for(int64_t(ncb) * N * 16, 256)), dim3(256), 0, s, X, N,
                                ncol, ncb, xt);
