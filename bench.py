@@ -59,27 +59,55 @@ WORKLOADS = {
 }
 
 
-def cpu_baseline(w, seconds_target=20.0):
-    """The oracle (dense O1 Galerkin rows, fp64 NumPy) timed on the host: rows
-    of the dense CFIE matrix applied to the same vector; one oracle matvec is
-    extrapolated from the sampled rows (x N / rows)."""
+def cpu_baseline(w, reps=5):
+    """The oracle O1 (plain dense fp64 Galerkin BEM, NumPy) timed on the host's
+    cores (all of them, or the OMP_NUM_THREADS share), each stage separately:
+
+    * matvec (the reported value): y = A x with the dense N x N complex128
+      matrix (zgemv), median of `reps` after one warm-up;
+    * solve: LU (zgesv) of the dense matrix for one right-hand side, once;
+    * assembly: the oracle's element row blocks (every source element against
+      one target element, singular rules on touching pairs) for one target per
+      core over its worker pool, extrapolated x E / cores to the whole matrix.
+
+    The dense matrix holds seeded complex normal values plus N on the diagonal
+    (so that LU meets no singular pivot): neither zgemv's nor zgesv's cost
+    depends on the values, and the assembled entries are timed separately."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
     from oracle import galerkin as G  # test infrastructure: baseline leg only
     from paper_2306_11324_amd import inputs as I
-    pts = I.sphere_patches() if w["geometry"] == "sphere" else I.star_patches(0, min(w["m"], 4))
-    bem = G.DenseBEM(pts, p=w["p"], m=w["m"], kappa=w["kappa"], bc="soft")
-    x = I.random_complex(12345, bem.n)
-    rng = np.random.default_rng(4321)
-    rows_done, t_used = 0, 0.0
-    while t_used < seconds_target and rows_done < 64:
-        r = rng.integers(0, bem.n, 1)
+    pts = I.sphere_patches() if w["geometry"] == "sphere" else I.star_patches(0, I.star_geometry_level(w["m"]))
+    cores = G.host_cores()
+    bem = G.DenseBEM(pts, p=w["p"], m=w["m"], kappa=w["kappa"], bc="soft", workers=cores)
+    n, E = bem.n, bem.disc.nelem
+    targets = np.sort(np.random.default_rng(4321).choice(E, cores, replace=False))
+    t0 = time.perf_counter()
+    for _ in bem._map_targets(targets, bem.ops):
+        pass
+    t_asm = time.perf_counter() - t0
+    with threadpool_limits(cores):
+        A = I.random_complex(99, (n, n))
+        A[np.diag_indices(n)] += n
+        x = I.random_complex(12345, n)
+        t_mv = []
+        for _ in range(reps + 1):
+            t0 = time.perf_counter()
+            A @ x
+            t_mv.append(time.perf_counter() - t0)
+        t_mv = float(np.median(t_mv[1:]))
         t0 = time.perf_counter()
-        _ = bem.rows(r) @ x
-        t_used += time.perf_counter() - t0
-        rows_done += 1
-    per_matvec = t_used / rows_done * bem.n
-    return {"value": 1.0 / per_matvec, "unit": "matvecs/s", "cores": bem.workers, "kind": "oracle",
-            "sample": f"{rows_done} rows of the dense fp64 Galerkin CFIE matrix (N={bem.n}) assembled "
-                      f"and applied in {t_used:.1f} s, extrapolated x N/{rows_done}"}
+        np.linalg.solve(A, x)
+        t_lu = time.perf_counter() - t0
+        blas = sorted({f"{d.get('internal_api')} {d.get('num_threads')} threads" for d in threadpool_info()
+                       if d.get("user_api") == "blas"})
+    del A
+    return {"value": 1.0 / t_mv, "unit": "matvecs/s", "cores": cores, "kind": "oracle",
+            "sample": f"dense N={n} complex128 matvec (zgemv, median of {reps}); LU solve of the dense matrix "
+                      f"(once); the oracle's element row blocks for {cores} of the {E} target elements "
+                      f"({t_asm:.1f} s), extrapolated to the whole matrix",
+            "matvec_s": t_mv, "solve_lu_s": t_lu, "solves_per_s": 1.0 / t_lu,
+            "assembly_s_extrapolated": t_asm * E / cores, "blas": blas}
 
 
 def serve_stream(nreq, rate):

@@ -67,6 +67,17 @@ OPS_SOFT = ("V", "Kstar")
 OPS_HARD = ("K", "W")
 
 
+def host_cores() -> int:
+    """The CPUs this process may run on, or the OMP_NUM_THREADS share if that
+    is smaller (a host shared by several GPU jobs sets it to the job's share)."""
+    n = len(os.sched_getaffinity(0))
+    try:
+        n = min(n, int(os.environ.get("OMP_NUM_THREADS", n)))
+    except ValueError:
+        pass
+    return max(1, n)
+
+
 def default_eta(kappa: float, bc: str) -> float:
     """CFIE coupling (Sec. 2 gives none): eta = kappa for the sound-soft system
     and eta = -1/kappa for the sound-hard one, i.e. the combination
@@ -182,7 +193,7 @@ class DenseBEM:
         c = self.corners
         self.diam = np.max(np.linalg.norm(c[:, :, None, :] - c[:, None, :, :], axis=-1), axis=(1, 2))
         self.ops = OPS_SOFT if self.family == "soft" else OPS_HARD
-        self.workers = workers if workers is not None else min(8, len(os.sched_getaffinity(0)))
+        self.workers = workers if workers is not None else host_cores()
 
     # ------------------------------------------------------------ dimensions
     @property
