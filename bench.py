@@ -51,7 +51,7 @@ HBM_PEAK_GBS = 8000.0
 # make a plain 1 GiB device copy read and write 1 GiB), taken for the kernels
 # as they stand: profiles/m2l_sphere_m5_p2_k8_hbm_counters.md.  To be reset
 # to None whenever one of these kernels changes.
-MEASURED_TRAFFIC = {"m2l_chunks_wave": 2.147e9, "fp64": 2.608e9, "fp32": 1.281e9, "bf16": 0.644e9}
+MEASURED_TRAFFIC = {"m2l_chunks_wave": 2.147e9, "fp64": None, "fp32": 1.281e9, "bf16": 0.644e9}
 
 WORKLOADS = {
     "sphere_m5_p2_k8": dict(geometry="sphere", m=5, p=2, kappa=8.0, q=6, eta_adm=1.6, leaf_depth=2,
@@ -311,7 +311,7 @@ def main():
         return {"ncol": nc, "column_matvecs_per_s": nc / tb, "ms_per_block_matvec": tb * 1e3, "kernel_ms": km,
                 "m2l_algorithmic_bytes": byts,
                 "m2l_traffic_bytes": MEASURED_TRAFFIC.get(prec_name) if args.workload == "sphere_m5_p2_k8" else None,
-                "m2l_kernel": "m2l_mfma_soft (fp64 matrix cores)" if prec_name == "fp64" else
+                "m2l_kernel": "m2l_mfma64_soft (fp64 matrix cores)" if prec_name == "fp64" else
                               f"m2l_mfma_soft ({prec_name} matrix cores)",
                 "m2l_GBps": byts / avg / 1e9, "m2l_TFLOPs": flops / avg / 1e12,
                 "m2l_frac_hbm_peak": byts / avg / (HBM_PEAK_GBS * 1e9),
@@ -427,7 +427,13 @@ def main():
             if o is not op:
                 del o
             torch.cuda.empty_cache()
-        del xb, yb
+        # fp64 at 64 columns (the width of a 64-direction block): the coupling's
+        # arithmetic intensity passes the fp64 ridge, the matrix-core roofline applies
+        x64 = torch.from_numpy(I.random_complex(778, (64, n))).to(dev)
+        y64 = torch.zeros_like(x64)
+        block_mv["fp64_64col"] = block_matvec(op, "fp64", x64, y64, max(5, args.matvecs // 5))
+        block_mv["fp64_64col"]["m2l_traffic_bytes"] = None
+        del xb, yb, x64, y64
 
     # matvec-only loop with HIP-event kernel timing on the launch stream
     x = torch.from_numpy(I.random_complex(12345, n)).to(dev)

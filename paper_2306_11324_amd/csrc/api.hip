@@ -303,9 +303,10 @@ static igb_status build_one(igb_ctx ctx, igb_geom g, const igb_op_params* prm, c
     // held during assembly only: the staged element blocks and the near pair lists
     const size_t transient = std::min<size_t>(op->near_src.size(), size_t(1) << 22) * nl * nl * 16 +
                              op->near_src.size() * 12 + (size_t(1) << 20);
-    if (prm->precision == IGB_MIX_BF16)   // fp32 near field in tiles
-        need += size_t(op->near_tile_vals) * 8 + op->near_tiles.size() * sizeof(NearTile) +
-                op->near_tile_cols.size() * 4;
+    // the near field in tiles: fp32 values (bf16 operators), fp64 values (fp64 operators)
+    if (op->nnz > 0 && prm->precision != IGB_MIX_FP32)
+        need += size_t(op->near_tile_vals) * (prm->precision == IGB_MIX_BF16 ? 8 : 16) +
+                op->near_tiles.size() * sizeof(NearTile) + op->near_tile_cols.size() * 4;
     if (prm->precision != IGB_FP64) {
         // rounded tiles (rows padded to 16 bytes)
         const size_t esz = prm->precision == IGB_MIX_FP32 ? 8 : 4, epl = 16 / esz;

@@ -167,6 +167,9 @@ struct NearTile {
     int ncols, nrows;
     int rows[NEAR_TILE_ROWS];
 };
+// blocks of at least this many columns take the matrix-core paths of fp64
+// operators (coupling and near product)
+constexpr int MF64_MIN_COLS = 16;
 
 struct igb_op_s {
     igb_geom geom = nullptr;
@@ -217,12 +220,15 @@ struct igb_op_s {
     // bf16 operators: fp32 near-field values and fp32 copies of the columns for the
     // near product of the inner (refinement) matvecs
     igb::DevBuf d_val_lo, d_xnear_lo, d_near_tiles, d_near_tile_cols;
+    // fp64 operators: fp64 near-field values in the same tiles, for the near
+    // product of blocks of >= 16 columns on the fp64 matrix cores
+    igb::DevBuf d_val64;
     igb::DevBuf d_near_ptr, d_near_src;
     igb::DevBuf d_s2_to_s0, d_s0_ptr, d_s0_reps;
     igb::DevBuf d_far_src;
     // reduced-precision path: source vectors rounded per matvec, fp32 partials
     igb::DevBuf d_xlo, d_part_lo;
-    igb::DevBuf d_xhat, d_yhat, d_yraw, d_part, d_yfar, d_x2, d_cluoff, d_leafbuf;
+    igb::DevBuf d_xhat, d_yhat, d_yraw, d_part, d_yfar, d_x2, d_cluoff, d_leafbuf, d_xnear64;
     size_t dev_bytes = 0;
     int64_t nclusters = 0;
     // solver scratch (kept between solves, grown on demand): Krylov basis and
@@ -298,7 +304,7 @@ igb_status assemble_far_device(igb_op op, hipStream_t s);
 igb_status alloc_work(igb_op op, int nrhs);
 // bytes of the matvec work buffers for ncol columns (alloc_work's sizes)
 struct WorkSizes {
-    enum { XHAT, YHAT, YRAW, PART, XLO, PART_LO, XNEAR_LO, YFAR, X2, LEAFBUF, COUNT };
+    enum { XHAT, YHAT, YRAW, PART, XLO, PART_LO, XNEAR_LO, YFAR, X2, LEAFBUF, XNEAR64, COUNT };
     size_t b[COUNT];
     size_t total() const {
         size_t t = 0;
@@ -314,6 +320,7 @@ struct MatvecWork {
     void *xlo = nullptr, *part_lo = nullptr;
     float2* xnear_lo = nullptr;
     double2 *yfar = nullptr, *x2 = nullptr, *leafbuf = nullptr;
+    double2* xnear64 = nullptr;   // transposed fp64 columns of the tile near product
 };
 constexpr int SCRATCH_MAX_DEVICES = 64;
 // takes the device address of the scratch array of the current device (once per device)

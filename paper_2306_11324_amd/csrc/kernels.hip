@@ -1177,7 +1177,6 @@ static inline size_t lo_esz(igb_op op) {
 // the matrix-core coupling serves the operator's own precision; an fp64
 // operator with tiles uses it for every product
 static inline bool mf_fp64(igb_op op) { return op->prm.precision == IGB_FP64 && !op->prm.far_on_the_fly; }
-constexpr int MF64_MIN_COLS = 16;
 // zeroed guard bytes after the last tile (A reads are clamped to the tile)
 static inline size_t lo_slack(igb_op op) { return size_t(3) * op->nq * 16 + 256; }
 
@@ -1290,6 +1289,90 @@ __global__ __launch_bounds__(512) void m2l_mfma(const typename OPS::LT* __restri
             if (ar < nq)
                 part[((ch * NVO + v) * nq + ar) * ncol + c] = make_pt<typename OPS::PT>(acc[v][0][r], acc[v][1][r]);
         }
+}
+
+// fp64 sound-soft coupling for blocks of >= 16 columns on the fp64 matrix
+// cores, with A reuse: wave w owns output rows 16w..16w+15 of the chunk's
+// target and NC tiles of 16 columns, so every A fragment (16 rows x 4 source
+// nodes of one tile) read from HBM serves NC column tiles (the coupling of 64
+// columns reads each tile once: arithmetic intensity 32 flop/B, past the fp64
+// ridge).  The waves of a workgroup read the same source fragments, which the
+// cache serves once.  Each column sums the chunk's pairs and k blocks in
+// order in its own accumulator, so its result does not depend on NC or on the
+// other columns.  KU steps are loaded per group, two groups in flight.
+template <int NC, int KU>
+__global__ __launch_bounds__(512) void m2l_mfma64_soft(const double2* __restrict__ coup, int nkc,
+                                                       const double2* __restrict__ xlo, int kbp, int ncolp,
+                                                       const int* __restrict__ far_src_g,
+                                                       const int64_t* __restrict__ chunk_pair,
+                                                       const int* __restrict__ chunk_len, int64_t nchunk, int nq,
+                                                       int ncol, double2* __restrict__ part) {
+    using OPS = MfmaF64;
+    constexpr int KB = OPS::KB;
+    const int64_t ch = xcd_chunk(blockIdx.x, nchunk);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    // A row of this lane; rows past nq re-read the last row (outputs not stored)
+    const int a = min(wave * 16 + li, nq - 1);
+    const int c0 = blockIdx.y * 16 * NC;
+    const int64_t p0 = chunk_pair[ch];
+    const int len = chunk_len[ch];
+    const int nkb = (nq + KB - 1) / KB;
+    const int64_t tile_el = int64_t(nkc) * nq;
+    const int nstep = len * nkb;
+    const int srcv = lane < len ? far_src_g[p0 + lane] : 0;
+    const int64_t vstride = int64_t(ncolp) * kbp;
+    const unsigned offB = unsigned(g * ncolp + c0 + li);
+    OPS::ACC acc[NC][2];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) acc[j][0] = acc[j][1] = OPS::ACC{0, 0, 0, 0};
+    // next step to load; past the last step the loads repeat it (in bounds,
+    // unused), so every load is issued unconditionally
+    int ni = 0, nkbi = 0;
+    auto load = [&](uint4 (&A)[KU], uint4 (&X)[KU][NC]) {
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int i = ni, kb = nkbi;
+            const bool last = ni == len - 1 && nkbi == nkb - 1;
+            nkbi = last ? nkbi : (nkbi + 1 == nkb ? 0 : nkbi + 1);
+            ni = last ? ni : (nkbi == 0 ? ni + 1 : ni);
+            const int src = __builtin_amdgcn_readlane(srcv, i);
+            const int kcg = min(kb * KB + g, nkc - 1);   // clamped to the tile (B is zero past nq)
+            A[u] = *reinterpret_cast<const uint4*>(coup + (p0 + i) * tile_el + int64_t(kcg) * nq + a);
+            const double2* Bu = xlo + int64_t(src) * vstride + kb * (KB * ncolp) + offB;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) X[u][j] = *reinterpret_cast<const uint4*>(Bu + 16 * j);
+        }
+    };
+    auto compute = [&](int j0, const uint4 (&A)[KU], const uint4 (&X)[KU][NC]) {
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            if (j0 + u >= nstep) break;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                acc[j][0] = OPS::step(A[u], OPS::re_part(X[u][j]), acc[j][0]);
+                acc[j][1] = OPS::step(A[u], OPS::im_part(X[u][j]), acc[j][1]);
+            }
+        }
+    };
+    uint4 A0[KU], X0[KU][NC], A1[KU], X1[KU][NC];
+    load(A0, X0);
+    for (int j0 = 0; j0 < nstep; j0 += 2 * KU) {
+        load(A1, X1);
+        compute(j0, A0, X0);
+        load(A0, X0);
+        compute(j0 + KU, A1, X1);
+    }
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        const int c = c0 + 16 * j + li;
+        if (c >= ncol) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ar = wave * 16 + OPS::orow(g, r);
+            if (ar < nq) part[(ch * nq + ar) * ncol + c] = make_double2(acc[j][0][r], acc[j][1][r]);
+        }
+    }
 }
 
 // Sound-soft coupling on the matrix cores with B reuse: the 4 waves of a
@@ -2054,6 +2137,132 @@ __global__ __launch_bounds__(64 * NEAR_TILE_WAVES) void near_tiles_mfma(const Ne
     }
 }
 
+// fp64 tile layout of the near field for blocks of >= 16 columns of fp64
+// operators: tile t holds its rows' values as [k block of 4][row][4] over the
+// tile's column list, zero where a row has no entry (the same tiles and column
+// lists as the fp32 layout, at the same offsets: a tile's fp64 region is no
+// longer than its fp32 one).
+__global__ void near_tile_values64(const NearTile* __restrict__ tiles, const int* __restrict__ tcol,
+                                   const int64_t* __restrict__ row_ptr, const int* __restrict__ col,
+                                   const double2* __restrict__ val, double2* __restrict__ vt) {
+    const NearTile& T = tiles[blockIdx.x];
+    const int i = threadIdx.x;
+    if (i >= T.nrows) return;
+    const int nr = T.nrows, nc = T.ncols;
+    const int* tc = tcol + T.col_off;
+    const int r = T.rows[i];
+    int64_t q = row_ptr[r];
+    const int64_t qe = row_ptr[r + 1];
+    const int nk = (nc + MfmaF64::KB - 1) / MfmaF64::KB * MfmaF64::KB;
+    for (int k = 0; k < nk; ++k) {
+        double2 v = make_double2(0.0, 0.0);
+        if (k < nc && q < qe && col[q] == tc[k]) v = val[q++];
+        vt[T.val_off + (int64_t(k / MfmaF64::KB) * nr + i) * MfmaF64::KB + k % MfmaF64::KB] = v;
+    }
+}
+
+// x^T for the fp64 tile product: xt[b][row][16] = x[16 b + c][row] (zero for
+// columns past ncol)
+__global__ void columns_t64(const double2* __restrict__ x, int64_t nrows, int ncol, int ncb, double2* __restrict__ xt) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= int64_t(ncb) * nrows * 16) return;
+    const int c = int(i / (nrows * 16)) * 16 + int(i % 16);
+    const int64_t row = (i / 16) % nrows;
+    xt[i] = c < ncol ? x[int64_t(c) * nrows + row] : make_double2(0.0, 0.0);
+}
+
+// Near product of fp64 operators for blocks of >= 16 columns on the fp64
+// matrix cores: per tile and 16 columns, Y = V X with the fp64 tile values as
+// the A operand (16 rows; rows past nrows read row 0, their outputs are not
+// stored) and the columns gathered through the tile's column list as the B
+// operand.  The waves take every NW-th k block of 4 columns in increasing
+// order and meet in LDS in wave order; each output column depends only on its
+// own input column in an order fixed by the tile, so every block of >= 16
+// columns gives bitwise the same column results (which differ from the
+// one-column CSR product by rounding: another summation order).
+constexpr int NEAR64_WAVES = 8;
+__global__ __launch_bounds__(64 * NEAR64_WAVES) void near_tiles_mfma64(
+    const NearTile* __restrict__ tiles, int64_t ntile, const int* __restrict__ tcol, const double2* __restrict__ vt,
+    const double2* __restrict__ xt, int64_t nrows, const double2* __restrict__ yfar, int64_t n2,
+    const int* __restrict__ s0_ptr, const int* __restrict__ s0_reps, int use_near, int ncol,
+    double2* __restrict__ y) {
+    constexpr int NW = NEAR64_WAVES, KB = MfmaF64::KB;
+    __shared__ f64x4 red[NW - 1][2][64];
+    __shared__ int cidx[NEAR_TILE_CHUNK];
+    const int64_t t = xcd_chunk(blockIdx.x, ntile);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    const NearTile& T = tiles[t];
+    const int nr = T.nrows, nc = T.ncols;
+    const int nkb = (nc + KB - 1) / KB;
+    const double2* xb = xt + int64_t(blockIdx.y) * nrows * 16 + li;
+    const int* cl = tcol + T.col_off;
+    const int ra = li < nr ? li : 0;
+    const double2* va = vt + T.val_off + ra * KB + g;
+    const int64_t kbstride = int64_t(nr) * KB;
+    f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    auto load = [&](int kb, int kl, uint4& A, uint4& X) {
+        A = *reinterpret_cast<const uint4*>(va + kb * kbstride);
+        X = *reinterpret_cast<const uint4*>(xb + int64_t(cidx[kl + g]) * 16);
+    };
+    auto compute = [&](const uint4& A, const uint4& X) {
+        acc0 = MfmaF64::step(A, MfmaF64::re_part(X), acc0);
+        acc1 = MfmaF64::step(A, MfmaF64::im_part(X), acc1);
+    };
+    if (use_near) {
+        // chunks of columns: indices to LDS (past the list: its last column, whose
+        // tile values are zero there), then each wave's k blocks kb = wave mod NW
+        // in increasing order, two loads in flight
+        for (int k0 = 0; k0 < nkb * KB; k0 += NEAR_TILE_CHUNK) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < NEAR_TILE_CHUNK; i += blockDim.x) cidx[i] = cl[min(k0 + i, nc - 1)];
+            __syncthreads();
+            const int kb0 = k0 / KB, kb1 = min(nkb, kb0 + NEAR_TILE_CHUNK / KB);
+            int kb = kb0 + wave;
+            for (; kb + NW < kb1; kb += 2 * NW) {
+                uint4 A0, X0, A1, X1;
+                load(kb, (kb - kb0) * KB, A0, X0);
+                load(kb + NW, (kb + NW - kb0) * KB, A1, X1);
+                compute(A0, X0);
+                compute(A1, X1);
+            }
+            if (kb < kb1) {
+                uint4 A0, X0;
+                load(kb, (kb - kb0) * KB, A0, X0);
+                compute(A0, X0);
+            }
+        }
+    }
+    if (wave > 0) {
+        red[wave - 1][0][lane] = acc0;
+        red[wave - 1][1][lane] = acc1;
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int w = 0; w < NW - 1; ++w) {
+        acc0 += red[w][0][lane];
+        acc1 += red[w][1][lane];
+    }
+    const int c = blockIdx.y * 16 + li;
+    if (c >= ncol) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = MfmaF64::orow(g, r);
+        if (i >= nr) continue;
+        const int row = T.rows[i];
+        double2 a = make_double2(acc0[r], acc1[r]);
+        if (yfar) {
+            if (s0_ptr) {
+                for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q) a = cadd(a, yfar[int64_t(c) * n2 + s0_reps[q]]);
+            } else {
+                a = cadd(a, yfar[int64_t(c) * n2 + row]);
+            }
+        }
+        y[int64_t(c) * nrows + row] = a;
+    }
+}
+
 // --------------------------------------------------------------------------
 // Right-hand sides and far field
 // --------------------------------------------------------------------------
@@ -2709,6 +2918,18 @@ igb_status assemble_near_device(igb_op op, hipStream_t s) {
         else
             return hard ? near_launch<P, true>(op, s) : near_launch<P, false>(op, s);
     });
+    if (!st && op->prm.precision == IGB_FP64 && op->nnz > 0 && !op->near_tiles.empty()) {
+        // fp64 copy of the near field in the tile layout (blocks of >= 16 columns)
+        const int64_t nt = int64_t(op->near_tiles.size());
+        if ((st = upload(op->d_near_tiles, op->near_tiles.data(), op->near_tiles.size(), acct))) return st;
+        if ((st = upload(op->d_near_tile_cols, op->near_tile_cols.data(), op->near_tile_cols.size(), acct))) return st;
+        if ((st = alloc(op->d_val64, size_t(op->near_tile_vals) * sizeof(double2), acct))) return st;
+        hipLaunchKernelGGL(near_tile_values64, dim3(unsigned(nt)), dim3(64), 0, s, op->d_near_tiles.as<NearTile>(),
+                           op->d_near_tile_cols.as<int>(), op->d_rowptr.as<int64_t>(), op->d_col.as<int>(),
+                           op->d_val.as<double2>(), op->d_val64.as<double2>());
+        IGB_HIP(hipGetLastError());
+        IGB_HIP(hipStreamSynchronize(s));
+    }
     if (!st && op->prm.precision == IGB_MIX_BF16 && op->nnz > 0) {
         // fp32 copy of the near field for the inner matvecs of the bf16 refinement (whose
         // inner solves stop at 1e-3; the fp32 operator's inner solves aim at the full
@@ -2935,6 +3156,8 @@ WorkSizes work_sizes(const igb_op_s* op, int ncol) {
     }
     if (op->prm.precision == IGB_MIX_BF16 && op->nnz > 0)
         w.b[WorkSizes::XNEAR_LO] = (C + 15) / 16 * 16 * op->N * sizeof(float2);
+    if (op->prm.precision == IGB_FP64 && op->nnz > 0 && C >= size_t(MF64_MIN_COLS))
+        w.b[WorkSizes::XNEAR64] = (C + 15) / 16 * 16 * op->N * sizeof(double2);
     w.b[WorkSizes::YFAR] = C * op->geom->n2 * sizeof(double2);
     w.b[WorkSizes::X2] = w.b[WorkSizes::YFAR];
     const size_t win = (size_t(1) << op->d) + op->geom->p;
@@ -2945,7 +3168,7 @@ WorkSizes work_sizes(const igb_op_s* op, int ncol) {
 static igb::DevBuf* work_buf(igb_op op, int i) {
     igb::DevBuf* bufs[WorkSizes::COUNT] = {&op->d_xhat, &op->d_yhat, &op->d_yraw,  &op->d_part, &op->d_xlo,
                                            &op->d_part_lo, &op->d_xnear_lo, &op->d_yfar, &op->d_x2,
-                                           &op->d_leafbuf};
+                                           &op->d_leafbuf, &op->d_xnear64};
     return bufs[i];
 }
 
@@ -3080,6 +3303,40 @@ static void launch_m2l_lo_t(igb_op op, const MatvecWork& W, const double2* xh, i
     (void)timer_mark(op, 0, s);
 }
 
+// fp64 sound-soft blocks of >= 16 columns: up to 4 column tiles per wave
+static void launch_m2l_f64_soft(igb_op op, const MatvecWork& W, const double2* xh, int ncol, hipStream_t s) {
+    const M2LChunks& C = op->chunks_mfma;
+    const int64_t nchunk = int64_t(C.len.size());
+    const int ncolp = (ncol + 15) / 16 * 16, kbp = lo_kbp(op), nq = op->nq;
+    const int64_t nv = op->nclusters * ncolp * kbp;
+    double2* xlo = static_cast<double2*>(W.xlo);
+    hipLaunchKernelGGL((round_vectors<1, double2>), dim3(unsigned((nv + 255) / 256)), dim3(256), 0, s, xh, int64_t(0),
+                       op->d_nodes.as<double>(), op->nclusters, nq, kbp, ncol, ncolp, xlo);
+    (void)timer_mark(op, 0, s);
+    if (nchunk > 0) {
+        // NC column tiles per workgroup, NC dividing the padded tile count (the
+        // last workgroup's tiles stay inside the rounded source vectors)
+        const int ntile = ncolp / 16;
+        const int nc = ntile % 4 == 0 ? 4 : ntile % 2 == 0 ? 2 : 1;
+        const dim3 grid(unsigned(nchunk), unsigned((ntile + nc - 1) / nc)), block(64 * ((nq + 15) / 16));
+        const double2* cp = op->d_coupling.as<double2>();
+        double2* pp = static_cast<double2*>(W.part_lo);
+        const int* fs = op->d_far_src.as<int>();
+        const int64_t* cpair = C.d_pair.as<int64_t>();
+        const int* clen = C.d_len.as<int>();
+        if (nc == 4)
+            hipLaunchKernelGGL((m2l_mfma64_soft<4, 1>), grid, block, 0, s, cp, lo_nkc(op), xlo, kbp, ncolp, fs, cpair,
+                               clen, nchunk, nq, ncol, pp);
+        else if (nc == 2)
+            hipLaunchKernelGGL((m2l_mfma64_soft<2, 2>), grid, block, 0, s, cp, lo_nkc(op), xlo, kbp, ncolp, fs, cpair,
+                               clen, nchunk, nq, ncol, pp);
+        else
+            hipLaunchKernelGGL((m2l_mfma64_soft<1, 4>), grid, block, 0, s, cp, lo_nkc(op), xlo, kbp, ncolp, fs, cpair,
+                               clen, nchunk, nq, ncol, pp);
+    }
+    (void)timer_mark(op, 0, s);
+}
+
 // coupling partials [chunk][nvec][nq][ncol] of the far pairs.  kind: 0 fp64
 // partials of the vector path, 1 fp32 partials of the matrix-core path at
 // reduced precision, 2 fp64 partials of the matrix-core path
@@ -3091,7 +3348,7 @@ static igb_status launch_m2l(igb_op op, const MatvecWork& W, double2* xh, int64_
     kind = lo ? 1 : (mf_fp64(op) && ncol >= MF64_MIN_COLS) ? 2 : 0;
     if (kind == 2) {
         if (hard) launch_m2l_lo_t<MfmaF64, true>(op, W, xh, ks, ncol, s);
-        else launch_m2l_lo_t<MfmaF64, false>(op, W, xh, ks, ncol, s);
+        else launch_m2l_f64_soft(op, W, xh, ncol, s);
     } else if (!lo) {
         if ((op->nq + 63) / 64 * 64 > 128) {
             set_error("h2_matvec: interpolation degree too large for the coupling kernel");
@@ -3179,6 +3436,7 @@ static MatvecWork own_work(igb_op op) {
     W.yfar = op->d_yfar.as<double2>();
     W.x2 = op->d_x2.as<double2>();
     W.leafbuf = op->d_leafbuf.as<double2>();
+    W.xnear64 = op->d_xnear64.as<double2>();
     return W;
 }
 
@@ -3250,6 +3508,7 @@ igb_status matvec_noalloc(igb_op op, const double* x, double* y, int ncol, int p
     W.yfar = static_cast<double2*>(at(WorkSizes::YFAR));
     W.x2 = static_cast<double2*>(at(WorkSizes::X2));
     W.leafbuf = static_cast<double2*>(at(WorkSizes::LEAFBUF));
+    W.xnear64 = static_cast<double2*>(at(WorkSizes::XNEAR64));
     return matvec_launches(op, W, x, y, ncol, parts, s);
 }
 
@@ -3397,6 +3656,16 @@ static igb_status matvec_launches(igb_op op, const MatvecWork& W, const double* 
     } else if (ncol == 1) {
         hipLaunchKernelGGL(spmv_combine<1>, sg, sb, 0, s, rp, rco, dcl, vl, X, N, yfar, g->n2, s0p, s0r, use_near,
                            ncol, Y);
+    } else if (ncol >= MF64_MIN_COLS && op->d_val64.ptr && W.xnear64) {
+        // fp64 matrix cores over the tiles: columns transposed into 16-wide rows once
+        const int ncb = (ncol + 15) / 16;
+        if (use_near)
+            hipLaunchKernelGGL(columns_t64, dim3(blocks_for(int64_t(ncb) * N * 16, 256)), dim3(256), 0, s, X, N,
+                               ncol, ncb, W.xnear64);
+        hipLaunchKernelGGL(near_tiles_mfma64, dim3(unsigned(op->near_tiles.size()), unsigned(ncb)),
+                           dim3(64 * NEAR64_WAVES), 0, s, op->d_near_tiles.as<NearTile>(),
+                           int64_t(op->near_tiles.size()), op->d_near_tile_cols.as<int>(), op->d_val64.as<double2>(),
+                           W.xnear64, N, yfar, g->n2, s0p, s0r, use_near, ncol, Y);
     } else {
         hipLaunchKernelGGL(spmv_combine<4>, sg, sb, 0, s, rp, rco, dcl, vl, X, N, yfar, g->n2, s0p, s0r, use_near,
                            ncol, Y);

@@ -412,7 +412,7 @@ igb_status near_pattern(igb_op op) {
         std::copy(src->begin(), src->end(), op->col.begin() + op->row_ptr[r]);
     });
 
-    // bf16 operators: rows with the same leaves (hence the same column list) form
+    // rows with the same leaves (hence the same column list) form
     // groups, taken in order of their first row; up to 16 rows of neighbouring
     // groups share a tile whose columns are the union of theirs, as long as the
     // union stays within NEAR_TILE_FILL of the longest member list (the rows'
@@ -441,7 +441,10 @@ igb_status near_pattern(igb_op op) {
                              op->col.begin() + op->row_ptr[g->front() + 1]);
         for (int r : *g) op->row_coff[r] = off;
     }
-    if (op->prm.precision == IGB_MIX_BF16) {
+    {
+        // bf16 operators use the tiles with fp32 values (inner matvecs), fp64
+        // operators with fp64 values (blocks of >= 16 columns); built for every
+        // operator (host plan only)
         std::vector<int> rows, cols, tmp;
         size_t longest = 0;
         auto emit = [&]() {

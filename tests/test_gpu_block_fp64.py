@@ -15,7 +15,11 @@ the same products in different orders, so:
   rounding only: at most 1e-12 relative to max |y| (the sums run over
   ~5,000 tiles of 25 x 25 products, so fp64 reordering moves them by ~1e-15);
 * lockstep solves of 16 directions on the level-2 spheres reproduce the
-  oracle's dense LU solution and far field of the one direction it stores.
+  oracle's dense LU solution and far field of the one direction it stores;
+* the near product of blocks of >= 16 columns runs on the fp64 matrix cores
+  over tiles of up to 16 rows with a common column list: it matches O1's near
+  product and, entry by entry, the one-column CSR product within the fp64
+  rounding bound of the two summation orders.
 """
 import functools
 import os
@@ -122,3 +126,68 @@ def test_sixteen_direction_fp64_solve_matches_oracle_lu(bc):
     print(f"{bc}: 16-direction fp64 block, column 5 vs LU {e_t:.2e}, far field vs LU {e_u:.2e}, vs Mie "
           f"{e_mie:.2e}", flush=True)
     assert e_t < 1e-6 and e_u < 1e-6 and e_mie < 1e-3
+
+
+U64 = 2.0 ** -53
+
+
+def near_bound(op, X, factor=2.0):
+    """factor * gamma_{n+2} * sum_j |v_ij| |x_j| per row and column (fp64
+    rounding of a length-n complex inner product, each of the two summation
+    orders), from the operator's CSR."""
+    import scipy.sparse as sp
+    rp, col, val = op.near_csr()
+    n = len(rp) - 1
+    A = sp.csr_matrix((np.abs(val), col, rp), shape=(n, n))
+    lens = np.diff(rp).astype(np.float64) + 2
+    gamma = lens * U64 / (1 - lens * U64)
+    return factor * gamma[None, :] * (A @ np.abs(X).T).T
+
+
+@BCS
+@pytest.mark.parametrize("ncol", [16, 20])
+def test_fp64_tile_near_product_matches_oracle(bc, ncol):
+    """Blocks of >= 16 columns take the near product on the fp64 matrix cores
+    (tiles of up to 16 rows over a common column list): column 0 (the oracle's
+    vector) against O1's near product (quadrature tolerance 1e-8), and every
+    column against the one-column CSR product within the fp64 rounding bound
+    of the two summation orders."""
+    g = gold(SMALL[bc])
+    gb = gold("sphere_m3_p2_k2_q4_block")
+    geo, op = operator(3, 2, 2.0, 4, 1, bc)
+    X = np.concatenate([g["x"][None, :], gb[f"{bc}_X"][1:ncol]])
+    Y = apply_block(op, X, B().PART_NEAR)
+    e_or = rel(Y[0], g["y_near"])
+    Y1 = np.stack([apply_block(op, X[c:c + 1], B().PART_NEAR)[0] for c in range(ncol)])
+    bound = near_bound(op, X)
+    err = np.abs(Y - Y1)
+    print(f"{bc} {ncol}: near vs oracle {e_or:.2e}; tile vs CSR max err / bound "
+          f"{(err / np.maximum(bound, 1e-300)).max():.3f}, rel {err.max() / np.abs(Y1).max():.2e}", flush=True)
+    assert e_or < 1e-8
+    assert np.all(err <= bound)
+    assert err.max() > 0, "the block did not take the tile path"
+
+
+SMALL = {"soft": "sphere_m3_p2_k2_q4", "hard": "sphere_m3_p2_k2_q4_hard"}
+
+
+@pytest.mark.parametrize("bc,m,d", [("soft", 5, 2), ("hard", 4, 1)])
+def test_fp64_tile_near_product_at_size(bc, m, d):
+    """The bench workload's sphere (m = 5, kappa = 8, q = 6, leaf depth 2) and
+    a level-4 hard operator: 16 and 20 columns of the fp64 tile near product
+    against the one-column CSR product, entry by entry within the bound; with
+    the far part added (PART_ALL) the block equals near + far."""
+    from paper_2306_11324_amd import inputs as I
+    geo, op = operator(m, 2, 8.0, 6, d, bc)
+    for ncol in (16, 20):
+        X = I.random_complex(41 + ncol, (ncol, op.n))
+        Y = apply_block(op, X, B().PART_NEAR)
+        Y1 = np.stack([apply_block(op, X[c:c + 1], B().PART_NEAR)[0] for c in range(ncol)])
+        bound = near_bound(op, X)
+        err = np.abs(Y - Y1)
+        print(f"{bc} m={m} ncol={ncol}: max err / bound {(err / np.maximum(bound, 1e-300)).max():.3f}, rel "
+              f"{err.max() / np.abs(Y1).max():.2e}", flush=True)
+        assert np.all(err <= bound)
+        Z = apply_block(op, X, B().PART_ALL)
+        F = apply_block(op, X, B().PART_FAR)
+        assert np.abs(Z - (Y + F)).max() <= 1e-12 * np.abs(Z).max()
