@@ -56,7 +56,15 @@ MEASURED_TRAFFIC = {"m2l_chunks_wave": 2.147e9, "fp64": None, "fp32": 1.281e9, "
 WORKLOADS = {
     "sphere_m5_p2_k8": dict(geometry="sphere", m=5, p=2, kappa=8.0, q=6, eta_adm=1.6, leaf_depth=2,
                             kcap=0.0, tol=1e-8, golden="sphere_m5_p2_k8_rows"),
+    # the star configurations: one operator solving a block of directions
+    "star_m6_p2_k16": dict(geometry="star", m=6, p=2, kappa=16.0, q=8, eta_adm=1.6, leaf_depth=3, kcap=5.0,
+                           tol=1e-8, bc="soft", ndir=64, precision="fp64", on_the_fly=False, dir_seed=1,
+                           golden="star_m6_p2_k16_rows"),
+    "star_m7_p2_k32_hard": dict(geometry="star", m=7, p=2, kappa=32.0, q=8, eta_adm=1.6, leaf_depth=3, kcap=8.0,
+                                tol=1e-8, bc="hard", ndir=16, precision="bf16", on_the_fly=True, dir_seed=2,
+                                golden="star_m7_p2_k32_hard_rows"),
 }
+PEAKS = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
 
 
 def cpu_baseline(w, reps=5):
@@ -108,6 +116,194 @@ def cpu_baseline(w, reps=5):
                       f"({t_asm:.1f} s), extrapolated to the whole matrix",
             "matvec_s": t_mv, "solve_lu_s": t_lu, "solves_per_s": 1.0 / t_lu,
             "assembly_s_extrapolated": t_asm * E / cores, "blas": blas}
+
+
+def large_workload(name, steps, warmup):
+    """A star configuration: one operator, a block of incident directions solved
+    in lockstep (fp64, or bf16 couplings inside fp64 refinement), far fields at
+    64 directions.  One step = one block solve + its far fields; `value` counts
+    the column matvecs inside the timed steps.  Beside it: the single-column fp64
+    matvec, the block matvec alone with per-kernel HIP-event times and the
+    coupling kernel's roofline, the error against the stored oracle rows (relative
+    to the operator and to this product), and the far-field invariants of the
+    solved block (optical theorem per direction, reciprocity)."""
+    import torch
+
+    from paper_2306_11324_amd import binding as B
+    from paper_2306_11324_amd import inputs as I
+    w = WORKLOADS[name]
+    dev = torch.device("cuda:0")
+    torch.cuda.init()
+    ctx = B.Context(0)
+    prec = {"fp64": B.FP64, "fp32": B.MIX_FP32, "bf16": B.MIX_BF16}[w["precision"]]
+    t0 = time.perf_counter()
+    geo = B.Geometry(ctx, I.star_patches(0, I.star_geometry_level(w["m"])), w["m"], w["p"])
+    op = B.Operator(ctx, geo, kappa=w["kappa"], bc=B.SOFT if w["bc"] == "soft" else B.HARD, q=w["q"],
+                    eta_adm=w["eta_adm"], kcap=w["kcap"], leaf_depth=w["leaf_depth"], precision=prec,
+                    far_on_the_fly=w["on_the_fly"])
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    info = op.info
+    n, nd = op.n, w["ndir"]
+    print(f"# {name}: N={n} far_pairs={info.far_pairs} nnz={info.nnz} device={info.device_bytes / 1e9:.1f} GB "
+          f"setup={t_setup:.1f}s", file=sys.stderr, flush=True)
+    lowp = B.MV_LOWPREC if prec != B.FP64 else 0
+
+    def timed(ncol, parts, reps):
+        X = torch.from_numpy(I.random_complex(7 + ncol, (ncol, n))).to(dev)
+        Y = torch.zeros_like(X)
+        op.h2_matvec(X, Y, nrhs=ncol, parts=parts)
+        torch.cuda.synchronize()
+        op.profile(True)
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            op.h2_matvec(X, Y, nrhs=ncol, parts=parts)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / reps
+        km = {}
+        for k in ("m2l", "spmv", "upward", "downward"):
+            cnt, ms = op.kernel_time(k)
+            km[k] = ms / max(cnt, 1)
+        op.profile(False)
+        del X, Y
+        return dt, km
+
+    dt1, km1 = timed(1, B.PART_ALL, 5)
+    dtb, kmb = timed(nd, B.PART_ALL | lowp, 5)
+    nq2 = info.nq * info.nq
+    ntile = 2 if w["bc"] == "hard" else 1
+    nvec = 10 if w["bc"] == "hard" else 1      # hard: G on 6 vectors, H on 4
+    flops = 8.0 * info.far_pairs * nq2 * nd * (nvec if w["bc"] == "hard" else 1)
+    esz = {"fp64": 16, "fp32": 8, "bf16": 4}[w["precision"]]
+    tile_bytes = float(info.far_pairs * ntile * nq2 * esz)
+    m2l_s = kmb["m2l"] * 1e-3
+    if w["precision"] == "fp64":
+        roof = {"bound": "mfma", "achieved": flops / m2l_s / 1e12, "peak": PEAKS["fp64"] / 1e12, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": tile_bytes / m2l_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof.update({"frac": roof["achieved"] / roof["peak"], "traffic": None,
+                 "kernel": "m2l_mfma64_soft (fp64 matrix cores)" if w["precision"] == "fp64" else
+                           "m2l_mfma<bf16, hard> (bf16 matrix cores)",
+                 "avg_launch_ms": kmb["m2l"], "algorithmic_bytes": tile_bytes, "algorithmic_flops": flops})
+    # error against the stored oracle rows (fp64 product; also the reduced-precision one)
+    g = np.load(os.path.join(ROOT, "tests", "golden", w["golden"] + ".npz"))
+    errs = {}
+    for label, parts in (("fp64", B.PART_ALL), (w["precision"], B.PART_ALL | lowp)):
+        if label in errs:
+            continue
+        xg = torch.from_numpy(g["x"]).to(dev)
+        yg = torch.zeros_like(xg)
+        op.h2_matvec(xg, yg, parts=parts)
+        torch.cuda.synchronize()
+        yr = yg.cpu().numpy()[g["rows"]]
+        errs[label] = {"operator_relative": float(np.max(np.abs(yr - g["y"]) / (g["rownorm1"] * np.abs(g["x"]).max()))),
+                       "vector_relative": float(np.max(np.abs(yr - g["y"])) / np.max(np.abs(g["y"])))}
+    # block solves
+    dirs = I.random_directions(w["dir_seed"], nd)
+    obs = I.fibonacci_directions(64)
+    coeff = torch.zeros((nd, n), dtype=torch.complex128, device=dev)
+    uinf = torch.zeros((nd, 64), dtype=torch.complex128, device=dev)
+    for _ in range(warmup):
+        op.cfie_solve(dirs, coeff, tol=w["tol"], restart=30, maxit=3000)
+        op.farfield(coeff, obs, uinf, ndir=nd)
+    torch.cuda.synchronize()
+    mv, t_solve = 0, 0.0
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        si, st = op.cfie_solve(dirs, coeff, tol=w["tol"], restart=30, maxit=3000)
+        op.farfield(coeff, obs, uinf, ndir=nd)
+        mv += si.matvecs
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t1
+    # far-field invariants of the solved block (16,384-point Fibonacci lattice)
+    fobs = I.fibonacci_directions(16384)
+    u = torch.zeros((nd, len(fobs)), dtype=torch.complex128, device=dev)
+    op.farfield(coeff, fobs, u, ndir=nd)
+    fwd = torch.zeros((nd, nd), dtype=torch.complex128, device=dev)
+    op.farfield(coeff, dirs, fwd, ndir=nd)
+    back = torch.zeros((nd, nd), dtype=torch.complex128, device=dev)
+    op.farfield(coeff, -dirs, back, ndir=nd)
+    torch.cuda.synchronize()
+    u, fwd, back = u.cpu().numpy(), np.diag(fwd.cpu().numpy()), back.cpu().numpy()
+    lhs = 4 * np.pi * np.mean(np.abs(u) ** 2, axis=1)
+    rhs = 4 * np.pi / w["kappa"] * fwd.imag
+    out = {
+        "metric": METRIC, "value": mv / T, "unit": "matvecs/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": T / steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if w["precision"] == "fp64" else "bf16 far field, f64 near field and refinement",
+        "data": "synthetic",
+        "config": {"workload": name, "geometry": "star r = 1 + 0.1 sum c_lm Y_lm (l <= 4), seed 0, 6 patches",
+                   "level_m": w["m"], "degree_p": w["p"], "N": n, "kappa": w["kappa"], "bc": w["bc"],
+                   "q": w["q"], "eta_adm": w["eta_adm"], "kcap": w["kcap"], "leaf_depth": w["leaf_depth"],
+                   "rhs": nd, "precision": w["precision"], "fp64_far_on_the_fly": w["on_the_fly"],
+                   "gmres": f"restart 30, tol {w['tol']}", "far_pairs": info.far_pairs, "nnz_near": info.nnz,
+                   "device_GB": info.device_bytes / 1e9},
+        "solves_per_s": steps * nd / T, "gmres_iters": si.iters, "relres_true": si.relres_true,
+        "refinements": si.refinements, "escalated": si.escalated, "setup_s": t_setup,
+        "assembly_near_ms": info.assembly_near_ms, "assembly_far_ms": info.assembly_far_ms,
+        "single_column_fp64": {"matvecs_per_s": 1.0 / dt1, "kernel_ms": km1},
+        "block_matvec": {"ncol": nd, "column_matvecs_per_s": nd / dtb, "ms": dtb * 1e3, "kernel_ms": kmb},
+        "err_vs_oracle_rows": errs,
+        "farfield_invariants": {"optical_theorem_max_rel": float(np.max(np.abs(lhs - rhs) / np.abs(rhs))),
+                                "reciprocity_max_rel": float(np.max(np.abs(back - back.T)) / np.max(np.abs(back)))},
+        "roofline": roof,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def scaling_sweep(levels, kappa=2.0, q=6, leaf_depth=2):
+    """Matvec time, operator bytes and solve against the level m on the sphere
+    at fixed kappa and q (the paper's log-linear time-to-solution claim of Sec.
+    5.2): one JSON line per level."""
+    import torch
+
+    from paper_2306_11324_amd import binding as B
+    from paper_2306_11324_amd import inputs as I
+    dev = torch.device("cuda:0")
+    torch.cuda.init()
+    ctx = B.Context(0)
+    d = np.array([[0.0, 0.0, 1.0]])
+    rows = []
+    for m in levels:
+        t0 = time.perf_counter()
+        geo = B.Geometry(ctx, I.sphere_patches(), m, 2)
+        op = B.Operator(ctx, geo, kappa=kappa, q=q, eta_adm=1.6, leaf_depth=leaf_depth)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        x = torch.from_numpy(I.random_complex(12345, op.n)).to(dev)
+        y = torch.zeros_like(x)
+        op.h2_matvec(x, y)
+        torch.cuda.synchronize()
+        reps = 20
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            op.h2_matvec(x, y)
+        torch.cuda.synchronize()
+        t_mv = (time.perf_counter() - t0) / reps
+        coeff = torch.zeros((1, op.n), dtype=torch.complex128, device=dev)
+        info, st = op.cfie_solve(d, coeff, tol=1e-8, restart=30, maxit=3000)
+        oi = op.info
+        nq2 = oi.nq * oi.nq
+        rec = {"sweep": "sphere level", "m": m, "N": op.n, "kappa": kappa, "q": q, "leaf_depth": leaf_depth,
+               "far_pairs": oi.far_pairs, "nnz_near": oi.nnz,
+               "stream_bytes": oi.far_pairs * nq2 * 16 + oi.nnz * 16, "device_bytes": oi.device_bytes,
+               "matvec_ms": t_mv * 1e3, "setup_s": t_setup, "gmres_iters": info.iters,
+               "solve_s": info.seconds, "relres_true": info.relres_true}
+        rows.append(rec)
+        print(json.dumps(rec), flush=True)
+        del op, geo, x, y, coeff
+        torch.cuda.empty_cache()
+    # slopes of log(quantity) against log(N) over the levels whose matrix has a
+    # far field from the previous level on (below that the operator is the dense
+    # near field), and the paper's guide line m 4^m: time / (m 4^m) per level
+    far = [r for r in rows if r["far_pairs"] > 0][1:]
+    if len(far) > 1:
+        lN = np.log([r["N"] for r in far])
+        fit = {k: float(np.polyfit(lN, np.log([r[k] for r in far]), 1)[0])
+               for k in ("matvec_ms", "stream_bytes", "setup_s", "solve_s")}
+        guide = {r["m"]: r["matvec_ms"] / (r["m"] * 4.0 ** r["m"]) for r in rows}
+        print(json.dumps({"sweep": "sphere level", "levels_fitted": [r["m"] for r in far],
+                          "loglog_slope_vs_N": fit, "matvec_ms_over_m4m": guide}), flush=True)
 
 
 def serve_stream(nreq, rate):
@@ -222,6 +418,7 @@ def main():
     ap.add_argument("--conv-reference", default="cfie", choices=["cfie", "single_layer"],
                     help="reference solution: the finest CFIE solution or the single-layer one (as the paper)")
     ap.add_argument("--conv-out", default=None, help="also write the study's JSON lines to this file")
+    ap.add_argument("--sweep", default=None, help="levels m for the scaling sweep, e.g. 3,4,5,6,7")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
@@ -233,6 +430,12 @@ def main():
     if args.convergence:
         convergence_study(args.conv_mmax, args.conv_q, args.conv_quad_extra, tuple(args.conv_bc.split(",")),
                           args.conv_out, args.conv_reference)
+        return
+    if args.sweep:
+        scaling_sweep([int(v) for v in args.sweep.split(",")])
+        return
+    if args.workload != "sphere_m5_p2_k8":
+        large_workload(args.workload, args.steps, args.warmup)
         return
 
     import torch

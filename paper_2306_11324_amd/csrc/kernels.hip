@@ -2172,15 +2172,17 @@ __global__ void columns_t64(const double2* __restrict__ x, int64_t nrows, int nc
 }
 
 // Near product of fp64 operators for blocks of >= 16 columns on the fp64
-// matrix cores: per tile and 16 columns, Y = V X with the fp64 tile values as
-// the A operand (16 rows; rows past nrows read row 0, their outputs are not
-// stored) and the columns gathered through the tile's column list as the B
-// operand.  The waves take every NW-th k block of 4 columns in increasing
-// order and meet in LDS in wave order; each output column depends only on its
-// own input column in an order fixed by the tile, so every block of >= 16
-// columns gives bitwise the same column results (which differ from the
-// one-column CSR product by rounding: another summation order).
+// matrix cores: per tile and NC tiles of 16 columns, Y = V X with the fp64 tile
+// values as the A operand (16 rows; rows past nrows read row 0, their outputs
+// are not stored) and the columns gathered through the tile's column list as
+// the B operand, so every tile value read serves 16 NC columns.  The waves take
+// every NW-th k block of 4 columns in increasing order and meet in LDS in wave
+// order; each output column depends only on its own input column in an order
+// fixed by the tile, so every block of >= 16 columns gives bitwise the same
+// column results (which differ from the one-column CSR product by rounding:
+// another summation order).
 constexpr int NEAR64_WAVES = 8;
+template <int NC>
 __global__ __launch_bounds__(64 * NEAR64_WAVES) void near_tiles_mfma64(
     const NearTile* __restrict__ tiles, int64_t ntile, const int* __restrict__ tcol, const double2* __restrict__ vt,
     const double2* __restrict__ xt, int64_t nrows, const double2* __restrict__ yfar, int64_t n2,
@@ -2195,19 +2197,28 @@ __global__ __launch_bounds__(64 * NEAR64_WAVES) void near_tiles_mfma64(
     const NearTile& T = tiles[t];
     const int nr = T.nrows, nc = T.ncols;
     const int nkb = (nc + KB - 1) / KB;
-    const double2* xb = xt + int64_t(blockIdx.y) * nrows * 16 + li;
+    // column tile j of this workgroup: block (NC blockIdx.y + j) of the
+    // transposed columns [block][row][16]
+    const double2* xb = xt + int64_t(blockIdx.y) * NC * nrows * 16 + li;
     const int* cl = tcol + T.col_off;
     const int ra = li < nr ? li : 0;
     const double2* va = vt + T.val_off + ra * KB + g;
     const int64_t kbstride = int64_t(nr) * KB;
-    f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    auto load = [&](int kb, int kl, uint4& A, uint4& X) {
+    f64x4 acc[NC][2];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) acc[j][0] = acc[j][1] = f64x4{0.0, 0.0, 0.0, 0.0};
+    auto load = [&](int kb, int kl, uint4& A, uint4 (&X)[NC]) {
         A = *reinterpret_cast<const uint4*>(va + kb * kbstride);
-        X = *reinterpret_cast<const uint4*>(xb + int64_t(cidx[kl + g]) * 16);
+        const int64_t o = int64_t(cidx[kl + g]) * 16;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) X[j] = *reinterpret_cast<const uint4*>(xb + int64_t(j) * nrows * 16 + o);
     };
-    auto compute = [&](const uint4& A, const uint4& X) {
-        acc0 = MfmaF64::step(A, MfmaF64::re_part(X), acc0);
-        acc1 = MfmaF64::step(A, MfmaF64::im_part(X), acc1);
+    auto compute = [&](const uint4& A, const uint4 (&X)[NC]) {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            acc[j][0] = MfmaF64::step(A, MfmaF64::re_part(X[j]), acc[j][0]);
+            acc[j][1] = MfmaF64::step(A, MfmaF64::im_part(X[j]), acc[j][1]);
+        }
     };
     if (use_near) {
         // chunks of columns: indices to LDS (past the list: its last column, whose
@@ -2220,46 +2231,55 @@ __global__ __launch_bounds__(64 * NEAR64_WAVES) void near_tiles_mfma64(
             const int kb0 = k0 / KB, kb1 = min(nkb, kb0 + NEAR_TILE_CHUNK / KB);
             int kb = kb0 + wave;
             for (; kb + NW < kb1; kb += 2 * NW) {
-                uint4 A0, X0, A1, X1;
+                uint4 A0, X0[NC], A1, X1[NC];
                 load(kb, (kb - kb0) * KB, A0, X0);
                 load(kb + NW, (kb + NW - kb0) * KB, A1, X1);
                 compute(A0, X0);
                 compute(A1, X1);
             }
             if (kb < kb1) {
-                uint4 A0, X0;
+                uint4 A0, X0[NC];
                 load(kb, (kb - kb0) * KB, A0, X0);
                 compute(A0, X0);
             }
         }
     }
-    if (wave > 0) {
-        red[wave - 1][0][lane] = acc0;
-        red[wave - 1][1][lane] = acc1;
-    }
-    __syncthreads();
-    if (wave > 0) return;
+    // the waves' sums meet in LDS in wave order, one column tile at a time
 #pragma unroll
-    for (int w = 0; w < NW - 1; ++w) {
-        acc0 += red[w][0][lane];
-        acc1 += red[w][1][lane];
-    }
-    const int c = blockIdx.y * 16 + li;
-    if (c >= ncol) return;
+    for (int j = 0; j < NC; ++j) {
+        __syncthreads();
+        if (wave > 0) {
+            red[wave - 1][0][lane] = acc[j][0];
+            red[wave - 1][1][lane] = acc[j][1];
+        }
+        __syncthreads();
+        if (wave == 0) {
+            f64x4 s0 = acc[j][0], s1 = acc[j][1];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = MfmaF64::orow(g, r);
-        if (i >= nr) continue;
-        const int row = T.rows[i];
-        double2 a = make_double2(acc0[r], acc1[r]);
-        if (yfar) {
-            if (s0_ptr) {
-                for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q) a = cadd(a, yfar[int64_t(c) * n2 + s0_reps[q]]);
-            } else {
-                a = cadd(a, yfar[int64_t(c) * n2 + row]);
+            for (int w = 0; w < NW - 1; ++w) {
+                s0 += red[w][0][lane];
+                s1 += red[w][1][lane];
+            }
+            const int c = (blockIdx.y * NC + j) * 16 + li;
+            if (c < ncol) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = MfmaF64::orow(g, r);
+                    if (i >= nr) continue;
+                    const int row = T.rows[i];
+                    double2 a = make_double2(s0[r], s1[r]);
+                    if (yfar) {
+                        if (s0_ptr) {
+                            for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q)
+                                a = cadd(a, yfar[int64_t(c) * n2 + s0_reps[q]]);
+                        } else {
+                            a = cadd(a, yfar[int64_t(c) * n2 + row]);
+                        }
+                    }
+                    y[int64_t(c) * nrows + row] = a;
+                }
             }
         }
-        y[int64_t(c) * nrows + row] = a;
     }
 }
 
@@ -3662,10 +3682,30 @@ static igb_status matvec_launches(igb_op op, const MatvecWork& W, const double* 
         if (use_near)
             hipLaunchKernelGGL(columns_t64, dim3(blocks_for(int64_t(ncb) * N * 16, 256)), dim3(256), 0, s, X, N,
                                ncol, ncb, W.xnear64);
-        hipLaunchKernelGGL(near_tiles_mfma64, dim3(unsigned(op->near_tiles.size()), unsigned(ncb)),
-                           dim3(64 * NEAR64_WAVES), 0, s, op->d_near_tiles.as<NearTile>(),
-                           int64_t(op->near_tiles.size()), op->d_near_tile_cols.as<int>(), op->d_val64.as<double2>(),
-                           W.xnear64, N, yfar, g->n2, s0p, s0r, use_near, ncol, Y);
+        // NC column tiles per workgroup (each tile value read serves 16 NC columns),
+        // NC dividing the column tile count, as long as the grid keeps at least
+        // 2048 workgroups (8 per CU); the column results do not depend on NC
+        const int64_t ntl0 = int64_t(op->near_tiles.size());
+        int nct = 1;
+        for (int c : {4, 2})
+            if (ncb % c == 0 && ntl0 * (ncb / c) >= 2048) {
+                nct = c;
+                break;
+            }
+        const dim3 tg(unsigned(op->near_tiles.size()), unsigned(ncb / nct)), tb(64 * NEAR64_WAVES);
+        const NearTile* tl = op->d_near_tiles.as<NearTile>();
+        const int64_t ntl = int64_t(op->near_tiles.size());
+        const int* tcl = op->d_near_tile_cols.as<int>();
+        const double2* v64 = op->d_val64.as<double2>();
+        if (nct == 4)
+            hipLaunchKernelGGL(near_tiles_mfma64<4>, tg, tb, 0, s, tl, ntl, tcl, v64, W.xnear64, N, yfar, g->n2, s0p,
+                               s0r, use_near, ncol, Y);
+        else if (nct == 2)
+            hipLaunchKernelGGL(near_tiles_mfma64<2>, tg, tb, 0, s, tl, ntl, tcl, v64, W.xnear64, N, yfar, g->n2, s0p,
+                               s0r, use_near, ncol, Y);
+        else
+            hipLaunchKernelGGL(near_tiles_mfma64<1>, tg, tb, 0, s, tl, ntl, tcl, v64, W.xnear64, N, yfar, g->n2, s0p,
+                               s0r, use_near, ncol, Y);
     } else {
         hipLaunchKernelGGL(spmv_combine<4>, sg, sb, 0, s, rp, rco, dcl, vl, X, N, yfar, g->n2, s0p, s0r, use_near,
                            ncol, Y);
