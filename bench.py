@@ -335,6 +335,41 @@ def serve_stream(nreq, rate):
     return out
 
 
+def serve_study(capacity=None, n_capacity=48, n_sweep=48, fractions=(0.4, 0.6, 0.8, 1.0), n_main=200,
+                main_fraction=0.8):
+    """The serving protocol: capacity (every request visible at once: requests
+    served per second), then Poisson streams at fractions of that capacity
+    (p50 / p99 latency per rate), then `n_main` requests at `main_fraction` of
+    capacity.  Each stream is the seeded request_stream (levels 3..6, kappa in
+    [1, 32], 1..16 directions, soft / hard), one JSON line per stream;
+    `mean_in_service` = summed admitted-to-done time / wall time (requests
+    being served at once)."""
+    from paper_2306_11324_amd import inputs as I
+    from paper_2306_11324_amd.serving import ServeConfig, Server
+    cfg = ServeConfig(slots=4)
+    srv = Server(cfg)
+
+    def log(r):
+        print(f"# served request {r.rid}: N={r.n} directions={r.uinf.shape[0]} latency={r.latency:.2f}s",
+              file=sys.stderr, flush=True)
+
+    def run(n, rate, realtime, label):
+        reqs = I.request_stream(n, rate=rate, seed=3)
+        res = srv.run(reqs, realtime=realtime, log=log)
+        out = Server.summary(res, srv.wall)
+        out["mean_in_service"] = sum(r.done - r.admitted for r in res) / srv.wall
+        out.update({"stream": label, "arrival_rate_per_s": rate if realtime else None, "slots": cfg.slots})
+        print(json.dumps(out), flush=True)
+        return out
+
+    if capacity is None:
+        capacity = run(n_capacity, 1.0, False, "capacity: all requests visible at once")["requests_per_s"]
+    for f in fractions:
+        run(n_sweep, f * capacity, True, f"rate sweep: {f:.1f} x capacity {capacity:.3f}/s")
+    if n_main:
+        run(n_main, main_fraction * capacity, True, f"{n_main} requests at {main_fraction:.1f} x capacity")
+
+
 def convergence_study(mmax, q, quad_extra, bcs=("soft", "hard"), out_path=None, reference="cfie"):
     import torch
 
@@ -419,6 +454,11 @@ def main():
                     help="reference solution: the finest CFIE solution or the single-layer one (as the paper)")
     ap.add_argument("--conv-out", default=None, help="also write the study's JSON lines to this file")
     ap.add_argument("--sweep", default=None, help="levels m for the scaling sweep, e.g. 3,4,5,6,7")
+    ap.add_argument("--serve-study", action="store_true",
+                    help="serving protocol: capacity, rate sweep, --serve-main requests at 0.8 x capacity")
+    ap.add_argument("--serve-capacity", type=float, default=None, help="skip the capacity run (requests/s)")
+    ap.add_argument("--serve-fractions", default="0.4,0.6,0.8,1.0")
+    ap.add_argument("--serve-main", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
@@ -433,6 +473,10 @@ def main():
         return
     if args.sweep:
         scaling_sweep([int(v) for v in args.sweep.split(",")])
+        return
+    if args.serve_study:
+        fr = tuple(float(v) for v in args.serve_fractions.split(",")) if args.serve_fractions else ()
+        serve_study(args.serve_capacity, fractions=fr, n_main=args.serve_main)
         return
     if args.workload != "sphere_m5_p2_k8":
         large_workload(args.workload, args.steps, args.warmup)

@@ -19,8 +19,11 @@
  *     Handles own their device memory until destroyed; they may be destroyed in
  *     any order (an operator keeps its geometry, a geometry its context alive
  *     until the last dependent handle is destroyed).  Calls on one operator
- *     (h2_matvec, cfie_solve) use its internal work vectors and must not
- *     overlap; different operators may run concurrently on different streams.
+ *     (h2_matvec, cfie_rhs, cfie_solve, farfield, potential, potential_h2) use
+ *     its internal work vectors and must not overlap; different operators may
+ *     run concurrently on different streams.  Work buffers grow on demand and
+ *     stay with the operator until it is destroyed, so repeated calls of the
+ *     same size allocate nothing.
  *
  * Numbering (patch-major):
  *   elements  e = patch*4^m + ey*2^m + ex  covering [ex,ex+1]x[ey,ey+1]/2^m of the
@@ -201,10 +204,11 @@ typedef struct {
     int64_t near_elem_pairs;/* element pairs integrated by quadrature              */
     int64_t nnz;            /* nonzeros of the near-field matrix                    */
     int64_t device_bytes;   /* device memory held by the operator                   */
-    int64_t estimated_bytes;/* device memory the operator holds after assembly and
-                               a one-direction solve (size model; also on host-only
-                               contexts); assemble_nearfield checks the budget
-                               against this plus its own transient staging buffers */
+    int64_t estimated_bytes;/* device memory the operator holds after assembly, a
+                               one-direction solve and its far field at 64 directions
+                               (size model; also on host-only contexts);
+                               assemble_nearfield checks the budget against this
+                               plus its own transient staging buffers              */
     double assembly_near_ms, assembly_far_ms;
 } igb_op_info;
 
@@ -255,10 +259,12 @@ int64_t igb_op_ndof(igb_op op);
 int64_t igb_op_bytes(igb_op op);
 
 /* Size model of a solve: *bytes = device memory the operator holds after
- * cfie_solve with ndir directions and GMRES restart `restart` (0 = 30): its data
+ * cfie_solve with ndir directions and GMRES restart `restart` (0 = 30) and the
+ * far field of those ndir columns at up to 64 directions: its data
  * (estimated_bytes of igb_op_info without the one-column work), the matvec work
- * vectors of ndir columns and the solver's buffers (Krylov bases, right-hand
- * sides, refinement residual and corrections).  cfie_solve checks the budget
+ * vectors of ndir columns, the solver's buffers (Krylov bases, right-hand
+ * sides, refinement residual and corrections) and the right-hand-side and
+ * far-field quadrature buffers.  cfie_solve checks the budget
  * against this model before any work and returns IGB_ERR_BUDGET if the growth
  * would not fit.  Works on host-only contexts (admission planning). */
 igb_status igb_op_solve_bytes(igb_op op, int ndir, int restart, int64_t* bytes);

@@ -318,7 +318,7 @@ static igb_status build_one(igb_ctx ctx, igb_geom g, const igb_op_params* prm, c
     op->estimated_data = need;
     // plus the matvec work vectors of one column and a GMRES(30) solve of one column
     // (more columns: igb_op_solve_bytes)
-    need += work_sizes(op, 1).total() + solve_buffer_bytes(op, 30, 1);
+    need += work_sizes(op, 1).total() + solve_buffer_bytes(op, 30, 1) + quad_buffer_bytes(op, 1, 64);
     op->estimated_bytes = need;
     if (!budget_ok(ctx, need + transient)) {
         set_error("assemble_nearfield: HBM budget exceeded (%zu + %zu > %zu bytes)", ctx->used.load(),

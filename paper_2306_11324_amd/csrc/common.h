@@ -237,6 +237,10 @@ struct igb_op_s {
     igb::DevBuf d_krylov, d_w, d_h, d_b, d_dotpart, d_ref_r, d_ref_d, d_ref_d2;
     // device copies of host columns (h2_matvec with IGB_MV_HOST)
     igb::DevBuf d_hx, d_hy;
+    // right-hand side and far-field buffers (kept between calls): Gauss table,
+    // directions, element contributions, observation directions, quadrature
+    // points and densities
+    igb::DevBuf d_gauss, d_q_dirs, d_q_loc, d_q_obs, d_q_geo, d_q_dens;
     // false for a single boundary integral operator (no right-hand side or representation)
     bool system = true;
     // lazy sum y = sum_i sum_coef[i] sum_parts[i] x of separately stored H^2 matrices
@@ -367,9 +371,13 @@ igb_status gmres_device(igb_op op, const double* b, double* x, int ndir,
 // work vectors, Hessenberg steps, inner-product partials, right-hand sides and
 // (reduced-precision operators) the refinement residual and corrections
 size_t solve_buffer_bytes(const igb_op_s* op, int m, int ndir);
-// device bytes an operator holds after cfie_solve(ndir, restart m): its data,
-// the matvec work vectors of ndir columns and solve_buffer_bytes
-size_t solve_model_bytes(const igb_op_s* op, int m, int ndir);
+// device bytes an operator holds after cfie_solve(ndir, restart m) and a far
+// field of its ndir columns at nobs directions: its data, the matvec work
+// vectors of ndir columns, solve_buffer_bytes and quad_buffer_bytes
+size_t solve_model_bytes(const igb_op_s* op, int m, int ndir, int nobs = 64);
+// bytes of the right-hand side and far-field buffers (Gauss table, directions,
+// element contributions, quadrature points and densities)
+size_t quad_buffer_bytes(const igb_op_s* op, int ndir, int nobs);
 
 // kernel timing helpers (no-ops unless op->profile)
 igb_status timer_mark(igb_op op, int slot, hipStream_t s);

@@ -409,8 +409,8 @@ size_t solve_buffer_bytes(const igb_op_s* op, int m, int ndir) {
     return z.krylov + z.w + z.h + z.dotpart + z.rhs + 3 * z.ref;
 }
 
-size_t solve_model_bytes(const igb_op_s* op, int m, int ndir) {
-    size_t b = solve_buffer_bytes(op, m, ndir);
+size_t solve_model_bytes(const igb_op_s* op, int m, int ndir, int nobs) {
+    size_t b = solve_buffer_bytes(op, m, ndir) + quad_buffer_bytes(op, ndir, nobs);
     if (op->sum_parts.empty()) return b + op->estimated_data + work_sizes(op, ndir).total();
     for (const igb_op_s* p : op->sum_parts) b += p->estimated_data + work_sizes(p, ndir).total();
     return b + size_t(ndir) * op->N * sizeof(double2);   // the lazy sum's column buffer

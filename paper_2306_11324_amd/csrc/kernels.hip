@@ -3719,6 +3719,27 @@ int smooth_order(igb_op op, int base) {
     return std::min(NGMAX, base + kd_boost(op->kd_elem) + std::max(0, op->prm.quad_extra));
 }
 
+// bytes of the right-hand side and far-field buffers for ndir directions and
+// nobs observation directions (operator-owned, kept between calls)
+size_t quad_buffer_bytes(const igb_op_s* op, int ndir, int nobs) {
+    const igb_geom_s* g = op->geom;
+    const size_t nl = size_t(g->p + 1) * (g->p + 1);
+    const int nqd = smooth_order(const_cast<igb_op>(op), 6);
+    const size_t npts = size_t(g->nelem) * nqd * nqd;
+    return size_t(NGMAX + 1) * 2 * NGMAX * sizeof(double) + size_t(3) * ndir * sizeof(double) +
+           size_t(ndir) * g->nelem * nl * sizeof(double2) + size_t(3) * nobs * sizeof(double) +
+           npts * 8 * sizeof(double) + size_t(ndir) * npts * sizeof(double2);
+}
+
+// the Gauss-Legendre table on the device, once per operator
+static igb_status gauss_on_device(igb_op op) {
+    if (op->d_gauss.ptr) return IGB_OK;
+    const std::vector<double> gl = gauss_table();
+    if (igb_status st = op_reserve(op, op->d_gauss, gl.size() * sizeof(double), "gauss table")) return st;
+    IGB_HIP(hipMemcpy(op->d_gauss.ptr, gl.data(), gl.size() * sizeof(double), hipMemcpyHostToDevice));
+    return IGB_OK;
+}
+
 igb_status rhs_device(igb_op op, const double* dirs, int ndir, double* b, hipStream_t s) {
     igb_geom g = op->geom;
     std::vector<double> dn(3 * ndir);
@@ -3732,13 +3753,17 @@ igb_status rhs_device(igb_op op, const double* dirs, int ndir, double* b, hipStr
         for (int c = 0; c < 3; ++c) dn[3 * i + c] = dirs[3 * i + c] / nr;
     }
     igb_status st;
-    DevBuf d_dirs, d_gl, d_loc;
-    std::vector<double> gl = gauss_table();
-    if ((st = upload(d_dirs, dn.data(), dn.size(), nullptr))) return st;
-    if ((st = upload(d_gl, gl.data(), gl.size(), nullptr))) return st;
+    // operator-owned buffers, kept between calls (no allocation or free per call
+    // once they have grown): Gauss table, directions, element contributions
     const int NL = (g->p + 1) * (g->p + 1);
-    if ((st = alloc(d_loc, size_t(ndir) * g->nelem * NL * sizeof(double2), nullptr))) return st;
-    QuadGeoArgs A{g->d_bez.as<double>(), g->d_pg.as<int>(), g->d_C1.as<double>(), d_gl.as<double>(),
+    if ((st = gauss_on_device(op)) || (st = op_reserve(op, op->d_q_dirs, size_t(3) * ndir * sizeof(double), "cfie_rhs")) ||
+        (st = op_reserve(op, op->d_q_loc, size_t(ndir) * g->nelem * NL * sizeof(double2), "cfie_rhs")))
+        return st;
+    IGB_HIP(hipStreamSynchronize(s));   // earlier work on s may still read the direction buffer
+    IGB_HIP(hipMemcpy(op->d_q_dirs.ptr, dn.data(), dn.size() * sizeof(double), hipMemcpyHostToDevice));
+    const DevBuf& d_dirs = op->d_q_dirs;
+    const DevBuf& d_loc = op->d_q_loc;
+    QuadGeoArgs A{g->d_bez.as<double>(), g->d_pg.as<int>(), g->d_C1.as<double>(), op->d_gauss.as<double>(),
                   g->nel1, g->p, smooth_order(op, 6), g->nelem};
     const bool hard = op->bc == IGB_HARD;
     dim3 grid1(unsigned((g->nelem + 127) / 128), unsigned(ndir));
@@ -3757,7 +3782,6 @@ igb_status rhs_device(igb_op op, const double* dirs, int ndir, double* b, hipStr
          })))
         return st;
     IGB_HIP(hipGetLastError());
-    IGB_HIP(hipStreamSynchronize(s));  // temporaries are freed on return
     return IGB_OK;
 }
 
@@ -3776,13 +3800,18 @@ igb_status farfield_device(igb_op op, const double* coeffs, int ndir, const doub
     igb_status st;
     const int nqd = smooth_order(op, 6);
     const int64_t npts = g->nelem * nqd * nqd;
-    DevBuf d_obs, d_gl, d_geo, d_dens;
-    std::vector<double> gl = gauss_table();
-    if ((st = upload(d_obs, on.data(), on.size(), nullptr))) return st;
-    if ((st = upload(d_gl, gl.data(), gl.size(), nullptr))) return st;
-    if ((st = alloc(d_geo, size_t(npts) * 8 * sizeof(double), nullptr))) return st;
-    if ((st = alloc(d_dens, size_t(ndir) * npts * sizeof(double2), nullptr))) return st;
-    QuadGeoArgs A{g->d_bez.as<double>(), g->d_pg.as<int>(), g->d_C1.as<double>(), d_gl.as<double>(),
+    // operator-owned buffers, kept between calls: Gauss table, observation
+    // directions, quadrature points and densities
+    if ((st = gauss_on_device(op)) || (st = op_reserve(op, op->d_q_obs, on.size() * sizeof(double), "farfield")) ||
+        (st = op_reserve(op, op->d_q_geo, size_t(npts) * 8 * sizeof(double), "farfield")) ||
+        (st = op_reserve(op, op->d_q_dens, size_t(ndir) * npts * sizeof(double2), "farfield")))
+        return st;
+    IGB_HIP(hipStreamSynchronize(s));   // earlier work on s may still read these buffers
+    IGB_HIP(hipMemcpy(op->d_q_obs.ptr, on.data(), on.size() * sizeof(double), hipMemcpyHostToDevice));
+    const DevBuf& d_obs = op->d_q_obs;
+    const DevBuf& d_geo = op->d_q_geo;
+    const DevBuf& d_dens = op->d_q_dens;
+    QuadGeoArgs A{g->d_bez.as<double>(), g->d_pg.as<int>(), g->d_C1.as<double>(), op->d_gauss.as<double>(),
                   g->nel1, g->p, nqd, g->nelem};
     const bool hard = op->bc == IGB_HARD;
     const double2* C = reinterpret_cast<const double2*>(coeffs);

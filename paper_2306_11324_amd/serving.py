@@ -124,10 +124,10 @@ class Server:
         nd = len(req.dirs)
         geom_bytes = geo.nelem * (16 * 4 * 8 + 8) + 4096
         restart = self.cfg.restart_soft if req.bc == "soft" else self.cfg.restart_hard
-        # the library's size model of the operator after an nd-direction solve
-        # (data, matvec work vectors, Krylov bases, refinement buffers), plus the
-        # far-field output and temporaries
-        return int(op.solve_bytes(nd, restart) + geom_bytes + 4 * nd * self.cfg.nobs * 16 + (1 << 20))
+        # the library's size model of the operator after an nd-direction solve and
+        # its far field (data, matvec work vectors, Krylov bases, refinement and
+        # quadrature buffers), plus the caller's coefficient and far-field arrays
+        return int(op.solve_bytes(nd, restart) + geom_bytes + nd * (op.n + self.cfg.nobs) * 16 + (1 << 20))
 
     def solve(self, req: I.Request, ctx: B.Context):
         """Returns (n, solve info, far field [ndir][nobs], stage seconds)."""

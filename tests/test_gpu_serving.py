@@ -21,3 +21,21 @@ def test_each_result_same_alone_and_in_mix():
         m = mix[r.rid]
         assert np.array_equal(a.uinf, m.uinf), r.rid
     assert {r.bc for r in reqs} == {"soft", "hard"}
+
+
+def test_larger_requests_same_alone_and_in_mix():
+    """Levels 4 and 5 (up to N = 6,936), kappa in [4, 16], up to 13 directions,
+    bf16 couplings for soft and hard requests with fp64 refinement, 4 requests
+    in 3 slots: each far field bitwise the same alone and in the mix."""
+    from paper_2306_11324_amd import inputs as I
+    from paper_2306_11324_amd.serving import ServeConfig, Server
+    reqs = I.request_stream(4, rate=50.0, seed=30, m_values=(4, 5), kappa_range=(4.0, 16.0), max_dirs=16)
+    print("case: 4 requests m in {4,5}, kappa in [4,16], <= 13 directions, soft/hard bf16", flush=True)
+    assert {r.bc for r in reqs} == {"soft", "hard"} and any(r.m == 5 and r.bc == "hard" for r in reqs)
+    cfg = dict(q=6, leaf_depth=2, nobs=16)
+    mix = Server(ServeConfig(slots=3, **cfg)).run(reqs, realtime=False)
+    assert all(r.converged == r.uinf.shape[0] and r.relres_true <= 1e-8 for r in mix)
+    alone = Server(ServeConfig(slots=1, **cfg))
+    for r in reqs:
+        a = alone.run([r], realtime=False)[0]
+        assert np.array_equal(a.uinf, mix[r.rid].uinf), r.rid
