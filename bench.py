@@ -3,7 +3,10 @@
 Workload (default): the unit sphere as six rational-quadratic patches, level
 m = 5 (6144 elements), degree-2 B-splines (N = 6936), kappa = 8, sound-soft
 CFIE, interpolation degree q = 6, admissibility eta = 1.6, leaf depth 2, fp64,
-one incident plane wave d = (0,0,1), GMRES(30) to 1e-8.
+one incident plane wave d = (0,0,1), GMRES(30) to 1e-8.  The fp64 coupling
+tiles are recompressed (pivoted QR, each tile to 1e-8 relative in Frobenius
+norm) and the one-column products stream the factors; the error against the
+oracle rows is that of the tiles, and the tiles themselves are timed beside it.
 
 One timed step = one CFIE solve on the assembled operator (right-hand side,
 restarted GMRES with one H^2 matvec plus CGS2 Arnoldi per iteration, final
@@ -15,8 +18,9 @@ Beside the headline line's value: the served forms (16 directions in lockstep
 with fp64, fp32 or bf16 couplings; the reduced precisions run on the matrix
 cores inside fp64 iterative refinement), each block matvec's kernel times and
 roofline, a continuous-batching request stream with p50/p99 latency, the same
-solves with one H^2 matrix per operator (`paper_mode`) and with recompressed
-coupling tiles (`recompressed`), and the scattered field at points off the
+solves with one H^2 matrix per operator (`paper_mode`) and streaming the
+uncompressed tiles or factors truncated at 1e-7 (`recompressed`), and the
+scattered field at points off the
 boundary by direct summation and by the H^2 evaluation (`potential`).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
@@ -51,11 +55,12 @@ HBM_PEAK_GBS = 8000.0
 # make a plain 1 GiB device copy read and write 1 GiB), taken for the kernels
 # as they stand: profiles/m2l_sphere_m5_p2_k8_hbm_counters.md.  To be reset
 # to None whenever one of these kernels changes.
-MEASURED_TRAFFIC = {"m2l_chunks_wave": 2.147e9, "fp64": None, "fp32": 1.281e9, "bf16": 0.644e9}
+MEASURED_TRAFFIC = {"m2l_chunks_wave": 2.147e9, "m2l_chunks_lowrank": None, "fp64": None, "fp32": 1.281e9,
+                    "bf16": 0.644e9}
 
 WORKLOADS = {
     "sphere_m5_p2_k8": dict(geometry="sphere", m=5, p=2, kappa=8.0, q=6, eta_adm=1.6, leaf_depth=2,
-                            kcap=0.0, tol=1e-8, golden="sphere_m5_p2_k8_rows"),
+                            kcap=0.0, tol=1e-8, golden="sphere_m5_p2_k8_rows", recompress_tol=1e-8),
     # the star configurations: one operator solving a block of directions
     "star_m6_p2_k16": dict(geometry="star", m=6, p=2, kappa=16.0, q=8, eta_adm=1.6, leaf_depth=3, kcap=5.0,
                            tol=1e-8, bc="soft", ndir=64, precision="fp64", on_the_fly=False, dir_seed=1,
@@ -345,7 +350,7 @@ def serve_study(capacity=None, n_capacity=48, n_sweep=48, fractions=(0.4, 0.6, 0
     `mean_in_service` = summed admitted-to-done time / wall time (requests
     being served at once)."""
     from paper_2306_11324_amd import inputs as I
-    from paper_2306_11324_amd.serving import ServeConfig, Server
+    from paper_2306_11324_amd.serving import ServeConfig, Server, percentile
     cfg = ServeConfig(slots=4)
     srv = Server(cfg)
 
@@ -358,6 +363,9 @@ def serve_study(capacity=None, n_capacity=48, n_sweep=48, fractions=(0.4, 0.6, 0
         res = srv.run(reqs, realtime=realtime, log=log)
         out = Server.summary(res, srv.wall)
         out["mean_in_service"] = sum(r.done - r.admitted for r in res) / srv.wall
+        if not realtime:   # every request visible at time 0: latency = completion time
+            lat = [r.done for r in res]
+            out["p50_latency_s"], out["p99_latency_s"] = percentile(lat, 50), percentile(lat, 99)
         out.update({"stream": label, "arrival_rate_per_s": rate if realtime else None, "slots": cfg.slots})
         print(json.dumps(out), flush=True)
         return out
@@ -495,7 +503,7 @@ def main():
     t0 = time.perf_counter()
     geo = B.Geometry(ctx, pts, w["m"], w["p"])
     op = B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"], kcap=w["kcap"],
-                    leaf_depth=w["leaf_depth"])
+                    leaf_depth=w["leaf_depth"], recompress_tol=w["recompress_tol"])
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     info = op.info
@@ -564,6 +572,14 @@ def main():
                 "m2l_frac_hbm_peak": byts / avg / (HBM_PEAK_GBS * 1e9),
                 "m2l_frac_matrix_peak": flops / avg / mfma_peak[prec_name]}
 
+    g_rows = np.load(os.path.join(ROOT, "tests", "golden", w["golden"] + ".npz"))
+
+    def oracle_row_error(y):
+        yr = y[g_rows["rows"]]
+        return {"operator_relative": float(np.max(np.abs(yr - g_rows["y"]) /
+                                                  (g_rows["rownorm1"] * np.abs(g_rows["x"]).max()))),
+                "vector_relative": float(np.max(np.abs(yr - g_rows["y"])) / np.max(np.abs(g_rows["y"])))}
+
     plain = run_solves(op, d, args.steps, args.warmup)
     value = plain["matvecs_per_s"]
     # scattered field of the plain solution at points on the radius-2 sphere
@@ -626,16 +642,24 @@ def main():
                                         "assembly_ms": c.assembly_ms, "device_bytes": c.device_bytes}
                                        for c in cand]}
     torch.cuda.empty_cache()
-    # the same solves with the coupling tiles recompressed (cross approximation, 1e-8 relative)
-    op_lr = B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"], kcap=w["kcap"],
-                       leaf_depth=w["leaf_depth"], recompress_tol=1e-8)
-    lr = run_solves(op_lr, d, args.steps, args.warmup)
-    recompressed = {
-        "tol": 1e-8, "matvecs_per_s": lr["matvecs_per_s"], "solves_per_s": lr["solves_per_s"],
-        "speedup_vs_tiles": lr["matvecs_per_s"] / value, "device_bytes": op_lr.info.device_bytes,
-        "far_field_rel_diff_vs_tiles": float((lr["uinf"] - plain["uinf"]).abs().max() / plain["uinf"].abs().max()),
-        "note": "one-column products stream rank-one factors of every tile instead of the tile"}
-    del op_lr, lr
+    # the same solves streaming the coupling tiles themselves (no recompression),
+    # and with the factors truncated at 1e-7
+    recompressed = {}
+    for label, rt in (("tiles", 0.0), ("tol_1e-7", 1e-7)):
+        op_t = B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"], kcap=w["kcap"],
+                          leaf_depth=w["leaf_depth"], recompress_tol=rt)
+        rs = run_solves(op_t, d, args.steps, args.warmup)
+        xt = torch.from_numpy(g_rows["x"]).to(dev)
+        yt = torch.zeros_like(xt)
+        op_t.h2_matvec(xt, yt)
+        torch.cuda.synchronize()
+        recompressed[label] = {
+            "far_recompress_tol": rt, "matvecs_per_s": rs["matvecs_per_s"], "solves_per_s": rs["solves_per_s"],
+            "headline_speedup": value / rs["matvecs_per_s"], "device_bytes": op_t.info.device_bytes,
+            "err_matvec_vs_oracle_rows": oracle_row_error(yt.cpu().numpy()),
+            "far_field_rel_diff_vs_headline": float((rs["uinf"] - plain["uinf"]).abs().max()
+                                                    / plain["uinf"].abs().max())}
+        del op_t, rs, xt, yt
     torch.cuda.empty_cache()
     T = plain["T"]
     iters = [plain["gmres_iters"]]
@@ -711,21 +735,21 @@ def main():
         del src, dst
 
     nq = info.nq
-    m2l_bytes = info.far_pairs * nq * nq * 16 + info.far_pairs * nq * 16
+    # algorithmic bytes of the single-column coupling: the tile factors (or the
+    # tiles), the source moments of every pair and the chunk partials
+    nchunk_est = info.far_pairs / 8.0
+    tile_or_factor = info.far_factor_entries * 16 if info.far_factor_entries else info.far_pairs * nq * nq * 16
+    m2l_bytes = tile_or_factor + info.far_pairs * nq * 16 + nchunk_est * nq * 16
     m2l_avg = m2l_ms / max(m2l_n, 1) / 1e3
     achieved = m2l_bytes / m2l_avg / 1e9 if m2l_n else None
 
     # error against the stored fp64 oracle rows / Mie
-    err_oracle = None
-    gp = os.path.join(ROOT, "tests", "golden", w["golden"] + ".npz")
-    if os.path.exists(gp):
-        g = np.load(gp)
-        xg = torch.from_numpy(g["x"]).to(dev)
-        yg = torch.zeros_like(xg)
-        op.h2_matvec(xg, yg)
-        torch.cuda.synchronize()
-        yr = yg.cpu().numpy()[g["rows"]]
-        err_oracle = float(np.max(np.abs(yr - g["y"]) / (g["rownorm1"] * np.abs(g["x"]).max())))
+    xg = torch.from_numpy(g_rows["x"]).to(dev)
+    yg = torch.zeros_like(xg)
+    op.h2_matvec(xg, yg)
+    torch.cuda.synchronize()
+    err_rows = oracle_row_error(yg.cpu().numpy())
+    err_oracle = err_rows["operator_relative"]
     err_mie = None
     if w["geometry"] == "sphere":
         from scipy.special import eval_legendre, spherical_jn, spherical_yn
@@ -755,6 +779,7 @@ def main():
         "config": {"workload": args.workload, "geometry": "unit sphere, 6 rational-quadratic patches",
                    "level_m": w["m"], "degree_p": w["p"], "N": n, "kappa": w["kappa"], "bc": "soft",
                    "q": w["q"], "eta_adm": w["eta_adm"], "kcap": w["kcap"], "leaf_depth": w["leaf_depth"],
+                   "far_recompress_tol": w["recompress_tol"],
                    "rhs": 1, "gmres": f"restart 30, tol {w['tol']}", "far_pairs": info.far_pairs,
                    "nnz_near": info.nnz},
         "solves_per_s": plain["solves_per_s"],
@@ -775,12 +800,16 @@ def main():
         "served": served,
         "block_matvec": block_mv,
         "err_matvec_vs_oracle_rows": err_oracle,
+        "err_matvec_vs_oracle_rows_measures": err_rows,
+        "far_factor_avg_rank": info.far_factor_entries / (2.0 * nq * info.far_pairs) if info.far_factor_entries
+                               else None,
         "err_farfield_vs_mie": err_mie,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": MEASURED_TRAFFIC["m2l_chunks_wave"] if args.workload == "sphere_m5_p2_k8" else None,
-                     "kernel": "m2l_chunks_wave", "bytes_per_launch": m2l_bytes,
-                     "avg_launch_ms": m2l_avg * 1e3},
+                     "traffic": MEASURED_TRAFFIC.get("m2l_chunks_lowrank") if info.far_factor_entries
+                                else MEASURED_TRAFFIC["m2l_chunks_wave"],
+                     "kernel": "m2l_chunks_lowrank" if info.far_factor_entries else "m2l_chunks_wave",
+                     "bytes_per_launch": m2l_bytes, "avg_launch_ms": m2l_avg * 1e3},
     }
     if args.serve > 0:
         out["serving"] = serve_stream(args.serve, args.serve_rate)

@@ -144,12 +144,14 @@ typedef enum {
  *              igb_op_far_blocks, igb_op_near_pairs, igb_op_profile and
  *              igb_op_kernel_time return IGB_ERR_ARG on such an operator.
  *   far_recompress_tol  0: off.  > 0 (at most 1e-2; sound-soft family, stored fp64
- *              couplings, q <= 7): each coupling tile K is also factored as a sum of
- *              rank-one terms u v^T by cross approximation with complete pivoting,
- *              stopped when no entry of K - sum u v^T exceeds tol * max|K|; the
- *              one-column fp64 products (h2_matvec with nrhs = 1, single-direction
- *              solves and residuals) then stream the factors instead of the tiles.
- *              Products of several columns keep using the tiles. */
+ *              couplings, q <= 7): each coupling tile K is also factored by
+ *              Householder QR with column pivoting, K P = Q R, truncated at the
+ *              first rank k with ||R(k:, k:)||_F <= tol ||K||_F, so K ~ U W with
+ *              U = Q(:, 0:k), W = R(0:k, :) P^T and ||K - U W||_F <= tol ||K||_F;
+ *              the one-column fp64 products (h2_matvec with nrhs = 1,
+ *              single-direction solves and residuals) then stream the factors
+ *              (2 nq k complex per pair instead of nq^2).  Products of several
+ *              columns keep using the tiles. */
 typedef struct {
     double kappa;
     int bc;
@@ -210,6 +212,8 @@ typedef struct {
                                assemble_nearfield checks the budget against this
                                plus its own transient staging buffers              */
     double assembly_near_ms, assembly_far_ms;
+    int64_t far_factor_entries; /* far_recompress_tol > 0: complex entries of all tile
+                                   factors (2 nq rank per far pair); else 0          */
 } igb_op_info;
 
 /* ---------------------------------------------------------------- context */

@@ -497,6 +497,7 @@ igb_status igb_op_get_info(igb_op op, igb_op_info* info) {
     info->estimated_bytes = int64_t(op->estimated_bytes);
     info->assembly_near_ms = op->t_assembly_near;
     info->assembly_far_ms = op->t_assembly_far;
+    info->far_factor_entries = op->lr_entries;
     return IGB_OK;
 }
 

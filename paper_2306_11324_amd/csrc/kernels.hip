@@ -1697,118 +1697,263 @@ __global__ __launch_bounds__(64) void m2l_chunks_wave(const double2* __restrict_
     if (a < nq) part[ch * nq + a] = acc;
 }
 
-// Recompression of one fp64 coupling tile, K(a, b) stored at [b*nq + a] (a target,
-// b source), by cross approximation with complete pivoting: the residual's
-// largest entry R(a*, b*) gives the term u v^T with u(a) = R(a, b*) / R(a*, b*)
-// and v(b) = R(a*, b); stop when no residual entry exceeds tol * max|K|.  Pass 1
-// (fac == nullptr) writes the number of terms; pass 2 repeats the same steps and
-// writes u_k at fac[off + k*nq + a] and v_k transposed at fac[off + K*nq + b*K + k].
+// Recompression of one fp64 coupling tile K (nq x nq, K(a, b) stored at
+// [b*nq + a]: a target node, b source node) by Householder QR with column
+// pivoting (the trailing column of largest norm first): K P = Q R.  The
+// factorisation stops at the first k with ||R(k:, k:)||_F <= tol ||K||_F, so
+// that K ~ U W with U = Q(:, 0:k) and W = R(0:k, :) P^T and
+// ||K - U W||_F <= tol ||K||_F.  Reflectors H = I - tau v v^H with v(k) = 1
+// (stored below the diagonal), R(k, k) real.  Pass 1 (fac == nullptr) writes
+// k; pass 2 repeats the same steps and writes u_k(a) at fac[off + k*nq + a] and
+// w_k(b) at fac[off + K*nq + b*K + k].  One workgroup per tile at a time, the
+// tile in LDS (nq <= 64).
 __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
     const double d = b.x * b.x + b.y * b.y;
     return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
+__device__ __forceinline__ double2 cconj_mul(double2 a, double2 b) {   // conj(a) b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
 
-__global__ __launch_bounds__(256) void tile_aca(const double2* __restrict__ coup, int64_t npairs, int nq, double tol,
-                                                int* __restrict__ rank, const int64_t* __restrict__ off,
-                                                double2* __restrict__ fac) {
-    __shared__ double2 R[64 * 64];
-    __shared__ double2 cu[64], cv[64];
-    __shared__ double rv[256];
-    __shared__ int ri[256];
+__global__ __launch_bounds__(256) void tile_rrqr(const double2* __restrict__ coup, int64_t npairs, int nq, double tol,
+                                                 int* __restrict__ rank, const int64_t* __restrict__ off,
+                                                 double2* __restrict__ fac) {
+    __shared__ double2 A[64 * 64];   // column c at A[c*nq + i]
+    __shared__ double cn[64];        // squared norms of the trailing columns, rows k..
+    __shared__ double2 tau[64];
+    __shared__ int perm[64];
+    __shared__ double red[256];
+    __shared__ double sh_trail;
+    __shared__ int sh_piv;
     const int tid = threadIdx.x, n2 = nq * nq;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int qc = tid >> 2, qr = tid & 3;   // column (offset) and row quarter of this thread in the updates
     for (int64_t p = blockIdx.x; p < npairs; p += gridDim.x) {
         __syncthreads();
-        for (int i = tid; i < n2; i += 256) R[i] = coup[p * n2 + i];
-        const int kmax = fac ? rank[p] : nq;
-        const int64_t o = fac ? off[p] : 0;
-        double amax2 = -1;
-        for (int k = 0;; ++k) {
-            // largest |R|^2, lowest index on ties
-            double best = -1;
-            int bi = 0;
-            __syncthreads();
-            for (int i = tid; i < n2; i += 256) {
-                const double m = R[i].x * R[i].x + R[i].y * R[i].y;
-                if (m > best) {
-                    best = m;
-                    bi = i;
-                }
-            }
-            rv[tid] = best;
-            ri[tid] = bi;
-            __syncthreads();
-            for (int st = 128; st > 0; st >>= 1) {
-                if (tid < st && (rv[tid + st] > rv[tid] || (rv[tid + st] == rv[tid] && ri[tid + st] < ri[tid]))) {
-                    rv[tid] = rv[tid + st];
-                    ri[tid] = ri[tid + st];
-                }
-                __syncthreads();
-            }
-            const double m2 = rv[0];
-            const int piv = ri[0];
-            if (k == 0) amax2 = m2;
-            if (!(m2 > tol * tol * amax2) || k >= kmax) {
-                if (!fac && tid == 0) rank[p] = k;
-                break;
-            }
-            const int bs = piv / nq, as = piv % nq;
-            const double2 pv = R[piv];
-            for (int i = tid; i < nq; i += 256) {
-                cu[i] = cdiv(R[bs * nq + i], pv);
-                cv[i] = R[i * nq + as];
-            }
-            __syncthreads();
-            for (int i = tid; i < n2; i += 256) {
-                const double2 t = cmul(cu[i % nq], cv[i / nq]);
-                R[i] = make_double2(R[i].x - t.x, R[i].y - t.y);
-            }
-            if (fac)
-                for (int i = tid; i < nq; i += 256) {
-                    fac[o + int64_t(k) * nq + i] = cu[i];
-                    fac[o + int64_t(kmax) * nq + int64_t(i) * kmax + k] = cv[i];
-                }
+        double s = 0;
+        for (int i = tid; i < n2; i += 256) {
+            const double2 v = coup[p * n2 + i];
+            A[i] = v;
+            s += v.x * v.x + v.y * v.y;
         }
+        if (tid < nq) perm[tid] = tid;
+        red[tid] = s;
+        __syncthreads();
+        for (int st = 128; st > 0; st >>= 1) {
+            if (tid < st) red[tid] += red[tid + st];
+            __syncthreads();
+        }
+        const double total = red[0];
+        const int kmax = fac ? rank[p] : nq;
+        int k = 0;
+        for (; k < nq; ++k) {
+            // squared norms of the trailing columns over rows k..nq-1
+            if (tid < nq) {
+                double c2 = 0;
+                if (tid >= k)
+                    for (int i = k; i < nq; ++i) {
+                        const double2 v = A[tid * nq + i];
+                        c2 += v.x * v.x + v.y * v.y;
+                    }
+                cn[tid] = c2;
+            }
+            __syncthreads();
+            if (wave == 0) {
+                double sum = lane < nq && lane >= k ? cn[lane] : 0.0;
+                double mx = lane < nq && lane >= k ? cn[lane] : -1.0;
+                int mi = lane;
+                for (int o = 32; o >= 1; o >>= 1) {
+                    sum += __shfl_xor(sum, o, 64);
+                    const double om = __shfl_xor(mx, o, 64);
+                    const int oi = __shfl_xor(mi, o, 64);
+                    if (om > mx || (om == mx && oi < mi)) {
+                        mx = om;
+                        mi = oi;
+                    }
+                }
+                if (lane == 0) {
+                    sh_trail = sum;
+                    sh_piv = mi;
+                }
+            }
+            __syncthreads();
+            if (k >= kmax || !(sh_trail > tol * tol * total)) break;
+            const int pv = sh_piv;
+            if (pv != k) {
+                for (int i = tid; i < nq; i += 256) {
+                    const double2 t = A[k * nq + i];
+                    A[k * nq + i] = A[pv * nq + i];
+                    A[pv * nq + i] = t;
+                }
+                if (tid == 0) {
+                    const int t = perm[k];
+                    perm[k] = perm[pv];
+                    perm[pv] = t;
+                }
+            }
+            __syncthreads();
+            // reflector of column k, rows k..nq-1
+            if (wave == 0) {
+                const double2 x = lane > k && lane < nq ? A[k * nq + lane] : make_double2(0, 0);
+                double xn2 = x.x * x.x + x.y * x.y;
+                for (int o = 32; o >= 1; o >>= 1) xn2 += __shfl_xor(xn2, o, 64);
+                const double2 al = A[k * nq + k];
+                double2 t = make_double2(0, 0);
+                if (xn2 > 0 || al.y != 0) {
+                    const double beta = -copysign(sqrt(al.x * al.x + al.y * al.y + xn2), al.x);
+                    t = make_double2((beta - al.x) / beta, -al.y / beta);
+                    const double2 sc = cdiv(make_double2(1.0, 0.0), make_double2(al.x - beta, al.y));
+                    if (lane > k && lane < nq) A[k * nq + lane] = cmul(x, sc);
+                    if (lane == 0) A[k * nq + k] = make_double2(beta, 0.0);
+                }
+                if (lane == 0) tau[k] = t;
+            }
+            __syncthreads();
+            // A(k:, c) -= conj(tau) v (v^H A(k:, c)) for the columns c > k
+            const double2 tk = tau[k];
+            const int c = k + 1 + qc;
+            double2 dot = make_double2(0, 0);
+            if (c < nq)
+                for (int i = k + qr; i < nq; i += 4) {
+                    const double2 v = i == k ? make_double2(1.0, 0.0) : A[k * nq + i];
+                    dot = cadd(dot, cconj_mul(v, A[c * nq + i]));
+                }
+            dot.x += __shfl_xor(dot.x, 1, 64);
+            dot.y += __shfl_xor(dot.y, 1, 64);
+            dot.x += __shfl_xor(dot.x, 2, 64);
+            dot.y += __shfl_xor(dot.y, 2, 64);
+            const double2 wv = cmul(make_double2(tk.x, -tk.y), dot);
+            if (c < nq)
+                for (int i = k + qr; i < nq; i += 4) {
+                    const double2 v = i == k ? make_double2(1.0, 0.0) : A[k * nq + i];
+                    const double2 d = cmul(v, wv);
+                    A[c * nq + i] = make_double2(A[c * nq + i].x - d.x, A[c * nq + i].y - d.y);
+                }
+            __syncthreads();
+        }
+        const int K = k;
+        if (!fac) {
+            if (tid == 0) rank[p] = K;
+            continue;
+        }
+        const int64_t o = off[p];
+        // W = R(0:K, :) P^T
+        for (int e = tid; e < nq * K; e += 256) {
+            const int j = e / K, kk = e % K;
+            fac[o + int64_t(K) * nq + int64_t(perm[j]) * K + kk] = kk <= j ? A[j * nq + kk] : make_double2(0, 0);
+        }
+        __syncthreads();
+        // Q(:, 0:K) in place, from the last reflector to the first: columns i+1..K-1
+        // already hold Q's columns when H_i is applied to them
+        for (int i = K - 1; i >= 0; --i) {
+            const double2 ti = tau[i];
+            const int c = i + 1 + qc;
+            double2 dot = make_double2(0, 0);
+            if (c < K)
+                for (int r = i + qr; r < nq; r += 4) {
+                    const double2 v = r == i ? make_double2(1.0, 0.0) : A[i * nq + r];
+                    dot = cadd(dot, cconj_mul(v, A[c * nq + r]));
+                }
+            dot.x += __shfl_xor(dot.x, 1, 64);
+            dot.y += __shfl_xor(dot.y, 1, 64);
+            dot.x += __shfl_xor(dot.x, 2, 64);
+            dot.y += __shfl_xor(dot.y, 2, 64);
+            const double2 wv = cmul(ti, dot);
+            if (c < K)
+                for (int r = i + qr; r < nq; r += 4) {
+                    const double2 v = r == i ? make_double2(1.0, 0.0) : A[i * nq + r];
+                    const double2 d = cmul(v, wv);
+                    A[c * nq + r] = make_double2(A[c * nq + r].x - d.x, A[c * nq + r].y - d.y);
+                }
+            __syncthreads();
+            // column i of Q: (1 - tau) at row i, -tau v below, zero above
+            for (int r = tid; r < nq; r += 256) {
+                const double2 v = A[i * nq + r];
+                A[i * nq + r] = r < i ? make_double2(0, 0)
+                                      : r == i ? make_double2(1.0 - ti.x, -ti.y)
+                                               : make_double2(-(ti.x * v.x - ti.y * v.y), -(ti.x * v.y + ti.y * v.x));
+            }
+            __syncthreads();
+        }
+        for (int e = tid; e < nq * K; e += 256) fac[o + e] = A[e];
     }
 }
 
-// coupling, sound-soft, one column, from the recompressed tiles: per pair
-// t_k = sum_b v_k(b) x(b) (lane k, v^T rows read contiguously) and
-// y(a) += sum_k u_k(a) t_k (lane a), the moments and t reaching the lanes by
-// readlane; one wave per chunk as in m2l_chunks_wave.
-__global__ __launch_bounds__(64) void m2l_chunks_lowrank(const double2* __restrict__ fac,
-                                                         const int* __restrict__ rank,
-                                                         const int64_t* __restrict__ off,
-                                                         const double2* __restrict__ xh,
-                                                         const int* __restrict__ far_src_g,
-                                                         const int64_t* __restrict__ chunk_pair,
-                                                         const int* __restrict__ chunk_len, int64_t nchunk, int nq,
-                                                         double2* __restrict__ part) {
+constexpr int LR_WAVES = 2;
+// coupling, sound-soft, one column, from the recompressed tiles: one
+// workgroup of NW waves per chunk (up to 8 pairs of one target), wave w taking
+// the pairs w, w + NW, ...  Each wave first forms t_k = sum_b w_k(b) x(b) for
+// its pairs at once (lane k; for each source node b one load per pair, so the
+// pairs' loads are independent and in flight together; the moments broadcast
+// by readlane), then y(a) += sum_k sum_i u_k(a) t_k over its pairs for k = 0,
+// 1, ... (lane a); the waves' sums meet in LDS in wave order.  Pairs past the
+// chunk or of rank 0 read a valid factor entry and multiply it by zero, so the
+// loops carry no branches.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void m2l_chunks_lowrank(const double2* __restrict__ fac,
+                                                              const int* __restrict__ rank,
+                                                              const int64_t* __restrict__ off,
+                                                              const double2* __restrict__ xh,
+                                                              const int* __restrict__ far_src_g,
+                                                              const int64_t* __restrict__ chunk_pair,
+                                                              const int* __restrict__ chunk_len, int64_t nchunk,
+                                                              int nq, double2* __restrict__ part) {
+    constexpr int PW = (M2L_CHUNK + NW - 1) / NW;   // pairs per wave
+    __shared__ double2 red[NW > 1 ? NW - 1 : 1][64];
     const int64_t ch = blockIdx.x;
     if (ch >= nchunk) return;
-    const int a = threadIdx.x;
+    const int a = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ac = a < nq ? a : nq - 1;
     const int64_t p0 = chunk_pair[ch];
     const int len = chunk_len[ch];
+    const int rk = a < len ? rank[p0 + a] : 0;
+    const int64_t of = a < len ? off[p0 + a] : 0;
+    const int sr = a < len ? far_src_g[p0 + a] : 0;
+    int K[PW], kmax = 0;
+    const double2* U[PW];
+    const double2* WT[PW];
+    double2 xv[PW], t[PW];
+    int kc[PW], Ks[PW];
+#pragma unroll
+    for (int j = 0; j < PW; ++j) {
+        const int i = wave + NW * j;   // pair of the chunk (>= len: none)
+        const int Ki = i < M2L_CHUNK ? __builtin_amdgcn_readlane(rk, i) : 0;
+        const int64_t o = i < M2L_CHUNK ? (int64_t(__builtin_amdgcn_readlane(int(of >> 32), i)) << 32) |
+                                              unsigned(__builtin_amdgcn_readlane(int(of & 0xffffffff), i))
+                                        : 0;
+        const bool live = Ki > 0;
+        K[j] = live ? Ki : 0;
+        Ks[j] = live ? Ki : 1;
+        kmax = max(kmax, K[j]);
+        U[j] = live ? fac + o : fac;
+        WT[j] = live ? fac + o + int64_t(Ki) * nq : fac;
+        kc[j] = live ? min(a, Ki - 1) : 0;   // idle lanes repeat the last term (never read)
+        xv[j] = live ? xh[int64_t(__builtin_amdgcn_readlane(sr, i)) * nq + ac] : make_double2(0, 0);
+        t[j] = make_double2(0, 0);
+    }
+    for (int b = 0; b < nq; ++b) {
+#pragma unroll
+        for (int j = 0; j < PW; ++j) {
+            const double2 xb = make_double2(readlane_d(xv[j].x, b), readlane_d(xv[j].y, b));
+            t[j] = cfma(WT[j][int64_t(b) * Ks[j] + kc[j]], xb, t[j]);
+        }
+    }
     double2 acc = make_double2(0, 0);
-    double2 xn = xh[int64_t(far_src_g[p0]) * nq + ac];
-    for (int i = 0; i < len; ++i) {
-        const double2 xv = xn;
-        if (i + 1 < len) xn = xh[int64_t(far_src_g[p0 + i + 1]) * nq + ac];
-        const int64_t pr = p0 + i;
-        const int K = rank[pr];
-        if (K == 0) continue;
-        const double2* U = fac + off[pr];
-        const double2* VT = U + int64_t(K) * nq;
-        const int kc = a < K ? a : K - 1;   // idle lanes repeat the last term (never read)
-        double2 t = make_double2(0, 0);
-        for (int b = 0; b < nq; ++b) {
-            const double2 xb = make_double2(readlane_d(xv.x, b), readlane_d(xv.y, b));
-            t = cfma(VT[int64_t(b) * K + kc], xb, t);
+    for (int k = 0; k < kmax; ++k) {
+#pragma unroll
+        for (int j = 0; j < PW; ++j) {
+            const bool use = k < K[j];
+            const double tr = readlane_d(t[j].x, k), ti = readlane_d(t[j].y, k);
+            const double2 tk = use ? make_double2(tr, ti) : make_double2(0, 0);
+            acc = cfma(U[j][int64_t(use ? k : 0) * nq + ac], tk, acc);
         }
-        for (int k = 0; k < K; ++k) {
-            const double2 tk = make_double2(readlane_d(t.x, k), readlane_d(t.y, k));
-            acc = cfma(U[int64_t(k) * nq + ac], tk, acc);
-        }
+    }
+    if (NW > 1) {
+        if (wave > 0) red[wave - 1][a] = acc;
+        __syncthreads();
+        if (wave > 0) return;
+#pragma unroll
+        for (int w = 0; w < NW - 1; ++w) acc = cadd(acc, red[w][a]);
     }
     if (a < nq) part[ch * nq + a] = acc;
 }
@@ -3095,7 +3240,7 @@ igb_status assemble_far_device(igb_op op, hipStream_t s) {
         // factors of every tile: count the terms, lay them out, then write them
         if ((st = alloc(op->d_lr_rank, size_t(op->nfar) * sizeof(int), acct))) return st;
         const dim3 grid(unsigned(std::min<int64_t>(op->nfar, 1 << 16)));
-        hipLaunchKernelGGL(tile_aca, grid, dim3(256), 0, s, op->d_coupling.as<double2>(), op->nfar, nq,
+        hipLaunchKernelGGL(tile_rrqr, grid, dim3(256), 0, s, op->d_coupling.as<double2>(), op->nfar, nq,
                            op->prm.far_recompress_tol, op->d_lr_rank.as<int>(), nullptr, nullptr);
         IGB_HIP(hipGetLastError());
         std::vector<int> rk(op->nfar);
@@ -3109,8 +3254,9 @@ igb_status assemble_far_device(igb_op op, hipStream_t s) {
         }
         op->lr_entries = tot;
         if ((st = upload(op->d_lr_off, off.data(), off.size(), acct))) return st;
-        if ((st = alloc(op->d_lr, size_t(std::max<int64_t>(tot, 1)) * sizeof(double2), acct))) return st;
-        hipLaunchKernelGGL(tile_aca, grid, dim3(256), 0, s, op->d_coupling.as<double2>(), op->nfar, nq,
+        // at least 64 entries: the product kernel's idle pairs read the first nq
+        if ((st = alloc(op->d_lr, size_t(std::max<int64_t>(tot, 64)) * sizeof(double2), acct))) return st;
+        hipLaunchKernelGGL(tile_rrqr, grid, dim3(256), 0, s, op->d_coupling.as<double2>(), op->nfar, nq,
                            op->prm.far_recompress_tol, op->d_lr_rank.as<int>(), op->d_lr_off.as<int64_t>(),
                            op->d_lr.as<double2>());
         IGB_HIP(hipGetLastError());
@@ -3266,7 +3412,8 @@ static void launch_m2l_fp64(igb_op op, const MatvecWork& W, double2* xh, int64_t
                            dim3(NT), 0, s, coup, xh, ks, op->d_nodes.as<double>(), op->d_far_src.as<int>(),
                            C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol, W.part);
     } else if (ncol == 1 && op->d_lr.ptr) {
-        hipLaunchKernelGGL(m2l_chunks_lowrank, dim3(unsigned(nchunk)), dim3(64), 0, s, op->d_lr.as<double2>(),
+        hipLaunchKernelGGL(m2l_chunks_lowrank<LR_WAVES>, dim3(unsigned(nchunk)), dim3(64 * LR_WAVES), 0, s,
+                           op->d_lr.as<double2>(),
                            op->d_lr_rank.as<int>(), op->d_lr_off.as<int64_t>(), xh, op->d_far_src.as<int>(),
                            C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, W.part);
     } else if (ncol == 1 && op->nq <= 64) {
