@@ -53,10 +53,11 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the coupling kernels on the sphere_m5_p2_k8 workload,
 # from two rocprofv3 passes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0; the factors
 # make a plain 1 GiB device copy read and write 1 GiB), taken for the kernels
-# as they stand: profiles/m2l_sphere_m5_p2_k8_hbm_counters.md.  To be reset
-# to None whenever one of these kernels changes.
-MEASURED_TRAFFIC = {"m2l_chunks_wave": 2.147e9, "m2l_chunks_lowrank": None, "fp64": None, "fp32": 1.281e9,
-                    "bf16": 0.644e9}
+# as they stand: profiles/m2l_sphere_m5_p2_k8_hbm_counters.md and
+# profiles/matvec_kernels_sphere_m5_p2_k8_counters.md.  To be reset to None
+# whenever one of these kernels changes.
+MEASURED_TRAFFIC = {"m2l_chunks_wave": 2.147e9, "m2l_chunks_lowrank": 1.170e9, "fp64": 2.782e9,
+                    "fp64_64col": 5.076e9, "fp32": 1.281e9, "bf16": 0.6445e9}
 
 WORKLOADS = {
     "sphere_m5_p2_k8": dict(geometry="sphere", m=5, p=2, kappa=8.0, q=6, eta_adm=1.6, leaf_depth=2,
@@ -340,6 +341,76 @@ def serve_stream(nreq, rate):
     return out
 
 
+def kernels_only(reps=20):
+    """The matvecs of the default workload alone, for counter runs (rocprofv3
+    --pmc) and kernel traces: the headline operator's one-column product (tile
+    factors), the fp64 blocks of 16 and 64 columns (matrix-core coupling and
+    near tiles), the bf16 block of 16 columns, then a plain 1 GiB device copy
+    (the counters' calibration)."""
+    import torch
+
+    from paper_2306_11324_amd import binding as B
+    from paper_2306_11324_amd import inputs as I
+    w = WORKLOADS["sphere_m5_p2_k8"]
+    dev = torch.device("cuda:0")
+    torch.cuda.init()
+    ctx = B.Context(0)
+    geo = B.Geometry(ctx, I.sphere_patches(), w["m"], w["p"])
+    kw = dict(kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"], kcap=w["kcap"], leaf_depth=w["leaf_depth"])
+    op = B.Operator(ctx, geo, recompress_tol=w["recompress_tol"], **kw)
+    lo = B.Operator(ctx, geo, precision=B.MIX_BF16, **kw)
+    for o, nc, parts, label in ((op, 1, B.PART_ALL, "fp64 1 column"), (op, 16, B.PART_ALL, "fp64 16 columns"),
+                                (op, 64, B.PART_ALL, "fp64 64 columns"),
+                                (lo, 16, B.PART_ALL | B.MV_LOWPREC, "bf16 16 columns")):
+        X = torch.from_numpy(I.random_complex(5, (nc, o.n))).to(dev)
+        Y = torch.zeros_like(X)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            o.h2_matvec(X, Y, nrhs=nc, parts=parts)
+        torch.cuda.synchronize()
+        print(f"# {label}: {(time.perf_counter() - t0) / reps * 1e3:.3f} ms per matvec", flush=True)
+        del X, Y
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print("# copy calibration: 3 x 1 GiB device copies", flush=True)
+
+
+def counter_summary(dirs, simds=1024):
+    """Markdown table of rocprofv3 --pmc runs of `--kernels-only` (their
+    run_counter_collection.csv files): per kernel and grid, the mean per
+    dispatch of FETCH_SIZE and WRITE_SIZE (bytes, from KiB) and, where
+    collected, the MFMA busy fraction SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE
+    x SIMDs) and the fp64 / bf16 matrix flops (MOPS x 512) per dispatch, with the
+    plain 1 GiB device copy's FETCH_SIZE and WRITE_SIZE as the calibration."""
+    import collections
+    import csv
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for d in dirs:
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            key = (r["Kernel_Name"].split("(")[0], int(r["Grid_Size"]))
+            acc[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    print("| kernel | grid | dispatches | FETCH_SIZE (MB) | WRITE_SIZE (MB) | MFMA busy | fp64 MFMA GFLOP | bf16 MFMA GFLOP |")
+    print("|---|---|---|---|---|---|---|---|")
+    for (name, grid), c in sorted(acc.items(), key=lambda kv: -np.mean(kv[1].get("FETCH_SIZE", [0]))):
+        def mean(k):
+            return float(np.mean(c[k])) if k in c else None
+        fetch, write = mean("FETCH_SIZE"), mean("WRITE_SIZE")
+        busy, act = mean("SQ_VALU_MFMA_BUSY_CYCLES"), mean("GRBM_GUI_ACTIVE")
+        f64, b16 = mean("SQ_INSTS_VALU_MFMA_MOPS_F64"), mean("SQ_INSTS_VALU_MFMA_MOPS_BF16")
+        n = max(len(v) for v in c.values())
+        if (fetch or 0) < 1024 and not f64 and not b16:   # skip kernels below 1 MB of traffic
+            continue
+        cell = lambda v, f: "" if v is None else f.format(v)
+        print(f"| `{name}` | {grid} | {n} | {cell(fetch and fetch * 1024 / 1e6, '{:.1f}')} | "
+              f"{cell(write and write * 1024 / 1e6, '{:.1f}')} | "
+              f"{cell(busy / (act * simds) if busy and act else None, '{:.1%}')} | "
+              f"{cell(f64 and f64 * 512 / 1e9, '{:.2f}')} | {cell(b16 and b16 * 512 / 1e9, '{:.2f}')} |")
+
+
 def serve_study(capacity=None, n_capacity=48, n_sweep=48, fractions=(0.4, 0.6, 0.8, 1.0), n_main=200,
                 main_fraction=0.8):
     """The serving protocol: capacity (every request visible at once: requests
@@ -462,6 +533,10 @@ def main():
                     help="reference solution: the finest CFIE solution or the single-layer one (as the paper)")
     ap.add_argument("--conv-out", default=None, help="also write the study's JSON lines to this file")
     ap.add_argument("--sweep", default=None, help="levels m for the scaling sweep, e.g. 3,4,5,6,7")
+    ap.add_argument("--counter-summary", nargs="+", default=None,
+                    help="summarise rocprofv3 --pmc output directories of --kernels-only (no GPU)")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the default workload's matvecs (and a 1 GiB copy), for counter runs")
     ap.add_argument("--serve-study", action="store_true",
                     help="serving protocol: capacity, rate sweep, --serve-main requests at 0.8 x capacity")
     ap.add_argument("--serve-capacity", type=float, default=None, help="skip the capacity run (requests/s)")
@@ -481,6 +556,12 @@ def main():
         return
     if args.sweep:
         scaling_sweep([int(v) for v in args.sweep.split(",")])
+        return
+    if args.counter_summary:
+        counter_summary(args.counter_summary)
+        return
+    if args.kernels_only:
+        kernels_only()
         return
     if args.serve_study:
         fr = tuple(float(v) for v in args.serve_fractions.split(",")) if args.serve_fractions else ()
@@ -703,7 +784,7 @@ def main():
         x64 = torch.from_numpy(I.random_complex(778, (64, n))).to(dev)
         y64 = torch.zeros_like(x64)
         block_mv["fp64_64col"] = block_matvec(op, "fp64", x64, y64, max(5, args.matvecs // 5))
-        block_mv["fp64_64col"]["m2l_traffic_bytes"] = None
+        block_mv["fp64_64col"]["m2l_traffic_bytes"] = MEASURED_TRAFFIC["fp64_64col"]
         del xb, yb, x64, y64
 
     # matvec-only loop with HIP-event kernel timing on the launch stream
