@@ -1705,7 +1705,7 @@ __global__ __launch_bounds__(64) void m2l_chunks_wave(const double2* __restrict_
 // ||K - U W||_F <= tol ||K||_F.  Reflectors H = I - tau v v^H with v(k) = 1
 // (stored below the diagonal), R(k, k) real.  Pass 1 (fac == nullptr) writes
 // k; pass 2 repeats the same steps and writes u_k(a) at fac[off + k*nq + a] and
-// w_k(b) at fac[off + K*nq + b*K + k].  One workgroup per tile at a time, the
+// w_k(b) at fac[off + K*nq + k*nq + b].  One workgroup per tile at a time, the
 // tile in LDS (nq <= 64).
 __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
     const double d = b.x * b.x + b.y * b.y;
@@ -1840,7 +1840,7 @@ __global__ __launch_bounds__(256) void tile_rrqr(const double2* __restrict__ cou
         // W = R(0:K, :) P^T
         for (int e = tid; e < nq * K; e += 256) {
             const int j = e / K, kk = e % K;
-            fac[o + int64_t(K) * nq + int64_t(perm[j]) * K + kk] = kk <= j ? A[j * nq + kk] : make_double2(0, 0);
+            fac[o + int64_t(K) * nq + int64_t(kk) * nq + perm[j]] = kk <= j ? A[j * nq + kk] : make_double2(0, 0);
         }
         __syncthreads();
         // Q(:, 0:K) in place, from the last reflector to the first: columns i+1..K-1
@@ -1879,16 +1879,20 @@ __global__ __launch_bounds__(256) void tile_rrqr(const double2* __restrict__ cou
     }
 }
 
-constexpr int LR_WAVES = 2;
+constexpr int LR_WAVES = 8;
 // coupling, sound-soft, one column, from the recompressed tiles: one
 // workgroup of NW waves per chunk (up to 8 pairs of one target), wave w taking
-// the pairs w, w + NW, ...  Each wave first forms t_k = sum_b w_k(b) x(b) for
-// its pairs at once (lane k; for each source node b one load per pair, so the
-// pairs' loads are independent and in flight together; the moments broadcast
-// by readlane), then y(a) += sum_k sum_i u_k(a) t_k over its pairs for k = 0,
-// 1, ... (lane a); the waves' sums meet in LDS in wave order.  Pairs past the
-// chunk or of rank 0 read a valid factor entry and multiply it by zero, so the
-// loops carry no branches.
+// the pairs w, w + NW, ...  For each pair and group of 8 terms k: the rows
+// w_k(.) and u_k(.) are read full width (lane = node), lane b forms
+// w_k(b) x(b) with the source moment it holds, the 8 sums over b are reduced
+// together (three halving exchanges leave lane L with term k = 4 L5 + 2 L4 +
+// L3 of the group, L5..L3 its bits 5..3, three more complete the sum), and
+// y(a) += u_k(a) t_k for the group's terms below the rank.  Rows past the rank
+// are read at the last row (their sums are never used); lanes past nq hold a
+// zero moment.  The waves' sums meet in LDS in wave order.
+__device__ __forceinline__ double2 shfl_xor_c(double2 v, int m) {
+    return make_double2(__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64));
+}
 template <int NW>
 __global__ __launch_bounds__(64 * NW) void m2l_chunks_lowrank(const double2* __restrict__ fac,
                                                               const int* __restrict__ rank,
@@ -1909,43 +1913,52 @@ __global__ __launch_bounds__(64 * NW) void m2l_chunks_lowrank(const double2* __r
     const int rk = a < len ? rank[p0 + a] : 0;
     const int64_t of = a < len ? off[p0 + a] : 0;
     const int sr = a < len ? far_src_g[p0 + a] : 0;
-    int K[PW], kmax = 0;
-    const double2* U[PW];
-    const double2* WT[PW];
-    double2 xv[PW], t[PW];
-    int kc[PW], Ks[PW];
+    const bool hi5 = a & 32, hi4 = a & 16, hi3 = a & 8;
+    double2 acc = make_double2(0, 0);
 #pragma unroll
     for (int j = 0; j < PW; ++j) {
-        const int i = wave + NW * j;   // pair of the chunk (>= len: none)
-        const int Ki = i < M2L_CHUNK ? __builtin_amdgcn_readlane(rk, i) : 0;
-        const int64_t o = i < M2L_CHUNK ? (int64_t(__builtin_amdgcn_readlane(int(of >> 32), i)) << 32) |
-                                              unsigned(__builtin_amdgcn_readlane(int(of & 0xffffffff), i))
-                                        : 0;
-        const bool live = Ki > 0;
-        K[j] = live ? Ki : 0;
-        Ks[j] = live ? Ki : 1;
-        kmax = max(kmax, K[j]);
-        U[j] = live ? fac + o : fac;
-        WT[j] = live ? fac + o + int64_t(Ki) * nq : fac;
-        kc[j] = live ? min(a, Ki - 1) : 0;   // idle lanes repeat the last term (never read)
-        xv[j] = live ? xh[int64_t(__builtin_amdgcn_readlane(sr, i)) * nq + ac] : make_double2(0, 0);
-        t[j] = make_double2(0, 0);
-    }
-    for (int b = 0; b < nq; ++b) {
+        const int i = wave + NW * j;   // pair of the chunk
+        const int K = i < M2L_CHUNK ? __builtin_amdgcn_readlane(rk, i) : 0;
+        if (K == 0) continue;   // past the chunk or rank 0 (uniform)
+        const int64_t o = (int64_t(__builtin_amdgcn_readlane(int(of >> 32), i)) << 32) |
+                          unsigned(__builtin_amdgcn_readlane(int(of & 0xffffffff), i));
+        const double2 xv = a < nq ? xh[int64_t(__builtin_amdgcn_readlane(sr, i)) * nq + a] : make_double2(0, 0);
+        const double2* U = fac + o;
+        const double2* Wr = fac + o + int64_t(K) * nq;
+        for (int k0 = 0; k0 < K; k0 += 8) {
+            double2 p[8], u[8];
 #pragma unroll
-        for (int j = 0; j < PW; ++j) {
-            const double2 xb = make_double2(readlane_d(xv[j].x, b), readlane_d(xv[j].y, b));
-            t[j] = cfma(WT[j][int64_t(b) * Ks[j] + kc[j]], xb, t[j]);
-        }
-    }
-    double2 acc = make_double2(0, 0);
-    for (int k = 0; k < kmax; ++k) {
+            for (int r = 0; r < 8; ++r) {
+                const int k = min(k0 + r, K - 1);
+                const double2 wv = Wr[int64_t(k) * nq + ac];
+                u[r] = U[int64_t(k) * nq + ac];
+                p[r] = cmul(wv, xv);
+            }
+            double2 q4[4], q2[2], q1;
 #pragma unroll
-        for (int j = 0; j < PW; ++j) {
-            const bool use = k < K[j];
-            const double tr = readlane_d(t[j].x, k), ti = readlane_d(t[j].y, k);
-            const double2 tk = use ? make_double2(tr, ti) : make_double2(0, 0);
-            acc = cfma(U[j][int64_t(use ? k : 0) * nq + ac], tk, acc);
+            for (int r = 0; r < 4; ++r) {
+                const double2 keep = hi5 ? p[4 + r] : p[r], give = hi5 ? p[r] : p[4 + r];
+                q4[r] = cadd(keep, shfl_xor_c(give, 32));
+            }
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const double2 keep = hi4 ? q4[2 + r] : q4[r], give = hi4 ? q4[r] : q4[2 + r];
+                q2[r] = cadd(keep, shfl_xor_c(give, 16));
+            }
+            {
+                const double2 keep = hi3 ? q2[1] : q2[0], give = hi3 ? q2[0] : q2[1];
+                q1 = cadd(keep, shfl_xor_c(give, 8));
+            }
+            q1 = cadd(q1, shfl_xor_c(q1, 4));
+            q1 = cadd(q1, shfl_xor_c(q1, 2));
+            q1 = cadd(q1, shfl_xor_c(q1, 1));
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                if (k0 + r >= K) break;   // uniform
+                const int src_lane = ((r & 4) ? 32 : 0) + ((r & 2) ? 16 : 0) + ((r & 1) ? 8 : 0);
+                const double2 tk = make_double2(readlane_d(q1.x, src_lane), readlane_d(q1.y, src_lane));
+                acc = cfma(u[r], tk, acc);
+            }
         }
     }
     if (NW > 1) {
