@@ -2092,6 +2092,8 @@ __global__ void m2l_reduce(const PT* part, const int* tgt_chunk_ptr, int64_t ncl
     yh[gid] = s;
 }
 
+constexpr int SPMV_U1 = 4;   // row strides in flight per lane of the one-column near product
+
 // y[r][row] = sum_j val x[r][col] (+ far part mapped to the solution space); one
 // wave per row, lanes stride over the row, butterfly reduction (fixed order).
 // Columns come from the row's group list (rows with the same leaves share one),
@@ -2111,7 +2113,9 @@ __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ 
                                                     const int* __restrict__ s0_reps, int use_near, int ncol,
                                                     double2* __restrict__ y) {
     const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    // consecutive rows on the same XCD: rows of one group read its column
+    // list from that XCD's L2 instead of once per XCD
+    const int64_t row = xcd_chunk(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (row >= nrows) return;
     const int64_t b = row_ptr[row], e = row_ptr[row + 1];
     const int64_t cbase = row_coff[row] - b;   // the row's shared column list, indexed like its values
@@ -2120,7 +2124,26 @@ __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ 
 #pragma unroll
         for (int cb = 0; cb < RB; ++cb) acc[cb] = make_double2(0, 0);
         if (use_near) {
-            for (int64_t idx = b + lane; idx < e; idx += 64) {
+            // one column: U strides of the row per trip, their loads issued
+            // before the first product (more bytes in flight per wave); the
+            // products still enter acc in idx order
+            constexpr int U = RB == 1 ? SPMV_U1 : 1;
+            int64_t idx = b + lane;
+            for (; idx + (U - 1) * 64 < e; idx += U * 64) {
+                double2 v[U];
+                int cc[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    v[u] = val[idx + u * 64];
+                    cc[u] = col[cbase + idx + u * 64];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int cb = 0; cb < RB; ++cb)
+                        if (c0 + cb < ncol) acc[cb] = cfma(v[u], x[int64_t(c0 + cb) * nrows + cc[u]], acc[cb]);
+            }
+            for (; idx < e; idx += 64) {
                 const double2 v = val[idx];
                 const int64_t cc = col[cbase + idx];
 #pragma unroll
