@@ -50,18 +50,21 @@ sys.path.insert(0, ROOT)
 METRIC = "H2 matvecs/s and CFIE solves/s vs plain FP64 at 1e-6 rel err; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of the coupling kernels on the sphere_m5_p2_k8 workload,
-# from two rocprofv3 passes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0; the factors
+# HBM bytes per launch of the matvec kernels on the sphere_m5_p2_k8 workload,
+# keyed by (kernel or block form, leaf depth), from two rocprofv3 passes over
+# `bench.py --kernels-only` (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0; the factors
 # make a plain 1 GiB device copy read and write 1 GiB), taken for the kernels
-# as they stand: profiles/m2l_sphere_m5_p2_k8_hbm_counters.md and
-# profiles/matvec_kernels_sphere_m5_p2_k8_counters.md.  To be reset to None
-# whenever one of these kernels changes.
-MEASURED_TRAFFIC = {"m2l_chunks_wave": 2.147e9, "m2l_chunks_lowrank": 1.170e9, "fp64": 2.782e9,
-                    "fp64_64col": 5.076e9, "fp32": 1.281e9, "bf16": 0.6445e9}
+# as they stand: profiles/matvec_kernels_sphere_m5_p2_k8_counters.md.  An
+# entry is removed whenever its kernel changes.
+MEASURED_TRAFFIC = {}
 
 WORKLOADS = {
-    "sphere_m5_p2_k8": dict(geometry="sphere", m=5, p=2, kappa=8.0, q=6, eta_adm=1.6, leaf_depth=2,
-                            kcap=0.0, tol=1e-8, golden="sphere_m5_p2_k8_rows", recompress_tol=1e-8),
+    # leaf depth and recompression are tuned per run (tune_leaf_depths x {tiles,
+    # recompress_tol}); leaf_depth is the choice measured on MI355X, which the
+    # kernel-only counter runs use
+    "sphere_m5_p2_k8": dict(geometry="sphere", m=5, p=2, kappa=8.0, q=6, eta_adm=1.6, leaf_depth=3,
+                            tune_leaf_depths=(2, 3, 4), kcap=0.0, tol=1e-8, golden="sphere_m5_p2_k8_rows",
+                            recompress_tol=1e-8),
     # the star configurations: one operator solving a block of directions
     "star_m6_p2_k16": dict(geometry="star", m=6, p=2, kappa=16.0, q=8, eta_adm=1.6, leaf_depth=3, kcap=5.0,
                            tol=1e-8, bc="soft", ndir=64, precision="fp64", on_the_fly=False, dir_seed=1,
@@ -581,10 +584,27 @@ def main():
     torch.cuda.init()
     ctx = B.Context(0)
     pts = I.sphere_patches() if w["geometry"] == "sphere" else I.star_patches(0, min(w["m"], 4))
-    t0 = time.perf_counter()
     geo = B.Geometry(ctx, pts, w["m"], w["p"])
+    # the operator's shape for this workload: the autotuner over leaf depth and
+    # tiles / recompressed factors, costed by matvec time (the operator serves
+    # every timed solve), among shapes with admissible blocks; a leaf depth
+    # without any (the dense matrix) is measured and listed beside them
+    from paper_2306_11324_amd import autotune as AT
+    best, cand = AT.tune(ctx, geo, w["m"], w["p"], 1, w["kappa"], q=w["q"], precision=B.FP64, eta_adm=w["eta_adm"],
+                        leaf_depths=w["tune_leaf_depths"], on_the_fly=(False,),
+                        recompress_tols=(0.0, w["recompress_tol"]), matvecs=10 ** 6, reps=20, require_far=True)
+    LD, RT = best.leaf_depth, best.recompress_tol
+    headline_tuning = {"choice": {"leaf_depth": LD, "far_recompress_tol": RT},
+                       "candidates": [{"leaf_depth": c.leaf_depth, "far_recompress_tol": c.recompress_tol,
+                                       "far_pairs": c.far_pairs, "matvec_ms": c.matvec_ms,
+                                       "assembly_ms": c.assembly_ms, "device_bytes": c.device_bytes}
+                                      for c in cand],
+                       "note": "one fp64 column, 20 timed matvecs per candidate; far_pairs = 0 is the dense "
+                               "matrix (no admissible blocks), listed and not chosen"}
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
     op = B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"], kcap=w["kcap"],
-                    leaf_depth=w["leaf_depth"], recompress_tol=w["recompress_tol"])
+                    leaf_depth=LD, recompress_tol=RT)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     info = op.info
@@ -646,7 +666,8 @@ def main():
         byts = float(info.far_pairs * nq2 * elem_bytes[prec_name])
         return {"ncol": nc, "column_matvecs_per_s": nc / tb, "ms_per_block_matvec": tb * 1e3, "kernel_ms": km,
                 "m2l_algorithmic_bytes": byts,
-                "m2l_traffic_bytes": MEASURED_TRAFFIC.get(prec_name) if args.workload == "sphere_m5_p2_k8" else None,
+                "m2l_traffic_bytes": MEASURED_TRAFFIC.get((f"{prec_name} {nc}col", w["m"] - o.info.leaf_level)),
+                "leaf_depth": w["m"] - o.info.leaf_level,
                 "m2l_kernel": "m2l_mfma64_soft (fp64 matrix cores)" if prec_name == "fp64" else
                               f"m2l_mfma_soft ({prec_name} matrix cores)",
                 "m2l_GBps": byts / avg / 1e9, "m2l_TFLOPs": flops / avg / 1e12,
@@ -700,7 +721,7 @@ def main():
     op.use_graphs(False)
     # the same solves with one H^2 matrix per operator summed lazily (Sec. 5.1's set-up)
     op_sep = B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"], kcap=w["kcap"],
-                        leaf_depth=w["leaf_depth"], separate=True)
+                        leaf_depth=LD, separate=True)
     sep = run_solves(op_sep, d, args.steps, args.warmup)
     paper_mode = {
         "matvecs_per_s": sep["matvecs_per_s"], "solves_per_s": sep["solves_per_s"],
@@ -710,32 +731,33 @@ def main():
         "note": "separate H^2 matrices of 1/2 M + K* and V, applied as a lazy sum, against the fused kernel"}
     del op_sep, sep
     torch.cuda.empty_cache()
-    # the autotuner's view of this workload class: leaf depth for one fp64 column and for
-    # 16 bf16 columns (the headline keeps leaf depth 2: at this size deeper leaves turn the
-    # operator into a mostly dense near field)
-    from paper_2306_11324_amd import autotune as T
-    tuned = {}
-    for label, prec, nc in (("fp64_1col", B.FP64, 1), ("bf16_16col", B.MIX_BF16, 16)):
-        best, cand = T.tune(ctx, geo, w["m"], w["p"], nc, w["kappa"], q=w["q"], precision=prec,
-                            eta_adm=w["eta_adm"], leaf_depths=(2, 3, 4), on_the_fly=(False,), reps=5)
-        tuned[label] = {"choice_leaf_depth": best.leaf_depth,
+    # the autotuner's view of the served block form: leaf depth for 16 bf16 columns
+    tuned = {"fp64_1col": headline_tuning}
+    for label, prec, nc in (("bf16_16col", B.MIX_BF16, 16),):
+        bb, cc = AT.tune(ctx, geo, w["m"], w["p"], nc, w["kappa"], q=w["q"], precision=prec,
+                         eta_adm=w["eta_adm"], leaf_depths=(2, 3, 4), on_the_fly=(False,), reps=5)
+        tuned[label] = {"choice_leaf_depth": bb.leaf_depth,
                         "candidates": [{"leaf_depth": c.leaf_depth, "matvec_ms": c.matvec_ms,
                                         "assembly_ms": c.assembly_ms, "device_bytes": c.device_bytes}
-                                       for c in cand]}
+                                       for c in cc]}
     torch.cuda.empty_cache()
     # the same solves streaming the coupling tiles themselves (no recompression),
-    # and with the factors truncated at 1e-7
+    # with the factors truncated at 1e-7, and at leaf depth 2 (smaller leaves:
+    # a sparser near field, four times the coupling tiles)
     recompressed = {}
-    for label, rt in (("tiles", 0.0), ("tol_1e-7", 1e-7)):
+    for label, ld, rt in (("tiles", LD, 0.0), ("tol_1e-7", LD, 1e-7), ("leaf_depth_2", 2, RT)):
+        if label == "leaf_depth_2" and LD == 2:
+            continue
         op_t = B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"], kcap=w["kcap"],
-                          leaf_depth=w["leaf_depth"], recompress_tol=rt)
+                          leaf_depth=ld, recompress_tol=rt)
         rs = run_solves(op_t, d, args.steps, args.warmup)
         xt = torch.from_numpy(g_rows["x"]).to(dev)
         yt = torch.zeros_like(xt)
         op_t.h2_matvec(xt, yt)
         torch.cuda.synchronize()
         recompressed[label] = {
-            "far_recompress_tol": rt, "matvecs_per_s": rs["matvecs_per_s"], "solves_per_s": rs["solves_per_s"],
+            "leaf_depth": ld, "far_recompress_tol": rt, "matvecs_per_s": rs["matvecs_per_s"],
+            "solves_per_s": rs["solves_per_s"], "gmres_iters": rs["gmres_iters"],
             "headline_speedup": value / rs["matvecs_per_s"], "device_bytes": op_t.info.device_bytes,
             "err_matvec_vs_oracle_rows": oracle_row_error(yt.cpu().numpy()),
             "far_field_rel_diff_vs_headline": float((rs["uinf"] - plain["uinf"]).abs().max()
@@ -755,9 +777,12 @@ def main():
         ref_coeff = None
         xb = torch.from_numpy(I.random_complex(777, (args.block, n))).to(dev)
         yb = torch.zeros_like(xb)
+        # the fp64 block runs on the headline operator, the mixed-precision ones at
+        # the leaf depth the autotuner chose for 16 bf16 columns
+        ld_lo = tuned["bf16_16col"]["choice_leaf_depth"]
         for prec_name, prec in (("fp64", B.FP64), ("fp32", B.MIX_FP32), ("bf16", B.MIX_BF16)):
             o = op if prec == B.FP64 else B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"],
-                                                      kcap=w["kcap"], leaf_depth=w["leaf_depth"], precision=prec)
+                                                      kcap=w["kcap"], leaf_depth=ld_lo, precision=prec)
             r = run_solves(o, dirs_b, max(1, args.steps // 2), 1)
             c = r.pop("coeff").cpu().numpy()
             r.pop("uinf")
@@ -784,7 +809,6 @@ def main():
         x64 = torch.from_numpy(I.random_complex(778, (64, n))).to(dev)
         y64 = torch.zeros_like(x64)
         block_mv["fp64_64col"] = block_matvec(op, "fp64", x64, y64, max(5, args.matvecs // 5))
-        block_mv["fp64_64col"]["m2l_traffic_bytes"] = MEASURED_TRAFFIC["fp64_64col"]
         del xb, yb, x64, y64
 
     # matvec-only loop with HIP-event kernel timing on the launch stream
@@ -822,7 +846,17 @@ def main():
     tile_or_factor = info.far_factor_entries * 16 if info.far_factor_entries else info.far_pairs * nq * nq * 16
     m2l_bytes = tile_or_factor + info.far_pairs * nq * 16 + nchunk_est * nq * 16
     m2l_avg = m2l_ms / max(m2l_n, 1) / 1e3
-    achieved = m2l_bytes / m2l_avg / 1e9 if m2l_n else None
+    # ... and of the one-column near product: the values, the groups' column
+    # lists, row pointers and list offsets, x, the far part and y
+    spmv_bytes = info.nnz * 16 + info.near_col_entries * 4 + n * 16 + 3 * n * 16
+    spmv_avg = spmv_ms / max(spmv_n, 1) / 1e3
+    # the roofline of the kernel that takes the most time per matvec
+    if spmv_n and spmv_avg > m2l_avg:
+        roof_kernel, roof_bytes, roof_avg = "spmv_combine<1>", spmv_bytes, spmv_avg
+    else:
+        roof_kernel = "m2l_chunks_lowrank" if info.far_factor_entries else "m2l_chunks_wave"
+        roof_bytes, roof_avg = m2l_bytes, m2l_avg
+    achieved = roof_bytes / roof_avg / 1e9 if roof_avg > 0 else None
 
     # error against the stored fp64 oracle rows / Mie
     xg = torch.from_numpy(g_rows["x"]).to(dev)
@@ -859,8 +893,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "geometry": "unit sphere, 6 rational-quadratic patches",
                    "level_m": w["m"], "degree_p": w["p"], "N": n, "kappa": w["kappa"], "bc": "soft",
-                   "q": w["q"], "eta_adm": w["eta_adm"], "kcap": w["kcap"], "leaf_depth": w["leaf_depth"],
-                   "far_recompress_tol": w["recompress_tol"],
+                   "q": w["q"], "eta_adm": w["eta_adm"], "kcap": w["kcap"], "leaf_depth": LD,
+                   "far_recompress_tol": RT, "shape": "autotuned (leaf depth, tiles / factors)",
                    "rhs": 1, "gmres": f"restart 30, tol {w['tol']}", "far_pairs": info.far_pairs,
                    "nnz_near": info.nnz},
         "solves_per_s": plain["solves_per_s"],
@@ -887,10 +921,17 @@ def main():
         "err_farfield_vs_mie": err_mie,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": MEASURED_TRAFFIC.get("m2l_chunks_lowrank") if info.far_factor_entries
-                                else MEASURED_TRAFFIC["m2l_chunks_wave"],
-                     "kernel": "m2l_chunks_lowrank" if info.far_factor_entries else "m2l_chunks_wave",
-                     "bytes_per_launch": m2l_bytes, "avg_launch_ms": m2l_avg * 1e3},
+                     "traffic": MEASURED_TRAFFIC.get((roof_kernel, LD)),
+                     "kernel": roof_kernel, "bytes_per_launch": roof_bytes, "avg_launch_ms": roof_avg * 1e3,
+                     "coupling": {"kernel": "m2l_chunks_lowrank" if info.far_factor_entries else "m2l_chunks_wave",
+                                  "bytes_per_launch": m2l_bytes, "avg_launch_ms": m2l_avg * 1e3,
+                                  "achieved_GBps": m2l_bytes / m2l_avg / 1e9 if m2l_n else None,
+                                  "traffic": MEASURED_TRAFFIC.get(
+                                      ("m2l_chunks_lowrank" if info.far_factor_entries else "m2l_chunks_wave", LD))},
+                     "near": {"kernel": "spmv_combine<1>", "bytes_per_launch": spmv_bytes,
+                              "avg_launch_ms": spmv_avg * 1e3,
+                              "achieved_GBps": spmv_bytes / spmv_avg / 1e9 if spmv_n else None,
+                              "traffic": MEASURED_TRAFFIC.get(("spmv_combine<1>", LD))}},
     }
     if args.serve > 0:
         out["serving"] = serve_stream(args.serve, args.serve_rate)

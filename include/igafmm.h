@@ -214,6 +214,9 @@ typedef struct {
     double assembly_near_ms, assembly_far_ms;
     int64_t far_factor_entries; /* far_recompress_tol > 0: complex entries of all tile
                                    factors (2 nq rank per far pair); else 0          */
+    int64_t near_col_entries;   /* int32 column indices the one-column near product
+                                   reads: one list per group of rows with the same
+                                   leaves (the CSR's own indices are not read)      */
 } igb_op_info;
 
 /* ---------------------------------------------------------------- context */
@@ -327,9 +330,14 @@ igb_status igb_op_use_graphs(igb_op op, int enable);
  * blocks of 1..15 columns are bitwise equal to single-column results, results of
  * blocks of >= 16 columns bitwise equal to those of any other block of >= 16,
  * and the two differ by rounding (<= 1e-12 relative to max|y| of the column;
- * ~1e-15 measured).  Reduced-precision products (IGB_MV_LOWPREC) use the matrix
- * cores for every block size and are batch invariant bitwise.  x and y must not
- * overlap.  Stream-ordered. */
+ * ~1e-15 measured).  Operators with far_recompress_tol > 0 apply the tile
+ * factors to single columns and the tiles to blocks of 2 or more: a column
+ * alone and the same column in a block differ by the truncation, at most
+ * far_recompress_tol ||K||_F per tile (2e-10 relative to max|y| measured at
+ * 1e-8 on the level-5 sphere); blocks of 2..15 columns agree bitwise with each
+ * other.  Reduced-precision products (IGB_MV_LOWPREC) use the matrix cores for
+ * every block size and are batch invariant bitwise.  x and y must not overlap.
+ * Stream-ordered. */
 igb_status h2_matvec(igb_op op, const double* x, double* y, int nrhs, int parts, void* hip_stream);
 
 /* Allocation-free variant of h2_matvec, for callers that cannot allocate device
@@ -362,9 +370,11 @@ igb_status cfie_rhs(igb_op op, const double* dirs, int ndir, double* b, void* hi
  * array coeffs [ndir][n].  The directions run in lockstep: one block matvec per
  * Arnoldi step, each column with its own Krylov basis, rotations and stopping
  * test, so a column's solution does not depend on the other columns (with the
- * exception stated at h2_matvec: IGB_FP64 operators with stored couplings solve
+ * exceptions stated at h2_matvec: IGB_FP64 operators with stored couplings solve
  * ndir >= 16 with matrix-core couplings, whose iterates differ from those of
- * smaller batches by rounding; within either range they agree bitwise).
+ * smaller batches by rounding, and recompressed operators solve one direction
+ * with the tile factors and several with the tiles; within each range the
+ * iterates agree bitwise).
  * Operators with IGB_MIX_* precision solve by iterative refinement:
  * x += GMRES(A_rounded, b - A_fp64 x) until the fp64 residual reaches tol; a
  * column whose step reduces that residual by less than a factor 10 continues

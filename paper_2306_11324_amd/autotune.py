@@ -1,13 +1,15 @@
 """Autotuner over the operator's shape: the leaf depth d (cluster size, hence
 how the work splits between the near field and the coupling tiles, and how
-many tiles there are) and stored versus on-the-fly fp64 couplings, measured
-on the device for a workload class and cached per class.
+many tiles there are), stored versus on-the-fly fp64 couplings, and stored
+tiles versus tiles recompressed to low-rank factors at a given tolerance,
+measured on the device for a workload class and cached per class.
 
 Every candidate keeps the admissibility rule and the interpolation degree, so
-the compression error bound is the same; only time and memory are traded.  The
-cost of a candidate is its assembly time plus an expected number of block
-matvecs at the class's column count (a served request assembles once and
-applies the operator a few hundred times).  Timing is wall time around
+the interpolation error bound is the same (a recompression tolerance adds its
+own relative error per tile, far below it at 1e-8); only time and memory are
+traded.  The cost of a candidate is its assembly time plus an expected number
+of block matvecs at the class's column count (a served request assembles once
+and applies the operator a few hundred times).  Timing is wall time around
 synchronised launches; nothing here computes any part of the method.
 """
 from __future__ import annotations
@@ -48,6 +50,8 @@ class Choice:
     matvec_ms: float
     assembly_ms: float
     device_bytes: int
+    recompress_tol: float = 0.0
+    far_pairs: int = -1
 
 
 class TuneCache:
@@ -100,7 +104,7 @@ def measure(ctx, geo, ncol: int, reps: int = 5, **op_args) -> Choice | None:
     torch.cuda.synchronize()
     t_mv = (time.perf_counter() - t0) / reps * 1e3
     ch = Choice(op_args.get("leaf_depth", 2), bool(op_args.get("far_on_the_fly", False)), t_mv, t_asm,
-                op.info.device_bytes)
+                op.info.device_bytes, float(op_args.get("recompress_tol", 0.0)), int(op.info.far_pairs))
     del op
     torch.cuda.empty_cache()
     return ch
@@ -108,11 +112,15 @@ def measure(ctx, geo, ncol: int, reps: int = 5, **op_args) -> Choice | None:
 
 def tune(ctx, geo, m: int, p: int, ncol: int, kappa: float, bc: int = B.SOFT, q: int = 8,
          precision: int = B.FP64, eta_adm: float = 1.6, quad_extra: int = 0, matvecs: int = 200,
-         leaf_depths=(1, 2, 3, 4), on_the_fly=(False, True), cache: TuneCache | None = None,
-         reps: int = 5):
-    """Best (leaf depth, stored / on-the-fly) for the class of this operator;
-    returns (choice, [every measured candidate]).  A cached choice is returned
-    without measuring."""
+         leaf_depths=(1, 2, 3, 4), on_the_fly=(False, True), recompress_tols=(0.0,),
+         cache: TuneCache | None = None, reps: int = 5, require_far: bool = False):
+    """Best (leaf depth, stored / on-the-fly, recompression tolerance) for the
+    class of this operator; returns (choice, [every measured candidate]).  A
+    cached choice is returned without measuring.  Recompression applies to
+    stored fp64 tiles only (on-the-fly and reduced-precision candidates take
+    tolerance 0).  With require_far, candidates without admissible blocks (a
+    leaf depth so coarse that the whole operator is near field, i.e. dense)
+    are measured and listed but not chosen."""
     key = TuneKey(device_arch(), m, p, q, bc, precision, round(math.log2(kappa)), nrhs_bucket(ncol))
     if cache is not None and cache.get(key) is not None:
         return cache.get(key), []
@@ -121,13 +129,16 @@ def tune(ctx, geo, m: int, p: int, ncol: int, kappa: float, bc: int = B.SOFT, q:
         if d > m:
             continue
         for otf in on_the_fly:
-            ch = measure(ctx, geo, ncol, reps, kappa=kappa, bc=bc, q=q, eta_adm=eta_adm, leaf_depth=d,
-                         precision=precision, far_on_the_fly=otf, quad_extra=quad_extra)
-            if ch is not None:
-                measured.append(ch)
-    if not measured:
+            tols = (0.0,) if otf or precision != B.FP64 else recompress_tols
+            for rt in tols:
+                ch = measure(ctx, geo, ncol, reps, kappa=kappa, bc=bc, q=q, eta_adm=eta_adm, leaf_depth=d,
+                             precision=precision, far_on_the_fly=otf, quad_extra=quad_extra, recompress_tol=rt)
+                if ch is not None:
+                    measured.append(ch)
+    eligible = [c for c in measured if c.far_pairs != 0] if require_far else measured
+    if not eligible:
         raise RuntimeError("autotune: no candidate could be assembled")
-    best = min(measured, key=lambda c: (c.assembly_ms + matvecs * c.matvec_ms, c.device_bytes))
+    best = min(eligible, key=lambda c: (c.assembly_ms + matvecs * c.matvec_ms, c.device_bytes))
     if cache is not None:
         cache.put(key, best)
     return best, measured

@@ -498,6 +498,7 @@ igb_status igb_op_get_info(igb_op op, igb_op_info* info) {
     info->assembly_near_ms = op->t_assembly_near;
     info->assembly_far_ms = op->t_assembly_far;
     info->far_factor_entries = op->lr_entries;
+    info->near_col_entries = int64_t(op->near_dcol.size());
     return IGB_OK;
 }
 

@@ -255,7 +255,9 @@ igb_status norms(const double2* v, int64_t n, int C, double* dev_tmp, std::vecto
 // matvec always covers all C columns, so a column's iterates depend on the batch
 // only through the matvec's code path: fp64 operators with stored couplings
 // take the matrix-core coupling for C >= 16 (another summation order, equal to
-// the vector path up to rounding), every other case is bitwise batch invariant.
+// the vector path up to rounding), recompressed operators the tile factors for
+// C = 1 and the tiles for C >= 2 (equal up to the truncation); every other
+// case is bitwise batch invariant.
 igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, const std::vector<int>& maxit,
                        const std::vector<double>& tol, int mvflags, hipStream_t s, std::vector<ColumnResult>& res,
                        const SolveLog& log) {

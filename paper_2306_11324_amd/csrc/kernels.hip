@@ -1879,6 +1879,14 @@ __global__ __launch_bounds__(256) void tile_rrqr(const double2* __restrict__ cou
     }
 }
 
+// operator data streamed once per product: non-temporal loads leave the
+// caches to the vectors the product reuses
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_nt(const double2* p) {
+    const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
+    return make_double2(v.x, v.y);
+}
+
 constexpr int LR_WAVES = 8;
 // coupling, sound-soft, one column, from the recompressed tiles: one
 // workgroup of NW waves per chunk (up to 8 pairs of one target), wave w taking
@@ -2097,7 +2105,9 @@ constexpr int SPMV_U1 = 4;   // row strides in flight per lane of the one-column
 // y[r][row] = sum_j val x[r][col] (+ far part mapped to the solution space); one
 // wave per row, lanes stride over the row, butterfly reduction (fixed order).
 // Columns come from the row's group list (rows with the same leaves share one),
-// so the index reads mostly hit the caches and HBM streams the values alone.
+// so the index reads mostly hit the caches and HBM streams the values alone
+// (non-temporal loads: the values are read once per product, x and the
+// column lists stay in the caches).
 // (RB columns per pass; consecutive nonzeros of a row mostly have consecutive
 // columns, so the lanes' x reads coalesce.  Each column's operations and
 // their order do not depend on RB.  On the m = 5 sphere with 16 columns,
@@ -2134,7 +2144,7 @@ __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ 
                 int cc[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    v[u] = val[idx + u * 64];
+                    v[u] = ld_nt(val + idx + u * 64);
                     cc[u] = col[cbase + idx + u * 64];
                 }
 #pragma unroll
@@ -2144,7 +2154,7 @@ __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ 
                         if (c0 + cb < ncol) acc[cb] = cfma(v[u], x[int64_t(c0 + cb) * nrows + cc[u]], acc[cb]);
             }
             for (; idx < e; idx += 64) {
-                const double2 v = val[idx];
+                const double2 v = ld_nt(val + idx);
                 const int64_t cc = col[cbase + idx];
 #pragma unroll
                 for (int cb = 0; cb < RB; ++cb)

@@ -114,7 +114,8 @@ class Server:
             ch = c.tune_cache.get(T.TuneKey(T.device_arch(), req.m, c.p, c.q, bc, prec,
                                             round(math.log2(req.kappa)), T.nrhs_bucket(len(req.dirs))))
             if ch is not None:
-                args.update(leaf_depth=ch.leaf_depth, far_on_the_fly=ch.far_on_the_fly)
+                args.update(leaf_depth=ch.leaf_depth, far_on_the_fly=ch.far_on_the_fly,
+                            recompress_tol=ch.recompress_tol)
         return args
 
     def estimate(self, req: I.Request) -> int:

@@ -1,7 +1,9 @@
-"""Autotuner over leaf depth and stored / on-the-fly couplings: every candidate
-keeps the accuracy against the dense oracle rows (same admissibility and q),
-the choice is the cheapest measured candidate, and the cache round-trips
-through its JSON file and is what the server's operator arguments use."""
+"""Autotuner over leaf depth, stored / on-the-fly couplings and tiles /
+recompressed factors: every candidate keeps the accuracy against the dense
+oracle rows (same admissibility and q), the choice is the cheapest measured
+candidate (with require_far, the cheapest with admissible blocks), and the
+cache round-trips through its JSON file and is what the server's operator
+arguments use."""
 import os
 import sys
 
@@ -21,21 +23,25 @@ def test_tuned_shape_is_cheapest_and_accurate(tmp_path):
     from paper_2306_11324_amd import binding as B
     from paper_2306_11324_amd import inputs as I
     g = dict(np.load(os.path.join(GOLD, "sphere_m5_p2_k8_rows.npz")))
-    print("case: sphere m=5 p=2 kappa=8 q=6 fp64, one column, leaf depths 1-3, stored / on the fly", flush=True)
+    print("case: sphere m=5 p=2 kappa=8 q=6 fp64, one column, leaf depths 1-3, stored / on the fly / "
+          "recompressed at 1e-8", flush=True)
     ctx = B.Context(0)
     geo = B.Geometry(ctx, I.sphere_patches(), 5, 2)
     cache = T.TuneCache(str(tmp_path / "tune.json"))
-    best, measured = T.tune(ctx, geo, 5, 2, 1, 8.0, q=6, leaf_depths=(1, 2, 3), cache=cache, reps=3)
+    best, measured = T.tune(ctx, geo, 5, 2, 1, 8.0, q=6, leaf_depths=(1, 2, 3), recompress_tols=(0.0, 1e-8),
+                            cache=cache, reps=3)
     for c in measured:
-        print(f"  d={c.leaf_depth} otf={c.far_on_the_fly}: matvec {c.matvec_ms:.3f} ms, assembly "
-              f"{c.assembly_ms:.0f} ms, {c.device_bytes / 1e9:.2f} GB", flush=True)
-    assert len(measured) >= 4
+        print(f"  d={c.leaf_depth} otf={c.far_on_the_fly} tol={c.recompress_tol:g}: matvec {c.matvec_ms:.3f} ms, "
+              f"assembly {c.assembly_ms:.0f} ms, {c.device_bytes / 1e9:.2f} GB, {c.far_pairs} far pairs", flush=True)
+    assert len(measured) >= 9 and {c.recompress_tol for c in measured} == {0.0, 1e-8}
+    assert all(c.far_pairs > 0 for c in measured)
     cost = [c.assembly_ms + 200 * c.matvec_ms for c in measured]
     assert best.assembly_ms + 200 * best.matvec_ms == min(cost)
     # every candidate is as accurate as the default against the oracle rows
     x = torch.from_numpy(g["x"]).cuda()
     for c in measured:
-        op = B.Operator(ctx, geo, kappa=8.0, q=6, leaf_depth=c.leaf_depth, far_on_the_fly=c.far_on_the_fly)
+        op = B.Operator(ctx, geo, kappa=8.0, q=6, leaf_depth=c.leaf_depth, far_on_the_fly=c.far_on_the_fly,
+                        recompress_tol=c.recompress_tol)
         y = torch.zeros_like(x)
         op.h2_matvec(x, y)
         torch.cuda.synchronize()
@@ -54,3 +60,19 @@ def test_tuned_shape_is_cheapest_and_accurate(tmp_path):
     srv.cfg = S.ServeConfig(p=2, q=6, precision=B.FP64, tune_cache=again)
     args = srv._op_args(req)
     assert args["leaf_depth"] == best.leaf_depth and args["far_on_the_fly"] == best.far_on_the_fly
+    assert args["recompress_tol"] == best.recompress_tol
+
+
+def test_require_far_skips_the_dense_shape():
+    """Leaf depth 4 on the level-5 sphere leaves no admissible block (the whole
+    operator is near field): with require_far it is measured but not chosen."""
+    from paper_2306_11324_amd import autotune as T
+    from paper_2306_11324_amd import binding as B
+    from paper_2306_11324_amd import inputs as I
+    print("case: sphere m=5 p=2 kappa=8 q=6 fp64, one column, leaf depths 3 and 4, require_far", flush=True)
+    ctx = B.Context(0)
+    geo = B.Geometry(ctx, I.sphere_patches(), 5, 2)
+    best, measured = T.tune(ctx, geo, 5, 2, 1, 8.0, q=6, leaf_depths=(3, 4), on_the_fly=(False,), reps=3,
+                            require_far=True)
+    assert {c.leaf_depth: c.far_pairs == 0 for c in measured} == {3: False, 4: True}
+    assert best.leaf_depth == 3 and best.far_pairs > 0

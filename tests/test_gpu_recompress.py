@@ -3,7 +3,7 @@ Householder QR with column pivoting, truncated where the trailing block's
 Frobenius norm falls below tol times the tile's, the one-column products
 streaming the factors.
 
-  * the level-5 sphere workload (kappa = 8, q = 6): one-column matvec against
+  * the level-5 sphere workload (kappa = 8, q = 6, leaf depths 2 and 3): one-column matvec against
     the tiles (the truncation moves each tile by at most tol in Frobenius norm;
     the product by <= 200 tol relative to max |y|) and against the sampled
     oracle rows (tests/golden/sphere_m5_p2_k8_rows.npz): the error against the
@@ -33,16 +33,16 @@ def _apply(op, x):
     return y.cpu().numpy()
 
 
-@pytest.mark.parametrize("tol", [1e-10, 1e-8, 1e-7])
-def test_recompressed_tiles_match_tiles_and_oracle(tol):
+@pytest.mark.parametrize("ld,tol", [(2, 1e-10), (2, 1e-8), (2, 1e-7), (3, 1e-8)])
+def test_recompressed_tiles_match_tiles_and_oracle(ld, tol):
     from paper_2306_11324_amd import binding as B
     from paper_2306_11324_amd import inputs as I
     g = dict(np.load(os.path.join(GOLD, "sphere_m5_p2_k8_rows.npz")))
-    print(f"case: sphere m=5 p=2 kappa=8 q=6 leaf depth 2, recompression tolerance {tol:g}", flush=True)
+    print(f"case: sphere m=5 p=2 kappa=8 q=6 leaf depth {ld}, recompression tolerance {tol:g}", flush=True)
     ctx = B.Context(0)
     geo = B.Geometry(ctx, I.sphere_patches(), 5, 2)
-    dense = B.Operator(ctx, geo, kappa=8.0, q=6, leaf_depth=2)
-    lr = B.Operator(ctx, geo, kappa=8.0, q=6, leaf_depth=2, recompress_tol=tol)
+    dense = B.Operator(ctx, geo, kappa=8.0, q=6, leaf_depth=ld)
+    lr = B.Operator(ctx, geo, kappa=8.0, q=6, leaf_depth=ld, recompress_tol=tol)
     x = g["x"]
     yd, yl = _apply(dense, x), _apply(lr, x)
     e_dense = float(np.abs(yl - yd).max() / np.abs(yd).max())
