@@ -661,9 +661,10 @@ def main():
             km[k] = ms / max(cnt, 1)
         o.profile(False)
         avg = km["m2l"] / 1e3
-        nq2 = info.nq * info.nq
-        flops = 8.0 * info.far_pairs * nq2 * nc
-        byts = float(info.far_pairs * nq2 * elem_bytes[prec_name])
+        oi = o.info
+        nq2 = oi.nq * oi.nq
+        flops = 8.0 * oi.far_pairs * nq2 * nc
+        byts = float(oi.far_pairs * nq2 * elem_bytes[prec_name])
         return {"ncol": nc, "column_matvecs_per_s": nc / tb, "ms_per_block_matvec": tb * 1e3, "kernel_ms": km,
                 "m2l_algorithmic_bytes": byts,
                 "m2l_traffic_bytes": MEASURED_TRAFFIC.get((f"{prec_name} {nc}col", w["m"] - o.info.leaf_level)),
@@ -732,12 +733,14 @@ def main():
     del op_sep, sep
     torch.cuda.empty_cache()
     # the autotuner's view of the served block form: leaf depth for 16 bf16 columns
+    # (costed as a served request: assembly plus 200 block matvecs)
     tuned = {"fp64_1col": headline_tuning}
     for label, prec, nc in (("bf16_16col", B.MIX_BF16, 16),):
         bb, cc = AT.tune(ctx, geo, w["m"], w["p"], nc, w["kappa"], q=w["q"], precision=prec,
-                         eta_adm=w["eta_adm"], leaf_depths=(2, 3, 4), on_the_fly=(False,), reps=5)
+                         eta_adm=w["eta_adm"], leaf_depths=(2, 3, 4), on_the_fly=(False,), reps=5,
+                         require_far=True)
         tuned[label] = {"choice_leaf_depth": bb.leaf_depth,
-                        "candidates": [{"leaf_depth": c.leaf_depth, "matvec_ms": c.matvec_ms,
+                        "candidates": [{"leaf_depth": c.leaf_depth, "far_pairs": c.far_pairs, "matvec_ms": c.matvec_ms,
                                         "assembly_ms": c.assembly_ms, "device_bytes": c.device_bytes}
                                        for c in cc]}
     torch.cuda.empty_cache()
@@ -777,12 +780,11 @@ def main():
         ref_coeff = None
         xb = torch.from_numpy(I.random_complex(777, (args.block, n))).to(dev)
         yb = torch.zeros_like(xb)
-        # the fp64 block runs on the headline operator, the mixed-precision ones at
-        # the leaf depth the autotuner chose for 16 bf16 columns
-        ld_lo = tuned["bf16_16col"]["choice_leaf_depth"]
+        # the fp64 block runs on the headline operator, the mixed-precision ones on
+        # operators of the same shape
         for prec_name, prec in (("fp64", B.FP64), ("fp32", B.MIX_FP32), ("bf16", B.MIX_BF16)):
             o = op if prec == B.FP64 else B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"],
-                                                      kcap=w["kcap"], leaf_depth=ld_lo, precision=prec)
+                                                      kcap=w["kcap"], leaf_depth=LD, precision=prec)
             r = run_solves(o, dirs_b, max(1, args.steps // 2), 1)
             c = r.pop("coeff").cpu().numpy()
             r.pop("uinf")

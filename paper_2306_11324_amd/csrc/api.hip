@@ -132,7 +132,8 @@ igb_status igb_ctx_create(int device, size_t hbm_budget_bytes, igb_ctx* out) {
         delete c;
         return st;
     }
-    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    hipError_t e = hipDeviceGetAttribute(&c->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete c;
         set_error("igb_ctx_create: %s", hipGetErrorString(e));
@@ -298,7 +299,8 @@ static igb_status build_one(igb_ctx ctx, igb_geom g, const igb_op_params* prm, c
     const size_t fp64_tiles =
         prm->far_on_the_fly ? 0 : size_t(op->nfar) * op->nq * op->nq * 16 * ntile + size_t(3) * op->nq * 16 + 256;
     size_t need = fp64_tiles + size_t(op->nnz) * 20 + size_t(op->N + 1) * 8 + op->near_dcol.size() * 4 +
-                  op->row_coff.size() * 8 +
+                  op->row_coff.size() * 8 + op->near_wgs.size() * sizeof(NearGroupWG) +
+                  op->near_grp_rows.size() * 4 +
                   size_t(op->nclusters) * op->nq * (16 * 8 + 32) + op->near_src.size() * 4;
     // held during assembly only: the staged element blocks and the near pair lists
     const size_t transient = std::min<size_t>(op->near_src.size(), size_t(1) << 22) * nl * nl * 16 +

@@ -57,6 +57,7 @@ struct igb_ctx_s {
     // geometries and operators (tables, work vectors, Krylov bases, temporaries)
     std::atomic<size_t> used{0};
     hipStream_t stream = nullptr;
+    int lds_max = 0;     // LDS bytes a workgroup may allocate
 };
 
 namespace igb {
@@ -161,6 +162,15 @@ struct M2LChunks {
 constexpr int NEAR_TILE_ROWS = 16;
 constexpr int NEAR_TILE_K = 8;
 constexpr double NEAR_TILE_FILL = 0.35;   // union at most 35% longer than the longest member list
+// rows per workgroup of the group-staged one-column near product (one wave each)
+constexpr int NEAR_GROUP_ROWS = 16;
+struct NearGroupWG {
+    int64_t list_off;   // the group's column list in near_dcol
+    int list_len;       // its length (every row of the group has this many entries)
+    int row0, nrows;    // the workgroup's rows: near_grp_rows[row0 .. row0 + nrows)
+    int pad;
+};
+
 struct NearTile {
     int64_t val_off;   // first complex entry of the tile in the tile layout
     int64_t col_off;   // first entry of the tile's column list (sorted)
@@ -204,6 +214,12 @@ struct igb_op_s {
     // and per row the offset of its list (the near products read columns from here)
     std::vector<int> near_dcol;
     std::vector<int64_t> row_coff;
+    // the one-column near product by groups: workgroups of up to
+    // NEAR_GROUP_ROWS rows of one group (rows listed group by group in
+    // near_grp_rows), each staging its group's x entries in LDS once
+    std::vector<NearGroupWG> near_wgs;
+    std::vector<int> near_grp_rows;
+    int near_list_max = 0;   // longest group column list
     // bf16 operators: the near rows in tiles of up to 16 rows over a common column list
     std::vector<NearTile> near_tiles;
     std::vector<int> near_tile_cols;  // the tiles' column lists
@@ -216,7 +232,7 @@ struct igb_op_s {
     // its factors (complex entries) and the factors u_k [k][nq], v_k^T [nq][rank]
     igb::DevBuf d_lr, d_lr_rank, d_lr_off;
     int64_t lr_entries = 0;
-    igb::DevBuf d_rowptr, d_col, d_val, d_dcol, d_row_coff;
+    igb::DevBuf d_rowptr, d_col, d_val, d_dcol, d_row_coff, d_near_wgs, d_near_grp_rows;
     // bf16 operators: fp32 near-field values and fp32 copies of the columns for the
     // near product of the inner (refinement) matvecs
     igb::DevBuf d_val_lo, d_xnear_lo, d_near_tiles, d_near_tile_cols;

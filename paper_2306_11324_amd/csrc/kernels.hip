@@ -2187,6 +2187,61 @@ __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ 
     }
 }
 
+// The one-column near product by groups: a workgroup takes up to
+// NEAR_GROUP_ROWS rows of one group, gathers the group's x entries into LDS in
+// list order (every row of the group has exactly the group's columns, entry j
+// of a row belonging to list entry j), and then each wave forms one row's sum
+// against LDS: no column index and no x gather per nonzero.  The lanes, trips
+// and butterfly are those of spmv_combine<1>, with the same x values, so the
+// rows equal spmv_combine's bitwise.
+template <int NWV>
+__global__ __launch_bounds__(64 * NWV) void spmv_groups(const NearGroupWG* __restrict__ wgs,
+                                                        const int* __restrict__ grp_rows,
+                                                        const int64_t* __restrict__ row_ptr,
+                                                        const int* __restrict__ col,
+                                                        const double2* __restrict__ val,
+                                                        const double2* __restrict__ x,
+                                                        const double2* __restrict__ yfar, int64_t n2,
+                                                        const int* __restrict__ s0_ptr,
+                                                        const int* __restrict__ s0_reps, double2* __restrict__ y) {
+    extern __shared__ double2 xs[];
+    // consecutive workgroups (the same or neighbouring groups) on one XCD
+    const NearGroupWG W = wgs[xcd_chunk(blockIdx.x, gridDim.x)];
+    for (int j = threadIdx.x; j < W.list_len; j += 64 * NWV) xs[j] = x[col[W.list_off + j]];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wave >= W.nrows) return;
+    const int row = grp_rows[W.row0 + wave];
+    const double2* v0 = val + row_ptr[row];
+    const int len = W.list_len;
+    constexpr int U = SPMV_U1;
+    double2 acc = make_double2(0, 0);
+    int j = lane;
+    for (; j + (U - 1) * 64 < len; j += U * 64) {
+        double2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = ld_nt(v0 + j + u * 64);
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc = cfma(v[u], xs[j + u * 64], acc);
+    }
+    for (; j < len; j += 64) acc = cfma(ld_nt(v0 + j), xs[j], acc);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        acc.x += __shfl_xor(acc.x, off, 64);
+        acc.y += __shfl_xor(acc.y, off, 64);
+    }
+    if (lane == 0) {
+        if (yfar) {
+            if (s0_ptr) {
+                for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q) acc = cadd(acc, yfar[s0_reps[q]]);
+            } else {
+                acc = cadd(acc, yfar[row]);
+            }
+        }
+        y[row] = acc;
+    }
+}
+
 // fp32 tile layout of the near field: tile t holds its rows' values as
 // [k block][row][8] over the tile's column list (zero where the row has no
 // entry and past the list's end), rounded (RNE) from the fp64 CSR values.
@@ -2999,6 +3054,8 @@ static igb_status near_launch(igb_op op, hipStream_t s) {
     if ((st = upload(op->d_col, op->col.data(), op->col.size(), acct))) return st;
     if ((st = upload(op->d_dcol, op->near_dcol.data(), op->near_dcol.size(), acct))) return st;
     if ((st = upload(op->d_row_coff, op->row_coff.data(), op->row_coff.size(), acct))) return st;
+    if ((st = upload(op->d_near_wgs, op->near_wgs.data(), op->near_wgs.size(), acct))) return st;
+    if ((st = upload(op->d_near_grp_rows, op->near_grp_rows.data(), op->near_grp_rows.size(), acct))) return st;
     if ((st = alloc(op->d_val, op->nnz * sizeof(double2), acct))) return st;
     IGB_HIP(hipMemsetAsync(op->d_val.ptr, 0, op->nnz * sizeof(double2), s));
 
@@ -3866,6 +3923,12 @@ static igb_status matvec_launches(igb_op op, const MatvecWork& W, const double* 
                            op->d_near_tiles.as<NearTile>(), int64_t(op->near_tiles.size()),
                            op->d_near_tile_cols.as<int>(),
                            op->d_val_lo.as<float2>(), xt, N, yfar, g->n2, s0p, s0r, use_near, ncol, Y);
+    } else if (ncol == 1 && use_near && !op->near_wgs.empty() &&
+               size_t(op->near_list_max) * sizeof(double2) <= size_t(g->ctx->lds_max)) {
+        hipLaunchKernelGGL(spmv_groups<NEAR_GROUP_ROWS>, dim3(unsigned(op->near_wgs.size())),
+                           dim3(64 * NEAR_GROUP_ROWS), size_t(op->near_list_max) * sizeof(double2), s,
+                           op->d_near_wgs.as<NearGroupWG>(), op->d_near_grp_rows.as<int>(), rp, dcl, vl, X, yfar,
+                           g->n2, s0p, s0r, Y);
     } else if (ncol == 1) {
         hipLaunchKernelGGL(spmv_combine<1>, sg, sb, 0, s, rp, rco, dcl, vl, X, N, yfar, g->n2, s0p, s0r, use_near,
                            ncol, Y);

@@ -435,11 +435,27 @@ igb_status near_pattern(igb_op op) {
     // each group's column list once; every row points at its group's list
     op->near_dcol.clear();
     op->row_coff.assign(N, 0);
+    op->near_wgs.clear();
+    op->near_grp_rows.clear();
+    op->near_list_max = 0;
     for (const std::vector<int>* g : order) {
         const int64_t off = int64_t(op->near_dcol.size());
+        const int len = int(op->row_ptr[g->front() + 1] - op->row_ptr[g->front()]);
         op->near_dcol.insert(op->near_dcol.end(), op->col.begin() + op->row_ptr[g->front()],
                              op->col.begin() + op->row_ptr[g->front() + 1]);
-        for (int r : *g) op->row_coff[r] = off;
+        op->near_list_max = std::max(op->near_list_max, len);
+        for (size_t i = 0; i < g->size(); i += NEAR_GROUP_ROWS) {
+            NearGroupWG w{};
+            w.list_off = off;
+            w.list_len = len;
+            w.row0 = int(op->near_grp_rows.size() + i);
+            w.nrows = int(std::min<size_t>(NEAR_GROUP_ROWS, g->size() - i));
+            op->near_wgs.push_back(w);
+        }
+        for (int r : *g) {
+            op->row_coff[r] = off;
+            op->near_grp_rows.push_back(r);
+        }
     }
     {
         // bf16 operators use the tiles with fp32 values (inner matvecs), fp64
