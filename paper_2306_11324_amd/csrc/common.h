@@ -289,10 +289,13 @@ struct igb_op_s {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
         graphs.clear();
     }
-    void* h_pin = nullptr;            // pinned host buffer of the GMRES Hessenberg steps
+    void* h_pin = nullptr;            // pinned host buffers of the GMRES Hessenberg steps (two)
     size_t h_pin_bytes = 0;
+    hipEvent_t ev_h[2] = {nullptr, nullptr};   // their copies have landed
     ~igb_op_s() {
         if (h_pin) (void)hipHostFree(h_pin);
+        for (hipEvent_t e : ev_h)
+            if (e) (void)hipEventDestroy(e);
         clear_graphs();
         for (auto& t : timers)
             for (hipEvent_t e : t.pool) (void)hipEventDestroy(e);

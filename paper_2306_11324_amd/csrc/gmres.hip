@@ -172,7 +172,8 @@ struct Work {
     int m, C, nseg;
     double2 *V, *w, *r, *R, *D, *h, *h2, *y, *part;
     double *nrm, *sc;
-    double2* hp;   // pinned host copy of h, h2 and the squared norms
+    double2* hp[2];      // pinned host copies of h, h2 and the squared norms (alternate steps)
+    hipEvent_t ev[2];    // the copy into hp[k] has landed
 };
 
 struct SolveSizes {
@@ -228,14 +229,19 @@ igb_status ensure_work(igb_op op, int m, int C, Work& W) {
     W.nrm = reinterpret_cast<double*>(W.h2 + int64_t(m + 2) * C);
     W.sc = W.nrm + C;
     W.y = reinterpret_cast<double2*>(W.sc + C);
-    if (op->h_pin_bytes < need_h) {
+    if (op->h_pin_bytes < 2 * need_h) {
         if (op->h_pin) (void)hipHostFree(op->h_pin);
         op->h_pin = nullptr;
         op->h_pin_bytes = 0;
-        IGB_HIP(hipHostMalloc(&op->h_pin, need_h, hipHostMallocDefault));
-        op->h_pin_bytes = need_h;
+        IGB_HIP(hipHostMalloc(&op->h_pin, 2 * need_h, hipHostMallocDefault));
+        op->h_pin_bytes = 2 * need_h;
     }
-    W.hp = static_cast<double2*>(op->h_pin);
+    W.hp[0] = static_cast<double2*>(op->h_pin);
+    W.hp[1] = reinterpret_cast<double2*>(static_cast<char*>(op->h_pin) + need_h);   // need_h is a multiple of 16
+    for (int k = 0; k < 2; ++k) {
+        if (!op->ev_h[k]) IGB_HIP(hipEventCreateWithFlags(&op->ev_h[k], hipEventDisableTiming));
+        W.ev[k] = op->ev_h[k];
+    }
     return IGB_OK;
 }
 
@@ -298,69 +304,91 @@ igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, 
         }
         IGB_HIP(hipMemcpyAsync(Wk.sc, sc.data(), C * sizeof(double), hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(cscale_multi, dim3(gb), dim3(256), 0, s, r, n, C, Wk.sc, V);
-        int j = 0;
-        for (; j < m; ++j) {
-            bool going = false;
-            for (int c = 0; c < C; ++c) going = going || (in_cycle[c] && jc[c] == j && active(c));
-            if (!going) break;
-            if ((st = matvec_device(op, reinterpret_cast<const double*>(V + int64_t(j) * C * n),
-                                    reinterpret_cast<double*>(w), C, mvflags, s)))
-                return st;
+        // A column takes part in step jj if, after step jj - 1, it is in the cycle,
+        // has taken jj steps and is still active.  Step j is enqueued before the
+        // host processes step j - 1 (the device runs step j meanwhile, its
+        // Hessenberg entries go to the other pinned buffer); if step j - 1 ends
+        // every column, step j is dropped unprocessed (and not counted).
+        auto going = [&](int jj) {
+            for (int c = 0; c < C; ++c)
+                if (in_cycle[c] && jc[c] == jj && active(c)) return true;
+            return false;
+        };
+        const size_t hcopy = size_t(2) * (m + 2) * C * sizeof(double2) + size_t(C) * sizeof(double);
+        auto enqueue = [&](int jj) -> igb_status {
+            igb_status st2;
+            if ((st2 = matvec_device(op, reinterpret_cast<const double*>(V + int64_t(jj) * C * n),
+                                     reinterpret_cast<double*>(w), C, mvflags, s)))
+                return st2;
             // classical Gram-Schmidt, twice
-            const size_t hlds = size_t(std::min<int64_t>(C, 63 / n + 2)) * (j + 1) * sizeof(double2);
-            hipLaunchKernelGGL(cdots_seg, dim3(j + 1, Wk.nseg, C), dim3(RT), 0, s, V, n, C, Wk.nseg, w, Wk.part);
-            hipLaunchKernelGGL(cmaxpy_fin, dim3(gb64), dim3(64), hlds, s, V, j + 1, n, C, Wk.part, Wk.nseg, Wk.h, w);
-            hipLaunchKernelGGL(cdots_seg, dim3(j + 1, Wk.nseg, C), dim3(RT), 0, s, V, n, C, Wk.nseg, w, Wk.part);
-            hipLaunchKernelGGL(cmaxpy_fin, dim3(gb64), dim3(64), hlds, s, V, j + 1, n, C, Wk.part, Wk.nseg, Wk.h2, w);
+            const size_t hlds = size_t(std::min<int64_t>(C, 63 / n + 2)) * (jj + 1) * sizeof(double2);
+            hipLaunchKernelGGL(cdots_seg, dim3(jj + 1, Wk.nseg, C), dim3(RT), 0, s, V, n, C, Wk.nseg, w, Wk.part);
+            hipLaunchKernelGGL(cmaxpy_fin, dim3(gb64), dim3(64), hlds, s, V, jj + 1, n, C, Wk.part, Wk.nseg, Wk.h, w);
+            hipLaunchKernelGGL(cdots_seg, dim3(jj + 1, Wk.nseg, C), dim3(RT), 0, s, V, n, C, Wk.nseg, w, Wk.part);
+            hipLaunchKernelGGL(cmaxpy_fin, dim3(gb64), dim3(64), hlds, s, V, jj + 1, n, C, Wk.part, Wk.nseg, Wk.h2, w);
             // ||w||^2 and the next basis vector on the device, then one copy of
             // the step's Hessenberg entries and norms to the host
             hipLaunchKernelGGL(cnorm2_multi, dim3(C), dim3(1024), 0, s, w, n, Wk.nrm);
             hipLaunchKernelGGL(cscale_by_norm, dim3(gb), dim3(256), 0, s, w, n, C, Wk.nrm,
-                               V + int64_t(j + 1) * C * n);
+                               V + int64_t(jj + 1) * C * n);
             IGB_HIP(hipGetLastError());
-            const size_t hcopy = size_t(2) * (m + 2) * C * sizeof(double2) + size_t(C) * sizeof(double);
-            IGB_HIP(hipMemcpyAsync(Wk.hp, Wk.h, hcopy, hipMemcpyDeviceToHost, s));
-            IGB_HIP(hipStreamSynchronize(s));
-            const double2* hp1 = Wk.hp;
-            const double2* hp2 = Wk.hp + int64_t(m + 2) * C;
-            const double* hpn = reinterpret_cast<const double*>(Wk.hp + int64_t(2) * (m + 2) * C);
+            IGB_HIP(hipMemcpyAsync(Wk.hp[jj & 1], Wk.h, hcopy, hipMemcpyDeviceToHost, s));
+            IGB_HIP(hipEventRecord(Wk.ev[jj & 1], s));
+            return IGB_OK;
+        };
+        auto process = [&](int jj) -> igb_status {
+            IGB_HIP(hipEventSynchronize(Wk.ev[jj & 1]));
+            const double2* hp1 = Wk.hp[jj & 1];
+            const double2* hp2 = hp1 + int64_t(m + 2) * C;
+            const double* hpn = reinterpret_cast<const double*>(hp1 + int64_t(2) * (m + 2) * C);
             hn.resize(C);
             for (int c = 0; c < C; ++c) hn[c] = std::sqrt(hpn[c]);
             for (int c = 0; c < C; ++c) {
-                if (!(in_cycle[c] && jc[c] == j && active(c))) continue;
+                if (!(in_cycle[c] && jc[c] == jj && active(c))) continue;
                 ++res[c].iters;
                 ++res[c].applications;
                 std::vector<cplx>& Hc = H[c];
-                for (int i = 0; i <= j; ++i) {
+                for (int i = 0; i <= jj; ++i) {
                     const double2 a1 = hp1[size_t(i) * C + c], a2 = hp2[size_t(i) * C + c];
-                    Hc[size_t(i) * m + j] = cplx(a1.x + a2.x, a1.y + a2.y);
+                    Hc[size_t(i) * m + jj] = cplx(a1.x + a2.x, a1.y + a2.y);
                 }
-                Hc[size_t(j + 1) * m + j] = hn[c];
-                for (int i = 0; i < j; ++i) {
-                    cplx a = Hc[size_t(i) * m + j], bb = Hc[size_t(i + 1) * m + j];
-                    Hc[size_t(i) * m + j] = cs[c][i] * a + sn[c][i] * bb;
-                    Hc[size_t(i + 1) * m + j] = -std::conj(sn[c][i]) * a + cs[c][i] * bb;
+                Hc[size_t(jj + 1) * m + jj] = hn[c];
+                for (int i = 0; i < jj; ++i) {
+                    cplx a = Hc[size_t(i) * m + jj], bb = Hc[size_t(i + 1) * m + jj];
+                    Hc[size_t(i) * m + jj] = cs[c][i] * a + sn[c][i] * bb;
+                    Hc[size_t(i + 1) * m + jj] = -std::conj(sn[c][i]) * a + cs[c][i] * bb;
                 }
-                cplx a = Hc[size_t(j) * m + j], bb = Hc[size_t(j + 1) * m + j];
+                cplx a = Hc[size_t(jj) * m + jj], bb = Hc[size_t(jj + 1) * m + jj];
                 const double rr = std::sqrt(std::norm(a) + std::norm(bb));
                 if (rr == 0) {
-                    cs[c][j] = 1;
-                    sn[c][j] = 0;
+                    cs[c][jj] = 1;
+                    sn[c][jj] = 0;
                 } else if (std::abs(a) == 0) {
-                    cs[c][j] = 0;
-                    sn[c][j] = std::conj(bb) / rr;
+                    cs[c][jj] = 0;
+                    sn[c][jj] = std::conj(bb) / rr;
                 } else {
-                    cs[c][j] = std::abs(a) / rr;
-                    sn[c][j] = (a / std::abs(a)) * std::conj(bb) / rr;
+                    cs[c][jj] = std::abs(a) / rr;
+                    sn[c][jj] = (a / std::abs(a)) * std::conj(bb) / rr;
                 }
-                Hc[size_t(j) * m + j] = cs[c][j] * a + sn[c][j] * bb;
-                Hc[size_t(j + 1) * m + j] = 0;
-                g[c][j + 1] = -std::conj(sn[c][j]) * g[c][j];
-                g[c][j] = cs[c][j] * g[c][j];
-                res[c].relres = std::abs(g[c][j + 1]) / bnorm[c];
-                jc[c] = j + 1;
+                Hc[size_t(jj) * m + jj] = cs[c][jj] * a + sn[c][jj] * bb;
+                Hc[size_t(jj + 1) * m + jj] = 0;
+                g[c][jj + 1] = -std::conj(sn[c][jj]) * g[c][jj];
+                g[c][jj] = cs[c][jj] * g[c][jj];
+                res[c].relres = std::abs(g[c][jj + 1]) / bnorm[c];
+                jc[c] = jj + 1;
                 if (res[c].relres <= tol[c] || hn[c] == 0) res[c].converged = true;
             }
+            return IGB_OK;
+        };
+        int pend = -1;   // step enqueued, not yet processed
+        for (int j = 0;; ++j) {
+            // exact when nothing is pending; otherwise step j may run if some
+            // column takes part in the pending step
+            const bool enq = j < m && going(pend < 0 ? j : pend);
+            if (enq && (st = enqueue(j))) return st;
+            if (pend >= 0 && (st = process(pend))) return st;
+            if (!enq) break;
+            pend = j;
         }
         // X += V y per column (zeros beyond a column's own step count)
         int jmax = 0;
