@@ -853,8 +853,9 @@ def main():
     spmv_bytes = info.nnz * 16 + info.near_col_entries * 4 + n * 16 + 3 * n * 16
     spmv_avg = spmv_ms / max(spmv_n, 1) / 1e3
     # the roofline of the kernel that takes the most time per matvec
+    near_kernel = "spmv_groups<16>" if info.near_group_staged else "spmv_combine<1>"
     if spmv_n and spmv_avg > m2l_avg:
-        roof_kernel, roof_bytes, roof_avg = "spmv_combine<1>", spmv_bytes, spmv_avg
+        roof_kernel, roof_bytes, roof_avg = near_kernel, spmv_bytes, spmv_avg
     else:
         roof_kernel = "m2l_chunks_lowrank" if info.far_factor_entries else "m2l_chunks_wave"
         roof_bytes, roof_avg = m2l_bytes, m2l_avg
@@ -930,10 +931,10 @@ def main():
                                   "achieved_GBps": m2l_bytes / m2l_avg / 1e9 if m2l_n else None,
                                   "traffic": MEASURED_TRAFFIC.get(
                                       ("m2l_chunks_lowrank" if info.far_factor_entries else "m2l_chunks_wave", LD))},
-                     "near": {"kernel": "spmv_combine<1>", "bytes_per_launch": spmv_bytes,
+                     "near": {"kernel": near_kernel, "bytes_per_launch": spmv_bytes,
                               "avg_launch_ms": spmv_avg * 1e3,
                               "achieved_GBps": spmv_bytes / spmv_avg / 1e9 if spmv_n else None,
-                              "traffic": MEASURED_TRAFFIC.get(("spmv_combine<1>", LD))}},
+                              "traffic": MEASURED_TRAFFIC.get((near_kernel, LD))}},
     }
     if args.serve > 0:
         out["serving"] = serve_stream(args.serve, args.serve_rate)

@@ -108,7 +108,9 @@ typedef enum {
  *              h2_matvec uses with IGB_MV_LOWPREC; Arnoldi and residuals stay fp64,
  *              and so does the near field, except that IGB_MIX_BF16 keeps an fp32 copy
  *              that IGB_MV_LOWPREC products use (fp32 columns, products and row sums,
- *              on the matrix cores in tiles of rows over a common column list)
+ *              on the matrix cores in tiles of rows over a common column list), and
+ *              IGB_MIX_FP32 an fp64 copy in the same tiles that its IGB_MV_LOWPREC
+ *              products use (fp64 on the matrix cores, every block size)
  *   far_on_the_fly  0: the fp64 couplings are stored ((q+1)^4 complex per far pair,
  *              two for IGB_HARD); 1: none are stored and every fp64 far-field
  *              product (fp64 matvecs, refinement residuals) evaluates the kernel at
@@ -217,6 +219,10 @@ typedef struct {
     int64_t near_col_entries;   /* int32 column indices the one-column near product
                                    reads: one list per group of rows with the same
                                    leaves (the CSR's own indices are not read)      */
+    int64_t near_group_staged;  /* 1: the one-column near product stages each row
+                                   group's x entries in LDS (the longest list fits
+                                   the device's LDS per workgroup); 0: it gathers x
+                                   per nonzero                                      */
 } igb_op_info;
 
 /* ---------------------------------------------------------------- context */

@@ -305,8 +305,8 @@ static igb_status build_one(igb_ctx ctx, igb_geom g, const igb_op_params* prm, c
     // held during assembly only: the staged element blocks and the near pair lists
     const size_t transient = std::min<size_t>(op->near_src.size(), size_t(1) << 22) * nl * nl * 16 +
                              op->near_src.size() * 12 + (size_t(1) << 20);
-    // the near field in tiles: fp32 values (bf16 operators), fp64 values (fp64 operators)
-    if (op->nnz > 0 && prm->precision != IGB_MIX_FP32)
+    // the near field in tiles: fp32 values (bf16 operators), fp64 values (fp64 and fp32 operators)
+    if (op->nnz > 0)
         need += size_t(op->near_tile_vals) * (prm->precision == IGB_MIX_BF16 ? 8 : 16) +
                 op->near_tiles.size() * sizeof(NearTile) + op->near_tile_cols.size() * 4;
     if (prm->precision != IGB_FP64) {
@@ -501,6 +501,8 @@ igb_status igb_op_get_info(igb_op op, igb_op_info* info) {
     info->assembly_far_ms = op->t_assembly_far;
     info->far_factor_entries = op->lr_entries;
     info->near_col_entries = int64_t(op->near_dcol.size());
+    info->near_group_staged = !op->near_wgs.empty() &&
+                              size_t(op->near_list_max) * 16 <= size_t(op->geom->ctx->lds_max) ? 1 : 0;
     return IGB_OK;
 }
 

@@ -146,6 +146,7 @@ struct FarLevel {
 // chunk produces one partial result, summed per target in chunk order
 constexpr int M2L_CHUNK = 8;
 constexpr int M2L_CHUNK_MFMA = 16;
+constexpr int64_t M2L_MFMA_CHUNKS_MIN = 1024;
 struct M2LChunks {
     std::vector<int> tgt;       // global cluster index of the chunk's target
     std::vector<int64_t> pair;  // first pair of the chunk

@@ -131,21 +131,33 @@ __global__ __launch_bounds__(1024) void cnorm2_multi(const double2* w, int64_t n
     if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+// out[r] = ||w[r]||^2 and v[r][i] = w[r][i] / sqrt(out[r]) (0 for a zero
+// column), one workgroup per column: the next Arnoldi vector, normalised on the
+// device so that no scale factors travel per step (the norm's sums are those of
+// cnorm2_multi)
+__global__ __launch_bounds__(1024) void cnorm_scale(const double2* w, int64_t n, double* out, double2* v) {
+    __shared__ double red[1024];
+    const double2* x = w + int64_t(blockIdx.x) * n;
+    double acc = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) acc = fma(x[i].x, x[i].x, fma(x[i].y, x[i].y, acc));
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    const double q = red[0];
+    if (threadIdx.x == 0) out[blockIdx.x] = q;
+    const double f = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+    double2* y = v + int64_t(blockIdx.x) * n;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) y[i] = make_double2(x[i].x * f, x[i].y * f);
+}
+
 // v[r][i] = w[r][i] * sc[r]
 __global__ void cscale_multi(const double2* w, int64_t n, int C, const double* sc, double2* v) {
     const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gid >= n * C) return;
     const double f = sc[gid / n];
-    v[gid] = make_double2(w[gid].x * f, w[gid].y * f);
-}
-
-// v[r][i] = w[r][i] / sqrt(nrm2[r]) (0 for a zero column): the next Arnoldi
-// vector, normalised on the device so that no scale factors travel per step
-__global__ void cscale_by_norm(const double2* w, int64_t n, int C, const double* nrm2, double2* v) {
-    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (gid >= n * C) return;
-    const double q = nrm2[gid / n];
-    const double f = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
     v[gid] = make_double2(w[gid].x * f, w[gid].y * f);
 }
 
@@ -328,9 +340,7 @@ igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, 
             hipLaunchKernelGGL(cmaxpy_fin, dim3(gb64), dim3(64), hlds, s, V, jj + 1, n, C, Wk.part, Wk.nseg, Wk.h2, w);
             // ||w||^2 and the next basis vector on the device, then one copy of
             // the step's Hessenberg entries and norms to the host
-            hipLaunchKernelGGL(cnorm2_multi, dim3(C), dim3(1024), 0, s, w, n, Wk.nrm);
-            hipLaunchKernelGGL(cscale_by_norm, dim3(gb), dim3(256), 0, s, w, n, C, Wk.nrm,
-                               V + int64_t(jj + 1) * C * n);
+            hipLaunchKernelGGL(cnorm_scale, dim3(C), dim3(1024), 0, s, w, n, Wk.nrm, V + int64_t(jj + 1) * C * n);
             IGB_HIP(hipGetLastError());
             IGB_HIP(hipMemcpyAsync(Wk.hp[jj & 1], Wk.h, hcopy, hipMemcpyDeviceToHost, s));
             IGB_HIP(hipEventRecord(Wk.ev[jj & 1], s));

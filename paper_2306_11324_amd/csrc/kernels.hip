@@ -3186,8 +3186,10 @@ igb_status assemble_near_device(igb_op op, hipStream_t s) {
         else
             return hard ? near_launch<P, true>(op, s) : near_launch<P, false>(op, s);
     });
-    if (!st && op->prm.precision == IGB_FP64 && op->nnz > 0 && !op->near_tiles.empty()) {
-        // fp64 copy of the near field in the tile layout (blocks of >= 16 columns)
+    if (!st && (op->prm.precision == IGB_FP64 || op->prm.precision == IGB_MIX_FP32) && op->nnz > 0 &&
+        !op->near_tiles.empty()) {
+        // fp64 copy of the near field in the tile layout: fp64 operators' blocks of
+        // >= 16 columns, fp32 operators' reduced-precision products (every block size)
         const int64_t nt = int64_t(op->near_tiles.size());
         if ((st = upload(op->d_near_tiles, op->near_tiles.data(), op->near_tiles.size(), acct))) return st;
         if ((st = upload(op->d_near_tile_cols, op->near_tile_cols.data(), op->near_tile_cols.size(), acct))) return st;
@@ -3425,7 +3427,8 @@ WorkSizes work_sizes(const igb_op_s* op, int ncol) {
     }
     if (op->prm.precision == IGB_MIX_BF16 && op->nnz > 0)
         w.b[WorkSizes::XNEAR_LO] = (C + 15) / 16 * 16 * op->N * sizeof(float2);
-    if (op->prm.precision == IGB_FP64 && op->nnz > 0 && C >= size_t(MF64_MIN_COLS))
+    if (op->nnz > 0 && ((op->prm.precision == IGB_FP64 && C >= size_t(MF64_MIN_COLS)) ||
+                        op->prm.precision == IGB_MIX_FP32))
         w.b[WorkSizes::XNEAR64] = (C + 15) / 16 * 16 * op->N * sizeof(double2);
     w.b[WorkSizes::YFAR] = C * op->geom->n2 * sizeof(double2);
     w.b[WorkSizes::X2] = w.b[WorkSizes::YFAR];
@@ -3586,8 +3589,14 @@ static void launch_m2l_f64_soft(igb_op op, const MatvecWork& W, const double2* x
     if (nchunk > 0) {
         // NC column tiles per workgroup, NC dividing the padded tile count (the
         // last workgroup's tiles stay inside the rounded source vectors)
+        // (the widest grouping that keeps at least 2048 workgroups, 8 per CU)
         const int ntile = ncolp / 16;
-        const int nc = ntile % 4 == 0 ? 4 : ntile % 2 == 0 ? 2 : 1;
+        int nc = 1;
+        for (int c : {4, 2})
+            if (ntile % c == 0 && nchunk * (ntile / c) >= 2048) {
+                nc = c;
+                break;
+            }
         const dim3 grid(unsigned(nchunk), unsigned((ntile + nc - 1) / nc)), block(64 * ((nq + 15) / 16));
         const double2* cp = op->d_coupling.as<double2>();
         double2* pp = static_cast<double2*>(W.part_lo);
@@ -3923,16 +3932,8 @@ static igb_status matvec_launches(igb_op op, const MatvecWork& W, const double* 
                            op->d_near_tiles.as<NearTile>(), int64_t(op->near_tiles.size()),
                            op->d_near_tile_cols.as<int>(),
                            op->d_val_lo.as<float2>(), xt, N, yfar, g->n2, s0p, s0r, use_near, ncol, Y);
-    } else if (ncol == 1 && use_near && !op->near_wgs.empty() &&
-               size_t(op->near_list_max) * sizeof(double2) <= size_t(g->ctx->lds_max)) {
-        hipLaunchKernelGGL(spmv_groups<NEAR_GROUP_ROWS>, dim3(unsigned(op->near_wgs.size())),
-                           dim3(64 * NEAR_GROUP_ROWS), size_t(op->near_list_max) * sizeof(double2), s,
-                           op->d_near_wgs.as<NearGroupWG>(), op->d_near_grp_rows.as<int>(), rp, dcl, vl, X, yfar,
-                           g->n2, s0p, s0r, Y);
-    } else if (ncol == 1) {
-        hipLaunchKernelGGL(spmv_combine<1>, sg, sb, 0, s, rp, rco, dcl, vl, X, N, yfar, g->n2, s0p, s0r, use_near,
-                           ncol, Y);
-    } else if (ncol >= MF64_MIN_COLS && op->d_val64.ptr && W.xnear64) {
+    } else if (op->d_val64.ptr && W.xnear64 &&
+               (op->prm.precision == IGB_FP64 ? ncol >= MF64_MIN_COLS : low)) {
         // fp64 matrix cores over the tiles: columns transposed into 16-wide rows once
         const int ncb = (ncol + 15) / 16;
         if (use_near)
@@ -3962,6 +3963,15 @@ static igb_status matvec_launches(igb_op op, const MatvecWork& W, const double* 
         else
             hipLaunchKernelGGL(near_tiles_mfma64<1>, tg, tb, 0, s, tl, ntl, tcl, v64, W.xnear64, N, yfar, g->n2, s0p,
                                s0r, use_near, ncol, Y);
+    } else if (ncol == 1 && use_near && !op->near_wgs.empty() &&
+               size_t(op->near_list_max) * sizeof(double2) <= size_t(g->ctx->lds_max)) {
+        hipLaunchKernelGGL(spmv_groups<NEAR_GROUP_ROWS>, dim3(unsigned(op->near_wgs.size())),
+                           dim3(64 * NEAR_GROUP_ROWS), size_t(op->near_list_max) * sizeof(double2), s,
+                           op->d_near_wgs.as<NearGroupWG>(), op->d_near_grp_rows.as<int>(), rp, dcl, vl, X, yfar,
+                           g->n2, s0p, s0r, Y);
+    } else if (ncol == 1) {
+        hipLaunchKernelGGL(spmv_combine<1>, sg, sb, 0, s, rp, rco, dcl, vl, X, N, yfar, g->n2, s0p, s0r, use_near,
+                           ncol, Y);
     } else {
         hipLaunchKernelGGL(spmv_combine<4>, sg, sb, 0, s, rp, rco, dcl, vl, X, N, yfar, g->n2, s0p, s0r, use_near,
                            ncol, Y);

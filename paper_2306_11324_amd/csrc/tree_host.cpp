@@ -211,7 +211,12 @@ igb_status tree_build(igb_op op) {
     // M2L work decompositions: chunks of at most M2L_CHUNK (vector path) and
     // M2L_CHUNK_MFMA (matrix-core path) sources of one target
     build_chunks(op, M2L_CHUNK, op->chunks);
-    build_chunks(op, M2L_CHUNK_MFMA, op->chunks_mfma);
+    // (matrix-core chunks shrink, down to 2 sources, until there are about
+    // M2L_MFMA_CHUNKS_MIN of them: an operator with few far pairs otherwise
+    // leaves most CUs idle in its block products)
+    int chm = M2L_CHUNK_MFMA;
+    while (chm > 2 && op->nfar / chm < M2L_MFMA_CHUNKS_MIN) chm /= 2;
+    build_chunks(op, chm, op->chunks_mfma);
     return IGB_OK;
 }
 
