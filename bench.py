@@ -56,7 +56,8 @@ HBM_PEAK_GBS = 8000.0
 # make a plain 1 GiB device copy read and write 1 GiB), taken for the kernels
 # as they stand: profiles/matvec_kernels_sphere_m5_p2_k8_counters.md.  An
 # entry is removed whenever its kernel changes.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {("spmv_groups<16>", 3): 397.96e6, ("m2l_chunks_lowrank", 3): 148.10e6,
+                    ("fp64 16col", 3): 225.82e6, ("fp64 64col", 3): 554.67e6, ("bf16 16col", 3): 60.73e6}
 
 WORKLOADS = {
     # leaf depth and recompression are tuned per run (tune_leaf_depths x {tiles,

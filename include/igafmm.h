@@ -219,6 +219,10 @@ typedef struct {
     int64_t near_col_entries;   /* int32 column indices the one-column near product
                                    reads: one list per group of rows with the same
                                    leaves (the CSR's own indices are not read)      */
+    int64_t near_tile_entries;  /* complex entries of the near field in the tile
+                                   layout of the matrix-core near products (rows of a
+                                   tile share one column list; missing entries are
+                                   stored as zeros)                                 */
     int64_t near_group_staged;  /* 1: the one-column near product stages each row
                                    group's x entries in LDS (the longest list fits
                                    the device's LDS per workgroup); 0: it gathers x

@@ -66,7 +66,8 @@ class IgbOpInfo(C.Structure):
                 ("far_per_level", C.c_int64 * 16), ("near_elem_pairs", C.c_int64), ("nnz", C.c_int64),
                 ("device_bytes", C.c_int64), ("estimated_bytes", C.c_int64), ("assembly_near_ms", C.c_double),
                 ("assembly_far_ms", C.c_double), ("far_factor_entries", C.c_int64),
-                ("near_col_entries", C.c_int64), ("near_group_staged", C.c_int64)]
+                ("near_col_entries", C.c_int64), ("near_tile_entries", C.c_int64),
+                ("near_group_staged", C.c_int64)]
 
 
 _P = C.c_void_p

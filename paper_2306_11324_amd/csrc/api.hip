@@ -501,6 +501,7 @@ igb_status igb_op_get_info(igb_op op, igb_op_info* info) {
     info->assembly_far_ms = op->t_assembly_far;
     info->far_factor_entries = op->lr_entries;
     info->near_col_entries = int64_t(op->near_dcol.size());
+    info->near_tile_entries = int64_t(op->near_tile_vals);
     info->near_group_staged = !op->near_wgs.empty() &&
                               size_t(op->near_list_max) * 16 <= size_t(op->geom->ctx->lds_max) ? 1 : 0;
     return IGB_OK;
