@@ -345,6 +345,42 @@ def serve_stream(nreq, rate):
     return out
 
 
+def trace_overlap(path):
+    """Device overlap of a rocprofv3 kernel trace (its kernel_trace.csv): the
+    time at least one kernel runs (busy), the summed kernel durations, and the
+    share of busy time during which two or more kernels run, overall and for
+    the kernels of different queues (HIP streams map to hardware queues), so
+    that work of concurrent requests on their own streams shows as overlap."""
+    import csv
+    ev = []
+    for r in csv.DictReader(open(path)):
+        ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r.get("Queue_Id", "0")))
+    if not ev:
+        print(json.dumps({"error": "no kernels in the trace"}))
+        return
+    pts = sorted([(s0, 1, q) for s0, e0, q in ev] + [(e0, -1, q) for s0, e0, q in ev], key=lambda t: (t[0], t[1]))
+    busy = multi = cross = 0
+    running, per_q = 0, {}
+    last = pts[0][0]
+    for t, d, q in pts:
+        dt = t - last
+        if running >= 1:
+            busy += dt
+        if running >= 2:
+            multi += dt
+        if sum(1 for v in per_q.values() if v > 0) >= 2:
+            cross += dt
+        running += d
+        per_q[q] = per_q.get(q, 0) + d
+        last = t
+    summed = sum(e0 - s0 for s0, e0, q in ev)
+    span = max(e0 for s0, e0, q in ev) - min(s0 for s0, e0, q in ev)
+    print(json.dumps({"kernels": len(ev), "queues": len({q for _, _, q in ev}), "span_s": span / 1e9,
+                      "busy_s": busy / 1e9, "summed_kernel_s": summed / 1e9,
+                      "overlap_factor": summed / max(busy, 1), "busy_share_two_or_more": multi / max(busy, 1),
+                      "busy_share_two_or_more_queues": cross / max(busy, 1)}), flush=True)
+
+
 def kernels_only(reps=20):
     """The matvecs of the default workload alone, for counter runs (rocprofv3
     --pmc) and kernel traces: the headline operator's one-column product (tile
@@ -546,6 +582,10 @@ def main():
     ap.add_argument("--serve-capacity", type=float, default=None, help="skip the capacity run (requests/s)")
     ap.add_argument("--serve-fractions", default="0.4,0.6,0.8,1.0")
     ap.add_argument("--serve-main", type=int, default=200)
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the request stream (--serve requests at --serve-rate), e.g. under a kernel trace")
+    ap.add_argument("--trace-overlap", default=None,
+                    help="device overlap of a rocprofv3 kernel_trace.csv (no GPU)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
@@ -566,6 +606,12 @@ def main():
         return
     if args.kernels_only:
         kernels_only()
+        return
+    if args.trace_overlap:
+        trace_overlap(args.trace_overlap)
+        return
+    if args.serve_only:
+        print(json.dumps(serve_stream(args.serve, args.serve_rate)), flush=True)
         return
     if args.serve_study:
         fr = tuple(float(v) for v in args.serve_fractions.split(",")) if args.serve_fractions else ()
