@@ -56,14 +56,18 @@ HBM_PEAK_GBS = 8000.0
 # make a plain 1 GiB device copy read and write 1 GiB), taken for the kernels
 # as they stand: profiles/matvec_kernels_sphere_m5_p2_k8_counters.md.  An
 # entry is removed whenever its kernel changes.
-MEASURED_TRAFFIC = {("spmv_groups<16>", 3): 397.96e6, ("m2l_chunks_lowrank", 3): 148.10e6,
-                    ("fp64 16col", 3): 225.82e6, ("fp64 64col", 3): 554.67e6, ("bf16 16col", 3): 60.73e6}
+MEASURED_TRAFFIC = {("spmv_groups<16>", 3): 398.1e6, ("m2l_chunks_lowrank", 3): 148.1e6,
+                    ("fp64 16col", 3): 226.0e6, ("fp64 64col", 3): 554.4e6, ("bf16 16col", 3): 60.7e6,
+                    ("fp64 16col", 2): 2743.0e6, ("fp64 64col", 2): 5054.1e6, ("bf16 16col", 2): 644.8e6,
+                    ("fp32 16col", 2): 1281.7e6}
 
 WORKLOADS = {
     # leaf depth and recompression are tuned per run (tune_leaf_depths x {tiles,
-    # recompress_tol}); leaf_depth is the choice measured on MI355X, which the
+    # recompress_tol}); leaf_depth is the choice measured on MI355X and
+    # served_leaf_depth the one for served 16-column bf16 blocks, which the
     # kernel-only counter runs use
     "sphere_m5_p2_k8": dict(geometry="sphere", m=5, p=2, kappa=8.0, q=6, eta_adm=1.6, leaf_depth=3,
+                            served_leaf_depth=2,
                             tune_leaf_depths=(2, 3, 4), kcap=0.0, tol=1e-8, golden="sphere_m5_p2_k8_rows",
                             recompress_tol=1e-8),
     # the star configurations: one operator solving a block of directions
@@ -383,10 +387,12 @@ def trace_overlap(path):
 
 def kernels_only(reps=20):
     """The matvecs of the default workload alone, for counter runs (rocprofv3
-    --pmc) and kernel traces: the headline operator's one-column product (tile
-    factors), the fp64 blocks of 16 and 64 columns (matrix-core coupling and
-    near tiles), the bf16 block of 16 columns, then a plain 1 GiB device copy
-    (the counters' calibration)."""
+    --pmc) and kernel traces: at the headline's leaf depth the one-column
+    product (tile factors), the fp64 blocks of 16 and 64 columns (matrix-core
+    coupling and near tiles) and the bf16 block of 16 columns; at the served
+    blocks' leaf depth the fp64 blocks of 16 and 64 columns and the bf16 and
+    fp32 blocks of 16 columns; then a plain 1 GiB device copy (the counters'
+    calibration)."""
     import torch
 
     from paper_2306_11324_amd import binding as B
@@ -396,12 +402,22 @@ def kernels_only(reps=20):
     torch.cuda.init()
     ctx = B.Context(0)
     geo = B.Geometry(ctx, I.sphere_patches(), w["m"], w["p"])
-    kw = dict(kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"], kcap=w["kcap"], leaf_depth=w["leaf_depth"])
-    op = B.Operator(ctx, geo, recompress_tol=w["recompress_tol"], **kw)
-    lo = B.Operator(ctx, geo, precision=B.MIX_BF16, **kw)
-    for o, nc, parts, label in ((op, 1, B.PART_ALL, "fp64 1 column"), (op, 16, B.PART_ALL, "fp64 16 columns"),
-                                (op, 64, B.PART_ALL, "fp64 64 columns"),
-                                (lo, 16, B.PART_ALL | B.MV_LOWPREC, "bf16 16 columns")):
+    kw = dict(kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"], kcap=w["kcap"])
+    d1, d2 = w["leaf_depth"], w["served_leaf_depth"]
+    op = B.Operator(ctx, geo, recompress_tol=w["recompress_tol"], leaf_depth=d1, **kw)
+    lo = B.Operator(ctx, geo, precision=B.MIX_BF16, leaf_depth=d1, **kw)
+    runs = [(op, 1, B.PART_ALL, f"depth {d1}: fp64 1 column"), (op, 16, B.PART_ALL, f"depth {d1}: fp64 16 columns"),
+            (op, 64, B.PART_ALL, f"depth {d1}: fp64 64 columns"),
+            (lo, 16, B.PART_ALL | B.MV_LOWPREC, f"depth {d1}: bf16 16 columns")]
+    if d2 != d1:
+        op2 = B.Operator(ctx, geo, leaf_depth=d2, **kw)
+        lo2 = B.Operator(ctx, geo, precision=B.MIX_BF16, leaf_depth=d2, **kw)
+        f32 = B.Operator(ctx, geo, precision=B.MIX_FP32, leaf_depth=d2, **kw)
+        runs += [(op2, 16, B.PART_ALL, f"depth {d2}: fp64 16 columns"),
+                 (op2, 64, B.PART_ALL, f"depth {d2}: fp64 64 columns"),
+                 (lo2, 16, B.PART_ALL | B.MV_LOWPREC, f"depth {d2}: bf16 16 columns"),
+                 (f32, 16, B.PART_ALL | B.MV_LOWPREC, f"depth {d2}: fp32 16 columns")]
+    for o, nc, parts, label in runs:
         X = torch.from_numpy(I.random_complex(5, (nc, o.n))).to(dev)
         Y = torch.zeros_like(X)
         torch.cuda.synchronize()
@@ -827,11 +843,20 @@ def main():
         ref_coeff = None
         xb = torch.from_numpy(I.random_complex(777, (args.block, n))).to(dev)
         yb = torch.zeros_like(xb)
-        # the fp64 block runs on the headline operator, the mixed-precision ones on
-        # operators of the same shape
+        # the served blocks at the leaf depth the autotuner chose for served requests
+        # of 16 bf16 columns (assembly + 200 block matvecs), every precision alike;
+        # the fp64 block on the headline operator when the depths agree
+        ld_lo = tuned["bf16_16col"]["choice_leaf_depth"]
+        served["leaf_depth"] = ld_lo
+        op64 = op if ld_lo == LD else None
         for prec_name, prec in (("fp64", B.FP64), ("fp32", B.MIX_FP32), ("bf16", B.MIX_BF16)):
-            o = op if prec == B.FP64 else B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"],
-                                                      kcap=w["kcap"], leaf_depth=LD, precision=prec)
+            if prec == B.FP64 and op64 is not None:
+                o = op64
+            else:
+                o = B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"], kcap=w["kcap"],
+                               leaf_depth=ld_lo, precision=prec)
+                if prec == B.FP64:
+                    op64 = o
             r = run_solves(o, dirs_b, max(1, args.steps // 2), 1)
             c = r.pop("coeff").cpu().numpy()
             r.pop("uinf")
@@ -850,15 +875,28 @@ def main():
             served[f"{prec_name}_block{args.block}_graphs"] = {
                 "matvecs_per_s": rg["matvecs_per_s"], "solves_per_s": rg["solves_per_s"],
                 "ms_per_step": rg["ms_per_step"], "relres_true": rg["relres_true"]}
-            if o is not op:
+            if prec != B.FP64:
                 del o
             torch.cuda.empty_cache()
         # fp64 at 64 columns (the width of a 64-direction block): the coupling's
         # arithmetic intensity passes the fp64 ridge, the matrix-core roofline applies
         x64 = torch.from_numpy(I.random_complex(778, (64, n))).to(dev)
         y64 = torch.zeros_like(x64)
-        block_mv["fp64_64col"] = block_matvec(op, "fp64", x64, y64, max(5, args.matvecs // 5))
+        block_mv["fp64_64col"] = block_matvec(op64, "fp64", x64, y64, max(5, args.matvecs // 5))
+        if op64 is not op:
+            del op64
+        # the bf16 block at the headline's own shape
+        if ld_lo != LD:
+            ob = B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"], kcap=w["kcap"],
+                            leaf_depth=LD, precision=B.MIX_BF16)
+            r = run_solves(ob, dirs_b, max(1, args.steps // 2), 1)
+            r.pop("coeff"), r.pop("uinf"), r.pop("T")
+            r["speedup_matvecs_vs_plain_fp64"] = r["matvecs_per_s"] / value
+            r["leaf_depth"] = LD
+            served[f"bf16_block{args.block}_headline_shape"] = r
+            del ob
         del xb, yb, x64, y64
+        torch.cuda.empty_cache()
 
     # matvec-only loop with HIP-event kernel timing on the launch stream
     x = torch.from_numpy(I.random_complex(12345, n)).to(dev)

@@ -245,7 +245,7 @@ struct igb_op_s {
     igb::DevBuf d_far_src;
     // reduced-precision path: source vectors rounded per matvec, fp32 partials
     igb::DevBuf d_xlo, d_part_lo;
-    igb::DevBuf d_xhat, d_yhat, d_yraw, d_part, d_yfar, d_x2, d_cluoff, d_leafbuf, d_xnear64;
+    igb::DevBuf d_xhat, d_yhat, d_yraw, d_part, d_x2, d_cluoff, d_leafbuf, d_xnear64;
     size_t dev_bytes = 0;
     int64_t nclusters = 0;
     // solver scratch (kept between solves, grown on demand): Krylov basis and
@@ -328,7 +328,7 @@ igb_status assemble_far_device(igb_op op, hipStream_t s);
 igb_status alloc_work(igb_op op, int nrhs);
 // bytes of the matvec work buffers for ncol columns (alloc_work's sizes)
 struct WorkSizes {
-    enum { XHAT, YHAT, YRAW, PART, XLO, PART_LO, XNEAR_LO, YFAR, X2, LEAFBUF, XNEAR64, COUNT };
+    enum { XHAT, YHAT, YRAW, PART, XLO, PART_LO, XNEAR_LO, X2, LEAFBUF, XNEAR64, COUNT };
     size_t b[COUNT];
     size_t total() const {
         size_t t = 0;
@@ -343,7 +343,7 @@ struct MatvecWork {
     double2 *xhat = nullptr, *yhat = nullptr, *yraw = nullptr, *part = nullptr;
     void *xlo = nullptr, *part_lo = nullptr;
     float2* xnear_lo = nullptr;
-    double2 *yfar = nullptr, *x2 = nullptr, *leafbuf = nullptr;
+    double2 *x2 = nullptr, *leafbuf = nullptr;
     double2* xnear64 = nullptr;   // transposed fp64 columns of the tile near product
 };
 constexpr int SCRATCH_MAX_DEVICES = 64;

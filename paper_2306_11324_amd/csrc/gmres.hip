@@ -1,8 +1,8 @@
 // Restarted GMRES (Sec. 5.1: GMRES with restart 30 on the CFIE systems) on the
 // device, for one or many right-hand sides in lockstep.  Arnoldi with classical
 // Gram-Schmidt applied twice (CGS2); all vectors stay on the device, only the
-// new Hessenberg columns (<= restart+1 complex numbers per right-hand side) are
-// read back per iteration for the Givens rotations.
+// new Hessenberg columns (<= restart+1 complex numbers per right-hand side) go
+// to pinned host memory per iteration for the Givens rotations.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -184,8 +184,9 @@ struct Work {
     int m, C, nseg;
     double2 *V, *w, *r, *R, *D, *h, *h2, *y, *part;
     double *nrm, *sc;
-    double2* hp[2];      // pinned host copies of h, h2 and the squared norms (alternate steps)
-    hipEvent_t ev[2];    // the copy into hp[k] has landed
+    double2* hp[2];      // pinned coherent host buffers that the kernels of alternate steps write
+                         // h, h2 and the squared norms into
+    hipEvent_t ev[2];    // the step writing hp[k] has finished
 };
 
 struct SolveSizes {
@@ -245,7 +246,7 @@ igb_status ensure_work(igb_op op, int m, int C, Work& W) {
         if (op->h_pin) (void)hipHostFree(op->h_pin);
         op->h_pin = nullptr;
         op->h_pin_bytes = 0;
-        IGB_HIP(hipHostMalloc(&op->h_pin, 2 * need_h, hipHostMallocDefault));
+        IGB_HIP(hipHostMalloc(&op->h_pin, 2 * need_h, hipHostMallocCoherent));
         op->h_pin_bytes = 2 * need_h;
     }
     W.hp[0] = static_cast<double2*>(op->h_pin);
@@ -326,7 +327,6 @@ igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, 
                 if (in_cycle[c] && jc[c] == jj && active(c)) return true;
             return false;
         };
-        const size_t hcopy = size_t(2) * (m + 2) * C * sizeof(double2) + size_t(C) * sizeof(double);
         auto enqueue = [&](int jj) -> igb_status {
             igb_status st2;
             if ((st2 = matvec_device(op, reinterpret_cast<const double*>(V + int64_t(jj) * C * n),
@@ -335,14 +335,17 @@ igb_status gmres_block(igb_op op, const Work& Wk, const double2* B, double2* X, 
             // classical Gram-Schmidt, twice
             const size_t hlds = size_t(std::min<int64_t>(C, 63 / n + 2)) * (jj + 1) * sizeof(double2);
             hipLaunchKernelGGL(cdots_seg, dim3(jj + 1, Wk.nseg, C), dim3(RT), 0, s, V, n, C, Wk.nseg, w, Wk.part);
-            hipLaunchKernelGGL(cmaxpy_fin, dim3(gb64), dim3(64), hlds, s, V, jj + 1, n, C, Wk.part, Wk.nseg, Wk.h, w);
+            // the Hessenberg entries and the norm go straight into the step's pinned
+            // host buffer (device-visible, coherent): no copy per step
+            double2* hh = Wk.hp[jj & 1];
+            hipLaunchKernelGGL(cmaxpy_fin, dim3(gb64), dim3(64), hlds, s, V, jj + 1, n, C, Wk.part, Wk.nseg, hh, w);
             hipLaunchKernelGGL(cdots_seg, dim3(jj + 1, Wk.nseg, C), dim3(RT), 0, s, V, n, C, Wk.nseg, w, Wk.part);
-            hipLaunchKernelGGL(cmaxpy_fin, dim3(gb64), dim3(64), hlds, s, V, jj + 1, n, C, Wk.part, Wk.nseg, Wk.h2, w);
-            // ||w||^2 and the next basis vector on the device, then one copy of
-            // the step's Hessenberg entries and norms to the host
-            hipLaunchKernelGGL(cnorm_scale, dim3(C), dim3(1024), 0, s, w, n, Wk.nrm, V + int64_t(jj + 1) * C * n);
+            hipLaunchKernelGGL(cmaxpy_fin, dim3(gb64), dim3(64), hlds, s, V, jj + 1, n, C, Wk.part, Wk.nseg,
+                               hh + int64_t(m + 2) * C, w);
+            // ||w||^2 (to the host buffer) and the next basis vector on the device
+            hipLaunchKernelGGL(cnorm_scale, dim3(C), dim3(1024), 0, s, w, n,
+                               reinterpret_cast<double*>(hh + int64_t(2) * (m + 2) * C), V + int64_t(jj + 1) * C * n);
             IGB_HIP(hipGetLastError());
-            IGB_HIP(hipMemcpyAsync(Wk.hp[jj & 1], Wk.h, hcopy, hipMemcpyDeviceToHost, s));
             IGB_HIP(hipEventRecord(Wk.ev[jj & 1], s));
             return IGB_OK;
         };

@@ -792,18 +792,21 @@ static void launch_m2m_levels(const double* T1, int q, int L, int npatch, const 
                            lds, s, T1, q, l, clu_off[l], clu_off[l + 1], xh, ncol, cb);
 }
 
-// y[r][i] = sum over kinds and the leaves whose window contains i (fixed order)
-__global__ void leaf_gather(const double2* __restrict__ leafbuf, int d, int p, int L, int k, int npatch, int kinds,
-                            int ncol, double2* __restrict__ y) {
-    const int64_t n2 = int64_t(npatch) * k * k;
-    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (gid >= n2 * ncol) return;
-    const int64_t r = gid / n2, i = gid % n2;
-    const int patch = int(i / (int64_t(k) * k));
-    const int rem = int(i % (int64_t(k) * k));
-    const int iv = rem / k, iu = rem % k;
-    const int s = 1 << d, w = s + p, n = 1 << L;
-    const int64_t nleaf = int64_t(npatch) * n * n;
+// The far part of the product at S^2 index i and column r, gathered from the
+// leaf buffers of the downward pass: the sum over the leaves whose B-spline
+// windows hold i (and over the moment kinds), in a fixed order.  The near
+// kernels add it to each row after the row's near sum.
+struct FarLeaves {
+    const double2* leafbuf;   // null: no far part
+    int d, p, L, k, npatch, kinds, ncol;
+};
+__device__ __forceinline__ double2 far_value(const FarLeaves& F, int64_t i, int r) {
+    const int64_t kk = int64_t(F.k) * F.k;
+    const int patch = int(i / kk);
+    const int rem = int(i % kk);
+    const int iv = rem / F.k, iu = rem % F.k;
+    const int s = 1 << F.d, w = s + F.p, n = 1 << F.L;
+    const int64_t nleaf = int64_t(F.npatch) * n * n;
     double2 acc = make_double2(0, 0);
     const int cy0 = max(0, (iv - w + s) / s), cy1 = min(n - 1, iv / s);
     const int cx0 = max(0, (iu - w + s) / s), cx1 = min(n - 1, iu / s);
@@ -813,12 +816,12 @@ __global__ void leaf_gather(const double2* __restrict__ leafbuf, int d, int p, i
         for (int cx = cx0; cx <= cx1; ++cx) {
             const int lu = iu - cx * s;
             if (lu < 0 || lu >= w) continue;
-            const int64_t leaf = (int64_t(patch) << (2 * L)) + int64_t(cy) * n + cx;
-            for (int kd = 0; kd < kinds; ++kd)
-                acc = cadd(acc, leafbuf[((kd * nleaf + leaf) * ncol + r) * w * w + lv * w + lu]);
+            const int64_t leaf = (int64_t(patch) << (2 * F.L)) + int64_t(cy) * n + cx;
+            for (int kd = 0; kd < F.kinds; ++kd)
+                acc = cadd(acc, F.leafbuf[((kd * nleaf + leaf) * F.ncol + r) * w * w + lv * w + lu]);
         }
     }
-    y[gid] = acc;
+    return acc;
 }
 
 // storage types of the coupling tiles: fp64, fp32 or bf16 complex; products and
@@ -2118,8 +2121,7 @@ __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ 
                                                     const int* __restrict__ col,
                                                     const double2* __restrict__ val,
                                                     const double2* __restrict__ x, int64_t nrows,
-                                                    const double2* __restrict__ yfar, int64_t n2,
-                                                    const int* __restrict__ s0_ptr,
+                                                    FarLeaves F, const int* __restrict__ s0_ptr,
                                                     const int* __restrict__ s0_reps, int use_near, int ncol,
                                                     double2* __restrict__ y) {
     const int lane = threadIdx.x & 63;
@@ -2174,11 +2176,11 @@ __global__ __launch_bounds__(256) void spmv_combine(const int64_t* __restrict__ 
                 const int r = c0 + cb;
                 if (r >= ncol) continue;
                 double2 a = acc[cb];
-                if (yfar) {
+                if (F.leafbuf) {
                     if (s0_ptr) {
-                        for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q) a = cadd(a, yfar[r * n2 + s0_reps[q]]);
+                        for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q) a = cadd(a, far_value(F, s0_reps[q], r));
                     } else {
-                        a = cadd(a, yfar[r * n2 + row]);
+                        a = cadd(a, far_value(F, row, r));
                     }
                 }
                 y[int64_t(r) * nrows + row] = a;
@@ -2201,8 +2203,7 @@ __global__ __launch_bounds__(64 * NWV) void spmv_groups(const NearGroupWG* __res
                                                         const int* __restrict__ col,
                                                         const double2* __restrict__ val,
                                                         const double2* __restrict__ x,
-                                                        const double2* __restrict__ yfar, int64_t n2,
-                                                        const int* __restrict__ s0_ptr,
+                                                        FarLeaves F, const int* __restrict__ s0_ptr,
                                                         const int* __restrict__ s0_reps, double2* __restrict__ y) {
     extern __shared__ double2 xs[];
     // consecutive workgroups (the same or neighbouring groups) on one XCD
@@ -2231,11 +2232,11 @@ __global__ __launch_bounds__(64 * NWV) void spmv_groups(const NearGroupWG* __res
         acc.y += __shfl_xor(acc.y, off, 64);
     }
     if (lane == 0) {
-        if (yfar) {
+        if (F.leafbuf) {
             if (s0_ptr) {
-                for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q) acc = cadd(acc, yfar[s0_reps[q]]);
+                for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q) acc = cadd(acc, far_value(F, s0_reps[q], 0));
             } else {
-                acc = cadd(acc, yfar[row]);
+                acc = cadd(acc, far_value(F, row, 0));
             }
         }
         y[row] = acc;
@@ -2299,8 +2300,7 @@ constexpr int NEAR_TILE_WAVES = 16;
 __global__ __launch_bounds__(64 * NEAR_TILE_WAVES) void near_tiles_mfma(const NearTile* __restrict__ tiles, int64_t ntile,
                                                        const int* __restrict__ tcol, const float2* __restrict__ vt,
                                                        const float2* __restrict__ xt, int64_t nrows,
-                                                       const double2* __restrict__ yfar, int64_t n2,
-                                                       const int* __restrict__ s0_ptr,
+                                                       FarLeaves F, const int* __restrict__ s0_ptr,
                                                        const int* __restrict__ s0_reps, int use_near, int ncol,
                                                        double2* __restrict__ y) {
     constexpr int NW = NEAR_TILE_WAVES;
@@ -2372,11 +2372,11 @@ __global__ __launch_bounds__(64 * NEAR_TILE_WAVES) void near_tiles_mfma(const Ne
         if (i >= nr) continue;
         const int row = T.rows[i];
         double2 a = make_double2(double(acc0[r]), double(acc1[r]));
-        if (yfar) {
+        if (F.leafbuf) {
             if (s0_ptr) {
-                for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q) a = cadd(a, yfar[int64_t(c) * n2 + s0_reps[q]]);
+                for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q) a = cadd(a, far_value(F, s0_reps[q], c));
             } else {
-                a = cadd(a, yfar[int64_t(c) * n2 + row]);
+                a = cadd(a, far_value(F, row, c));
             }
         }
         y[int64_t(c) * nrows + row] = a;
@@ -2431,7 +2431,7 @@ constexpr int NEAR64_WAVES = 8;
 template <int NC>
 __global__ __launch_bounds__(64 * NEAR64_WAVES) void near_tiles_mfma64(
     const NearTile* __restrict__ tiles, int64_t ntile, const int* __restrict__ tcol, const double2* __restrict__ vt,
-    const double2* __restrict__ xt, int64_t nrows, const double2* __restrict__ yfar, int64_t n2,
+    const double2* __restrict__ xt, int64_t nrows, FarLeaves F,
     const int* __restrict__ s0_ptr, const int* __restrict__ s0_reps, int use_near, int ncol,
     double2* __restrict__ y) {
     constexpr int NW = NEAR64_WAVES, KB = MfmaF64::KB;
@@ -2514,12 +2514,12 @@ __global__ __launch_bounds__(64 * NEAR64_WAVES) void near_tiles_mfma64(
                     if (i >= nr) continue;
                     const int row = T.rows[i];
                     double2 a = make_double2(s0[r], s1[r]);
-                    if (yfar) {
+                    if (F.leafbuf) {
                         if (s0_ptr) {
                             for (int q = s0_ptr[row]; q < s0_ptr[row + 1]; ++q)
-                                a = cadd(a, yfar[int64_t(c) * n2 + s0_reps[q]]);
+                                a = cadd(a, far_value(F, s0_reps[q], c));
                         } else {
-                            a = cadd(a, yfar[int64_t(c) * n2 + row]);
+                            a = cadd(a, far_value(F, row, c));
                         }
                     }
                     y[int64_t(c) * nrows + row] = a;
@@ -3430,8 +3430,7 @@ WorkSizes work_sizes(const igb_op_s* op, int ncol) {
     if (op->nnz > 0 && ((op->prm.precision == IGB_FP64 && C >= size_t(MF64_MIN_COLS)) ||
                         op->prm.precision == IGB_MIX_FP32))
         w.b[WorkSizes::XNEAR64] = (C + 15) / 16 * 16 * op->N * sizeof(double2);
-    w.b[WorkSizes::YFAR] = C * op->geom->n2 * sizeof(double2);
-    w.b[WorkSizes::X2] = w.b[WorkSizes::YFAR];
+    w.b[WorkSizes::X2] = hard ? C * op->geom->n2 * sizeof(double2) : 0;   // S^0 -> S^2 copy of x
     const size_t win = (size_t(1) << op->d) + op->geom->p;
     w.b[WorkSizes::LEAFBUF] = C * kinds * clusters_on_level(op->geom->npatch, op->L) * win * win * sizeof(double2);
     return w;
@@ -3439,7 +3438,7 @@ WorkSizes work_sizes(const igb_op_s* op, int ncol) {
 
 static igb::DevBuf* work_buf(igb_op op, int i) {
     igb::DevBuf* bufs[WorkSizes::COUNT] = {&op->d_xhat, &op->d_yhat, &op->d_yraw,  &op->d_part, &op->d_xlo,
-                                           &op->d_part_lo, &op->d_xnear_lo, &op->d_yfar, &op->d_x2,
+                                           &op->d_part_lo, &op->d_xnear_lo, &op->d_x2,
                                            &op->d_leafbuf, &op->d_xnear64};
     return bufs[i];
 }
@@ -3712,7 +3711,6 @@ static MatvecWork own_work(igb_op op) {
     W.xlo = op->d_xlo.ptr;
     W.part_lo = op->d_part_lo.ptr;
     W.xnear_lo = op->d_xnear_lo.as<float2>();
-    W.yfar = op->d_yfar.as<double2>();
     W.x2 = op->d_x2.as<double2>();
     W.leafbuf = op->d_leafbuf.as<double2>();
     W.xnear64 = op->d_xnear64.as<double2>();
@@ -3784,7 +3782,6 @@ igb_status matvec_noalloc(igb_op op, const double* x, double* y, int ncol, int p
     W.xlo = at(WorkSizes::XLO);
     W.part_lo = at(WorkSizes::PART_LO);
     W.xnear_lo = static_cast<float2*>(at(WorkSizes::XNEAR_LO));
-    W.yfar = static_cast<double2*>(at(WorkSizes::YFAR));
     W.x2 = static_cast<double2*>(at(WorkSizes::X2));
     W.leafbuf = static_cast<double2*>(at(WorkSizes::LEAFBUF));
     W.xnear64 = static_cast<double2*>(at(WorkSizes::XNEAR64));
@@ -3906,13 +3903,11 @@ static igb_status matvec_launches(igb_op op, const MatvecWork& W, const double* 
                                (lo ? op->chunks_mfma : op->chunks).d_tgt_ptr.as<int>(), Tc, cof, m1, q, w, L, 0, 0,
                                stride_kind, ncol, dcb, lb);
         }
-        hipLaunchKernelGGL(leaf_gather, dim3(blocks_for(g->n2 * ncol, 256)), dim3(256), 0, s,
-                           W.leafbuf, op->d, g->p, L, g->k, g->npatch, kinds, ncol,
-                           W.yfar);
         if ((st = timer_mark(op, 3, s))) return st;
     }
     if ((st = timer_mark(op, 1, s))) return st;
-    const double2* yfar = far ? W.yfar : nullptr;
+    // the far part: gathered from the downward pass's leaf buffers by the near kernels
+    const FarLeaves yfar{far ? W.leafbuf : nullptr, op->d, g->p, op->L, g->k, g->npatch, hard ? 3 : 1, ncol};
     const int* s0p = hard ? op->d_s0_ptr.as<int>() : nullptr;
     const int* s0r = hard ? op->d_s0_reps.as<int>() : nullptr;
     const int use_near = (parts & IGB_PART_NEAR) ? 1 : 0;
@@ -3931,7 +3926,7 @@ static igb_status matvec_launches(igb_op op, const MatvecWork& W, const double* 
                            dim3(64 * NEAR_TILE_WAVES), 0, s,
                            op->d_near_tiles.as<NearTile>(), int64_t(op->near_tiles.size()),
                            op->d_near_tile_cols.as<int>(),
-                           op->d_val_lo.as<float2>(), xt, N, yfar, g->n2, s0p, s0r, use_near, ncol, Y);
+                           op->d_val_lo.as<float2>(), xt, N, yfar, s0p, s0r, use_near, ncol, Y);
     } else if (op->d_val64.ptr && W.xnear64 &&
                (op->prm.precision == IGB_FP64 ? ncol >= MF64_MIN_COLS : low)) {
         // fp64 matrix cores over the tiles: columns transposed into 16-wide rows once
@@ -3955,25 +3950,25 @@ static igb_status matvec_launches(igb_op op, const MatvecWork& W, const double* 
         const int* tcl = op->d_near_tile_cols.as<int>();
         const double2* v64 = op->d_val64.as<double2>();
         if (nct == 4)
-            hipLaunchKernelGGL(near_tiles_mfma64<4>, tg, tb, 0, s, tl, ntl, tcl, v64, W.xnear64, N, yfar, g->n2, s0p,
+            hipLaunchKernelGGL(near_tiles_mfma64<4>, tg, tb, 0, s, tl, ntl, tcl, v64, W.xnear64, N, yfar, s0p,
                                s0r, use_near, ncol, Y);
         else if (nct == 2)
-            hipLaunchKernelGGL(near_tiles_mfma64<2>, tg, tb, 0, s, tl, ntl, tcl, v64, W.xnear64, N, yfar, g->n2, s0p,
+            hipLaunchKernelGGL(near_tiles_mfma64<2>, tg, tb, 0, s, tl, ntl, tcl, v64, W.xnear64, N, yfar, s0p,
                                s0r, use_near, ncol, Y);
         else
-            hipLaunchKernelGGL(near_tiles_mfma64<1>, tg, tb, 0, s, tl, ntl, tcl, v64, W.xnear64, N, yfar, g->n2, s0p,
+            hipLaunchKernelGGL(near_tiles_mfma64<1>, tg, tb, 0, s, tl, ntl, tcl, v64, W.xnear64, N, yfar, s0p,
                                s0r, use_near, ncol, Y);
     } else if (ncol == 1 && use_near && !op->near_wgs.empty() &&
                size_t(op->near_list_max) * sizeof(double2) <= size_t(g->ctx->lds_max)) {
         hipLaunchKernelGGL(spmv_groups<NEAR_GROUP_ROWS>, dim3(unsigned(op->near_wgs.size())),
                            dim3(64 * NEAR_GROUP_ROWS), size_t(op->near_list_max) * sizeof(double2), s,
                            op->d_near_wgs.as<NearGroupWG>(), op->d_near_grp_rows.as<int>(), rp, dcl, vl, X, yfar,
-                           g->n2, s0p, s0r, Y);
+                           s0p, s0r, Y);
     } else if (ncol == 1) {
-        hipLaunchKernelGGL(spmv_combine<1>, sg, sb, 0, s, rp, rco, dcl, vl, X, N, yfar, g->n2, s0p, s0r, use_near,
+        hipLaunchKernelGGL(spmv_combine<1>, sg, sb, 0, s, rp, rco, dcl, vl, X, N, yfar, s0p, s0r, use_near,
                            ncol, Y);
     } else {
-        hipLaunchKernelGGL(spmv_combine<4>, sg, sb, 0, s, rp, rco, dcl, vl, X, N, yfar, g->n2, s0p, s0r, use_near,
+        hipLaunchKernelGGL(spmv_combine<4>, sg, sb, 0, s, rp, rco, dcl, vl, X, N, yfar, s0p, s0r, use_near,
                            ncol, Y);
     }
     IGB_HIP(hipGetLastError());

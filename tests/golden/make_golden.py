@@ -41,6 +41,12 @@ Cases
   sphere_m2_k1_operators  the single Galerkin matrices on the level-2 sphere,
                       kappa = 1, applied to the seeded vector: V and K* on S^2
                       (p = 1), K and the regularised W on S^0 (p = 2).
+  sphere_m5_p2_potential  the level-5 sphere (p = 2, 6144 elements), kappa = 3
+                      and 8, soft (S^2) and hard (S^0): the scattered field of
+                      seeded density coefficients at 160 seeded points in the
+                      shell 1.2 <= |x| <= 4 (representation formulas, tensor
+                      Gauss 10 x 10 per element; the points are at least four
+                      element sizes from the surface).
   star_m6_p2_k16_rows  seed-0 star, m = 6, p = 2, kappa = 16, soft: sampled rows
                       of the dense O1 matrix applied to the seeded vector.
   star_m7_p2_k32_hard_rows  seed-0 star, m = 7, p = 2, kappa = 32, hard (S^0):
@@ -189,6 +195,23 @@ def case_torus_k2p5_potential():
     return out
 
 
+POT_SEED = 2718
+
+
+def case_sphere_m5_p2_potential():
+    rng = np.random.default_rng(POT_SEED)
+    dirs = rng.normal(size=(160, 3))
+    pts = dirs / np.linalg.norm(dirs, axis=1, keepdims=True) * rng.uniform(1.2, 4.0, size=(160, 1))
+    out = {"pts": pts}
+    for bc in ("soft", "hard"):
+        for kappa in (3.0, 8.0):
+            bem = G.DenseBEM(I.sphere_patches(), p=2, m=5, kappa=kappa, bc=bc)
+            c = I.random_complex(X_SEED + 2, bem.n)
+            out[f"{bc}_c"] = c
+            out[f"{bc}_k{int(kappa)}_pot"] = bem.potential(c, pts)
+    return out
+
+
 def _star_rows(m, kappa, bc, nrows):
     bem = G.DenseBEM(I.star_patches(0, I.star_geometry_level(m)), p=2, m=m, kappa=kappa, bc=bc)
     x = I.random_complex(X_SEED, bem.n)
@@ -213,6 +236,7 @@ CASES = {
     "sphere_m2_p1_k1": case_sphere_m2_p1_k1,
     "sphere_m5_p2_k8_rows": case_sphere_m5_p2_k8_rows,
     "star_m6_p2_k16_rows": case_star_m6_p2_k16_rows,
+    "sphere_m5_p2_potential": case_sphere_m5_p2_potential,
     "sphere_m2_k1_potential": case_sphere_m2_k1_potential,
     "star_m7_p2_k32_hard_rows": case_star_m7_p2_k32_hard_rows,
     "torus_k2p5_potential": case_torus_k2p5_potential,

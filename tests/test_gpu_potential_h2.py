@@ -7,7 +7,9 @@ oracle and Mie is tested elsewhere:
     sphere, kappa = 3, q = 8, soft and hard, one and three columns;
   * a planar grid (a degenerate box direction) and a cylinder grid around the
     torus, kappa = 2.5;
-  * the level-2 sphere's 72 golden points against the Mie series.
+  * the level-2 sphere's 72 golden points against the Mie series;
+  * the level-5 sphere with seeded coefficients at 160 points against the
+    oracle's representation formulas (both evaluations, kappa = 3 and 8).
 """
 import os
 import sys
@@ -100,3 +102,28 @@ def test_h2_potential_against_mie_on_level2_sphere():
     e_mie = float(np.abs(uh[0] - G["soft_mie"]).max() / np.abs(G["soft_mie"]).max())
     print(f"72 points: H^2 vs direct {e_dir:.2e}, vs Mie {e_mie:.2e}", flush=True)
     assert e_dir < 1e-8 and e_mie < 1e-3
+
+
+@pytest.mark.parametrize("bc", ["soft", "hard"])
+@pytest.mark.parametrize("kappa,q", [(3.0, 8), (8.0, 6)])
+def test_potentials_match_oracle_at_size(bc, kappa, q):
+    """The level-5 sphere (6144 elements) with seeded density coefficients:
+    the direct summation and the H^2 evaluation against the oracle's
+    representation formulas at 160 seeded points in 1.2 <= |x| <= 4
+    (tests/golden/sphere_m5_p2_potential.npz), at kappa = 3 (q = 8) and at the
+    bench workload's kappa = 8 (q = 6)."""
+    from paper_2306_11324_amd import binding as B
+    from paper_2306_11324_amd import inputs as I
+    G = dict(np.load(os.path.join(GOLD, "sphere_m5_p2_potential.npz")))
+    print(f"case: sphere m=5 p=2 {bc} kappa={kappa} q={q}, 160 points, seeded coefficients", flush=True)
+    ctx = B.Context(0)
+    geo = B.Geometry(ctx, I.sphere_patches(), 5, 2)
+    op = B.Operator(ctx, geo, kappa=kappa, bc=B.SOFT if bc == "soft" else B.HARD, q=q, leaf_depth=2)
+    c = torch.from_numpy(G[f"{bc}_c"]).cuda().reshape(1, -1)
+    assert c.shape[1] == op.n
+    ud, uh = _both(op, c, G["pts"], 1)
+    ref = G[f"{bc}_k{int(kappa)}_pot"]
+    e_dir = float(np.abs(ud[0] - ref).max() / np.abs(ref).max())
+    e_h2 = float(np.abs(uh[0] - ref).max() / np.abs(ref).max())
+    print(f"direct vs oracle {e_dir:.2e}, H^2 vs oracle {e_h2:.2e}", flush=True)
+    assert e_dir < 1e-6 and e_h2 < 1e-5
