@@ -182,6 +182,14 @@ def large_workload(name, steps, warmup):
         del X, Y
         return dt, km
 
+    # the block kernels' tile shapes, tuned on this operator for the block width
+    tile_shape = None
+    if prec == B.FP64 and nd >= 32:
+        from paper_2306_11324_amd import autotune as AT
+        best_t, cand_t = AT.tune_tile_shape(op, nd, reps=3)
+        tile_shape = {"choice": {"coupling_col_tiles": best_t[0], "near_col_tiles": best_t[1]},
+                      "candidates": [{"coupling_col_tiles": a, "near_col_tiles": b, "matvec_ms": t}
+                                     for a, b, t in cand_t]}
     dt1, km1 = timed(1, B.PART_ALL, 5)
     dtb, kmb = timed(nd, B.PART_ALL | lowp, 5)
     nq2 = info.nq * info.nq
@@ -261,6 +269,7 @@ def large_workload(name, steps, warmup):
         "farfield_invariants": {"optical_theorem_max_rel": float(np.max(np.abs(lhs - rhs) / np.abs(rhs))),
                                 "reciprocity_max_rel": float(np.max(np.abs(back - back.T)) / np.max(np.abs(back)))},
         "roofline": roof,
+        "tile_shape": tile_shape,
     }
     print(json.dumps(out), flush=True)
 
@@ -882,19 +891,27 @@ def main():
         # arithmetic intensity passes the fp64 ridge, the matrix-core roofline applies
         x64 = torch.from_numpy(I.random_complex(778, (64, n))).to(dev)
         y64 = torch.zeros_like(x64)
+        best_t, cand_t = AT.tune_tile_shape(op64, 64, reps=5)
         block_mv["fp64_64col"] = block_matvec(op64, "fp64", x64, y64, max(5, args.matvecs // 5))
+        block_mv["fp64_64col"]["tile_shape"] = {
+            "choice": {"coupling_col_tiles": best_t[0], "near_col_tiles": best_t[1]},
+            "candidates": [{"coupling_col_tiles": a, "near_col_tiles": b, "matvec_ms": t} for a, b, t in cand_t]}
+        op64.set_tile_shape(0, 0)
         if op64 is not op:
             del op64
-        # the bf16 block at the headline's own shape
+        # the fp64 and bf16 blocks at the headline's own shape (assembly not counted)
         if ld_lo != LD:
-            ob = B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"], eta_adm=w["eta_adm"], kcap=w["kcap"],
-                            leaf_depth=LD, precision=B.MIX_BF16)
-            r = run_solves(ob, dirs_b, max(1, args.steps // 2), 1)
-            r.pop("coeff"), r.pop("uinf"), r.pop("T")
-            r["speedup_matvecs_vs_plain_fp64"] = r["matvecs_per_s"] / value
-            r["leaf_depth"] = LD
-            served[f"bf16_block{args.block}_headline_shape"] = r
-            del ob
+            for prec_name, prec in (("fp64", B.FP64), ("bf16", B.MIX_BF16)):
+                ob = op if prec == B.FP64 else B.Operator(ctx, geo, kappa=w["kappa"], q=w["q"],
+                                                          eta_adm=w["eta_adm"], kcap=w["kcap"], leaf_depth=LD,
+                                                          precision=prec)
+                r = run_solves(ob, dirs_b, max(1, args.steps // 2), 1)
+                r.pop("coeff"), r.pop("uinf"), r.pop("T")
+                r["speedup_matvecs_vs_plain_fp64"] = r["matvecs_per_s"] / value
+                r["leaf_depth"] = LD
+                served[f"{prec_name}_block{args.block}_headline_shape"] = r
+                if ob is not op:
+                    del ob
         del xb, yb, x64, y64
         torch.cuda.empty_cache()
 

@@ -322,6 +322,17 @@ igb_status igb_op_kernel_time(igb_op op, const char* name, int64_t* launches, do
  * operator's work buffers grow and when graphs are disabled. */
 igb_status igb_op_use_graphs(igb_op op, int enable);
 
+/* Tile shapes of the block kernels (a tuning knob; results do not change):
+ * coupling_col_tiles = 16-column tiles each workgroup of the fp64 matrix-core
+ * coupling carries (every tile value read serves that many column tiles),
+ * near_col_tiles = the same for the fp64 matrix-core near product; 1, 2 or 4,
+ * or 0 for the automatic choice (the widest that keeps at least 2048
+ * workgroups).  A value that does not divide a block's column tile count
+ * falls back to the automatic choice for that block.  Every column's result
+ * is bitwise the same for every shape.  Drops the operator's captured graphs.
+ * IGB_ERR_ARG for other values. */
+igb_status igb_op_set_tile_shape(igb_op op, int coupling_col_tiles, int near_col_tiles);
+
 #define IGB_PART_NEAR 1
 #define IGB_PART_FAR 2
 #define IGB_PART_ALL 3

@@ -142,3 +142,33 @@ def tune(ctx, geo, m: int, p: int, ncol: int, kappa: float, bc: int = B.SOFT, q:
     if cache is not None:
         cache.put(key, best)
     return best, measured
+
+
+def tune_tile_shape(op, ncol: int, reps: int = 10, parts: int | None = None):
+    """Kernel tile shapes of an fp64 operator's block product of ncol columns:
+    each (coupling, near) pair of column tiles per workgroup in {1, 2, 4}
+    that divides the block's 16-column tile count is set on the operator
+    (igb_op_set_tile_shape) and its block matvec timed; the fastest is left
+    set.  The shapes do not change any result.  Returns (choice, [(coupling,
+    near, ms)])."""
+    import torch
+    from . import inputs as I
+    ntile = (ncol + 15) // 16
+    shapes = [c for c in (1, 2, 4) if ntile % c == 0]
+    x = torch.from_numpy(I.random_complex(4322, (ncol, op.n))).cuda()
+    y = torch.zeros_like(x)
+    parts = B.PART_ALL if parts is None else parts
+    measured = []
+    for cc in shapes:
+        for nc in shapes:
+            op.set_tile_shape(cc, nc)
+            op.h2_matvec(x, y, nrhs=ncol, parts=parts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                op.h2_matvec(x, y, nrhs=ncol, parts=parts)
+            torch.cuda.synchronize()
+            measured.append((cc, nc, (time.perf_counter() - t0) / reps * 1e3))
+    best = min(measured, key=lambda t: t[2])
+    op.set_tile_shape(best[0], best[1])
+    return best, measured

@@ -98,6 +98,7 @@ _SIGS = {
     "potential_h2": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double), C.c_int, _P, _P]),
     "igb_op_profile": (C.c_int, [_P, C.c_int]),
     "igb_op_use_graphs": (C.c_int, [_P, C.c_int]),
+    "igb_op_set_tile_shape": (C.c_int, [_P, C.c_int, C.c_int]),
     "igb_op_kernel_time": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "igb_last_error": (C.c_char_p, []),
 }
@@ -265,6 +266,11 @@ class Operator:
     def use_graphs(self, enable: bool = True):
         """Capture the matvec into HIP graphs (single-threaded use; see the header)."""
         _check("igb_op_use_graphs", _lib.igb_op_use_graphs(self.h, 1 if enable else 0))
+
+    def set_tile_shape(self, coupling_col_tiles: int = 0, near_col_tiles: int = 0):
+        """Column tiles per workgroup of the fp64 block kernels (0: automatic)."""
+        _check("igb_op_set_tile_shape", _lib.igb_op_set_tile_shape(self.h, int(coupling_col_tiles),
+                                                                     int(near_col_tiles)))
 
     def kernel_time(self, name: str):
         """(launches, total ms) of the named kernel since the last query."""

@@ -600,6 +600,24 @@ igb_status igb_op_use_graphs(igb_op op, int enable) {
     return IGB_OK;
 }
 
+igb_status igb_op_set_tile_shape(igb_op op, int coupling_col_tiles, int near_col_tiles) {
+    if (!op) {
+        set_error("igb_op_set_tile_shape: NULL argument");
+        return IGB_ERR_ARG;
+    }
+    auto ok = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4; };
+    if (!ok(coupling_col_tiles) || !ok(near_col_tiles)) {
+        set_error("igb_op_set_tile_shape: column tiles must be 0, 1, 2 or 4 (got %d, %d)", coupling_col_tiles,
+                  near_col_tiles);
+        return IGB_ERR_ARG;
+    }
+    op->tile_m2l_nc = coupling_col_tiles;
+    op->tile_near_nct = near_col_tiles;
+    op->clear_graphs();
+    for (igb_op part : op->sum_parts) igb_op_set_tile_shape(part, coupling_col_tiles, near_col_tiles);
+    return IGB_OK;
+}
+
 igb_status igb_op_kernel_time(igb_op op, const char* name, int64_t* launches, double* total_ms) {
     if (!op || !name || !launches || !total_ms) {
         set_error("igb_op_kernel_time: NULL argument");

@@ -286,6 +286,8 @@ struct igb_op_s {
     };
     std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
     bool use_graphs = false;
+    // tile shapes of the fp64 block kernels (0: automatic)
+    int tile_m2l_nc = 0, tile_near_nct = 0;
     void clear_graphs() {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
         graphs.clear();

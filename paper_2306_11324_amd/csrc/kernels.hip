@@ -3596,6 +3596,7 @@ static void launch_m2l_f64_soft(igb_op op, const MatvecWork& W, const double2* x
                 nc = c;
                 break;
             }
+        if (op->tile_m2l_nc > 0 && ntile % op->tile_m2l_nc == 0) nc = op->tile_m2l_nc;   // tuned shape
         const dim3 grid(unsigned(nchunk), unsigned((ntile + nc - 1) / nc)), block(64 * ((nq + 15) / 16));
         const double2* cp = op->d_coupling.as<double2>();
         double2* pp = static_cast<double2*>(W.part_lo);
@@ -3944,6 +3945,7 @@ static igb_status matvec_launches(igb_op op, const MatvecWork& W, const double* 
                 nct = c;
                 break;
             }
+        if (op->tile_near_nct > 0 && ncb % op->tile_near_nct == 0) nct = op->tile_near_nct;   // tuned shape
         const dim3 tg(unsigned(op->near_tiles.size()), unsigned(ncb / nct)), tb(64 * NEAR64_WAVES);
         const NearTile* tl = op->d_near_tiles.as<NearTile>();
         const int64_t ntl = int64_t(op->near_tiles.size());

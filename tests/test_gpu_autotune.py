@@ -76,3 +76,35 @@ def test_require_far_skips_the_dense_shape():
                             require_far=True)
     assert {c.leaf_depth: c.far_pairs == 0 for c in measured} == {3: False, 4: True}
     assert best.leaf_depth == 3 and best.far_pairs > 0
+
+
+@pytest.mark.parametrize("bc", ["soft", "hard"])
+def test_tile_shapes_change_no_result_and_tuner_keeps_the_fastest(bc):
+    """Every coupling / near column-tile shape of a 64-column fp64 block gives
+    bitwise the automatic shape's result; the tuner leaves its fastest shape
+    set; shapes other than 0, 1, 2, 4 are rejected."""
+    from paper_2306_11324_amd import autotune as T
+    from paper_2306_11324_amd import binding as B
+    from paper_2306_11324_amd import inputs as I
+    print(f"case: sphere m=3 p=2 kappa=2 q=4 leaf depth 1 {bc} fp64, 64 columns, tile shapes", flush=True)
+    ctx = B.Context(0)
+    geo = B.Geometry(ctx, I.sphere_patches(), 3, 2)
+    op = B.Operator(ctx, geo, kappa=2.0, q=4, leaf_depth=1, bc=B.SOFT if bc == "soft" else B.HARD)
+    X = torch.from_numpy(I.random_complex(64, (64, op.n))).cuda()
+
+    def apply():
+        y = torch.zeros_like(X)
+        op.h2_matvec(X, y, nrhs=64)
+        torch.cuda.synchronize()
+        return y.cpu().numpy()
+
+    ref = apply()
+    for cc in (1, 2, 4):
+        for nc in (1, 2, 4):
+            op.set_tile_shape(cc, nc)
+            assert np.array_equal(apply(), ref), (cc, nc)
+    best, measured = T.tune_tile_shape(op, 64, reps=3)
+    assert len(measured) == 9 and best == min(measured, key=lambda t: t[2])
+    assert np.array_equal(apply(), ref)
+    with pytest.raises(B.IgbError):
+        op.set_tile_shape(3, 0)
