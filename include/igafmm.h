@@ -326,8 +326,8 @@ igb_status igb_op_use_graphs(igb_op op, int enable);
  * coupling_col_tiles = 16-column tiles each workgroup of the fp64 matrix-core
  * coupling carries (every tile value read serves that many column tiles),
  * near_col_tiles = the same for the fp64 matrix-core near product; 1, 2 or 4,
- * or 0 for the automatic choice (the widest that keeps at least 2048
- * workgroups).  A value that does not divide a block's column tile count
+ * or 0 for the automatic choice (coupling: the widest that keeps at least 512
+ * workgroups; near product: 2 where that keeps 512 workgroups, else 1).  A value that does not divide a block's column tile count
  * falls back to the automatic choice for that block.  Every column's result
  * is bitwise the same for every shape.  Drops the operator's captured graphs.
  * IGB_ERR_ARG for other values. */

@@ -3588,11 +3588,12 @@ static void launch_m2l_f64_soft(igb_op op, const MatvecWork& W, const double2* x
     if (nchunk > 0) {
         // NC column tiles per workgroup, NC dividing the padded tile count (the
         // last workgroup's tiles stay inside the rounded source vectors)
-        // (the widest grouping that keeps at least 2048 workgroups, 8 per CU)
+        // (the widest grouping that keeps at least 512 workgroups, 2 per CU: on
+        // the level-5 sphere the tuner's choice at 32 and 64 columns)
         const int ntile = ncolp / 16;
         int nc = 1;
         for (int c : {4, 2})
-            if (ntile % c == 0 && nchunk * (ntile / c) >= 2048) {
+            if (ntile % c == 0 && nchunk * (ntile / c) >= 512) {
                 nc = c;
                 break;
             }
@@ -3935,16 +3936,12 @@ static igb_status matvec_launches(igb_op op, const MatvecWork& W, const double* 
         if (use_near)
             hipLaunchKernelGGL(columns_t64, dim3(blocks_for(int64_t(ncb) * N * 16, 256)), dim3(256), 0, s, X, N,
                                ncol, ncb, W.xnear64);
-        // NC column tiles per workgroup (each tile value read serves 16 NC columns),
-        // NC dividing the column tile count, as long as the grid keeps at least
-        // 2048 workgroups (8 per CU); the column results do not depend on NC
+        // NC column tiles per workgroup (each tile value read serves 16 NC columns):
+        // 2 when it divides the column tile count and the grid keeps at least
+        // 512 workgroups (2 per CU), else 1 (4 measured slower on the level-5
+        // sphere and the level-6 star); the column results do not depend on NC
         const int64_t ntl0 = int64_t(op->near_tiles.size());
-        int nct = 1;
-        for (int c : {4, 2})
-            if (ncb % c == 0 && ntl0 * (ncb / c) >= 2048) {
-                nct = c;
-                break;
-            }
+        int nct = ncb % 2 == 0 && ntl0 * (ncb / 2) >= 512 ? 2 : 1;
         if (op->tile_near_nct > 0 && ncb % op->tile_near_nct == 0) nct = op->tile_near_nct;   // tuned shape
         const dim3 tg(unsigned(op->near_tiles.size()), unsigned(ncb / nct)), tb(64 * NEAR64_WAVES);
         const NearTile* tl = op->d_near_tiles.as<NearTile>();
