@@ -1184,11 +1184,15 @@ static inline bool mf_fp64(igb_op op) { return op->prm.precision == IGB_FP64 && 
 static inline size_t lo_slack(igb_op op) { return size_t(3) * op->nq * 16 + 256; }
 
 // Coupling of one chunk (consecutive far pairs of one target) for 16 columns
-// on the matrix cores: wave w owns output rows 16w..16w+15.  Soft: one tile,
-// one vector.  Hard: H acts on vectors {3, 0, 1, 2}, G on {0, 1, 2, 4, 5, 6},
-// giving the 10 partial vectors of the vector-path kernel in the same order.
-template <class OPS, bool HARD>
-__global__ __launch_bounds__(512) void m2l_mfma(const typename OPS::LT* __restrict__ coup, int nkc,
+// on the matrix cores: wave w owns the RPW output row tiles RPW w .. RPW w +
+// RPW - 1 (16 rows each), so the source fragments a wave loads per step serve
+// RPW row tiles.  Soft: one tile, one vector.  Hard: H acts on vectors
+// {3, 0, 1, 2}, G on {0, 1, 2, 4, 5, 6}, giving the 10 partial vectors of the
+// vector-path kernel in the same order.  Each output row's operations and
+// their order do not depend on RPW.
+constexpr int M2L_RPW = 3;   // row tiles per wave of m2l_mfma (fp32 / bf16)
+template <class OPS, bool HARD, int RPW = 1>
+__global__ __launch_bounds__(512 / RPW) void m2l_mfma(const typename OPS::LT* __restrict__ coup, int nkc,
                                                 const typename OPS::LT* __restrict__ xlo, int kbp, int ncolp,
                                                 const int* __restrict__ far_src_g,
                                                 const int64_t* __restrict__ chunk_pair,
@@ -1199,18 +1203,22 @@ __global__ __launch_bounds__(512) void m2l_mfma(const typename OPS::LT* __restri
     const int64_t ch = xcd_chunk(blockIdx.x, nchunk);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, g = lane >> 4;
-    // A row of this lane; rows past nq re-read the last row (their outputs are
+    // A rows of this lane; rows past nq re-read the last row (their outputs are
     // not stored, and an output row depends only on its own A row)
-    const int a = min(wave * 16 + li, nq - 1);
+    int a[RPW];
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) a[k] = min((wave * RPW + k) * 16 + li, nq - 1);
     const int c0 = blockIdx.y * 16;
     const int64_t p0 = chunk_pair[ch];
     const int len = chunk_len[ch];
     const int nkb = (nq + KB - 1) / KB;
     const int64_t tile_el = int64_t(nkc) * nq * EPL;
     using ACC = typename OPS::ACC;
-    ACC acc[NVO][2];
+    ACC acc[RPW][NVO][2];
 #pragma unroll
-    for (int v = 0; v < NVO; ++v) acc[v][0] = acc[v][1] = ACC{0, 0, 0, 0};
+    for (int k = 0; k < RPW; ++k)
+#pragma unroll
+        for (int v = 0; v < NVO; ++v) acc[k][v][0] = acc[k][v][1] = ACC{0, 0, 0, 0};
     // steps j = (pair i, k block kb) in order; KU steps issue their loads
     // before any of their products, so each wave keeps KU blocks in flight
     constexpr int KU = HARD ? 1 : 4;
@@ -1222,14 +1230,16 @@ __global__ __launch_bounds__(512) void m2l_mfma(const typename OPS::LT* __restri
     // addresses: a uniform part per step (scalar unit) plus a per-lane 32-bit
     // offset fixed for the whole kernel
     using LT = typename OPS::LT;
-    const unsigned offA = unsigned(a * EPL);
+    unsigned offA[RPW];
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) offA[k] = unsigned(a[k] * EPL);
     const unsigned offB = unsigned((g * ncolp + c0 + li) * EPL);
     // next step to load: pair ni, k block nkbi.  Past the last step the loads
     // repeat the last step's (in bounds, unused): every load is issued
     // unconditionally, so the compiler can wait for exactly the buffer a group
     // of products needs while the other buffer's loads stay in flight.
     int ni = 0, nkbi = 0;
-    auto load = [&](uint4 (&A)[KU][NT], uint4 (&X)[KU][NVS]) {
+    auto load = [&](uint4 (&A)[KU][RPW][NT], uint4 (&X)[KU][NVS]) {
 #pragma unroll
         for (int u = 0; u < KU; ++u) {
             const int i = ni, kb = nkbi;
@@ -1243,37 +1253,43 @@ __global__ __launch_bounds__(512) void m2l_mfma(const typename OPS::LT* __restri
             const LT* Au = coup + (p0 + i) * (NT * tile_el) + int64_t(kcg) * nq * EPL;
             const LT* Bu = xlo + int64_t(src) * (NVS * vstride) + kb * (4 * ncolp * EPL);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) A[u][t] = *reinterpret_cast<const uint4*>(Au + t * tile_el + offA);
+            for (int k = 0; k < RPW; ++k)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    A[u][k][t] = *reinterpret_cast<const uint4*>(Au + t * tile_el + offA[k]);
 #pragma unroll
             for (int v = 0; v < NVS; ++v) X[u][v] = *reinterpret_cast<const uint4*>(Bu + v * vstride + offB);
         }
     };
-    auto compute = [&](int j0, const uint4 (&A)[KU][NT], const uint4 (&X)[KU][NVS]) {
+    auto compute = [&](int j0, const uint4 (&A)[KU][RPW][NT], const uint4 (&X)[KU][NVS]) {
 #pragma unroll
         for (int u = 0; u < KU; ++u) {
             if (j0 + u >= nstep) break;
-            if constexpr (!HARD) {
-                acc[0][0] = OPS::step(A[u][0], OPS::re_part(X[u][0]), acc[0][0]);
-                acc[0][1] = OPS::step(A[u][0], OPS::im_part(X[u][0]), acc[0][1]);
-            } else {
-                constexpr int hv[4] = {3, 0, 1, 2};
-                constexpr int gv[6] = {0, 1, 2, 4, 5, 6};
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    acc[jj][0] = OPS::step(A[u][1], OPS::re_part(X[u][hv[jj]]), acc[jj][0]);
-                    acc[jj][1] = OPS::step(A[u][1], OPS::im_part(X[u][hv[jj]]), acc[jj][1]);
-                }
+            for (int k = 0; k < RPW; ++k) {
+                if constexpr (!HARD) {
+                    acc[k][0][0] = OPS::step(A[u][k][0], OPS::re_part(X[u][0]), acc[k][0][0]);
+                    acc[k][0][1] = OPS::step(A[u][k][0], OPS::im_part(X[u][0]), acc[k][0][1]);
+                } else {
+                    constexpr int hv[4] = {3, 0, 1, 2};
+                    constexpr int gv[6] = {0, 1, 2, 4, 5, 6};
 #pragma unroll
-                for (int jj = 0; jj < 6; ++jj) {
-                    acc[4 + jj][0] = OPS::step(A[u][0], OPS::re_part(X[u][gv[jj]]), acc[4 + jj][0]);
-                    acc[4 + jj][1] = OPS::step(A[u][0], OPS::im_part(X[u][gv[jj]]), acc[4 + jj][1]);
+                    for (int jj = 0; jj < 4; ++jj) {
+                        acc[k][jj][0] = OPS::step(A[u][k][1], OPS::re_part(X[u][hv[jj]]), acc[k][jj][0]);
+                        acc[k][jj][1] = OPS::step(A[u][k][1], OPS::im_part(X[u][hv[jj]]), acc[k][jj][1]);
+                    }
+#pragma unroll
+                    for (int jj = 0; jj < 6; ++jj) {
+                        acc[k][4 + jj][0] = OPS::step(A[u][k][0], OPS::re_part(X[u][gv[jj]]), acc[k][4 + jj][0]);
+                        acc[k][4 + jj][1] = OPS::step(A[u][k][0], OPS::im_part(X[u][gv[jj]]), acc[k][4 + jj][1]);
+                    }
                 }
             }
         }
     };
     // two register buffers: the next group's loads are in flight while the
     // current group's products run
-    uint4 A0[KU][NT], X0[KU][NVS], A1[KU][NT], X1[KU][NVS];
+    uint4 A0[KU][RPW][NT], X0[KU][NVS], A1[KU][RPW][NT], X1[KU][NVS];
     load(A0, X0);
     for (int j0 = 0; j0 < nstep; j0 += 2 * KU) {
         load(A1, X1);
@@ -1285,13 +1301,16 @@ __global__ __launch_bounds__(512) void m2l_mfma(const typename OPS::LT* __restri
     const int c = c0 + li;
     if (c >= ncol) return;
 #pragma unroll
-    for (int v = 0; v < NVO; ++v)
+    for (int k = 0; k < RPW; ++k)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int ar = wave * 16 + OPS::orow(g, r);
-            if (ar < nq)
-                part[((ch * NVO + v) * nq + ar) * ncol + c] = make_pt<typename OPS::PT>(acc[v][0][r], acc[v][1][r]);
-        }
+        for (int v = 0; v < NVO; ++v)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ar = (wave * RPW + k) * 16 + OPS::orow(g, r);
+                if (ar < nq)
+                    part[((ch * NVO + v) * nq + ar) * ncol + c] =
+                        make_pt<typename OPS::PT>(acc[k][v][0][r], acc[k][v][1][r]);
+            }
 }
 
 // fp64 sound-soft coupling for blocks of >= 16 columns on the fp64 matrix
@@ -3567,11 +3586,14 @@ static void launch_m2l_lo_t(igb_op op, const MatvecWork& W, const double2* xh, i
             default: IGB_SOFT_MT(8); break;
         }
 #undef IGB_SOFT_MT
-    } else if (nchunk > 0)
-        hipLaunchKernelGGL((m2l_mfma<OPS, HARD>), dim3(unsigned(nchunk), unsigned(ncolp / 16)),
-                           dim3(64 * ((nq + 15) / 16)), 0, s, cp, lo_nkc(op), static_cast<LT*>(W.xlo), kbp, ncolp,
-                           op->d_far_src.as<int>(), C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, nq, ncol,
-                           static_cast<PT*>(W.part_lo));
+    } else if (nchunk > 0) {
+        // fp64 accumulators are twice the size: one row tile per wave
+        constexpr int RPWO = std::is_same<OPS, MfmaF64>::value ? 1 : M2L_RPW;
+        hipLaunchKernelGGL((m2l_mfma<OPS, HARD, RPWO>), dim3(unsigned(nchunk), unsigned(ncolp / 16)),
+                           dim3(64 * (((nq + 15) / 16 + RPWO - 1) / RPWO)), 0, s, cp, lo_nkc(op),
+                           static_cast<LT*>(W.xlo), kbp, ncolp, op->d_far_src.as<int>(), C.d_pair.as<int64_t>(),
+                           C.d_len.as<int>(), nchunk, nq, ncol, static_cast<PT*>(W.part_lo));
+    }
     (void)timer_mark(op, 0, s);
 }
 
