@@ -428,14 +428,19 @@ igb_status potential(igb_op op, const double* coeffs, int ndir, const double* po
 
 /* The same scattered field evaluated with the H^2 structure of the operator
  * (Sec. 4.4's interpolation applied to the representation formula, Sec. 2):
- * the points are sorted into the boxes of an octree (at most 128 points each);
- * a source cluster admissible for a box (the operator's eta_adm, boxes of the
- * points and of the clusters' control points, and kappa * max(diam) at most
- * the operator's kcap, or q/2 if kcap is 0) acts through its moments on the
- * (q+1)^3 tensor Chebyshev nodes of the box, interpolated to the points; the
- * elements of the box's inadmissible leaf clusters are summed directly as in
- * potential().  Error against potential(): the interpolation error of q on
- * the box side and the cluster side.  Arguments, layout, ownership and errors
+ * the points are sorted into the boxes of an octree (at most 128 points each).
+ * A source cluster acts through its moments at its (q+1)^2 interpolation
+ * nodes when it is admissible for a box: distance at least the operator's
+ * eta_adm times the cluster's diameter (boxes of the points and of the
+ * cluster's control points) and kappa * diam at most the operator's kcap, or
+ * q/2 if kcap is 0.  Where the box holds more points than the (q+1)^3 tensor
+ * Chebyshev nodes of its own box, and the pair is admissible with the box's
+ * diameter too, the nodes' kernel values are summed on the box's nodes and
+ * interpolated to the points; otherwise they are summed at the points
+ * directly.  The elements of the box's inadmissible leaf clusters are summed
+ * directly as in potential().  Error against potential(): the interpolation
+ * error of q on the cluster side (and the box side where its nodes are
+ * used).  Arguments, layout, ownership and errors
  * as for potential(); the operator's matvec work buffers are used, so this
  * must not overlap other calls on the operator.  Synchronous. */
 igb_status potential_h2(igb_op op, const double* coeffs, int ndir, const double* points, int npts, double* u,

@@ -374,14 +374,18 @@ inline int aspect_boost(double a) { return (a >= 2.0) + (a >= 3.0) + (a >= 5.0);
 int smooth_order(igb_op op, int base);
 // H^2 evaluation of the scattered field at many points (host plan): points sorted
 // into target boxes of an octree (at most POT_LEAF_POINTS each), and per box the
-// admissible source clusters (far, interpolated on (q+1)^3 box nodes) and the
-// inadmissible leaf clusters (near, direct quadrature).
+// source clusters admissible for both sides (far, interpolated on (q+1)^3 box
+// nodes; taken only where the box holds more points than nodes), those
+// admissible for the source side (m2p: their interpolation nodes act on the
+// box's points directly) and the inadmissible leaf clusters (near, direct
+// quadrature).
 constexpr int POT_LEAF_POINTS = 128;
 struct PotentialPlan {
     std::vector<int> perm;                 // points by box: perm[i] = caller's index
     std::vector<int> box_ptr;              // [nbox+1] into perm
     std::vector<double> box_lo, box_hi;    // [nbox][3] interpolation boxes
-    std::vector<int> far_ptr, far_src;     // per box: global ids of admissible clusters
+    std::vector<int> far_ptr, far_src;     // per box: global ids of clusters interpolated on the box
+    std::vector<int> m2p_ptr, m2p_src;     // per box: global ids of clusters evaluated at the points
     std::vector<int> near_ptr, near_leaf;  // per box: leaf clusters (index on the leaf level)
 };
 igb_status potential_plan(igb_op op, const double* points, int npts, PotentialPlan& P);

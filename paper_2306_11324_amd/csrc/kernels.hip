@@ -2832,42 +2832,69 @@ __device__ double2 pot_l2p(const double* x, const double* lo, const double* hi, 
 }
 
 // H^2 potential, per point: the box expansion interpolated at the point (tensor
-// Lagrange on the box's Chebyshev nodes) plus direct quadrature over the
-// elements of the box's inadmissible leaf clusters, whose quadrature points are
-// staged in LDS a tile at a time and shared by the box's points.  One
-// workgroup per (box, column), one point per thread (more points in rounds).
-constexpr int POT_TILE = 256;   // quadrature points per LDS tile
+// Lagrange on the box's Chebyshev nodes), plus the interpolation nodes of the
+// clusters that act on the points directly (each node a source point carrying
+// the cluster's moment), plus direct quadrature over the elements of the box's
+// inadmissible leaf clusters.  Source points are staged in LDS a tile at a time
+// and shared by the box's points.  One workgroup per (box, column); a box of
+// few points gives each point a group of lanes (a power of two) that split
+// every tile and add their partial sums in a fixed order, so a column's result
+// does not depend on the others.
+constexpr int POT_TILE = 256;   // source points per LDS tile
 __global__ __launch_bounds__(POT_LEAF_POINTS) void pot_l2p_near(
     const double* __restrict__ pts, const int* __restrict__ perm, const int* __restrict__ box_ptr,
     const double* __restrict__ box_lo, const double* __restrict__ box_hi, const double* __restrict__ tch, int q,
-    const double2* __restrict__ lbox, int ncol, const int* __restrict__ near_ptr, const int* __restrict__ near_leaf,
-    int d, int L, int nel1, int nqp, const double* __restrict__ geo, const double2* __restrict__ dens, int64_t nqtot,
-    double kappa, int hard, int npt, double2* __restrict__ u) {
-    // the box expansion and the quadrature tiles share the LDS (one after the other)
+    const double2* __restrict__ lbox, int ncol, const int* __restrict__ m2p_ptr, const int* __restrict__ m2p_src,
+    const double* __restrict__ nodes, const double2* __restrict__ xh, const int* __restrict__ near_ptr,
+    const int* __restrict__ near_leaf, int d, int L, int nel1, int nqp, const double* __restrict__ geo,
+    const double2* __restrict__ dens, int64_t nqtot, double kappa, int hard, int npt, double2* __restrict__ u) {
+    // the box expansion, the source tiles and the partial sums share the LDS (one after the other)
     constexpr int LX = (QMAX + 1) * (QMAX + 1) * (QMAX + 1), TL = POT_TILE * 5;
+    static_assert(TL >= POT_LEAF_POINTS, "partial sums fit the tile space");
     __shared__ double2 smem[LX > TL ? LX : TL];
     double2* lx = smem;
     double(*tg)[8] = reinterpret_cast<double(*)[8]>(smem);     // [POT_TILE][8]
     double2* td = smem + POT_TILE * 4;                           // [POT_TILE]
     const int b = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
-    const int q1 = q + 1, n3 = q1 * q1 * q1;
+    const int q1 = q + 1, nq = q1 * q1, n3 = nq * q1;
     const bool has_far = lbox != nullptr;
     const double2* D = dens + int64_t(r) * nqtot;
     const int n = 1 << L, s = 1 << d, per_leaf = s * s * nqp;
     const int p0 = box_ptr[b], p1 = box_ptr[b + 1];
+    // lanes per point: the largest power of two gs with gs * points <= the workgroup
+    int gs = 1;
+    while (gs < POT_LEAF_POINTS && 2 * gs * (p1 - p0) <= POT_LEAF_POINTS) gs *= 2;
+    const int slot = tid / gs, lane = tid % gs, per_round = POT_LEAF_POINTS / gs;
+    const int f0 = m2p_ptr[b], nm2p = (m2p_ptr[b + 1] - f0) * nq;
     // (a box at the depth cap may hold more points than threads)
-    for (int base = p0; base < p1; base += POT_LEAF_POINTS) {
-        const int i = base + tid;
+    for (int base = p0; base < p1; base += per_round) {
+        const int i = base + slot;
         const bool mine = i < p1;
         const int pi = mine ? perm[i] : 0;
         const double x[3] = {pts[3 * pi], pts[3 * pi + 1], pts[3 * pi + 2]};
         double2 acc = make_double2(0, 0);
-        __syncthreads();   // the previous round's tiles consumed
+        __syncthreads();   // the previous round's tiles and partial sums consumed
         if (has_far) {
             for (int a = tid; a < n3; a += POT_LEAF_POINTS) lx[a] = lbox[(int64_t(b) * n3 + a) * ncol + r];
             __syncthreads();
-            if (mine) acc = pot_l2p(x, box_lo + 3 * b, box_hi + 3 * b, tch, q, lx);
+            if (mine && lane == 0) acc = pot_l2p(x, box_lo + 3 * b, box_hi + 3 * b, tch, q, lx);
             __syncthreads();   // lx consumed before the tiles overwrite it
+        }
+        // cluster nodes evaluated at the points: position, n~, a, weight 1, the moment as density
+        for (int t0 = 0; t0 < nm2p; t0 += POT_TILE) {
+            const int cnt = min(POT_TILE, nm2p - t0);
+            for (int k = tid; k < cnt; k += POT_LEAF_POINTS) {
+                const int64_t sc = m2p_src[f0 + (t0 + k) / nq];
+                const int64_t ni = sc * nq + (t0 + k) % nq;
+#pragma unroll
+                for (int c = 0; c < 7; ++c) tg[k][c] = nodes[ni * 16 + c];
+                tg[k][7] = 1.0;
+                td[k] = xh[ni * ncol + r];
+            }
+            __syncthreads();
+            if (mine)
+                for (int k = lane; k < cnt; k += gs) acc = cfma(repr_kernel(x, tg[k], kappa, hard), td[k], acc);
+            __syncthreads();
         }
         for (int f = near_ptr[b]; f < near_ptr[b + 1]; ++f) {
             const int64_t loc = near_leaf[f];
@@ -2885,11 +2912,20 @@ __global__ __launch_bounds__(POT_LEAF_POINTS) void pot_l2p_near(
                 }
                 __syncthreads();
                 if (mine)
-                    for (int k = 0; k < cnt; ++k) acc = cfma(repr_kernel(x, tg[k], kappa, hard), td[k], acc);
+                    for (int k = lane; k < cnt; k += gs) acc = cfma(repr_kernel(x, tg[k], kappa, hard), td[k], acc);
                 __syncthreads();
             }
         }
-        if (mine) u[int64_t(r) * npt + pi] = acc;
+        if (gs == 1) {
+            if (mine) u[int64_t(r) * npt + pi] = acc;
+        } else {
+            smem[tid] = acc;
+            __syncthreads();
+            if (mine && lane == 0) {
+                for (int l = 1; l < gs; ++l) acc = cadd(acc, smem[tid + l]);
+                u[int64_t(r) * npt + pi] = acc;
+            }
+        }
     }
 }
 
@@ -4186,7 +4222,8 @@ igb_status potential_h2_device(igb_op op, const double* coeffs, int ndir, const 
     // boundary density and geometry at the quadrature points (near part)
     const int nqd = smooth_order(op, 8);
     const int64_t nqtot = g->nelem * nqd * nqd;
-    DevBuf d_gl, d_geo, d_dens, d_pts, d_perm, d_bptr, d_blo, d_bhi, d_tch, d_fptr, d_fsrc, d_nptr, d_nleaf, d_lbox;
+    DevBuf d_gl, d_geo, d_dens, d_pts, d_perm, d_bptr, d_blo, d_bhi, d_tch, d_fptr, d_fsrc, d_mptr, d_msrc, d_nptr, d_nleaf,
+        d_lbox;
     std::vector<double> gl = gauss_table();
     if ((st = upload(d_gl, gl.data(), gl.size(), nullptr))) return st;
     if ((st = alloc(d_geo, size_t(nqtot) * 8 * sizeof(double), nullptr))) return st;
@@ -4209,9 +4246,11 @@ igb_status potential_h2_device(igb_op op, const double* coeffs, int ndir, const 
         (st = upload(d_bhi, P.box_hi.data(), P.box_hi.size(), nullptr)) ||
         (st = upload(d_tch, t.data(), t.size(), nullptr)) ||
         (st = upload(d_fptr, P.far_ptr.data(), P.far_ptr.size(), nullptr)) ||
-        (st = upload(d_nptr, P.near_ptr.data(), P.near_ptr.size(), nullptr)))
+        (st = upload(d_nptr, P.near_ptr.data(), P.near_ptr.size(), nullptr)) ||
+        (st = upload(d_mptr, P.m2p_ptr.data(), P.m2p_ptr.size(), nullptr)))
         return st;
     if (!P.far_src.empty() && (st = upload(d_fsrc, P.far_src.data(), P.far_src.size(), nullptr))) return st;
+    if (!P.m2p_src.empty() && (st = upload(d_msrc, P.m2p_src.data(), P.m2p_src.size(), nullptr))) return st;
     if (!P.near_leaf.empty() && (st = upload(d_nleaf, P.near_leaf.data(), P.near_leaf.size(), nullptr))) return st;
     const bool any_far = !P.far_src.empty();
     if (any_far) {
@@ -4224,9 +4263,10 @@ igb_status potential_h2_device(igb_op op, const double* coeffs, int ndir, const 
     }
     hipLaunchKernelGGL(pot_l2p_near, dim3(unsigned(nbox), unsigned(ndir)), dim3(POT_LEAF_POINTS), 0, s,
                        d_pts.as<double>(), d_perm.as<int>(), d_bptr.as<int>(), d_blo.as<double>(), d_bhi.as<double>(),
-                       d_tch.as<double>(), q, any_far ? d_lbox.as<double2>() : nullptr, ndir, d_nptr.as<int>(),
-                       d_nleaf.as<int>(), sp->d, L, g->nel1, nqd * nqd, d_geo.as<double>(), d_dens.as<double2>(),
-                       nqtot, op->kappa, hard ? 1 : 0, npt, reinterpret_cast<double2*>(u));
+                       d_tch.as<double>(), q, any_far ? d_lbox.as<double2>() : nullptr, ndir, d_mptr.as<int>(),
+                       d_msrc.as<int>(), sp->d_nodes.as<double>(), xh, d_nptr.as<int>(), d_nleaf.as<int>(), sp->d, L,
+                       g->nel1, nqd * nqd, d_geo.as<double>(), d_dens.as<double2>(), nqtot, op->kappa, hard ? 1 : 0,
+                       npt, reinterpret_cast<double2*>(u));
     IGB_HIP(hipGetLastError());
     IGB_HIP(hipStreamSynchronize(s));   // temporaries are freed on return
     return IGB_OK;

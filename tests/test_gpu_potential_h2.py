@@ -1,7 +1,8 @@
 """Scattered field through the H^2 structure (potential_h2: octree boxes of
-the points, far clusters interpolated on (q+1)^3 box nodes, near leaves summed
-directly) against the direct summation (potential), whose own parity with the
-oracle and Mie is tested elsewhere:
+the points; admissible clusters act through their interpolation nodes, summed
+at the points or, for boxes with more points than (q+1)^3, on the box's
+Chebyshev nodes; near leaves summed directly) against the direct summation
+(potential), whose own parity with the oracle and Mie is tested elsewhere:
 
   * a seeded shell of 200,000 points (1.2 <= |x| <= 4) around the level-5
     sphere, kappa = 3, q = 8, soft and hard, one and three columns;
@@ -9,7 +10,9 @@ oracle and Mie is tested elsewhere:
     torus, kappa = 2.5;
   * the level-2 sphere's 72 golden points against the Mie series;
   * the level-5 sphere with seeded coefficients at 160 points against the
-    oracle's representation formulas (both evaluations, kappa = 3 and 8).
+    oracle's representation formulas (both evaluations, kappa = 3 and 8);
+  * a grid of 125-point boxes beside the level-4 sphere at q = 3 (box nodes)
+    and q = 4 (cluster nodes at the points).
 """
 import os
 import sys
@@ -127,3 +130,26 @@ def test_potentials_match_oracle_at_size(bc, kappa, q):
     e_h2 = float(np.abs(uh[0] - ref).max() / np.abs(ref).max())
     print(f"direct vs oracle {e_dir:.2e}, H^2 vs oracle {e_h2:.2e}", flush=True)
     assert e_dir < 1e-6 and e_h2 < 1e-5
+
+
+@pytest.mark.parametrize("q", [3, 4])
+def test_box_interpolation_and_cluster_nodes_on_a_grid(q):
+    """A 20 x 20 x 20 grid in a unit cube beside the level-4 sphere splits into
+    octree boxes of 5 x 5 x 5 = 125 points: at q = 3 a box holds more points
+    than its (q+1)^3 = 64 nodes, so admissible clusters act through the box's
+    nodes (two-sided interpolation); at q = 4 (125 nodes) they act on the
+    points through the cluster's nodes alone.  Both against the direct sum."""
+    from paper_2306_11324_amd import binding as B
+    from paper_2306_11324_amd import inputs as I
+    print(f"case: sphere m=4 p=2 kappa=1 q={q} leaf depth 1 soft, 8000 grid points in [2, 3] x [-0.5, 0.5]^2",
+          flush=True)
+    ctx = B.Context(0)
+    geo = B.Geometry(ctx, I.sphere_patches(), 4, 2)
+    op = B.Operator(ctx, geo, kappa=1.0, q=q, leaf_depth=1)
+    c = _solve(op, np.array([[1.0, 0.0, 0.0]]))
+    g = np.linspace(0.0, 1.0, 20)
+    pts = np.stack(np.meshgrid(g + 2.0, g - 0.5, g - 0.5, indexing="ij"), -1).reshape(-1, 3)
+    ud, uh = _both(op, c, pts, 1)
+    e = float(np.abs(uh - ud).max() / np.abs(ud).max())
+    print(f"H^2 vs direct {e:.2e}", flush=True)
+    assert e < {3: 3e-4, 4: 3e-5}[q]
