@@ -345,9 +345,11 @@ igb_status igb_op_set_tile_shape(igb_op op, int coupling_col_tiles, int near_col
  * near-field (incl. 1/2 M) and/or far-field (H^2) contributions.  The columns
  * share every pass over the couplings and the near-field matrix.  Batch
  * invariance: a column's result does not depend on the other columns, with one
- * exception -- IGB_FP64 operators with stored couplings run the coupling of
- * blocks of 16 or more columns on the fp64 matrix cores, which sum the same
- * products in another order than the single-column vector kernels.  Results of
+ * exception -- IGB_FP64 operators with stored couplings, and the fp64 far field
+ * of sound-hard operators evaluated on the fly (far_on_the_fly, any precision),
+ * run the coupling of blocks of 16 or more columns on the fp64 matrix cores,
+ * which sum the same products in another order than the single-column vector
+ * kernels.  Results of
  * blocks of 1..15 columns are bitwise equal to single-column results, results of
  * blocks of >= 16 columns bitwise equal to those of any other block of >= 16,
  * and the two differ by rounding (<= 1e-12 relative to max|y| of the column;
@@ -393,7 +395,8 @@ igb_status cfie_rhs(igb_op op, const double* dirs, int ndir, double* b, void* hi
  * test, so a column's solution does not depend on the other columns (with the
  * exceptions stated at h2_matvec: IGB_FP64 operators with stored couplings solve
  * ndir >= 16 with matrix-core couplings, whose iterates differ from those of
- * smaller batches by rounding, and recompressed operators solve one direction
+ * smaller batches by rounding, as do the fp64 residuals of sound-hard
+ * operators with the far field on the fly, and recompressed operators solve one direction
  * with the tile factors and several with the tiles; within each range the
  * iterates agree bitwise).
  * Operators with IGB_MIX_* precision solve by iterative refinement:

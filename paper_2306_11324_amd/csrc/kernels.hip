@@ -1173,6 +1173,8 @@ static inline int lo_epl(igb_op op) {
 }
 static inline int lo_nkc(igb_op op) { return (op->nq + lo_epl(op) - 1) / lo_epl(op); }
 static inline int lo_kbp(igb_op op) { return (op->nq + lo_kb(op) - 1) / lo_kb(op) * lo_kb(op); }
+// k extent of the fp64 matrix-core source vectors (the on-the-fly coupling's)
+static inline int kbp_f64(int nq) { return (nq + MfmaF64::KB - 1) / MfmaF64::KB * MfmaF64::KB; }
 static inline size_t lo_esz(igb_op op) {
     return op->prm.precision == IGB_MIX_FP32 ? sizeof(float2)
                                               : op->prm.precision == IGB_MIX_BF16 ? sizeof(bf16x2) : sizeof(double2);
@@ -1634,6 +1636,106 @@ __global__ __launch_bounds__(NT) void m2l_otf_hard(const double* __restrict__ no
             for (int v = 0; v < 4; ++v) part[((ch * 10 + v) * nq + a) * ncol + c0 + cb] = rh[v][cb];
 #pragma unroll
             for (int v = 0; v < 6; ++v) part[((ch * 10 + 4 + v) * nq + a) * ncol + c0 + cb] = rg[v][cb];
+        }
+}
+
+// fp64 sound-hard coupling without stored tiles for blocks of >= 16 columns
+// on the fp64 matrix cores.  Per pair, the G and H values of SLAB source nodes
+// at a time are evaluated at every target node into LDS together with the
+// slab's source vectors (16 columns, from round_vectors), and wave w
+// multiplies target rows 16w..16w+15 as the stored-tile kernel does (H on
+// vectors {3, 0, 1, 2}, G on {0, 1, 2, 4, 5, 6}: the vector-path kernel's 10
+// partials in its order).  Two LDS buffers: each thread evaluates the next
+// slab while the matrix cores work through the current one; one barrier per
+// slab.  Every output sums the chunk's pairs and their source nodes in order,
+// so a column's result does not depend on the other columns.  Target rows
+// past nq evaluate the last row (their outputs are not stored).
+template <int NW, int SLAB>
+__global__ __launch_bounds__(64 * NW) void m2l_otf_mfma_hard(
+    const double* __restrict__ nodes, const double2* __restrict__ xv, int kbp, int ncolp,
+    const int* __restrict__ far_src_g, const int* __restrict__ chunk_tgt, const int64_t* __restrict__ chunk_pair,
+    const int* __restrict__ chunk_len, int64_t nchunk, int nq, int ncol, double kappa, double2* __restrict__ part) {
+    constexpr int R = 16 * NW, NT = 64 * NW, EB = NT / R, KS = SLAB / 4;
+    static_assert(SLAB % 4 == 0 && SLAB % EB == 0, "a slab is whole k blocks and evaluation passes");
+    __shared__ double2 gh[2][2][SLAB][R];    // [buffer][G, H][source node in slab][target row]
+    __shared__ double2 vs[2][7][SLAB][16];   // [buffer][source vector][source node in slab][column]
+    const int64_t ch = xcd_chunk(blockIdx.x, nchunk);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, g = lane >> 4;
+    const int c0 = blockIdx.y * 16;
+    const int64_t p0 = chunk_pair[ch];
+    const int len = chunk_len[ch];
+    const int nkb = (nq + 3) / 4, nsl = (nq + SLAB - 1) / SLAB, nstep = len * nsl;
+    // evaluation: fixed target row, source nodes eb0, eb0 + EB, ... of each slab
+    const int ea = tid % R, eb0 = tid / R;
+    double X[3];
+    {
+        const double* T = nodes + (int64_t(chunk_tgt[ch]) * nq + min(ea, nq - 1)) * 16;
+        X[0] = T[0];
+        X[1] = T[1];
+        X[2] = T[2];
+    }
+    const int64_t vstride = int64_t(kbp) * ncolp;
+    auto stage = [&](int j, int bf) {
+        const int i = j / nsl, sl = j % nsl;
+        const int64_t src = far_src_g[p0 + i];
+        const double* Y = nodes + src * nq * 16;
+#pragma unroll
+        for (int e = eb0; e < SLAB; e += EB) {
+            const int b = sl * SLAB + e;
+            double2 G = make_double2(0, 0), H = G;
+            if (b < nq) kernel_gh(X, Y + b * 16, kappa, G, H);
+            gh[bf][0][e][ea] = G;
+            gh[bf][1][e][ea] = H;
+        }
+        // the source vectors are zero past nq up to kbp; slab nodes past kbp are not read
+        for (int e = tid; e < 7 * SLAB * 16; e += NT) {
+            const int c = e % 16, b = (e / 16) % SLAB, v = e / (16 * SLAB), bb = sl * SLAB + b;
+            vs[bf][v][b][c] = bb < kbp ? xv[(src * 7 + v) * vstride + int64_t(bb) * ncolp + c0 + c] : make_double2(0, 0);
+        }
+    };
+    f64x4 acc[10][2];
+#pragma unroll
+    for (int v = 0; v < 10; ++v) acc[v][0] = acc[v][1] = f64x4{0, 0, 0, 0};
+    auto consume = [&](int bf, int sl) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            if (sl * KS + ks >= nkb) break;
+            const int e = ks * 4 + g;
+            const uint4 AG = *reinterpret_cast<const uint4*>(&gh[bf][0][e][wave * 16 + li]);
+            const uint4 AH = *reinterpret_cast<const uint4*>(&gh[bf][1][e][wave * 16 + li]);
+            uint4 V[7];
+#pragma unroll
+            for (int v = 0; v < 7; ++v) V[v] = *reinterpret_cast<const uint4*>(&vs[bf][v][e][li]);
+            constexpr int hv[4] = {3, 0, 1, 2};
+            constexpr int gv[6] = {0, 1, 2, 4, 5, 6};
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                acc[jj][0] = MfmaF64::step(AH, MfmaF64::re_part(V[hv[jj]]), acc[jj][0]);
+                acc[jj][1] = MfmaF64::step(AH, MfmaF64::im_part(V[hv[jj]]), acc[jj][1]);
+            }
+#pragma unroll
+            for (int jj = 0; jj < 6; ++jj) {
+                acc[4 + jj][0] = MfmaF64::step(AG, MfmaF64::re_part(V[gv[jj]]), acc[4 + jj][0]);
+                acc[4 + jj][1] = MfmaF64::step(AG, MfmaF64::im_part(V[gv[jj]]), acc[4 + jj][1]);
+            }
+        }
+    };
+    if (nstep > 0) stage(0, 0);
+    __syncthreads();
+    for (int j = 0; j < nstep; ++j) {
+        if (j + 1 < nstep) stage(j + 1, (j + 1) & 1);
+        consume(j & 1, j % nsl);
+        __syncthreads();
+    }
+    // lane holds column li and rows MfmaF64::orow(g, 0..3) of its row tile
+    const int c = c0 + li;
+    if (c >= ncol) return;
+#pragma unroll
+    for (int v = 0; v < 10; ++v)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ar = wave * 16 + MfmaF64::orow(g, r);
+            if (ar < nq) part[((ch * 10 + v) * nq + ar) * ncol + c] = make_double2(acc[v][0][r], acc[v][1][r]);
         }
 }
 
@@ -3480,6 +3582,13 @@ WorkSizes work_sizes(const igb_op_s* op, int ncol) {
         w.b[WorkSizes::XLO] = size_t(op->nclusters) * (hard ? 7 : 1) * ncolp * lo_kbp(o) * lo_esz(o);
         w.b[WorkSizes::PART_LO] = C * std::max<size_t>(1, op->chunks_mfma.len.size()) * nvec * nq * pt;
     }
+    if (op->prm.far_on_the_fly && hard && C >= size_t(MF64_MIN_COLS)) {
+        // fp64 source vectors of the on-the-fly matrix-core coupling (the rounded
+        // copy's buffer, shared: the two products never run in one matvec)
+        const size_t ncolp = (C + 15) / 16 * 16;
+        w.b[WorkSizes::XLO] = std::max(w.b[WorkSizes::XLO], size_t(op->nclusters) * 7 * ncolp * kbp_f64(op->nq) *
+                                                               sizeof(double2));
+    }
     if (op->prm.precision == IGB_MIX_BF16 && op->nnz > 0)
         w.b[WorkSizes::XNEAR_LO] = (C + 15) / 16 * 16 * op->N * sizeof(float2);
     if (op->nnz > 0 && ((op->prm.precision == IGB_FP64 && C >= size_t(MF64_MIN_COLS)) ||
@@ -3541,6 +3650,36 @@ igb_status timer_mark(igb_op op, int slot, hipStream_t s) {
     return IGB_OK;
 }
 
+// fp64 sound-hard coupling on the fly for blocks of >= 16 columns: the source
+// vectors rounded (to fp64: copied) into the matrix-core layout, then one
+// workgroup of ceil(nq / 16) waves per (chunk, 16 columns)
+static void launch_m2l_otf_mfma_hard(igb_op op, const MatvecWork& W, const double2* xh, int64_t ks, int ncol,
+                                     hipStream_t s) {
+    const M2LChunks& C = op->chunks;
+    const int64_t nchunk = int64_t(C.len.size());
+    const int ncolp = (ncol + 15) / 16 * 16, nq = op->nq, kbp = kbp_f64(nq);
+    double2* xv = static_cast<double2*>(W.xlo);
+    const int64_t nv = op->nclusters * 7 * ncolp * kbp;
+    hipLaunchKernelGGL((round_vectors<7, double2>), dim3(unsigned((nv + 255) / 256)), dim3(256), 0, s, xh, ks,
+                       op->d_nodes.as<double>(), op->nclusters, nq, kbp, ncol, ncolp, xv);
+    const dim3 grid(unsigned(nchunk), unsigned(ncolp / 16));
+#define IGB_OTF_MF(NWV, SLABV)                                                                                     \
+    hipLaunchKernelGGL((m2l_otf_mfma_hard<NWV, SLABV>), grid, dim3(64 * NWV), 0, s, op->d_nodes.as<double>(), xv,  \
+                       kbp, ncolp, op->d_far_src.as<int>(), C.d_tgt.as<int>(), C.d_pair.as<int64_t>(),           \
+                       C.d_len.as<int>(), nchunk, nq, ncol, op->kappa, W.part)
+    switch ((nq + 15) / 16) {
+        case 1: IGB_OTF_MF(1, 16); break;
+        case 2: IGB_OTF_MF(2, 16); break;
+        case 3: IGB_OTF_MF(3, 16); break;
+        case 4: IGB_OTF_MF(4, 16); break;
+        case 5: IGB_OTF_MF(5, 16); break;
+        case 6: IGB_OTF_MF(6, 16); break;
+        case 7: IGB_OTF_MF(7, 8); break;
+        default: IGB_OTF_MF(8, 8); break;
+    }
+#undef IGB_OTF_MF
+}
+
 // vector path (fp64 couplings): the soft kernel keeps 8 accumulators per lane,
 // the hard one 10 per column
 template <int NT>
@@ -3551,11 +3690,21 @@ static void launch_m2l_fp64(igb_op op, const MatvecWork& W, double2* xh, int64_t
     if (nchunk == 0) return;
     if (op->prm.far_on_the_fly) {
         const double* nd = op->d_nodes.as<double>();
-        if (op->bc == IGB_HARD) {
+        if (op->bc == IGB_HARD && ncol >= MF64_MIN_COLS) {
+            launch_m2l_otf_mfma_hard(op, W, xh, ks, ncol, s);
+        } else if (op->bc == IGB_HARD) {
             constexpr int RB = 4;
             hipLaunchKernelGGL((m2l_otf_hard<NT, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
                                dim3(NT), 0, s, nd, xh, ks, op->d_far_src.as<int>(), C.d_tgt.as<int>(),
                                C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol, op->kappa,
+                               W.part);
+        } else if (ncol >= 16) {
+            // (16 accumulators per lane: each kernel value serves twice the columns;
+            // 4.6 -> 3.4 ms at 16 columns on the level-6 star, slower for one column)
+            constexpr int RB = 16;
+            hipLaunchKernelGGL((m2l_otf_soft<NT, RB>), dim3(unsigned(nchunk), unsigned((ncol + RB - 1) / RB)),
+                               dim3(NT), 0, s, nd, xh, op->d_far_src.as<int>(), C.d_tgt.as<int>(),
+                               C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, op->nq, ncol, op->kappa, op->mix,
                                W.part);
         } else {
             constexpr int RB = 8;
