@@ -787,9 +787,7 @@ def main():
         ush[name] = uu.cpu().numpy()
     shell["h2_rel_diff_vs_direct"] = float(np.abs(ush["h2"] - ush["direct"]).max() / np.abs(ush["direct"]).max())
     shell["h2_speedup"] = shell["direct_seconds"] / shell["h2_seconds"]
-    shell["leaf_depth"] = LD
-    shell["note"] = ("200,000 seeded points in 1.2 <= |x| <= 4 (potential vs potential_h2, host plan included); "
-                     "clusters spanning more than q / 2 radians are not interpolated")
+    shell["note"] = "200,000 seeded points in 1.2 <= |x| <= 4 (potential vs potential_h2, host plan included)"
     potential["shell_200k"] = shell
     op.use_graphs(True)
     plain_graphs = run_solves(op, d, args.steps, args.warmup)
@@ -899,21 +897,6 @@ def main():
             "choice": {"coupling_col_tiles": best_t[0], "near_col_tiles": best_t[1]},
             "candidates": [{"coupling_col_tiles": a, "near_col_tiles": b, "matvec_ms": t} for a, b, t in cand_t]}
         op64.set_tile_shape(0, 0)
-        # the H^2 potential of the headline solution through this depth's cluster tree
-        # (its leaves are narrow enough at this kappa to be interpolated)
-        if op64 is not op:
-            uu = torch.zeros(len(sh), dtype=torch.complex128, device=dev)
-            op64.potential_h2(plain["coeff"], sh[:4096], uu[:4096])
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            op64.potential_h2(plain["coeff"], sh, uu)
-            torch.cuda.synchronize()
-            t_h2 = time.perf_counter() - t0
-            u_h2 = uu.cpu().numpy()
-            shell[f"h2_leaf_depth_{ld_lo}"] = {
-                "seconds": t_h2, "speedup": shell["direct_seconds"] / t_h2,
-                "rel_diff_vs_direct": float(np.abs(u_h2 - ush["direct"]).max() / np.abs(ush["direct"]).max())}
-            del uu
         if op64 is not op:
             del op64
         # the fp64 and bf16 blocks at the headline's own shape (assembly not counted)

@@ -429,10 +429,14 @@ igb_status farfield(igb_op op, const double* coeffs, int ndir, const double* obs
 igb_status potential(igb_op op, const double* coeffs, int ndir, const double* points, int npts, double* u,
                      void* hip_stream);
 
-/* The same scattered field evaluated with the H^2 structure of the operator
- * (Sec. 4.4's interpolation applied to the representation formula, Sec. 2):
- * the points are sorted into the boxes of an octree (at most 128 points each).
- * A source cluster acts through its moments at its (q+1)^2 interpolation
+/* The same scattered field evaluated with an H^2 structure on the operator's
+ * geometry, with its q, eta_adm and kcap (Sec. 4.4's interpolation applied to
+ * the representation formula, Sec. 2):
+ * the points are sorted into the boxes of an octree (at most 128 points each);
+ * the sources are the patch quadtrees down to clusters of 4 elements (level
+ * max(m - 1, 0), whatever the operator's leaf depth), with the moments of the
+ * density on the (q+1)^2 tensor Chebyshev nodes of each cluster's parameter
+ * square.  A source cluster acts through its moments at its interpolation
  * nodes when it is admissible for a box: distance at least the operator's
  * eta_adm times the cluster's diameter (boxes of the points and of the
  * cluster's control points) and kappa * diam at most the operator's kcap, or
@@ -440,12 +444,12 @@ igb_status potential(igb_op op, const double* coeffs, int ndir, const double* po
  * Chebyshev nodes of its own box, and the pair is admissible with the box's
  * diameter too, the nodes' kernel values are summed on the box's nodes and
  * interpolated to the points; otherwise they are summed at the points
- * directly.  The elements of the box's inadmissible leaf clusters are summed
+ * directly.  The elements of the box's inadmissible 4-element clusters are summed
  * directly as in potential().  Error against potential(): the interpolation
  * error of q on the cluster side (and the box side where its nodes are
  * used).  Arguments, layout, ownership and errors
- * as for potential(); the operator's matvec work buffers are used, so this
- * must not overlap other calls on the operator.  Synchronous. */
+ * as for potential(); its buffers are its own, allocated and freed by the
+ * call.  Synchronous. */
 igb_status potential_h2(igb_op op, const double* coeffs, int ndir, const double* points, int npts, double* u,
                         void* hip_stream);
 

@@ -372,21 +372,25 @@ inline int aspect_boost(double a) { return (a >= 2.0) + (a >= 3.0) + (a >= 5.0);
 // no singularity: right-hand side and far field (base 6), potential off the
 // boundary (base 8); raised with kappa * element size and quad_extra > 0.
 int smooth_order(igb_op op, int base);
-// H^2 evaluation of the scattered field at many points (host plan): points sorted
-// into target boxes of an octree (at most POT_LEAF_POINTS each), and per box the
-// source clusters admissible for both sides (far, interpolated on (q+1)^3 box
-// nodes; taken only where the box holds more points than nodes), those
+// H^2 evaluation of the scattered field at many points (host plan).  Sources:
+// the patch quadtrees down to level lmax = max(m - 1, 0) (clusters of 4
+// elements), independent of the operator's leaf depth.  Targets: the points
+// sorted into the boxes of an octree (at most POT_LEAF_POINTS each).  Per box:
+// the source clusters admissible for both sides (far, interpolated on (q+1)^3
+// box nodes; taken only where the box holds more points than nodes), those
 // admissible for the source side (m2p: their interpolation nodes act on the
-// box's points directly) and the inadmissible leaf clusters (near, direct
-// quadrature).
+// box's points directly) and the inadmissible clusters of level lmax (near,
+// direct quadrature).
 constexpr int POT_LEAF_POINTS = 128;
 struct PotentialPlan {
+    int lmax = 0;                          // finest source level
+    std::vector<int64_t> off;              // [lmax+2] first global id of each source level
     std::vector<int> perm;                 // points by box: perm[i] = caller's index
     std::vector<int> box_ptr;              // [nbox+1] into perm
     std::vector<double> box_lo, box_hi;    // [nbox][3] interpolation boxes
     std::vector<int> far_ptr, far_src;     // per box: global ids of clusters interpolated on the box
     std::vector<int> m2p_ptr, m2p_src;     // per box: global ids of clusters evaluated at the points
-    std::vector<int> near_ptr, near_leaf;  // per box: leaf clusters (index on the leaf level)
+    std::vector<int> near_ptr, near_leaf;  // per box: clusters of level lmax (index on the level)
 };
 igb_status potential_plan(igb_op op, const double* points, int npts, PotentialPlan& P);
 igb_status potential_h2_device(igb_op op, const double* coeffs, int ndir, const double* points, int npt, double* u,

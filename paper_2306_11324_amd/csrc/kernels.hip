@@ -2844,6 +2844,64 @@ __global__ __launch_bounds__(256) void potential_sum(const double* geo, const do
     if (threadIdx.x == 0) u[int64_t(dir) * npt + o] = red[0];
 }
 
+// H^2 potential, sources: moments of the finest source clusters (s x s
+// elements each) from the density at the quadrature points,
+// mom[c][b (q+1) + a][r] = sum over the cluster's points of L_a(u) L_b(v) w rho
+// / nel1^2, with (u, v) the point in the cluster's square and w / nel1^2 its
+// weight in patch coordinates (the measure the interpolation nodes carry).
+// Gauss rules of nqd >= 8 points per element and direction integrate these
+// products (degree q + p in each direction) exactly, so these are the
+// moments of the leaf-moment kernels.  One workgroup per (cluster, column).
+constexpr int POTM_TILE = 256;
+__global__ __launch_bounds__(256) void pot_leaf_moments(const double* __restrict__ geo,
+                                                        const double2* __restrict__ dens, int64_t nqtot,
+                                                        const double* __restrict__ gl, int nqd, int nel1, int lev,
+                                                        int s, const double* __restrict__ tch, int q, int ncol,
+                                                        double2* __restrict__ mom) {
+    __shared__ double lu[POTM_TILE][QMAX + 1], lv[POTM_TILE][QMAX + 1];
+    __shared__ double2 wd[POTM_TILE];
+    const int64_t c = blockIdx.x;
+    const int r = blockIdx.y, tid = threadIdx.x, q1 = q + 1, nq = q1 * q1;
+    const int n = 1 << lev;
+    const int64_t patch = c / (int64_t(n) * n);
+    const int cy = int((c / n) % n), cx = int(c % n);
+    const double* gx = gl + nqd * 2 * NGMAX;
+    const int nqp = nqd * nqd, npt = s * s * nqp;
+    const double inv = 1.0 / (double(nel1) * nel1);
+    const double2* D = dens + int64_t(r) * nqtot;
+    const int a = tid % q1, b = tid / q1;
+    auto lag = [&](int j, double x) {
+        double v = 1;
+        for (int i = 0; i < q1; ++i)
+            if (i != j) v *= (x - tch[i]) / (tch[j] - tch[i]);
+        return v;
+    };
+    double2 acc = make_double2(0, 0);
+    for (int t0 = 0; t0 < npt; t0 += POTM_TILE) {
+        const int cnt = min(POTM_TILE, npt - t0);
+        __syncthreads();   // the previous tile consumed
+        for (int k = tid; k < cnt; k += blockDim.x) {
+            const int li = t0 + k, el = li / nqp, gp = li % nqp, ex = el % s, ey = el / s;
+            const int64_t gi = ((patch * nel1 + cy * s + ey) * nel1 + cx * s + ex) * nqp + gp;
+            const double u = (ex + gx[gp % nqd]) / s, v = (ey + gx[gp / nqd]) / s;
+            for (int j = 0; j < q1; ++j) {
+                lu[k][j] = lag(j, u);
+                lv[k][j] = lag(j, v);
+            }
+            const double w = geo[gi * 8 + 7] * inv;
+            wd[k] = make_double2(w * D[gi].x, w * D[gi].y);
+        }
+        __syncthreads();
+        if (tid < nq)
+            for (int k = 0; k < cnt; ++k) {
+                const double f = lu[k][a] * lv[k][b];
+                acc.x = fma(f, wd[k].x, acc.x);
+                acc.y = fma(f, wd[k].y, acc.y);
+            }
+    }
+    if (tid < nq) mom[(c * nq + tid) * ncol + r] = acc;
+}
+
 // H^2 potential, far part: local expansion of every target box on its (q+1)^3
 // Chebyshev nodes from the moments of its admissible source clusters, the
 // kernel evaluated at node pairs (source nodes carry a and n~ like the
@@ -2937,7 +2995,7 @@ __device__ double2 pot_l2p(const double* x, const double* lo, const double* hi, 
 // Lagrange on the box's Chebyshev nodes), plus the interpolation nodes of the
 // clusters that act on the points directly (each node a source point carrying
 // the cluster's moment), plus direct quadrature over the elements of the box's
-// inadmissible leaf clusters.  Source points are staged in LDS a tile at a time
+// inadmissible finest clusters (level L, s x s elements each).  Source points are staged in LDS a tile at a time
 // and shared by the box's points.  One workgroup per (box, column); a box of
 // few points gives each point a group of lanes (a power of two) that split
 // every tile and add their partial sums in a fixed order, so a column's result
@@ -4345,7 +4403,7 @@ igb_status potential_h2_device(igb_op op, const double* coeffs, int ndir, const 
             set_error("potential_h2: point %d is not finite", i / 3);
             return IGB_ERR_ARG;
         }
-    // the tree, moments and source nodes live on the first part of a separate-form operator
+    // geometry, q and the transfers of the first part of a separate-form operator
     const igb_op sp = op->sum_parts.empty() ? op : op->sum_parts.front();
     igb_geom g = sp->geom;
     const bool hard = op->bc == IGB_HARD;
@@ -4354,25 +4412,13 @@ igb_status potential_h2_device(igb_op op, const double* coeffs, int ndir, const 
     if ((st = potential_plan(sp, points, npt, P))) return st;
     const int nbox = int(P.box_ptr.size()) - 1;
     if (nbox == 0) return IGB_OK;
-    const int q = sp->q, q1 = q + 1, nq = sp->nq, n3 = nq * q1, L = sp->L;
+    const int q = sp->q, q1 = q + 1, nq = sp->nq, n3 = nq * q1, lmax = P.lmax;
     const double2* C = reinterpret_cast<const double2*>(coeffs);
-    // source moments (value kind) of every cluster: leaf moments, then upward
-    if ((st = alloc_work(sp, ndir))) return st;
-    const double2* x2 = C;
-    if (hard) {
-        hipLaunchKernelGGL(glue_gather, dim3(blocks_for(g->n2 * ndir, 256)), dim3(256), 0, s,
-                           sp->d_s2_to_s0.as<int>(), C, sp->N, sp->d_x2.as<double2>(), g->n2, ndir);
-        x2 = sp->d_x2.as<double2>();
-    }
-    double2* xh = sp->d_xhat.as<double2>();
-    launch_leaf_moments(sp, x2, xh, 0, 0, ndir, s);
-    launch_m2m_levels(sp->d_T.as<double>(), q, L, g->npatch, sp->clu_off, xh, ndir, s);
-    IGB_HIP(hipGetLastError());
-    // boundary density and geometry at the quadrature points (near part)
+    // boundary density and geometry at the quadrature points
     const int nqd = smooth_order(op, 8);
     const int64_t nqtot = g->nelem * nqd * nqd;
     DevBuf d_gl, d_geo, d_dens, d_pts, d_perm, d_bptr, d_blo, d_bhi, d_tch, d_fptr, d_fsrc, d_mptr, d_msrc, d_nptr, d_nleaf,
-        d_lbox;
+        d_lbox, d_off, d_nodes, d_mom;
     std::vector<double> gl = gauss_table();
     if ((st = upload(d_gl, gl.data(), gl.size(), nullptr))) return st;
     if ((st = alloc(d_geo, size_t(nqtot) * 8 * sizeof(double), nullptr))) return st;
@@ -4387,13 +4433,28 @@ igb_status potential_h2_device(igb_op op, const double* coeffs, int ndir, const 
              return IGB_OK;
          })))
         return st;
+    // source clusters: interpolation nodes, moments of the finest level from the
+    // quadrature points, then the coarser levels by the transfers
     std::vector<double> t(q1);
     cheb_nodes(q, t.data());
+    const int64_t nclu = P.off[lmax + 1];
+    if ((st = upload(d_tch, t.data(), t.size(), nullptr)) || (st = upload(d_off, P.off.data(), P.off.size(), nullptr)) ||
+        (st = alloc(d_nodes, size_t(nclu) * nq * 16 * sizeof(double), nullptr)) ||
+        (st = alloc(d_mom, size_t(nclu) * nq * ndir * sizeof(double2), nullptr)))
+        return st;
+    hipLaunchKernelGGL(node_geometry, dim3(unsigned((nclu * nq + 255) / 256)), dim3(256), 0, s, g->d_bez.as<double>(),
+                       g->d_pg.as<int>(), g->nel1, g->npatch, lmax, d_off.as<int64_t>(), d_tch.as<double>(), q,
+                       d_nodes.as<double>());
+    double2* mom = d_mom.as<double2>();
+    hipLaunchKernelGGL(pot_leaf_moments, dim3(unsigned(clusters_on_level(g->npatch, lmax)), unsigned(ndir)), dim3(256),
+                       0, s, d_geo.as<double>(), d_dens.as<double2>(), nqtot, d_gl.as<double>(), nqd, g->nel1, lmax,
+                       1 << (g->m - lmax), d_tch.as<double>(), q, ndir, mom + P.off[lmax] * nq * ndir);
+    launch_m2m_levels(sp->d_T.as<double>(), q, lmax, g->npatch, P.off, mom, ndir, s);
+    IGB_HIP(hipGetLastError());
     if ((st = upload(d_pts, points, size_t(3) * npt, nullptr)) || (st = upload(d_perm, P.perm.data(), P.perm.size(), nullptr)) ||
         (st = upload(d_bptr, P.box_ptr.data(), P.box_ptr.size(), nullptr)) ||
         (st = upload(d_blo, P.box_lo.data(), P.box_lo.size(), nullptr)) ||
         (st = upload(d_bhi, P.box_hi.data(), P.box_hi.size(), nullptr)) ||
-        (st = upload(d_tch, t.data(), t.size(), nullptr)) ||
         (st = upload(d_fptr, P.far_ptr.data(), P.far_ptr.size(), nullptr)) ||
         (st = upload(d_nptr, P.near_ptr.data(), P.near_ptr.size(), nullptr)) ||
         (st = upload(d_mptr, P.m2p_ptr.data(), P.m2p_ptr.size(), nullptr)))
@@ -4404,18 +4465,17 @@ igb_status potential_h2_device(igb_op op, const double* coeffs, int ndir, const 
     const bool any_far = !P.far_src.empty();
     if (any_far) {
         if ((st = alloc(d_lbox, size_t(nbox) * n3 * ndir * sizeof(double2), nullptr))) return st;
-        hipLaunchKernelGGL(pot_box_m2l, dim3(unsigned(nbox), unsigned(ndir)), dim3(256), 0, s,
-                           sp->d_nodes.as<double>(), xh, q, d_blo.as<double>(), d_bhi.as<double>(), d_tch.as<double>(),
-                           d_fptr.as<int>(), d_fsrc.as<int>(), ndir, op->kappa, hard ? 1 : 0,
-                           d_lbox.as<double2>());
+        hipLaunchKernelGGL(pot_box_m2l, dim3(unsigned(nbox), unsigned(ndir)), dim3(256), 0, s, d_nodes.as<double>(),
+                           mom, q, d_blo.as<double>(), d_bhi.as<double>(), d_tch.as<double>(), d_fptr.as<int>(),
+                           d_fsrc.as<int>(), ndir, op->kappa, hard ? 1 : 0, d_lbox.as<double2>());
         IGB_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(pot_l2p_near, dim3(unsigned(nbox), unsigned(ndir)), dim3(POT_LEAF_POINTS), 0, s,
                        d_pts.as<double>(), d_perm.as<int>(), d_bptr.as<int>(), d_blo.as<double>(), d_bhi.as<double>(),
                        d_tch.as<double>(), q, any_far ? d_lbox.as<double2>() : nullptr, ndir, d_mptr.as<int>(),
-                       d_msrc.as<int>(), sp->d_nodes.as<double>(), xh, d_nptr.as<int>(), d_nleaf.as<int>(), sp->d, L,
-                       g->nel1, nqd * nqd, d_geo.as<double>(), d_dens.as<double2>(), nqtot, op->kappa, hard ? 1 : 0,
-                       npt, reinterpret_cast<double2*>(u));
+                       d_msrc.as<int>(), d_nodes.as<double>(), mom, d_nptr.as<int>(), d_nleaf.as<int>(),
+                       g->m - lmax, lmax, g->nel1, nqd * nqd, d_geo.as<double>(), d_dens.as<double2>(), nqtot,
+                       op->kappa, hard ? 1 : 0, npt, reinterpret_cast<double2*>(u));
     IGB_HIP(hipGetLastError());
     IGB_HIP(hipStreamSynchronize(s));   // temporaries are freed on return
     return IGB_OK;

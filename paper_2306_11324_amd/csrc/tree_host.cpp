@@ -513,7 +513,40 @@ igb_status near_pattern(igb_op op) {
 // Target boxes and interaction lists of the H^2 potential evaluation
 // --------------------------------------------------------------------------
 igb_status potential_plan(igb_op op, const double* pts, int npts, PotentialPlan& P) {
-    const int np = op->geom->npatch, L = op->L;
+    igb_geom g = op->geom;
+    const int np = g->npatch, m = g->m, L = std::max(m - 1, 0);
+    // source cluster boxes, levels 0..L: the elements' boxes merged upward
+    P.lmax = L;
+    P.off.assign(L + 2, 0);
+    for (int l = 0; l <= L; ++l) P.off[l + 1] = P.off[l] + clusters_on_level(np, l);
+    std::vector<double> clo(size_t(P.off[L + 1]) * 3), chi(size_t(P.off[L + 1]) * 3);
+    {
+        std::vector<double> lo(g->lo), hi(g->hi);
+        for (int l = m; l >= 0; --l) {
+            const int n = 1 << l;
+            if (l <= L)
+                for (int64_t src = 0; src < clusters_on_level(np, l); ++src)
+                    for (int c = 0; c < 3; ++c) {
+                        clo[3 * (P.off[l] + src) + c] = lo[3 * src + c];
+                        chi[3 * (P.off[l] + src) + c] = hi[3 * src + c];
+                    }
+            if (l == 0) break;
+            const int h = n / 2;
+            std::vector<double> plo(size_t(np) * h * h * 3, 1e300), phi(size_t(np) * h * h * 3, -1e300);
+            for (int j = 0; j < np; ++j)
+                for (int cy = 0; cy < n; ++cy)
+                    for (int cx = 0; cx < n; ++cx) {
+                        const int64_t src = (int64_t(j) * n + cy) * n + cx;
+                        const int64_t dst = (int64_t(j) * h + cy / 2) * h + cx / 2;
+                        for (int c = 0; c < 3; ++c) {
+                            plo[3 * dst + c] = std::min(plo[3 * dst + c], lo[3 * src + c]);
+                            phi[3 * dst + c] = std::max(phi[3 * dst + c], hi[3 * src + c]);
+                        }
+                    }
+            lo.swap(plo);
+            hi.swap(phi);
+        }
+    }
     P.perm.resize(npts);
     for (int i = 0; i < npts; ++i) P.perm[i] = i;
     P.box_ptr.assign(1, 0);
@@ -616,8 +649,8 @@ igb_status potential_plan(igb_op op, const double* pts, int npts, PotentialPlan&
             const int l = st.back().first;
             const int64_t loc = st.back().second;
             st.pop_back();
-            const int64_t gid = op->clu_off[l] + loc;
-            const double *ls = &op->clo[3 * gid], *hs = &op->chi[3 * gid];
+            const int64_t gid = P.off[l] + loc;
+            const double *ls = &clo[3 * gid], *hs = &chi[3 * gid];
             double gap2 = 0, ds2 = 0;
             for (int c = 0; c < 3; ++c) {
                 const double gp = std::max(0.0, std::max(ls[c] - ht[c], lt[c] - hs[c]));
