@@ -1222,8 +1222,11 @@ __global__ __launch_bounds__(512 / RPW) void m2l_mfma(const typename OPS::LT* __
 #pragma unroll
         for (int v = 0; v < NVO; ++v) acc[k][v][0] = acc[k][v][1] = ACC{0, 0, 0, 0};
     // steps j = (pair i, k block kb) in order; KU steps issue their loads
-    // before any of their products, so each wave keeps KU blocks in flight
-    constexpr int KU = HARD ? 1 : 4;
+    // before any of their products, so each wave keeps KU blocks in flight.
+    // (Sound-hard, one wave per SIMD: two steps in flight instead of one took
+    // the bf16 coupling of the level-6 hard star from 1.11 to 0.68 ms; the fp64
+    // form, two waves per SIMD, would spill.)
+    constexpr int KU = HARD ? (std::is_same<OPS, MfmaF64>::value ? 1 : 2) : 4;
     const int nstep = len * nkb;
     // the chunk's source clusters, lane i holding pair i (len <= 64), read back
     // with readlane: no dependent scalar load inside the loop
