@@ -213,8 +213,11 @@ igb_status tree_build(igb_op op) {
     build_chunks(op, M2L_CHUNK, op->chunks);
     // (matrix-core chunks shrink, down to 2 sources, until there are about
     // M2L_MFMA_CHUNKS_MIN of them: an operator with few far pairs otherwise
-    // leaves most CUs idle in its block products)
-    int chm = M2L_CHUNK_MFMA;
+    // leaves most CUs idle in its block products.  Sound-hard chunks start 4x
+    // longer: each writes 10 partial vectors, at 16 sources a quarter of the
+    // bytes of its bf16 tiles; on the level-7 hard star the partials' reduction
+    // went from 2.7 to 0.8 ms and the 16-column product from 36.3 to 33.9 ms.)
+    int chm = op->bc == IGB_HARD ? 4 * M2L_CHUNK_MFMA : M2L_CHUNK_MFMA;
     while (chm > 2 && op->nfar / chm < M2L_MFMA_CHUNKS_MIN) chm /= 2;
     build_chunks(op, chm, op->chunks_mfma);
     return IGB_OK;
