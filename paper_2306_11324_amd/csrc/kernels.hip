@@ -1645,31 +1645,37 @@ __global__ __launch_bounds__(NT) void m2l_otf_hard(const double* __restrict__ no
 // fp64 sound-hard coupling without stored tiles for blocks of >= 16 columns
 // on the fp64 matrix cores.  Per pair, the G and H values of SLAB source nodes
 // at a time are evaluated at every target node into LDS together with the
-// slab's source vectors (16 columns, from round_vectors), and wave w
-// multiplies target rows 16w..16w+15 as the stored-tile kernel does (H on
-// vectors {3, 0, 1, 2}, G on {0, 1, 2, 4, 5, 6}: the vector-path kernel's 10
-// partials in its order).  Two LDS buffers: each thread evaluates the next
-// slab while the matrix cores work through the current one; one barrier per
-// slab.  Every output sums the chunk's pairs and their source nodes in order,
-// so a column's result does not depend on the other columns.  Target rows
-// past nq evaluate the last row (their outputs are not stored).
-template <int NW, int SLAB>
-__global__ __launch_bounds__(64 * NW) void m2l_otf_mfma_hard(
+// slab's source vectors (16 columns, from round_vectors), and the waves
+// multiply them as the stored-tile kernel does (H on vectors {3, 0, 1, 2}, G
+// on {0, 1, 2, 4, 5, 6}: the vector-path kernel's 10 partials in its order).
+// SPLIT: two waves per 16-row tile, one taking the 4 H products and G on
+// vector 0, the other G on {1, 2, 4, 5, 6}, so that six row tiles (q = 8)
+// give 12 waves, 3 per SIMD, instead of 6 on 4 SIMDs.  Two LDS buffers: each
+// thread evaluates the next slab while the matrix cores work through the
+// current one; one barrier per slab.  Every output sums the chunk's pairs and
+// their source nodes in order, so a column's result does not depend on the
+// other columns (nor on SPLIT).  Target rows past nq are not evaluated (zero;
+// their outputs are not stored).
+template <int NW, int SLAB, bool SPLIT>
+__global__ __launch_bounds__(64 * NW * (SPLIT ? 2 : 1)) void m2l_otf_mfma_hard(
     const double* __restrict__ nodes, const double2* __restrict__ xv, int kbp, int ncolp,
     const int* __restrict__ far_src_g, const int* __restrict__ chunk_tgt, const int64_t* __restrict__ chunk_pair,
     const int* __restrict__ chunk_len, int64_t nchunk, int nq, int ncol, double kappa, double2* __restrict__ part) {
-    constexpr int R = 16 * NW, NT = 64 * NW, EB = NT / R, KS = SLAB / 4;
+    constexpr int R = 16 * NW, NT = 64 * NW * (SPLIT ? 2 : 1), EB = NT / R, KS = SLAB / 4;
+    constexpr int NA = SPLIT ? 5 : 10;   // accumulated products per wave
     static_assert(SLAB % 4 == 0 && SLAB % EB == 0, "a slab is whole k blocks and evaluation passes");
     __shared__ double2 gh[2][2][SLAB][R];    // [buffer][G, H][source node in slab][target row]
     __shared__ double2 vs[2][7][SLAB][16];   // [buffer][source vector][source node in slab][column]
     const int64_t ch = xcd_chunk(blockIdx.x, nchunk);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, g = lane >> 4;
+    const int rt = SPLIT ? wave >> 1 : wave, half = SPLIT ? wave & 1 : 0;   // row tile, product half
     const int c0 = blockIdx.y * 16;
     const int64_t p0 = chunk_pair[ch];
     const int len = chunk_len[ch];
     const int nkb = (nq + 3) / 4, nsl = (nq + SLAB - 1) / SLAB, nstep = len * nsl;
     // evaluation: fixed target row, source nodes eb0, eb0 + EB, ... of each slab
     const int ea = tid % R, eb0 = tid / R;
+    const bool erow = ea < nq;
     double X[3];
     {
         const double* T = nodes + (int64_t(chunk_tgt[ch]) * nq + min(ea, nq - 1)) * 16;
@@ -1686,7 +1692,7 @@ __global__ __launch_bounds__(64 * NW) void m2l_otf_mfma_hard(
         for (int e = eb0; e < SLAB; e += EB) {
             const int b = sl * SLAB + e;
             double2 G = make_double2(0, 0), H = G;
-            if (b < nq) kernel_gh(X, Y + b * 16, kappa, G, H);
+            if (erow && b < nq) kernel_gh(X, Y + b * 16, kappa, G, H);
             gh[bf][0][e][ea] = G;
             gh[bf][1][e][ea] = H;
         }
@@ -1696,30 +1702,44 @@ __global__ __launch_bounds__(64 * NW) void m2l_otf_mfma_hard(
             vs[bf][v][b][c] = bb < kbp ? xv[(src * 7 + v) * vstride + int64_t(bb) * ncolp + c0 + c] : make_double2(0, 0);
         }
     };
-    f64x4 acc[10][2];
+    f64x4 acc[NA][2];
 #pragma unroll
-    for (int v = 0; v < 10; ++v) acc[v][0] = acc[v][1] = f64x4{0, 0, 0, 0};
+    for (int v = 0; v < NA; ++v) acc[v][0] = acc[v][1] = f64x4{0, 0, 0, 0};
+    auto product = [&](int o, const uint4& A, const uint4& V) {
+        acc[o][0] = MfmaF64::step(A, MfmaF64::re_part(V), acc[o][0]);
+        acc[o][1] = MfmaF64::step(A, MfmaF64::im_part(V), acc[o][1]);
+    };
     auto consume = [&](int bf, int sl) {
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             if (sl * KS + ks >= nkb) break;
             const int e = ks * 4 + g;
-            const uint4 AG = *reinterpret_cast<const uint4*>(&gh[bf][0][e][wave * 16 + li]);
-            const uint4 AH = *reinterpret_cast<const uint4*>(&gh[bf][1][e][wave * 16 + li]);
-            uint4 V[7];
+            auto ld = [&](const double2& x) { return *reinterpret_cast<const uint4*>(&x); };
+            const uint4 AG = ld(gh[bf][0][e][rt * 16 + li]);
+            if (!SPLIT) {
+                const uint4 AH = ld(gh[bf][1][e][rt * 16 + li]);
+                uint4 V[7];
 #pragma unroll
-            for (int v = 0; v < 7; ++v) V[v] = *reinterpret_cast<const uint4*>(&vs[bf][v][e][li]);
-            constexpr int hv[4] = {3, 0, 1, 2};
-            constexpr int gv[6] = {0, 1, 2, 4, 5, 6};
+                for (int v = 0; v < 7; ++v) V[v] = ld(vs[bf][v][e][li]);
+                constexpr int hv[4] = {3, 0, 1, 2};
+                constexpr int gv[6] = {0, 1, 2, 4, 5, 6};
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                acc[jj][0] = MfmaF64::step(AH, MfmaF64::re_part(V[hv[jj]]), acc[jj][0]);
-                acc[jj][1] = MfmaF64::step(AH, MfmaF64::im_part(V[hv[jj]]), acc[jj][1]);
-            }
+                for (int jj = 0; jj < 4; ++jj) product(jj, AH, V[hv[jj]]);
 #pragma unroll
-            for (int jj = 0; jj < 6; ++jj) {
-                acc[4 + jj][0] = MfmaF64::step(AG, MfmaF64::re_part(V[gv[jj]]), acc[4 + jj][0]);
-                acc[4 + jj][1] = MfmaF64::step(AG, MfmaF64::im_part(V[gv[jj]]), acc[4 + jj][1]);
+                for (int jj = 0; jj < 6; ++jj) product(4 + jj, AG, V[gv[jj]]);
+            } else if (half == 0) {
+                const uint4 AH = ld(gh[bf][1][e][rt * 16 + li]);
+                const uint4 V0 = ld(vs[bf][0][e][li]), V1 = ld(vs[bf][1][e][li]), V2 = ld(vs[bf][2][e][li]),
+                            V3 = ld(vs[bf][3][e][li]);
+                product(0, AH, V3);
+                product(1, AH, V0);
+                product(2, AH, V1);
+                product(3, AH, V2);
+                product(4, AG, V0);
+            } else {
+                constexpr int gv[5] = {1, 2, 4, 5, 6};
+#pragma unroll
+                for (int jj = 0; jj < 5; ++jj) product(jj, AG, ld(vs[bf][gv[jj]][e][li]));
             }
         }
     };
@@ -1730,15 +1750,17 @@ __global__ __launch_bounds__(64 * NW) void m2l_otf_mfma_hard(
         consume(j & 1, j % nsl);
         __syncthreads();
     }
-    // lane holds column li and rows MfmaF64::orow(g, 0..3) of its row tile
-    const int c = c0 + li;
+    // lane holds column li and rows MfmaF64::orow(g, 0..3) of its row tile;
+    // this wave's products are the partial vectors v0 .. v0 + NA - 1
+    const int c = c0 + li, v0 = SPLIT ? 5 * half : 0;
     if (c >= ncol) return;
 #pragma unroll
-    for (int v = 0; v < 10; ++v)
+    for (int v = 0; v < NA; ++v)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int ar = wave * 16 + MfmaF64::orow(g, r);
-            if (ar < nq) part[((ch * 10 + v) * nq + ar) * ncol + c] = make_double2(acc[v][0][r], acc[v][1][r]);
+            const int ar = rt * 16 + MfmaF64::orow(g, r);
+            if (ar < nq)
+                part[((ch * 10 + v0 + v) * nq + ar) * ncol + c] = make_double2(acc[v][0][r], acc[v][1][r]);
         }
 }
 
@@ -3724,19 +3746,21 @@ static void launch_m2l_otf_mfma_hard(igb_op op, const MatvecWork& W, const doubl
     hipLaunchKernelGGL((round_vectors<7, double2>), dim3(unsigned((nv + 255) / 256)), dim3(256), 0, s, xh, ks,
                        op->d_nodes.as<double>(), op->nclusters, nq, kbp, ncol, ncolp, xv);
     const dim3 grid(unsigned(nchunk), unsigned(ncolp / 16));
-#define IGB_OTF_MF(NWV, SLABV)                                                                                     \
-    hipLaunchKernelGGL((m2l_otf_mfma_hard<NWV, SLABV>), grid, dim3(64 * NWV), 0, s, op->d_nodes.as<double>(), xv,  \
-                       kbp, ncolp, op->d_far_src.as<int>(), C.d_tgt.as<int>(), C.d_pair.as<int64_t>(),           \
-                       C.d_len.as<int>(), nchunk, nq, ncol, op->kappa, W.part)
+    // (an even number of row tiles splits each tile's products over two waves,
+    // balanced over the 4 SIMDs of a CU)
+#define IGB_OTF_MF(NWV, SLABV, SPLITV)                                                                             \
+    hipLaunchKernelGGL((m2l_otf_mfma_hard<NWV, SLABV, SPLITV>), grid, dim3(64 * NWV * (SPLITV ? 2 : 1)), 0, s,      \
+                       op->d_nodes.as<double>(), xv, kbp, ncolp, op->d_far_src.as<int>(), C.d_tgt.as<int>(),      \
+                       C.d_pair.as<int64_t>(), C.d_len.as<int>(), nchunk, nq, ncol, op->kappa, W.part)
     switch ((nq + 15) / 16) {
-        case 1: IGB_OTF_MF(1, 16); break;
-        case 2: IGB_OTF_MF(2, 16); break;
-        case 3: IGB_OTF_MF(3, 16); break;
-        case 4: IGB_OTF_MF(4, 16); break;
-        case 5: IGB_OTF_MF(5, 16); break;
-        case 6: IGB_OTF_MF(6, 16); break;
-        case 7: IGB_OTF_MF(7, 8); break;
-        default: IGB_OTF_MF(8, 8); break;
+        case 1: IGB_OTF_MF(1, 16, false); break;
+        case 2: IGB_OTF_MF(2, 16, true); break;
+        case 3: IGB_OTF_MF(3, 16, false); break;
+        case 4: IGB_OTF_MF(4, 16, true); break;
+        case 5: IGB_OTF_MF(5, 16, false); break;
+        case 6: IGB_OTF_MF(6, 16, true); break;
+        case 7: IGB_OTF_MF(7, 8, false); break;
+        default: IGB_OTF_MF(8, 8, false); break;
     }
 #undef IGB_OTF_MF
 }
