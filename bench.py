@@ -615,7 +615,7 @@ def main():
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (sharding an operator or "
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (sharding an operator or "
                                    "a request stream across GPUs is not built)"}))
         sys.exit(2)
 

@@ -55,7 +55,7 @@ typedef int igb_status;
 #define IGB_ERR_GEOMETRY (-2)  /* invalid knots / weights / non-conforming patches   */
 #define IGB_ERR_BUDGET (-3)    /* the context's HBM budget would be exceeded          */
 #define IGB_ERR_HIP (-4)       /* a HIP runtime call failed                           */
-#define IGB_ERR_UNSUPPORTED (-5) /* parameters outside what this build implements     */
+#define IGB_ERR_UNSUPPORTED (-5) /* parameters outside what the library implements    */
 #define IGB_WARN_NOT_CONVERGED 1 /* iterative solve stopped at maxit                  */
 
 typedef struct igb_ctx_s* igb_ctx;
