@@ -201,6 +201,8 @@ struct igb_op_s {
     std::vector<double> clo, chi;     // [nclusters][3] boxes
     std::vector<FarLevel> far;        // one entry per level 0..L
     int64_t nfar = 0;
+    int far_lmin = 0;                 // coarsest level with admissible pairs (L + 1: none); moments and
+                                      // expansions of coarser levels are neither formed nor transferred
     // near field: per target element the sorted near source elements
     std::vector<int64_t> near_ptr;    // [E+1]
     std::vector<int> near_src;

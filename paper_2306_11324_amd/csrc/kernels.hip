@@ -780,14 +780,15 @@ __global__ __launch_bounds__(256) void m2m_wg(const double* __restrict__ T1, int
 
 // the upward pass above the leaves: m2m_wg level by level, up to 8 columns per
 // workgroup within 48 KB of dynamic LDS
+// levels L-1 down to lmin (the coarser ones are not needed)
 static void launch_m2m_levels(const double* T1, int q, int L, int npatch, const std::vector<int64_t>& clu_off,
-                              double2* xh, int ncol, hipStream_t s) {
+                              double2* xh, int ncol, hipStream_t s, int lmin = 0) {
     const int nq = (q + 1) * (q + 1);
     int cb = std::min(ncol, 8);
     while (cb > 2 && size_t(8) * nq * cb * sizeof(double2) > 48 * 1024) cb /= 2;
     const size_t lds = size_t(8) * nq * cb * sizeof(double2);
     const unsigned cblk = unsigned((ncol + cb - 1) / cb);
-    for (int l = L - 1; l >= 0; --l)
+    for (int l = L - 1; l >= std::max(lmin, 0); --l)
         hipLaunchKernelGGL(m2m_wg, dim3(unsigned(clusters_on_level(npatch, l)), cblk), dim3(cb >= 4 ? 256 : TREE_THREADS),
                            lds, s, T1, q, l, clu_off[l], clu_off[l + 1], xh, ncol, cb);
 }
@@ -861,8 +862,9 @@ __global__ __launch_bounds__(256) void down_project_leaf(const double2* __restri
                                                          const double* __restrict__ Tc,
                                                          const int64_t* __restrict__ clu_off,
                                                          const double* __restrict__ m1, int q, int w, int L,
-                                                         int deriv_u, int deriv_v, int64_t m1_stride_kind,
-                                                         int ncol, int cb, double2* __restrict__ leafbuf) {
+                                                         int lmin, int deriv_u, int deriv_v,
+                                                         int64_t m1_stride_kind, int ncol, int cb,
+                                                         double2* __restrict__ leafbuf) {
     extern __shared__ double2 dyn[];
     __shared__ double Mu[TQ1 * TQ1], Mv[TQ1 * TQ1];
     const int q1 = q + 1, nq = q1 * q1, tid = threadIdx.x, nt = blockDim.x;
@@ -886,7 +888,8 @@ __global__ __launch_bounds__(256) void down_project_leaf(const double2* __restri
         return acc;
     };
     for (int i = tid; i < nq * nr; i += nt) Y[i] = yget(clu_off[L] + c, i / nr, r0 + i % nr);
-    for (int l = L - 1; l >= 0; --l) {
+    // ancestors coarser than lmin hold no coupling results
+    for (int l = L - 1; l >= lmin; --l) {
         const int dl = L - l, msk = (1 << dl) - 1;
         const int64_t A = clu_off[l] + (int64_t(patch) << (2 * l)) + (int64_t(cy >> dl) << l) + (cx >> dl);
         const double* Tu = Tc + int64_t((1 << dl) - 2 + (cx & msk)) * q1 * q1;
@@ -4147,7 +4150,8 @@ static igb_status matvec_launches(igb_op op, const MatvecWork& W, const double* 
         if ((st = timer_mark(op, 2, s))) return st;
         for (int kd = 0; kd < kinds; ++kd) {
             launch_leaf_moments(op, x2, xh + kd * ks, du[kd], dv[kd], ncol, s);
-            launch_m2m_levels(op->d_T.as<double>(), q, L, g->npatch, op->clu_off, xh + kd * ks, ncol, s);
+            launch_m2m_levels(op->d_T.as<double>(), q, L, g->npatch, op->clu_off, xh + kd * ks, ncol, s,
+                              op->far_lmin);
         }
         if ((st = timer_mark(op, 2, s))) return st;
         int pkind = 0;
@@ -4181,21 +4185,23 @@ static igb_status matvec_launches(igb_op op, const MatvecWork& W, const double* 
         const int64_t* cof = op->d_cluoff.as<int64_t>();
         const double* m1 = op->d_m1.as<double>();
         double2* lb = W.leafbuf;
+        const int lmin = op->far_lmin;
         if (hard) {
             for (int kd = 0; kd < kinds; ++kd)
                 hipLaunchKernelGGL(down_project_leaf<double2>, dgrid, dblock, dlds, s, yh + kd * ks,
                                    static_cast<const double2*>(nullptr), static_cast<const int*>(nullptr), Tc, cof, m1,
-                                   q, w, L, du[kd], dv[kd], stride_kind, ncol, dcb, lb + kd * nleaf * ncol * w * w);
+                                   q, w, L, lmin, du[kd], dv[kd], stride_kind, ncol, dcb,
+                                   lb + kd * nleaf * ncol * w * w);
         } else if (pkind == 1) {
             hipLaunchKernelGGL(down_project_leaf<float2>, dgrid, dblock, dlds, s, yh, static_cast<float2*>(W.part_lo),
-                               op->chunks_mfma.d_tgt_ptr.as<int>(), Tc, cof, m1, q, w, L, 0, 0, stride_kind, ncol,
-                               dcb, lb);
+                               op->chunks_mfma.d_tgt_ptr.as<int>(), Tc, cof, m1, q, w, L, lmin, 0, 0, stride_kind,
+                               ncol, dcb, lb);
         } else {
             const bool lo = pkind == 2;
             hipLaunchKernelGGL(down_project_leaf<double2>, dgrid, dblock, dlds, s, yh,
                                lo ? static_cast<double2*>(W.part_lo) : W.part,
-                               (lo ? op->chunks_mfma : op->chunks).d_tgt_ptr.as<int>(), Tc, cof, m1, q, w, L, 0, 0,
-                               stride_kind, ncol, dcb, lb);
+                               (lo ? op->chunks_mfma : op->chunks).d_tgt_ptr.as<int>(), Tc, cof, m1, q, w, L, lmin,
+                               0, 0, stride_kind, ncol, dcb, lb);
         }
         if ((st = timer_mark(op, 3, s))) return st;
     }

@@ -176,6 +176,9 @@ igb_status tree_build(igb_op op) {
         cur.swap(nxt);
     }
     op->nfar = pair_off;
+    op->far_lmin = L + 1;
+    for (int l = L; l >= 0; --l)
+        if (!op->far[l].src.empty()) op->far_lmin = l;
 
     // near element pairs, per target element sorted by source element
     const int64_t E = g->nelem;
