@@ -448,8 +448,9 @@ igb_status potential(igb_op op, const double* coeffs, int ndir, const double* po
  * directly as in potential().  Error against potential(): the interpolation
  * error of q on the cluster side (and the box side where its nodes are
  * used).  Arguments, layout, ownership and errors
- * as for potential(); its buffers are its own, allocated and freed by the
- * call.  Synchronous. */
+ * as for potential(), and IGB_ERR_ARG if a box list outgrows 2^31 entries
+ * (hundreds of millions of points: pass them in parts); its buffers are its
+ * own, allocated and freed by the call.  Synchronous. */
 igb_status potential_h2(igb_op op, const double* coeffs, int ndir, const double* points, int npts, double* u,
                         void* hip_stream);
 

@@ -682,6 +682,17 @@ igb_status potential_plan(igb_op op, const double* pts, int npts, PotentialPlan&
     P.far_ptr.assign(nbox + 1, 0);
     P.m2p_ptr.assign(nbox + 1, 0);
     P.near_ptr.assign(nbox + 1, 0);
+    int64_t tot[3] = {0, 0, 0};
+    for (int64_t b = 0; b < nbox; ++b) {
+        tot[0] += int64_t(far[b].size());
+        tot[1] += int64_t(m2p[b].size());
+        tot[2] += int64_t(near[b].size());
+    }
+    if (std::max(tot[0], std::max(tot[1], tot[2])) > int64_t(INT32_MAX)) {
+        set_error("potential_h2: interaction lists of %d points exceed 2^31 entries; pass fewer points per call",
+                  npts);
+        return IGB_ERR_ARG;
+    }
     for (int64_t b = 0; b < nbox; ++b) {
         P.far_ptr[b + 1] = P.far_ptr[b] + int(far[b].size());
         P.m2p_ptr[b + 1] = P.m2p_ptr[b] + int(m2p[b].size());
