@@ -3023,8 +3023,8 @@ __device__ double2 pot_l2p(const double* x, const double* lo, const double* hi, 
 // Lagrange on the box's Chebyshev nodes), plus the interpolation nodes of the
 // clusters that act on the points directly (each node a source point carrying
 // the cluster's moment), plus direct quadrature over the elements of the box's
-// inadmissible finest clusters (level L, s x s elements each).  Source points are staged in LDS a tile at a time
-// and shared by the box's points.  One workgroup per (box, column); a box of
+// inadmissible finest clusters (level L, s x s elements each).  Source points
+// are staged in LDS a tile at a time and shared by the box's points.  One workgroup per (box, column); a box of
 // few points gives each point a group of lanes (a power of two) that split
 // every tile and add their partial sums in a fixed order, so a column's result
 // does not depend on the others.
@@ -3738,7 +3738,8 @@ igb_status timer_mark(igb_op op, int slot, hipStream_t s) {
 
 // fp64 sound-hard coupling on the fly for blocks of >= 16 columns: the source
 // vectors rounded (to fp64: copied) into the matrix-core layout, then one
-// workgroup of ceil(nq / 16) waves per (chunk, 16 columns)
+// workgroup of ceil(nq / 16) waves (twice that where the products are split)
+// per (chunk, 16 columns)
 static void launch_m2l_otf_mfma_hard(igb_op op, const MatvecWork& W, const double2* xh, int64_t ks, int ncol,
                                      hipStream_t s) {
     const M2LChunks& C = op->chunks;
