@@ -274,6 +274,60 @@ def large_workload(name, steps, warmup):
     print(json.dumps(out), flush=True)
 
 
+def potential_sweep(counts, m=3, p=3, kappa=2.5, q=8, leaf_depth=2):
+    """Scattered-field evaluation time against the number of points, direct
+    summation vs the H^2 evaluation (the paper's potential-scaling figure of
+    Sec. 5, there on the turbine, whose CAD is not available): the degree-3
+    torus at level 3 (R = 2, r = 0.5), kappa = 2.5, q = 8, one incident
+    direction along x; seeded points filling the cylinder r <= 4, |z| <= 2
+    outside the tube of radius 0.75 around the torus' core circle.  One JSON
+    line per point count, then the log-log slopes over the counts from 10^4 on."""
+    import torch
+
+    from paper_2306_11324_amd import binding as B
+    from paper_2306_11324_amd import inputs as I
+    dev = torch.device("cuda:0")
+    torch.cuda.init()
+    ctx = B.Context(0)
+    geo = B.Geometry(ctx, I.torus_patches(), m, p)
+    op = B.Operator(ctx, geo, kappa=kappa, q=q, eta_adm=1.6, leaf_depth=leaf_depth)
+    coeff = torch.zeros((1, op.n), dtype=torch.complex128, device=dev)
+    info, st = op.cfie_solve(np.array([[1.0, 0.0, 0.0]]), coeff, tol=1e-8, restart=30, maxit=3000)
+    rng = np.random.default_rng(5)
+    nmax = max(counts)
+    pts = np.zeros((0, 3))
+    while len(pts) < nmax:
+        cand = np.column_stack([rng.uniform(-4, 4, 2 * nmax), rng.uniform(-4, 4, 2 * nmax),
+                                rng.uniform(-2, 2, 2 * nmax)])
+        rho = np.hypot(cand[:, 0], cand[:, 1])
+        keep = (rho <= 4.0) & (np.hypot(rho - 2.0, cand[:, 2]) > 0.75)
+        pts = np.concatenate([pts, cand[keep]])
+    pts = pts[:nmax]
+    rows = []
+    for npt in counts:
+        P = np.ascontiguousarray(pts[:npt])
+        out = {}
+        for name, f in (("direct", op.potential), ("h2", op.potential_h2)):
+            u = torch.zeros((1, npt), dtype=torch.complex128, device=dev)
+            f(coeff, P[:min(npt, 1000)], u[:, :min(npt, 1000)])   # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f(coeff, P, u)
+            torch.cuda.synchronize()
+            out[name] = (time.perf_counter() - t0, u.cpu().numpy())
+        e = float(np.abs(out["h2"][1] - out["direct"][1]).max() / np.abs(out["direct"][1]).max())
+        rec = {"sweep": "potential points", "geometry": "torus R=2 r=0.5", "m": m, "p": p, "kappa": kappa, "q": q,
+               "points": npt, "direct_s": out["direct"][0], "h2_s": out["h2"][0],
+               "speedup": out["direct"][0] / out["h2"][0], "h2_rel_diff_vs_direct": e}
+        rows.append(rec)
+        print(json.dumps(rec), flush=True)
+    big = [r for r in rows if r["points"] >= 10000]
+    if len(big) >= 2:
+        lx = np.log([r["points"] for r in big])
+        print(json.dumps({"sweep": "potential points", "loglog_slope_vs_points": {
+            k: float(np.polyfit(lx, np.log([r[k] for r in big]), 1)[0]) for k in ("direct_s", "h2_s")}}), flush=True)
+
+
 def scaling_sweep(levels, kappa=2.0, q=6, leaf_depth=2):
     """Matvec time, operator bytes and solve against the level m on the sphere
     at fixed kappa and q (the paper's log-linear time-to-solution claim of Sec.
@@ -598,6 +652,8 @@ def main():
                     help="reference solution: the finest CFIE solution or the single-layer one (as the paper)")
     ap.add_argument("--conv-out", default=None, help="also write the study's JSON lines to this file")
     ap.add_argument("--sweep", default=None, help="levels m for the scaling sweep, e.g. 3,4,5,6,7")
+    ap.add_argument("--potential-sweep", default=None,
+                    help="point counts for the scattered-field sweep (direct vs H^2), e.g. 1000,10000,100000")
     ap.add_argument("--counter-summary", nargs="+", default=None,
                     help="summarise rocprofv3 --pmc output directories of --kernels-only (no GPU)")
     ap.add_argument("--kernels-only", action="store_true",
@@ -625,6 +681,9 @@ def main():
         return
     if args.sweep:
         scaling_sweep([int(v) for v in args.sweep.split(",")])
+        return
+    if args.potential_sweep:
+        potential_sweep([int(v) for v in args.potential_sweep.split(",")])
         return
     if args.counter_summary:
         counter_summary(args.counter_summary)
