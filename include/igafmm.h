@@ -454,6 +454,21 @@ igb_status potential(igb_op op, const double* coeffs, int ndir, const double* po
 igb_status potential_h2(igb_op op, const double* coeffs, int ndir, const double* points, int npts, double* u,
                         void* hip_stream);
 
+/* The plan potential_h2 builds for these points (Sec. 4.4's block partition
+ * between the points' octree boxes and the source clusters), made on the host
+ * alone; works on host-only contexts.  counts (4 entries, required): boxes,
+ * (box, cluster) pairs summed on the box's nodes, (box, cluster) pairs summed
+ * at the points through the cluster's nodes, and (box, 4-element cluster)
+ * pairs summed directly.  perm (npts entries) and box_ptr (counts[0] + 1
+ * entries), each optional (NULL): the points in box order (box b holds the
+ * points perm[box_ptr[b]] .. perm[box_ptr[b+1] - 1], boxes in depth-first
+ * octant order), so a caller sizing box_ptr calls once with it NULL.  Host
+ * arrays owned by the caller.  IGB_ERR_ARG for NULL op, points or counts,
+ * npts < 1, a non-finite point or lists beyond 2^31 entries, as for
+ * potential_h2. */
+igb_status igb_op_potential_plan(igb_op op, const double* points, int npts, int64_t* counts, int32_t* perm,
+                                 int32_t* box_ptr);
+
 const char* igb_last_error(void);
 
 #ifdef __cplusplus

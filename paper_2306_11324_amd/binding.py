@@ -88,6 +88,8 @@ _SIGS = {
     "igb_op_near_csr": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "igb_op_far_blocks": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "igb_op_near_pairs": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "igb_op_potential_plan": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "h2_matvec": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, _P]),
     "h2_matvec_noalloc": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, _P]),
     "cfie_rhs": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int, _P, _P]),
@@ -259,6 +261,22 @@ class Operator:
             self.h, ptr.ctypes.data_as(C.POINTER(C.c_int64)), src.ctypes.data_as(C.POINTER(C.c_int32)),
             kind.ctypes.data_as(C.POINTER(C.c_int32))))
         return ptr, src, kind
+
+    def potential_plan(self, points):
+        """The H^2 potential's plan for host points [npts][3]: (counts, perm,
+        box_ptr) with counts = boxes, box-node pairs, cluster-node pairs, direct
+        pairs; box b holds the points perm[box_ptr[b]:box_ptr[b+1]]."""
+        pt, pp = _dbl(np.atleast_2d(points))
+        counts = np.zeros(4, dtype=np.int64)
+        i32 = C.POINTER(C.c_int32)
+        _check("igb_op_potential_plan", _lib.igb_op_potential_plan(
+            self.h, pp, pt.shape[0], counts.ctypes.data_as(C.POINTER(C.c_int64)), None, None))
+        perm = np.zeros(pt.shape[0], dtype=np.int32)
+        box_ptr = np.zeros(int(counts[0]) + 1, dtype=np.int32)
+        _check("igb_op_potential_plan", _lib.igb_op_potential_plan(
+            self.h, pp, pt.shape[0], counts.ctypes.data_as(C.POINTER(C.c_int64)), perm.ctypes.data_as(i32),
+            box_ptr.ctypes.data_as(i32)))
+        return counts, perm, box_ptr
 
     def profile(self, enable: bool = True):
         _check("igb_op_profile", _lib.igb_op_profile(self.h, 1 if enable else 0))

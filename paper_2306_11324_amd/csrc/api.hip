@@ -557,6 +557,30 @@ igb_status igb_op_far_blocks(igb_op op, int32_t* out) {
     return IGB_OK;
 }
 
+igb_status igb_op_potential_plan(igb_op op, const double* points, int npts, int64_t* counts, int32_t* perm,
+                                 int32_t* box_ptr) {
+    if (!op || !points || !counts || npts < 1) {
+        set_error("igb_op_potential_plan: invalid argument");
+        return IGB_ERR_ARG;
+    }
+    for (int64_t i = 0; i < 3 * int64_t(npts); ++i)
+        if (!std::isfinite(points[i])) {
+            set_error("igb_op_potential_plan: point %lld is not finite", (long long)(i / 3));
+            return IGB_ERR_ARG;
+        }
+    // the geometry and q of the first part of a separate-form operator, as potential_h2
+    const igb_op sp = op->sum_parts.empty() ? op : op->sum_parts.front();
+    PotentialPlan P;
+    if (igb_status st = potential_plan(sp, points, npts, P)) return st;
+    counts[0] = int64_t(P.box_ptr.size()) - 1;
+    counts[1] = int64_t(P.far_src.size());
+    counts[2] = int64_t(P.m2p_src.size());
+    counts[3] = int64_t(P.near_leaf.size());
+    if (perm) std::memcpy(perm, P.perm.data(), P.perm.size() * sizeof(int32_t));
+    if (box_ptr) std::memcpy(box_ptr, P.box_ptr.data(), P.box_ptr.size() * sizeof(int32_t));
+    return IGB_OK;
+}
+
 igb_status igb_op_near_pairs(igb_op op, int64_t* ptr, int32_t* src, int32_t* kind) {
     if (!op || !ptr || !src || !kind) {
         set_error("igb_op_near_pairs: NULL argument");

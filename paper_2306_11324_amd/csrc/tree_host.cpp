@@ -2,7 +2,9 @@
 // (Sec. 4.4), near element pairs with their quadrature class, and the sparsity
 // pattern of the near-field matrix.
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <memory>
 #include <map>
 
 #include "common.h"
@@ -584,18 +586,119 @@ igb_status potential_plan(igb_op op, const double* pts, int npts, PotentialPlan&
     // error against the direct sum rose from 7e-9 to 2e-6.)
     const double kcap = op->prm.kcap > 0 ? op->prm.kcap : 0.5 * op->q;
     const int64_t n3 = int64_t(op->q + 1) * (op->q + 1) * (op->q + 1);
-    // octree of cubes over index ranges (depth-first, children in octant order)
+    // octree of cubes over index ranges, leaves (the interpolation boxes) in
+    // depth-first octant order; the coordinates travel with the permutation so
+    // that every pass reads them in order
     struct Node {
         int b, e, depth;
         double lo[3], h;
     };
-    std::vector<Node> stack{Node{0, npts, 0, {glo[0], glo[1], glo[2]}, side}};
-    while (!stack.empty()) {
-        Node nd = stack.back();
-        stack.pop_back();
-        // (smaller boxes at high kappa, so that more of them can interpolate, cost
-        // more per point on the m = 5 sphere at kappa = 8 than they save)
-        if (nd.e - nd.b <= POT_LEAF_POINTS || nd.depth >= 20) {
+    // (smaller boxes at high kappa, so that more of them can interpolate, cost
+    // more per point on the m = 5 sphere at kappa = 8 than they save)
+    const auto is_leaf = [](const Node& nd) { return nd.e - nd.b <= POT_LEAF_POINTS || nd.depth >= 20; };
+    // work arrays left uninitialised and first touched by the threads that use them
+    std::unique_ptr<double[]> xs(new double[3 * size_t(npts)]), xtmp(new double[3 * size_t(npts)]);
+    std::unique_ptr<int[]> ptmp(new int[npts]);
+    std::unique_ptr<unsigned char[]> code(new unsigned char[npts]);
+    constexpr int64_t GRAIN = 1 << 16;
+    parallel_for((npts + GRAIN - 1) / GRAIN, 1, [&](int64_t k) {
+        const int64_t a = k * GRAIN, e = std::min<int64_t>(npts, a + GRAIN);
+        std::copy(pts + 3 * a, pts + 3 * e, xs.get() + 3 * a);
+    });
+    // stable partition of [b, e) into the 8 octants, in chunks of GRAIN points (the
+    // chunks in parallel when wide); the non-empty children in octant order
+    const auto split = [&](const Node& nd, bool wide, std::vector<Node>& kids) {
+        const double h = 0.5 * nd.h;
+        const int64_t nch = (nd.e - nd.b + GRAIN - 1) / GRAIN;
+        std::vector<std::array<int, 8>> cnt(nch);
+        const auto over = [&](const auto& f) {
+            if (wide) parallel_for(nch, 1, f);
+            else for (int64_t k = 0; k < nch; ++k) f(k);
+        };
+        over([&](int64_t k) {
+            cnt[k].fill(0);
+            const int a = nd.b + int(k * GRAIN), e = std::min<int64_t>(nd.e, a + GRAIN);
+            for (int i = a; i < e; ++i) {
+                int o = 0;
+                for (int c = 0; c < 3; ++c)
+                    if (xs[3 * size_t(i) + c] >= nd.lo[c] + h) o |= 1 << c;
+                code[i] = (unsigned char)o;
+                ++cnt[k][o];
+            }
+        });
+        // chunk k's points of octant o start after all points of lower octants and
+        // after the octant-o points of chunks before k
+        int start[9];
+        start[0] = nd.b;
+        for (int o = 0; o < 8; ++o) {
+            int tot = 0;
+            for (int64_t k = 0; k < nch; ++k) tot += cnt[k][o];
+            start[o + 1] = start[o] + tot;
+        }
+        std::vector<std::array<int, 8>> pos(nch);
+        for (int o = 0; o < 8; ++o) {
+            int p = start[o];
+            for (int64_t k = 0; k < nch; ++k) {
+                pos[k][o] = p;
+                p += cnt[k][o];
+            }
+        }
+        over([&](int64_t k) {
+            const int a = nd.b + int(k * GRAIN), e = std::min<int64_t>(nd.e, a + GRAIN);
+            for (int i = a; i < e; ++i) {
+                const size_t j = size_t(pos[k][code[i]]++);
+                ptmp[j] = P.perm[i];
+                for (int c = 0; c < 3; ++c) xtmp[3 * j + c] = xs[3 * size_t(i) + c];
+            }
+        });
+        over([&](int64_t k) {
+            const int a = nd.b + int(k * GRAIN), e = std::min<int64_t>(nd.e, a + GRAIN);
+            std::copy(ptmp.get() + a, ptmp.get() + e, P.perm.begin() + a);
+            std::copy(xtmp.get() + 3 * size_t(a), xtmp.get() + 3 * size_t(e), xs.get() + 3 * size_t(a));
+        });
+        for (int o = 0; o < 8; ++o)
+            if (start[o + 1] > start[o])
+                kids.push_back(Node{start[o], start[o + 1], nd.depth + 1,
+                                    {nd.lo[0] + ((o & 1) ? h : 0), nd.lo[1] + ((o & 2) ? h : 0),
+                                     nd.lo[2] + ((o & 4) ? h : 0)},
+                                    h});
+    };
+    // the top levels split level by level into a frontier in depth-first order (a
+    // level of few nodes splits each node in parallel, a wider one its nodes in
+    // parallel), whose subtrees are then built in parallel
+    std::vector<Node> front{Node{0, npts, 0, {glo[0], glo[1], glo[2]}, side}};
+    const size_t nthr = size_t(host_threads()), want = 8 * nthr;
+    while (front.size() < want && std::any_of(front.begin(), front.end(), [&](const Node& nd) { return !is_leaf(nd); })) {
+        std::vector<std::vector<Node>> kids(front.size());
+        const auto one = [&](int64_t f, bool wide) {
+            if (is_leaf(front[f])) kids[f].push_back(front[f]);
+            else split(front[f], wide, kids[f]);
+        };
+        if (front.size() < nthr)
+            for (size_t f = 0; f < front.size(); ++f) one(int64_t(f), true);
+        else
+            parallel_for(int64_t(front.size()), 1, [&](int64_t f) { one(f, false); });
+        std::vector<Node> next;
+        for (const auto& k : kids) next.insert(next.end(), k.begin(), k.end());
+        front.swap(next);
+    }
+    struct Leaves {
+        std::vector<int> end;
+        std::vector<double> lo, hi;
+    };
+    std::vector<Leaves> sub(front.size());
+    parallel_for(int64_t(front.size()), 1, [&](int64_t f) {
+        Leaves& out = sub[f];
+        std::vector<Node> stack{front[f]}, kids;
+        while (!stack.empty()) {
+            const Node nd = stack.back();
+            stack.pop_back();
+            if (!is_leaf(nd)) {
+                kids.clear();
+                split(nd, false, kids);
+                stack.insert(stack.end(), kids.rbegin(), kids.rend());   // octant 0 taken first
+                continue;
+            }
             // interpolation box: the points' own box, each side at least 1e-3 of the cube
             double lo[3], hi[3];
             for (int c = 0; c < 3; ++c) {
@@ -604,40 +707,21 @@ igb_status potential_plan(igb_op op, const double* pts, int npts, PotentialPlan&
             }
             for (int i = nd.b; i < nd.e; ++i)
                 for (int c = 0; c < 3; ++c) {
-                    lo[c] = std::min(lo[c], pts[3 * P.perm[i] + c]);
-                    hi[c] = std::max(hi[c], pts[3 * P.perm[i] + c]);
+                    lo[c] = std::min(lo[c], xs[3 * size_t(i) + c]);
+                    hi[c] = std::max(hi[c], xs[3 * size_t(i) + c]);
                 }
             for (int c = 0; c < 3; ++c) {
                 const double mid = 0.5 * (lo[c] + hi[c]), half = std::max(0.5 * (hi[c] - lo[c]), 5e-4 * nd.h);
-                P.box_lo.push_back(mid - half);
-                P.box_hi.push_back(mid + half);
+                out.lo.push_back(mid - half);
+                out.hi.push_back(mid + half);
             }
-            P.box_ptr.push_back(nd.e);
-            continue;
+            out.end.push_back(nd.e);
         }
-        const double h = 0.5 * nd.h;
-        auto oct = [&](int i) {
-            int o = 0;
-            for (int c = 0; c < 3; ++c)
-                if (pts[3 * i + c] >= nd.lo[c] + h) o |= 1 << c;
-            return o;
-        };
-        // stable partition of [b, e) into the 8 octants
-        int cnt[9] = {0};
-        for (int i = nd.b; i < nd.e; ++i) ++cnt[oct(P.perm[i]) + 1];
-        for (int o = 0; o < 8; ++o) cnt[o + 1] += cnt[o];
-        std::vector<int> tmp(nd.e - nd.b);
-        int pos[8];
-        for (int o = 0; o < 8; ++o) pos[o] = cnt[o];
-        for (int i = nd.b; i < nd.e; ++i) tmp[pos[oct(P.perm[i])]++] = P.perm[i];
-        std::copy(tmp.begin(), tmp.end(), P.perm.begin() + nd.b);
-        // pushed in reverse so that octant 0 is taken first (boxes in octant order)
-        for (int o = 7; o >= 0; --o) {
-            if (cnt[o + 1] == cnt[o]) continue;
-            Node ch{nd.b + cnt[o], nd.b + cnt[o + 1], nd.depth + 1,
-                    {nd.lo[0] + ((o & 1) ? h : 0), nd.lo[1] + ((o & 2) ? h : 0), nd.lo[2] + ((o & 4) ? h : 0)}, h};
-            stack.push_back(ch);
-        }
+    });
+    for (const auto& s : sub) {
+        P.box_ptr.insert(P.box_ptr.end(), s.end.begin(), s.end.end());
+        P.box_lo.insert(P.box_lo.end(), s.lo.begin(), s.lo.end());
+        P.box_hi.insert(P.box_hi.end(), s.hi.begin(), s.hi.end());
     }
     const int64_t nbox = int64_t(P.box_ptr.size()) - 1;
     // interaction lists: descend the source cluster tree from the patches

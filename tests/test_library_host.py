@@ -223,3 +223,62 @@ def test_recompression_parameter_is_validated(hctx):
         args.update(kw)
         with pytest.raises(B.IgbError):
             B.Operator(hctx, geo, **args)
+
+
+def octree_boxes(pts, leaf=128, max_depth=20):
+    """The points' octree written out plainly: the cube of side the bounding
+    box's widest extent at its low corner, split at the midpoints (a point on a
+    midpoint goes to the upper half), the points of a cube kept in their order
+    within each octant, a cube of at most `leaf` points (or at depth 20) a box,
+    boxes in depth-first octant order.  Returns (perm, box_ptr)."""
+    lo0 = pts.min(0)
+    side = float((pts.max(0) - lo0).max())
+    if not side > 0:
+        side = 1.0
+    perm, ends = [], [0]
+
+    def visit(idx, lo, h, depth):
+        if len(idx) <= leaf or depth >= max_depth:
+            perm.append(idx)
+            ends.append(ends[-1] + len(idx))
+            return
+        half = 0.5 * h
+        upper = pts[idx] >= lo + half
+        code = upper[:, 0] * 1 + upper[:, 1] * 2 + upper[:, 2] * 4
+        for o in range(8):
+            sel = idx[code == o]
+            if len(sel):
+                bits = np.array([o & 1, o & 2, o & 4]) != 0
+                visit(sel, lo + np.where(bits, half, 0.0), half, depth + 1)
+
+    visit(np.arange(len(pts)), lo0, side, 0)
+    return np.concatenate(perm), np.array(ends)
+
+
+def test_potential_plan_boxes_and_lists(hctx):
+    """The H^2 potential's plan on the host: its octree equals a plain one (on
+    enough points that the top levels split in parallel chunks, with a run of
+    repeated points down to the depth cap); far points need no direct sums and
+    near ones do; the separate-form operator plans as the fused one."""
+    geo = B.Geometry(hctx, I.sphere_patches(), 3, 2)
+    op = B.Operator(hctx, geo, kappa=2.0, q=6, leaf_depth=1)
+    rng = np.random.default_rng(11)
+    d = rng.normal(size=(150000, 3))
+    pts = d / np.linalg.norm(d, axis=1, keepdims=True) * rng.uniform(1.2, 3.0, size=(150000, 1))
+    pts[-1000:] = [2.0, 0.5, -0.25]
+    counts, perm, box_ptr = op.potential_plan(pts)
+    ref_perm, ref_ptr = octree_boxes(pts)
+    assert counts[0] == len(ref_ptr) - 1
+    np.testing.assert_array_equal(box_ptr, ref_ptr)
+    np.testing.assert_array_equal(perm, ref_perm)
+    assert counts[1] > 0 and counts[2] > 0 and counts[3] > 0    # the repeated run uses its box's nodes
+    sep = B.Operator(hctx, geo, kappa=2.0, q=6, leaf_depth=1, separate=True)
+    np.testing.assert_array_equal(sep.potential_plan(pts)[0], counts)
+    far = rng.normal(size=(3000, 3)) * 5.0 + [60.0, 0.0, 0.0]
+    c_far, perm_far, ptr_far = op.potential_plan(far)
+    assert c_far[3] == 0 and c_far[2] > 0
+    np.testing.assert_array_equal(np.sort(perm_far), np.arange(3000))
+    bad = far.copy()
+    bad[17, 1] = np.inf
+    with pytest.raises(B.IgbError):
+        op.potential_plan(bad)
