@@ -5,7 +5,10 @@
 
 #include <algorithm>
 #include <atomic>
+#include <memory>
 #include <mutex>
+#include <new>
+#include <utility>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -384,15 +387,38 @@ int smooth_order(igb_op op, int base);
 // box's points directly) and the inadmissible clusters of level lmax (near,
 // direct quadrature).
 constexpr int POT_LEAF_POINTS = 128;
+// allocator whose resize leaves ints uninitialised (for lists filled right after)
+template <class T>
+struct UninitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = UninitAlloc<U>;
+    };
+    UninitAlloc() = default;
+    template <class U>
+    UninitAlloc(const UninitAlloc<U>&) {}
+    template <class U>
+    void construct(U* p) noexcept {
+        ::new (static_cast<void*>(p)) U;
+    }
+    template <class U, class... A>
+    void construct(U* p, A&&... a) {
+        ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
+    }
+};
+using IdList = std::vector<int, UninitAlloc<int>>;
+
 struct PotentialPlan {
     int lmax = 0;                          // finest source level
     std::vector<int64_t> off;              // [lmax+2] first global id of each source level
     std::vector<int> perm;                 // points by box: perm[i] = caller's index
     std::vector<int> box_ptr;              // [nbox+1] into perm
     std::vector<double> box_lo, box_hi;    // [nbox][3] interpolation boxes
-    std::vector<int> far_ptr, far_src;     // per box: global ids of clusters interpolated on the box
-    std::vector<int> m2p_ptr, m2p_src;     // per box: global ids of clusters evaluated at the points
-    std::vector<int> near_ptr, near_leaf;  // per box: clusters of level lmax (index on the level)
+    // per box (ptr into the flat list): global ids of the clusters interpolated on
+    // the box, global ids of those evaluated at the points, and the clusters of
+    // level lmax summed directly (index on the level)
+    std::vector<int> far_ptr, m2p_ptr, near_ptr;
+    IdList far_src, m2p_src, near_leaf;
 };
 igb_status potential_plan(igb_op op, const double* points, int npts, PotentialPlan& P);
 igb_status potential_h2_device(igb_op op, const double* coeffs, int ndir, const double* points, int npt, double* u,

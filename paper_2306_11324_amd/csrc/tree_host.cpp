@@ -785,11 +785,14 @@ igb_status potential_plan(igb_op op, const double* pts, int npts, PotentialPlan&
     P.far_src.resize(P.far_ptr[nbox]);
     P.m2p_src.resize(P.m2p_ptr[nbox]);
     P.near_leaf.resize(P.near_ptr[nbox]);
-    for (int64_t b = 0; b < nbox; ++b) {
+    parallel_for(nbox, 256, [&](int64_t b) {
         std::copy(far[b].begin(), far[b].end(), P.far_src.begin() + P.far_ptr[b]);
         std::copy(m2p[b].begin(), m2p[b].end(), P.m2p_src.begin() + P.m2p_ptr[b]);
         std::copy(near[b].begin(), near[b].end(), P.near_leaf.begin() + P.near_ptr[b]);
-    }
+        std::vector<int>().swap(far[b]);
+        std::vector<int>().swap(m2p[b]);
+        std::vector<int>().swap(near[b]);
+    });
     return IGB_OK;
 }
 
