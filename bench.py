@@ -714,7 +714,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.init()
     ctx = B.Context(0)
-    pts = I.sphere_patches() if w["geometry"] == "sphere" else I.star_patches(0, min(w["m"], 4))
+    pts = I.sphere_patches() if w["geometry"] == "sphere" else I.star_patches(0, I.star_geometry_level(w["m"]))
     geo = B.Geometry(ctx, pts, w["m"], w["p"])
     # the operator's shape for this workload: the autotuner over leaf depth and
     # tiles / recompressed factors, costed by matvec time (the operator serves

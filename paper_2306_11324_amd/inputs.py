@@ -224,8 +224,17 @@ def star_patches(seed: int, g: int) -> list[Patch]:
 
 
 def star_geometry_level(m: int) -> int:
-    """Geometry span exponent g = min(m, 4): geometry knots nest in the mesh."""
-    return min(m, 4)
+    """Geometry span exponent g = min(max(m - 3, 0), 4) of the level-m star.
+
+    The geometry knots nest in the mesh, and every cluster of up to 8 x 8
+    elements (leaf depth <= 3) lies inside one geometry span.  The degree-2
+    mapping is only C^1 across its knot lines, so its surface measure and
+    normal have kinks there; a kernel interpolated on a cluster that straddles
+    one converges only algebraically in the interpolation degree, whereas
+    inside one polynomial piece the pulled-back kernel is analytic and the
+    Chebyshev error decays geometrically.  (Sec. 3.2 takes the patch mappings
+    to be smooth; Sec. 4.4 interpolates the kernel pulled back to them.)"""
+    return min(max(m - 3, 0), 4)
 
 
 # ---------------------------------------------------------------------------

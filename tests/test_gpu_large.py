@@ -11,11 +11,16 @@ at any size: the optical theorem and far-field reciprocity.
 
 Both need the kappa * diameter cap on admissible blocks: without it the
 coarse blocks are several wavelengths across and nine Chebyshev points per
-direction do not resolve the kernel.  The cap sets the compression error,
-stated two ways against the oracle rows: relative to the operator (|dy_r| /
-(||A_r||_1 ||x||_inf)) and relative to this y (|dy| / max|y|; a random x
-gives a y 50-300 times below the operator bound by cancellation).  The
-oracle rows themselves agree with higher-order quadrature to 1e-13.
+direction do not resolve the kernel.  At both levels the star's geometry
+spans hold whole leaf clusters (8 x 8 elements), so every admissible block
+interpolates an analytic pulled-back kernel; the cap then sets the
+compression error, stated two ways against the oracle rows: relative to the
+operator (|dy_r| / (||A_r||_1 ||x||_inf)) and relative to this y
+(|dy| / max|y|; a random x gives a y 50-300 times below the operator bound by
+cancellation).  The level-6 product must meet 1e-6 in the second, stricter
+measure (measured 1.6e-9); the level-7 fp64 product, whose blocks reach
+kappa * diameter 8, is held to 1e-5 (measured 2.0e-6).  The oracle rows
+themselves agree with higher-order quadrature to 1e-13.
 """
 import os
 import sys
@@ -76,7 +81,7 @@ def test_star_level6_soft_rows_and_64_direction_solve():
     torch.cuda.synchronize()
     e_norm, e_rel = row_errors(y.cpu().numpy(), g)
     print(f"matvec vs oracle rows: operator-relative {e_norm:.2e}, vector-relative {e_rel:.2e}", flush=True)
-    assert e_norm < 1e-6 and e_rel < 5e-5
+    assert e_norm < 1e-8 and e_rel < 1e-6
     dirs = I.random_directions(1, 64)
     coeff = torch.zeros((64, op.n), dtype=torch.complex128, device="cuda")
     info, st = op.cfie_solve(dirs, coeff, tol=1e-8, restart=30, maxit=3000, verbose=True)
