@@ -13,7 +13,11 @@ interpolation of the pulled-back kernel on the reference domain, H^2 format):
        dist(B_t, B_s) >= eta * max(diam B_t, diam B_s)
    with B the axis-aligned box of the cluster's Bezier control points (these
    contain the surface piece by the convex hull property, weights > 0), plus the
-   optional cap kappa * max(diam) <= kcap.
+   optional cap kappa * max(diam) <= kcap, and only for clusters that lie
+   inside one knot span of their patch's geometry in both directions (Sec. 3.2
+   takes the patch mappings to be smooth; across an interior knot a spline
+   mapping is only finitely smooth, and the interpolant of the pulled-back
+   kernel no longer converges geometrically in q).
 3. Degenerate kernel: on an admissible pair the pulled-back kernel
    k(x^, y^) is replaced by its tensor Chebyshev interpolant of degree q in
    each reference coordinate of both clusters (rank (q+1)^2, Sec. 4.4):
@@ -129,7 +133,19 @@ class H2Oracle:
         el = self.cluster_elements(c)
         return self.el_lo[el].min(0), self.el_hi[el].max(0)
 
+    def inside_one_span(self, c: Cluster) -> bool:
+        """No interior geometry knot lies strictly inside the cluster's square."""
+        mp = self.disc.maps[c.patch]
+        w = 2.0 ** -c.level
+        for knots, i in ((mp.ku, c.cx), (mp.kv, c.cy)):
+            a, b = i * w, (i + 1) * w
+            if np.any((knots > a + 1e-12) & (knots < b - 1e-12)):
+                return False
+        return True
+
     def admissible(self, t: Cluster, s: Cluster) -> bool:
+        if not (self.inside_one_span(t) and self.inside_one_span(s)):
+            return False
         lt, ht = self.box(t)
         ls, hs = self.box(s)
         gap = np.maximum(0.0, np.maximum(ls - ht, lt - hs))

@@ -121,6 +121,7 @@ struct igb_geom_s {
     std::vector<double> bez;     // [E][NBZ][4]: homogeneous rational Bezier net of the element
     std::vector<int> pg;         // [E][2]: geometry degree in u and v
     std::vector<double> lo, hi;  // [E][3]: box of the projected Bezier control points
+    std::vector<int> espan;      // [E][2]: index of the geometry knot span (u, v) holding the element
     std::vector<double> corner;  // [E][4][3]: physical corners at local (0,0),(1,0),(0,1),(1,1)
     std::vector<int> vert;       // [E][4]: global vertex id of each corner
     std::vector<double> C1;      // [nel1][p+1][p+1]: b_{ex+a} = sum_k C1[ex][a][k] Bernstein_k

@@ -187,6 +187,7 @@ igb_status geometry_build(igb_ctx ctx, const igb_patch* patches, int npatch, int
     g->bez.assign(E * NBZ * 4, 0.0);
     g->pg.assign(E * 2, 0);
     g->lo.assign(E * 3, 0.0);
+    g->espan.assign(E * 2, 0);
     g->hi.assign(E * 3, 0.0);
     g->corner.assign(E * 12, 0.0);
     const double h = 1.0 / nel1;
@@ -241,6 +242,8 @@ igb_status geometry_build(igb_ctx ctx, const igb_patch* patches, int npatch, int
                     set_error("build_geometry: element not inside one knot span (patch %d)", j);
                     return IGB_ERR_GEOMETRY;
                 }
+                g->espan[2 * e] = su;
+                g->espan[2 * e + 1] = sv;
                 const int pu = P.deg_u, pv = P.deg_v;
                 // u-direction first: rows b = sv-pv..sv give Bezier nets in u
                 double rowbez[PGMAX + 1][(PGMAX + 1) * 4];

@@ -83,8 +83,12 @@ igb_status tree_build(igb_op op) {
     op->clo.assign(op->nclusters * 3, 0.0);
     op->chi.assign(op->nclusters * 3, 0.0);
 
-    // boxes: elements merged upward level by level
+    // boxes: elements merged upward level by level; with them the geometry knot
+    // span holding the cluster (-1 where its elements lie in several spans)
     std::vector<double> lo(g->lo), hi(g->hi);
+    std::vector<int64_t> span(size_t(g->nelem));
+    for (int64_t e = 0; e < g->nelem; ++e) span[e] = (int64_t(g->espan[2 * e]) << 32) | g->espan[2 * e + 1];
+    std::vector<char> one_span(size_t(op->nclusters), 0);
     for (int l = m; l >= 0; --l) {
         const int n = 1 << l;
         if (l <= L) {
@@ -97,11 +101,13 @@ igb_status tree_build(igb_op op) {
                             op->clo[3 * dst + c] = lo[3 * src + c];
                             op->chi[3 * dst + c] = hi[3 * src + c];
                         }
+                        one_span[dst] = span[src] >= 0;
                     }
         }
         if (l == 0) break;
         const int h = n / 2;
         std::vector<double> plo(size_t(np) * h * h * 3, 1e300), phi(size_t(np) * h * h * 3, -1e300);
+        std::vector<int64_t> pspan(size_t(np) * h * h, -2);   // -2: no child seen yet
         for (int j = 0; j < np; ++j)
             for (int cy = 0; cy < n; ++cy)
                 for (int cx = 0; cx < n; ++cx) {
@@ -111,13 +117,22 @@ igb_status tree_build(igb_op op) {
                         plo[3 * dst + c] = std::min(plo[3 * dst + c], lo[3 * src + c]);
                         phi[3 * dst + c] = std::max(phi[3 * dst + c], hi[3 * src + c]);
                     }
+                    int64_t& ps = pspan[dst];
+                    ps = ps == -2 ? span[src] : (ps == span[src] ? ps : -1);
                 }
         lo.swap(plo);
         hi.swap(phi);
+        span.swap(pspan);
     }
     (void)nel1;
 
+    // A pair is interpolated only where both clusters lie inside one knot span of
+    // their patch's geometry: across a knot line a spline mapping is only finitely
+    // smooth (the surface measure and normal of a degree-2 mapping have kinks), and
+    // the interpolation error of the pulled-back kernel then decays only
+    // algebraically in q; inside one span the mapping is one rational piece.
     auto admissible = [&](int64_t t, int64_t s) {
+        if (!one_span[t] || !one_span[s]) return false;
         const double *lt = &op->clo[3 * t], *ht = &op->chi[3 * t];
         const double *ls = &op->clo[3 * s], *hs = &op->chi[3 * s];
         double gap2 = 0, dt2 = 0, ds2 = 0;

@@ -35,6 +35,10 @@ class ServeConfig:
     p: int = 2
     q: int = 8
     eta_adm: float = 1.6
+    # cap on kappa * diameter of interpolated clusters (0: the paper's rule alone).
+    # Without it a block at high kappa may span several wavelengths and its
+    # interpolation error, not the solver tolerance, bounds the result's accuracy
+    kcap: float = 0.0
     leaf_depth: int = 2
     # one Gauss point per direction fewer than the library default in the near
     # field: entries ~1e-9 relative (hard ~1e-8), far below the H2 compression
@@ -107,8 +111,8 @@ class Server:
         c = self.cfg
         bc = B.SOFT if req.bc == "soft" else B.HARD
         prec = c.precision if req.bc == "soft" else c.precision_hard
-        args = dict(kappa=req.kappa, bc=bc, q=c.q, eta_adm=c.eta_adm, leaf_depth=c.leaf_depth, precision=prec,
-                    quad_extra=c.quad_extra)
+        args = dict(kappa=req.kappa, bc=bc, q=c.q, eta_adm=c.eta_adm, kcap=c.kcap, leaf_depth=c.leaf_depth,
+                    precision=prec, quad_extra=c.quad_extra)
         if c.tune_cache is not None:
             from . import autotune as T
             ch = c.tune_cache.get(T.TuneKey(T.device_arch(), req.m, c.p, c.q, bc, prec,

@@ -50,10 +50,16 @@ def _oracle_blocks(patches, m, p, q, d, kcap, kappa=2.0):
     return h2.H2Oracle(bem, q=q, eta=1.6, leaf_depth=d, kcap=kcap)
 
 
-@pytest.mark.parametrize("geom,m,p,q,d,kcap", [("sphere", 3, 2, 4, 1, 0.0), ("sphere", 4, 2, 6, 2, 3.0),
-                                              ("star", 3, 2, 5, 1, 0.0)])
-def test_block_partition_matches_oracle(hctx, geom, m, p, q, d, kcap):
-    pts = I.sphere_patches() if geom == "sphere" else I.star_patches(0, min(m, 4))
+@pytest.mark.parametrize("geom,m,p,q,d,kcap,g", [("sphere", 3, 2, 4, 1, 0.0, 0), ("sphere", 4, 2, 6, 2, 3.0, 0),
+                                                ("star", 3, 2, 5, 1, 0.0, 0), ("star", 4, 2, 4, 1, 0.0, 1),
+                                                ("star", 4, 2, 4, 2, 0.0, 2), ("star", 3, 2, 4, 1, 0.0, 3)])
+def test_block_partition_matches_oracle(hctx, geom, m, p, q, d, kcap, g):
+    """The library's far blocks and near leaf pairs equal the oracle's, also on
+    stars whose geometry has 2^g knot spans per side: there a cluster that
+    straddles a geometry knot line is never admissible (g = 1, 2: only the
+    finer levels are; g = 3 at m = 3: every element is its own span and every
+    pair is near)."""
+    pts = I.sphere_patches() if geom == "sphere" else I.star_patches(0, g)
     geo = B.Geometry(hctx, pts, m, p)
     op = B.Operator(hctx, geo, kappa=2.0, q=q, leaf_depth=d, kcap=kcap)
     H = _oracle_blocks(pts, m, p, q, d, kcap)
@@ -64,6 +70,12 @@ def test_block_partition_matches_oracle(hctx, geom, m, p, q, d, kcap):
 
     ref = np.array([(t.level, loc(t), loc(s)) for t, s in H.far]).reshape(-1, 3)
     assert np.array_equal(op.far_blocks(), ref)
+    if geom == "star":
+        # every far cluster inside one span: levels >= g only (2^(m-l) elements
+        # per cluster side, 2^(m-g) per span side)
+        assert len(ref) == 0 if g >= m else ref[:, 0].min(initial=m) >= g
+        if g < m - d:
+            assert len(ref) > 0
     ptr, src, kind = op.near_pairs()
     pairs = H.near_pairs()
     pairs = pairs[np.lexsort((pairs[:, 1], pairs[:, 0]))]
