@@ -81,6 +81,17 @@ WORKLOADS = {
 PEAKS = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
 
 
+def mie_soft_farfield(ka, ct):
+    """Far-field pattern of the sound-soft unit sphere (Mie series) at the
+    cosines ct of the angles between observation and incidence directions."""
+    from scipy.special import eval_legendre, spherical_jn, spherical_yn
+    ref = np.zeros(len(ct), dtype=np.complex128)
+    for nn in range(int(ka) + 30):
+        h = spherical_jn(nn, ka) + 1j * spherical_yn(nn, ka)
+        ref += (2 * nn + 1) * spherical_jn(nn, ka) / h * eval_legendre(nn, ct)
+    return ref * (1j / ka)
+
+
 def cpu_baseline(w, reps=5):
     """The oracle O1 (plain dense fp64 Galerkin BEM, NumPy) timed on the host's
     cores (all of them, or the OMP_NUM_THREADS share), each stage separately:
@@ -927,10 +938,17 @@ def main():
                     op64 = o
             r = run_solves(o, dirs_b, max(1, args.steps // 2), 1)
             c = r.pop("coeff").cpu().numpy()
-            r.pop("uinf")
+            u = r.pop("uinf").cpu().numpy()
             if ref_coeff is None:
-                ref_coeff = c
+                ref_coeff, ref_uinf = c, u
             r["solution_rel_diff_vs_fp64_block"] = float(np.abs(c - ref_coeff).max() / np.abs(ref_coeff).max())
+            # the result's own error: far field per direction against the fp64
+            # block's and against the Mie series of the sphere
+            r["farfield_rel_diff_vs_fp64_block"] = float(np.abs(u - ref_uinf).max() / np.abs(ref_uinf).max())
+            if w["geometry"] == "sphere" and w.get("bc", "soft") == "soft":
+                r["farfield_max_rel_err_vs_mie"] = max(
+                    float(np.abs(u[i] - mref).max() / np.abs(mref).max())
+                    for i, mref in enumerate(mie_soft_farfield(w["kappa"], obs @ dv) for dv in dirs_b))
             r["speedup_matvecs_vs_plain_fp64"] = r["matvecs_per_s"] / value
             r["speedup_solves_vs_plain_fp64"] = r["solves_per_s"] / plain["solves_per_s"]
             r.pop("T")
@@ -1031,14 +1049,7 @@ def main():
     err_oracle = err_rows["operator_relative"]
     err_mie = None
     if w["geometry"] == "sphere":
-        from scipy.special import eval_legendre, spherical_jn, spherical_yn
-        ka = w["kappa"]
-        ct = obs @ d[0]
-        ref = np.zeros(len(ct), dtype=np.complex128)
-        for nn in range(int(ka) + 30):
-            h = spherical_jn(nn, ka) + 1j * spherical_yn(nn, ka)
-            ref += (2 * nn + 1) * spherical_jn(nn, ka) / h * eval_legendre(nn, ct)
-        ref *= 1j / ka
+        ref = mie_soft_farfield(w["kappa"], obs @ d[0])
         u = uinf.cpu().numpy()
         err_mie = float(np.abs(u - ref).max() / np.abs(ref).max())
 
