@@ -97,7 +97,11 @@ typedef enum {
  *              points of the first kind, Sec. 4.4), 1 <= q <= 10
  *   eta_adm    admissibility: dist(B_t,B_s) >= eta_adm * max(diam B_t, diam B_s)
  *              for the boxes of the clusters' Bezier control points (Sec. 4.4
- *              gives eta = 1.6 without the inequality; this reading)
+ *              gives eta = 1.6 without the inequality; this reading), and only
+ *              for clusters that each lie inside one knot span of their
+ *              patch's geometry (Sec. 3.2 takes the mappings to be smooth;
+ *              across a knot line the pulled-back kernel is only finitely
+ *              smooth and its interpolant converges algebraically in q)
  *   kcap       if > 0, a block is admissible only if kappa*max(diam) <= kcap
  *   leaf_depth clusters stop at 4^leaf_depth elements (leaf level m - leaf_depth),
  *              0 <= leaf_depth <= 6
