@@ -84,3 +84,16 @@ def test_request_larger_than_budget_is_rejected():
     except ValueError:
         return
     raise AssertionError("expected a ValueError")
+
+
+def test_kappa_cap_reaches_the_size_model():
+    """ServeConfig.kcap is passed to the operator: on a level-4 request at
+    kappa = 32 a cap of 4 keeps coarse blocks out of the far field, so the
+    host plan's size estimate changes (no device memory is touched)."""
+    req = I.Request(rid=0, arrival=0.0, seed=5, m=4, kappa=32.0, dirs=I.random_directions(0, 2), bc="soft")
+    sizes = {}
+    for kcap in (0.0, 4.0):
+        srv = Server(ServeConfig(kcap=kcap, nobs=4), solve_fn=lambda r, s: None)
+        assert srv._op_args(req)["kcap"] == kcap
+        sizes[kcap] = srv.estimate(req)
+    assert sizes[0.0] > 0 and sizes[4.0] > 0 and sizes[0.0] != sizes[4.0]
