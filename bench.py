@@ -143,7 +143,7 @@ def cpu_baseline(w, reps=5):
             "assembly_s_extrapolated": t_asm * E / cores, "blas": blas}
 
 
-def large_workload(name, steps, warmup):
+def large_workload(name, steps, warmup, overrides=None):
     """A star configuration: one operator, a block of incident directions solved
     in lockstep (fp64, or bf16 couplings inside fp64 refinement), far fields at
     64 directions.  One step = one block solve + its far fields; `value` counts
@@ -156,7 +156,7 @@ def large_workload(name, steps, warmup):
 
     from paper_2306_11324_amd import binding as B
     from paper_2306_11324_amd import inputs as I
-    w = WORKLOADS[name]
+    w = dict(WORKLOADS[name], **(overrides or {}))
     dev = torch.device("cuda:0")
     torch.cuda.init()
     ctx = B.Context(0)
@@ -649,6 +649,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sphere_m5_p2_k8", choices=sorted(WORKLOADS))
     ap.add_argument("--matvecs", type=int, default=50, help="matvec-only timing loop length")
+    ap.add_argument("--kcap", type=float, default=None, help="star workloads: kappa*diam cap override")
+    ap.add_argument("--q", type=int, default=None, help="star workloads: interpolation degree override")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block", type=int, default=16, help="directions per served block (0: skip)")
     ap.add_argument("--serve", type=int, default=32, help="requests in the served stream (0: skip)")
@@ -713,7 +715,8 @@ def main():
         serve_study(args.serve_capacity, fractions=fr, n_main=args.serve_main)
         return
     if args.workload != "sphere_m5_p2_k8":
-        large_workload(args.workload, args.steps, args.warmup)
+        large_workload(args.workload, args.steps, args.warmup,
+                       {k: v for k, v in (("kcap", args.kcap), ("q", args.q)) if v is not None})
         return
 
     import torch
