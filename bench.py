@@ -394,15 +394,17 @@ def scaling_sweep(levels, kappa=2.0, q=6, leaf_depth=2):
                           "loglog_slope_vs_N": fit, "matvec_ms_over_m4m": guide}), flush=True)
 
 
-def serve_stream(nreq, rate):
+def serve_stream(nreq, rate, catalog=0):
     """Continuous batching of a Poisson request stream: each request a seeded
     star-shaped scatterer at level 3..6, kappa in [1, 32], 1..16 directions,
     sound-soft or sound-hard, bf16 couplings with fp64 refinement, admitted by
-    HBM budget into 4 concurrent slots.  Latency = completion - arrival."""
+    HBM budget into 4 concurrent slots.  Latency = completion - arrival.  With
+    catalog > 0 the scattering problems come from a catalog of that many, and
+    waiting requests for one problem share a block."""
     from paper_2306_11324_amd import inputs as I
     from paper_2306_11324_amd.serving import ServeConfig, Server
     cfg = ServeConfig(slots=4)
-    reqs = I.request_stream(nreq, rate=rate, seed=3)
+    reqs = I.request_stream(nreq, rate=rate, seed=3, catalog=catalog)
     srv = Server(cfg)
 
     def log(r):
@@ -419,7 +421,8 @@ def serve_stream(nreq, rate):
                 "precision": "bf16 couplings, fp64 near field and refinement", "q": cfg.q,
                 "leaf_depth": cfg.leaf_depth, "tol": cfg.tol, "peak_reserved_GB": srv.peak_reserved / 1e9,
                 "stage_seconds_total": stages,
-                "stream": "request_stream(seed=3): level 3..6, kappa U[1,32], 1..16 directions, soft/hard"})
+                "stream": "request_stream(seed=3): level 3..6, kappa U[1,32], 1..16 directions, soft/hard"
+                          + (f", problems from a catalog of {catalog}" if catalog else "")})
     return out
 
 
@@ -676,6 +679,8 @@ def main():
     ap.add_argument("--serve-capacity", type=float, default=None, help="skip the capacity run (requests/s)")
     ap.add_argument("--serve-fractions", default="0.4,0.6,0.8,1.0")
     ap.add_argument("--serve-main", type=int, default=200)
+    ap.add_argument("--serve-catalog", type=int, default=0,
+                    help="draw the stream's scattering problems from a catalog of this many (0: all distinct)")
     ap.add_argument("--serve-only", action="store_true",
                     help="only the request stream (--serve requests at --serve-rate), e.g. under a kernel trace")
     ap.add_argument("--trace-overlap", default=None,
@@ -708,7 +713,7 @@ def main():
         trace_overlap(args.trace_overlap)
         return
     if args.serve_only:
-        print(json.dumps(serve_stream(args.serve, args.serve_rate)), flush=True)
+        print(json.dumps(serve_stream(args.serve, args.serve_rate, args.serve_catalog)), flush=True)
         return
     if args.serve_study:
         fr = tuple(float(v) for v in args.serve_fractions.split(",")) if args.serve_fractions else ()

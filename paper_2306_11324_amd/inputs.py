@@ -301,12 +301,29 @@ class Request:
 
 
 def request_stream(n: int, rate: float, seed: int = 3, m_values=(3, 4, 5, 6), kappa_range=(1.0, 32.0),
-                   max_dirs: int = 16) -> list[Request]:
+                   max_dirs: int = 16, catalog: int = 0) -> list[Request]:
+    """Poisson arrivals at `rate`; each request a seeded star, level, wavenumber,
+    boundary condition and 1..max_dirs incident directions.  With catalog > 0
+    the (star, level, wavenumber, boundary condition) of each request is drawn
+    from a seeded catalog of that many scattering problems, so that requests
+    share operators (new directions on a known problem); the directions stay
+    the request's own."""
     rng = np.random.default_rng(seed)
+    problems = []
+    if catalog > 0:
+        crng = np.random.default_rng(seed + 1)
+        for _ in range(catalog):
+            problems.append((int(crng.integers(0, 10 ** 6 + 1)), int(crng.choice(m_values)),
+                             float(crng.uniform(*kappa_range)), "soft" if crng.integers(0, 2) == 0 else "hard"))
     t = 0.0
     out = []
     for i in range(n):
         t += rng.exponential(1.0 / rate)
+        if problems:
+            rseed, m, kappa, bc = problems[int(rng.integers(0, len(problems)))]
+            ndir = int(rng.integers(1, max_dirs + 1))
+            out.append(Request(i, t, rseed, m, kappa, bc, random_directions(int(rng.integers(0, 2 ** 31)), ndir)))
+            continue
         rseed = int(rng.integers(0, 10 ** 6 + 1))
         m = int(rng.choice(m_values))
         kappa = float(rng.uniform(*kappa_range))

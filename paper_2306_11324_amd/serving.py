@@ -6,9 +6,14 @@ memory -- from the operator's size model, computed by a host-only plan before
 anything is allocated -- fits the remaining HBM budget.  Admitted requests run
 concurrently, one HIP stream per slot: geometry, operator assembly, the
 lockstep multi-direction CFIE solve (mixed precision with fp64 refinement) and
-the far field.  A request's result depends only on the request: every
-reduction in the library has a fixed order and slots share no state, so a
-request gives the same far field alone and in the mix.
+the far field.  Waiting requests for the same scattering problem (star, level,
+wavenumber, boundary condition) join the admitted one as further columns of
+its lockstep block: one operator, one block matvec per Arnoldi step.  A
+request's result depends only on the request: every reduction in the library
+has a fixed order, slots share no state and each column of a block keeps its
+own Krylov basis, so a request gives the same far field alone and in the mix
+(bitwise when it runs alone in its slot; within the solver's tolerance when
+its block shares columns with another request).
 
 All numerical work runs in the HIP library; this module schedules.
 """
@@ -51,6 +56,10 @@ class ServeConfig:
     restart_soft: int = 30
     restart_hard: int = 30
     maxit: int = 1500        # Arnoldi steps per direction; a request that reaches it is reported unconverged
+    # requests for the same scattering problem (star, level, wavenumber, boundary
+    # condition) that wait together are solved as one lockstep block of up to
+    # merge_max_dirs directions on one operator (0: every request alone)
+    merge_max_dirs: int = 64
     # autotuned operator shapes (leaf depth, stored / on-the-fly couplings) per request class;
     # classes without an entry use leaf_depth and stored couplings
     tune_cache: object = None
@@ -71,10 +80,16 @@ class Result:
     escalated: int        # directions finished on the fp64 operator
     uinf: np.ndarray      # (ndir, nobs)
     stages: dict = dataclasses.field(default_factory=dict)   # seconds per stage
+    batch: tuple = ()     # ids of the requests solved in the same block (this one first)
 
     @property
     def latency(self) -> float:
         return self.done - self.arrival
+
+
+def problem_key(req: I.Request):
+    """Requests with equal keys have the same operator."""
+    return (req.seed, req.m, req.kappa, req.bc)
 
 
 def percentile(values, pct):
@@ -203,33 +218,59 @@ class Server:
                         if pick is not None:
                             pending.remove(pick)
                             state["free"] -= est[pick.rid]
+                            # waiting requests for the same problem join the block
+                            # (each reserves its own estimate: an upper bound)
+                            batch, ndir = [pick], len(pick.dirs)
+                            for r in list(pending):
+                                if (problem_key(r) == problem_key(pick)
+                                        and ndir + len(r.dirs) <= self.cfg.merge_max_dirs
+                                        and est[r.rid] <= state["free"]):
+                                    pending.remove(r)
+                                    state["free"] -= est[r.rid]
+                                    batch.append(r)
+                                    ndir += len(r.dirs)
                             self.peak_reserved = max(self.peak_reserved, self.cfg.hbm_budget - state["free"])
                             break
                         if state["arrived"] == len(reqs) and not pending:
                             return
                         lock.wait(0.05)
                 admitted = now()
+                job = pick if len(batch) == 1 else dataclasses.replace(
+                    pick, dirs=np.concatenate([r.dirs for r in batch]))
+                reserved = sum(est[r.rid] for r in batch)
                 try:
                     if self.solve_fn is not None:
-                        n, info, u, *rest = self.solve_fn(pick, slot)
+                        n, info, u, *rest = self.solve_fn(job, slot)
                     else:
-                        n, info, u, *rest = self.solve(pick, self.ctxs[slot])
+                        n, info, u, *rest = self.solve(job, self.ctxs[slot])
                 except Exception as exc:  # recorded, the stream continues
                     with lock:
-                        state["errors"].append((pick.rid, repr(exc)))
-                        state["free"] += est[pick.rid]
+                        state["errors"].extend((r.rid, repr(exc)) for r in batch)
+                        state["free"] += reserved
                         lock.notify_all()
                     continue
                 done = now()
-                res = Result(pick.rid, pick.arrival, admitted, done, n, est[pick.rid], info.iters, info.matvecs,
-                             info.relres_true, info.converged, getattr(info, "escalated", 0), u,
-                             rest[0] if rest else {})
+                # the block's far field split back by request; the solve's counts
+                # are the block's (unconverged columns are not attributed, so a
+                # request counts as converged only when the whole block is)
+                ids, off, out = tuple(r.rid for r in batch), 0, []
+                total = len(job.dirs)
+                for r in batch:
+                    nd = len(r.dirs)
+                    conv = nd if info.converged == total else max(0, info.converged - (total - nd))
+                    out.append(Result(r.rid, r.arrival, admitted, done, n, est[r.rid], info.iters,
+                                      info.matvecs * nd // total,
+                                      info.relres_true, conv, getattr(info, "escalated", 0), u[off:off + nd],
+                                      rest[0] if rest else {}, (r.rid,) + tuple(i for i in ids if i != r.rid)))
+                    off += nd
                 with lock:
-                    results[pick.rid] = res
-                    state["free"] += est[pick.rid]
+                    for res in out:
+                        results[res.rid] = res
+                    state["free"] += reserved
                     lock.notify_all()
                 if log is not None:
-                    log(res)
+                    for res in out:
+                        log(res)
 
         threads = [threading.Thread(target=feeder, daemon=True)]
         threads += [threading.Thread(target=worker, args=(i,), daemon=True) for i in range(self.cfg.slots)]
@@ -251,4 +292,5 @@ class Server:
                 "p50_latency_s": percentile(lat, 50), "p99_latency_s": percentile(lat, 99),
                 "max_relres_true": max(r.relres_true for r in results),
                 "escalated_directions": sum(r.escalated for r in results),
+                "merged_requests": sum(1 for r in results if len(r.batch) > 1),
                 "all_converged": all(r.converged == r.uinf.shape[0] for r in results)}

@@ -97,3 +97,37 @@ def test_kappa_cap_reaches_the_size_model():
         assert srv._op_args(req)["kcap"] == kcap
         sizes[kcap] = srv.estimate(req)
     assert sizes[0.0] > 0 and sizes[4.0] > 0 and sizes[0.0] != sizes[4.0]
+
+
+def test_requests_for_one_problem_share_a_block():
+    """Requests of a catalog stream that wait together for the same problem are
+    solved as one block: the executor sees their directions concatenated, and
+    each result holds exactly its own directions' far field."""
+    reqs = I.request_stream(30, rate=1000.0, seed=5, catalog=3, max_dirs=6)
+    keys = {(r.seed, r.m, r.kappa, r.bc) for r in reqs}
+    assert len(keys) == 3
+    jobs = []
+
+    def solve(job, slot):
+        jobs.append(len(job.dirs))
+        time.sleep(0.002)
+        info = types.SimpleNamespace(iters=1, matvecs=2 * len(job.dirs), relres_true=0.0,
+                                     converged=len(job.dirs))
+        return 10, info, job.dirs[:, :2].astype(complex)   # a far field that names its direction
+
+    srv = Server(ServeConfig(slots=1, hbm_budget=10 ** 6, nobs=2, merge_max_dirs=40),
+                 solve_fn=solve, estimate_fn=lambda r: 10)
+    res = srv.run(reqs, realtime=False)
+    assert max(jobs) > 6 and sum(jobs) == sum(len(r.dirs) for r in reqs)
+    for r, out in zip(sorted(reqs, key=lambda r: r.rid), res):
+        assert np.array_equal(out.uinf, r.dirs[:, :2].astype(complex)) and out.converged == len(r.dirs)
+        assert out.batch[0] == r.rid
+        assert all((reqs[i].seed, reqs[i].m, reqs[i].kappa, reqs[i].bc) == (r.seed, r.m, r.kappa, r.bc)
+                   for i in out.batch)
+    assert Server.summary(res, srv.wall)["merged_requests"] > 0
+    # merging off: one job per request
+    jobs.clear()
+    srv = Server(ServeConfig(slots=1, hbm_budget=10 ** 6, nobs=2, merge_max_dirs=0),
+                 solve_fn=solve, estimate_fn=lambda r: 10)
+    srv.run(reqs, realtime=False)
+    assert len(jobs) == len(reqs)
